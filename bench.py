@@ -1,0 +1,181 @@
+"""Benchmark: acoustic FWI gradient (forward + checkpointed adjoint) on one GPU.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+Workload: the 1000x300 layered-plus-anomaly model (8 layers, 20 Gaussian
+anomalies of +-10 %), dx = 10 m, dt = 1 ms, 3000 steps, 40-cell C-PML (padded
+1080x380), 64 Ricker (8 Hz) shots at depth 5 and 1000 receivers per shot,
+checkpoints every 50 steps. One step = forward of all 64 shots with
+checkpointing, L2 misfit against observed data, and the adjoint pass that
+returns the model gradient. Inputs are resident in HBM before timing starts.
+
+Metric: fwd+adj Gcell-updates/s = 2 * shots * NX * NZ * nt / step time (padded
+cells counted; recomputation is overhead, not work). Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+WORKLOAD = "layered1000x300"
+
+
+def _kernel_bytes(w, NX, NZ, plan):
+    """Algorithmic HBM bytes per launch of each step-kernel class (interior or
+    frame cells of all shots; per cell-update: forward 16 B, recompute 20 B,
+    adjoint 28 B interior; frame cells add the memory-variable traffic)."""
+    P = w.pml
+    interior_cells = (NX - 2 * P) * (NZ - 2 * P)
+    return interior_cells
+
+
+def cpu_baseline(w, max_seconds=30.0):
+    """The FP64 oracle on the host cores, on a bounded sample of the workload:
+    `ns` shots (one per host thread) for `nt_s` of the steps, forward + gradient,
+    in the metric's unit (fwd+adj Gcell-updates/s)."""
+    import oracle
+    from tests.helpers import case_from_workload, f32
+    import synth
+
+    oracle.lib()
+    cores = os.cpu_count() or 1
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except Exception:
+        pass
+    cores = max(1, min(cores, 16, w.nshots))
+    nt_s = 200
+    shots = list(range(0, w.nshots, max(1, w.nshots // cores)))[:cores]
+    case = case_from_workload(w, shots=shots, nt=nt_s)
+    case.nt = nt_s
+    pb = case.oracle_problem(oracle, nthreads=cores)
+    resid = f32(synth.bandlimited_noise((len(shots), nt_s, w.nrec), w.f0, w.dt, 5))
+    t0 = time.perf_counter()
+    oracle.ac_gradient(pb, case.v, case.src, case.wav, case.rec, resid)
+    t = time.perf_counter() - t0
+    NX, NZ = w.NX, w.NZ
+    cells = 2.0 * len(shots) * NX * NZ * nt_s
+    return {"value": cells / t / 1e9, "unit": "Gcell-updates/s", "cores": cores,
+            "kind": "oracle",
+            "sample": f"{len(shots)} of {w.nshots} shots x {nt_s} of {w.nt} steps, "
+                      f"forward+checkpointed adjoint gradient (k=50), FP64, "
+                      f"{t:.1f} s wall"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--rz", type=int, default=8)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--nt", type=int, default=0, help="override the step count (testing)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU shot "
+                          "partitioning is described in DESIGN.md but not implemented",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+    import paper_2604_14189_amd as sw
+    import synth
+    from tests.helpers import case_from_workload
+
+    w = synth.workload(WORKLOAD)
+    if args.nt:
+        w = w.replace(nt=args.nt)
+    case = case_from_workload(w)
+    dev = torch.device("cuda:0")
+    plan = case.plan()
+    plan.set_tuning(rz=args.rz)
+    NX, NZ = plan.padded()
+    v_true = torch.tensor(case.v, dtype=torch.float32, device=dev)
+    v0 = torch.tensor(synth.smooth(case.v, 20.0), dtype=torch.float32, device=dev)
+    wav = torch.tensor(case.wav, dtype=torch.float32, device=dev)
+    obs_plan = case.plan()
+    d_obs = obs_plan.forward(v_true, wav).clone()
+    obs_plan.release_workspace()
+    del obs_plan
+    torch.cuda.synchronize()
+
+    def step():
+        d = plan.forward(v0, wav, save=True)
+        resid, J = sw.l2_misfit(d, d_obs)
+        g = plan.backward(resid)
+        return g, J
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    plan.set_profiling(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        g, J = step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    kt = plan.kernel_times()
+    plan.set_profiling(False)
+
+    cell_updates = 2.0 * w.nshots * NX * NZ * w.nt
+    value = cell_updates / dt / 1e9
+
+    # dominant kernel: the adjoint interior step (largest share of the step time)
+    P = w.pml
+    n_int_cells = 0
+    # interior tiles cover the interior tile rectangle; count exact cells from the plan tiling
+    TZ = 4 * args.rz
+    itx0 = (P + 4 + 63) // 64
+    itx1 = (NX - P - 4) // 64
+    itz0 = (P + 4 + TZ - 1) // TZ
+    itz1 = (NZ - P - 4) // TZ
+    n_int_cells = max(0, itx1 - itx0) * 64 * max(0, itz1 - itz0) * TZ
+    shares = {k: v[1] for k, v in kt.items()}
+    dom = max(shares, key=lambda k: shares[k])
+    per_cell = {"fwd_interior": 16, "rec_interior": 20, "adj_interior": 28}
+    roof = None
+    if dom in per_cell and kt[dom][0] > 0:
+        launches, tot_ms = kt[dom]
+        avg_s = tot_ms / launches / 1e3
+        bytes_per_launch = per_cell[dom] * n_int_cells * w.nshots
+        achieved = bytes_per_launch / avg_s / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": dom, "avg_launch_us": round(avg_s * 1e6, 2),
+                "algorithmic_bytes_per_launch": bytes_per_launch}
+
+    out = {
+        "metric": "Gcell-updates/s fwd+adj (FWI gradient, checkpointed, batched shots)",
+        "value": round(value, 3),
+        "unit": "Gcell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(dt * 1e3, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD, "nx": w.nx, "nz": w.nz, "padded": f"{NX}x{NZ}",
+                   "nt": w.nt, "shots": w.nshots, "receivers": w.nrec, "pml": w.pml,
+                   "ckpt_every": w.ckpt_every, "rz": args.rz, "misfit_J": float(J.item())},
+        "roofline": roof,
+        "kernel_ms": {k: [v[0], round(v[1], 3)] for k, v in kt.items()},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

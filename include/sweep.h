@@ -1,0 +1,146 @@
+/*
+ * libsweep: MI355X (gfx950) HIP implementation of the SWEEP hot path
+ * (arXiv 2604.14189): the 2-D finite-difference time loop, its exact adjoint and
+ * the resulting full-waveform-inversion gradients, for the constant-density
+ * acoustic equation (Sec. 3.1.2, Eq. 2) and the isotropic elastic
+ * velocity-stress system (Sec. 3.5, Eq. 12); plus the Fourier-feature MLP
+ * velocity model the paper's neural-network workflow calls for (Sec. 1).
+ *
+ * The split follows the paper's Propagator / Source / Receiver modules
+ * (Sec. 2.1): a plan fixes the grid, time axis, absorbing pad, sources and
+ * receivers ("shapes are inferred from the model"); forward() runs the whole
+ * time loop for every shot and returns shot gathers; backward() runs the
+ * adjoint and returns d(loss)/d(model) for a given d(loss)/d(gathers).
+ * Batch modelling (Sec. 2.2): every call advances all shots of a plan, and the
+ * batch API advances several plans of uneven size, in one kernel per step.
+ *
+ * Conventions for every call
+ *  - Fields and models are float32, row-major [z][x] with x contiguous
+ *    (x = horizontal, z = depth). Source / receiver positions are integer cell
+ *    indices (x, z) of the model grid.
+ *  - All pointers named d_* are DEVICE pointers owned by the caller; the library
+ *    never allocates, frees or keeps them beyond the call. Host pointers are
+ *    read during the call only.
+ *  - `stream` is a hipStream_t passed as void*; every call only enqueues work on
+ *    it and returns without synchronising (except where stated).
+ *  - Return value: SWEEP_OK (0) or a negative error code; sweep_last_error()
+ *    gives a message for the calling thread. No C++ exception crosses the ABI.
+ *  - Calls on one plan are not thread-safe; different plans are independent.
+ */
+#ifndef SWEEP_H
+#define SWEEP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SWEEP_OK 0
+#define SWEEP_EINVAL (-1) /* bad shape, position outside the model, nt < 1, ... */
+#define SWEEP_EHIP (-2)   /* a HIP runtime call failed; the message names it */
+#define SWEEP_ENOMEM (-3) /* the workspace passed is smaller than required */
+#define SWEEP_ECFL (-4)   /* pml_vmax * dt / h exceeds the scheme's stability limit */
+#define SWEEP_ESTATE (-5) /* call out of order (e.g. backward without a saved forward) */
+
+#define SWEEP_ACOUSTIC 0 /* Eq. 2: 2nd order in time, 8th order in space, C-PML */
+#define SWEEP_ELASTIC 1  /* Eq. 12: staggered velocity-stress, 4th order, C-PML */
+
+/* Problem description. The padded grid adds `pml` absorbing cells on each side
+ * (and none on top when free_surface = 1, elastic only); the model is
+ * replicated from its edge cells into the pad. */
+typedef struct {
+  int physics;      /* SWEEP_ACOUSTIC or SWEEP_ELASTIC */
+  int nx, nz;       /* model grid (cells) */
+  int pml;          /* absorbing pad width (cells), >= 0 */
+  int free_surface; /* elastic: 1 = traction-free top row; acoustic: must be 0 */
+  double h;         /* grid spacing dx = dz (m) */
+  double dt;        /* time step (s) */
+  int nt;           /* time steps */
+  double pml_vmax;  /* velocity of the damping profile (m/s); fixed, not differentiated */
+  double pml_f0;    /* C-PML frequency (Hz), usually the source peak frequency */
+  double pml_R;     /* target reflection coefficient, e.g. 1e-3 */
+  int ckpt_every;   /* checkpoint interval k (steps) for backward(); 0 = default 50 */
+  int nshots;       /* shots advanced together */
+  int nrec;         /* receivers per shot */
+} sweep_problem;
+
+/* Tile / launch choices (what the autotuner searches). Results are bitwise
+ * independent of every field here. */
+typedef struct {
+  int rz;          /* rows per thread in the interior step kernels: 1, 2, 4 or 8 */
+  int shots_per_block; /* shots a work-group advances (shares the model reads): 1, 2, 4 */
+  int use_graph;   /* 1 = capture each forward/backward time loop as a hipGraph */
+} sweep_tuning;
+
+typedef struct sweep_plan sweep_plan;
+
+/* Message describing the last error on the calling thread ("" if none). */
+const char* sweep_last_error(void);
+
+/* Create a plan. src_xz: host [nshots][2]; rec_xz: host [nshots][nrec][2]
+ * (model-grid cells, x then z). The arrays are copied. Fails with SWEEP_EINVAL on
+ * inconsistent sizes or positions outside the model, SWEEP_ECFL when
+ * pml_vmax*dt/h exceeds 0.5546 (acoustic, 8th order) or 0.6061 (elastic, 4th).
+ * Does not touch the GPU. */
+int sweep_plan_create(const sweep_problem* pb, const int32_t* src_xz, const int32_t* rec_xz,
+                      sweep_plan** out);
+void sweep_plan_destroy(sweep_plan* plan);
+
+/* Select tile / launch choices (validated; SWEEP_EINVAL if unsupported). */
+int sweep_plan_set_tuning(sweep_plan* plan, const sweep_tuning* t);
+int sweep_plan_get_tuning(const sweep_plan* plan, sweep_tuning* t);
+
+/* Device workspace the caller must provide: for_backward = 0 for a forward-only
+ * call, 1 for forward(save_for_backward=1) followed by backward(). */
+size_t sweep_plan_workspace_bytes(const sweep_plan* plan, int for_backward);
+
+/* Padded grid size of the plan (NX, NZ). */
+int sweep_plan_padded(const sweep_plan* plan, int* NX, int* NZ);
+
+/* Forward modelling of every shot.
+ *   d_model   [nparam][nz][nx]: acoustic vp (nparam 1); elastic vp, vs, rho (3)
+ *   d_wavelet [nshots][nt]: source time function, sample n injected at step n
+ *   d_gathers [nshots][nt][nrec][ncomp] out: acoustic p (ncomp 1) at step n+1;
+ *             elastic (vx, vz) (ncomp 2)
+ *   d_work    workspace of at least sweep_plan_workspace_bytes(plan, save) bytes
+ *   save_for_backward: 1 stores checkpoints every ckpt_every steps in d_work
+ * Acoustic: the padded-grid recurrence is p^{n+1} = 2p^n - p^{n-1} + (v dt)^2 B^n
+ * + (dt/h)^2 s_n at the source, where B^n is the 8th-order Laplacian with C-PML
+ * memory terms (the step function of Sec. 2.1 in the interior). */
+int sweep_forward(sweep_plan* plan, const float* d_model, const float* d_wavelet,
+                  float* d_gathers, void* d_work, size_t work_bytes, int save_for_backward,
+                  void* stream);
+
+/* Adjoint: given d_resid = dJ/d(gathers) (layout of d_gathers), writes
+ * d_grad [nparam][nz][nx] = dJ/d(model) summed over shots. Requires the
+ * preceding sweep_forward(save_for_backward = 1) on the same plan, model and
+ * workspace (SWEEP_ESTATE otherwise). The result is the exact transpose of the
+ * forward recurrence (dot-product test of Sec. 1), evaluated by recomputing each
+ * checkpoint segment and sweeping it backwards. */
+int sweep_backward(sweep_plan* plan, const float* d_resid, float* d_grad, void* d_work,
+                   size_t work_bytes, void* stream);
+
+/* Kernel timing for measurement tools. When enabled, every launch of the step
+ * kernels is bracketed by a pair of hipEvents recorded on the call's stream
+ * (the events add a few microseconds per launch). Classes:
+ *   0 forward interior, 1 forward pad-frame, 2 adjoint interior,
+ *   3 adjoint pad-frame, 4 recompute interior (also stores B^n), 5 recompute frame.
+ * sweep_plan_set_profiling resets the counters; sweep_plan_kernel_time waits for
+ * the recorded events and returns the number of launches and their summed
+ * duration in milliseconds since the reset. */
+int sweep_plan_set_profiling(sweep_plan* plan, int enable);
+int sweep_plan_kernel_time(sweep_plan* plan, int kernel_class, int* launches, double* total_ms);
+
+/* L2 misfit: d_resid[i] = d_pred[i] - d_obs[i] and *d_J = 0.5 * sum resid^2
+ * (float64, device). Deterministic two-stage reduction; d_scratch must hold
+ * sweep_l2_misfit_scratch_bytes(n) bytes. d_resid may alias d_pred. */
+size_t sweep_l2_misfit_scratch_bytes(size_t n);
+int sweep_l2_misfit(const float* d_pred, const float* d_obs, float* d_resid, double* d_J,
+                    size_t n, void* d_scratch, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,106 @@
+// Internal declarations shared by the library's translation units.
+// Host code and kernels for gfx950; nothing here crosses the C-ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "sweep.h"
+
+namespace sweep {
+
+// ------------------------------------------------------------------ errors
+void set_error(const std::string& msg);
+#define SWEEP_HIP(call)                                                              \
+  do {                                                                               \
+    hipError_t e_ = (call);                                                          \
+    if (e_ != hipSuccess) {                                                          \
+      ::sweep::set_error(std::string(#call) + " failed: " + hipGetErrorString(e_));  \
+      return SWEEP_EHIP;                                                             \
+    }                                                                                \
+  } while (0)
+
+// Work-group shape used by every stencil kernel: one wave64 row of 64 columns,
+// four rows of waves (256 threads). A tile is 64 columns by TZ rows.
+constexpr int kTX = 64;
+constexpr int kThreads = 256;
+
+inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
+
+// ------------------------------------------------------------------ acoustic
+// Device-side view of one time step of the acoustic recurrence (all shots of one
+// plan). Fields are [shot][NZ][NX]; x-strip memory variables [shot][NZ][2P]
+// (columns [0,P) then [NX-P,NX)); z-strip ones [shot][2P][NX].
+struct AcStep {
+  int NX, NZ, P, nt, nrec, nshots;
+  int n;          // time step being taken (forward) or reversed (adjoint)
+  int tiles_x;    // tile columns in the global tiling
+  int ntiles;     // tiles in the global tiling (receiver CSR stride)
+  float w;        // (dt/h)^2, source scale
+  const float* Cs;   // (v dt / h)^2, [NZ][NX]
+  const float* ax;   // C-PML a, b along x [NX] and z [NZ]
+  const float* bx;
+  const float* az;
+  const float* bz;
+  // forward: p^n (cur), p^{n-1} (prev), p^{n+1} (next, may alias prev)
+  // adjoint: lambda^{n+1} (cur), lambda^{n+2} (prev), lambda^n (next)
+  const float* cur;
+  const float* prev;
+  float* next;
+  // memory variables: read *_in (time n-1), write *_out (time n)
+  const float* psx_in;
+  float* psx_out;
+  const float* zex_in;
+  float* zex_out;
+  const float* psz_in;
+  float* psz_out;
+  const float* zez_in;
+  float* zez_out;
+  // sources / receivers
+  const int* src_cell;    // [nshots] padded linear index
+  const float* wavelet;   // [nshots][nt]
+  const int* rec_off;     // [nshots * ntiles + 1] CSR over (shot, tile)
+  const int2* rec_ent;    // (local cell index in tile, receiver index)
+  float* gathers;         // forward: [nshots][nt][nrec] output, or null
+  const float* resid;     // adjoint: [nshots][nt][nrec] injected at step n-1
+  // forward extras
+  float* B_out;           // [nshots][NZ][NX] Laplacian term B^n, or null
+  float* ck_cur;          // checkpoint of the inputs, or null (all six together)
+  float* ck_prev;
+  float* ck_psx;
+  float* ck_zex;
+  float* ck_psz;
+  float* ck_zez;
+  // adjoint extras
+  const float* B_in;      // B^n of this step
+  float* g;               // [nshots][NZ][NX] gradient partial
+  int g_init;             // 1: g = P1 B (first step of a segment), 0: g += P1 B
+  // tile lists
+  const int* frame_tiles; // tiles touching the absorbing pad
+  int n_frame;
+  int int_tx0, int_tz0, int_ntx;  // interior tile rectangle origin, width
+};
+
+// Launchers (acoustic.hip). `rz` selects the interior kernel variant (TZ = 4 rz).
+int ac_launch_prep(const float* v, float* vpad, float* Cs, float* ax, float* bx, float* az,
+                   float* bz, int nx, int nz, int P, double h, double dt, double vmax,
+                   double f0, double R, hipStream_t s);
+int ac_launch_fwd(const AcStep& a, int rz, int n_int_tiles, hipStream_t s, hipEvent_t* ev);
+int ac_launch_adj(const AcStep& a, int rz, int n_int_tiles, hipStream_t s, hipEvent_t* ev);
+int ac_launch_adj_init(float* lam_cur, float* lam_prev, size_t plane_elems, float* aux,
+                       size_t aux_elems, const int* rec_cell, const float* resid, int nshots,
+                       int nt, int nrec, hipStream_t s);
+int ac_launch_fold(double* tot, const float* gpart, int nshots, size_t plane, hipStream_t s);
+int ac_launch_finish(const double* tot, const float* vpad, float* grad, int nx, int nz, int P,
+                     int NX, double scale, hipStream_t s);
+
+// Generic helpers (util.hip).
+int launch_fill(float* p, size_t n, float v, hipStream_t s);
+int launch_fill_f64(double* p, size_t n, double v, hipStream_t s);
+int launch_copy(float* dst, const float* src, size_t n, hipStream_t s);
+
+}  // namespace sweep

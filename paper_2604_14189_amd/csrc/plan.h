@@ -1,0 +1,70 @@
+// Host-side plan object and workspace layout (not part of the C-ABI).
+#pragma once
+
+#include <vector>
+
+#include "internal.h"
+
+// Workspace layout of an acoustic plan (byte offsets into the caller's buffer).
+namespace sweep {
+struct AcLayout {
+  size_t plane, xs, zs, aux_elems;
+  size_t ax, bx, az, bz, vpad, Cs, wav, src_cell, rec_cell, rec_off, rec_ent, frame;
+  size_t pA, pB, aux[2];
+  size_t fwd_end;
+  int nseg;
+  size_t slot_elems;
+  size_t ck, Bseg, lA, lB, adjaux[2], gpart, tot;
+  size_t bwd_end;
+};
+}  // namespace sweep
+
+// Optional per-launch timing of the step kernels (hipEvent pairs recorded on the
+// caller's stream around every launch of a kernel class).
+namespace sweep {
+enum KernelClass {
+  kFwdInterior = 0,
+  kFwdFrame = 1,
+  kAdjInterior = 2,
+  kAdjFrame = 3,
+  kRecInterior = 4,
+  kRecFrame = 5,
+  kNumClasses = 6
+};
+struct KernelTimer {
+  bool on = false;
+  std::vector<hipEvent_t> ev[kNumClasses];  // start, stop, start, stop, ...
+  size_t used[kNumClasses] = {0, 0, 0, 0, 0, 0};
+  ~KernelTimer();
+  void reset();
+  // Four events for one interior + frame launch pair of classes (ci, cf), or
+  // null when timing is off.
+  hipEvent_t* take(int ci, int cf);
+  hipEvent_t quad[4];
+};
+}  // namespace sweep
+
+struct sweep_plan {
+  sweep_problem pb;
+  sweep_tuning tune;
+  int P = 0, NX = 0, NZ = 0, ckpt = 50;
+  std::vector<int> src_cell;  // [nshots] padded linear index
+  std::vector<int> rec_cell;  // [nshots][nrec] padded linear index
+  // tiling for the current tuning
+  int TZ = 0, tiles_x = 0, tiles_z = 0, ntiles = 0;
+  int itx0 = 0, itz0 = 0, intx = 0, intz = 0;
+  std::vector<int> frame;
+  std::vector<int> rec_off;
+  std::vector<int2> rec_ent;
+  // state of the last forward
+  bool saved = false;
+  const void* saved_work = nullptr;
+  const float* saved_model = nullptr;
+  int saved_rz = 0;
+  sweep::KernelTimer timer;
+};
+
+namespace sweep {
+void ac_build_tiling(sweep_plan* p);
+void ac_layout(const sweep_plan* p, AcLayout& L);
+}  // namespace sweep

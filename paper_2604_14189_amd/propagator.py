@@ -1,0 +1,224 @@
+"""Python face of libsweep: plans, forward / backward, autograd.
+
+Mirrors the paper's Propagator / Source / Receiver split (Sec. 2.1): a Plan
+fixes the grid, time axis, absorbing pad, sources and receivers; `forward`
+returns shot gathers for every shot at once (batch modelling, Sec. 2.2) and
+`backward` returns d(loss)/d(model) through the exact adjoint. PyTorch supplies
+device memory and the stream; all arithmetic happens in libsweep's kernels.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import ACOUSTIC, ELASTIC, Problem, Tuning, check, lib
+
+__all__ = ["Plan", "WaveFn", "l2_misfit", "ACOUSTIC", "ELASTIC"]
+
+
+def _stream() -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t: torch.Tensor) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _need(t: torch.Tensor, shape, name: str, dtype=torch.float32):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+class Plan:
+    """A modelling problem on one GPU: all shots advance in the same launches.
+
+    src_xz: int array [nshots, 2] of model-grid cells (x, z);
+    rec_xz: int array [nshots, nrec, 2]. Model tensors are [nparam, nz, nx]
+    (acoustic: vp only, so [nz, nx] is also accepted).
+    """
+
+    def __init__(self, *, nx: int, nz: int, h: float, dt: float, nt: int, pml: int,
+                 src_xz, rec_xz, pml_vmax: float, pml_f0: float, pml_R: float = 1e-3,
+                 ckpt_every: int = 50, physics: int = ACOUSTIC, free_surface: int = 0,
+                 device: Optional[torch.device] = None):
+        src = np.ascontiguousarray(src_xz, dtype=np.int32)
+        rec = np.ascontiguousarray(rec_xz, dtype=np.int32)
+        if src.ndim != 2 or src.shape[1] != 2:
+            raise ValueError("src_xz must be [nshots, 2]")
+        if rec.ndim != 3 or rec.shape[0] != src.shape[0] or rec.shape[2] != 2:
+            raise ValueError("rec_xz must be [nshots, nrec, 2]")
+        self.pb = Problem(physics, nx, nz, pml, free_surface, h, dt, nt, pml_vmax, pml_f0,
+                          pml_R, ckpt_every, src.shape[0], rec.shape[1])
+        self.nshots, self.nrec, self.nt, self.nx, self.nz = (src.shape[0], rec.shape[1], nt,
+                                                               nx, nz)
+        self.physics = physics
+        self.nparam = 1 if physics == ACOUSTIC else 3
+        self.ncomp = 1 if physics == ACOUSTIC else 2
+        self.device = torch.device(device) if device is not None else torch.device("cuda")
+        self._src, self._rec = src, rec
+        h_ = ctypes.c_void_p()
+        check(lib().sweep_plan_create(ctypes.byref(self.pb), src.ctypes.data_as(ctypes.c_void_p),
+                                      rec.ctypes.data_as(ctypes.c_void_p), ctypes.byref(h_)))
+        self._h = h_
+        self._work = None
+        self._fwd_id = 0
+        self._saved_id = -1
+
+    @classmethod
+    def from_workload(cls, w, **kw) -> "Plan":
+        """Plan for a synth.Workload (its sources, receivers and constants)."""
+        args = dict(nx=w.nx, nz=w.nz, h=w.h, dt=w.dt, nt=w.nt, pml=w.pml,
+                    src_xz=w.sources(), rec_xz=w.receivers(), pml_vmax=w.pml_vmax(),
+                    pml_f0=w.f0, pml_R=w.pml_R, ckpt_every=w.ckpt_every,
+                    physics=ACOUSTIC if w.physics == "acoustic" else ELASTIC,
+                    free_surface=w.free_surface)
+        args.update(kw)
+        return cls(**args)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            try:
+                lib().sweep_plan_destroy(h)
+            except Exception:
+                pass
+            self._h = None
+
+    # ---------------------------------------------------------------- tuning
+    @property
+    def tuning(self) -> dict:
+        t = Tuning()
+        check(lib().sweep_plan_get_tuning(self._h, ctypes.byref(t)))
+        return {"rz": t.rz, "shots_per_block": t.shots_per_block, "use_graph": t.use_graph}
+
+    def set_tuning(self, rz: int = 8, shots_per_block: int = 1, use_graph: int = 0):
+        t = Tuning(rz, shots_per_block, use_graph)
+        check(lib().sweep_plan_set_tuning(self._h, ctypes.byref(t)))
+        self._saved_id = -1
+
+    def padded(self):
+        a, b = ctypes.c_int(), ctypes.c_int()
+        check(lib().sweep_plan_padded(self._h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
+    def workspace_bytes(self, for_backward: bool) -> int:
+        return int(lib().sweep_plan_workspace_bytes(self._h, int(bool(for_backward))))
+
+    def _workspace(self, for_backward: bool) -> torch.Tensor:
+        need = self.workspace_bytes(for_backward)
+        if self._work is None or self._work.numel() < need:
+            self._work = None
+            torch.cuda.synchronize(self.device)
+            self._work = torch.empty(need, dtype=torch.uint8, device=self.device)
+        return self._work
+
+    def release_workspace(self):
+        self._work = None
+        self._saved_id = -1
+
+    # ---------------------------------------------------------------- compute
+    def _model_shape(self):
+        return (self.nparam, self.nz, self.nx)
+
+    def gathers_shape(self):
+        if self.ncomp == 1:
+            return (self.nshots, self.nt, self.nrec)
+        return (self.nshots, self.nt, self.nrec, self.ncomp)
+
+    def forward(self, model: torch.Tensor, wavelet: torch.Tensor, save: bool = False,
+                out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """Shot gathers [nshots, nt, nrec(, ncomp)] for every shot."""
+        if self.nparam == 1 and model.dim() == 2:
+            model = model.unsqueeze(0)
+        _need(model, self._model_shape(), "model")
+        _need(wavelet, (self.nshots, self.nt), "wavelet")
+        if out is None:
+            out = torch.empty(self.gathers_shape(), dtype=torch.float32, device=model.device)
+        _need(out, self.gathers_shape(), "out")
+        work = self._workspace(save)
+        check(lib().sweep_forward(self._h, _ptr(model), _ptr(wavelet), _ptr(out), _ptr(work),
+                                  work.numel(), int(bool(save)), _stream()))
+        self._fwd_id += 1
+        self._saved_id = self._fwd_id if save else -1
+        return out
+
+    def backward(self, resid: torch.Tensor, out: Optional[torch.Tensor] = None,
+                 forward_id: Optional[int] = None) -> torch.Tensor:
+        """d(loss)/d(model) [nparam, nz, nx] for d(loss)/d(gathers) = resid."""
+        if self._saved_id < 0 or (forward_id is not None and forward_id != self._saved_id):
+            raise RuntimeError("backward() needs the state saved by the matching "
+                               "forward(save=True); a later forward overwrote it")
+        _need(resid, self.gathers_shape(), "resid")
+        if out is None:
+            out = torch.empty(self._model_shape(), dtype=torch.float32, device=resid.device)
+        _need(out, self._model_shape(), "out")
+        work = self._work
+        check(lib().sweep_backward(self._h, _ptr(resid), _ptr(out), _ptr(work), work.numel(),
+                                   _stream()))
+        return out
+
+    # ---------------------------------------------------------------- timing
+    KERNEL_CLASSES = ("fwd_interior", "fwd_frame", "adj_interior", "adj_frame",
+                      "rec_interior", "rec_frame")
+
+    def set_profiling(self, enable: bool):
+        check(lib().sweep_plan_set_profiling(self._h, int(bool(enable))))
+
+    def kernel_times(self) -> dict:
+        """{class: (launches, total_ms)} since the last set_profiling()."""
+        out = {}
+        for i, name in enumerate(self.KERNEL_CLASSES):
+            n, ms = ctypes.c_int(), ctypes.c_double()
+            check(lib().sweep_plan_kernel_time(self._h, i, ctypes.byref(n), ctypes.byref(ms)))
+            out[name] = (n.value, ms.value)
+        return out
+
+    @property
+    def last_forward_id(self) -> int:
+        return self._fwd_id
+
+
+class WaveFn(torch.autograd.Function):
+    """gathers = F(model); backward returns J^T grad_gathers via the adjoint."""
+
+    @staticmethod
+    def forward(ctx, model, wavelet, plan: Plan):
+        squeeze = plan.nparam == 1 and model.dim() == 2
+        g = plan.forward(model.contiguous(), wavelet.contiguous(), save=True)
+        ctx.plan = plan
+        ctx.fid = plan.last_forward_id
+        ctx.squeeze = squeeze
+        return g
+
+    @staticmethod
+    def backward(ctx, grad_g):
+        grad = ctx.plan.backward(grad_g.contiguous(), forward_id=ctx.fid)
+        if ctx.squeeze:
+            grad = grad[0]
+        return grad, None, None
+
+
+def l2_misfit(pred: torch.Tensor, obs: torch.Tensor):
+    """(resid, J): resid = pred - obs, J = 0.5 sum resid^2 (float64 tensor on device)."""
+    if pred.shape != obs.shape:
+        raise ValueError("pred and obs shapes differ")
+    _need(pred, pred.shape, "pred")
+    _need(obs, obs.shape, "obs")
+    n = pred.numel()
+    resid = torch.empty_like(pred)
+    J = torch.empty((), dtype=torch.float64, device=pred.device)
+    scratch = torch.empty(int(lib().sweep_l2_misfit_scratch_bytes(n)), dtype=torch.uint8,
+                          device=pred.device)
+    check(lib().sweep_l2_misfit(_ptr(pred), _ptr(obs), _ptr(resid), _ptr(J), n, _ptr(scratch),
+                                _stream()))
+    return resid, J

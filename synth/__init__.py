@@ -23,7 +23,7 @@ from typing import List, Optional, Tuple
 import numpy as np
 
 __all__ = [
-    "ricker", "layered_anomaly", "interface_model", "smooth", "elastic_model",
+    "ricker", "bandlimited_noise", "layered_anomaly", "interface_model", "smooth", "elastic_model",
     "surface_shots", "line_receivers", "Workload", "workload", "batched_workloads",
     "WORKLOADS",
 ]
@@ -106,6 +106,22 @@ def line_receivers(nx: int, nshots: int, depth: int, nrec: Optional[int] = None)
         xs = np.floor((np.arange(nrec) + 0.5) * nx / nrec).astype(np.int32)
     one = np.stack([xs, np.full(len(xs), depth, np.int32)], axis=1)
     return np.ascontiguousarray(np.broadcast_to(one, (nshots,) + one.shape)).astype(np.int32)
+
+
+def bandlimited_noise(shape, f0: float, dt: float, seed: int) -> np.ndarray:
+    """Seeded white noise along the last-but-one (time) axis of `shape`
+    [..., nt, nrec], filtered by a Ricker of peak f0 so it lies in the band of
+    the simulation; a stand-in residual for adjoint tests."""
+    rng = np.random.default_rng(seed)
+    x = rng.standard_normal(shape)
+    w = ricker(f0, int(round(3.0 / f0 / dt)) + 1, dt, delay=1.5 / f0)
+    from scipy.signal import fftconvolve
+    k = w.reshape((1,) * (x.ndim - 2) + (-1, 1))
+    y = fftconvolve(x, k, mode="full", axes=x.ndim - 2)
+    n0 = (len(w) - 1) // 2
+    sl = [slice(None)] * x.ndim
+    sl[x.ndim - 2] = slice(n0, n0 + shape[-2])
+    return np.ascontiguousarray(y[tuple(sl)])
 
 
 @dataclasses.dataclass

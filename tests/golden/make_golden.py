@@ -1,0 +1,46 @@
+"""Writes the stored oracle values used by the full-size parity test.
+
+Calls only the FP64 oracle (oracle/) and the seeded input generators (synth);
+nothing here touches the HIP library.
+
+    python tests/golden/make_golden.py
+
+layered1000x300_shot37.npz: shot 37 of the 1000x300 / 3000-step / 40-cell-pad
+acoustic workload (64 shots, 1000 receivers at depth 5, 8 Hz Ricker). Stores
+8 complete receiver traces and the model gradient for a band-limited seeded
+residual on that shot (20 000 sampled cells plus the full gradient norm).
+"""
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+import oracle  # noqa: E402
+import synth  # noqa: E402
+from tests.helpers import case_from_workload, f32  # noqa: E402
+
+
+def layered_shot37(path):
+    w = synth.workload("layered1000x300")
+    s = 37
+    case = case_from_workload(w, shots=[s])
+    pb = case.oracle_problem(oracle)
+    resid = f32(synth.bandlimited_noise((1, w.nt, w.nrec), w.f0, w.dt, 37))
+    t = time.time()
+    g, _, d = oracle.ac_gradient(pb, case.v, case.src, case.wav, case.rec, resid,
+                                 want_gathers=True)
+    print("oracle gradient took %.1f s" % (time.time() - t), flush=True)
+    trace_idx = np.linspace(0, w.nrec - 1, 8).round().astype(np.int64)
+    cells = np.random.default_rng(37).choice(g.size, 20000, replace=False)
+    np.savez_compressed(path, shot=s, trace_idx=trace_idx, traces=d[0][:, trace_idx],
+                        grad_cells=cells, grad=g.ravel()[cells],
+                        grad_norm=np.linalg.norm(g))
+
+
+if __name__ == "__main__":
+    oracle.build(force=False)
+    layered_shot37(os.path.join(HERE, "layered1000x300_shot37.npz"))
