@@ -31,15 +31,23 @@ constexpr float kB2 = -1.0f / 5.0f;
 constexpr float kB3 = 4.0f / 105.0f;
 constexpr float kB4 = -1.0f / 280.0f;
 
+// The library is built with -ffp-contract=off and every fused multiply-add is
+// written out, so each kernel variant rounds identically (results are bitwise
+// independent of the tiling and of which kernel handles a cell).
 __device__ __forceinline__ float d2c(float c, float p1, float m1, float p2, float m2, float p3,
                                      float m3, float p4, float m4) {
-  return kA1 * ((p1 - c) + (m1 - c)) + kA2 * ((p2 - c) + (m2 - c)) +
-         kA3 * ((p3 - c) + (m3 - c)) + kA4 * ((p4 - c) + (m4 - c));
+  float s = kA1 * ((p1 - c) + (m1 - c));
+  s = fmaf(kA2, (p2 - c) + (m2 - c), s);
+  s = fmaf(kA3, (p3 - c) + (m3 - c), s);
+  return fmaf(kA4, (p4 - c) + (m4 - c), s);
 }
 
 __device__ __forceinline__ float d1c(float p1, float m1, float p2, float m2, float p3, float m3,
                                      float p4, float m4) {
-  return kB1 * (p1 - m1) + kB2 * (p2 - m2) + kB3 * (p3 - m3) + kB4 * (p4 - m4);
+  float s = kB1 * (p1 - m1);
+  s = fmaf(kB2, p2 - m2, s);
+  s = fmaf(kB3, p3 - m3, s);
+  return fmaf(kB4, p4 - m4, s);
 }
 
 // Column of an x-strip memory variable, or -1 outside the strip.
@@ -149,7 +157,7 @@ __global__ __launch_bounds__(kThreads) void ac_fwd_interior(AcStep a) {
     const int idx = (z0 + zb + r) * NX + gx;
     const size_t gi = shot * plane + idx;
     const float pp = a.prev[gi];
-    float pn = 2.0f * c - pp + a.Cs[idx] * B;
+    float pn = fmaf(a.Cs[idx], B, 2.0f * c - pp);
     if (idx == src) pn += sw;
     a.next[gi] = pn;
     if (a.B_out) a.B_out[gi] = B;
@@ -220,7 +228,7 @@ __global__ __launch_bounds__(kThreads) void ac_fwd_frame(AcStep a) {
         const float d1 = d1c(q[1], q[-1], q[2], q[-2], q[3], q[-3], q[4], q[-4]);
         const size_t si = shot * xs_plane + (size_t)gz * P2 + col;
         const float old = a.psx_in[si];
-        v = a.bx[gx] * old + a.ax[gx] * d1;
+        v = fmaf(a.ax[gx], d1, a.bx[gx] * old);
         if (lc >= 4 && lc < 4 + kTX) {
           a.psx_out[si] = v;
           if (a.ck_psx) a.ck_psx[si] = old;
@@ -242,7 +250,7 @@ __global__ __launch_bounds__(kThreads) void ac_fwd_frame(AcStep a) {
                              q[4 * PW], q[-4 * PW]);
         const size_t si = shot * zs_plane + (size_t)row * NX + gx;
         const float old = a.psz_in[si];
-        v = a.bz[gz] * old + a.az[gz] * d1;
+        v = fmaf(a.az[gz], d1, a.bz[gz] * old);
         if (lz >= 4 && lz < 4 + TZ) {
           a.psz_out[si] = v;
           if (a.ck_psz) a.ck_psz[si] = old;
@@ -275,7 +283,7 @@ __global__ __launch_bounds__(kThreads) void ac_fwd_frame(AcStep a) {
       if (col >= 0) {
         const size_t si = shot * xs_plane + (size_t)gz * P2 + col;
         const float old = a.zex_in[si];
-        zx = a.bx[gx] * old + a.ax[gx] * Qx;
+        zx = fmaf(a.ax[gx], Qx, a.bx[gx] * old);
         a.zex_out[si] = zx;
         if (a.ck_zex) a.ck_zex[si] = old;
       }
@@ -283,7 +291,7 @@ __global__ __launch_bounds__(kThreads) void ac_fwd_frame(AcStep a) {
       if (row >= 0) {
         const size_t si = shot * zs_plane + (size_t)row * NX + gx;
         const float old = a.zez_in[si];
-        zz = a.bz[gz] * old + a.az[gz] * Qz;
+        zz = fmaf(a.az[gz], Qz, a.bz[gz] * old);
         a.zez_out[si] = zz;
         if (a.ck_zez) a.ck_zez[si] = old;
       }
@@ -291,7 +299,7 @@ __global__ __launch_bounds__(kThreads) void ac_fwd_frame(AcStep a) {
       const int idx = gz * NX + gx;
       const size_t gi = shot * plane + idx;
       const float pp = a.prev[gi];
-      pn = 2.0f * c - pp + a.Cs[idx] * B;
+      pn = fmaf(a.Cs[idx], B, 2.0f * c - pp);
       if (idx == src) pn += sw;
       a.next[gi] = pn;
       if (a.B_out) a.B_out[gi] = B;
@@ -381,10 +389,12 @@ __global__ __launch_bounds__(kThreads) void ac_adj_interior(AcStep a) {
                           win[r + 1], win[r + 8], win[r]);
     const int idx = (z0 + zb + r) * NX + gx;
     const size_t gi = shot * plane + idx;
-    const float p1 = cur[gi];
+    const float p1 = a.cur[gi];
     const float gb = p1 * a.B_in[gi];
     a.g[gi] = a.g_init ? gb : a.g[gi] + gb;
-    out[r] = (2.0f * p1 - a.prev[gi]) + (sxx + szz);
+    // same association as the frame kernel, so a cell's value does not depend
+    // on which kernel updates it
+    out[r] = ((2.0f * p1 - a.prev[gi]) + sxx) + szz;
   }
 
   const int* ro = a.rec_off + (size_t)shot * a.ntiles + tile;
@@ -443,7 +453,7 @@ __global__ __launch_bounds__(kThreads) void ac_adj_frame(AcStep a) {
       if (col >= 0) {
         const size_t si = shot * xs_plane + (size_t)gz * P2 + col;
         const float zb = a.zex_in[si] + cp;
-        q = cp + a.ax[gx] * zb;
+        q = fmaf(a.ax[gx], zb, cp);
         if (lc >= 8 && lc < 8 + kTX) a.zex_out[si] = a.bx[gx] * zb;
       }
     }
@@ -461,7 +471,7 @@ __global__ __launch_bounds__(kThreads) void ac_adj_frame(AcStep a) {
       if (row >= 0) {
         const size_t si = shot * zs_plane + (size_t)row * NX + gx;
         const float zb = a.zez_in[si] + cp;
-        q = cp + a.az[gz] * zb;
+        q = fmaf(a.az[gz], zb, cp);
         if (lz >= 8 && lz < 8 + TZ) a.zez_out[si] = a.bz[gz] * zb;
       }
     }
@@ -522,7 +532,7 @@ __global__ __launch_bounds__(kThreads) void ac_adj_frame(AcStep a) {
       const float d1z = d1c(tz[kTX], tz[-kTX], tz[2 * kTX], tz[-2 * kTX], tz[3 * kTX],
                             tz[-3 * kTX], tz[4 * kTX], tz[-4 * kTX]);
       const size_t gi = shot * plane + (size_t)gz * NX + gx;
-      const float p1 = cur[gi];
+      const float p1 = a.cur[gi];
       const float gb = p1 * a.B_in[gi];
       a.g[gi] = a.g_init ? gb : a.g[gi] + gb;
       lam = (((2.0f * p1 - a.prev[gi]) + d2x) + d2z) - d1x - d1z;
