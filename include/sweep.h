@@ -125,8 +125,9 @@ int sweep_backward(sweep_plan* plan, const float* d_resid, float* d_grad, void* 
 /* Kernel timing for measurement tools. When enabled, every launch of the step
  * kernels is bracketed by a pair of hipEvents recorded on the call's stream
  * (the events add a few microseconds per launch). Classes:
- *   0 forward interior, 1 forward pad-frame, 2 adjoint interior,
- *   3 adjoint pad-frame, 4 recompute interior (also stores B^n), 5 recompute frame.
+ *   0 forward main (whole-grid stencil), 1 forward C-PML bands (x and z band
+ *   kernels of one step, timed together), 2 adjoint main, 3 adjoint bands,
+ *   4 recompute main (also stores B^n), 5 recompute bands.
  * sweep_plan_set_profiling resets the counters; sweep_plan_kernel_time waits for
  * the recorded events and returns the number of launches and their summed
  * duration in milliseconds since the reset. */

@@ -7,13 +7,17 @@
 //   Cs = (v dt / h)^2, D2' = h^2 D2, D1' = h D1, psi' = h psi, zeta' = h^2 zeta,
 //   B' = h^2 B, so p^{n+1} = 2 p^n - p^{n-1} + Cs B'^n + (dt/h)^2 s_n e_src.
 //
-// Every work-group covers a 64-column x TZ-row tile of one shot. Interior tiles
-// (the tile and its 4-cell halo clear of the pad) run the plain update with a
-// halo tile of p staged in LDS and TZ/4 rows per thread held in registers, so
-// each HBM array is read once per cell. Tiles touching the pad run a general
-// kernel that stages p with an 8-cell halo and computes the memory variables
-// for the halo redundantly; memory variables are double-buffered so no
-// work-group reads a value another one is overwriting in the same launch.
+// Decomposition of one step. B' = D2' p + Ex + Ez, where the C-PML part
+//   Ex = D1x' psi_x + zeta_x   is non-zero only in the x band (columns within
+//   P+4 of the left/right edges) and Ez likewise in the z band. Per step:
+//   1. band kernels (x, then z): update the memory variables and fold the pad
+//      terms into the previous field in place, p^{n-1} <- p^{n-1} - Cs E;
+//   2. main kernel over the whole grid: p^{n+1} = 2 p^n - p^{n-1} + Cs D2' p^n,
+//      source injection and receiver recording.
+// The adjoint is the same split of the transposed recurrence. The main kernel
+// stages a 4-cell halo tile of the field in LDS and keeps RZ rows per thread in
+// registers; the band kernels are 1-D along their axis (a wave per row segment
+// for x, a 64-column slab for z) and touch only the band cells.
 #include "internal.h"
 
 namespace sweep {
@@ -33,7 +37,7 @@ constexpr float kB4 = -1.0f / 280.0f;
 
 // The library is built with -ffp-contract=off and every fused multiply-add is
 // written out, so each kernel variant rounds identically (results are bitwise
-// independent of the tiling and of which kernel handles a cell).
+// independent of the tiling).
 __device__ __forceinline__ float d2c(float c, float p1, float m1, float p2, float m2, float p3,
                                      float m3, float p4, float m4) {
   float s = kA1 * ((p1 - c) + (m1 - c));
@@ -50,6 +54,16 @@ __device__ __forceinline__ float d1c(float p1, float m1, float p2, float m2, flo
   return fmaf(kB4, p4 - m4, s);
 }
 
+// Stencils on a strided LDS array centred at f.
+__device__ __forceinline__ float d2s(const float* f, int st) {
+  return d2c(f[0], f[st], f[-st], f[2 * st], f[-2 * st], f[3 * st], f[-3 * st], f[4 * st],
+             f[-4 * st]);
+}
+__device__ __forceinline__ float d1s(const float* f, int st) {
+  return d1c(f[st], f[-st], f[2 * st], f[-2 * st], f[3 * st], f[-3 * st], f[4 * st],
+             f[-4 * st]);
+}
+
 // Column of an x-strip memory variable, or -1 outside the strip.
 __device__ __forceinline__ int xstrip_col(int gx, int NX, int P) {
   if (gx < P) return gx;
@@ -61,6 +75,12 @@ __device__ __forceinline__ int zstrip_row(int gz, int NZ, int P) {
   if (gz < P) return gz;
   if (gz >= NZ - P) return gz - (NZ - 2 * P);
   return -1;
+}
+__device__ __forceinline__ bool in_xband(int gx, int NX, int P) {
+  return P > 0 && (gx < P + 4 || gx >= NX - P - 4);
+}
+__device__ __forceinline__ bool in_zband(int gz, int NZ, int P) {
+  return P > 0 && (gz < P + 4 || gz >= NZ - P - 4);
 }
 
 // ---------------------------------------------------------------------------
@@ -105,65 +125,106 @@ __global__ void ac_tables_kernel(float* ax, float* bx, float* az, float* bz, int
 }
 
 // ---------------------------------------------------------------------------
-// Forward step, interior tiles. TZ = 4 RZ rows; thread (lx, wz) owns column lx
-// and rows [wz RZ, wz RZ + RZ) of the tile.
+// Main kernels: a 64 x TZ tile per work-group, TZ = 4 RZ; thread (lx, w) owns
+// column lx and rows [w RZ, w RZ + RZ). Tiles whose 4-cell halo lies inside
+// the grid take unguarded loads; edge tiles zero-fill outside the grid.
 // ---------------------------------------------------------------------------
 template <int RZ>
-__global__ __launch_bounds__(kThreads) void ac_fwd_interior(AcStep a) {
-  constexpr int TZ = 4 * RZ;
-  constexpr int LW = kTX + 8;
-  constexpr int LH = TZ + 8;
-  __shared__ float sp[LH * LW];
+struct MainTile {
+  static constexpr int TZ = 4 * RZ;
+  static constexpr int LW = kTX + 8;
+  static constexpr int LH = TZ + 8;
+};
 
+// Stage f (or g * f, pointwise) on the tile plus a 4-cell halo. Every thread
+// issues all of its loads before the first LDS store, so a work-group keeps
+// ~12 (or ~24 for the product) loads per lane in flight instead of one.
+template <int RZ, bool kProduct>
+__device__ __forceinline__ void stage_box(float* s, const float* __restrict__ f,
+                                          const float* __restrict__ g, int x0, int z0, int NX,
+                                          int NZ, bool inside) {
+  using T = MainTile<RZ>;
+  constexpr int N = T::LH * T::LW;
+  constexpr int K = (N + kThreads - 1) / kThreads;
+  const int tid = threadIdx.x;
+  float v[K], u[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int e = tid + k * kThreads;
+    const int r = e / T::LW;
+    const int c = e - r * T::LW;
+    const int gx = x0 - 4 + c, gz = z0 - 4 + r;
+    const bool ok = e < N && (inside || (gx >= 0 && gx < NX && gz >= 0 && gz < NZ));
+    const size_t idx = ok ? (size_t)gz * NX + gx : 0;
+    v[k] = ok ? f[idx] : 0.0f;
+    if (kProduct) u[k] = ok ? g[idx] : 0.0f;
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int e = tid + k * kThreads;
+    if (e < N) s[e] = kProduct ? u[k] * v[k] : v[k];
+  }
+}
+
+template <int RZ>
+__global__ __launch_bounds__(kThreads) void ac_fwd_main(AcStep a) {
+  using T = MainTile<RZ>;
+  __shared__ float sp[T::LH * T::LW];
   const int tid = threadIdx.x;
   const int lx = tid & 63;
   const int zb = (tid >> 6) * RZ;
-  const int t = blockIdx.x;
-  const int tx = a.int_tx0 + t % a.int_ntx;
-  const int tz = a.int_tz0 + t / a.int_ntx;
-  const int tile = tz * a.tiles_x + tx;
+  const int tile = blockIdx.x;
   const int shot = blockIdx.y;
-  const int NX = a.NX;
-  const size_t plane = (size_t)NX * a.NZ;
-  const int x0 = tx * kTX, z0 = tz * TZ;
-  const float* __restrict__ cur = a.cur + shot * plane;
+  const int NX = a.NX, NZ = a.NZ, P = a.P;
+  const size_t plane = (size_t)NX * NZ;
+  const int x0 = (tile % a.tiles_x) * kTX, z0 = (tile / a.tiles_x) * T::TZ;
+  const bool inside = x0 >= 4 && x0 + kTX + 4 <= NX && z0 >= 4 && z0 + T::TZ + 4 <= NZ;
+  const int gx = x0 + lx;
 
-  {  // stage p^n with a 4-cell halo (entirely inside the grid)
-    const float* base = cur + (size_t)(z0 - 4) * NX + (x0 - 4);
-    for (int e = tid; e < LH * LW; e += kThreads) {
-      const int r = e / LW;
-      const int c = e - r * LW;
-      sp[e] = base[(size_t)r * NX + c];
+  // the per-cell operands are fetched first so their latency overlaps the
+  // staging of the halo tile
+  float pp[RZ], cs[RZ], bo[RZ];
+  const bool xb = in_xband(gx, NX, P);
+#pragma unroll
+  for (int r = 0; r < RZ; ++r) {
+    const int gz = z0 + zb + r;
+    pp[r] = 0.0f;
+    cs[r] = 0.0f;
+    bo[r] = 0.0f;
+    if (inside || (gx < NX && gz < NZ)) {
+      const int idx = gz * NX + gx;
+      pp[r] = a.prev[shot * plane + idx];
+      cs[r] = a.Cs[idx];
+      if (a.B_out && (xb || in_zband(gz, NZ, P))) bo[r] = a.B_out[shot * plane + idx];
     }
   }
+  stage_box<RZ, false>(sp, a.cur + shot * plane, nullptr, x0, z0, NX, NZ, inside);
   __syncthreads();
 
   float win[RZ + 8];
 #pragma unroll
-  for (int m = 0; m < RZ + 8; ++m) win[m] = sp[(zb + m) * LW + lx + 4];
+  for (int m = 0; m < RZ + 8; ++m) win[m] = sp[(zb + m) * T::LW + lx + 4];
 
-  const int gx = x0 + lx;
   const int src = a.src_cell[shot];
   const float sw = a.w * a.wavelet[(size_t)shot * a.nt + a.n];
   float out[RZ];
 #pragma unroll
   for (int r = 0; r < RZ; ++r) {
-    const float* row = &sp[(zb + r + 4) * LW + lx + 4];
+    const float* row = &sp[(zb + r + 4) * T::LW + lx + 4];
     const float c = win[r + 4];
     const float sx = d2c(c, row[1], row[-1], row[2], row[-2], row[3], row[-3], row[4], row[-4]);
     const float sz = d2c(c, win[r + 5], win[r + 3], win[r + 6], win[r + 2], win[r + 7],
                          win[r + 1], win[r + 8], win[r]);
-    const float B = sx + sz;
-    const int idx = (z0 + zb + r) * NX + gx;
-    const size_t gi = shot * plane + idx;
-    const float pp = a.prev[gi];
-    float pn = fmaf(a.Cs[idx], B, 2.0f * c - pp);
-    if (idx == src) pn += sw;
-    a.next[gi] = pn;
-    if (a.B_out) a.B_out[gi] = B;
-    if (a.ck_cur) {
-      a.ck_cur[gi] = c;
-      a.ck_prev[gi] = pp;
+    const float L = sx + sz;
+    const int gz = z0 + zb + r;
+    float pn = 0.0f;
+    if (inside || (gx < NX && gz < NZ)) {
+      const int idx = gz * NX + gx;
+      const size_t gi = shot * plane + idx;
+      pn = fmaf(cs[r], L, 2.0f * c - pp[r]);
+      if (idx == src) pn += sw;
+      a.next[gi] = pn;
+      if (a.B_out) a.B_out[gi] = (xb || in_zband(gz, NZ, P)) ? L + bo[r] : L;
     }
     out[r] = pn;
   }
@@ -184,145 +245,6 @@ __global__ __launch_bounds__(kThreads) void ac_fwd_interior(AcStep a) {
   }
 }
 
-// ---------------------------------------------------------------------------
-// Forward step, tiles touching the pad (general form with memory variables).
-// ---------------------------------------------------------------------------
-template <int TZ>
-__global__ __launch_bounds__(kThreads) void ac_fwd_frame(AcStep a) {
-  constexpr int PW = kTX + 16;  // p with an 8-cell halo
-  constexpr int PH = TZ + 16;
-  constexpr int XW = kTX + 8;   // psi_x on the tile rows, 4-cell x halo
-  constexpr int ZH = TZ + 8;    // psi_z on the tile columns, 4-cell z halo
-  __shared__ float sp[PH * PW];
-  __shared__ float sx[TZ * XW];
-  __shared__ float sz[ZH * kTX];
-  __shared__ float st[TZ * kTX];
-
-  const int tid = threadIdx.x;
-  const int tile = a.frame_tiles[blockIdx.x];
-  const int shot = blockIdx.y;
-  const int NX = a.NX, NZ = a.NZ, P = a.P, P2 = 2 * a.P;
-  const size_t plane = (size_t)NX * NZ;
-  const size_t xs_plane = (size_t)NZ * P2;
-  const size_t zs_plane = (size_t)P2 * NX;
-  const int x0 = (tile % a.tiles_x) * kTX;
-  const int z0 = (tile / a.tiles_x) * TZ;
-  const float* __restrict__ cur = a.cur + shot * plane;
-
-  for (int e = tid; e < PH * PW; e += kThreads) {
-    const int lz = e / PW, lc = e - lz * PW;
-    const int gx = x0 - 8 + lc, gz = z0 - 8 + lz;
-    sp[e] = (gx >= 0 && gx < NX && gz >= 0 && gz < NZ) ? cur[(size_t)gz * NX + gx] : 0.0f;
-  }
-  __syncthreads();
-
-  // psi_x^n = b_x psi_x^{n-1} + a_x D1x' p^n on the tile rows, columns x0-4 .. x0+67
-  for (int e = tid; e < TZ * XW; e += kThreads) {
-    const int lz = e / XW, lc = e - lz * XW;
-    const int gx = x0 - 4 + lc, gz = z0 + lz;
-    float v = 0.0f;
-    if (gz < NZ && gx >= 0 && gx < NX) {
-      const int col = xstrip_col(gx, NX, P);
-      if (col >= 0) {
-        const float* q = &sp[(lz + 8) * PW + lc + 4];
-        const float d1 = d1c(q[1], q[-1], q[2], q[-2], q[3], q[-3], q[4], q[-4]);
-        const size_t si = shot * xs_plane + (size_t)gz * P2 + col;
-        const float old = a.psx_in[si];
-        v = fmaf(a.ax[gx], d1, a.bx[gx] * old);
-        if (lc >= 4 && lc < 4 + kTX) {
-          a.psx_out[si] = v;
-          if (a.ck_psx) a.ck_psx[si] = old;
-        }
-      }
-    }
-    sx[e] = v;
-  }
-  // psi_z^n on the tile columns, rows z0-4 .. z0+TZ+3
-  for (int e = tid; e < ZH * kTX; e += kThreads) {
-    const int lz = e / kTX, lc = e - lz * kTX;
-    const int gx = x0 + lc, gz = z0 - 4 + lz;
-    float v = 0.0f;
-    if (gx < NX && gz >= 0 && gz < NZ) {
-      const int row = zstrip_row(gz, NZ, P);
-      if (row >= 0) {
-        const float* q = &sp[(lz + 4) * PW + lc + 8];
-        const float d1 = d1c(q[PW], q[-PW], q[2 * PW], q[-2 * PW], q[3 * PW], q[-3 * PW],
-                             q[4 * PW], q[-4 * PW]);
-        const size_t si = shot * zs_plane + (size_t)row * NX + gx;
-        const float old = a.psz_in[si];
-        v = fmaf(a.az[gz], d1, a.bz[gz] * old);
-        if (lz >= 4 && lz < 4 + TZ) {
-          a.psz_out[si] = v;
-          if (a.ck_psz) a.ck_psz[si] = old;
-        }
-      }
-    }
-    sz[e] = v;
-  }
-  __syncthreads();
-
-  const int src = a.src_cell[shot];
-  const float sw = a.w * a.wavelet[(size_t)shot * a.nt + a.n];
-  for (int e = tid; e < TZ * kTX; e += kThreads) {
-    const int lz = e / kTX, lc = e - lz * kTX;
-    const int gx = x0 + lc, gz = z0 + lz;
-    float pn = 0.0f;
-    if (gx < NX && gz < NZ) {
-      const float* pc = &sp[(lz + 8) * PW + lc + 8];
-      const float c = pc[0];
-      const float d2x = d2c(c, pc[1], pc[-1], pc[2], pc[-2], pc[3], pc[-3], pc[4], pc[-4]);
-      const float d2z = d2c(c, pc[PW], pc[-PW], pc[2 * PW], pc[-2 * PW], pc[3 * PW],
-                            pc[-3 * PW], pc[4 * PW], pc[-4 * PW]);
-      const float* qx = &sx[lz * XW + lc + 4];
-      const float* qz = &sz[(lz + 4) * kTX + lc];
-      const float Qx = d2x + d1c(qx[1], qx[-1], qx[2], qx[-2], qx[3], qx[-3], qx[4], qx[-4]);
-      const float Qz = d2z + d1c(qz[kTX], qz[-kTX], qz[2 * kTX], qz[-2 * kTX], qz[3 * kTX],
-                                 qz[-3 * kTX], qz[4 * kTX], qz[-4 * kTX]);
-      float zx = 0.0f, zz = 0.0f;
-      const int col = xstrip_col(gx, NX, P);
-      if (col >= 0) {
-        const size_t si = shot * xs_plane + (size_t)gz * P2 + col;
-        const float old = a.zex_in[si];
-        zx = fmaf(a.ax[gx], Qx, a.bx[gx] * old);
-        a.zex_out[si] = zx;
-        if (a.ck_zex) a.ck_zex[si] = old;
-      }
-      const int row = zstrip_row(gz, NZ, P);
-      if (row >= 0) {
-        const size_t si = shot * zs_plane + (size_t)row * NX + gx;
-        const float old = a.zez_in[si];
-        zz = fmaf(a.az[gz], Qz, a.bz[gz] * old);
-        a.zez_out[si] = zz;
-        if (a.ck_zez) a.ck_zez[si] = old;
-      }
-      const float B = ((Qx + zx) + Qz) + zz;
-      const int idx = gz * NX + gx;
-      const size_t gi = shot * plane + idx;
-      const float pp = a.prev[gi];
-      pn = fmaf(a.Cs[idx], B, 2.0f * c - pp);
-      if (idx == src) pn += sw;
-      a.next[gi] = pn;
-      if (a.B_out) a.B_out[gi] = B;
-      if (a.ck_cur) {
-        a.ck_cur[gi] = c;
-        a.ck_prev[gi] = pp;
-      }
-    }
-    st[e] = pn;
-  }
-
-  const int* ro = a.rec_off + (size_t)shot * a.ntiles + tile;
-  const int e0 = ro[0], e1 = ro[1];
-  if (a.gathers && e1 > e0) {
-    __syncthreads();
-    float* dst = a.gathers + ((size_t)shot * a.nt + a.n) * a.nrec;
-    for (int e = e0 + tid; e < e1; e += kThreads) {
-      const int2 en = a.rec_ent[e];
-      dst[en.y] = st[en.x];
-    }
-  }
-}
-
 // Adds r_{n-1} at the receivers of this (shot, tile) to the staged lambda values
 // st[local] (run heads handle several receivers on one cell, in receiver order).
 __device__ __forceinline__ void inject_residual(const AcStep& a, int shot, int tile, float* st) {
@@ -339,62 +261,61 @@ __device__ __forceinline__ void inject_residual(const AcStep& a, int shot, int t
   }
 }
 
-// ---------------------------------------------------------------------------
-// Adjoint step, interior tiles: lambda^n = 2 lambda^{n+1} - lambda^{n+2}
-// + D2'(Cs lambda^{n+1}); g += lambda^{n+1} B'^n; then r_{n-1} is injected.
-// ---------------------------------------------------------------------------
+// lambda^n = 2 lambda^{n+1} - lambda^{n+2}' + D2'(Cs lambda^{n+1}), where the band
+// kernels already subtracted their pad terms from lambda^{n+2}' in place;
+// g += lambda^{n+1} B'^n; then r_{n-1} is injected at the receivers.
 template <int RZ>
-__global__ __launch_bounds__(kThreads) void ac_adj_interior(AcStep a) {
-  constexpr int TZ = 4 * RZ;
-  constexpr int LW = kTX + 8;
-  constexpr int LH = TZ + 8;
-  __shared__ float sq[LH * LW];
-
+__global__ __launch_bounds__(kThreads) void ac_adj_main(AcStep a) {
+  using T = MainTile<RZ>;
+  __shared__ float sq[T::LH * T::LW];
   const int tid = threadIdx.x;
   const int lx = tid & 63;
   const int zb = (tid >> 6) * RZ;
-  const int t = blockIdx.x;
-  const int tx = a.int_tx0 + t % a.int_ntx;
-  const int tz = a.int_tz0 + t / a.int_ntx;
-  const int tile = tz * a.tiles_x + tx;
+  const int tile = blockIdx.x;
   const int shot = blockIdx.y;
-  const int NX = a.NX;
-  const size_t plane = (size_t)NX * a.NZ;
-  const int x0 = tx * kTX, z0 = tz * TZ;
-  const float* __restrict__ cur = a.cur + shot * plane;
+  const int NX = a.NX, NZ = a.NZ;
+  const size_t plane = (size_t)NX * NZ;
+  const int x0 = (tile % a.tiles_x) * kTX, z0 = (tile / a.tiles_x) * T::TZ;
+  const bool inside = x0 >= 4 && x0 + kTX + 4 <= NX && z0 >= 4 && z0 + T::TZ + 4 <= NZ;
+  const int gx = x0 + lx;
 
-  {  // stage q = Cs lambda^{n+1} with a 4-cell halo
-    const size_t off = (size_t)(z0 - 4) * NX + (x0 - 4);
-    for (int e = tid; e < LH * LW; e += kThreads) {
-      const int r = e / LW;
-      const int c = e - r * LW;
-      const size_t k = off + (size_t)r * NX + c;
-      sq[e] = a.Cs[k] * cur[k];
+  float p1[RZ], pp[RZ], bb[RZ], gg[RZ];
+#pragma unroll
+  for (int r = 0; r < RZ; ++r) {
+    const int gz = z0 + zb + r;
+    p1[r] = pp[r] = bb[r] = gg[r] = 0.0f;
+    if (inside || (gx < NX && gz < NZ)) {
+      const size_t gi = shot * plane + (size_t)gz * NX + gx;
+      p1[r] = a.cur[gi];
+      pp[r] = a.prev[gi];
+      bb[r] = a.B_in[gi];
+      if (!a.g_init) gg[r] = a.g[gi];
     }
   }
+  stage_box<RZ, true>(sq, a.cur + shot * plane, a.Cs, x0, z0, NX, NZ, inside);
   __syncthreads();
 
   float win[RZ + 8];
 #pragma unroll
-  for (int m = 0; m < RZ + 8; ++m) win[m] = sq[(zb + m) * LW + lx + 4];
+  for (int m = 0; m < RZ + 8; ++m) win[m] = sq[(zb + m) * T::LW + lx + 4];
 
-  const int gx = x0 + lx;
   float out[RZ];
 #pragma unroll
   for (int r = 0; r < RZ; ++r) {
-    const float* row = &sq[(zb + r + 4) * LW + lx + 4];
+    const float* row = &sq[(zb + r + 4) * T::LW + lx + 4];
     const float c = win[r + 4];
     const float sxx = d2c(c, row[1], row[-1], row[2], row[-2], row[3], row[-3], row[4], row[-4]);
     const float szz = d2c(c, win[r + 5], win[r + 3], win[r + 6], win[r + 2], win[r + 7],
                           win[r + 1], win[r + 8], win[r]);
-    const int idx = (z0 + zb + r) * NX + gx;
-    const size_t gi = shot * plane + idx;
-    const float p1 = a.cur[gi];
-    const float gb = p1 * a.B_in[gi];
-    a.g[gi] = a.g_init ? gb : a.g[gi] + gb;
-    // same association as the frame kernel, so a cell's value does not depend
-    // on which kernel updates it
-    out[r] = ((2.0f * p1 - a.prev[gi]) + sxx) + szz;
+    const int gz = z0 + zb + r;
+    float lam = 0.0f;
+    if (inside || (gx < NX && gz < NZ)) {
+      const size_t gi = shot * plane + (size_t)gz * NX + gx;
+      const float gb = p1[r] * bb[r];
+      a.g[gi] = a.g_init ? gb : gg[r] + gb;
+      lam = ((2.0f * p1[r] - pp[r]) + sxx) + szz;
+    }
+    out[r] = lam;
   }
 
   const int* ro = a.rec_off + (size_t)shot * a.ntiles + tile;
@@ -409,151 +330,325 @@ __global__ __launch_bounds__(kThreads) void ac_adj_interior(AcStep a) {
     for (int r = 0; r < RZ; ++r) out[r] = sq[(zb + r) * kTX + lx];
   }
 #pragma unroll
-  for (int r = 0; r < RZ; ++r) a.next[shot * plane + (size_t)(z0 + zb + r) * NX + gx] = out[r];
+  for (int r = 0; r < RZ; ++r) {
+    const int gz = z0 + zb + r;
+    if (inside || (gx < NX && gz < NZ)) a.next[shot * plane + (size_t)gz * NX + gx] = out[r];
+  }
 }
 
 // ---------------------------------------------------------------------------
-// Adjoint step, tiles touching the pad (exact transpose of ac_fwd_frame):
-//   zbar = Z + Cs P1, Qbar = Cs P1 + a zbar, psbar = Psi - D1' Qbar,
-//   lambda = 2 P1 - P1prev + D2x' Qbar_x + D2z' Qbar_z - D1x'(a_x psbar_x) - D1z'(a_z psbar_z),
-//   Psi <- b psbar, Z <- b zbar (kept only inside the strips, where a != 0).
+// x band (columns within P+4 of the left/right edges, all rows). One wave per
+// (row, chunk): lane l holds column c0 - 8 + l; a chunk produces up to 48
+// outputs (lanes 8 .. 8+W) and reads an 8-cell halo on each side.
 // ---------------------------------------------------------------------------
-template <int TZ>
-__global__ __launch_bounds__(kThreads) void ac_adj_frame(AcStep a) {
-  constexpr int QXW = kTX + 16;  // Qbar_x: tile rows, 8-cell x halo
-  constexpr int QZH = TZ + 16;   // Qbar_z: tile columns, 8-cell z halo
-  constexpr int TXW = kTX + 8;   // a_x psbar_x: 4-cell x halo
-  constexpr int TZH = TZ + 8;    // a_z psbar_z: 4-cell z halo
-  __shared__ float sqx[TZ * QXW];
-  __shared__ float sqz[QZH * kTX];
-  __shared__ float stx[TZ * TXW];
-  __shared__ float stz[TZH * kTX];
-  __shared__ float st[TZ * kTX];
+constexpr int kChunk = 48;
 
-  const int tid = threadIdx.x;
-  const int tile = a.frame_tiles[blockIdx.x];
-  const int shot = blockIdx.y;
-  const int NX = a.NX, NZ = a.NZ, P = a.P, P2 = 2 * a.P;
+// Rows handled by one wave of an x-band work-group (a work-group covers
+// 4 * kXRows consecutive rows of one chunk). All global operands of a wave's
+// rows are loaded before any of them is used.
+constexpr int kXRows = 4;
+
+// psi_x^n, zeta_x^n and Ex = D1x' psi_x^n + zeta_x^n; p^{n-1} -= Cs Ex.
+__global__ __launch_bounds__(kThreads) void ac_fwd_xband(AcStep a) {
+  __shared__ float sp[4][kXRows][64];
+  __shared__ float ss[4][kXRows][64];
+  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int2 ch = a.xchunks[blockIdx.x];
+  const int shot = blockIdx.z;
+  const int NX = a.NX, NZ = a.NZ, P = a.P, P2 = 2 * P;
+  const int gx = ch.x - 8 + l;
   const size_t plane = (size_t)NX * NZ;
-  const size_t xs_plane = (size_t)NZ * P2;
-  const size_t zs_plane = (size_t)P2 * NX;
-  const int x0 = (tile % a.tiles_x) * kTX;
-  const int z0 = (tile / a.tiles_x) * TZ;
-  const float* __restrict__ cur = a.cur + shot * plane;
-
-  for (int e = tid; e < TZ * QXW; e += kThreads) {
-    const int lz = e / QXW, lc = e - lz * QXW;
-    const int gx = x0 - 8 + lc, gz = z0 + lz;
-    float q = 0.0f;
-    if (gx >= 0 && gx < NX && gz < NZ) {
-      const size_t k = (size_t)gz * NX + gx;
-      const float cp = a.Cs[k] * cur[k];
-      q = cp;
-      const int col = xstrip_col(gx, NX, P);
-      if (col >= 0) {
-        const size_t si = shot * xs_plane + (size_t)gz * P2 + col;
-        const float zb = a.zex_in[si] + cp;
-        q = fmaf(a.ax[gx], zb, cp);
-        if (lc >= 8 && lc < 8 + kTX) a.zex_out[si] = a.bx[gx] * zb;
-      }
-    }
-    sqx[e] = q;
+  const bool own = l >= 8 && l < 8 + ch.y;
+  const bool col_ok = gx >= 0 && gx < NX;
+  const int col0 = col_ok ? xstrip_col(gx, NX, P) : -1;
+  const float axv = col0 >= 0 ? a.ax[gx] : 0.0f, bxv = col0 >= 0 ? a.bx[gx] : 0.0f;
+  const int gz0 = (blockIdx.y * 4 + w) * kXRows;
+  float pv[kXRows], psio[kXRows], zo[kXRows], cs[kXRows], pp[kXRows];
+#pragma unroll
+  for (int rr = 0; rr < kXRows; ++rr) {
+    const int gz = gz0 + rr;
+    const bool in_grid = col_ok && gz < NZ;
+    const bool strip = in_grid && col0 >= 0;
+    const size_t si = shot * (size_t)NZ * P2 + (size_t)gz * P2 + (strip ? col0 : 0);
+    const size_t gi = shot * plane + (size_t)gz * NX + (in_grid ? gx : 0);
+    pv[rr] = in_grid ? a.cur[gi] : 0.0f;
+    psio[rr] = (strip && l >= 4 && l < 60) ? a.psx_in[si] : 0.0f;
+    zo[rr] = (strip && own) ? a.zex_in[si] : 0.0f;
+    cs[rr] = (in_grid && own) ? a.Cs[(size_t)gz * NX + gx] : 0.0f;
+    pp[rr] = (in_grid && own) ? a.prev_adj[gi] : 0.0f;
   }
-  for (int e = tid; e < QZH * kTX; e += kThreads) {
-    const int lz = e / kTX, lc = e - lz * kTX;
-    const int gx = x0 + lc, gz = z0 - 8 + lz;
-    float q = 0.0f;
-    if (gx < NX && gz >= 0 && gz < NZ) {
-      const size_t k = (size_t)gz * NX + gx;
-      const float cp = a.Cs[k] * cur[k];
-      q = cp;
-      const int row = zstrip_row(gz, NZ, P);
-      if (row >= 0) {
-        const size_t si = shot * zs_plane + (size_t)row * NX + gx;
-        const float zb = a.zez_in[si] + cp;
-        q = fmaf(a.az[gz], zb, cp);
-        if (lz >= 8 && lz < 8 + TZ) a.zez_out[si] = a.bz[gz] * zb;
-      }
+#pragma unroll
+  for (int rr = 0; rr < kXRows; ++rr) sp[w][rr][l] = pv[rr];
+  __syncthreads();
+#pragma unroll
+  for (int rr = 0; rr < kXRows; ++rr) {
+    const int gz = gz0 + rr;
+    const bool strip = col0 >= 0 && gz < NZ;
+    float psi = 0.0f;
+    if (strip && l >= 4 && l < 60) {
+      psi = fmaf(axv, d1s(&sp[w][rr][l], 1), bxv * psio[rr]);
+      if (own) a.psx_out[shot * (size_t)NZ * P2 + (size_t)gz * P2 + col0] = psi;
     }
-    sqz[e] = q;
+    ss[w][rr][l] = psi;
   }
   __syncthreads();
+#pragma unroll
+  for (int rr = 0; rr < kXRows; ++rr) {
+    const int gz = gz0 + rr;
+    if (!(own && col_ok && gz < NZ)) continue;
+    const float d1p = d1s(&ss[w][rr][l], 1);
+    float E = d1p;
+    if (col0 >= 0) {
+      const float Q = d2s(&sp[w][rr][l], 1) + d1p;
+      const float zeta = fmaf(axv, Q, bxv * zo[rr]);
+      a.zex_out[shot * (size_t)NZ * P2 + (size_t)gz * P2 + col0] = zeta;
+      E = d1p + zeta;
+    }
+    const size_t gi = shot * plane + (size_t)gz * NX + gx;
+    a.prev_adj[gi] = fmaf(-cs[rr], E, pp[rr]);
+    if (a.B_out) a.B_out[gi] = E;
+  }
+}
 
-  for (int e = tid; e < TZ * TXW; e += kThreads) {
-    const int lz = e / TXW, lc = e - lz * TXW;
-    const int gx = x0 - 4 + lc, gz = z0 + lz;
+// Adjoint of the x band: zbar = Z + q, Qbar = q + a_x zbar (q = Cs lambda^{n+1}),
+// psbar = Psi - D1x' Qbar, Eadj = D2x'(a_x zbar) - D1x'(a_x psbar);
+// lambda^{n+2}' -= Eadj; Psi <- b_x psbar, Z <- b_x zbar.
+__global__ __launch_bounds__(kThreads) void ac_adj_xband(AcStep a) {
+  __shared__ float sQ[4][kXRows][64];
+  __shared__ float sS[4][kXRows][64];
+  __shared__ float sT[4][kXRows][64];
+  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int2 ch = a.xchunks[blockIdx.x];
+  const int shot = blockIdx.z;
+  const int NX = a.NX, NZ = a.NZ, P = a.P, P2 = 2 * P;
+  const int gx = ch.x - 8 + l;
+  const size_t plane = (size_t)NX * NZ;
+  const bool own = l >= 8 && l < 8 + ch.y;
+  const bool col_ok = gx >= 0 && gx < NX;
+  const int col0 = col_ok ? xstrip_col(gx, NX, P) : -1;
+  const float axv = col0 >= 0 ? a.ax[gx] : 0.0f, bxv = col0 >= 0 ? a.bx[gx] : 0.0f;
+  const int gz0 = (blockIdx.y * 4 + w) * kXRows;
+  float lv[kXRows], cv[kXRows], zi[kXRows], psi_in[kXRows], pp[kXRows];
+#pragma unroll
+  for (int rr = 0; rr < kXRows; ++rr) {
+    const int gz = gz0 + rr;
+    const bool in_grid = col_ok && gz < NZ;
+    const bool strip = in_grid && col0 >= 0;
+    const size_t si = shot * (size_t)NZ * P2 + (size_t)gz * P2 + (strip ? col0 : 0);
+    const size_t gi = shot * plane + (size_t)gz * NX + (in_grid ? gx : 0);
+    lv[rr] = in_grid ? a.cur[gi] : 0.0f;
+    cv[rr] = in_grid ? a.Cs[(size_t)gz * NX + gx] : 0.0f;
+    zi[rr] = strip ? a.zex_in[si] : 0.0f;
+    psi_in[rr] = (strip && l >= 4 && l < 60) ? a.psx_in[si] : 0.0f;
+    pp[rr] = (in_grid && own) ? a.prev_adj[gi] : 0.0f;
+  }
+#pragma unroll
+  for (int rr = 0; rr < kXRows; ++rr) {
+    const int gz = gz0 + rr;
+    float q = cv[rr] * lv[rr];
+    float sv = 0.0f;
+    if (col0 >= 0 && gz < NZ) {
+      const float zb = zi[rr] + q;
+      sv = axv * zb;
+      q = q + sv;
+      if (own) a.zex_out[shot * (size_t)NZ * P2 + (size_t)gz * P2 + col0] = bxv * zb;
+    }
+    sQ[w][rr][l] = q;
+    sS[w][rr][l] = sv;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int rr = 0; rr < kXRows; ++rr) {
+    const int gz = gz0 + rr;
     float t = 0.0f;
-    if (gx >= 0 && gx < NX && gz < NZ) {
-      const int col = xstrip_col(gx, NX, P);
-      if (col >= 0) {
-        const float* q = &sqx[lz * QXW + lc + 4];
-        const size_t si = shot * xs_plane + (size_t)gz * P2 + col;
-        const float psb =
-            a.psx_in[si] - d1c(q[1], q[-1], q[2], q[-2], q[3], q[-3], q[4], q[-4]);
-        t = a.ax[gx] * psb;
-        if (lc >= 4 && lc < 4 + kTX) a.psx_out[si] = a.bx[gx] * psb;
-      }
+    if (col0 >= 0 && gz < NZ && l >= 4 && l < 60) {
+      const float psb = psi_in[rr] - d1s(&sQ[w][rr][l], 1);
+      t = axv * psb;
+      if (own) a.psx_out[shot * (size_t)NZ * P2 + (size_t)gz * P2 + col0] = bxv * psb;
     }
-    stx[e] = t;
-  }
-  for (int e = tid; e < TZH * kTX; e += kThreads) {
-    const int lz = e / kTX, lc = e - lz * kTX;
-    const int gx = x0 + lc, gz = z0 - 4 + lz;
-    float t = 0.0f;
-    if (gx < NX && gz >= 0 && gz < NZ) {
-      const int row = zstrip_row(gz, NZ, P);
-      if (row >= 0) {
-        const float* q = &sqz[(lz + 4) * kTX + lc];
-        const size_t si = shot * zs_plane + (size_t)row * NX + gx;
-        const float psb = a.psz_in[si] - d1c(q[kTX], q[-kTX], q[2 * kTX], q[-2 * kTX],
-                                             q[3 * kTX], q[-3 * kTX], q[4 * kTX], q[-4 * kTX]);
-        t = a.az[gz] * psb;
-        if (lz >= 4 && lz < 4 + TZ) a.psz_out[si] = a.bz[gz] * psb;
-      }
-    }
-    stz[e] = t;
+    sT[w][rr][l] = t;
   }
   __syncthreads();
-
-  for (int e = tid; e < TZ * kTX; e += kThreads) {
-    const int lz = e / kTX, lc = e - lz * kTX;
-    const int gx = x0 + lc, gz = z0 + lz;
-    float lam = 0.0f;
-    if (gx < NX && gz < NZ) {
-      const float* qx = &sqx[lz * QXW + lc + 8];
-      const float* qz = &sqz[(lz + 8) * kTX + lc];
-      const float* tx = &stx[lz * TXW + lc + 4];
-      const float* tz = &stz[(lz + 4) * kTX + lc];
-      const float d2x =
-          d2c(qx[0], qx[1], qx[-1], qx[2], qx[-2], qx[3], qx[-3], qx[4], qx[-4]);
-      const float d2z = d2c(qz[0], qz[kTX], qz[-kTX], qz[2 * kTX], qz[-2 * kTX], qz[3 * kTX],
-                            qz[-3 * kTX], qz[4 * kTX], qz[-4 * kTX]);
-      const float d1x = d1c(tx[1], tx[-1], tx[2], tx[-2], tx[3], tx[-3], tx[4], tx[-4]);
-      const float d1z = d1c(tz[kTX], tz[-kTX], tz[2 * kTX], tz[-2 * kTX], tz[3 * kTX],
-                            tz[-3 * kTX], tz[4 * kTX], tz[-4 * kTX]);
-      const size_t gi = shot * plane + (size_t)gz * NX + gx;
-      const float p1 = a.cur[gi];
-      const float gb = p1 * a.B_in[gi];
-      a.g[gi] = a.g_init ? gb : a.g[gi] + gb;
-      lam = (((2.0f * p1 - a.prev[gi]) + d2x) + d2z) - d1x - d1z;
-    }
-    st[e] = lam;
-  }
-  __syncthreads();
-  if (a.n >= 1) {
-    inject_residual(a, shot, tile, st);
-    __syncthreads();
-  }
-  for (int e = tid; e < TZ * kTX; e += kThreads) {
-    const int lz = e / kTX, lc = e - lz * kTX;
-    const int gx = x0 + lc, gz = z0 + lz;
-    if (gx < NX && gz < NZ) a.next[shot * plane + (size_t)gz * NX + gx] = st[e];
+#pragma unroll
+  for (int rr = 0; rr < kXRows; ++rr) {
+    const int gz = gz0 + rr;
+    if (!(own && col_ok && gz < NZ)) continue;
+    const float E = d2s(&sS[w][rr][l], 1) - d1s(&sT[w][rr][l], 1);
+    a.prev_adj[shot * plane + (size_t)gz * NX + gx] = pp[rr] - E;
   }
 }
 
 // ---------------------------------------------------------------------------
-// Adjoint start: zero the adjoint state, then lambda^{nt}[rec] = r_{nt-1}
-// (receiver order, so coincident receivers add up deterministically).
+// z band (rows within P+4 of the top/bottom edges, all columns). A work-group
+// covers 64 columns x up to 48 output rows with an 8-row halo above and below;
+// wave w handles the LDS rows congruent to w mod 4, and issues all of its
+// global loads of a phase before using any of them.
+// ---------------------------------------------------------------------------
+constexpr int kZRows = kChunk + 16;
+constexpr int kZStage = kZRows / 4;       // staged rows per wave (64 / 4)
+constexpr int kZPsi = (kZRows - 8) / 4;   // psi rows per wave
+constexpr int kZOut = kChunk / 4;         // output rows per wave
+
+__global__ __launch_bounds__(kThreads) void ac_fwd_zband(AcStep a) {
+  __shared__ float sp[kZRows * kTX];
+  __shared__ float ss[kZRows * kTX];
+  const int c = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int2 ch = a.zchunks[blockIdx.y];
+  const int x0 = blockIdx.x * kTX, gx = x0 + c;
+  const int shot = blockIdx.z;
+  const int NX = a.NX, NZ = a.NZ, P = a.P;
+  const bool col_ok = gx < NX;
+  const size_t plane = (size_t)NX * NZ;
+  const size_t zs_plane = (size_t)2 * P * NX;
+  const int rows = ch.y + 16;  // LDS row r <-> grid row ch.x - 8 + r
+  {
+    float v[kZStage];
+#pragma unroll
+    for (int k = 0; k < kZStage; ++k) {
+      const int r = w + 4 * k, gz = ch.x - 8 + r;
+      const bool ok = col_ok && r < rows && gz >= 0 && gz < NZ;
+      v[k] = ok ? a.cur[shot * plane + (size_t)gz * NX + gx] : 0.0f;
+    }
+#pragma unroll
+    for (int k = 0; k < kZStage; ++k) sp[(w + 4 * k) * kTX + c] = v[k];
+  }
+  __syncthreads();
+  {
+    float old[kZPsi];
+#pragma unroll
+    for (int k = 0; k < kZPsi; ++k) {
+      const int r = 4 + w + 4 * k, gz = ch.x - 8 + r;
+      const int row = (col_ok && r < rows - 4 && gz >= 0 && gz < NZ) ? zstrip_row(gz, NZ, P) : -1;
+      old[k] = row >= 0 ? a.psz_in[shot * zs_plane + (size_t)row * NX + gx] : 0.0f;
+    }
+#pragma unroll
+    for (int k = 0; k < kZPsi; ++k) {
+      const int r = 4 + w + 4 * k, gz = ch.x - 8 + r;
+      const int row = (col_ok && r < rows - 4 && gz >= 0 && gz < NZ) ? zstrip_row(gz, NZ, P) : -1;
+      float psi = 0.0f;
+      if (row >= 0) {
+        psi = fmaf(a.az[gz], d1s(&sp[r * kTX + c], kTX), a.bz[gz] * old[k]);
+        if (r >= 8 && r < 8 + ch.y) a.psz_out[shot * zs_plane + (size_t)row * NX + gx] = psi;
+      }
+      ss[r * kTX + c] = psi;
+    }
+  }
+  __syncthreads();
+  float zo[kZOut], cs[kZOut], pp[kZOut], bo[kZOut];
+  const bool xb = in_xband(gx, NX, P);
+#pragma unroll
+  for (int k = 0; k < kZOut; ++k) {
+    const int r = 8 + w + 4 * k, gz = ch.x - 8 + r;
+    const bool ok = col_ok && r < 8 + ch.y && gz < NZ;
+    const int row = ok ? zstrip_row(gz, NZ, P) : -1;
+    const size_t kk = ok ? (size_t)gz * NX + gx : 0;
+    zo[k] = row >= 0 ? a.zez_in[shot * zs_plane + (size_t)row * NX + gx] : 0.0f;
+    cs[k] = ok ? a.Cs[kk] : 0.0f;
+    pp[k] = ok ? a.prev_adj[shot * plane + kk] : 0.0f;
+    bo[k] = (ok && a.B_out && xb) ? a.B_out[shot * plane + kk] : 0.0f;
+  }
+#pragma unroll
+  for (int k = 0; k < kZOut; ++k) {
+    const int r = 8 + w + 4 * k, gz = ch.x - 8 + r;
+    if (!(col_ok && r < 8 + ch.y && gz < NZ)) continue;
+    const float d1p = d1s(&ss[r * kTX + c], kTX);
+    float E = d1p;
+    const int row = zstrip_row(gz, NZ, P);
+    if (row >= 0) {
+      const float Q = d2s(&sp[r * kTX + c], kTX) + d1p;
+      const float zeta = fmaf(a.az[gz], Q, a.bz[gz] * zo[k]);
+      a.zez_out[shot * zs_plane + (size_t)row * NX + gx] = zeta;
+      E = d1p + zeta;
+    }
+    const size_t gi = shot * plane + (size_t)gz * NX + gx;
+    a.prev_adj[gi] = fmaf(-cs[k], E, pp[k]);
+    if (a.B_out) a.B_out[gi] = xb ? bo[k] + E : E;
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void ac_adj_zband(AcStep a) {
+  __shared__ float sQ[kZRows * kTX];
+  __shared__ float sS[kZRows * kTX];
+  __shared__ float sT[kZRows * kTX];
+  const int c = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int2 ch = a.zchunks[blockIdx.y];
+  const int x0 = blockIdx.x * kTX, gx = x0 + c;
+  const int shot = blockIdx.z;
+  const int NX = a.NX, NZ = a.NZ, P = a.P;
+  const bool col_ok = gx < NX;
+  const size_t plane = (size_t)NX * NZ;
+  const size_t zs_plane = (size_t)2 * P * NX;
+  const int rows = ch.y + 16;
+  {
+    float lv[kZStage], cv[kZStage], zi[kZStage];
+#pragma unroll
+    for (int k = 0; k < kZStage; ++k) {
+      const int r = w + 4 * k, gz = ch.x - 8 + r;
+      const bool ok = col_ok && r < rows && gz >= 0 && gz < NZ;
+      const size_t kk = ok ? (size_t)gz * NX + gx : 0;
+      const int row = ok ? zstrip_row(gz, NZ, P) : -1;
+      lv[k] = ok ? a.cur[shot * plane + kk] : 0.0f;
+      cv[k] = ok ? a.Cs[kk] : 0.0f;
+      zi[k] = row >= 0 ? a.zez_in[shot * zs_plane + (size_t)row * NX + gx] : 0.0f;
+    }
+#pragma unroll
+    for (int k = 0; k < kZStage; ++k) {
+      const int r = w + 4 * k, gz = ch.x - 8 + r;
+      const bool ok = col_ok && r < rows && gz >= 0 && gz < NZ;
+      const int row = ok ? zstrip_row(gz, NZ, P) : -1;
+      float q = cv[k] * lv[k], sv = 0.0f;
+      if (row >= 0) {
+        const float zb = zi[k] + q;
+        sv = a.az[gz] * zb;
+        q = q + sv;
+        if (r >= 8 && r < 8 + ch.y) a.zez_out[shot * zs_plane + (size_t)row * NX + gx] = a.bz[gz] * zb;
+      }
+      sQ[r * kTX + c] = q;
+      sS[r * kTX + c] = sv;
+    }
+  }
+  __syncthreads();
+  {
+    float pin[kZPsi];
+#pragma unroll
+    for (int k = 0; k < kZPsi; ++k) {
+      const int r = 4 + w + 4 * k, gz = ch.x - 8 + r;
+      const int row = (col_ok && r < rows - 4 && gz >= 0 && gz < NZ) ? zstrip_row(gz, NZ, P) : -1;
+      pin[k] = row >= 0 ? a.psz_in[shot * zs_plane + (size_t)row * NX + gx] : 0.0f;
+    }
+#pragma unroll
+    for (int k = 0; k < kZPsi; ++k) {
+      const int r = 4 + w + 4 * k, gz = ch.x - 8 + r;
+      const int row = (col_ok && r < rows - 4 && gz >= 0 && gz < NZ) ? zstrip_row(gz, NZ, P) : -1;
+      float t = 0.0f;
+      if (row >= 0) {
+        const float psb = pin[k] - d1s(&sQ[r * kTX + c], kTX);
+        t = a.az[gz] * psb;
+        if (r >= 8 && r < 8 + ch.y) a.psz_out[shot * zs_plane + (size_t)row * NX + gx] = a.bz[gz] * psb;
+      }
+      sT[r * kTX + c] = t;
+    }
+  }
+  __syncthreads();
+  float pp[kZOut];
+#pragma unroll
+  for (int k = 0; k < kZOut; ++k) {
+    const int r = 8 + w + 4 * k, gz = ch.x - 8 + r;
+    const bool ok = col_ok && r < 8 + ch.y && gz < NZ;
+    pp[k] = ok ? a.prev_adj[shot * plane + (size_t)gz * NX + gx] : 0.0f;
+  }
+#pragma unroll
+  for (int k = 0; k < kZOut; ++k) {
+    const int r = 8 + w + 4 * k, gz = ch.x - 8 + r;
+    if (!(col_ok && r < 8 + ch.y && gz < NZ)) continue;
+    const float E = d2s(&sS[r * kTX + c], kTX) - d1s(&sT[r * kTX + c], kTX);
+    a.prev_adj[shot * plane + (size_t)gz * NX + gx] = pp[k] - E;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint start: lambda^{nt}[rec] += r_{nt-1} (receiver order, so coincident
+// receivers add up deterministically), after the state was zero-filled.
 // ---------------------------------------------------------------------------
 __global__ void ac_inject_last(float* lam, size_t plane, const int* rec_cell,
                                const float* resid, int nshots, int nt, int nrec) {
@@ -592,38 +687,35 @@ __global__ void ac_finish_kernel(const double* tot, const float* vpad, float* gr
   grad[(size_t)jj * nx + ii] = (float)acc;
 }
 
-// ev (optional): start/stop event pairs recorded around the interior launch
-// (ev[0], ev[1]) and the frame launch (ev[2], ev[3]).
-template <int RZ>
-int launch_fwd_rz(const AcStep& a, int n_int, hipStream_t s, hipEvent_t* ev) {
-  constexpr int TZ = 4 * RZ;
-  if (n_int > 0) {
-    if (ev) SWEEP_HIP(hipEventRecord(ev[0], s));
-    hipLaunchKernelGGL(ac_fwd_interior<RZ>, dim3(n_int, a.nshots), dim3(kThreads), 0, s, a);
-    if (ev) SWEEP_HIP(hipEventRecord(ev[1], s));
-  }
-  if (a.n_frame > 0) {
+// ev (optional): start/stop event pairs recorded around the main launch
+// (ev[0], ev[1]) and the two band launches (ev[2], ev[3]).
+template <int RZ, bool kAdj>
+int launch_step(const AcStep& a, hipStream_t s, hipEvent_t* ev) {
+  if (a.n_xchunks > 0 || a.n_zchunks > 0) {
     if (ev) SWEEP_HIP(hipEventRecord(ev[2], s));
-    hipLaunchKernelGGL(ac_fwd_frame<TZ>, dim3(a.n_frame, a.nshots), dim3(kThreads), 0, s, a);
+    if (a.n_xchunks > 0) {
+      const dim3 g(a.n_xchunks, (a.NZ + 4 * kXRows - 1) / (4 * kXRows), a.nshots);
+      if (kAdj)
+        hipLaunchKernelGGL(ac_adj_xband, g, dim3(kThreads), 0, s, a);
+      else
+        hipLaunchKernelGGL(ac_fwd_xband, g, dim3(kThreads), 0, s, a);
+    }
+    if (a.n_zchunks > 0) {
+      const dim3 g((a.NX + kTX - 1) / kTX, a.n_zchunks, a.nshots);
+      if (kAdj)
+        hipLaunchKernelGGL(ac_adj_zband, g, dim3(kThreads), 0, s, a);
+      else
+        hipLaunchKernelGGL(ac_fwd_zband, g, dim3(kThreads), 0, s, a);
+    }
     if (ev) SWEEP_HIP(hipEventRecord(ev[3], s));
   }
-  SWEEP_HIP(hipGetLastError());
-  return SWEEP_OK;
-}
-
-template <int RZ>
-int launch_adj_rz(const AcStep& a, int n_int, hipStream_t s, hipEvent_t* ev) {
-  constexpr int TZ = 4 * RZ;
-  if (n_int > 0) {
-    if (ev) SWEEP_HIP(hipEventRecord(ev[0], s));
-    hipLaunchKernelGGL(ac_adj_interior<RZ>, dim3(n_int, a.nshots), dim3(kThreads), 0, s, a);
-    if (ev) SWEEP_HIP(hipEventRecord(ev[1], s));
-  }
-  if (a.n_frame > 0) {
-    if (ev) SWEEP_HIP(hipEventRecord(ev[2], s));
-    hipLaunchKernelGGL(ac_adj_frame<TZ>, dim3(a.n_frame, a.nshots), dim3(kThreads), 0, s, a);
-    if (ev) SWEEP_HIP(hipEventRecord(ev[3], s));
-  }
+  if (ev) SWEEP_HIP(hipEventRecord(ev[0], s));
+  const dim3 g(a.ntiles, a.nshots);
+  if (kAdj)
+    hipLaunchKernelGGL(ac_adj_main<RZ>, g, dim3(kThreads), 0, s, a);
+  else
+    hipLaunchKernelGGL(ac_fwd_main<RZ>, g, dim3(kThreads), 0, s, a);
+  if (ev) SWEEP_HIP(hipEventRecord(ev[1], s));
   SWEEP_HIP(hipGetLastError());
   return SWEEP_OK;
 }
@@ -643,23 +735,23 @@ int ac_launch_prep(const float* v, float* vpad, float* Cs, float* ax, float* bx,
   return SWEEP_OK;
 }
 
-int ac_launch_fwd(const AcStep& a, int rz, int n_int, hipStream_t s, hipEvent_t* ev) {
+int ac_launch_fwd(const AcStep& a, int rz, hipStream_t s, hipEvent_t* ev) {
   switch (rz) {
-    case 1: return launch_fwd_rz<1>(a, n_int, s, ev);
-    case 2: return launch_fwd_rz<2>(a, n_int, s, ev);
-    case 4: return launch_fwd_rz<4>(a, n_int, s, ev);
-    case 8: return launch_fwd_rz<8>(a, n_int, s, ev);
+    case 1: return launch_step<1, false>(a, s, ev);
+    case 2: return launch_step<2, false>(a, s, ev);
+    case 4: return launch_step<4, false>(a, s, ev);
+    case 8: return launch_step<8, false>(a, s, ev);
   }
   set_error("unsupported rz");
   return SWEEP_EINVAL;
 }
 
-int ac_launch_adj(const AcStep& a, int rz, int n_int, hipStream_t s, hipEvent_t* ev) {
+int ac_launch_adj(const AcStep& a, int rz, hipStream_t s, hipEvent_t* ev) {
   switch (rz) {
-    case 1: return launch_adj_rz<1>(a, n_int, s, ev);
-    case 2: return launch_adj_rz<2>(a, n_int, s, ev);
-    case 4: return launch_adj_rz<4>(a, n_int, s, ev);
-    case 8: return launch_adj_rz<8>(a, n_int, s, ev);
+    case 1: return launch_step<1, true>(a, s, ev);
+    case 2: return launch_step<2, true>(a, s, ev);
+    case 4: return launch_step<4, true>(a, s, ev);
+    case 8: return launch_step<8, true>(a, s, ev);
   }
   set_error("unsupported rz");
   return SWEEP_EINVAL;

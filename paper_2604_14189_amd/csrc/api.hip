@@ -59,6 +59,11 @@ struct Carver {
 
 }  // namespace
 
+// Splits [lo, hi) into pieces of at most 48 cells.
+static void add_chunks(std::vector<int2>& v, int lo, int hi) {
+  for (int c = lo; c < hi; c += 48) v.push_back(make_int2(c, std::min(48, hi - c)));
+}
+
 void ac_build_tiling(sweep_plan* p) {
   const int TZ = 4 * p->tune.rz;
   p->TZ = TZ;
@@ -66,21 +71,18 @@ void ac_build_tiling(sweep_plan* p) {
   p->tiles_z = (p->NZ + TZ - 1) / TZ;
   p->ntiles = p->tiles_x * p->tiles_z;
   const int P = p->P;
-  // interior tiles: the tile plus a 4-cell halo lies clear of the pad
-  int itx0 = (P + 4 + kTX - 1) / kTX, itx1 = (p->NX - P - 4) / kTX;
-  int itz0 = (P + 4 + TZ - 1) / TZ, itz1 = (p->NZ - P - 4) / TZ;
-  if (itx1 < itx0 || itz1 < itz0) itx1 = itx0 = itz1 = itz0 = 0;
-  if (itx1 <= itx0 || itz1 <= itz0) itx1 = itx0 = itz1 = itz0 = 0;
-  p->itx0 = itx0;
-  p->itz0 = itz0;
-  p->intx = itx1 - itx0;
-  p->intz = itz1 - itz0;
-  p->frame.clear();
-  for (int tz = 0; tz < p->tiles_z; ++tz)
-    for (int tx = 0; tx < p->tiles_x; ++tx) {
-      const bool in = tx >= itx0 && tx < itx1 && tz >= itz0 && tz < itz1;
-      if (!in) p->frame.push_back(tz * p->tiles_x + tx);
-    }
+  // C-PML bands: cells within P+4 of an edge along each axis (the memory
+  // variables live in the outer P cells; their first derivative reaches 4 more)
+  p->xchunks.clear();
+  p->zchunks.clear();
+  if (P > 0) {
+    const int xl = std::min(P + 4, p->NX), xr = std::max(p->NX - P - 4, xl);
+    add_chunks(p->xchunks, 0, xl);
+    add_chunks(p->xchunks, xr, p->NX);
+    const int zl = std::min(P + 4, p->NZ), zr = std::max(p->NZ - P - 4, zl);
+    add_chunks(p->zchunks, 0, zl);
+    add_chunks(p->zchunks, zr, p->NZ);
+  }
   // receiver CSR over (shot, tile), entries sorted by (local cell, receiver)
   const int ns = p->pb.nshots, nr = p->pb.nrec;
   p->rec_off.assign((size_t)ns * p->ntiles + 1, 0);
@@ -130,7 +132,8 @@ void ac_layout(const sweep_plan* p, AcLayout& L) {
   L.rec_cell = c.take(ns * nr * sizeof(int));
   L.rec_off = c.take((ns * ac_max_tiles(p) + 1) * sizeof(int));
   L.rec_ent = c.take(std::max<size_t>(ns * nr, 1) * sizeof(int2));
-  L.frame = c.take(ac_max_tiles(p) * sizeof(int));
+  L.xch = c.take(((size_t)p->NX / 48 + 4) * sizeof(int2));
+  L.zch = c.take(((size_t)p->NZ / 48 + 4) * sizeof(int2));
   L.pA = c.take(ns * plane * f);
   L.pB = c.take(ns * plane * f);
   L.aux[0] = c.take(L.aux_elems * f);
@@ -174,6 +177,17 @@ AuxPtr aux_ptrs(float* base, const AcLayout& L, size_t ns) {
   return a;
 }
 
+void set_aux(AcStep& a, const AuxPtr& i, const AuxPtr& o) {
+  a.psx_in = i.psx;
+  a.zex_in = i.zex;
+  a.psz_in = i.psz;
+  a.zez_in = i.zez;
+  a.psx_out = o.psx;
+  a.zex_out = o.zex;
+  a.psz_out = o.psz;
+  a.zez_out = o.zez;
+}
+
 int check_work(const sweep_plan* p, size_t need, void* work, size_t bytes) {
   if (!work) {
     set_error("workspace pointer is null");
@@ -208,11 +222,10 @@ AcStep ac_base(const sweep_plan* p, void* work, const AcLayout& L) {
   a.src_cell = at<int>(work, L.src_cell);
   a.rec_off = at<int>(work, L.rec_off);
   a.rec_ent = at<int2>(work, L.rec_ent);
-  a.frame_tiles = at<int>(work, L.frame);
-  a.n_frame = (int)p->frame.size();
-  a.int_tx0 = p->itx0;
-  a.int_tz0 = p->itz0;
-  a.int_ntx = p->intx;
+  a.xchunks = at<int2>(work, L.xch);
+  a.n_xchunks = (int)p->xchunks.size();
+  a.zchunks = at<int2>(work, L.zch);
+  a.n_zchunks = (int)p->zchunks.size();
   return a;
 }
 
@@ -227,9 +240,12 @@ int ac_upload_geometry(sweep_plan* p, void* work, const AcLayout& L, hipStream_t
   }
   SWEEP_HIP(hipMemcpyAsync(at<int>(work, L.rec_off), p->rec_off.data(),
                            p->rec_off.size() * sizeof(int), hipMemcpyHostToDevice, s));
-  if (!p->frame.empty())
-    SWEEP_HIP(hipMemcpyAsync(at<int>(work, L.frame), p->frame.data(),
-                             p->frame.size() * sizeof(int), hipMemcpyHostToDevice, s));
+  if (!p->xchunks.empty())
+    SWEEP_HIP(hipMemcpyAsync(at<int2>(work, L.xch), p->xchunks.data(),
+                             p->xchunks.size() * sizeof(int2), hipMemcpyHostToDevice, s));
+  if (!p->zchunks.empty())
+    SWEEP_HIP(hipMemcpyAsync(at<int2>(work, L.zch), p->zchunks.data(),
+                             p->zchunks.size() * sizeof(int2), hipMemcpyHostToDevice, s));
   return SWEEP_OK;
 }
 
@@ -260,36 +276,26 @@ int ac_forward(sweep_plan* p, const float* model, const float* wavelet, float* g
   AcStep base = ac_base(p, work, L);
   base.wavelet = wav;
   base.gathers = gathers;
-  const int n_int = p->intx * p->intz;
   const int k = p->ckpt;
   float* ck = at<float>(work, L.ck);
   for (int n = 0; n < pb.nt; ++n) {
     AcStep a = base;
     a.n = n;
-    a.cur = (n % 2 == 0) ? pB : pA;
-    a.prev = (n % 2 == 0) ? pA : pB;
-    a.next = (n % 2 == 0) ? pA : pB;
-    const AuxPtr ai = aux_ptrs(aux[n % 2], L, ns), ao = aux_ptrs(aux[(n + 1) % 2], L, ns);
-    a.psx_in = ai.psx;
-    a.zex_in = ai.zex;
-    a.psz_in = ai.psz;
-    a.zez_in = ai.zez;
-    a.psx_out = ao.psx;
-    a.zex_out = ao.zex;
-    a.psz_out = ao.psz;
-    a.zez_out = ao.zez;
+    float* cur = (n % 2 == 0) ? pB : pA;
+    float* prev = (n % 2 == 0) ? pA : pB;
+    a.cur = cur;
+    a.prev = prev;
+    a.next = prev;
+    a.prev_adj = prev;
+    set_aux(a, aux_ptrs(aux[n % 2], L, ns), aux_ptrs(aux[(n + 1) % 2], L, ns));
     if (save && n % k == 0) {
+      // checkpoint: the state entering step n
       float* slot = ck + (size_t)(n / k) * L.slot_elems;
-      a.ck_cur = slot;
-      a.ck_prev = slot + ns * L.plane;
-      const AuxPtr ca = aux_ptrs(slot + 2 * ns * L.plane, L, ns);
-      a.ck_psx = ca.psx;
-      a.ck_zex = ca.zex;
-      a.ck_psz = ca.psz;
-      a.ck_zez = ca.zez;
+      if ((rc = launch_copy(slot, cur, ns * L.plane, s))) return rc;
+      if ((rc = launch_copy(slot + ns * L.plane, prev, ns * L.plane, s))) return rc;
+      if ((rc = launch_copy(slot + 2 * ns * L.plane, aux[n % 2], L.aux_elems, s))) return rc;
     }
-    if ((rc = ac_launch_fwd(a, p->tune.rz, n_int, s, p->timer.take(kFwdInterior, kFwdFrame))))
-      return rc;
+    if ((rc = ac_launch_fwd(a, p->tune.rz, s, p->timer.take(kFwdMain, kFwdBand)))) return rc;
   }
   p->saved = save != 0;
   p->saved_work = work;
@@ -331,7 +337,6 @@ int ac_backward(sweep_plan* p, const float* resid, float* grad, void* work, size
   if ((rc = launch_fill_f64(tot, L.plane, 0.0, s))) return rc;
 
   AcStep base = ac_base(p, work, L);
-  const int n_int = p->intx * p->intz;
   for (int sg = L.nseg - 1; sg >= 0; --sg) {
     const int n0 = sg * k, n1 = std::min(nt, n0 + k);
     // restore the state entering step n0 and recompute the segment, keeping B^n
@@ -344,21 +349,14 @@ int ac_backward(sweep_plan* p, const float* resid, float* grad, void* work, size
       AcStep a = base;
       a.n = n;
       a.wavelet = at<float>(work, L.wav);
+      float* prev = (m % 2 == 0) ? pA : pB;
       a.cur = (m % 2 == 0) ? pB : pA;
-      a.prev = (m % 2 == 0) ? pA : pB;
-      a.next = (m % 2 == 0) ? pA : pB;
-      const AuxPtr ai = aux_ptrs(aux[m % 2], L, ns), ao = aux_ptrs(aux[(m + 1) % 2], L, ns);
-      a.psx_in = ai.psx;
-      a.zex_in = ai.zex;
-      a.psz_in = ai.psz;
-      a.zez_in = ai.zez;
-      a.psx_out = ao.psx;
-      a.zex_out = ao.zex;
-      a.psz_out = ao.psz;
-      a.zez_out = ao.zez;
+      a.prev = prev;
+      a.next = prev;
+      a.prev_adj = prev;
+      set_aux(a, aux_ptrs(aux[m % 2], L, ns), aux_ptrs(aux[(m + 1) % 2], L, ns));
       a.B_out = Bseg + (size_t)m * ns * L.plane;
-      if ((rc = ac_launch_fwd(a, p->tune.rz, n_int, s, p->timer.take(kRecInterior, kRecFrame))))
-        return rc;
+      if ((rc = ac_launch_fwd(a, p->tune.rz, s, p->timer.take(kRecMain, kRecBand)))) return rc;
     }
     // reverse sweep over the segment
     for (int n = n1 - 1; n >= n0; --n) {
@@ -366,24 +364,16 @@ int ac_backward(sweep_plan* p, const float* resid, float* grad, void* work, size
       AcStep a = base;
       a.n = n;
       a.resid = resid;
+      float* prev = (it % 2 == 0) ? lA : lB;
       a.cur = (it % 2 == 0) ? lB : lA;
-      a.prev = (it % 2 == 0) ? lA : lB;
-      a.next = (it % 2 == 0) ? lA : lB;
-      const AuxPtr ai = aux_ptrs(adjaux[it % 2], L, ns),
-                   ao = aux_ptrs(adjaux[(it + 1) % 2], L, ns);
-      a.psx_in = ai.psx;
-      a.zex_in = ai.zex;
-      a.psz_in = ai.psz;
-      a.zez_in = ai.zez;
-      a.psx_out = ao.psx;
-      a.zex_out = ao.zex;
-      a.psz_out = ao.psz;
-      a.zez_out = ao.zez;
+      a.prev = prev;
+      a.next = prev;
+      a.prev_adj = prev;
+      set_aux(a, aux_ptrs(adjaux[it % 2], L, ns), aux_ptrs(adjaux[(it + 1) % 2], L, ns));
       a.B_in = Bseg + (size_t)(n - n0) * ns * L.plane;
       a.g = gpart;
       a.g_init = (n == n1 - 1);
-      if ((rc = ac_launch_adj(a, p->tune.rz, n_int, s, p->timer.take(kAdjInterior, kAdjFrame))))
-        return rc;
+      if ((rc = ac_launch_adj(a, p->tune.rz, s, p->timer.take(kAdjMain, kAdjBand)))) return rc;
     }
     if ((rc = ac_launch_fold(tot, gpart, (int)ns, L.plane, s))) return rc;
   }

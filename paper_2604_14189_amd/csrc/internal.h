@@ -46,11 +46,13 @@ struct AcStep {
   const float* bx;
   const float* az;
   const float* bz;
-  // forward: p^n (cur), p^{n-1} (prev), p^{n+1} (next, may alias prev)
-  // adjoint: lambda^{n+1} (cur), lambda^{n+2} (prev), lambda^n (next)
+  // forward: p^n (cur), p^{n-1} (prev), p^{n+1} (next, aliases prev)
+  // adjoint: lambda^{n+1} (cur), lambda^{n+2} (prev), lambda^n (next, aliases prev)
+  // The band kernels update prev in place through prev_adj (same buffer).
   const float* cur;
   const float* prev;
   float* next;
+  float* prev_adj;
   // memory variables: read *_in (time n-1), write *_out (time n)
   const float* psx_in;
   float* psx_out;
@@ -68,29 +70,24 @@ struct AcStep {
   float* gathers;         // forward: [nshots][nt][nrec] output, or null
   const float* resid;     // adjoint: [nshots][nt][nrec] injected at step n-1
   // forward extras
-  float* B_out;           // [nshots][NZ][NX] Laplacian term B^n, or null
-  float* ck_cur;          // checkpoint of the inputs, or null (all six together)
-  float* ck_prev;
-  float* ck_psx;
-  float* ck_zex;
-  float* ck_psz;
-  float* ck_zez;
+  float* B_out;           // [nshots][NZ][NX] Laplacian term B'^n, or null
   // adjoint extras
-  const float* B_in;      // B^n of this step
+  const float* B_in;      // B'^n of this step
   float* g;               // [nshots][NZ][NX] gradient partial
   int g_init;             // 1: g = P1 B (first step of a segment), 0: g += P1 B
-  // tile lists
-  const int* frame_tiles; // tiles touching the absorbing pad
-  int n_frame;
-  int int_tx0, int_tz0, int_ntx;  // interior tile rectangle origin, width
+  // C-PML bands: (first column or row, count <= 48) pieces of the x and z bands
+  const int2* xchunks;
+  int n_xchunks;
+  const int2* zchunks;
+  int n_zchunks;
 };
 
-// Launchers (acoustic.hip). `rz` selects the interior kernel variant (TZ = 4 rz).
+// Launchers (acoustic.hip). `rz` selects the main kernel variant (TZ = 4 rz).
 int ac_launch_prep(const float* v, float* vpad, float* Cs, float* ax, float* bx, float* az,
                    float* bz, int nx, int nz, int P, double h, double dt, double vmax,
                    double f0, double R, hipStream_t s);
-int ac_launch_fwd(const AcStep& a, int rz, int n_int_tiles, hipStream_t s, hipEvent_t* ev);
-int ac_launch_adj(const AcStep& a, int rz, int n_int_tiles, hipStream_t s, hipEvent_t* ev);
+int ac_launch_fwd(const AcStep& a, int rz, hipStream_t s, hipEvent_t* ev);
+int ac_launch_adj(const AcStep& a, int rz, hipStream_t s, hipEvent_t* ev);
 int ac_launch_adj_init(float* lam_cur, float* lam_prev, size_t plane_elems, float* aux,
                        size_t aux_elems, const int* rec_cell, const float* resid, int nshots,
                        int nt, int nrec, hipStream_t s);

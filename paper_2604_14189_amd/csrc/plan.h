@@ -9,7 +9,7 @@
 namespace sweep {
 struct AcLayout {
   size_t plane, xs, zs, aux_elems;
-  size_t ax, bx, az, bz, vpad, Cs, wav, src_cell, rec_cell, rec_off, rec_ent, frame;
+  size_t ax, bx, az, bz, vpad, Cs, wav, src_cell, rec_cell, rec_off, rec_ent, xch, zch;
   size_t pA, pB, aux[2];
   size_t fwd_end;
   int nseg;
@@ -22,13 +22,14 @@ struct AcLayout {
 // Optional per-launch timing of the step kernels (hipEvent pairs recorded on the
 // caller's stream around every launch of a kernel class).
 namespace sweep {
+// Main = whole-grid stencil kernel; Band = the two C-PML band kernels of a step.
 enum KernelClass {
-  kFwdInterior = 0,
-  kFwdFrame = 1,
-  kAdjInterior = 2,
-  kAdjFrame = 3,
-  kRecInterior = 4,
-  kRecFrame = 5,
+  kFwdMain = 0,
+  kFwdBand = 1,
+  kAdjMain = 2,
+  kAdjBand = 3,
+  kRecMain = 4,
+  kRecBand = 5,
   kNumClasses = 6
 };
 struct KernelTimer {
@@ -37,8 +38,8 @@ struct KernelTimer {
   size_t used[kNumClasses] = {0, 0, 0, 0, 0, 0};
   ~KernelTimer();
   void reset();
-  // Four events for one interior + frame launch pair of classes (ci, cf), or
-  // null when timing is off.
+  // Four events for one main + band launch pair of classes (ci, cf), or null
+  // when timing is off.
   hipEvent_t* take(int ci, int cf);
   hipEvent_t quad[4];
 };
@@ -52,8 +53,7 @@ struct sweep_plan {
   std::vector<int> rec_cell;  // [nshots][nrec] padded linear index
   // tiling for the current tuning
   int TZ = 0, tiles_x = 0, tiles_z = 0, ntiles = 0;
-  int itx0 = 0, itz0 = 0, intx = 0, intz = 0;
-  std::vector<int> frame;
+  std::vector<int2> xchunks, zchunks;  // C-PML band pieces (start, count <= 48)
   std::vector<int> rec_off;
   std::vector<int2> rec_ent;
   // state of the last forward

@@ -168,8 +168,7 @@ class Plan:
         return out
 
     # ---------------------------------------------------------------- timing
-    KERNEL_CLASSES = ("fwd_interior", "fwd_frame", "adj_interior", "adj_frame",
-                      "rec_interior", "rec_frame")
+    KERNEL_CLASSES = ("fwd_main", "fwd_band", "adj_main", "adj_band", "rec_main", "rec_band")
 
     def set_profiling(self, enable: bool):
         check(lib().sweep_plan_set_profiling(self._h, int(bool(enable))))
