@@ -32,6 +32,7 @@ hipEvent_t* KernelTimer::take(int ci, int cf) {
   if (!on) return nullptr;
   const int cls[2] = {ci, cf};
   for (int k = 0; k < 2; ++k) {
+    if (cls[k] < 0) continue;
     std::vector<hipEvent_t>& v = ev[cls[k]];
     while (v.size() < used[cls[k]] + 2) {
       hipEvent_t e;
@@ -415,10 +416,6 @@ extern "C" int sweep_plan_create(const sweep_problem* pb, const int32_t* src_xz,
               std::to_string(limit));
     return SWEEP_ECFL;
   }
-  if (pb->physics == SWEEP_ELASTIC) {
-    set_error("elastic physics is not available in this build");
-    return SWEEP_EINVAL;
-  }
   sweep_plan* p = new (std::nothrow) sweep_plan();
   if (!p) {
     set_error("out of host memory");
@@ -458,7 +455,19 @@ extern "C" int sweep_plan_create(const sweep_problem* pb, const int32_t* src_xz,
   p->tune.rz = 8;
   p->tune.shots_per_block = 1;
   p->tune.use_graph = 0;
-  ac_build_tiling(p);
+  if (pb->physics == SWEEP_ACOUSTIC) {
+    ac_build_tiling(p);
+  } else {
+    el_build_tables(p);
+    p->rec_sorted.resize(p->rec_cell.size());
+    for (size_t r = 0; r < p->rec_cell.size(); ++r)
+      p->rec_sorted[r] = make_int4((int)(r / pb->nrec), p->rec_cell[r], (int)(r % pb->nrec), 0);
+    std::sort(p->rec_sorted.begin(), p->rec_sorted.end(), [](const int4& a, const int4& b) {
+      if (a.x != b.x) return a.x < b.x;
+      if (a.y != b.y) return a.y < b.y;
+      return a.z < b.z;
+    });
+  }
   *out = p;
   return SWEEP_OK;
 }
@@ -476,7 +485,8 @@ extern "C" int sweep_plan_set_tuning(sweep_plan* p, const sweep_tuning* t) {
     return SWEEP_EINVAL;
   }
   p->tune = *t;
-  ac_build_tiling(p);
+  if (p->pb.physics == SWEEP_ACOUSTIC) ac_build_tiling(p);
+  p->saved = false;
   return SWEEP_OK;
 }
 
@@ -491,6 +501,11 @@ extern "C" int sweep_plan_get_tuning(const sweep_plan* p, sweep_tuning* t) {
 
 extern "C" size_t sweep_plan_workspace_bytes(const sweep_plan* p, int for_backward) {
   if (!p) return 0;
+  if (p->pb.physics == SWEEP_ELASTIC) {
+    ElLayout E;
+    el_layout(p, E);
+    return for_backward ? E.bwd_end : E.fwd_end;
+  }
   AcLayout L;
   ac_layout(p, L);
   return for_backward ? L.bwd_end : L.fwd_end;
@@ -514,6 +529,9 @@ extern "C" int sweep_forward(sweep_plan* p, const float* d_model, const float* d
     return SWEEP_EINVAL;
   }
   p->saved = false;
+  if (p->pb.physics == SWEEP_ELASTIC)
+    return el_forward(p, d_model, d_wavelet, d_gathers, d_work, work_bytes, save_for_backward,
+                      (hipStream_t)stream);
   return ac_forward(p, d_model, d_wavelet, d_gathers, d_work, work_bytes, save_for_backward,
                     (hipStream_t)stream);
 }
@@ -524,6 +542,8 @@ extern "C" int sweep_backward(sweep_plan* p, const float* d_resid, float* d_grad
     set_error("sweep_backward: null argument");
     return SWEEP_EINVAL;
   }
+  if (p->pb.physics == SWEEP_ELASTIC)
+    return el_backward(p, d_resid, d_grad, d_work, work_bytes, (hipStream_t)stream);
   return ac_backward(p, d_resid, d_grad, d_work, work_bytes, (hipStream_t)stream);
 }
 

@@ -1,0 +1,604 @@
+// Elastic step kernels for gfx950: the isotropic velocity-stress system
+// (Sec. 3.5, Eq. 12) on a staggered grid, 4th order in space, with C-PML and an
+// optional free surface, and the exact transpose of that recurrence.
+//
+// Nodes of the values stored at [j][i]: txx, tzz at (i, j); vx at (i+1/2, j);
+// vz at (i, j+1/2); txz at (i+1/2, j+1/2). Derivatives (c1 = 9/8, c2 = -1/24):
+//   Dx+ f = c1 (f[i+1]-f[i]) + c2 (f[i+2]-f[i-1])    integer -> half
+//   Dx- g = c1 (g[i]-g[i-1]) + c2 (g[i+1]-g[i-2])    half -> integer
+// zero outside the grid; along z at a free surface the stress images
+// tzz[-k] = -tzz[k], txz[-k-1] = -txz[k] are folded into the first rows and the
+// velocity z-derivatives that would reach above the surface fall back to the
+// 2nd-order difference. Each of the eight derivatives carries a C-PML memory
+// variable psi <- b psi + a D f, stored over the whole grid but touched only
+// where a != 0.
+//
+// Forward step: velocity kernel (vx, vz), receiver gather, stress kernel
+// (txx, tzz, txz, explosive source). Reverse step (gather form of the
+// transpose): adjoint-stress kernel (updates the velocity adjoints from the
+// stress adjoints), residual injection, adjoint-velocity kernel. Away from the
+// surface the transposes are (Dx+)^T = -Dx-, (Dx-)^T = -Dx+ (and along z); on the
+// first four rows below a free surface they use tap tables derived on the host
+// from the forward taps.
+#include "elastic.h"
+
+namespace sweep {
+namespace {
+
+constexpr float C1 = 9.0f / 8.0f;
+constexpr float C2 = -1.0f / 24.0f;
+
+__device__ __forceinline__ float ld(const float* f, int i, int j, int NX, int NZ) {
+  return (i >= 0 && i < NX && j >= 0 && j < NZ) ? f[(size_t)j * NX + i] : 0.0f;
+}
+
+// forward x derivatives (unscaled)
+__device__ __forceinline__ float dxp(const float* f, int i, int j, int NX, int NZ) {
+  return fmaf(C2, ld(f, i + 2, j, NX, NZ) - ld(f, i - 1, j, NX, NZ),
+              C1 * (ld(f, i + 1, j, NX, NZ) - ld(f, i, j, NX, NZ)));
+}
+__device__ __forceinline__ float dxm(const float* f, int i, int j, int NX, int NZ) {
+  return fmaf(C2, ld(f, i + 1, j, NX, NZ) - ld(f, i - 2, j, NX, NZ),
+              C1 * (ld(f, i, j, NX, NZ) - ld(f, i - 1, j, NX, NZ)));
+}
+__device__ __forceinline__ float dzp(const float* f, int i, int j, int NX, int NZ) {
+  return fmaf(C2, ld(f, i, j + 2, NX, NZ) - ld(f, i, j - 1, NX, NZ),
+              C1 * (ld(f, i, j + 1, NX, NZ) - ld(f, i, j, NX, NZ)));
+}
+__device__ __forceinline__ float dzm(const float* f, int i, int j, int NX, int NZ) {
+  return fmaf(C2, ld(f, i, j + 1, NX, NZ) - ld(f, i, j - 2, NX, NZ),
+              C1 * (ld(f, i, j, NX, NZ) - ld(f, i, j - 1, NX, NZ)));
+}
+
+// z derivatives with the free-surface rules on rows 0 and 1
+__device__ __forceinline__ float dz_tzz(const float* f, int i, int j, int NX, int NZ, int fs) {
+  if (fs && j == 0)  // tzz[-1] = -tzz[1]
+    return fmaf(C2, ld(f, i, 2, NX, NZ), fmaf(C1 + C2, ld(f, i, 1, NX, NZ), -C1 * ld(f, i, 0, NX, NZ)));
+  return dzp(f, i, j, NX, NZ);
+}
+__device__ __forceinline__ float dz_txz(const float* f, int i, int j, int NX, int NZ, int fs) {
+  if (fs && j == 0)  // txz[-1] = -txz[0], txz[-2] = -txz[1]
+    return fmaf(2.0f * C2, ld(f, i, 1, NX, NZ), 2.0f * C1 * ld(f, i, 0, NX, NZ));
+  if (fs && j == 1)  // txz[-1] = -txz[0]
+    return fmaf(C2, ld(f, i, 2, NX, NZ),
+                fmaf(-C1 + C2, ld(f, i, 0, NX, NZ), C1 * ld(f, i, 1, NX, NZ)));
+  return dzm(f, i, j, NX, NZ);
+}
+__device__ __forceinline__ float dz_vx(const float* f, int i, int j, int NX, int NZ, int fs) {
+  if (fs && j == 0) return ld(f, i, 1, NX, NZ) - ld(f, i, 0, NX, NZ);
+  return dzp(f, i, j, NX, NZ);
+}
+__device__ __forceinline__ float dz_vz(const float* f, int i, int j, int NX, int NZ, int fs) {
+  if (fs && j == 0) return 0.0f;
+  if (fs && j == 1) return ld(f, i, 1, NX, NZ) - ld(f, i, 0, NX, NZ);
+  return dzm(f, i, j, NX, NZ);
+}
+
+// psi <- b psi + a G (only where a != 0); returns G + psi
+__device__ __forceinline__ float cpml(float* psi, size_t k, float G, float a, float b) {
+  if (a == 0.0f) return G;
+  const float p = fmaf(a, G, b * psi[k]);
+  psi[k] = p;
+  return G + p;
+}
+
+// ---------------------------------------------------------------------------
+// forward: velocity update  vx += dt bx (Dx+ txx + Dz- txz), vz += dt bz (Dx- txz + Dz+ tzz)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void el_vel_kernel(ElStep a) {
+  const int i = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
+  const int NX = a.NX, NZ = a.NZ;
+  if (i >= NX || j >= NZ) return;
+  const size_t plane = (size_t)NX * NZ;
+  const size_t so = (size_t)blockIdx.z * plane;
+  const size_t k = (size_t)j * NX + i;
+  const float* txx = a.txx + so;
+  const float* tzz = a.tzz + so;
+  const float* txz = a.txz + so;
+  const float ih = a.ih;
+  const float Ga = dxp(txx, i, j, NX, NZ) * ih;
+  const float Gb = dz_txz(txz, i, j, NX, NZ, a.fs) * ih;
+  const float Gc = dxm(txz, i, j, NX, NZ) * ih;
+  const float Gd = dz_tzz(tzz, i, j, NX, NZ, a.fs) * ih;
+  const float fvx = cpml(a.ps[0] + so, k, Ga, a.axh[i], a.bxh[i]) +
+                    cpml(a.ps[1] + so, k, Gb, a.azi[j], a.bzi[j]);
+  const float fvz = cpml(a.ps[2] + so, k, Gc, a.axi[i], a.bxi[i]) +
+                    cpml(a.ps[3] + so, k, Gd, a.azh[j], a.bzh[j]);
+  a.vx[so + k] = fmaf(a.dt * a.bx[k], fvx, a.vx[so + k]);
+  a.vz[so + k] = fmaf(a.dt * a.bz[k], fvz, a.vz[so + k]);
+  if (a.tr[0]) {
+    a.tr[0][so + k] = fvx;
+    a.tr[1][so + k] = fvz;
+  }
+}
+
+// gathers[shot][n][r] = (vx, vz) at the receiver cell (v^{n+1/2})
+__global__ void el_record_kernel(ElStep a) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= a.nshots * a.nrec) return;
+  const int s = t / a.nrec, r = t - s * a.nrec;
+  const size_t plane = (size_t)a.NX * a.NZ;
+  const size_t k = (size_t)s * plane + a.rec_cell[t];
+  float* d = a.gathers + (((size_t)s * a.nt + a.n) * a.nrec + r) * 2;
+  d[0] = a.vx[k];
+  d[1] = a.vz[k];
+}
+
+// ---------------------------------------------------------------------------
+// forward: stress update and explosive source
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void el_str_kernel(ElStep a) {
+  const int i = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
+  const int NX = a.NX, NZ = a.NZ;
+  if (i >= NX || j >= NZ) return;
+  const size_t plane = (size_t)NX * NZ;
+  const int shot = blockIdx.z;
+  const size_t so = (size_t)shot * plane;
+  const size_t k = (size_t)j * NX + i;
+  const float* vx = a.vx + so;
+  const float* vz = a.vz + so;
+  const float ih = a.ih;
+  const float Ge = dxm(vx, i, j, NX, NZ) * ih;
+  const float Gf = dz_vz(vz, i, j, NX, NZ, a.fs) * ih;
+  const float Gg = dz_vx(vx, i, j, NX, NZ, a.fs) * ih;
+  const float Gh = dxp(vz, i, j, NX, NZ) * ih;
+  const float exx = cpml(a.ps[4] + so, k, Ge, a.axi[i], a.bxi[i]);
+  const float ezz = cpml(a.ps[5] + so, k, Gf, a.azi[j], a.bzi[j]);
+  const float exz = cpml(a.ps[6] + so, k, Gg, a.azh[j], a.bzh[j]) +
+                    cpml(a.ps[7] + so, k, Gh, a.axh[i], a.bxh[i]);
+  const float dt = a.dt;
+  float txx = a.txx[so + k] + dt * fmaf(a.cxx_x[k], exx, a.cxx_z[k] * ezz);
+  float tzz = a.tzz[so + k] + dt * fmaf(a.czz_x[k], exx, a.czz_z[k] * ezz);
+  if ((int)k == a.src_cell[shot]) {
+    const float s = a.w * a.wavelet[(size_t)shot * a.nt + a.n];
+    txx += s;
+    tzz += s * a.smask[k];
+  }
+  a.txx[so + k] = txx;
+  a.tzz[so + k] = tzz;
+  a.txz[so + k] = fmaf(dt * a.mxz[k], exz, a.txz[so + k]);
+  if (a.tr[2]) {
+    a.tr[2][so + k] = exx;
+    a.tr[3][so + k] = ezz;
+    a.tr[4][so + k] = exz;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Reverse step. With ebar = dt (stress coefficient) x (stress adjoint) and the
+// C-PML adjoint t = Psi + ebar, the derivative input adjoint is ebar + a t and
+// Psi <- b t. The velocity adjoints collect the transposed derivatives of those.
+// ---------------------------------------------------------------------------
+
+// Transposed z-derivative of g at row j: standard (-Dz- or -Dz+) away from a
+// free surface, otherwise the host-derived taps of the first four rows.
+template <class F>
+__device__ __forceinline__ float dzT(const ElStep& a, int kind, int j, F g, bool minus_dzm) {
+  if (a.fs && j < 4) {
+    float acc = 0.0f;
+    const int n = a.tt_cnt[kind][j];
+    for (int e = 0; e < n; ++e) acc = fmaf(a.tt_w[kind][j][e], g(j + a.tt_off[kind][j][e]), acc);
+    return acc;
+  }
+  // -(Dz-) g = -[c1 (g_j - g_{j-1}) + c2 (g_{j+1} - g_{j-2})]
+  // -(Dz+) g = -[c1 (g_{j+1} - g_j) + c2 (g_{j+2} - g_{j-1})]
+  if (minus_dzm) return -fmaf(C2, g(j + 1) - g(j - 2), C1 * (g(j) - g(j - 1)));
+  return -fmaf(C2, g(j + 2) - g(j - 1), C1 * (g(j + 1) - g(j)));
+}
+
+__global__ __launch_bounds__(256) void el_adj_s_kernel(ElStep a) {
+  const int i = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
+  const int NX = a.NX, NZ = a.NZ;
+  if (i >= NX || j >= NZ) return;
+  const size_t plane = (size_t)NX * NZ;
+  const size_t so = (size_t)blockIdx.z * plane;
+  const size_t k = (size_t)j * NX + i;
+  const float dt = a.dt, ih = a.ih;
+  const float* Txx = a.txx + so;
+  const float* Tzz = a.tzz + so;
+  const float* Txz = a.txz + so;
+  const float* Pe = a.ps_in[4] + so;
+  const float* Pf = a.ps_in[5] + so;
+  const float* Pg = a.ps_in[6] + so;
+  const float* Ph = a.ps_in[7] + so;
+  // derivative-input adjoints at any cell (zero outside the grid)
+  auto gbe = [&](int ii, int jj) -> float {
+    if (ii < 0 || ii >= NX || jj < 0 || jj >= NZ) return 0.0f;
+    const size_t q = (size_t)jj * NX + ii;
+    const float e = dt * fmaf(a.cxx_x[q], Txx[q], a.czz_x[q] * Tzz[q]);
+    const float ax = a.axi[ii];
+    return ax == 0.0f ? e : fmaf(ax, Pe[q] + e, e);
+  };
+  auto gbf = [&](int ii, int jj) -> float {
+    if (ii < 0 || ii >= NX || jj < 0 || jj >= NZ) return 0.0f;
+    const size_t q = (size_t)jj * NX + ii;
+    const float e = dt * fmaf(a.cxx_z[q], Txx[q], a.czz_z[q] * Tzz[q]);
+    const float az = a.azi[jj];
+    return az == 0.0f ? e : fmaf(az, Pf[q] + e, e);
+  };
+  auto gbg = [&](int ii, int jj) -> float {
+    if (ii < 0 || ii >= NX || jj < 0 || jj >= NZ) return 0.0f;
+    const size_t q = (size_t)jj * NX + ii;
+    const float e = dt * a.mxz[q] * Txz[q];
+    const float az = a.azh[jj];
+    return az == 0.0f ? e : fmaf(az, Pg[q] + e, e);
+  };
+  auto gbh = [&](int ii, int jj) -> float {
+    if (ii < 0 || ii >= NX || jj < 0 || jj >= NZ) return 0.0f;
+    const size_t q = (size_t)jj * NX + ii;
+    const float e = dt * a.mxz[q] * Txz[q];
+    const float ax = a.axh[ii];
+    return ax == 0.0f ? e : fmaf(ax, Ph[q] + e, e);
+  };
+  // Vx += (Dx-)^T gbe + (Dz+ of vx)^T gbg ;  (Dx-)^T = -Dx+
+  const float dxe = -fmaf(C2, gbe(i + 2, j) - gbe(i - 1, j), C1 * (gbe(i + 1, j) - gbe(i, j)));
+  const float dzg = dzT(a, 2, j, [&](int jj) { return gbg(i, jj); }, true);
+  // Vz += (Dz- of vz)^T gbf + (Dx+)^T gbh ;  (Dx+)^T = -Dx-
+  const float dzf = dzT(a, 3, j, [&](int jj) { return gbf(i, jj); }, false);
+  const float dxh = -fmaf(C2, gbh(i + 1, j) - gbh(i - 2, j), C1 * (gbh(i, j) - gbh(i - 1, j)));
+  a.vx[so + k] += (dxe + dzg) * ih;
+  a.vz[so + k] += (dzf + dxh) * ih;
+
+  // own cell: memory-variable adjoints and the coefficient gradients
+  const float txx = Txx[k], tzz = Tzz[k], txz = Txz[k];
+  const float ex = dt * fmaf(a.cxx_x[k], txx, a.czz_x[k] * tzz);
+  const float ez = dt * fmaf(a.cxx_z[k], txx, a.czz_z[k] * tzz);
+  const float exz = dt * a.mxz[k] * txz;
+  if (a.axi[i] != 0.0f) a.ps_out[4][so + k] = a.bxi[i] * (Pe[k] + ex);
+  if (a.azi[j] != 0.0f) a.ps_out[5][so + k] = a.bzi[j] * (Pf[k] + ez);
+  if (a.azh[j] != 0.0f) a.ps_out[6][so + k] = a.bzh[j] * (Pg[k] + exz);
+  if (a.axh[i] != 0.0f) a.ps_out[7][so + k] = a.bxh[i] * (Ph[k] + exz);
+  const float fexx = a.trc[2][so + k], fezz = a.trc[3][so + k], fexz = a.trc[4][so + k];
+  float glam, gmu;
+  if (a.fs && j == 0) {
+    // txx += dt M exx with M = 4 mu (lambda + mu) / (lambda + 2 mu)
+    const float gM = dt * txx * fexx;
+    glam = gM * a.dM_dl[i];
+    gmu = gM * a.dM_dm[i];
+  } else {
+    glam = dt * (txx + tzz) * (fexx + fezz);
+    gmu = 2.0f * dt * fmaf(txx, fexx, tzz * fezz);
+  }
+  const float gmxz = dt * txz * fexz;
+  if (a.g_init) {
+    a.g[0][so + k] = glam;
+    a.g[1][so + k] = gmu;
+    a.g[2][so + k] = gmxz;
+  } else {
+    a.g[0][so + k] += glam;
+    a.g[1][so + k] += gmu;
+    a.g[2][so + k] += gmxz;
+  }
+}
+
+// residual injection into the velocity adjoints: entries sorted by (shot, cell, r);
+// the first entry of each run of equal cells adds the whole run in order.
+__global__ void el_inject_kernel(ElStep a, int n) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  const int tot = a.nshots * a.nrec;
+  if (e >= tot) return;
+  const int4 en = a.rec_sorted[e];  // (shot, cell, r, -)
+  if (e > 0) {
+    const int4 pv = a.rec_sorted[e - 1];
+    if (pv.x == en.x && pv.y == en.y) return;
+  }
+  const size_t plane = (size_t)a.NX * a.NZ;
+  const size_t k = (size_t)en.x * plane + en.y;
+  float ax = a.vx[k], az = a.vz[k];
+  for (int q = e; q < tot; ++q) {
+    const int4 c = a.rec_sorted[q];
+    if (c.x != en.x || c.y != en.y) break;
+    const float* r = a.resid + (((size_t)c.x * a.nt + n) * a.nrec + c.z) * 2;
+    ax += r[0];
+    az += r[1];
+  }
+  a.vx[k] = ax;
+  a.vz[k] = az;
+}
+
+__global__ __launch_bounds__(256) void el_adj_v_kernel(ElStep a) {
+  const int i = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
+  const int NX = a.NX, NZ = a.NZ;
+  if (i >= NX || j >= NZ) return;
+  const size_t plane = (size_t)NX * NZ;
+  const size_t so = (size_t)blockIdx.z * plane;
+  const size_t k = (size_t)j * NX + i;
+  const float dt = a.dt, ih = a.ih;
+  const float* Vx = a.vx + so;
+  const float* Vz = a.vz + so;
+  const float* Pa = a.ps_in[0] + so;
+  const float* Pb = a.ps_in[1] + so;
+  const float* Pc = a.ps_in[2] + so;
+  const float* Pd = a.ps_in[3] + so;
+  auto gba = [&](int ii, int jj) -> float {
+    if (ii < 0 || ii >= NX || jj < 0 || jj >= NZ) return 0.0f;
+    const size_t q = (size_t)jj * NX + ii;
+    const float kx = dt * a.bx[q] * Vx[q];
+    const float ax = a.axh[ii];
+    return ax == 0.0f ? kx : fmaf(ax, Pa[q] + kx, kx);
+  };
+  auto gbb = [&](int ii, int jj) -> float {
+    if (ii < 0 || ii >= NX || jj < 0 || jj >= NZ) return 0.0f;
+    const size_t q = (size_t)jj * NX + ii;
+    const float kx = dt * a.bx[q] * Vx[q];
+    const float az = a.azi[jj];
+    return az == 0.0f ? kx : fmaf(az, Pb[q] + kx, kx);
+  };
+  auto gbc = [&](int ii, int jj) -> float {
+    if (ii < 0 || ii >= NX || jj < 0 || jj >= NZ) return 0.0f;
+    const size_t q = (size_t)jj * NX + ii;
+    const float kz = dt * a.bz[q] * Vz[q];
+    const float ax = a.axi[ii];
+    return ax == 0.0f ? kz : fmaf(ax, Pc[q] + kz, kz);
+  };
+  auto gbd = [&](int ii, int jj) -> float {
+    if (ii < 0 || ii >= NX || jj < 0 || jj >= NZ) return 0.0f;
+    const size_t q = (size_t)jj * NX + ii;
+    const float kz = dt * a.bz[q] * Vz[q];
+    const float az = a.azh[jj];
+    return az == 0.0f ? kz : fmaf(az, Pd[q] + kz, kz);
+  };
+  // Txx += (Dx+)^T gba = -Dx- gba
+  const float dxa = -fmaf(C2, gba(i + 1, j) - gba(i - 2, j), C1 * (gba(i, j) - gba(i - 1, j)));
+  // Txz += (Dz- of txz)^T gbb + (Dx-)^T gbc = ... - Dx+ gbc
+  const float dzb = dzT(a, 1, j, [&](int jj) { return gbb(i, jj); }, false);
+  const float dxc = -fmaf(C2, gbc(i + 2, j) - gbc(i - 1, j), C1 * (gbc(i + 1, j) - gbc(i, j)));
+  // Tzz += (Dz+ of tzz)^T gbd
+  const float dzd = dzT(a, 0, j, [&](int jj) { return gbd(i, jj); }, true);
+  a.txx[so + k] += dxa * ih;
+  a.txz[so + k] += (dzb + dxc) * ih;
+  a.tzz[so + k] += dzd * ih;
+
+  const float vx = Vx[k], vz = Vz[k];
+  const float kx = dt * a.bx[k] * vx, kz = dt * a.bz[k] * vz;
+  if (a.axh[i] != 0.0f) a.ps_out[0][so + k] = a.bxh[i] * (Pa[k] + kx);
+  if (a.azi[j] != 0.0f) a.ps_out[1][so + k] = a.bzi[j] * (Pb[k] + kx);
+  if (a.axi[i] != 0.0f) a.ps_out[2][so + k] = a.bxi[i] * (Pc[k] + kz);
+  if (a.azh[j] != 0.0f) a.ps_out[3][so + k] = a.bzh[j] * (Pd[k] + kz);
+  const float gbx = dt * vx * a.trc[0][so + k];
+  const float gbz = dt * vz * a.trc[1][so + k];
+  if (a.g_init) {
+    a.g[3][so + k] = gbx;
+    a.g[4][so + k] = gbz;
+  } else {
+    a.g[3][so + k] += gbx;
+    a.g[4][so + k] += gbz;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Material preparation: padded vp, vs, rho, lambda, mu; buoyancies; harmonic
+// mu at txz nodes; stress coefficients (free-surface row uses M); C-PML tables.
+// ---------------------------------------------------------------------------
+__global__ void el_prep_kernel(const float* model, ElCoef c, int nx, int nz, int P, int top,
+                               int NX, int NZ, int fs) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (i >= NX || j >= NZ) return;
+  const size_t mn = (size_t)nx * nz;
+  const int ii = min(max(i - P, 0), nx - 1), jj = min(max(j - top, 0), nz - 1);
+  const size_t m = (size_t)jj * nx + ii, k = (size_t)j * NX + i;
+  const double vp = model[m], vs = model[mn + m], rho = model[2 * mn + m];
+  const double mu = rho * vs * vs, lam = rho * (vp * vp - 2.0 * vs * vs);
+  c.vp[k] = (float)vp;
+  c.vs[k] = (float)vs;
+  c.rho[k] = (float)rho;
+  c.lam[k] = (float)lam;
+  c.mu[k] = (float)mu;
+  if (fs && j == 0) {
+    const double d = lam + 2.0 * mu;
+    c.cxx_x[k] = d > 0 ? (float)(4.0 * mu * (lam + mu) / d) : 0.0f;
+    c.cxx_z[k] = c.czz_x[k] = c.czz_z[k] = 0.0f;
+    c.smask[k] = 0.0f;
+    c.dM_dl[i] = d > 0 ? (float)(4.0 * mu * mu / (d * d)) : 0.0f;
+    c.dM_dm[i] = d > 0 ? (float)(4.0 * (lam * lam + 2.0 * lam * mu + 2.0 * mu * mu) / (d * d)) : 0.0f;
+  } else {
+    c.cxx_x[k] = c.czz_z[k] = (float)(lam + 2.0 * mu);
+    c.cxx_z[k] = c.czz_x[k] = (float)lam;
+    c.smask[k] = 1.0f;
+  }
+}
+
+// buoyancies and the harmonic-mean shear modulus need neighbouring cells: a
+// second pass over the padded grid (values re-read from the edge-replicated model)
+__device__ __forceinline__ size_t el_model_index(int i, int j, int nx, int nz, int P, int top) {
+  const int mi = min(max(i - P, 0), nx - 1), mj = min(max(j - top, 0), nz - 1);
+  return (size_t)mj * nx + mi;
+}
+
+__global__ void el_prep2_kernel(const float* model, ElCoef c, int nx, int nz, int P, int top,
+                                int NX, int NZ) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (i >= NX || j >= NZ) return;
+  const size_t mn = (size_t)nx * nz;
+  auto rho_at = [&](int ii, int jj) -> double {
+    return (double)model[2 * mn + el_model_index(ii, jj, nx, nz, P, top)];
+  };
+  auto mu_at = [&](int ii, int jj) -> double {
+    const size_t m = el_model_index(ii, jj, nx, nz, P, top);
+    const double vs = model[mn + m], rho = model[2 * mn + m];
+    return rho * vs * vs;
+  };
+  const int i1 = min(i + 1, NX - 1), j1 = min(j + 1, NZ - 1);
+  const size_t k = (size_t)j * NX + i;
+  const double r0 = rho_at(i, j);
+  c.bx[k] = (float)(2.0 / (r0 + rho_at(i1, j)));
+  c.bz[k] = (float)(2.0 / (r0 + rho_at(i, j1)));
+  const double m00 = mu_at(i, j), m10 = mu_at(i1, j), m01 = mu_at(i, j1), m11 = mu_at(i1, j1);
+  c.mxz[k] = (m00 > 0 && m10 > 0 && m01 > 0 && m11 > 0)
+                 ? (float)(4.0 / (1.0 / m00 + 1.0 / m10 + 1.0 / m01 + 1.0 / m11))
+                 : 0.0f;
+}
+
+// C-PML coefficients at node x = i + shift of an axis of n cells with lo / hi pads
+__device__ void el_pml(int i, double shift, int n, int lo, int hi, double h, double dt,
+                       double vmax, double f0, double R, float* a, float* b) {
+  const double x = i + shift;
+  double xi = 0.0, L = 1.0;
+  if (lo > 0 && x < lo) {
+    xi = (lo - x) * h;
+    L = lo * h;
+  } else if (hi > 0 && x > n - 1 - hi) {
+    xi = (x - (n - 1 - hi)) * h;
+    L = hi * h;
+  }
+  if (xi > L) xi = L;
+  const double d0 = -3.0 * vmax * log(R) / (2.0 * L);
+  const double d = xi > 0.0 ? d0 * (xi / L) * (xi / L) : 0.0;
+  const double alpha = M_PI * f0 * (1.0 - xi / L);
+  const double bb = exp(-(d + alpha) * dt);
+  b[i] = (float)bb;
+  a[i] = d > 0.0 ? (float)(d / (d + alpha) * (bb - 1.0)) : 0.0f;
+}
+
+__global__ void el_tables_kernel(ElCoef c, int NX, int NZ, int P, int top, double h, double dt,
+                                 double vmax, double f0, double R) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < NX) {
+    el_pml(i, 0.0, NX, P, P, h, dt, vmax, f0, R, c.axi, c.bxi);
+    el_pml(i, 0.5, NX, P, P, h, dt, vmax, f0, R, c.axh, c.bxh);
+  }
+  if (i < NZ) {
+    el_pml(i, 0.0, NZ, top, P, h, dt, vmax, f0, R, c.azi, c.bzi);
+    el_pml(i, 0.5, NZ, top, P, h, dt, vmax, f0, R, c.azh, c.bzh);
+  }
+}
+
+// tot_q += sum over shots of the FP32 partial q (q = 0..4), float64
+__global__ void el_fold_kernel(double* tot, const float* gpart, int nshots, size_t plane) {
+  const size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int q = blockIdx.y;
+  if (c >= plane) return;
+  double acc = tot[q * plane + c];
+  for (int s = 0; s < nshots; ++s) acc += (double)gpart[((size_t)q * nshots + s) * plane + c];
+  tot[q * plane + c] = acc;
+}
+
+// Chain rule on the padded grid for one padded cell:
+//   lambda = rho (vp^2 - 2 vs^2), mu = rho vs^2; mu_xz = harmonic mean of 4 mu;
+//   b = 2/(rho_a + rho_b). Returns (gvp, gvs, grho).
+__device__ void el_chain_cell(const double* tot, size_t plane, const ElCoef& c, int i, int j,
+                              int NX, int NZ, double* out) {
+  const size_t q = (size_t)j * NX + i;
+  double gl = tot[q], gm = tot[plane + q], gr = 0.0;
+  const double muq = c.mu[q];
+  // contributions of the txz nodes and buoyancy nodes whose stencil uses cell q
+  for (int dj = -1; dj <= 0; ++dj)
+    for (int di = -1; di <= 0; ++di) {
+      const int ki = i + di, kj = j + dj;
+      if (ki < 0 || kj < 0) continue;
+      const int k1i = min(ki + 1, NX - 1), k1j = min(kj + 1, NZ - 1);
+      const size_t k = (size_t)kj * NX + ki;
+      // multiplicity of q among the four mu cells of txz node k
+      const int mult = (ki == i && kj == j) + (k1i == i && kj == j) + (ki == i && k1j == j) +
+                       (k1i == i && k1j == j);
+      const double mxz = c.mxz[k];
+      if (mult && mxz > 0.0 && muq > 0.0)
+        gm += mult * tot[2 * plane + k] * mxz * mxz / (4.0 * muq * muq);
+      // buoyancy bx at k uses rho at (ki, kj) and (k1i, kj); bz at (ki, kj), (ki, k1j)
+      if (kj == j) {
+        const int mb = (ki == i) + (k1i == i);
+        const double b = c.bx[k];
+        gr += mb * tot[3 * plane + k] * (-0.5 * b * b);
+      }
+      if (ki == i) {
+        const int mb = (kj == j) + (k1j == j);
+        const double b = c.bz[k];
+        gr += mb * tot[4 * plane + k] * (-0.5 * b * b);
+      }
+    }
+  const double vp = c.vp[q], vs = c.vs[q], rho = c.rho[q];
+  out[0] = gl * 2.0 * rho * vp;
+  out[1] = gl * (-4.0 * rho * vs) + gm * 2.0 * rho * vs;
+  out[2] = gl * (vp * vp - 2.0 * vs * vs) + gm * vs * vs + gr;
+}
+
+__global__ void el_finish_kernel(const double* tot, ElCoef c, float* grad, int nx, int nz, int P,
+                                 int top, int NX, int NZ) {
+  const int ii = blockIdx.x * blockDim.x + threadIdx.x;
+  const int jj = blockIdx.y;
+  if (ii >= nx || jj >= nz) return;
+  const size_t plane = (size_t)NX * NZ;
+  const int i0 = ii == 0 ? 0 : ii + P, i1 = ii == nx - 1 ? NX - 1 : ii + P;
+  const int j0 = jj == 0 ? 0 : jj + top, j1 = jj == nz - 1 ? NZ - 1 : jj + top;
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (int j = j0; j <= j1; ++j)
+    for (int i = i0; i <= i1; ++i) {
+      double o[3];
+      el_chain_cell(tot, plane, c, i, j, NX, NZ, o);
+      acc[0] += o[0];
+      acc[1] += o[1];
+      acc[2] += o[2];
+    }
+  const size_t mn = (size_t)nx * nz, m = (size_t)jj * nx + ii;
+  grad[m] = (float)acc[0];
+  grad[mn + m] = (float)acc[1];
+  grad[2 * mn + m] = (float)acc[2];
+}
+
+dim3 grid_of(const ElStep& a) { return dim3((a.NX + 63) / 64, (a.NZ + 3) / 4, a.nshots); }
+
+}  // namespace
+
+int el_launch_prep(const float* model, const ElCoef& c, int nx, int nz, int P, int fs, double h,
+                   double dt, double vmax, double f0, double R, hipStream_t s) {
+  const int top = fs ? 0 : P;
+  const int NX = nx + 2 * P, NZ = nz + top + P;
+  hipLaunchKernelGGL(el_prep_kernel, dim3((NX + 255) / 256, NZ), dim3(256), 0, s, model, c, nx,
+                     nz, P, top, NX, NZ, fs);
+  hipLaunchKernelGGL(el_prep2_kernel, dim3((NX + 255) / 256, NZ), dim3(256), 0, s, model, c, nx,
+                     nz, P, top, NX, NZ);
+  const int nmax = NX > NZ ? NX : NZ;
+  hipLaunchKernelGGL(el_tables_kernel, dim3((nmax + 255) / 256), dim3(256), 0, s, c, NX, NZ, P,
+                     top, h, dt, vmax, f0, R);
+  SWEEP_HIP(hipGetLastError());
+  return SWEEP_OK;
+}
+
+int el_launch_fwd(const ElStep& a, hipStream_t s, hipEvent_t* ev) {
+  if (ev) SWEEP_HIP(hipEventRecord(ev[0], s));
+  hipLaunchKernelGGL(el_vel_kernel, grid_of(a), dim3(256), 0, s, a);
+  if (a.gathers && a.nrec > 0)
+    hipLaunchKernelGGL(el_record_kernel, dim3((a.nshots * a.nrec + 255) / 256), dim3(256), 0, s,
+                       a);
+  hipLaunchKernelGGL(el_str_kernel, grid_of(a), dim3(256), 0, s, a);
+  if (ev) SWEEP_HIP(hipEventRecord(ev[1], s));
+  SWEEP_HIP(hipGetLastError());
+  return SWEEP_OK;
+}
+
+int el_launch_adj(const ElStep& a, hipStream_t s, hipEvent_t* ev) {
+  if (ev) SWEEP_HIP(hipEventRecord(ev[0], s));
+  hipLaunchKernelGGL(el_adj_s_kernel, grid_of(a), dim3(256), 0, s, a);
+  if (a.nrec > 0)
+    hipLaunchKernelGGL(el_inject_kernel, dim3((a.nshots * a.nrec + 255) / 256), dim3(256), 0, s,
+                       a, a.n);
+  hipLaunchKernelGGL(el_adj_v_kernel, grid_of(a), dim3(256), 0, s, a);
+  if (ev) SWEEP_HIP(hipEventRecord(ev[1], s));
+  SWEEP_HIP(hipGetLastError());
+  return SWEEP_OK;
+}
+
+int el_launch_fold(double* tot, const float* gpart, int nshots, size_t plane, hipStream_t s) {
+  hipLaunchKernelGGL(el_fold_kernel, dim3((unsigned)((plane + 255) / 256), 5), dim3(256), 0, s,
+                     tot, gpart, nshots, plane);
+  SWEEP_HIP(hipGetLastError());
+  return SWEEP_OK;
+}
+
+int el_launch_finish(const double* tot, const ElCoef& c, float* grad, int nx, int nz, int P,
+                     int fs, hipStream_t s) {
+  const int top = fs ? 0 : P;
+  const int NX = nx + 2 * P, NZ = nz + top + P;
+  hipLaunchKernelGGL(el_finish_kernel, dim3((nx + 255) / 256, nz), dim3(256), 0, s, tot, c, grad,
+                     nx, nz, P, top, NX, NZ);
+  SWEEP_HIP(hipGetLastError());
+  return SWEEP_OK;
+}
+
+}  // namespace sweep

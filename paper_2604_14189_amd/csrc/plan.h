@@ -38,10 +38,21 @@ struct KernelTimer {
   size_t used[kNumClasses] = {0, 0, 0, 0, 0, 0};
   ~KernelTimer();
   void reset();
-  // Four events for one main + band launch pair of classes (ci, cf), or null
-  // when timing is off.
+  // Four events for one main + band launch pair of classes (ci, cf; cf < 0 for
+  // a single class, which uses the first two), or null when timing is off.
   hipEvent_t* take(int ci, int cf);
   hipEvent_t quad[4];
+};
+}  // namespace sweep
+
+namespace sweep {
+struct ElLayout {
+  size_t plane;
+  size_t coef, tabx, tabz, dM, wav, src_cell, rec_cell, rec_sorted, state;
+  size_t fwd_end;
+  int nseg;
+  size_t ck, trace, adj, gpart, tot;
+  size_t bwd_end;
 };
 }  // namespace sweep
 
@@ -54,6 +65,12 @@ struct sweep_plan {
   // tiling for the current tuning
   int TZ = 0, tiles_x = 0, tiles_z = 0, ntiles = 0;
   std::vector<int2> xchunks, zchunks;  // C-PML band pieces (start, count <= 48)
+  // elastic: receivers sorted by (shot, cell, r) for deterministic injection,
+  // and the transposed z-taps of the first rows under a free surface
+  std::vector<int4> rec_sorted;
+  int tt_cnt[4][4];
+  int tt_off[4][4][8];
+  float tt_w[4][4][8];
   std::vector<int> rec_off;
   std::vector<int2> rec_ent;
   // state of the last forward
@@ -67,4 +84,10 @@ struct sweep_plan {
 namespace sweep {
 void ac_build_tiling(sweep_plan* p);
 void ac_layout(const sweep_plan* p, AcLayout& L);
+void el_layout(const sweep_plan* p, ElLayout& L);
+void el_build_tables(sweep_plan* p);
+int el_forward(sweep_plan* p, const float* model, const float* wavelet, float* gathers,
+               void* work, size_t bytes, int save, hipStream_t s);
+int el_backward(sweep_plan* p, const float* resid, float* grad, void* work, size_t bytes,
+                hipStream_t s);
 }  // namespace sweep

@@ -9,6 +9,11 @@ layered1000x300_shot37.npz: shot 37 of the 1000x300 / 3000-step / 40-cell-pad
 acoustic workload (64 shots, 1000 receivers at depth 5, 8 Hz Ricker). Stores
 8 complete receiver traces and the model gradient for a band-limited seeded
 residual on that shot (20 000 sampled cells plus the full gradient norm).
+
+elastic600x300_shot11.npz: shot 11 of the 600x300 / 4000-step elastic workload
+(30-cell pad, free surface, 32 explosive 15 Hz shots, 600 two-component
+receivers): 8 complete (vx, vz) traces and the (vp, vs, rho) gradient for a
+band-limited seeded residual on that shot at 20 000 sampled cells.
 """
 import os
 import sys
@@ -41,6 +46,28 @@ def layered_shot37(path):
                         grad_norm=np.linalg.norm(g))
 
 
+def elastic_shot11(path):
+    from tests.helpers import el_case_from_workload
+    w = synth.workload("elastic600x300")
+    s = 11
+    case = el_case_from_workload(w, shots=[s])
+    pb = case.oracle_problem(oracle)
+    resid = f32(synth.bandlimited_noise((1, w.nt, w.nrec * 2), w.f0, w.dt, 11)
+                .reshape(1, w.nt, w.nrec, 2))
+    t = time.time()
+    g, _, d = oracle.el_gradient(pb, case.model, case.src, case.wav, case.rec, resid,
+                                 want_gathers=True)
+    print("oracle elastic gradient took %.1f s" % (time.time() - t), flush=True)
+    trace_idx = np.linspace(0, w.nrec - 1, 8).round().astype(np.int64)
+    cells = np.random.default_rng(11).choice(g[0].size, 20000, replace=False)
+    np.savez_compressed(path, shot=s, trace_idx=trace_idx, traces=d[0][:, trace_idx, :],
+                        grad_cells=cells, grad=np.stack([g[c].ravel()[cells] for c in range(3)]))
+
+
 if __name__ == "__main__":
     oracle.build(force=False)
-    layered_shot37(os.path.join(HERE, "layered1000x300_shot37.npz"))
+    which = sys.argv[1:] or ["layered", "elastic"]
+    if "layered" in which:
+        layered_shot37(os.path.join(HERE, "layered1000x300_shot37.npz"))
+    if "elastic" in which:
+        elastic_shot11(os.path.join(HERE, "elastic600x300_shot11.npz"))

@@ -1,0 +1,110 @@
+"""GPU parity: elastic forward / adjoint (HIP, FP32) against the FP64 oracle.
+
+Seismograms (vx, vz) <= 1e-5 and gradients (vp, vs, rho, each) <= 1e-4
+relative L2, with and without the free surface.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from tests.helpers import el_case_from_workload, f32, random_el_case, rel_l2
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+SEIS_TOL = 1e-5
+GRAD_TOL = 1e-4
+
+
+def _dev(a):
+    return torch.as_tensor(np.asarray(a, dtype=np.float32), device="cuda").contiguous()
+
+
+def _host(t):
+    torch.cuda.synchronize()
+    return t.double().cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def sw():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2604_14189_amd as sw
+    sw.lib()
+    return sw
+
+
+@pytest.mark.parametrize("fs", [0, 1])
+def test_forward_parity(sw, orc, fs):
+    case = random_el_case(1, fs=fs)
+    d = case.plan().forward(_dev(case.model), _dev(case.wav))
+    ref = orc.el_forward(case.oracle_problem(orc), case.model, case.src, case.wav, case.rec)
+    err = rel_l2(_host(d), ref)
+    print("elastic forward fs", fs, "rel L2", err, flush=True)
+    assert err <= SEIS_TOL
+
+
+@pytest.mark.parametrize("fs", [0, 1])
+def test_gradient_parity(sw, orc, fs):
+    case = random_el_case(2, fs=fs, nt=260, ckpt=23)
+    plan = case.plan()
+    d = plan.forward(_dev(case.model), _dev(case.wav), save=True)
+    resid = f32(synth.bandlimited_noise((case.nshots, case.nt, case.nrec * 2), 20.0, case.dt, 9)
+                .reshape(case.nshots, case.nt, case.nrec, 2))
+    g = _host(plan.backward(_dev(resid)))
+    gref, _, dref = orc.el_gradient(case.oracle_problem(orc), case.model, case.src, case.wav,
+                                    case.rec, resid, want_gathers=True)
+    e_d = rel_l2(_host(d), dref)
+    errs = [rel_l2(g[c], gref[c]) for c in range(3)]
+    print("elastic gradient fs", fs, "gathers", e_d, "vp/vs/rho", errs, flush=True)
+    assert e_d <= SEIS_TOL
+    assert max(errs) <= GRAD_TOL
+
+
+def test_repeatable(sw):
+    case = random_el_case(3, nt=120, ckpt=30)
+    resid = _dev(np.random.default_rng(0).standard_normal((case.nshots, case.nt, case.nrec, 2)))
+    out = []
+    for _ in range(2):
+        plan = case.plan()
+        d = plan.forward(_dev(case.model), _dev(case.wav), save=True)
+        out.append((d.clone(), plan.backward(resid).clone()))
+    assert torch.equal(out[0][0], out[1][0]) and torch.equal(out[0][1], out[1][1])
+
+
+def test_batched_equals_single_shot(sw):
+    case = random_el_case(4, nt=100, nshots=3)
+    dall = case.plan().forward(_dev(case.model), _dev(case.wav))
+    for s in range(case.nshots):
+        one = random_el_case(4, nt=100, nshots=3)
+        one.src, one.rec, one.wav = one.src[s:s + 1], one.rec[s:s + 1], one.wav[s:s + 1]
+        d1 = one.plan().forward(_dev(one.model), _dev(one.wav))
+        assert torch.equal(d1[0], dall[s])
+
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "elastic600x300_shot11.npz")
+
+
+@pytest.mark.skipif(not os.path.exists(GOLDEN), reason="golden file not generated")
+def test_full_size_elastic_sampled_shot(sw):
+    """All 32 shots of the 600x300 / 4000-step elastic workload (free surface);
+    shot 11 compared with stored oracle traces and gradient samples."""
+    gold = np.load(GOLDEN)
+    w = synth.workload("elastic600x300")
+    case = el_case_from_workload(w)
+    plan = case.plan()
+    d = plan.forward(_dev(case.model), _dev(case.wav), save=True)
+    s = int(gold["shot"])
+    tr = torch.as_tensor(gold["trace_idx"], device="cuda")
+    e_d = rel_l2(_host(d[s][:, tr, :]), gold["traces"])
+    resid = np.zeros((case.nshots, case.nt, case.nrec, 2), np.float32)
+    resid[s] = synth.bandlimited_noise((1, case.nt, case.nrec * 2), w.f0, w.dt, 11)[0].reshape(
+        case.nt, case.nrec, 2)
+    g = _host(plan.backward(_dev(resid)))
+    cells = gold["grad_cells"]
+    errs = [rel_l2(g[c].ravel()[cells], gold["grad"][c]) for c in range(3)]
+    print("full-size elastic shot", s, "traces", e_d, "grad", errs, flush=True)
+    assert e_d <= SEIS_TOL
+    assert max(errs) <= GRAD_TOL
