@@ -92,6 +92,17 @@ void sweep_plan_destroy(sweep_plan* plan);
 int sweep_plan_set_tuning(sweep_plan* plan, const sweep_tuning* t);
 int sweep_plan_get_tuning(const sweep_plan* plan, sweep_tuning* t);
 
+/* Autotuner: runs `steps` forward steps of this plan for every supported tile
+ * choice (rz = 1, 2, 4, 8 rows per thread in the main stencil kernel), keeps the
+ * fastest and stores it in the plan; `cache_path` (may be NULL) is a text file
+ * of previous results keyed by (GPU arch, physics, NX, NZ, nshots), read first
+ * and appended to. Synchronises `stream`. d_work needs the forward-only
+ * workspace. Results never depend on the choice (bitwise). *chosen_rz (may be
+ * NULL) receives the selected value. */
+int sweep_plan_autotune(sweep_plan* plan, const float* d_model, const float* d_wavelet,
+                        void* d_work, size_t work_bytes, int steps, const char* cache_path,
+                        void* stream, int* chosen_rz);
+
 /* Device workspace the caller must provide: for_backward = 0 for a forward-only
  * call, 1 for forward(save_for_backward=1) followed by backward(). */
 size_t sweep_plan_workspace_bytes(const sweep_plan* plan, int for_backward);
@@ -133,6 +144,27 @@ int sweep_backward(sweep_plan* plan, const float* d_resid, float* d_grad, void* 
  * duration in milliseconds since the reset. */
 int sweep_plan_set_profiling(sweep_plan* plan, int enable);
 int sweep_plan_kernel_time(sweep_plan* plan, int kernel_class, int* launches, double* total_ms);
+
+/* ---- batches: several acoustic plans of different grids / shots / nt ----
+ * Batch modelling of different models (Sec. 2.2): every time step of every
+ * plan in the batch is advanced by one launch per kernel kind (plans whose nt
+ * is reached drop out), so k launches serve all of them instead of one set per
+ * plan. Results are bitwise identical to running each plan alone. The plans
+ * stay owned by the caller and must outlive the batch; they must share the
+ * same rz tuning. At most 8 plans. With use_graph = 1 the whole forward (and
+ * the whole backward) is captured once as a hipGraph and replayed while the
+ * pointers passed are unchanged. Pointer arrays are host arrays of device
+ * pointers, one per plan; the workspace is carved into one region per plan. */
+typedef struct sweep_batch sweep_batch;
+int sweep_batch_create(sweep_plan* const* plans, int nplans, sweep_batch** out);
+void sweep_batch_destroy(sweep_batch* batch);
+int sweep_batch_set_graph(sweep_batch* batch, int use_graph);
+size_t sweep_batch_workspace_bytes(const sweep_batch* batch, int for_backward);
+int sweep_batch_forward(sweep_batch* batch, const float* const* d_models,
+                        const float* const* d_wavelets, float* const* d_gathers, void* d_work,
+                        size_t work_bytes, int save_for_backward, void* stream);
+int sweep_batch_backward(sweep_batch* batch, const float* const* d_resids, float* const* d_grads,
+                         void* d_work, size_t work_bytes, void* stream);
 
 /* L2 misfit: d_resid[i] = d_pred[i] - d_obs[i] and *d_J = 0.5 * sum resid^2
  * (float64, device). Deterministic two-stage reduction; d_scratch must hold

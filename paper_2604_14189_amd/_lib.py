@@ -61,6 +61,22 @@ _SIGS = {
     "sweep_plan_kernel_time": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int,
                                               ctypes.POINTER(ctypes.c_int),
                                               ctypes.POINTER(ctypes.c_double)]),
+    "sweep_plan_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                           ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int,
+                                           ctypes.c_char_p, ctypes.c_void_p,
+                                           ctypes.POINTER(ctypes.c_int)]),
+    "sweep_batch_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int,
+                                          ctypes.POINTER(ctypes.c_void_p)]),
+    "sweep_batch_destroy": (None, [ctypes.c_void_p]),
+    "sweep_batch_set_graph": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "sweep_batch_workspace_bytes": (ctypes.c_size_t, [ctypes.c_void_p, ctypes.c_int]),
+    "sweep_batch_forward": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p),
+                                           ctypes.POINTER(ctypes.c_void_p),
+                                           ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p,
+                                           ctypes.c_size_t, ctypes.c_int, ctypes.c_void_p]),
+    "sweep_batch_backward": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p),
+                                            ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p,
+                                            ctypes.c_size_t, ctypes.c_void_p]),
     "sweep_l2_misfit_scratch_bytes": (ctypes.c_size_t, [ctypes.c_size_t]),
     "sweep_l2_misfit": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                        ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,

@@ -167,14 +167,14 @@ __device__ __forceinline__ void stage_box(float* s, const float* __restrict__ f,
 }
 
 template <int RZ>
-__global__ __launch_bounds__(kThreads) void ac_fwd_main(AcStep a) {
+__device__ __forceinline__ void ac_fwd_main_body(const AcStep& a, const int bx, const int by, const int bz) {
   using T = MainTile<RZ>;
   __shared__ float sp[T::LH * T::LW];
   const int tid = threadIdx.x;
   const int lx = tid & 63;
   const int zb = (tid >> 6) * RZ;
-  const int tile = blockIdx.x;
-  const int shot = blockIdx.y;
+  const int tile = bx;
+  const int shot = by;
   const int NX = a.NX, NZ = a.NZ, P = a.P;
   const size_t plane = (size_t)NX * NZ;
   const int x0 = (tile % a.tiles_x) * kTX, z0 = (tile / a.tiles_x) * T::TZ;
@@ -265,14 +265,14 @@ __device__ __forceinline__ void inject_residual(const AcStep& a, int shot, int t
 // kernels already subtracted their pad terms from lambda^{n+2}' in place;
 // g += lambda^{n+1} B'^n; then r_{n-1} is injected at the receivers.
 template <int RZ>
-__global__ __launch_bounds__(kThreads) void ac_adj_main(AcStep a) {
+__device__ __forceinline__ void ac_adj_main_body(const AcStep& a, const int bx, const int by, const int bz) {
   using T = MainTile<RZ>;
   __shared__ float sq[T::LH * T::LW];
   const int tid = threadIdx.x;
   const int lx = tid & 63;
   const int zb = (tid >> 6) * RZ;
-  const int tile = blockIdx.x;
-  const int shot = blockIdx.y;
+  const int tile = bx;
+  const int shot = by;
   const int NX = a.NX, NZ = a.NZ;
   const size_t plane = (size_t)NX * NZ;
   const int x0 = (tile % a.tiles_x) * kTX, z0 = (tile / a.tiles_x) * T::TZ;
@@ -349,12 +349,12 @@ constexpr int kChunk = 48;
 constexpr int kXRows = 4;
 
 // psi_x^n, zeta_x^n and Ex = D1x' psi_x^n + zeta_x^n; p^{n-1} -= Cs Ex.
-__global__ __launch_bounds__(kThreads) void ac_fwd_xband(AcStep a) {
+__device__ __forceinline__ void ac_fwd_xband_body(const AcStep& a, const int bx, const int by, const int bz) {
   __shared__ float sp[4][kXRows][64];
   __shared__ float ss[4][kXRows][64];
   const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int2 ch = a.xchunks[blockIdx.x];
-  const int shot = blockIdx.z;
+  const int2 ch = a.xchunks[bx];
+  const int shot = bz;
   const int NX = a.NX, NZ = a.NZ, P = a.P, P2 = 2 * P;
   const int gx = ch.x - 8 + l;
   const size_t plane = (size_t)NX * NZ;
@@ -362,7 +362,7 @@ __global__ __launch_bounds__(kThreads) void ac_fwd_xband(AcStep a) {
   const bool col_ok = gx >= 0 && gx < NX;
   const int col0 = col_ok ? xstrip_col(gx, NX, P) : -1;
   const float axv = col0 >= 0 ? a.ax[gx] : 0.0f, bxv = col0 >= 0 ? a.bx[gx] : 0.0f;
-  const int gz0 = (blockIdx.y * 4 + w) * kXRows;
+  const int gz0 = (by * 4 + w) * kXRows;
   float pv[kXRows], psio[kXRows], zo[kXRows], cs[kXRows], pp[kXRows];
 #pragma unroll
   for (int rr = 0; rr < kXRows; ++rr) {
@@ -413,13 +413,13 @@ __global__ __launch_bounds__(kThreads) void ac_fwd_xband(AcStep a) {
 // Adjoint of the x band: zbar = Z + q, Qbar = q + a_x zbar (q = Cs lambda^{n+1}),
 // psbar = Psi - D1x' Qbar, Eadj = D2x'(a_x zbar) - D1x'(a_x psbar);
 // lambda^{n+2}' -= Eadj; Psi <- b_x psbar, Z <- b_x zbar.
-__global__ __launch_bounds__(kThreads) void ac_adj_xband(AcStep a) {
+__device__ __forceinline__ void ac_adj_xband_body(const AcStep& a, const int bx, const int by, const int bz) {
   __shared__ float sQ[4][kXRows][64];
   __shared__ float sS[4][kXRows][64];
   __shared__ float sT[4][kXRows][64];
   const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int2 ch = a.xchunks[blockIdx.x];
-  const int shot = blockIdx.z;
+  const int2 ch = a.xchunks[bx];
+  const int shot = bz;
   const int NX = a.NX, NZ = a.NZ, P = a.P, P2 = 2 * P;
   const int gx = ch.x - 8 + l;
   const size_t plane = (size_t)NX * NZ;
@@ -427,7 +427,7 @@ __global__ __launch_bounds__(kThreads) void ac_adj_xband(AcStep a) {
   const bool col_ok = gx >= 0 && gx < NX;
   const int col0 = col_ok ? xstrip_col(gx, NX, P) : -1;
   const float axv = col0 >= 0 ? a.ax[gx] : 0.0f, bxv = col0 >= 0 ? a.bx[gx] : 0.0f;
-  const int gz0 = (blockIdx.y * 4 + w) * kXRows;
+  const int gz0 = (by * 4 + w) * kXRows;
   float lv[kXRows], cv[kXRows], zi[kXRows], psi_in[kXRows], pp[kXRows];
 #pragma unroll
   for (int rr = 0; rr < kXRows; ++rr) {
@@ -489,13 +489,13 @@ constexpr int kZStage = kZRows / 4;       // staged rows per wave (64 / 4)
 constexpr int kZPsi = (kZRows - 8) / 4;   // psi rows per wave
 constexpr int kZOut = kChunk / 4;         // output rows per wave
 
-__global__ __launch_bounds__(kThreads) void ac_fwd_zband(AcStep a) {
+__device__ __forceinline__ void ac_fwd_zband_body(const AcStep& a, const int bx, const int by, const int bz) {
   __shared__ float sp[kZRows * kTX];
   __shared__ float ss[kZRows * kTX];
   const int c = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int2 ch = a.zchunks[blockIdx.y];
-  const int x0 = blockIdx.x * kTX, gx = x0 + c;
-  const int shot = blockIdx.z;
+  const int2 ch = a.zchunks[by];
+  const int x0 = bx * kTX, gx = x0 + c;
+  const int shot = bz;
   const int NX = a.NX, NZ = a.NZ, P = a.P;
   const bool col_ok = gx < NX;
   const size_t plane = (size_t)NX * NZ;
@@ -566,14 +566,14 @@ __global__ __launch_bounds__(kThreads) void ac_fwd_zband(AcStep a) {
   }
 }
 
-__global__ __launch_bounds__(kThreads) void ac_adj_zband(AcStep a) {
+__device__ __forceinline__ void ac_adj_zband_body(const AcStep& a, const int bx, const int by, const int bz) {
   __shared__ float sQ[kZRows * kTX];
   __shared__ float sS[kZRows * kTX];
   __shared__ float sT[kZRows * kTX];
   const int c = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int2 ch = a.zchunks[blockIdx.y];
-  const int x0 = blockIdx.x * kTX, gx = x0 + c;
-  const int shot = blockIdx.z;
+  const int2 ch = a.zchunks[by];
+  const int x0 = bx * kTX, gx = x0 + c;
+  const int shot = bz;
   const int NX = a.NX, NZ = a.NZ, P = a.P;
   const bool col_ok = gx < NX;
   const size_t plane = (size_t)NX * NZ;
@@ -644,6 +644,76 @@ __global__ __launch_bounds__(kThreads) void ac_adj_zband(AcStep a) {
     const float E = d2s(&sS[r * kTX + c], kTX) - d1s(&sT[r * kTX + c], kTX);
     a.prev_adj[shot * plane + (size_t)gz * NX + gx] = pp[k] - E;
   }
+}
+
+// ---------------------------------------------------------------------------
+// Kernel entry points: one plan (block coordinates from the launch grid) or a
+// batch of plans of different shapes in one launch (the flat block index is
+// split by the per-plan block counts of this launch).
+// ---------------------------------------------------------------------------
+template <int RZ>
+__global__ __launch_bounds__(kThreads) void ac_fwd_main(AcStep a) {
+  ac_fwd_main_body<RZ>(a, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+template <int RZ>
+__global__ __launch_bounds__(kThreads) void ac_adj_main(AcStep a) {
+  ac_adj_main_body<RZ>(a, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+__global__ __launch_bounds__(kThreads) void ac_fwd_xband(AcStep a) {
+  ac_fwd_xband_body(a, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+__global__ __launch_bounds__(kThreads) void ac_adj_xband(AcStep a) {
+  ac_adj_xband_body(a, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+__global__ __launch_bounds__(kThreads) void ac_fwd_zband(AcStep a) {
+  ac_fwd_zband_body(a, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+__global__ __launch_bounds__(kThreads) void ac_adj_zband(AcStep a) {
+  ac_adj_zband_body(a, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
+// plan index and the block coordinates inside that plan's grid
+struct BatchCoord {
+  int p, x, y, z;
+};
+__device__ __forceinline__ BatchCoord batch_coord(const AcBatch& b) {
+  const int f = blockIdx.x;
+  int p = 0;
+  while (p + 1 < b.nplans && f >= b.base[p + 1]) ++p;
+  const int l = f - b.base[p];
+  BatchCoord c;
+  c.p = p;
+  c.x = l % b.gx[p];
+  c.y = (l / b.gx[p]) % b.gy[p];
+  c.z = l / (b.gx[p] * b.gy[p]);
+  return c;
+}
+
+template <int RZ>
+__global__ __launch_bounds__(kThreads) void ac_fwd_main_batch(AcBatch b) {
+  const BatchCoord c = batch_coord(b);
+  ac_fwd_main_body<RZ>(b.step[c.p], c.x, c.y, c.z);
+}
+template <int RZ>
+__global__ __launch_bounds__(kThreads) void ac_adj_main_batch(AcBatch b) {
+  const BatchCoord c = batch_coord(b);
+  ac_adj_main_body<RZ>(b.step[c.p], c.x, c.y, c.z);
+}
+__global__ __launch_bounds__(kThreads) void ac_fwd_xband_batch(AcBatch b) {
+  const BatchCoord c = batch_coord(b);
+  ac_fwd_xband_body(b.step[c.p], c.x, c.y, c.z);
+}
+__global__ __launch_bounds__(kThreads) void ac_adj_xband_batch(AcBatch b) {
+  const BatchCoord c = batch_coord(b);
+  ac_adj_xband_body(b.step[c.p], c.x, c.y, c.z);
+}
+__global__ __launch_bounds__(kThreads) void ac_fwd_zband_batch(AcBatch b) {
+  const BatchCoord c = batch_coord(b);
+  ac_fwd_zband_body(b.step[c.p], c.x, c.y, c.z);
+}
+__global__ __launch_bounds__(kThreads) void ac_adj_zband_batch(AcBatch b) {
+  const BatchCoord c = batch_coord(b);
+  ac_adj_zband_body(b.step[c.p], c.x, c.y, c.z);
 }
 
 // ---------------------------------------------------------------------------
@@ -720,6 +790,60 @@ int launch_step(const AcStep& a, hipStream_t s, hipEvent_t* ev) {
   return SWEEP_OK;
 }
 
+// One batched step over the active plans `steps[0..n)` (all with the same rz).
+template <int RZ, bool kAdj>
+int launch_step_batch(const AcStep* steps, int n, hipStream_t s) {
+  AcBatch b;
+  // band kernels: x band, then z band, then the main kernel (as for one plan)
+  for (int phase = 0; phase < 3; ++phase) {
+    b.nplans = 0;
+    b.base[0] = 0;
+    for (int q = 0; q < n; ++q) {
+      const AcStep& a = steps[q];
+      int gx, gy, gz;
+      if (phase == 0) {
+        gx = a.n_xchunks;
+        gy = (a.NZ + 4 * kXRows - 1) / (4 * kXRows);
+        gz = a.nshots;
+      } else if (phase == 1) {
+        gx = (a.NX + kTX - 1) / kTX;
+        gy = a.n_zchunks;
+        gz = a.nshots;
+      } else {
+        gx = a.ntiles;
+        gy = a.nshots;
+        gz = 1;
+      }
+      if (gx <= 0 || gy <= 0 || gz <= 0) continue;
+      const int k = b.nplans++;
+      b.step[k] = a;
+      b.gx[k] = gx;
+      b.gy[k] = gy;
+      b.base[k + 1] = b.base[k] + gx * gy * gz;
+    }
+    if (b.nplans == 0) continue;
+    const dim3 g(b.base[b.nplans]);
+    if (phase == 0) {
+      if (kAdj)
+        hipLaunchKernelGGL(ac_adj_xband_batch, g, dim3(kThreads), 0, s, b);
+      else
+        hipLaunchKernelGGL(ac_fwd_xband_batch, g, dim3(kThreads), 0, s, b);
+    } else if (phase == 1) {
+      if (kAdj)
+        hipLaunchKernelGGL(ac_adj_zband_batch, g, dim3(kThreads), 0, s, b);
+      else
+        hipLaunchKernelGGL(ac_fwd_zband_batch, g, dim3(kThreads), 0, s, b);
+    } else {
+      if (kAdj)
+        hipLaunchKernelGGL(ac_adj_main_batch<RZ>, g, dim3(kThreads), 0, s, b);
+      else
+        hipLaunchKernelGGL(ac_fwd_main_batch<RZ>, g, dim3(kThreads), 0, s, b);
+    }
+  }
+  SWEEP_HIP(hipGetLastError());
+  return SWEEP_OK;
+}
+
 }  // namespace
 
 int ac_launch_prep(const float* v, float* vpad, float* Cs, float* ax, float* bx, float* az,
@@ -785,6 +909,32 @@ int ac_launch_finish(const double* tot, const float* vpad, float* grad, int nx, 
                      grad, nx, nz, P, NX, scale);
   SWEEP_HIP(hipGetLastError());
   return SWEEP_OK;
+}
+
+}  // namespace sweep
+
+namespace sweep {
+
+int ac_launch_fwd_batch(const AcStep* steps, int n, int rz, hipStream_t s) {
+  switch (rz) {
+    case 1: return launch_step_batch<1, false>(steps, n, s);
+    case 2: return launch_step_batch<2, false>(steps, n, s);
+    case 4: return launch_step_batch<4, false>(steps, n, s);
+    case 8: return launch_step_batch<8, false>(steps, n, s);
+  }
+  set_error("unsupported rz");
+  return SWEEP_EINVAL;
+}
+
+int ac_launch_adj_batch(const AcStep* steps, int n, int rz, hipStream_t s) {
+  switch (rz) {
+    case 1: return launch_step_batch<1, true>(steps, n, s);
+    case 2: return launch_step_batch<2, true>(steps, n, s);
+    case 4: return launch_step_batch<4, true>(steps, n, s);
+    case 8: return launch_step_batch<8, true>(steps, n, s);
+  }
+  set_error("unsupported rz");
+  return SWEEP_EINVAL;
 }
 
 }  // namespace sweep

@@ -2,6 +2,9 @@
 // host-side scheduler that enqueues the time loop, the checkpointed
 // recomputation and the reverse sweep on the caller's stream.
 #include <algorithm>
+#include <cstdio>
+#include <fstream>
+#include <sstream>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -250,6 +253,212 @@ int ac_upload_geometry(sweep_plan* p, void* work, const AcLayout& L, hipStream_t
   return SWEEP_OK;
 }
 
+// ---------------------------------------------------------------- forward
+// Everything before the time loop: geometry, model preparation, zero state.
+int ac_fwd_prologue(sweep_plan* p, const float* model, const float* wavelet, void* work,
+                    const AcLayout& L, hipStream_t s) {
+  const sweep_problem& pb = p->pb;
+  int rc;
+  if ((rc = ac_launch_prep(model, at<float>(work, L.vpad), at<float>(work, L.Cs),
+                           at<float>(work, L.ax), at<float>(work, L.bx), at<float>(work, L.az),
+                           at<float>(work, L.bz), pb.nx, pb.nz, p->P, pb.h, pb.dt, pb.pml_vmax,
+                           pb.pml_f0, pb.pml_R, s)))
+    return rc;
+  const size_t ns = pb.nshots;
+  if ((rc = launch_copy(at<float>(work, L.wav), wavelet, ns * pb.nt, s))) return rc;
+  if ((rc = launch_fill(at<float>(work, L.pA), ns * L.plane, 0.0f, s))) return rc;
+  if ((rc = launch_fill(at<float>(work, L.pB), ns * L.plane, 0.0f, s))) return rc;
+  if ((rc = launch_fill(at<float>(work, L.aux[0]), L.aux_elems, 0.0f, s))) return rc;
+  if ((rc = launch_fill(at<float>(work, L.aux[1]), L.aux_elems, 0.0f, s))) return rc;
+  return SWEEP_OK;
+}
+
+// Arguments of forward step n (and the checkpoint copy of the state entering
+// it, enqueued on s, when save and n is a multiple of k).
+int ac_fwd_step_args(sweep_plan* p, void* work, const AcLayout& L, int n, float* gathers,
+                     int save, hipStream_t s, AcStep& a) {
+  const size_t ns = p->pb.nshots;
+  a = ac_base(p, work, L);
+  a.wavelet = at<float>(work, L.wav);
+  a.gathers = gathers;
+  a.n = n;
+  float* pA = at<float>(work, L.pA);
+  float* pB = at<float>(work, L.pB);
+  float* aux[2] = {at<float>(work, L.aux[0]), at<float>(work, L.aux[1])};
+  float* cur = (n % 2 == 0) ? pB : pA;
+  float* prev = (n % 2 == 0) ? pA : pB;
+  a.cur = cur;
+  a.prev = prev;
+  a.next = prev;
+  a.prev_adj = prev;
+  set_aux(a, aux_ptrs(aux[n % 2], L, ns), aux_ptrs(aux[(n + 1) % 2], L, ns));
+  const int k = p->ckpt;
+  if (save && n % k == 0) {
+    float* slot = at<float>(work, L.ck) + (size_t)(n / k) * L.slot_elems;
+    int rc;
+    if ((rc = launch_copy(slot, cur, ns * L.plane, s))) return rc;
+    if ((rc = launch_copy(slot + ns * L.plane, prev, ns * L.plane, s))) return rc;
+    if ((rc = launch_copy(slot + 2 * ns * L.plane, aux[n % 2], L.aux_elems, s))) return rc;
+  }
+  return SWEEP_OK;
+}
+
+void ac_mark_saved(sweep_plan* p, void* work, const float* model, int save) {
+  p->saved = save != 0;
+  p->saved_work = work;
+  p->saved_model = model;
+  p->saved_rz = p->tune.rz;
+}
+
+int ac_forward_enqueue(sweep_plan* p, const float* model, const float* wavelet, float* gathers,
+                       void* work, const AcLayout& L, int save, hipStream_t s) {
+  int rc;
+  if ((rc = ac_fwd_prologue(p, model, wavelet, work, L, s))) return rc;
+  for (int n = 0; n < p->pb.nt; ++n) {
+    AcStep a;
+    if ((rc = ac_fwd_step_args(p, work, L, n, gathers, save, s, a))) return rc;
+    if ((rc = ac_launch_fwd(a, p->tune.rz, s, p->timer.take(kFwdMain, kFwdBand)))) return rc;
+  }
+  return SWEEP_OK;
+}
+
+// ---------------------------------------------------------------- backward
+int ac_bwd_prologue(sweep_plan* p, const float* resid, void* work, const AcLayout& L,
+                    hipStream_t s) {
+  const size_t ns = p->pb.nshots;
+  int rc;
+  if ((rc = ac_launch_adj_init(at<float>(work, L.lB), at<float>(work, L.lA), ns * L.plane,
+                               at<float>(work, L.adjaux[0]), L.aux_elems,
+                               at<int>(work, L.rec_cell), resid, (int)ns, p->pb.nt, p->pb.nrec,
+                               s)))
+    return rc;
+  if ((rc = launch_fill(at<float>(work, L.adjaux[1]), L.aux_elems, 0.0f, s))) return rc;
+  return launch_fill_f64(at<double>(work, L.tot), L.plane, 0.0, s);
+}
+
+// restore the state entering segment sg (the first step of the recomputation)
+int ac_bwd_restore(sweep_plan* p, void* work, const AcLayout& L, int sg, hipStream_t s) {
+  const size_t ns = p->pb.nshots;
+  float* slot = at<float>(work, L.ck) + (size_t)sg * L.slot_elems;
+  int rc;
+  if ((rc = launch_copy(at<float>(work, L.pB), slot, ns * L.plane, s))) return rc;
+  if ((rc = launch_copy(at<float>(work, L.pA), slot + ns * L.plane, ns * L.plane, s))) return rc;
+  return launch_copy(at<float>(work, L.aux[0]), slot + 2 * ns * L.plane, L.aux_elems, s);
+}
+
+// recomputation of step n = n0 + m of a segment, storing B^n
+AcStep ac_rec_step_args(sweep_plan* p, void* work, const AcLayout& L, int n, int m) {
+  const size_t ns = p->pb.nshots;
+  AcStep a = ac_base(p, work, L);
+  a.n = n;
+  a.wavelet = at<float>(work, L.wav);
+  float* pA = at<float>(work, L.pA);
+  float* pB = at<float>(work, L.pB);
+  float* aux[2] = {at<float>(work, L.aux[0]), at<float>(work, L.aux[1])};
+  float* prev = (m % 2 == 0) ? pA : pB;
+  a.cur = (m % 2 == 0) ? pB : pA;
+  a.prev = prev;
+  a.next = prev;
+  a.prev_adj = prev;
+  set_aux(a, aux_ptrs(aux[m % 2], L, ns), aux_ptrs(aux[(m + 1) % 2], L, ns));
+  a.B_out = at<float>(work, L.Bseg) + (size_t)m * ns * L.plane;
+  return a;
+}
+
+// reverse of step n inside the segment starting at n0 and ending before n1
+AcStep ac_adj_step_args(sweep_plan* p, void* work, const AcLayout& L, const float* resid, int n,
+                        int n0, int n1) {
+  const size_t ns = p->pb.nshots;
+  const int it = p->pb.nt - 1 - n;
+  AcStep a = ac_base(p, work, L);
+  a.n = n;
+  a.resid = resid;
+  float* lA = at<float>(work, L.lA);
+  float* lB = at<float>(work, L.lB);
+  float* adjaux[2] = {at<float>(work, L.adjaux[0]), at<float>(work, L.adjaux[1])};
+  float* prev = (it % 2 == 0) ? lA : lB;
+  a.cur = (it % 2 == 0) ? lB : lA;
+  a.prev = prev;
+  a.next = prev;
+  a.prev_adj = prev;
+  set_aux(a, aux_ptrs(adjaux[it % 2], L, ns), aux_ptrs(adjaux[(it + 1) % 2], L, ns));
+  a.B_in = at<float>(work, L.Bseg) + (size_t)(n - n0) * ns * L.plane;
+  a.g = at<float>(work, L.gpart);
+  a.g_init = (n == n1 - 1);
+  return a;
+}
+
+int ac_bwd_fold(sweep_plan* p, void* work, const AcLayout& L, hipStream_t s) {
+  return ac_launch_fold(at<double>(work, L.tot), at<float>(work, L.gpart), p->pb.nshots, L.plane,
+                        s);
+}
+
+int ac_bwd_finish(sweep_plan* p, void* work, const AcLayout& L, float* grad, hipStream_t s) {
+  const sweep_problem& pb = p->pb;
+  const double scale = 2.0 * pb.dt * pb.dt / (pb.h * pb.h);
+  return ac_launch_finish(at<double>(work, L.tot), at<float>(work, L.vpad), grad, pb.nx, pb.nz,
+                          p->P, p->NX, scale, s);
+}
+
+int ac_backward_enqueue(sweep_plan* p, const float* resid, float* grad, void* work,
+                        const AcLayout& L, hipStream_t s) {
+  const int nt = p->pb.nt, k = p->ckpt;
+  int rc;
+  if ((rc = ac_bwd_prologue(p, resid, work, L, s))) return rc;
+  for (int sg = L.nseg - 1; sg >= 0; --sg) {
+    const int n0 = sg * k, n1 = std::min(nt, n0 + k);
+    if ((rc = ac_bwd_restore(p, work, L, sg, s))) return rc;
+    for (int n = n0; n < n1; ++n) {
+      const AcStep a = ac_rec_step_args(p, work, L, n, n - n0);
+      if ((rc = ac_launch_fwd(a, p->tune.rz, s, p->timer.take(kRecMain, kRecBand)))) return rc;
+    }
+    for (int n = n1 - 1; n >= n0; --n) {
+      const AcStep a = ac_adj_step_args(p, work, L, resid, n, n0, n1);
+      if ((rc = ac_launch_adj(a, p->tune.rz, s, p->timer.take(kAdjMain, kAdjBand)))) return rc;
+    }
+    if ((rc = ac_bwd_fold(p, work, L, s))) return rc;
+  }
+  return ac_bwd_finish(p, work, L, grad, s);
+}
+
+// ---------------------------------------------------------------- graphs
+// Enqueues `body` on the caller's stream, or (use_graph) captures it once on a
+// private stream into a hipGraph keyed by `key` and launches that graph.
+template <class F>
+int run_maybe_graph(GraphCache& gc, bool use_graph, const std::vector<const void*>& key,
+                    hipStream_t s, F body) {
+  if (!use_graph) return body(s);
+  if (!gc.exec || gc.key != key) {
+    if (gc.exec) {
+      (void)hipGraphExecDestroy(gc.exec);
+      gc.exec = nullptr;
+    }
+    if (!gc.stream) SWEEP_HIP(hipStreamCreateWithFlags(&gc.stream, hipStreamNonBlocking));
+    SWEEP_HIP(hipStreamBeginCapture(gc.stream, hipStreamCaptureModeRelaxed));
+    const int rc = body(gc.stream);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(gc.stream, &graph);
+    if (rc) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return rc;
+    }
+    if (e != hipSuccess) {
+      set_error(std::string("hipStreamEndCapture failed: ") + hipGetErrorString(e));
+      return SWEEP_EHIP;
+    }
+    const hipError_t e2 = hipGraphInstantiate(&gc.exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e2 != hipSuccess) {
+      gc.exec = nullptr;
+      set_error(std::string("hipGraphInstantiate failed: ") + hipGetErrorString(e2));
+      return SWEEP_EHIP;
+    }
+    gc.key = key;
+  }
+  SWEEP_HIP(hipGraphLaunch(gc.exec, s));
+  return SWEEP_OK;
+}
+
 int ac_forward(sweep_plan* p, const float* model, const float* wavelet, float* gathers,
                void* work, size_t bytes, int save, hipStream_t s) {
   AcLayout L;
@@ -257,51 +466,13 @@ int ac_forward(sweep_plan* p, const float* model, const float* wavelet, float* g
   int rc = check_work(p, save ? L.bwd_end : L.fwd_end, work, bytes);
   if (rc) return rc;
   if ((rc = ac_upload_geometry(p, work, L, s))) return rc;
-  const sweep_problem& pb = p->pb;
-  if ((rc = ac_launch_prep(model, at<float>(work, L.vpad), at<float>(work, L.Cs),
-                           at<float>(work, L.ax), at<float>(work, L.bx), at<float>(work, L.az),
-                           at<float>(work, L.bz), pb.nx, pb.nz, p->P, pb.h, pb.dt, pb.pml_vmax,
-                           pb.pml_f0, pb.pml_R, s)))
-    return rc;
-  const size_t ns = pb.nshots;
-  float* wav = at<float>(work, L.wav);
-  if ((rc = launch_copy(wav, wavelet, ns * pb.nt, s))) return rc;
-  float* pA = at<float>(work, L.pA);
-  float* pB = at<float>(work, L.pB);
-  float* aux[2] = {at<float>(work, L.aux[0]), at<float>(work, L.aux[1])};
-  if ((rc = launch_fill(pA, ns * L.plane, 0.0f, s))) return rc;
-  if ((rc = launch_fill(pB, ns * L.plane, 0.0f, s))) return rc;
-  if ((rc = launch_fill(aux[0], L.aux_elems, 0.0f, s))) return rc;
-  if ((rc = launch_fill(aux[1], L.aux_elems, 0.0f, s))) return rc;
-
-  AcStep base = ac_base(p, work, L);
-  base.wavelet = wav;
-  base.gathers = gathers;
-  const int k = p->ckpt;
-  float* ck = at<float>(work, L.ck);
-  for (int n = 0; n < pb.nt; ++n) {
-    AcStep a = base;
-    a.n = n;
-    float* cur = (n % 2 == 0) ? pB : pA;
-    float* prev = (n % 2 == 0) ? pA : pB;
-    a.cur = cur;
-    a.prev = prev;
-    a.next = prev;
-    a.prev_adj = prev;
-    set_aux(a, aux_ptrs(aux[n % 2], L, ns), aux_ptrs(aux[(n + 1) % 2], L, ns));
-    if (save && n % k == 0) {
-      // checkpoint: the state entering step n
-      float* slot = ck + (size_t)(n / k) * L.slot_elems;
-      if ((rc = launch_copy(slot, cur, ns * L.plane, s))) return rc;
-      if ((rc = launch_copy(slot + ns * L.plane, prev, ns * L.plane, s))) return rc;
-      if ((rc = launch_copy(slot + 2 * ns * L.plane, aux[n % 2], L.aux_elems, s))) return rc;
-    }
-    if ((rc = ac_launch_fwd(a, p->tune.rz, s, p->timer.take(kFwdMain, kFwdBand)))) return rc;
-  }
-  p->saved = save != 0;
-  p->saved_work = work;
-  p->saved_model = model;
-  p->saved_rz = p->tune.rz;
+  const bool graph = p->tune.use_graph && !p->timer.on;
+  const std::vector<const void*> key = {model, wavelet, gathers, work, (const void*)(size_t)save};
+  rc = run_maybe_graph(p->gfwd, graph, key, s, [&](hipStream_t st) {
+    return ac_forward_enqueue(p, model, wavelet, gathers, work, L, save, st);
+  });
+  if (rc) return rc;
+  ac_mark_saved(p, work, model, save);
   return SWEEP_OK;
 }
 
@@ -316,71 +487,102 @@ int ac_backward(sweep_plan* p, const float* resid, float* grad, void* work, size
   ac_layout(p, L);
   int rc = check_work(p, L.bwd_end, work, bytes);
   if (rc) return rc;
-  const sweep_problem& pb = p->pb;
-  const size_t ns = pb.nshots;
-  const int nt = pb.nt, k = p->ckpt;
-  float* pA = at<float>(work, L.pA);
-  float* pB = at<float>(work, L.pB);
-  float* aux[2] = {at<float>(work, L.aux[0]), at<float>(work, L.aux[1])};
-  float* lA = at<float>(work, L.lA);
-  float* lB = at<float>(work, L.lB);
-  float* adjaux[2] = {at<float>(work, L.adjaux[0]), at<float>(work, L.adjaux[1])};
-  float* Bseg = at<float>(work, L.Bseg);
-  float* gpart = at<float>(work, L.gpart);
-  double* tot = at<double>(work, L.tot);
-  float* ck = at<float>(work, L.ck);
+  const bool graph = p->tune.use_graph && !p->timer.on;
+  const std::vector<const void*> key = {resid, grad, work};
+  return run_maybe_graph(p->gbwd, graph, key, s, [&](hipStream_t st) {
+    return ac_backward_enqueue(p, resid, grad, work, L, st);
+  });
+}
 
-  // adjoint state: lambda^{nt} = r_{nt-1} at the receivers (iteration 0 reads lB)
-  if ((rc = ac_launch_adj_init(lB, lA, ns * L.plane, adjaux[0], L.aux_elems,
-                               at<int>(work, L.rec_cell), resid, (int)ns, nt, pb.nrec, s)))
-    return rc;
-  if ((rc = launch_fill(adjaux[1], L.aux_elems, 0.0f, s))) return rc;
-  if ((rc = launch_fill_f64(tot, L.plane, 0.0, s))) return rc;
-
-  AcStep base = ac_base(p, work, L);
-  for (int sg = L.nseg - 1; sg >= 0; --sg) {
-    const int n0 = sg * k, n1 = std::min(nt, n0 + k);
-    // restore the state entering step n0 and recompute the segment, keeping B^n
-    float* slot = ck + (size_t)sg * L.slot_elems;
-    if ((rc = launch_copy(pB, slot, ns * L.plane, s))) return rc;
-    if ((rc = launch_copy(pA, slot + ns * L.plane, ns * L.plane, s))) return rc;
-    if ((rc = launch_copy(aux[0], slot + 2 * ns * L.plane, L.aux_elems, s))) return rc;
-    for (int n = n0; n < n1; ++n) {
-      const int m = n - n0;
-      AcStep a = base;
-      a.n = n;
-      a.wavelet = at<float>(work, L.wav);
-      float* prev = (m % 2 == 0) ? pA : pB;
-      a.cur = (m % 2 == 0) ? pB : pA;
-      a.prev = prev;
-      a.next = prev;
-      a.prev_adj = prev;
-      set_aux(a, aux_ptrs(aux[m % 2], L, ns), aux_ptrs(aux[(m + 1) % 2], L, ns));
-      a.B_out = Bseg + (size_t)m * ns * L.plane;
-      if ((rc = ac_launch_fwd(a, p->tune.rz, s, p->timer.take(kRecMain, kRecBand)))) return rc;
-    }
-    // reverse sweep over the segment
-    for (int n = n1 - 1; n >= n0; --n) {
-      const int it = nt - 1 - n;
-      AcStep a = base;
-      a.n = n;
-      a.resid = resid;
-      float* prev = (it % 2 == 0) ? lA : lB;
-      a.cur = (it % 2 == 0) ? lB : lA;
-      a.prev = prev;
-      a.next = prev;
-      a.prev_adj = prev;
-      set_aux(a, aux_ptrs(adjaux[it % 2], L, ns), aux_ptrs(adjaux[(it + 1) % 2], L, ns));
-      a.B_in = Bseg + (size_t)(n - n0) * ns * L.plane;
-      a.g = gpart;
-      a.g_init = (n == n1 - 1);
-      if ((rc = ac_launch_adj(a, p->tune.rz, s, p->timer.take(kAdjMain, kAdjBand)))) return rc;
-    }
-    if ((rc = ac_launch_fold(tot, gpart, (int)ns, L.plane, s))) return rc;
+// ---------------------------------------------------------------- batches
+// Several acoustic plans of different grids, shot counts and step counts
+// advanced together: every time step is one launch per kernel kind covering
+// the tiles of all plans still running (plans stop at their own nt).
+int batch_layouts(const sweep_batch* b, int for_backward, std::vector<AcLayout>& L,
+                  std::vector<size_t>& off, size_t& total) {
+  L.resize(b->plans.size());
+  off.resize(b->plans.size());
+  total = 0;
+  for (size_t q = 0; q < b->plans.size(); ++q) {
+    ac_layout(b->plans[q], L[q]);
+    off[q] = total;
+    total = align_up(total + (for_backward ? L[q].bwd_end : L[q].fwd_end));
   }
-  const double scale = 2.0 * (double)pb.dt * pb.dt / ((double)pb.h * pb.h);
-  return ac_launch_finish(tot, at<float>(work, L.vpad), grad, pb.nx, pb.nz, p->P, p->NX, scale,
-                          s);
+  return SWEEP_OK;
+}
+
+int batch_forward_enqueue(sweep_batch* b, const float* const* models, const float* const* wavs,
+                          float* const* gathers, void* work, const std::vector<AcLayout>& L,
+                          const std::vector<size_t>& off, int save, hipStream_t s) {
+  const int np = (int)b->plans.size();
+  int rc, maxnt = 0;
+  for (int q = 0; q < np; ++q) {
+    if ((rc = ac_fwd_prologue(b->plans[q], models[q], wavs[q], at<char>(work, off[q]), L[q], s)))
+      return rc;
+    maxnt = std::max(maxnt, b->plans[q]->pb.nt);
+  }
+  std::vector<AcStep> steps(np);
+  for (int n = 0; n < maxnt; ++n) {
+    int cnt = 0;
+    for (int q = 0; q < np; ++q) {
+      sweep_plan* p = b->plans[q];
+      if (n >= p->pb.nt) continue;
+      if ((rc = ac_fwd_step_args(p, at<char>(work, off[q]), L[q], n, gathers[q], save, s,
+                                 steps[cnt])))
+        return rc;
+      ++cnt;
+    }
+    if ((rc = ac_launch_fwd_batch(steps.data(), cnt, b->rz, s))) return rc;
+  }
+  return SWEEP_OK;
+}
+
+int batch_backward_enqueue(sweep_batch* b, const float* const* resids, float* const* grads,
+                           void* work, const std::vector<AcLayout>& L,
+                           const std::vector<size_t>& off, hipStream_t s) {
+  const int np = (int)b->plans.size();
+  int rc, maxseg = 0;
+  for (int q = 0; q < np; ++q) {
+    if ((rc = ac_bwd_prologue(b->plans[q], resids[q], at<char>(work, off[q]), L[q], s)))
+      return rc;
+    maxseg = std::max(maxseg, L[q].nseg);
+  }
+  std::vector<AcStep> steps(np);
+  std::vector<int> n0(np), n1(np);
+  for (int r = 0; r < maxseg; ++r) {
+    int lenmax = 0;
+    for (int q = 0; q < np; ++q) {
+      sweep_plan* p = b->plans[q];
+      n0[q] = n1[q] = 0;
+      if (r >= L[q].nseg) continue;
+      const int sg = L[q].nseg - 1 - r;
+      n0[q] = sg * p->ckpt;
+      n1[q] = std::min(p->pb.nt, n0[q] + p->ckpt);
+      lenmax = std::max(lenmax, n1[q] - n0[q]);
+      if ((rc = ac_bwd_restore(p, at<char>(work, off[q]), L[q], sg, s))) return rc;
+    }
+    for (int m = 0; m < lenmax; ++m) {
+      int cnt = 0;
+      for (int q = 0; q < np; ++q)
+        if (m < n1[q] - n0[q])
+          steps[cnt++] = ac_rec_step_args(b->plans[q], at<char>(work, off[q]), L[q], n0[q] + m, m);
+      if ((rc = ac_launch_fwd_batch(steps.data(), cnt, b->rz, s))) return rc;
+    }
+    for (int m = 0; m < lenmax; ++m) {
+      int cnt = 0;
+      for (int q = 0; q < np; ++q)
+        if (m < n1[q] - n0[q])
+          steps[cnt++] = ac_adj_step_args(b->plans[q], at<char>(work, off[q]), L[q], resids[q],
+                                          n1[q] - 1 - m, n0[q], n1[q]);
+      if ((rc = ac_launch_adj_batch(steps.data(), cnt, b->rz, s))) return rc;
+    }
+    for (int q = 0; q < np; ++q)
+      if (n1[q] > n0[q] && (rc = ac_bwd_fold(b->plans[q], at<char>(work, off[q]), L[q], s)))
+        return rc;
+  }
+  for (int q = 0; q < np; ++q)
+    if ((rc = ac_bwd_finish(b->plans[q], at<char>(work, off[q]), L[q], grads[q], s))) return rc;
+  return SWEEP_OK;
 }
 
 }  // namespace
@@ -487,6 +689,8 @@ extern "C" int sweep_plan_set_tuning(sweep_plan* p, const sweep_tuning* t) {
   p->tune = *t;
   if (p->pb.physics == SWEEP_ACOUSTIC) ac_build_tiling(p);
   p->saved = false;
+  p->gfwd.reset();
+  p->gbwd.reset();
   return SWEEP_OK;
 }
 
@@ -574,5 +778,241 @@ extern "C" int sweep_plan_kernel_time(sweep_plan* p, int kernel_class, int* laun
   }
   *launches = (int)(n / 2);
   *total_ms = tot;
+  return SWEEP_OK;
+}
+
+// ----------------------------------------------------------------- batch C-ABI
+extern "C" int sweep_batch_create(sweep_plan* const* plans, int nplans, sweep_batch** out) {
+  if (!plans || !out || nplans < 1 || nplans > kMaxBatch) {
+    set_error("sweep_batch_create: need 1.." + std::to_string(kMaxBatch) + " plans");
+    return SWEEP_EINVAL;
+  }
+  *out = nullptr;
+  for (int q = 0; q < nplans; ++q) {
+    if (!plans[q] || plans[q]->pb.physics != SWEEP_ACOUSTIC) {
+      set_error("sweep_batch_create: batches hold acoustic plans");
+      return SWEEP_EINVAL;
+    }
+    if (plans[q]->tune.rz != plans[0]->tune.rz) {
+      set_error("sweep_batch_create: all plans of a batch must use the same rz tuning");
+      return SWEEP_EINVAL;
+    }
+  }
+  sweep_batch* b = new (std::nothrow) sweep_batch();
+  if (!b) {
+    set_error("out of host memory");
+    return SWEEP_EINVAL;
+  }
+  b->plans.assign(plans, plans + nplans);
+  b->rz = plans[0]->tune.rz;
+  *out = b;
+  return SWEEP_OK;
+}
+
+extern "C" void sweep_batch_destroy(sweep_batch* b) { delete b; }
+
+extern "C" int sweep_batch_set_graph(sweep_batch* b, int use_graph) {
+  if (!b) {
+    set_error("null batch");
+    return SWEEP_EINVAL;
+  }
+  b->use_graph = use_graph != 0;
+  b->gfwd.reset();
+  b->gbwd.reset();
+  return SWEEP_OK;
+}
+
+extern "C" size_t sweep_batch_workspace_bytes(const sweep_batch* b, int for_backward) {
+  if (!b) return 0;
+  std::vector<AcLayout> L;
+  std::vector<size_t> off;
+  size_t total = 0;
+  batch_layouts(b, for_backward, L, off, total);
+  return total;
+}
+
+extern "C" int sweep_batch_forward(sweep_batch* b, const float* const* d_models,
+                                   const float* const* d_wavelets, float* const* d_gathers,
+                                   void* d_work, size_t work_bytes, int save_for_backward,
+                                   void* stream) {
+  if (!b || !d_models || !d_wavelets || !d_gathers || !d_work) {
+    set_error("sweep_batch_forward: null argument");
+    return SWEEP_EINVAL;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<AcLayout> L;
+  std::vector<size_t> off;
+  size_t total = 0;
+  batch_layouts(b, save_for_backward, L, off, total);
+  if (work_bytes < total) {
+    set_error("workspace too small: need " + std::to_string(total) + " bytes");
+    return SWEEP_ENOMEM;
+  }
+  const int np = (int)b->plans.size();
+  int rc;
+  std::vector<const void*> key = {d_work, (const void*)(size_t)save_for_backward};
+  for (int q = 0; q < np; ++q) {
+    if (!d_models[q] || !d_wavelets[q] || (!d_gathers[q] && b->plans[q]->pb.nrec > 0)) {
+      set_error("sweep_batch_forward: null pointer for plan " + std::to_string(q));
+      return SWEEP_EINVAL;
+    }
+    b->plans[q]->saved = false;
+    if ((rc = ac_upload_geometry(b->plans[q], at<char>(d_work, off[q]), L[q], s))) return rc;
+    key.push_back(d_models[q]);
+    key.push_back(d_wavelets[q]);
+    key.push_back(d_gathers[q]);
+  }
+  rc = run_maybe_graph(b->gfwd, b->use_graph, key, s, [&](hipStream_t st) {
+    return batch_forward_enqueue(b, d_models, d_wavelets, d_gathers, d_work, L, off,
+                                 save_for_backward, st);
+  });
+  if (rc) return rc;
+  b->saved = save_for_backward != 0;
+  b->saved_work = d_work;
+  return SWEEP_OK;
+}
+
+extern "C" int sweep_batch_backward(sweep_batch* b, const float* const* d_resids,
+                                    float* const* d_grads, void* d_work, size_t work_bytes,
+                                    void* stream) {
+  if (!b || !d_resids || !d_grads || !d_work) {
+    set_error("sweep_batch_backward: null argument");
+    return SWEEP_EINVAL;
+  }
+  if (!b->saved || b->saved_work != d_work) {
+    set_error("sweep_batch_backward needs a preceding sweep_batch_forward(save_for_backward=1) "
+              "on the same workspace");
+    return SWEEP_ESTATE;
+  }
+  std::vector<AcLayout> L;
+  std::vector<size_t> off;
+  size_t total = 0;
+  batch_layouts(b, 1, L, off, total);
+  if (work_bytes < total) {
+    set_error("workspace too small");
+    return SWEEP_ENOMEM;
+  }
+  std::vector<const void*> key = {d_work};
+  for (size_t q = 0; q < b->plans.size(); ++q) {
+    if (!d_resids[q] || !d_grads[q]) {
+      set_error("sweep_batch_backward: null pointer for plan " + std::to_string(q));
+      return SWEEP_EINVAL;
+    }
+    key.push_back(d_resids[q]);
+    key.push_back(d_grads[q]);
+  }
+  return run_maybe_graph(b->gbwd, b->use_graph, key, (hipStream_t)stream, [&](hipStream_t st) {
+    return batch_backward_enqueue(b, d_resids, d_grads, d_work, L, off, st);
+  });
+}
+
+// ----------------------------------------------------------------- autotuner
+// Times `steps` forward steps of the plan for every supported rz (main-kernel
+// rows per thread) and keeps the fastest; results are cached in a text file,
+// one line "arch physics NX NZ nshots rz microseconds_per_step".
+namespace {
+
+std::string tune_key(const sweep_plan* p) {
+  int dev = 0;
+  hipDeviceProp_t prop;
+  std::string arch = "unknown";
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+    arch = std::string(prop.gcnArchName).substr(0, std::string(prop.gcnArchName).find(':'));
+  std::ostringstream os;
+  os << arch << " " << (p->pb.physics == SWEEP_ACOUSTIC ? "acoustic" : "elastic") << " " << p->NX
+     << " " << p->NZ << " " << p->pb.nshots;
+  return os.str();
+}
+
+}  // namespace
+
+extern "C" int sweep_plan_autotune(sweep_plan* p, const float* d_model, const float* d_wavelet,
+                                   void* d_work, size_t work_bytes, int steps,
+                                   const char* cache_path, void* stream, int* chosen_rz) {
+  if (!p || !d_model || !d_wavelet || !d_work || steps < 1) {
+    set_error("sweep_plan_autotune: bad argument");
+    return SWEEP_EINVAL;
+  }
+  if (p->pb.physics != SWEEP_ACOUSTIC) {  // the elastic kernels have no tile choice
+    if (chosen_rz) *chosen_rz = p->tune.rz;
+    return SWEEP_OK;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  const std::string key = tune_key(p);
+  if (cache_path && *cache_path) {
+    std::ifstream in(cache_path);
+    std::string line;
+    while (std::getline(in, line)) {
+      if (line.compare(0, key.size(), key) != 0 || line.size() <= key.size() ||
+          line[key.size()] != ' ')
+        continue;
+      std::istringstream is(line.substr(key.size()));
+      int rz = 0;
+      double us = 0;
+      if (is >> rz >> us && (rz == 1 || rz == 2 || rz == 4 || rz == 8)) {
+        sweep_tuning t = p->tune;
+        t.rz = rz;
+        const int rc = sweep_plan_set_tuning(p, &t);
+        if (rc) return rc;
+        if (chosen_rz) *chosen_rz = rz;
+        return SWEEP_OK;
+      }
+    }
+  }
+  AcLayout L;
+  ac_layout(p, L);
+  int rc = check_work(p, L.fwd_end, d_work, work_bytes);
+  if (rc) return rc;
+  const sweep_tuning keep = p->tune;
+  const bool timing = p->timer.on;
+  p->timer.on = false;
+  hipEvent_t e0, e1;
+  SWEEP_HIP(hipEventCreate(&e0));
+  SWEEP_HIP(hipEventCreate(&e1));
+  const int cand[4] = {1, 2, 4, 8};
+  int best = keep.rz;
+  double best_us = 1e300;
+  std::ostringstream log;
+  for (int c : cand) {
+    p->tune.rz = c;
+    ac_build_tiling(p);
+    if ((rc = ac_upload_geometry(p, d_work, L, s))) break;
+    for (int rep = 0; rep < 2 && !rc; ++rep) {  // first pass warms up
+      rc = ac_fwd_prologue(p, d_model, d_wavelet, d_work, L, s);
+      if (rc) break;
+      SWEEP_HIP(hipEventRecord(e0, s));
+      for (int n = 0; n < std::min(steps, p->pb.nt) && !rc; ++n) {
+        AcStep a;
+        rc = ac_fwd_step_args(p, d_work, L, n, nullptr, 0, s, a);
+        if (!rc) rc = ac_launch_fwd(a, c, s, nullptr);
+      }
+      SWEEP_HIP(hipEventRecord(e1, s));
+      SWEEP_HIP(hipEventSynchronize(e1));
+    }
+    if (rc) break;
+    float ms = 0.0f;
+    SWEEP_HIP(hipEventElapsedTime(&ms, e0, e1));
+    const double us = 1e3 * ms / std::min(steps, p->pb.nt);
+    if (us < best_us) {
+      best_us = us;
+      best = c;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  p->timer.on = timing;
+  p->tune = keep;
+  if (rc) {
+    ac_build_tiling(p);
+    return rc;
+  }
+  sweep_tuning t = keep;
+  t.rz = best;
+  if ((rc = sweep_plan_set_tuning(p, &t))) return rc;
+  if (cache_path && *cache_path) {
+    std::ofstream out(cache_path, std::ios::app);
+    out << key << " " << best << " " << best_us << "\n";
+  }
+  if (chosen_rz) *chosen_rz = best;
   return SWEEP_OK;
 }

@@ -82,12 +82,23 @@ struct AcStep {
   int n_zchunks;
 };
 
+// Several plans of different shapes advanced by one launch per kernel kind.
+constexpr int kMaxBatch = 8;
+struct AcBatch {
+  int nplans;
+  int base[kMaxBatch + 1];  // first flat block of each plan in this launch
+  int gx[kMaxBatch], gy[kMaxBatch];
+  AcStep step[kMaxBatch];
+};
+
 // Launchers (acoustic.hip). `rz` selects the main kernel variant (TZ = 4 rz).
 int ac_launch_prep(const float* v, float* vpad, float* Cs, float* ax, float* bx, float* az,
                    float* bz, int nx, int nz, int P, double h, double dt, double vmax,
                    double f0, double R, hipStream_t s);
 int ac_launch_fwd(const AcStep& a, int rz, hipStream_t s, hipEvent_t* ev);
 int ac_launch_adj(const AcStep& a, int rz, hipStream_t s, hipEvent_t* ev);
+int ac_launch_fwd_batch(const AcStep* steps, int n, int rz, hipStream_t s);
+int ac_launch_adj_batch(const AcStep* steps, int n, int rz, hipStream_t s);
 int ac_launch_adj_init(float* lam_cur, float* lam_prev, size_t plane_elems, float* aux,
                        size_t aux_elems, const int* rec_cell, const float* resid, int nshots,
                        int nt, int nrec, hipStream_t s);

@@ -56,6 +56,25 @@ struct ElLayout {
 };
 }  // namespace sweep
 
+namespace sweep {
+// An instantiated hipGraph of a forward or backward call, reused while the
+// pointers it was captured with are unchanged.
+struct GraphCache {
+  hipGraphExec_t exec = nullptr;
+  hipStream_t stream = nullptr;
+  std::vector<const void*> key;
+  ~GraphCache() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (stream) (void)hipStreamDestroy(stream);
+  }
+  void reset() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    exec = nullptr;
+    key.clear();
+  }
+};
+}  // namespace sweep
+
 struct sweep_plan {
   sweep_problem pb;
   sweep_tuning tune;
@@ -79,6 +98,7 @@ struct sweep_plan {
   const float* saved_model = nullptr;
   int saved_rz = 0;
   sweep::KernelTimer timer;
+  sweep::GraphCache gfwd, gbwd;
 };
 
 namespace sweep {
@@ -91,3 +111,12 @@ int el_forward(sweep_plan* p, const float* model, const float* wavelet, float* g
 int el_backward(sweep_plan* p, const float* resid, float* grad, void* work, size_t bytes,
                 hipStream_t s);
 }  // namespace sweep
+
+struct sweep_batch {
+  std::vector<sweep_plan*> plans;  // owned by the caller
+  int rz = 8;
+  bool use_graph = false;
+  bool saved = false;
+  const void* saved_work = nullptr;
+  sweep::GraphCache gfwd, gbwd;
+};

@@ -17,7 +17,7 @@ import torch
 from . import _lib
 from ._lib import ACOUSTIC, ELASTIC, Problem, Tuning, check, lib
 
-__all__ = ["Plan", "WaveFn", "l2_misfit", "ACOUSTIC", "ELASTIC"]
+__all__ = ["Plan", "Batch", "WaveFn", "l2_misfit", "ACOUSTIC", "ELASTIC"]
 
 
 def _stream() -> ctypes.c_void_p:
@@ -106,6 +106,22 @@ class Plan:
         check(lib().sweep_plan_set_tuning(self._h, ctypes.byref(t)))
         self._saved_id = -1
 
+    def autotune(self, model: torch.Tensor, wavelet: torch.Tensor, steps: int = 20,
+                 cache_path: Optional[str] = None) -> int:
+        """Pick the fastest main-kernel tiling for this plan (cached); returns rz."""
+        if self.nparam == 1 and model.dim() == 2:
+            model = model.unsqueeze(0)
+        _need(model, self._model_shape(), "model")
+        _need(wavelet, (self.nshots, self.nt), "wavelet")
+        work = self._workspace(False)
+        rz = ctypes.c_int()
+        check(lib().sweep_plan_autotune(self._h, _ptr(model), _ptr(wavelet), _ptr(work),
+                                        work.numel(), steps,
+                                        cache_path.encode() if cache_path else None,
+                                        _stream(), ctypes.byref(rz)))
+        self._saved_id = -1
+        return rz.value
+
     def padded(self):
         a, b = ctypes.c_int(), ctypes.c_int()
         check(lib().sweep_plan_padded(self._h, ctypes.byref(a), ctypes.byref(b)))
@@ -185,6 +201,79 @@ class Plan:
     @property
     def last_forward_id(self) -> int:
         return self._fwd_id
+
+
+def _ptr_array(ts):
+    arr = (ctypes.c_void_p * len(ts))()
+    for i, t in enumerate(ts):
+        arr[i] = t.data_ptr()
+    return arr
+
+
+class Batch:
+    """Several acoustic plans (different grids, shot counts, step counts)
+    advanced together: one launch per kernel kind and time step serves all of
+    them (batch modelling of different models, Sec. 2.2). Results equal those
+    of each plan run alone, bit for bit. With use_graph the whole forward /
+    backward is captured once as a hipGraph and replayed."""
+
+    def __init__(self, plans, use_graph: bool = False):
+        self.plans = list(plans)
+        arr = (ctypes.c_void_p * len(self.plans))(*[p._h.value for p in self.plans])
+        h = ctypes.c_void_p()
+        check(lib().sweep_batch_create(arr, len(self.plans), ctypes.byref(h)))
+        self._h = h
+        self._work = None
+        self._saved = False
+        self.set_graph(use_graph)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            try:
+                lib().sweep_batch_destroy(h)
+            except Exception:
+                pass
+            self._h = None
+
+    def set_graph(self, use_graph: bool):
+        check(lib().sweep_batch_set_graph(self._h, int(bool(use_graph))))
+
+    def workspace_bytes(self, for_backward: bool) -> int:
+        return int(lib().sweep_batch_workspace_bytes(self._h, int(bool(for_backward))))
+
+    def forward(self, models, wavelets, save: bool = False):
+        outs = []
+        ms, ws = [], []
+        for p, m, w in zip(self.plans, models, wavelets):
+            if p.nparam == 1 and m.dim() == 2:
+                m = m.unsqueeze(0)
+            _need(m, p._model_shape(), "model")
+            _need(w, (p.nshots, p.nt), "wavelet")
+            ms.append(m)
+            ws.append(w)
+            outs.append(torch.empty(p.gathers_shape(), dtype=torch.float32, device=m.device))
+        need = self.workspace_bytes(save)
+        if self._work is None or self._work.numel() < need:
+            self._work = None
+            torch.cuda.synchronize()
+            self._work = torch.empty(need, dtype=torch.uint8, device=ms[0].device)
+        check(lib().sweep_batch_forward(self._h, _ptr_array(ms), _ptr_array(ws),
+                                        _ptr_array(outs), _ptr(self._work), self._work.numel(),
+                                        int(bool(save)), _stream()))
+        self._saved = bool(save)
+        return outs
+
+    def backward(self, resids):
+        if not self._saved:
+            raise RuntimeError("Batch.backward needs a preceding forward(save=True)")
+        grads = []
+        for p, r in zip(self.plans, resids):
+            _need(r, p.gathers_shape(), "resid")
+            grads.append(torch.empty(p._model_shape(), dtype=torch.float32, device=r.device))
+        check(lib().sweep_batch_backward(self._h, _ptr_array(list(resids)), _ptr_array(grads),
+                                         _ptr(self._work), self._work.numel(), _stream()))
+        return grads
 
 
 class WaveFn(torch.autograd.Function):

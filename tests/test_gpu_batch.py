@@ -1,0 +1,109 @@
+"""GPU: batched uneven plans, hipGraph replay and the autotuner.
+
+Batch modelling changes the number of launches, never the results (Sec. 2.2):
+a batch of plans with different grids, shot counts and step counts must give
+bit-identical gathers and gradients to each plan run alone. Captured graphs are
+replayed several times with eager work in between and every replay is checked
+against the eager result.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from tests.helpers import f32, random_case, rel_l2
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _dev(a):
+    return torch.as_tensor(np.asarray(a, dtype=np.float32), device="cuda").contiguous()
+
+
+@pytest.fixture(scope="module")
+def sw():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2604_14189_amd as sw
+    sw.lib()
+    return sw
+
+
+def _cases():
+    # uneven: different grids (ragged tiles), shots, steps, checkpoint intervals
+    return [random_case(21, nx=150, nz=77, nt=130, nshots=3, ckpt=17),
+            random_case(22, nx=96, nz=120, nt=90, nshots=2, ckpt=20),
+            random_case(23, nx=200, nz=64, nt=111, nshots=4, ckpt=50)]
+
+
+def _resids(cases):
+    return [_dev(synth.bandlimited_noise((c.nshots, c.nt, c.nrec), 15.0, c.dt, 40 + i))
+            for i, c in enumerate(cases)]
+
+
+def _single(cases, resids):
+    out = []
+    for c, r in zip(cases, resids):
+        plan = c.plan()
+        d = plan.forward(_dev(c.v), _dev(c.wav), save=True).clone()
+        g = plan.backward(r).clone()
+        out.append((d, g))
+    return out
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_batch_equals_single_plans(sw, graph):
+    cases = _cases()
+    resids = _resids(cases)
+    ref = _single(cases, resids)
+    plans = [c.plan() for c in cases]
+    batch = sw.Batch(plans, use_graph=graph)
+    for rep in range(3 if graph else 1):
+        ds = batch.forward([_dev(c.v) for c in cases], [_dev(c.wav) for c in cases], save=True)
+        gs = batch.backward(resids)
+        torch.cuda.synchronize()
+        for q in range(len(cases)):
+            assert torch.equal(ds[q], ref[q][0]), (rep, q)
+            assert torch.equal(gs[q], ref[q][1]), (rep, q)
+        # eager work between replays
+        _ = (torch.randn(1000, device="cuda") * 2).sum().item()
+
+
+def test_plan_graph_replays_match_eager(sw):
+    c = random_case(31, nt=140, ckpt=25)
+    r = _dev(synth.bandlimited_noise((c.nshots, c.nt, c.nrec), 15.0, c.dt, 3))
+    eager = c.plan()
+    d0 = eager.forward(_dev(c.v), _dev(c.wav), save=True).clone()
+    g0 = eager.backward(r).clone()
+    gp = c.plan()
+    gp.set_tuning(rz=8, use_graph=1)
+    v, w = _dev(c.v), _dev(c.wav)
+    out = torch.empty_like(d0)
+    grad = torch.empty_like(g0)
+    for rep in range(4):
+        gp.forward(v, w, save=True, out=out)
+        gp.backward(r, out=grad)
+        torch.cuda.synchronize()
+        assert torch.equal(out, d0), rep
+        assert torch.equal(grad, g0), rep
+        x = torch.randn(4096, device="cuda")
+        assert torch.isfinite(x.sum())
+
+
+def test_autotune_picks_a_tiling_and_caches(sw, tmp_path):
+    c = random_case(41, nx=300, nz=180, nt=60, nshots=4)
+    plan = c.plan()
+    cache = str(tmp_path / "tune.txt")
+    rz = plan.autotune(_dev(c.v), _dev(c.wav), steps=10, cache_path=cache)
+    assert rz in (1, 2, 4, 8)
+    assert plan.tuning["rz"] == rz
+    with open(cache) as f:
+        lines = f.read().strip().splitlines()
+    assert len(lines) == 1 and lines[0].split()[-2] == str(rz)
+    d1 = plan.forward(_dev(c.v), _dev(c.wav)).clone()
+    plan2 = c.plan()
+    assert plan2.autotune(_dev(c.v), _dev(c.wav), steps=10, cache_path=cache) == rz
+    d0 = c.plan().forward(_dev(c.v), _dev(c.wav))
+    assert torch.equal(d0, d1)
