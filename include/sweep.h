@@ -173,6 +173,44 @@ size_t sweep_l2_misfit_scratch_bytes(size_t n);
 int sweep_l2_misfit(const float* d_pred, const float* d_obs, float* d_resid, double* d_J,
                     size_t n, void* d_scratch, void* stream);
 
+/* ---- MLP velocity model (neural-network velocity representation, Sec. 1) ----
+ * v(x) = vmin + vscale * sigmoid(f(gamma(x))), gamma(x) = [cos 2 pi B x, sin 2 pi B x]
+ * with 64 random frequencies B [64][2] and x = (i/(nx-1), j/(nz-1)) for model cell
+ * (i, j) (point index m = j nx + i); f: 128 -> 256 -> 256 -> 256 -> 256 -> 1 with ReLU.
+ * theta: float32 parameter vector of sweep_mlp_param_count() entries, in the order
+ * W1 [256][128], b1 [256], W2 [256][256], b2, W3, b3, W4, b4, w5 [256], b5 [1]
+ * (matrices stored out x in). Matrix products run on bf16 MFMA with float32
+ * accumulation: features, weights (the pack made by sweep_mlp_cast),
+ * hidden activations and back-propagated pre-activation gradients are
+ * bfloat16 (round to nearest even); everything else is float32.
+ * Device buffers: d_feats [npoints][128] bf16, d_wpack sweep_mlp_pack_count()
+ * uint16, d_v / d_dv [npoints] float32, d_grad like theta. d_work holds the
+ * forward activations that sweep_mlp_backward needs (same d_work, same npoints).
+ * Its layout is public so that callers can inspect the bf16 intermediates:
+ * with A(x) = x rounded up to a multiple of 256 bytes and S = npoints*256*2,
+ * H1..H4 (hidden activations) at 0, S, 2S, 3S; y (float32 pre-sigmoid output)
+ * at A(4S); after sweep_mlp_backward, dZ1..dZ4 (gradients with respect to the
+ * hidden pre-activations) at A(A(4S) + 4 npoints) + l S, l = 0..3; every block
+ * row-major [npoints][256].
+ * All reductions are split over fixed row chunks and summed in a fixed order:
+ * the results are deterministic. */
+size_t sweep_mlp_param_count(void);
+size_t sweep_mlp_pack_count(void);
+size_t sweep_mlp_workspace_bytes(int npoints);
+int sweep_mlp_encode(const float* d_B, int nx, int nz, uint16_t* d_feats, void* stream);
+int sweep_mlp_cast(const float* d_theta, uint16_t* d_wpack, void* stream);
+int sweep_mlp_forward(const uint16_t* d_wpack, const float* d_theta, const uint16_t* d_feats,
+                      int npoints, float vmin, float vscale, float* d_v, void* d_work,
+                      size_t work_bytes, void* stream);
+int sweep_mlp_backward(const uint16_t* d_wpack, const uint16_t* d_feats, int npoints, float vscale,
+                       const float* d_dv, float* d_grad, void* d_work, size_t work_bytes,
+                       void* stream);
+
+/* Adam (Kingma & Ba 2015) on n float32 parameters, step t >= 1 (bias-corrected):
+ * m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2; theta -= lr m^ / (sqrt(v^) + eps). */
+int sweep_adam_step(float* d_theta, float* d_m, float* d_v, const float* d_g, size_t n, float lr,
+                    float b1, float b2, float eps, int t, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

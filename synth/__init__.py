@@ -23,7 +23,7 @@ from typing import List, Optional, Tuple
 import numpy as np
 
 __all__ = [
-    "ricker", "bandlimited_noise", "layered_anomaly", "interface_model", "smooth", "elastic_model",
+    "ricker", "bandlimited_noise", "rff_frequencies", "layered_anomaly", "interface_model", "smooth", "elastic_model",
     "surface_shots", "line_receivers", "Workload", "workload", "batched_workloads",
     "WORKLOADS",
 ]
@@ -122,6 +122,12 @@ def bandlimited_noise(shape, f0: float, dt: float, seed: int) -> np.ndarray:
     sl = [slice(None)] * x.ndim
     sl[x.ndim - 2] = slice(n0, n0 + shape[-2])
     return np.ascontiguousarray(y[tuple(sl)])
+
+
+def rff_frequencies(nfreq: int = 64, sigma: float = 10.0, seed: int = 0) -> np.ndarray:
+    """Random Fourier frequencies B [nfreq][2] ~ N(0, sigma^2) for the MLP
+    velocity model's coordinate encoding."""
+    return np.random.default_rng(seed + 1234).normal(0.0, sigma, (nfreq, 2))
 
 
 @dataclasses.dataclass
