@@ -27,6 +27,34 @@ import numpy as np  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
 WORKLOAD = "layered1000x300"
+METRIC = "Gcell-updates/s fwd+adj; batched vs per-shot FWI gradient time at 1e-4 rel err"
+
+# HBM traffic of the dominant kernel per launch, from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE runs of this benchmark, each scaled by what the same counter reads
+# for a plain device copy of known size (--calibrate-copy). Keyed by kernel
+# class; valid only while the kernel source hashes to the recorded value.
+TRAFFIC = {"adj_main": {"bytes_per_launch": 981739276, "source": "c1407dd607838f67"}}
+
+
+def _source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    with open(os.path.join(ROOT, "paper_2604_14189_amd", "csrc", "acoustic.hip"), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def calibrate_copy(nbytes=1 << 30, reps=3):
+    """A plain device-to-device copy of known size, for scaling the HBM byte
+    counters (run under rocprofv3 --pmc)."""
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibrate_copy_bytes_read": nbytes, "bytes_written": nbytes,
+                      "reps": reps, "kernel": "torch copy_"}), flush=True)
 
 
 def cpu_baseline(w, max_seconds=30.0):
@@ -62,6 +90,48 @@ def cpu_baseline(w, max_seconds=30.0):
                       f"{t:.1f} s wall"}
 
 
+def per_shot_compare(sw, torch, w, v0, wav, d_obs, nsample, rz, t_batched):
+    """The same FWI gradient through the per-shot path: one single-shot plan
+    per shot, its kernels launched once per shot per step (no batching, no
+    graph), timed on `nsample` shots spread over the line and scaled to all
+    shots. Also checks that the per-shot gradients sum to the batched gradient
+    of the same shots."""
+    from tests.helpers import case_from_workload
+    shots = sorted(set(np.linspace(0, w.nshots - 1, nsample).round().astype(int).tolist()))
+    cs = case_from_workload(w, shots=shots)
+    bp = cs.plan()
+    bp.set_tuning(rz=rz)
+    idx = torch.tensor(shots, device=wav.device)
+    d = bp.forward(v0, wav[idx].contiguous(), save=True)
+    r, _ = sw.l2_misfit(d, d_obs[idx].contiguous())
+    g_batch = bp.backward(r).double()
+    bp.release_workspace()
+    del bp
+
+    def one(s):
+        p1 = case_from_workload(w, shots=[s]).plan()
+        p1.set_tuning(rz=rz)
+        d = p1.forward(v0, wav[s:s + 1], save=True)
+        r, _ = sw.l2_misfit(d, d_obs[s:s + 1])
+        g = p1.backward(r)
+        p1.release_workspace()
+        return g
+
+    one(shots[0])  # warm-up: kernels loaded, workspace block cached
+    torch.cuda.synchronize()
+    g_sum = torch.zeros_like(g_batch)
+    t0 = time.perf_counter()
+    for s in shots:
+        g_sum += one(s).double()
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / len(shots)
+    err = float(torch.linalg.norm(g_sum - g_batch) / torch.linalg.norm(g_batch))
+    est = t * w.nshots
+    return {"shots_timed": len(shots), "s_per_shot": round(t, 4),
+            "per_shot_gradient_s": round(est, 3), "batched_gradient_s": round(t_batched, 3),
+            "speedup": round(est / t_batched, 2), "grad_rel_err_vs_batched": err}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -70,12 +140,20 @@ def main():
     ap.add_argument("--rz", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--nt", type=int, default=0, help="override the step count (testing)")
+    ap.add_argument("--per-shot-sample", type=int, default=4,
+                    help="shots timed through the per-shot path (0: skip)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU shot "
                           "partitioning is described in DESIGN.md but not implemented",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
 
     import torch
     import paper_2604_14189_amd as sw
@@ -119,6 +197,10 @@ def main():
 
     cell_updates = 2.0 * w.nshots * NX * NZ * w.nt
     value = cell_updates / dt / 1e9
+    per_shot = None
+    if args.per_shot_sample > 0:
+        per_shot = per_shot_compare(sw, torch, w, v0, wav, d_obs, args.per_shot_sample, args.rz,
+                                    dt)
 
     # dominant kernel class by total time; algorithmic bytes per cell-update of
     # the whole-grid main kernels: forward 16 B (read p^n, p^{n-1}, Cs; write
@@ -135,13 +217,15 @@ def main():
         avg_s = tot_ms / launches / 1e3
         bytes_per_launch = per_cell[dom] * NX * NZ * w.nshots
         achieved = bytes_per_launch / avg_s / 1e9
+        tr = TRAFFIC.get(dom)
+        traffic = tr["bytes_per_launch"] if tr and tr["source"] == _source_hash() else None
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": dom, "avg_launch_us": round(avg_s * 1e6, 2),
                 "algorithmic_bytes_per_launch": int(bytes_per_launch)}
 
     out = {
-        "metric": "Gcell-updates/s fwd+adj (FWI gradient, checkpointed, batched shots)",
+        "metric": METRIC,
         "value": round(value, 3),
         "unit": "Gcell-updates/s",
         "n_gpus": 1,
@@ -156,7 +240,9 @@ def main():
         "config": {"workload": WORKLOAD, "nx": w.nx, "nz": w.nz, "padded": f"{NX}x{NZ}",
                    "nt": w.nt, "shots": w.nshots, "receivers": w.nrec, "pml": w.pml,
                    "ckpt_every": w.ckpt_every, "rz": args.rz, "misfit_J": float(J.item())},
+        "model_grid_value": round(value * w.nx * w.nz / (NX * NZ), 3),
         "roofline": roof,
+        "per_shot": per_shot,
         "kernel_ms": {name: [n, round(ms, 3)] for name, (n, ms) in kt.items()},
     }
     if not args.no_cpu_baseline:

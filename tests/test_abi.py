@@ -1,0 +1,78 @@
+"""Host-only checks of the C-ABI boundary: the built library loads without a
+GPU, exports exactly the entry points include/sweep.h declares, and its
+argument validation, which runs before any HIP call, rejects bad problems."""
+import ctypes
+import os
+import re
+import shutil
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sweep.h")
+LIB = os.path.join(ROOT, "paper_2604_14189_amd", "libsweep.so")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sweep_\w+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.fail("libsweep.so is not built (run __graft_entry__.build())")
+    return ctypes.CDLL(LIB)
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for core in ("sweep_plan_create", "sweep_forward", "sweep_backward", "sweep_batch_create",
+                 "sweep_batch_forward", "sweep_batch_backward", "sweep_l2_misfit",
+                 "sweep_mlp_forward", "sweep_mlp_backward", "sweep_adam_step",
+                 "sweep_plan_autotune", "sweep_last_error"):
+        assert core in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    missing = [n for n in _declared() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+@pytest.mark.skipif(shutil.which("nm") is None, reason="nm not available")
+def test_no_undeclared_c_exports():
+    out = subprocess.run(["nm", "-D", "--defined-only", LIB], capture_output=True, text=True,
+                         check=True).stdout
+    exported = sorted({ln.split()[-1] for ln in out.splitlines()
+                       if ln.split() and ln.split()[-1].startswith("sweep_")})
+    assert exported == _declared()
+
+
+def test_argument_validation_needs_no_gpu(lib):
+    from paper_2604_14189_amd._lib import Problem, EINVAL, ECFL
+    lib.sweep_plan_create.restype = ctypes.c_int
+    lib.sweep_plan_create.argtypes = [ctypes.POINTER(Problem), ctypes.c_void_p, ctypes.c_void_p,
+                                      ctypes.POINTER(ctypes.c_void_p)]
+    lib.sweep_last_error.restype = ctypes.c_char_p
+    src = (ctypes.c_int32 * 2)(5, 5)
+    rec = (ctypes.c_int32 * 2)(7, 5)
+
+    def create(**kw):
+        pb = dict(physics=0, nx=32, nz=32, pml=10, free_surface=0, h=10.0, dt=1e-3, nt=10,
+                  pml_vmax=2000.0, pml_f0=10.0, pml_R=1e-3, ckpt_every=5, nshots=1, nrec=1)
+        pb.update(kw)
+        out = ctypes.c_void_p()
+        rc = lib.sweep_plan_create(ctypes.byref(Problem(**pb)), src, rec, ctypes.byref(out))
+        return rc, lib.sweep_last_error().decode()
+
+    rc, msg = create(nt=0)
+    assert rc == EINVAL and msg
+    rc, msg = create(nx=-3)
+    assert rc == EINVAL
+    # Courant number vmax dt / h above the 8th-order leapfrog limit
+    rc, msg = create(pml_vmax=6000.0)
+    assert rc == ECFL and msg
+    rc, msg = create(physics=7)
+    assert rc == EINVAL
