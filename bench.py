@@ -90,7 +90,7 @@ def cpu_baseline(w, max_seconds=30.0):
                       f"{t:.1f} s wall"}
 
 
-def per_shot_compare(sw, torch, w, v0, wav, d_obs, nsample, rz, t_batched):
+def per_shot_compare(sw, torch, w, v0, wav, d_obs, nsample, tuning, t_batched):
     """The same FWI gradient through the per-shot path: one single-shot plan
     per shot, its kernels launched once per shot per step (no batching, no
     graph), timed on `nsample` shots spread over the line and scaled to all
@@ -100,7 +100,7 @@ def per_shot_compare(sw, torch, w, v0, wav, d_obs, nsample, rz, t_batched):
     shots = sorted(set(np.linspace(0, w.nshots - 1, nsample).round().astype(int).tolist()))
     cs = case_from_workload(w, shots=shots)
     bp = cs.plan()
-    bp.set_tuning(rz=rz)
+    bp.set_tuning(*tuning)
     idx = torch.tensor(shots, device=wav.device)
     d = bp.forward(v0, wav[idx].contiguous(), save=True)
     r, _ = sw.l2_misfit(d, d_obs[idx].contiguous())
@@ -110,7 +110,7 @@ def per_shot_compare(sw, torch, w, v0, wav, d_obs, nsample, rz, t_batched):
 
     def one(s):
         p1 = case_from_workload(w, shots=[s]).plan()
-        p1.set_tuning(rz=rz)
+        p1.set_tuning(*tuning)
         d = p1.forward(v0, wav[s:s + 1], save=True)
         r, _ = sw.l2_misfit(d, d_obs[s:s + 1])
         g = p1.backward(r)
@@ -137,7 +137,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--rz", type=int, default=8)
+    ap.add_argument("--rz", type=int, default=4)
+    ap.add_argument("--pml-rz", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--nt", type=int, default=0, help="override the step count (testing)")
     ap.add_argument("--per-shot-sample", type=int, default=4,
@@ -166,7 +167,7 @@ def main():
     case = case_from_workload(w)
     dev = torch.device("cuda:0")
     plan = case.plan()
-    plan.set_tuning(rz=args.rz)
+    plan.set_tuning(rz=args.rz, pml_rz=args.pml_rz)
     NX, NZ = plan.padded()
     v_true = torch.tensor(case.v, dtype=torch.float32, device=dev)
     v0 = torch.tensor(synth.smooth(case.v, 20.0), dtype=torch.float32, device=dev)
@@ -199,23 +200,32 @@ def main():
     value = cell_updates / dt / 1e9
     per_shot = None
     if args.per_shot_sample > 0:
-        per_shot = per_shot_compare(sw, torch, w, v0, wav, d_obs, args.per_shot_sample, args.rz,
-                                    dt)
+        per_shot = per_shot_compare(sw, torch, w, v0, wav, d_obs, args.per_shot_sample,
+                                    (args.rz, args.pml_rz), dt)
 
-    # dominant kernel class by total time; algorithmic bytes per cell-update of
-    # the whole-grid main kernels: forward 16 B (read p^n, p^{n-1}, Cs; write
-    # p^{n+1}), recompute 20 B (+ write B^n), adjoint 28 B (read lambda^{n+1},
+    # dominant kernel class by total time. Algorithmic bytes per cell-update:
+    # interior kernel forward 16 B (read p^n, p^{n-1}, Cs; write p^{n+1}),
+    # recompute 20 B (+ write B^n), adjoint 28 B (read lambda^{n+1},
     # lambda^{n+2}, Cs, B^n, g; write lambda^n, g), 24 B on the first step of a
-    # segment (g written, not read)
+    # segment (g written, not read). The PML kernel moves the same per cell plus
+    # 16 B per C-PML axis at each strip cell (psi and zeta read and written).
     k = w.ckpt_every
-    per_cell = {"fwd_main": 16.0, "rec_main": 20.0, "adj_main": (28.0 * (k - 1) + 24.0) / k}
+    n_int, n_pml, TZ = plan.tiles()
+    int_cells = n_int * 64 * TZ
+    frame_cells = NX * NZ - int_cells
+    strip_cells = 2 * w.pml * NZ + 2 * w.pml * NX
+    base = {"fwd": 16.0, "rec": 20.0, "adj": (28.0 * (k - 1) + 24.0) / k}
+    per_launch = {}
+    for ph, b in base.items():
+        per_launch[ph + "_main"] = b * int_cells * w.nshots
+        per_launch[ph + "_band"] = (b * frame_cells + 16.0 * strip_cells) * w.nshots
     shares = {kk: vv[1] for kk, vv in kt.items()}
     dom = max(shares, key=lambda kk: shares[kk])
     roof = None
-    if dom in per_cell and kt[dom][0] > 0:
+    if dom in per_launch and kt[dom][0] > 0:
         launches, tot_ms = kt[dom]
         avg_s = tot_ms / launches / 1e3
-        bytes_per_launch = per_cell[dom] * NX * NZ * w.nshots
+        bytes_per_launch = per_launch[dom]
         achieved = bytes_per_launch / avg_s / 1e9
         tr = TRAFFIC.get(dom)
         traffic = tr["bytes_per_launch"] if tr and tr["source"] == _source_hash() else None
@@ -223,6 +233,13 @@ def main():
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": dom, "avg_launch_us": round(avg_s * 1e6, 2),
                 "algorithmic_bytes_per_launch": int(bytes_per_launch)}
+    kernels = {}
+    for name, (nl, ms) in kt.items():
+        if nl > 0:
+            avg = ms / nl / 1e3
+            kernels[name] = {"launches": nl, "total_ms": round(ms, 3),
+                             "avg_us": round(avg * 1e6, 2),
+                             "algorithmic_GBps": round(per_launch[name] / avg / 1e9, 1)}
 
     out = {
         "metric": METRIC,
@@ -239,11 +256,12 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOAD, "nx": w.nx, "nz": w.nz, "padded": f"{NX}x{NZ}",
                    "nt": w.nt, "shots": w.nshots, "receivers": w.nrec, "pml": w.pml,
-                   "ckpt_every": w.ckpt_every, "rz": args.rz, "misfit_J": float(J.item())},
+                   "ckpt_every": w.ckpt_every, "rz": args.rz, "pml_rz": args.pml_rz, "misfit_J": float(J.item())},
         "model_grid_value": round(value * w.nx * w.nz / (NX * NZ), 3),
         "roofline": roof,
         "per_shot": per_shot,
-        "kernel_ms": {name: [n, round(ms, 3)] for name, (n, ms) in kt.items()},
+        "kernels": kernels,
+        "tiles": {"interior": n_int, "frame": n_pml, "rows": TZ},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)

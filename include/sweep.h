@@ -69,8 +69,10 @@ typedef struct {
 /* Tile / launch choices (what the autotuner searches). Results are bitwise
  * independent of every field here. */
 typedef struct {
-  int rz;          /* rows per thread in the interior step kernels: 1, 2, 4 or 8 */
-  int shots_per_block; /* shots a work-group advances (shares the model reads): 1, 2, 4 */
+  int rz;          /* acoustic tiles are 64 x 4 rz cells; rows per thread of the
+                      interior kernel: 1, 2, 4 or 8 (default 4) */
+  int pml_rz;      /* rows per thread of the C-PML (frame-tile) kernels, <= rz: a
+                      frame tile is split into rz / pml_rz work-groups (default 4) */
   int use_graph;   /* 1 = capture each forward/backward time loop as a hipGraph */
 } sweep_tuning;
 
@@ -93,10 +95,10 @@ int sweep_plan_set_tuning(sweep_plan* plan, const sweep_tuning* t);
 int sweep_plan_get_tuning(const sweep_plan* plan, sweep_tuning* t);
 
 /* Autotuner: runs `steps` forward steps of this plan for every supported tile
- * choice (rz = 1, 2, 4, 8 rows per thread in the main stencil kernel), keeps the
- * fastest and stores it in the plan; `cache_path` (may be NULL) is a text file
- * of previous results keyed by (GPU arch, physics, NX, NZ, nshots), read first
- * and appended to. Synchronises `stream`. d_work needs the forward-only
+ * choice (rz and pml_rz in 1, 2, 4, 8 with pml_rz <= rz), keeps the fastest and
+ * stores it in the plan; `cache_path` (may be NULL) is a text file of previous
+ * results, one line "arch physics NX NZ nshots rz pml_rz us_per_step", keyed by
+ * (GPU arch, physics, NX, NZ, nshots), read first and appended to. Synchronises `stream`. d_work needs the forward-only
  * workspace. Results never depend on the choice (bitwise). *chosen_rz (may be
  * NULL) receives the selected value. */
 int sweep_plan_autotune(sweep_plan* plan, const float* d_model, const float* d_wavelet,
@@ -109,6 +111,14 @@ size_t sweep_plan_workspace_bytes(const sweep_plan* plan, int for_backward);
 
 /* Padded grid size of the plan (NX, NZ). */
 int sweep_plan_padded(const sweep_plan* plan, int* NX, int* NZ);
+
+/* Acoustic tiling under the current tuning: the padded grid is cut into tiles
+ * of 64 columns x tile_rows rows. interior_tiles whole tiles hold no C-PML cell
+ * (no cell within pml + 4 of an edge) and are advanced by the interior kernel
+ * (16 bytes per cell-update forward); the frame_tiles others by the PML kernel.
+ * EINVAL for an elastic plan or a null pointer. */
+int sweep_plan_tiles(const sweep_plan* plan, int* interior_tiles, int* frame_tiles,
+                     int* tile_rows);
 
 /* Forward modelling of every shot.
  *   d_model   [nparam][nz][nx]: acoustic vp (nparam 1); elastic vp, vs, rho (3)

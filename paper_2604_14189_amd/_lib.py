@@ -36,7 +36,7 @@ class Problem(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     """Mirror of sweep_tuning."""
-    _fields_ = [("rz", ctypes.c_int), ("shots_per_block", ctypes.c_int),
+    _fields_ = [("rz", ctypes.c_int), ("pml_rz", ctypes.c_int),
                 ("use_graph", ctypes.c_int)]
 
 
@@ -52,6 +52,9 @@ _SIGS = {
     "sweep_plan_workspace_bytes": (ctypes.c_size_t, [ctypes.c_void_p, ctypes.c_int]),
     "sweep_plan_padded": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int),
                                          ctypes.POINTER(ctypes.c_int)]),
+    "sweep_plan_tiles": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int),
+                                        ctypes.POINTER(ctypes.c_int),
+                                        ctypes.POINTER(ctypes.c_int)]),
     "sweep_forward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
                                      ctypes.c_int, ctypes.c_void_p]),

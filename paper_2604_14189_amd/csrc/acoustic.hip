@@ -9,15 +9,17 @@
 //
 // Decomposition of one step. B' = D2' p + Ex + Ez, where the C-PML part
 //   Ex = D1x' psi_x + zeta_x   is non-zero only in the x band (columns within
-//   P+4 of the left/right edges) and Ez likewise in the z band. Per step:
-//   1. band kernels (x, then z): update the memory variables and fold the pad
-//      terms into the previous field in place, p^{n-1} <- p^{n-1} - Cs E;
-//   2. main kernel over the whole grid: p^{n+1} = 2 p^n - p^{n-1} + Cs D2' p^n,
-//      source injection and receiver recording.
-// The adjoint is the same split of the transposed recurrence. The main kernel
-// stages a 4-cell halo tile of the field in LDS and keeps RZ rows per thread in
-// registers; the band kernels are 1-D along their axis (a wave per row segment
-// for x, a 64-column slab for z) and touch only the band cells.
+//   P+4 of the left/right edges) and Ez likewise in the z band. The grid is cut
+//   into 64 x TZ tiles (TZ = 4 RZ). Tiles with no band cell form a rectangle and
+//   are advanced by the interior kernel, which computes only the leapfrog with
+//   D2' p (16 bytes per cell); the frame of tiles around it is advanced by the
+//   PML kernel, which does the whole update of its cells in one pass: psi on a
+//   4-cell halo ring in LDS, then zeta, B' and p^{n+1}. Both kernels record
+//   receivers and inject the source of their own tiles. At a cell outside the
+//   band every C-PML term is an exact zero, so both kernels produce the same
+//   bits there and results do not depend on the tiling.
+// The adjoint is the same split of the transposed recurrence. Work-groups are
+// spread over the XCDs in contiguous runs of tiles (see xcd_spread).
 #include "internal.h"
 
 namespace sweep {
@@ -76,12 +78,6 @@ __device__ __forceinline__ int zstrip_row(int gz, int NZ, int P) {
   if (gz >= NZ - P) return gz - (NZ - 2 * P);
   return -1;
 }
-__device__ __forceinline__ bool in_xband(int gx, int NX, int P) {
-  return P > 0 && (gx < P + 4 || gx >= NX - P - 4);
-}
-__device__ __forceinline__ bool in_zband(int gz, int NZ, int P) {
-  return P > 0 && (gz < P + 4 || gz >= NZ - P - 4);
-}
 
 // ---------------------------------------------------------------------------
 // Model preparation: edge-replicated padding, Cs = (v dt/h)^2, C-PML tables.
@@ -124,11 +120,46 @@ __global__ void ac_tables_kernel(float* ax, float* bx, float* az, float* bz, int
   if (i < NZ) pml_coeffs(i, NZ, P, h, dt, vmax, f0, R, az, bz);
 }
 
+
 // ---------------------------------------------------------------------------
-// Main kernels: a 64 x TZ tile per work-group, TZ = 4 RZ; thread (lx, w) owns
-// column lx and rows [w RZ, w RZ + RZ). Tiles whose 4-cell halo lies inside
-// the grid take unguarded loads; edge tiles zero-fill outside the grid.
+// Tiles and work-group placement.
 // ---------------------------------------------------------------------------
+// Work-groups of one launch are dealt to the 8 XCDs round-robin by flat index,
+// and each XCD has its own L2. xcd_spread renumbers the flat index f of n so
+// that every XCD receives one contiguous run of the logical block order
+// (consecutive tiles of a shot, then the next shot): tiles that share halo
+// cache lines then run under the same L2. It is a bijection of [0, n).
+__device__ __forceinline__ int xcd_spread(int f, int n) {
+  const int x = f & 7, k = f >> 3;
+  const int q = n >> 3, r = n & 7;
+  return x * q + min(x, r) + k;
+}
+
+// Global tile index of the b-th interior tile (row-major in the rectangle
+// [itx0, itx1) x [itz0, itz1) of tile coordinates).
+__device__ __forceinline__ int interior_tile(const AcStep& a, int b) {
+  const int w = a.itx1 - a.itx0;
+  return (a.itz0 + b / w) * a.tiles_x + a.itx0 + b % w;
+}
+
+// The frame (tiles outside the interior rectangle) is split in two sets.
+// x frame: the tile columns left and right of the rectangle, all rows; these
+// are exactly the columns with an x-strip cell within 4 cells.
+// z frame: the columns of the rectangle, in the rows above and below it.
+// With an empty rectangle (itx0 = itx1 = itz0 = itz1 = 0) the x frame is the
+// whole grid and the z frame is empty.
+__device__ __forceinline__ int xframe_tile(const AcStep& a, int f) {
+  const int nl = a.itx0, per = nl + (a.tiles_x - a.itx1);
+  const int tz = f / per, k = f % per;
+  return tz * a.tiles_x + (k < nl ? k : a.itx1 + (k - nl));
+}
+__device__ __forceinline__ int zframe_tile(const AcStep& a, int f) {
+  const int w = a.itx1 - a.itx0;
+  const int rr = f / w;
+  const int tz = rr < a.itz0 ? rr : a.itz1 + (rr - a.itz0);
+  return tz * a.tiles_x + a.itx0 + f % w;
+}
+
 template <int RZ>
 struct MainTile {
   static constexpr int TZ = 4 * RZ;
@@ -166,16 +197,87 @@ __device__ __forceinline__ void stage_box(float* s, const float* __restrict__ f,
   }
 }
 
+// Receivers of (shot, tile) in the block's rows [row0, row0 + 4 RZ) of the tile
+// record p^{n+1}: the outputs are staged in st (64 x 4 RZ) and each CSR entry
+// (local index (row within the tile) * 64 + column) copies one of them.
 template <int RZ>
-__device__ __forceinline__ void ac_fwd_main_body(const AcStep& a, const int bx, const int by, const int bz) {
+__device__ __forceinline__ void record_receivers(const AcStep& a, int shot, int tile, int row0,
+                                                 const float* out, float* st) {
+  const int* ro = a.rec_off + (size_t)shot * a.ntiles + tile;
+  const int e0 = ro[0], e1 = ro[1];
+  if (!a.gathers || e1 <= e0) return;
+  const int lx = threadIdx.x & 63, zb = (threadIdx.x >> 6) * RZ;
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < RZ; ++r) st[(zb + r) * kTX + lx] = out[r];
+  __syncthreads();
+  float* dst = a.gathers + ((size_t)shot * a.nt + a.n) * a.nrec;
+  for (int e = e0 + (int)threadIdx.x; e < e1; e += kThreads) {
+    const int2 en = a.rec_ent[e];
+    const int r = en.x >> 6;
+    if (r >= row0 && r < row0 + 4 * RZ) dst[en.y] = st[en.x - row0 * kTX];
+  }
+}
+
+// Adds r_{n-1} at the receivers of this (shot, tile) in rows [row0, row0 + nrows)
+// to the staged lambda values st[local - row0 * 64] (run heads handle several
+// receivers on one cell, in receiver order; a cell's entries are contiguous).
+__device__ __forceinline__ void inject_residual(const AcStep& a, int shot, int tile, int row0,
+                                                int nrows, float* st) {
+  const int* ro = a.rec_off + (size_t)shot * a.ntiles + tile;
+  const int e0 = ro[0], e1 = ro[1];
+  const float* r = a.resid + ((size_t)shot * a.nt + (a.n - 1)) * a.nrec;
+  for (int e = e0 + (int)threadIdx.x; e < e1; e += kThreads) {
+    const int2 en = a.rec_ent[e];
+    const int row = en.x >> 6;
+    if (row < row0 || row >= row0 + nrows) continue;
+    if (e == e0 || a.rec_ent[e - 1].x != en.x) {
+      float acc = st[en.x - row0 * kTX];
+      for (int k = e; k < e1 && a.rec_ent[k].x == en.x; ++k) acc += r[a.rec_ent[k].y];
+      st[en.x - row0 * kTX] = acc;
+    }
+  }
+}
+
+// Writes lambda^n of the tile, after injecting r_{n-1} at its receivers.
+template <int RZ>
+__device__ __forceinline__ void adj_store(const AcStep& a, int shot, int tile, int row0, int x0,
+                                          int z0, float* out, float* st) {
+  const int lx = threadIdx.x & 63, zb = (threadIdx.x >> 6) * RZ;
+  const int NX = a.NX, NZ = a.NZ;
+  const size_t plane = (size_t)NX * NZ;
+  const int* ro = a.rec_off + (size_t)shot * a.ntiles + tile;
+  if (a.n >= 1 && ro[1] > ro[0]) {
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < RZ; ++r) st[(zb + r) * kTX + lx] = out[r];
+    __syncthreads();
+    inject_residual(a, shot, tile, row0, 4 * RZ, st);
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < RZ; ++r) out[r] = st[(zb + r) * kTX + lx];
+  }
+  const int gx = x0 + lx;
+#pragma unroll
+  for (int r = 0; r < RZ; ++r) {
+    const int gz = z0 + zb + r;
+    if (gx < NX && gz < NZ) a.next[shot * plane + (size_t)gz * NX + gx] = out[r];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Interior kernels: a 64 x TZ tile per work-group; thread (lx, w) owns column
+// lx and rows [w RZ, w RZ + RZ), kept as a register window for the z stencil.
+// ---------------------------------------------------------------------------
+// p^{n+1} = 2 p^n - p^{n-1} + Cs D2' p^n (+ source); B'^n = D2' p^n if kept.
+template <int RZ>
+__device__ __forceinline__ void ac_fwd_int_body(const AcStep& a, const int tile, const int shot) {
   using T = MainTile<RZ>;
   __shared__ float sp[T::LH * T::LW];
   const int tid = threadIdx.x;
   const int lx = tid & 63;
   const int zb = (tid >> 6) * RZ;
-  const int tile = bx;
-  const int shot = by;
-  const int NX = a.NX, NZ = a.NZ, P = a.P;
+  const int NX = a.NX, NZ = a.NZ;
   const size_t plane = (size_t)NX * NZ;
   const int x0 = (tile % a.tiles_x) * kTX, z0 = (tile / a.tiles_x) * T::TZ;
   const bool inside = x0 >= 4 && x0 + kTX + 4 <= NX && z0 >= 4 && z0 + T::TZ + 4 <= NZ;
@@ -183,19 +285,16 @@ __device__ __forceinline__ void ac_fwd_main_body(const AcStep& a, const int bx, 
 
   // the per-cell operands are fetched first so their latency overlaps the
   // staging of the halo tile
-  float pp[RZ], cs[RZ], bo[RZ];
-  const bool xb = in_xband(gx, NX, P);
+  float pp[RZ], cs[RZ];
 #pragma unroll
   for (int r = 0; r < RZ; ++r) {
     const int gz = z0 + zb + r;
     pp[r] = 0.0f;
     cs[r] = 0.0f;
-    bo[r] = 0.0f;
     if (inside || (gx < NX && gz < NZ)) {
       const int idx = gz * NX + gx;
       pp[r] = a.prev[shot * plane + idx];
       cs[r] = a.Cs[idx];
-      if (a.B_out && (xb || in_zband(gz, NZ, P))) bo[r] = a.B_out[shot * plane + idx];
     }
   }
   stage_box<RZ, false>(sp, a.cur + shot * plane, nullptr, x0, z0, NX, NZ, inside);
@@ -224,55 +323,22 @@ __device__ __forceinline__ void ac_fwd_main_body(const AcStep& a, const int bx, 
       pn = fmaf(cs[r], L, 2.0f * c - pp[r]);
       if (idx == src) pn += sw;
       a.next[gi] = pn;
-      if (a.B_out) a.B_out[gi] = (xb || in_zband(gz, NZ, P)) ? L + bo[r] : L;
+      if (a.B_out) a.B_out[gi] = L;
     }
     out[r] = pn;
   }
-
-  // receivers in this tile record p^{n+1}
-  const int* ro = a.rec_off + (size_t)shot * a.ntiles + tile;
-  const int e0 = ro[0], e1 = ro[1];
-  if (a.gathers && e1 > e0) {
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < RZ; ++r) sp[(zb + r) * kTX + lx] = out[r];
-    __syncthreads();
-    float* dst = a.gathers + ((size_t)shot * a.nt + a.n) * a.nrec;
-    for (int e = e0 + tid; e < e1; e += kThreads) {
-      const int2 en = a.rec_ent[e];
-      dst[en.y] = sp[en.x];
-    }
-  }
+  record_receivers<RZ>(a, shot, tile, 0, out, sp);
 }
 
-// Adds r_{n-1} at the receivers of this (shot, tile) to the staged lambda values
-// st[local] (run heads handle several receivers on one cell, in receiver order).
-__device__ __forceinline__ void inject_residual(const AcStep& a, int shot, int tile, float* st) {
-  const int* ro = a.rec_off + (size_t)shot * a.ntiles + tile;
-  const int e0 = ro[0], e1 = ro[1];
-  const float* r = a.resid + ((size_t)shot * a.nt + (a.n - 1)) * a.nrec;
-  for (int e = e0 + (int)threadIdx.x; e < e1; e += kThreads) {
-    const int2 en = a.rec_ent[e];
-    if (e == e0 || a.rec_ent[e - 1].x != en.x) {
-      float acc = st[en.x];
-      for (int k = e; k < e1 && a.rec_ent[k].x == en.x; ++k) acc += r[a.rec_ent[k].y];
-      st[en.x] = acc;
-    }
-  }
-}
-
-// lambda^n = 2 lambda^{n+1} - lambda^{n+2}' + D2'(Cs lambda^{n+1}), where the band
-// kernels already subtracted their pad terms from lambda^{n+2}' in place;
+// lambda^n = 2 lambda^{n+1} - lambda^{n+2} + D2'(Cs lambda^{n+1});
 // g += lambda^{n+1} B'^n; then r_{n-1} is injected at the receivers.
 template <int RZ>
-__device__ __forceinline__ void ac_adj_main_body(const AcStep& a, const int bx, const int by, const int bz) {
+__device__ __forceinline__ void ac_adj_int_body(const AcStep& a, const int tile, const int shot) {
   using T = MainTile<RZ>;
   __shared__ float sq[T::LH * T::LW];
   const int tid = threadIdx.x;
   const int lx = tid & 63;
   const int zb = (tid >> 6) * RZ;
-  const int tile = bx;
-  const int shot = by;
   const int NX = a.NX, NZ = a.NZ;
   const size_t plane = (size_t)NX * NZ;
   const int x0 = (tile % a.tiles_x) * kTX, z0 = (tile / a.tiles_x) * T::TZ;
@@ -317,403 +383,492 @@ __device__ __forceinline__ void ac_adj_main_body(const AcStep& a, const int bx, 
     }
     out[r] = lam;
   }
+  adj_store<RZ>(a, shot, tile, 0, x0, z0, out, sq);
+}
 
-  const int* ro = a.rec_off + (size_t)shot * a.ntiles + tile;
-  if (a.n >= 1 && ro[1] > ro[0]) {
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < RZ; ++r) sq[(zb + r) * kTX + lx] = out[r];
-    __syncthreads();
-    inject_residual(a, shot, tile, sq);
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < RZ; ++r) out[r] = sq[(zb + r) * kTX + lx];
+// ---------------------------------------------------------------------------
+// PML kernels: the frame tiles, whole update in one pass. A work-group takes
+// rows [row0, row0 + 4 RZ) of one frame tile (a frame tile is split into
+// a.nsub such pieces), so its register and LDS footprint is set by its own RZ.
+// Most frame tiles meet the strips of one axis only; the body is specialised
+// on which axes have a strip cell within 4 cells of the piece (HX, HZ), and
+// the other axis reduces exactly to the plain second difference.
+// ---------------------------------------------------------------------------
+template <int RZ, bool HX, bool HZ>
+struct PmlGeom {
+  static constexpr int TZ = 4 * RZ;
+  static constexpr int hx = HX ? 8 : 4;  // halo of the staged field along x
+  static constexpr int hz = HZ ? 8 : 4;  // and along z
+  static constexpr int BW = kTX + 2 * hx;
+  static constexpr int BH = TZ + 2 * hz;
+  static constexpr int XW = kTX + 8;     // x ring (4-column halo)
+  static constexpr int ZH = TZ + 8;      // z ring (4-row halo)
+  // forward LDS: field box, psi_x ring, psi_z ring
+  static constexpr int NB = BH * BW;
+  static constexpr int NPX = HX ? TZ * XW : 0;
+  static constexpr int NPZ = HZ ? ZH * kTX : 0;
+  static constexpr int kFwdFloats = NB + NPX + NPZ;
+  // adjoint LDS: Qbar_x (tile rows, x halo hx), Qbar_z (tile columns, z halo hz), T rings
+  static constexpr int NQX = TZ * BW;
+  static constexpr int NQZ = BH * kTX;
+  static constexpr int kAdjFloats = NQX + NQZ + NPX + NPZ;
+};
+
+// LDS floats of the PML kernels: x frame (largest general variant, both axes)
+// and z frame (field box with an 8-row and 4-column halo)
+template <int RZ>
+struct PmlLds {
+  static constexpr int kFwd = PmlGeom<RZ, true, true>::kFwdFloats;
+  static constexpr int kAdj = PmlGeom<RZ, true, true>::kAdjFloats;
+  static constexpr int kZFwd = PmlGeom<RZ, false, true>::kFwdFloats;
+  static constexpr int kZAdj = PmlGeom<RZ, false, true>::kAdjFloats;
+  static constexpr int get(bool adj, bool z) {
+    return z ? (adj ? kZAdj : kZFwd) : (adj ? kAdj : kFwd);
   }
+};
+
+// Whether the piece [x0, x0+64) x [z0, z0+TZ) has an x-strip (z-strip) cell
+// within 4 cells along x (z).
+__device__ __forceinline__ bool near_xstrip(int x0, int NX, int P) {
+  return P > 0 && (x0 - 4 < P || x0 + kTX + 4 > NX - P);
+}
+__device__ __forceinline__ bool near_zstrip(int z0, int TZ, int NZ, int P) {
+  return P > 0 && (z0 - 4 < P || z0 + TZ + 4 > NZ - P);
+}
+
+// Forward. psi_x^n = b_x psi_x^{n-1} + a_x D1x' p^n on the tile rows and a
+// 4-column halo, psi_z^n likewise on the tile columns and a 4-row halo (zero
+// outside the strips); then per cell
+//   Bx = D2x' p + D1x' psi_x (+ zeta_x^n, zeta_x^n = b_x zeta_x^{n-1} + a_x (D2x' p + D1x' psi_x)
+//   in the x strip), Bz likewise, B' = Bx + Bz, p^{n+1} = 2 p^n - p^{n-1} + Cs B'.
+template <int RZ, bool HX, bool HZ>
+__device__ __forceinline__ void ac_fwd_pml_body(const AcStep& a, const int tile, const int shot,
+                                                const int row0, float* lds) {
+  using G = PmlGeom<RZ, HX, HZ>;
+  constexpr int TZ = G::TZ, BW = G::BW, XW = G::XW, hx = G::hx, hz = G::hz;
+  constexpr int NB = G::NB, KB = (NB + kThreads - 1) / kThreads;
+  constexpr int NPX = G::NPX, KPX = (NPX + kThreads - 1) / kThreads;
+  constexpr int NPZ = G::NPZ, KPZ = (NPZ + kThreads - 1) / kThreads;
+  float* sb = lds;              // p^n: rows z0-hz .., columns x0-hx ..
+  float* spx = lds + NB;        // psi_x^n: tile rows, columns x0-4 ..
+  float* spz = lds + NB + NPX;  // psi_z^n: rows z0-4 .., tile columns
+  const int tid = threadIdx.x;
+  const int lx = tid & 63;
+  const int zb = (tid >> 6) * RZ;
+  const int NX = a.NX, NZ = a.NZ, P = a.P, P2 = 2 * P;
+  const size_t plane = (size_t)NX * NZ;
+  const size_t xsp = (size_t)NZ * P2, zsp = (size_t)P2 * NX;
+  const int x0 = (tile % a.tiles_x) * kTX, z0 = (tile / a.tiles_x) * a.tz + row0;
+  const int gx = x0 + lx;
+  const float* cur = a.cur + shot * plane;
+
+  // all global loads of the step are issued before the first use
+  float vb[KB];
+#pragma unroll
+  for (int k = 0; k < KB; ++k) {
+    const int e = tid + k * kThreads;
+    const int r = e / BW, c = e - (e / BW) * BW;
+    const int gz = z0 - hz + r, gxx = x0 - hx + c;
+    const bool ok = e < NB && gxx >= 0 && gxx < NX && gz >= 0 && gz < NZ;
+    vb[k] = ok ? cur[(size_t)gz * NX + gxx] : 0.0f;
+  }
+  float opx[HX ? KPX : 1], opz[HZ ? KPZ : 1];
+  if constexpr (HX) {
+#pragma unroll
+    for (int k = 0; k < KPX; ++k) {
+      const int e = tid + k * kThreads;
+      const int r = e / XW, c = e - (e / XW) * XW;
+      const int gz = z0 + r, gxx = x0 - 4 + c;
+      const int col = (e < NPX && gz < NZ && gxx >= 0 && gxx < NX) ? xstrip_col(gxx, NX, P) : -1;
+      opx[k] = col >= 0 ? a.psx_in[shot * xsp + (size_t)gz * P2 + col] : 0.0f;
+    }
+  }
+  if constexpr (HZ) {
+#pragma unroll
+    for (int k = 0; k < KPZ; ++k) {
+      const int e = tid + k * kThreads;
+      const int r = e >> 6, c = e & 63;
+      const int gz = z0 - 4 + r, gxx = x0 + c;
+      const int row = (e < NPZ && gxx < NX && gz >= 0 && gz < NZ) ? zstrip_row(gz, NZ, P) : -1;
+      opz[k] = row >= 0 ? a.psz_in[shot * zsp + (size_t)row * NX + gxx] : 0.0f;
+    }
+  }
+  const int xcol = (HX && gx < NX) ? xstrip_col(gx, NX, P) : -1;
+  float pp[RZ], cs[RZ], zx[RZ], zz[RZ];
 #pragma unroll
   for (int r = 0; r < RZ; ++r) {
     const int gz = z0 + zb + r;
-    if (inside || (gx < NX && gz < NZ)) a.next[shot * plane + (size_t)gz * NX + gx] = out[r];
-  }
-}
-
-// ---------------------------------------------------------------------------
-// x band (columns within P+4 of the left/right edges, all rows). One wave per
-// (row, chunk): lane l holds column c0 - 8 + l; a chunk produces up to 48
-// outputs (lanes 8 .. 8+W) and reads an 8-cell halo on each side.
-// ---------------------------------------------------------------------------
-constexpr int kChunk = 48;
-
-// Rows handled by one wave of an x-band work-group (a work-group covers
-// 4 * kXRows consecutive rows of one chunk). All global operands of a wave's
-// rows are loaded before any of them is used.
-constexpr int kXRows = 4;
-
-// psi_x^n, zeta_x^n and Ex = D1x' psi_x^n + zeta_x^n; p^{n-1} -= Cs Ex.
-__device__ __forceinline__ void ac_fwd_xband_body(const AcStep& a, const int bx, const int by, const int bz) {
-  __shared__ float sp[4][kXRows][64];
-  __shared__ float ss[4][kXRows][64];
-  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int2 ch = a.xchunks[bx];
-  const int shot = bz;
-  const int NX = a.NX, NZ = a.NZ, P = a.P, P2 = 2 * P;
-  const int gx = ch.x - 8 + l;
-  const size_t plane = (size_t)NX * NZ;
-  const bool own = l >= 8 && l < 8 + ch.y;
-  const bool col_ok = gx >= 0 && gx < NX;
-  const int col0 = col_ok ? xstrip_col(gx, NX, P) : -1;
-  const float axv = col0 >= 0 ? a.ax[gx] : 0.0f, bxv = col0 >= 0 ? a.bx[gx] : 0.0f;
-  const int gz0 = (by * 4 + w) * kXRows;
-  float pv[kXRows], psio[kXRows], zo[kXRows], cs[kXRows], pp[kXRows];
-#pragma unroll
-  for (int rr = 0; rr < kXRows; ++rr) {
-    const int gz = gz0 + rr;
-    const bool in_grid = col_ok && gz < NZ;
-    const bool strip = in_grid && col0 >= 0;
-    const size_t si = shot * (size_t)NZ * P2 + (size_t)gz * P2 + (strip ? col0 : 0);
-    const size_t gi = shot * plane + (size_t)gz * NX + (in_grid ? gx : 0);
-    pv[rr] = in_grid ? a.cur[gi] : 0.0f;
-    psio[rr] = (strip && l >= 4 && l < 60) ? a.psx_in[si] : 0.0f;
-    zo[rr] = (strip && own) ? a.zex_in[si] : 0.0f;
-    cs[rr] = (in_grid && own) ? a.Cs[(size_t)gz * NX + gx] : 0.0f;
-    pp[rr] = (in_grid && own) ? a.prev_adj[gi] : 0.0f;
+    const bool ok = gx < NX && gz < NZ;
+    const size_t idx = ok ? (size_t)gz * NX + gx : 0;
+    pp[r] = ok ? a.prev[shot * plane + idx] : 0.0f;
+    cs[r] = ok ? a.Cs[idx] : 0.0f;
+    zx[r] = (HX && ok && xcol >= 0) ? a.zex_in[shot * xsp + (size_t)gz * P2 + xcol] : 0.0f;
+    const int zrow = (HZ && ok) ? zstrip_row(gz, NZ, P) : -1;
+    zz[r] = zrow >= 0 ? a.zez_in[shot * zsp + (size_t)zrow * NX + gx] : 0.0f;
   }
 #pragma unroll
-  for (int rr = 0; rr < kXRows; ++rr) sp[w][rr][l] = pv[rr];
-  __syncthreads();
-#pragma unroll
-  for (int rr = 0; rr < kXRows; ++rr) {
-    const int gz = gz0 + rr;
-    const bool strip = col0 >= 0 && gz < NZ;
-    float psi = 0.0f;
-    if (strip && l >= 4 && l < 60) {
-      psi = fmaf(axv, d1s(&sp[w][rr][l], 1), bxv * psio[rr]);
-      if (own) a.psx_out[shot * (size_t)NZ * P2 + (size_t)gz * P2 + col0] = psi;
-    }
-    ss[w][rr][l] = psi;
+  for (int k = 0; k < KB; ++k) {
+    const int e = tid + k * kThreads;
+    if (e < NB) sb[e] = vb[k];
   }
   __syncthreads();
-#pragma unroll
-  for (int rr = 0; rr < kXRows; ++rr) {
-    const int gz = gz0 + rr;
-    if (!(own && col_ok && gz < NZ)) continue;
-    const float d1p = d1s(&ss[w][rr][l], 1);
-    float E = d1p;
-    if (col0 >= 0) {
-      const float Q = d2s(&sp[w][rr][l], 1) + d1p;
-      const float zeta = fmaf(axv, Q, bxv * zo[rr]);
-      a.zex_out[shot * (size_t)NZ * P2 + (size_t)gz * P2 + col0] = zeta;
-      E = d1p + zeta;
-    }
-    const size_t gi = shot * plane + (size_t)gz * NX + gx;
-    a.prev_adj[gi] = fmaf(-cs[rr], E, pp[rr]);
-    if (a.B_out) a.B_out[gi] = E;
-  }
-}
 
-// Adjoint of the x band: zbar = Z + q, Qbar = q + a_x zbar (q = Cs lambda^{n+1}),
-// psbar = Psi - D1x' Qbar, Eadj = D2x'(a_x zbar) - D1x'(a_x psbar);
-// lambda^{n+2}' -= Eadj; Psi <- b_x psbar, Z <- b_x zbar.
-__device__ __forceinline__ void ac_adj_xband_body(const AcStep& a, const int bx, const int by, const int bz) {
-  __shared__ float sQ[4][kXRows][64];
-  __shared__ float sS[4][kXRows][64];
-  __shared__ float sT[4][kXRows][64];
-  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int2 ch = a.xchunks[bx];
-  const int shot = bz;
-  const int NX = a.NX, NZ = a.NZ, P = a.P, P2 = 2 * P;
-  const int gx = ch.x - 8 + l;
-  const size_t plane = (size_t)NX * NZ;
-  const bool own = l >= 8 && l < 8 + ch.y;
-  const bool col_ok = gx >= 0 && gx < NX;
-  const int col0 = col_ok ? xstrip_col(gx, NX, P) : -1;
-  const float axv = col0 >= 0 ? a.ax[gx] : 0.0f, bxv = col0 >= 0 ? a.bx[gx] : 0.0f;
-  const int gz0 = (by * 4 + w) * kXRows;
-  float lv[kXRows], cv[kXRows], zi[kXRows], psi_in[kXRows], pp[kXRows];
+  // memory variables on the halo rings (written back for the piece's own cells)
+  if constexpr (HX) {
 #pragma unroll
-  for (int rr = 0; rr < kXRows; ++rr) {
-    const int gz = gz0 + rr;
-    const bool in_grid = col_ok && gz < NZ;
-    const bool strip = in_grid && col0 >= 0;
-    const size_t si = shot * (size_t)NZ * P2 + (size_t)gz * P2 + (strip ? col0 : 0);
-    const size_t gi = shot * plane + (size_t)gz * NX + (in_grid ? gx : 0);
-    lv[rr] = in_grid ? a.cur[gi] : 0.0f;
-    cv[rr] = in_grid ? a.Cs[(size_t)gz * NX + gx] : 0.0f;
-    zi[rr] = strip ? a.zex_in[si] : 0.0f;
-    psi_in[rr] = (strip && l >= 4 && l < 60) ? a.psx_in[si] : 0.0f;
-    pp[rr] = (in_grid && own) ? a.prev_adj[gi] : 0.0f;
-  }
-#pragma unroll
-  for (int rr = 0; rr < kXRows; ++rr) {
-    const int gz = gz0 + rr;
-    float q = cv[rr] * lv[rr];
-    float sv = 0.0f;
-    if (col0 >= 0 && gz < NZ) {
-      const float zb = zi[rr] + q;
-      sv = axv * zb;
-      q = q + sv;
-      if (own) a.zex_out[shot * (size_t)NZ * P2 + (size_t)gz * P2 + col0] = bxv * zb;
-    }
-    sQ[w][rr][l] = q;
-    sS[w][rr][l] = sv;
-  }
-  __syncthreads();
-#pragma unroll
-  for (int rr = 0; rr < kXRows; ++rr) {
-    const int gz = gz0 + rr;
-    float t = 0.0f;
-    if (col0 >= 0 && gz < NZ && l >= 4 && l < 60) {
-      const float psb = psi_in[rr] - d1s(&sQ[w][rr][l], 1);
-      t = axv * psb;
-      if (own) a.psx_out[shot * (size_t)NZ * P2 + (size_t)gz * P2 + col0] = bxv * psb;
-    }
-    sT[w][rr][l] = t;
-  }
-  __syncthreads();
-#pragma unroll
-  for (int rr = 0; rr < kXRows; ++rr) {
-    const int gz = gz0 + rr;
-    if (!(own && col_ok && gz < NZ)) continue;
-    const float E = d2s(&sS[w][rr][l], 1) - d1s(&sT[w][rr][l], 1);
-    a.prev_adj[shot * plane + (size_t)gz * NX + gx] = pp[rr] - E;
-  }
-}
-
-// ---------------------------------------------------------------------------
-// z band (rows within P+4 of the top/bottom edges, all columns). A work-group
-// covers 64 columns x up to 48 output rows with an 8-row halo above and below;
-// wave w handles the LDS rows congruent to w mod 4, and issues all of its
-// global loads of a phase before using any of them.
-// ---------------------------------------------------------------------------
-constexpr int kZRows = kChunk + 16;
-constexpr int kZStage = kZRows / 4;       // staged rows per wave (64 / 4)
-constexpr int kZPsi = (kZRows - 8) / 4;   // psi rows per wave
-constexpr int kZOut = kChunk / 4;         // output rows per wave
-
-__device__ __forceinline__ void ac_fwd_zband_body(const AcStep& a, const int bx, const int by, const int bz) {
-  __shared__ float sp[kZRows * kTX];
-  __shared__ float ss[kZRows * kTX];
-  const int c = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int2 ch = a.zchunks[by];
-  const int x0 = bx * kTX, gx = x0 + c;
-  const int shot = bz;
-  const int NX = a.NX, NZ = a.NZ, P = a.P;
-  const bool col_ok = gx < NX;
-  const size_t plane = (size_t)NX * NZ;
-  const size_t zs_plane = (size_t)2 * P * NX;
-  const int rows = ch.y + 16;  // LDS row r <-> grid row ch.x - 8 + r
-  {
-    float v[kZStage];
-#pragma unroll
-    for (int k = 0; k < kZStage; ++k) {
-      const int r = w + 4 * k, gz = ch.x - 8 + r;
-      const bool ok = col_ok && r < rows && gz >= 0 && gz < NZ;
-      v[k] = ok ? a.cur[shot * plane + (size_t)gz * NX + gx] : 0.0f;
-    }
-#pragma unroll
-    for (int k = 0; k < kZStage; ++k) sp[(w + 4 * k) * kTX + c] = v[k];
-  }
-  __syncthreads();
-  {
-    float old[kZPsi];
-#pragma unroll
-    for (int k = 0; k < kZPsi; ++k) {
-      const int r = 4 + w + 4 * k, gz = ch.x - 8 + r;
-      const int row = (col_ok && r < rows - 4 && gz >= 0 && gz < NZ) ? zstrip_row(gz, NZ, P) : -1;
-      old[k] = row >= 0 ? a.psz_in[shot * zs_plane + (size_t)row * NX + gx] : 0.0f;
-    }
-#pragma unroll
-    for (int k = 0; k < kZPsi; ++k) {
-      const int r = 4 + w + 4 * k, gz = ch.x - 8 + r;
-      const int row = (col_ok && r < rows - 4 && gz >= 0 && gz < NZ) ? zstrip_row(gz, NZ, P) : -1;
-      float psi = 0.0f;
-      if (row >= 0) {
-        psi = fmaf(a.az[gz], d1s(&sp[r * kTX + c], kTX), a.bz[gz] * old[k]);
-        if (r >= 8 && r < 8 + ch.y) a.psz_out[shot * zs_plane + (size_t)row * NX + gx] = psi;
+    for (int k = 0; k < KPX; ++k) {
+      const int e = tid + k * kThreads;
+      if (e >= NPX) break;
+      const int r = e / XW, c = e - (e / XW) * XW;
+      const int gz = z0 + r, gxx = x0 - 4 + c;
+      const int col = (gz < NZ && gxx >= 0 && gxx < NX) ? xstrip_col(gxx, NX, P) : -1;
+      float ps = 0.0f;
+      if (col >= 0) {
+        ps = fmaf(a.ax[gxx], d1s(&sb[(r + hz) * BW + c + hx - 4], 1), a.bx[gxx] * opx[k]);
+        if (c >= 4 && c < 4 + kTX) a.psx_out[shot * xsp + (size_t)gz * P2 + col] = ps;
       }
-      ss[r * kTX + c] = psi;
+      spx[e] = ps;
     }
   }
-  __syncthreads();
-  float zo[kZOut], cs[kZOut], pp[kZOut], bo[kZOut];
-  const bool xb = in_xband(gx, NX, P);
+  if constexpr (HZ) {
 #pragma unroll
-  for (int k = 0; k < kZOut; ++k) {
-    const int r = 8 + w + 4 * k, gz = ch.x - 8 + r;
-    const bool ok = col_ok && r < 8 + ch.y && gz < NZ;
-    const int row = ok ? zstrip_row(gz, NZ, P) : -1;
-    const size_t kk = ok ? (size_t)gz * NX + gx : 0;
-    zo[k] = row >= 0 ? a.zez_in[shot * zs_plane + (size_t)row * NX + gx] : 0.0f;
-    cs[k] = ok ? a.Cs[kk] : 0.0f;
-    pp[k] = ok ? a.prev_adj[shot * plane + kk] : 0.0f;
-    bo[k] = (ok && a.B_out && xb) ? a.B_out[shot * plane + kk] : 0.0f;
-  }
-#pragma unroll
-  for (int k = 0; k < kZOut; ++k) {
-    const int r = 8 + w + 4 * k, gz = ch.x - 8 + r;
-    if (!(col_ok && r < 8 + ch.y && gz < NZ)) continue;
-    const float d1p = d1s(&ss[r * kTX + c], kTX);
-    float E = d1p;
-    const int row = zstrip_row(gz, NZ, P);
-    if (row >= 0) {
-      const float Q = d2s(&sp[r * kTX + c], kTX) + d1p;
-      const float zeta = fmaf(a.az[gz], Q, a.bz[gz] * zo[k]);
-      a.zez_out[shot * zs_plane + (size_t)row * NX + gx] = zeta;
-      E = d1p + zeta;
+    for (int k = 0; k < KPZ; ++k) {
+      const int e = tid + k * kThreads;
+      if (e >= NPZ) break;
+      const int r = e >> 6, c = e & 63;
+      const int gz = z0 - 4 + r, gxx = x0 + c;
+      const int row = (gxx < NX && gz >= 0 && gz < NZ) ? zstrip_row(gz, NZ, P) : -1;
+      float ps = 0.0f;
+      if (row >= 0) {
+        ps = fmaf(a.az[gz], d1s(&sb[(r + hz - 4) * BW + c + hx], BW), a.bz[gz] * opz[k]);
+        if (r >= 4 && r < 4 + TZ) a.psz_out[shot * zsp + (size_t)row * NX + gxx] = ps;
+      }
+      spz[e] = ps;
     }
-    const size_t gi = shot * plane + (size_t)gz * NX + gx;
-    a.prev_adj[gi] = fmaf(-cs[k], E, pp[k]);
-    if (a.B_out) a.B_out[gi] = xb ? bo[k] + E : E;
   }
+  if constexpr (HX || HZ) __syncthreads();
+
+  float win[RZ + 8];
+#pragma unroll
+  for (int m = 0; m < RZ + 8; ++m) win[m] = sb[(zb + hz - 4 + m) * BW + lx + hx];
+  const int src = a.src_cell[shot];
+  const float sw = a.w * a.wavelet[(size_t)shot * a.nt + a.n];
+  float out[RZ];
+#pragma unroll
+  for (int r = 0; r < RZ; ++r) {
+    const float* row = &sb[(zb + r + hz) * BW + lx + hx];
+    const float c = win[r + 4];
+    const float sx = d2c(c, row[1], row[-1], row[2], row[-2], row[3], row[-3], row[4], row[-4]);
+    const float sz = d2c(c, win[r + 5], win[r + 3], win[r + 6], win[r + 2], win[r + 7],
+                         win[r + 1], win[r + 8], win[r]);
+    float Bx = sx, Bz = sz;
+    if constexpr (HX) Bx = sx + d1s(&spx[(zb + r) * XW + lx + 4], 1);
+    if constexpr (HZ) Bz = sz + d1s(&spz[(zb + r + 4) * kTX + lx], kTX);
+    const int gz = z0 + zb + r;
+    float pn = 0.0f;
+    if (gx < NX && gz < NZ) {
+      const int idx = gz * NX + gx;
+      const size_t gi = shot * plane + idx;
+      if (HX && xcol >= 0) {
+        const float zeta = fmaf(a.ax[gx], Bx, a.bx[gx] * zx[r]);
+        a.zex_out[shot * xsp + (size_t)gz * P2 + xcol] = zeta;
+        Bx = Bx + zeta;
+      }
+      const int zrow = HZ ? zstrip_row(gz, NZ, P) : -1;
+      if (zrow >= 0) {
+        const float zeta = fmaf(a.az[gz], Bz, a.bz[gz] * zz[r]);
+        a.zez_out[shot * zsp + (size_t)zrow * NX + gx] = zeta;
+        Bz = Bz + zeta;
+      }
+      const float B = Bx + Bz;
+      pn = fmaf(cs[r], B, 2.0f * c - pp[r]);
+      if (idx == src) pn += sw;
+      a.next[gi] = pn;
+      if (a.B_out) a.B_out[gi] = B;
+    }
+    out[r] = pn;
+  }
+  record_receivers<RZ>(a, shot, tile, row0, out, sb);
 }
 
-__device__ __forceinline__ void ac_adj_zband_body(const AcStep& a, const int bx, const int by, const int bz) {
-  __shared__ float sQ[kZRows * kTX];
-  __shared__ float sS[kZRows * kTX];
-  __shared__ float sT[kZRows * kTX];
-  const int c = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int2 ch = a.zchunks[by];
-  const int x0 = bx * kTX, gx = x0 + c;
-  const int shot = bz;
-  const int NX = a.NX, NZ = a.NZ, P = a.P;
-  const bool col_ok = gx < NX;
+// Adjoint. With q = Cs lambda^{n+1}: in the x strip zbar_x = Z_x + q and
+// Qbar_x = q + a_x zbar_x (elsewhere Qbar_x = q), on the tile rows and an
+// 8-column halo; psbar_x = Psi_x - D1x' Qbar_x and T_x = a_x psbar_x on a
+// 4-column halo (zero outside the strip); z likewise. Then per cell
+//   lambda^n = 2 lambda^{n+1} - lambda^{n+2} + D2x' Qbar_x + D2z' Qbar_z - D1x' T_x - D1z' T_z,
+// the memory variables become Z = b zbar, Psi = b psbar, and g += lambda^{n+1} B'^n.
+template <int RZ, bool HX, bool HZ>
+__device__ __forceinline__ void ac_adj_pml_body(const AcStep& a, const int tile, const int shot,
+                                                const int row0, float* lds) {
+  using G = PmlGeom<RZ, HX, HZ>;
+  constexpr int TZ = G::TZ, BW = G::BW, XW = G::XW, hx = G::hx, hz = G::hz;
+  constexpr int NQX = G::NQX, KQX = (NQX + kThreads - 1) / kThreads;
+  constexpr int NQZ = G::NQZ, KQZ = (NQZ + kThreads - 1) / kThreads;
+  constexpr int NTX = G::NPX, KTX = (NTX + kThreads - 1) / kThreads;
+  constexpr int NTZ = G::NPZ, KTZ = (NTZ + kThreads - 1) / kThreads;
+  float* sqx = lds;                     // Qbar_x: tile rows, columns x0-hx ..
+  float* sqz = lds + NQX;               // Qbar_z: rows z0-hz .., tile columns
+  float* stx = lds + NQX + NQZ;         // T_x: tile rows, columns x0-4 ..
+  float* stz = lds + NQX + NQZ + NTX;   // T_z: rows z0-4 .., tile columns
+  const int tid = threadIdx.x;
+  const int lx = tid & 63;
+  const int zb = (tid >> 6) * RZ;
+  const int NX = a.NX, NZ = a.NZ, P = a.P, P2 = 2 * P;
   const size_t plane = (size_t)NX * NZ;
-  const size_t zs_plane = (size_t)2 * P * NX;
-  const int rows = ch.y + 16;
+  const size_t xsp = (size_t)NZ * P2, zsp = (size_t)P2 * NX;
+  const int x0 = (tile % a.tiles_x) * kTX, z0 = (tile / a.tiles_x) * a.tz + row0;
+  const int gx = x0 + lx;
+  const float* cur = a.cur + shot * plane;
+
   {
-    float lv[kZStage], cv[kZStage], zi[kZStage];
+    float lx_[KQX], cx_[KQX], zx_[HX ? KQX : 1];
 #pragma unroll
-    for (int k = 0; k < kZStage; ++k) {
-      const int r = w + 4 * k, gz = ch.x - 8 + r;
-      const bool ok = col_ok && r < rows && gz >= 0 && gz < NZ;
-      const size_t kk = ok ? (size_t)gz * NX + gx : 0;
-      const int row = ok ? zstrip_row(gz, NZ, P) : -1;
-      lv[k] = ok ? a.cur[shot * plane + kk] : 0.0f;
-      cv[k] = ok ? a.Cs[kk] : 0.0f;
-      zi[k] = row >= 0 ? a.zez_in[shot * zs_plane + (size_t)row * NX + gx] : 0.0f;
+    for (int k = 0; k < KQX; ++k) {
+      const int e = tid + k * kThreads;
+      const int r = e / BW, c = e - (e / BW) * BW;
+      const int gz = z0 + r, gxx = x0 - hx + c;
+      const bool ok = e < NQX && gz < NZ && gxx >= 0 && gxx < NX;
+      const size_t idx = ok ? (size_t)gz * NX + gxx : 0;
+      lx_[k] = ok ? cur[idx] : 0.0f;
+      cx_[k] = ok ? a.Cs[idx] : 0.0f;
+      if constexpr (HX) {
+        const int col = ok ? xstrip_col(gxx, NX, P) : -1;
+        zx_[k] = col >= 0 ? a.zex_in[shot * xsp + (size_t)gz * P2 + col] : 0.0f;
+      }
+    }
+    float lz_[KQZ], cz_[KQZ], zz_[HZ ? KQZ : 1];
+#pragma unroll
+    for (int k = 0; k < KQZ; ++k) {
+      const int e = tid + k * kThreads;
+      const int r = e >> 6, c = e & 63;
+      const int gz = z0 - hz + r, gxx = x0 + c;
+      const bool ok = e < NQZ && gxx < NX && gz >= 0 && gz < NZ;
+      const size_t idx = ok ? (size_t)gz * NX + gxx : 0;
+      lz_[k] = ok ? cur[idx] : 0.0f;
+      cz_[k] = ok ? a.Cs[idx] : 0.0f;
+      if constexpr (HZ) {
+        const int row = ok ? zstrip_row(gz, NZ, P) : -1;
+        zz_[k] = row >= 0 ? a.zez_in[shot * zsp + (size_t)row * NX + gxx] : 0.0f;
+      }
     }
 #pragma unroll
-    for (int k = 0; k < kZStage; ++k) {
-      const int r = w + 4 * k, gz = ch.x - 8 + r;
-      const bool ok = col_ok && r < rows && gz >= 0 && gz < NZ;
-      const int row = ok ? zstrip_row(gz, NZ, P) : -1;
-      float q = cv[k] * lv[k], sv = 0.0f;
-      if (row >= 0) {
-        const float zb = zi[k] + q;
-        sv = a.az[gz] * zb;
-        q = q + sv;
-        if (r >= 8 && r < 8 + ch.y) a.zez_out[shot * zs_plane + (size_t)row * NX + gx] = a.bz[gz] * zb;
+    for (int k = 0; k < KQX; ++k) {
+      const int e = tid + k * kThreads;
+      if (e >= NQX) break;
+      float q = cx_[k] * lx_[k];
+      if constexpr (HX) {
+        const int r = e / BW, c = e - (e / BW) * BW;
+        const int gz = z0 + r, gxx = x0 - hx + c;
+        const int col = (gz < NZ && gxx >= 0 && gxx < NX) ? xstrip_col(gxx, NX, P) : -1;
+        if (col >= 0) {
+          const float zbar = zx_[k] + q;
+          q = q + a.ax[gxx] * zbar;
+          if (c >= hx && c < hx + kTX)
+            a.zex_out[shot * xsp + (size_t)gz * P2 + col] = a.bx[gxx] * zbar;
+        }
       }
-      sQ[r * kTX + c] = q;
-      sS[r * kTX + c] = sv;
+      sqx[e] = q;
+    }
+#pragma unroll
+    for (int k = 0; k < KQZ; ++k) {
+      const int e = tid + k * kThreads;
+      if (e >= NQZ) break;
+      float q = cz_[k] * lz_[k];
+      if constexpr (HZ) {
+        const int r = e >> 6, c = e & 63;
+        const int gz = z0 - hz + r, gxx = x0 + c;
+        const int row = (gxx < NX && gz >= 0 && gz < NZ) ? zstrip_row(gz, NZ, P) : -1;
+        if (row >= 0) {
+          const float zbar = zz_[k] + q;
+          q = q + a.az[gz] * zbar;
+          if (r >= hz && r < hz + TZ)
+            a.zez_out[shot * zsp + (size_t)row * NX + gxx] = a.bz[gz] * zbar;
+        }
+      }
+      sqz[e] = q;
+    }
+  }
+  // Psi^{in} of the halo rings and the per-cell operands
+  float ox[HX ? KTX : 1], oz[HZ ? KTZ : 1];
+  if constexpr (HX) {
+#pragma unroll
+    for (int k = 0; k < KTX; ++k) {
+      const int e = tid + k * kThreads;
+      const int r = e / XW, c = e - (e / XW) * XW;
+      const int gz = z0 + r, gxx = x0 - 4 + c;
+      const int col = (e < NTX && gz < NZ && gxx >= 0 && gxx < NX) ? xstrip_col(gxx, NX, P) : -1;
+      ox[k] = col >= 0 ? a.psx_in[shot * xsp + (size_t)gz * P2 + col] : 0.0f;
+    }
+  }
+  if constexpr (HZ) {
+#pragma unroll
+    for (int k = 0; k < KTZ; ++k) {
+      const int e = tid + k * kThreads;
+      const int r = e >> 6, c = e & 63;
+      const int gz = z0 - 4 + r, gxx = x0 + c;
+      const int row = (e < NTZ && gxx < NX && gz >= 0 && gz < NZ) ? zstrip_row(gz, NZ, P) : -1;
+      oz[k] = row >= 0 ? a.psz_in[shot * zsp + (size_t)row * NX + gxx] : 0.0f;
+    }
+  }
+  float p1[RZ], pp[RZ], bb[RZ], gg[RZ];
+#pragma unroll
+  for (int r = 0; r < RZ; ++r) {
+    const int gz = z0 + zb + r;
+    p1[r] = pp[r] = bb[r] = gg[r] = 0.0f;
+    if (gx < NX && gz < NZ) {
+      const size_t gi = shot * plane + (size_t)gz * NX + gx;
+      p1[r] = a.cur[gi];
+      pp[r] = a.prev[gi];
+      bb[r] = a.B_in[gi];
+      if (!a.g_init) gg[r] = a.g[gi];
     }
   }
   __syncthreads();
-  {
-    float pin[kZPsi];
+
+  if constexpr (HX) {
 #pragma unroll
-    for (int k = 0; k < kZPsi; ++k) {
-      const int r = 4 + w + 4 * k, gz = ch.x - 8 + r;
-      const int row = (col_ok && r < rows - 4 && gz >= 0 && gz < NZ) ? zstrip_row(gz, NZ, P) : -1;
-      pin[k] = row >= 0 ? a.psz_in[shot * zs_plane + (size_t)row * NX + gx] : 0.0f;
+    for (int k = 0; k < KTX; ++k) {
+      const int e = tid + k * kThreads;
+      if (e >= NTX) break;
+      const int r = e / XW, c = e - (e / XW) * XW;
+      const int gz = z0 + r, gxx = x0 - 4 + c;
+      const int col = (gz < NZ && gxx >= 0 && gxx < NX) ? xstrip_col(gxx, NX, P) : -1;
+      float t = 0.0f;
+      if (col >= 0) {
+        const float psb = ox[k] - d1s(&sqx[r * BW + c + hx - 4], 1);
+        t = a.ax[gxx] * psb;
+        if (c >= 4 && c < 4 + kTX) a.psx_out[shot * xsp + (size_t)gz * P2 + col] = a.bx[gxx] * psb;
+      }
+      stx[e] = t;
     }
+  }
+  if constexpr (HZ) {
 #pragma unroll
-    for (int k = 0; k < kZPsi; ++k) {
-      const int r = 4 + w + 4 * k, gz = ch.x - 8 + r;
-      const int row = (col_ok && r < rows - 4 && gz >= 0 && gz < NZ) ? zstrip_row(gz, NZ, P) : -1;
+    for (int k = 0; k < KTZ; ++k) {
+      const int e = tid + k * kThreads;
+      if (e >= NTZ) break;
+      const int r = e >> 6, c = e & 63;
+      const int gz = z0 - 4 + r, gxx = x0 + c;
+      const int row = (gxx < NX && gz >= 0 && gz < NZ) ? zstrip_row(gz, NZ, P) : -1;
       float t = 0.0f;
       if (row >= 0) {
-        const float psb = pin[k] - d1s(&sQ[r * kTX + c], kTX);
+        const float psb = oz[k] - d1s(&sqz[(r + hz - 4) * kTX + c], kTX);
         t = a.az[gz] * psb;
-        if (r >= 8 && r < 8 + ch.y) a.psz_out[shot * zs_plane + (size_t)row * NX + gx] = a.bz[gz] * psb;
+        if (r >= 4 && r < 4 + TZ) a.psz_out[shot * zsp + (size_t)row * NX + gxx] = a.bz[gz] * psb;
       }
-      sT[r * kTX + c] = t;
+      stz[e] = t;
     }
   }
-  __syncthreads();
-  float pp[kZOut];
+  if constexpr (HX || HZ) __syncthreads();
+
+  float out[RZ];
 #pragma unroll
-  for (int k = 0; k < kZOut; ++k) {
-    const int r = 8 + w + 4 * k, gz = ch.x - 8 + r;
-    const bool ok = col_ok && r < 8 + ch.y && gz < NZ;
-    pp[k] = ok ? a.prev_adj[shot * plane + (size_t)gz * NX + gx] : 0.0f;
+  for (int r = 0; r < RZ; ++r) {
+    const float dxx = d2s(&sqx[(zb + r) * BW + lx + hx], 1);
+    const float dzz = d2s(&sqz[(zb + r + hz) * kTX + lx], kTX);
+    float tx = 0.0f, tz = 0.0f;
+    if constexpr (HX) tx = d1s(&stx[(zb + r) * XW + lx + 4], 1);
+    if constexpr (HZ) tz = d1s(&stz[(zb + r + 4) * kTX + lx], kTX);
+    const int gz = z0 + zb + r;
+    float lam = 0.0f;
+    if (gx < NX && gz < NZ) {
+      const size_t gi = shot * plane + (size_t)gz * NX + gx;
+      const float gb = p1[r] * bb[r];
+      a.g[gi] = a.g_init ? gb : gg[r] + gb;
+      lam = ((2.0f * p1[r] - pp[r]) + dxx) + dzz;
+      if constexpr (HX) lam = lam - tx;
+      if constexpr (HZ) lam = lam - tz;
+    }
+    out[r] = lam;
   }
-#pragma unroll
-  for (int k = 0; k < kZOut; ++k) {
-    const int r = 8 + w + 4 * k, gz = ch.x - 8 + r;
-    if (!(col_ok && r < 8 + ch.y && gz < NZ)) continue;
-    const float E = d2s(&sS[r * kTX + c], kTX) - d1s(&sT[r * kTX + c], kTX);
-    a.prev_adj[shot * plane + (size_t)gz * NX + gx] = pp[k] - E;
-  }
+  adj_store<RZ>(a, shot, tile, row0, x0, z0, out, sqz);
 }
 
 // ---------------------------------------------------------------------------
-// Kernel entry points: one plan (block coordinates from the launch grid) or a
-// batch of plans of different shapes in one launch (the flat block index is
-// split by the per-plan block counts of this launch).
+// Kernel entry points: one plan (1-D grid over kind tiles x shots) or a batch
+// of plans of different shapes in one launch (the flat block index is split by
+// the per-plan block counts of this launch).
 // ---------------------------------------------------------------------------
-template <int RZ>
-__global__ __launch_bounds__(kThreads) void ac_fwd_main(AcStep a) {
-  ac_fwd_main_body<RZ>(a, blockIdx.x, blockIdx.y, blockIdx.z);
-}
-template <int RZ>
-__global__ __launch_bounds__(kThreads) void ac_adj_main(AcStep a) {
-  ac_adj_main_body<RZ>(a, blockIdx.x, blockIdx.y, blockIdx.z);
-}
-__global__ __launch_bounds__(kThreads) void ac_fwd_xband(AcStep a) {
-  ac_fwd_xband_body(a, blockIdx.x, blockIdx.y, blockIdx.z);
-}
-__global__ __launch_bounds__(kThreads) void ac_adj_xband(AcStep a) {
-  ac_adj_xband_body(a, blockIdx.x, blockIdx.y, blockIdx.z);
-}
-__global__ __launch_bounds__(kThreads) void ac_fwd_zband(AcStep a) {
-  ac_fwd_zband_body(a, blockIdx.x, blockIdx.y, blockIdx.z);
-}
-__global__ __launch_bounds__(kThreads) void ac_adj_zband(AcStep a) {
-  ac_adj_zband_body(a, blockIdx.x, blockIdx.y, blockIdx.z);
+template <int RZ, bool kAdj>
+__device__ __forceinline__ void run_interior(const AcStep& a, int l) {
+  const int tile = interior_tile(a, l % a.n_int);
+  const int shot = l / a.n_int;
+  if (kAdj)
+    ac_adj_int_body<RZ>(a, tile, shot);
+  else
+    ac_fwd_int_body<RZ>(a, tile, shot);
 }
 
-// plan index and the block coordinates inside that plan's grid
-struct BatchCoord {
-  int p, x, y, z;
-};
-__device__ __forceinline__ BatchCoord batch_coord(const AcBatch& b) {
-  const int f = blockIdx.x;
+// Frame pieces: kZ selects the z frame (its pieces meet z strips only) or the
+// x frame (general body, specialised on the strips near the piece).
+template <int RZ, bool kAdj, bool kZ>
+__device__ __forceinline__ void run_frame(const AcStep& a, int l, float* lds) {
+  const int nk = (kZ ? a.n_zf : a.n_xf) * a.nsub;
+  const int t = l % nk, shot = l / nk;
+  const int tile = kZ ? zframe_tile(a, t / a.nsub) : xframe_tile(a, t / a.nsub);
+  const int row0 = (t % a.nsub) * 4 * RZ;
+  if (kZ) {
+    if (kAdj)
+      ac_adj_pml_body<RZ, false, true>(a, tile, shot, row0, lds);
+    else
+      ac_fwd_pml_body<RZ, false, true>(a, tile, shot, row0, lds);
+    return;
+  }
+  const int x0 = (tile % a.tiles_x) * kTX, z0 = (tile / a.tiles_x) * a.tz + row0;
+  const bool hx = near_xstrip(x0, a.NX, a.P), hz = near_zstrip(z0, 4 * RZ, a.NZ, a.P);
+  if (kAdj) {
+    if (hx && hz)
+      ac_adj_pml_body<RZ, true, true>(a, tile, shot, row0, lds);
+    else if (hx)
+      ac_adj_pml_body<RZ, true, false>(a, tile, shot, row0, lds);
+    else if (hz)
+      ac_adj_pml_body<RZ, false, true>(a, tile, shot, row0, lds);
+    else
+      ac_adj_pml_body<RZ, false, false>(a, tile, shot, row0, lds);
+  } else {
+    if (hx && hz)
+      ac_fwd_pml_body<RZ, true, true>(a, tile, shot, row0, lds);
+    else if (hx)
+      ac_fwd_pml_body<RZ, true, false>(a, tile, shot, row0, lds);
+    else if (hz)
+      ac_fwd_pml_body<RZ, false, true>(a, tile, shot, row0, lds);
+    else
+      ac_fwd_pml_body<RZ, false, false>(a, tile, shot, row0, lds);
+  }
+}
+
+template <int RZ, bool kAdj>
+__global__ __launch_bounds__(kThreads) void ac_int_kernel(AcStep a) {
+  run_interior<RZ, kAdj>(a, xcd_spread(blockIdx.x, gridDim.x));
+}
+
+template <int RZ, bool kAdj, bool kZ>
+__global__ __launch_bounds__(kThreads) void ac_pml_kernel(AcStep a) {
+  __shared__ float lds[PmlLds<RZ>::get(kAdj, kZ)];
+  run_frame<RZ, kAdj, kZ>(a, xcd_spread(blockIdx.x, gridDim.x), lds);
+}
+
+// plan of flat block f in a batched launch, and f's index inside that plan
+__device__ __forceinline__ int batch_plan(const AcBatch& b, int& f) {
   int p = 0;
   while (p + 1 < b.nplans && f >= b.base[p + 1]) ++p;
-  const int l = f - b.base[p];
-  BatchCoord c;
-  c.p = p;
-  c.x = l % b.gx[p];
-  c.y = (l / b.gx[p]) % b.gy[p];
-  c.z = l / (b.gx[p] * b.gy[p]);
-  return c;
+  f -= b.base[p];
+  return p;
 }
 
-template <int RZ>
-__global__ __launch_bounds__(kThreads) void ac_fwd_main_batch(AcBatch b) {
-  const BatchCoord c = batch_coord(b);
-  ac_fwd_main_body<RZ>(b.step[c.p], c.x, c.y, c.z);
+template <int RZ, bool kAdj>
+__global__ __launch_bounds__(kThreads) void ac_int_batch_kernel(AcBatch b) {
+  int f = xcd_spread(blockIdx.x, gridDim.x);
+  const int p = batch_plan(b, f);
+  run_interior<RZ, kAdj>(b.step[p], f);
 }
-template <int RZ>
-__global__ __launch_bounds__(kThreads) void ac_adj_main_batch(AcBatch b) {
-  const BatchCoord c = batch_coord(b);
-  ac_adj_main_body<RZ>(b.step[c.p], c.x, c.y, c.z);
-}
-__global__ __launch_bounds__(kThreads) void ac_fwd_xband_batch(AcBatch b) {
-  const BatchCoord c = batch_coord(b);
-  ac_fwd_xband_body(b.step[c.p], c.x, c.y, c.z);
-}
-__global__ __launch_bounds__(kThreads) void ac_adj_xband_batch(AcBatch b) {
-  const BatchCoord c = batch_coord(b);
-  ac_adj_xband_body(b.step[c.p], c.x, c.y, c.z);
-}
-__global__ __launch_bounds__(kThreads) void ac_fwd_zband_batch(AcBatch b) {
-  const BatchCoord c = batch_coord(b);
-  ac_fwd_zband_body(b.step[c.p], c.x, c.y, c.z);
-}
-__global__ __launch_bounds__(kThreads) void ac_adj_zband_batch(AcBatch b) {
-  const BatchCoord c = batch_coord(b);
-  ac_adj_zband_body(b.step[c.p], c.x, c.y, c.z);
+
+template <int RZ, bool kAdj, bool kZ>
+__global__ __launch_bounds__(kThreads) void ac_pml_batch_kernel(AcBatch b) {
+  __shared__ float lds[PmlLds<RZ>::get(kAdj, kZ)];
+  int f = xcd_spread(blockIdx.x, gridDim.x);
+  const int p = batch_plan(b, f);
+  run_frame<RZ, kAdj, kZ>(b.step[p], f, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -757,88 +912,90 @@ __global__ void ac_finish_kernel(const double* tot, const float* vpad, float* gr
   grad[(size_t)jj * nx + ii] = (float)acc;
 }
 
-// ev (optional): start/stop event pairs recorded around the main launch
-// (ev[0], ev[1]) and the two band launches (ev[2], ev[3]).
-template <int RZ, bool kAdj>
-int launch_step(const AcStep& a, hipStream_t s, hipEvent_t* ev) {
-  if (a.n_xchunks > 0 || a.n_zchunks > 0) {
+template <bool kAdj>
+void launch_interior(const AcStep& a, int rz, dim3 g, hipStream_t s) {
+  switch (rz) {
+    case 1: hipLaunchKernelGGL((ac_int_kernel<1, kAdj>), g, dim3(kThreads), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((ac_int_kernel<2, kAdj>), g, dim3(kThreads), 0, s, a); break;
+    case 4: hipLaunchKernelGGL((ac_int_kernel<4, kAdj>), g, dim3(kThreads), 0, s, a); break;
+    default: hipLaunchKernelGGL((ac_int_kernel<8, kAdj>), g, dim3(kThreads), 0, s, a); break;
+  }
+}
+
+template <bool kAdj, bool kZ>
+void launch_frame(const AcStep& a, int prz, dim3 g, hipStream_t s) {
+  switch (prz) {
+    case 1: hipLaunchKernelGGL((ac_pml_kernel<1, kAdj, kZ>), g, dim3(kThreads), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((ac_pml_kernel<2, kAdj, kZ>), g, dim3(kThreads), 0, s, a); break;
+    case 4: hipLaunchKernelGGL((ac_pml_kernel<4, kAdj, kZ>), g, dim3(kThreads), 0, s, a); break;
+    default: hipLaunchKernelGGL((ac_pml_kernel<8, kAdj, kZ>), g, dim3(kThreads), 0, s, a); break;
+  }
+}
+
+template <bool kAdj>
+void launch_interior_batch(const AcBatch& b, int rz, dim3 g, hipStream_t s) {
+  switch (rz) {
+    case 1: hipLaunchKernelGGL((ac_int_batch_kernel<1, kAdj>), g, dim3(kThreads), 0, s, b); break;
+    case 2: hipLaunchKernelGGL((ac_int_batch_kernel<2, kAdj>), g, dim3(kThreads), 0, s, b); break;
+    case 4: hipLaunchKernelGGL((ac_int_batch_kernel<4, kAdj>), g, dim3(kThreads), 0, s, b); break;
+    default: hipLaunchKernelGGL((ac_int_batch_kernel<8, kAdj>), g, dim3(kThreads), 0, s, b); break;
+  }
+}
+
+template <bool kAdj, bool kZ>
+void launch_frame_batch(const AcBatch& b, int prz, dim3 g, hipStream_t s) {
+  switch (prz) {
+    case 1: hipLaunchKernelGGL((ac_pml_batch_kernel<1, kAdj, kZ>), g, dim3(kThreads), 0, s, b); break;
+    case 2: hipLaunchKernelGGL((ac_pml_batch_kernel<2, kAdj, kZ>), g, dim3(kThreads), 0, s, b); break;
+    case 4: hipLaunchKernelGGL((ac_pml_batch_kernel<4, kAdj, kZ>), g, dim3(kThreads), 0, s, b); break;
+    default: hipLaunchKernelGGL((ac_pml_batch_kernel<8, kAdj, kZ>), g, dim3(kThreads), 0, s, b); break;
+  }
+}
+
+// ev (optional): start/stop event pairs recorded around the interior launch
+// (ev[0], ev[1]) and the two frame launches (ev[2], ev[3]). a.nsub = a.tz / (4 prz).
+template <bool kAdj>
+int launch_step(const AcStep& a, int rz, int prz, hipStream_t s, hipEvent_t* ev) {
+  if (a.n_xf + a.n_zf > 0) {
     if (ev) SWEEP_HIP(hipEventRecord(ev[2], s));
-    if (a.n_xchunks > 0) {
-      const dim3 g(a.n_xchunks, (a.NZ + 4 * kXRows - 1) / (4 * kXRows), a.nshots);
-      if (kAdj)
-        hipLaunchKernelGGL(ac_adj_xband, g, dim3(kThreads), 0, s, a);
-      else
-        hipLaunchKernelGGL(ac_fwd_xband, g, dim3(kThreads), 0, s, a);
-    }
-    if (a.n_zchunks > 0) {
-      const dim3 g((a.NX + kTX - 1) / kTX, a.n_zchunks, a.nshots);
-      if (kAdj)
-        hipLaunchKernelGGL(ac_adj_zband, g, dim3(kThreads), 0, s, a);
-      else
-        hipLaunchKernelGGL(ac_fwd_zband, g, dim3(kThreads), 0, s, a);
-    }
+    if (a.n_zf > 0) launch_frame<kAdj, true>(a, prz, dim3(a.n_zf * a.nsub * a.nshots), s);
+    if (a.n_xf > 0) launch_frame<kAdj, false>(a, prz, dim3(a.n_xf * a.nsub * a.nshots), s);
     if (ev) SWEEP_HIP(hipEventRecord(ev[3], s));
   }
-  if (ev) SWEEP_HIP(hipEventRecord(ev[0], s));
-  const dim3 g(a.ntiles, a.nshots);
-  if (kAdj)
-    hipLaunchKernelGGL(ac_adj_main<RZ>, g, dim3(kThreads), 0, s, a);
-  else
-    hipLaunchKernelGGL(ac_fwd_main<RZ>, g, dim3(kThreads), 0, s, a);
-  if (ev) SWEEP_HIP(hipEventRecord(ev[1], s));
+  if (a.n_int > 0) {
+    if (ev) SWEEP_HIP(hipEventRecord(ev[0], s));
+    launch_interior<kAdj>(a, rz, dim3(a.n_int * a.nshots), s);
+    if (ev) SWEEP_HIP(hipEventRecord(ev[1], s));
+  }
   SWEEP_HIP(hipGetLastError());
   return SWEEP_OK;
 }
 
-// One batched step over the active plans `steps[0..n)` (all with the same rz).
-template <int RZ, bool kAdj>
-int launch_step_batch(const AcStep* steps, int n, hipStream_t s) {
+// One batched step over the active plans `steps[0..n)` (all with the same rz and
+// prz): one launch per tile set (z frame, x frame, interior) for all plans.
+template <bool kAdj>
+int launch_step_batch(const AcStep* steps, int n, int rz, int prz, hipStream_t s) {
   AcBatch b;
-  // band kernels: x band, then z band, then the main kernel (as for one plan)
   for (int phase = 0; phase < 3; ++phase) {
     b.nplans = 0;
     b.base[0] = 0;
     for (int q = 0; q < n; ++q) {
       const AcStep& a = steps[q];
-      int gx, gy, gz;
-      if (phase == 0) {
-        gx = a.n_xchunks;
-        gy = (a.NZ + 4 * kXRows - 1) / (4 * kXRows);
-        gz = a.nshots;
-      } else if (phase == 1) {
-        gx = (a.NX + kTX - 1) / kTX;
-        gy = a.n_zchunks;
-        gz = a.nshots;
-      } else {
-        gx = a.ntiles;
-        gy = a.nshots;
-        gz = 1;
-      }
-      if (gx <= 0 || gy <= 0 || gz <= 0) continue;
+      const int blocks =
+          (phase == 0 ? a.n_zf * a.nsub : phase == 1 ? a.n_xf * a.nsub : a.n_int) * a.nshots;
+      if (blocks <= 0) continue;
       const int k = b.nplans++;
       b.step[k] = a;
-      b.gx[k] = gx;
-      b.gy[k] = gy;
-      b.base[k + 1] = b.base[k] + gx * gy * gz;
+      b.base[k + 1] = b.base[k] + blocks;
     }
     if (b.nplans == 0) continue;
     const dim3 g(b.base[b.nplans]);
-    if (phase == 0) {
-      if (kAdj)
-        hipLaunchKernelGGL(ac_adj_xband_batch, g, dim3(kThreads), 0, s, b);
-      else
-        hipLaunchKernelGGL(ac_fwd_xband_batch, g, dim3(kThreads), 0, s, b);
-    } else if (phase == 1) {
-      if (kAdj)
-        hipLaunchKernelGGL(ac_adj_zband_batch, g, dim3(kThreads), 0, s, b);
-      else
-        hipLaunchKernelGGL(ac_fwd_zband_batch, g, dim3(kThreads), 0, s, b);
-    } else {
-      if (kAdj)
-        hipLaunchKernelGGL(ac_adj_main_batch<RZ>, g, dim3(kThreads), 0, s, b);
-      else
-        hipLaunchKernelGGL(ac_fwd_main_batch<RZ>, g, dim3(kThreads), 0, s, b);
-    }
+    if (phase == 0)
+      launch_frame_batch<kAdj, true>(b, prz, g, s);
+    else if (phase == 1)
+      launch_frame_batch<kAdj, false>(b, prz, g, s);
+    else
+      launch_interior_batch<kAdj>(b, rz, g, s);
   }
   SWEEP_HIP(hipGetLastError());
   return SWEEP_OK;
@@ -859,26 +1016,25 @@ int ac_launch_prep(const float* v, float* vpad, float* Cs, float* ax, float* bx,
   return SWEEP_OK;
 }
 
-int ac_launch_fwd(const AcStep& a, int rz, hipStream_t s, hipEvent_t* ev) {
-  switch (rz) {
-    case 1: return launch_step<1, false>(a, s, ev);
-    case 2: return launch_step<2, false>(a, s, ev);
-    case 4: return launch_step<4, false>(a, s, ev);
-    case 8: return launch_step<8, false>(a, s, ev);
-  }
-  set_error("unsupported rz");
-  return SWEEP_EINVAL;
+static bool valid_rz(int rz, int prz) {
+  return (rz == 1 || rz == 2 || rz == 4 || rz == 8) &&
+         (prz == 1 || prz == 2 || prz == 4 || prz == 8) && prz <= rz;
 }
 
-int ac_launch_adj(const AcStep& a, int rz, hipStream_t s, hipEvent_t* ev) {
-  switch (rz) {
-    case 1: return launch_step<1, true>(a, s, ev);
-    case 2: return launch_step<2, true>(a, s, ev);
-    case 4: return launch_step<4, true>(a, s, ev);
-    case 8: return launch_step<8, true>(a, s, ev);
+int ac_launch_fwd(const AcStep& a, int rz, int prz, hipStream_t s, hipEvent_t* ev) {
+  if (!valid_rz(rz, prz)) {
+    set_error("unsupported rz / pml_rz");
+    return SWEEP_EINVAL;
   }
-  set_error("unsupported rz");
-  return SWEEP_EINVAL;
+  return launch_step<false>(a, rz, prz, s, ev);
+}
+
+int ac_launch_adj(const AcStep& a, int rz, int prz, hipStream_t s, hipEvent_t* ev) {
+  if (!valid_rz(rz, prz)) {
+    set_error("unsupported rz / pml_rz");
+    return SWEEP_EINVAL;
+  }
+  return launch_step<true>(a, rz, prz, s, ev);
 }
 
 int ac_launch_adj_init(float* lam_cur, float* lam_prev, size_t plane_elems, float* aux,
@@ -915,26 +1071,20 @@ int ac_launch_finish(const double* tot, const float* vpad, float* grad, int nx, 
 
 namespace sweep {
 
-int ac_launch_fwd_batch(const AcStep* steps, int n, int rz, hipStream_t s) {
-  switch (rz) {
-    case 1: return launch_step_batch<1, false>(steps, n, s);
-    case 2: return launch_step_batch<2, false>(steps, n, s);
-    case 4: return launch_step_batch<4, false>(steps, n, s);
-    case 8: return launch_step_batch<8, false>(steps, n, s);
+int ac_launch_fwd_batch(const AcStep* steps, int n, int rz, int prz, hipStream_t s) {
+  if (!valid_rz(rz, prz)) {
+    set_error("unsupported rz / pml_rz");
+    return SWEEP_EINVAL;
   }
-  set_error("unsupported rz");
-  return SWEEP_EINVAL;
+  return launch_step_batch<false>(steps, n, rz, prz, s);
 }
 
-int ac_launch_adj_batch(const AcStep* steps, int n, int rz, hipStream_t s) {
-  switch (rz) {
-    case 1: return launch_step_batch<1, true>(steps, n, s);
-    case 2: return launch_step_batch<2, true>(steps, n, s);
-    case 4: return launch_step_batch<4, true>(steps, n, s);
-    case 8: return launch_step_batch<8, true>(steps, n, s);
+int ac_launch_adj_batch(const AcStep* steps, int n, int rz, int prz, hipStream_t s) {
+  if (!valid_rz(rz, prz)) {
+    set_error("unsupported rz / pml_rz");
+    return SWEEP_EINVAL;
   }
-  set_error("unsupported rz");
-  return SWEEP_EINVAL;
+  return launch_step_batch<true>(steps, n, rz, prz, s);
 }
 
 }  // namespace sweep

@@ -63,30 +63,26 @@ struct Carver {
 
 }  // namespace
 
-// Splits [lo, hi) into pieces of at most 48 cells.
-static void add_chunks(std::vector<int2>& v, int lo, int hi) {
-  for (int c = lo; c < hi; c += 48) v.push_back(make_int2(c, std::min(48, hi - c)));
-}
-
 void ac_build_tiling(sweep_plan* p) {
   const int TZ = 4 * p->tune.rz;
   p->TZ = TZ;
   p->tiles_x = (p->NX + kTX - 1) / kTX;
   p->tiles_z = (p->NZ + TZ - 1) / TZ;
   p->ntiles = p->tiles_x * p->tiles_z;
-  const int P = p->P;
-  // C-PML bands: cells within P+4 of an edge along each axis (the memory
-  // variables live in the outer P cells; their first derivative reaches 4 more)
-  p->xchunks.clear();
-  p->zchunks.clear();
-  if (P > 0) {
-    const int xl = std::min(P + 4, p->NX), xr = std::max(p->NX - P - 4, xl);
-    add_chunks(p->xchunks, 0, xl);
-    add_chunks(p->xchunks, xr, p->NX);
-    const int zl = std::min(P + 4, p->NZ), zr = std::max(p->NZ - P - 4, zl);
-    add_chunks(p->zchunks, 0, zl);
-    add_chunks(p->zchunks, zr, p->NZ);
-  }
+  // Interior tiles: whole tiles with no cell within P+4 of an edge (the memory
+  // variables live in the outer P cells; their first derivative reaches 4 more).
+  const int m = p->P > 0 ? p->P + 4 : 0;
+  int itx0 = (m + kTX - 1) / kTX, itx1 = std::max(p->NX - m, 0) / kTX;
+  int itz0 = (m + TZ - 1) / TZ, itz1 = std::max(p->NZ - m, 0) / TZ;
+  if (itx1 <= itx0 || itz1 <= itz0) itx0 = itx1 = itz0 = itz1 = 0;
+  p->itx0 = itx0;
+  p->itx1 = itx1;
+  p->itz0 = itz0;
+  p->itz1 = itz1;
+  p->n_int = (itx1 - itx0) * (itz1 - itz0);
+  p->n_pml = p->ntiles - p->n_int;
+  p->n_xf = (itx0 + p->tiles_x - itx1) * p->tiles_z;
+  p->n_zf = (itx1 - itx0) * (itz0 + p->tiles_z - itz1);
   // receiver CSR over (shot, tile), entries sorted by (local cell, receiver)
   const int ns = p->pb.nshots, nr = p->pb.nrec;
   p->rec_off.assign((size_t)ns * p->ntiles + 1, 0);
@@ -136,8 +132,6 @@ void ac_layout(const sweep_plan* p, AcLayout& L) {
   L.rec_cell = c.take(ns * nr * sizeof(int));
   L.rec_off = c.take((ns * ac_max_tiles(p) + 1) * sizeof(int));
   L.rec_ent = c.take(std::max<size_t>(ns * nr, 1) * sizeof(int2));
-  L.xch = c.take(((size_t)p->NX / 48 + 4) * sizeof(int2));
-  L.zch = c.take(((size_t)p->NZ / 48 + 4) * sizeof(int2));
   L.pA = c.take(ns * plane * f);
   L.pB = c.take(ns * plane * f);
   L.aux[0] = c.take(L.aux_elems * f);
@@ -226,10 +220,16 @@ AcStep ac_base(const sweep_plan* p, void* work, const AcLayout& L) {
   a.src_cell = at<int>(work, L.src_cell);
   a.rec_off = at<int>(work, L.rec_off);
   a.rec_ent = at<int2>(work, L.rec_ent);
-  a.xchunks = at<int2>(work, L.xch);
-  a.n_xchunks = (int)p->xchunks.size();
-  a.zchunks = at<int2>(work, L.zch);
-  a.n_zchunks = (int)p->zchunks.size();
+  a.itx0 = p->itx0;
+  a.itx1 = p->itx1;
+  a.itz0 = p->itz0;
+  a.itz1 = p->itz1;
+  a.n_int = p->n_int;
+  a.n_pml = p->n_pml;
+  a.n_xf = p->n_xf;
+  a.n_zf = p->n_zf;
+  a.tz = p->TZ;
+  a.nsub = p->tune.rz / p->tune.pml_rz;
   return a;
 }
 
@@ -244,12 +244,6 @@ int ac_upload_geometry(sweep_plan* p, void* work, const AcLayout& L, hipStream_t
   }
   SWEEP_HIP(hipMemcpyAsync(at<int>(work, L.rec_off), p->rec_off.data(),
                            p->rec_off.size() * sizeof(int), hipMemcpyHostToDevice, s));
-  if (!p->xchunks.empty())
-    SWEEP_HIP(hipMemcpyAsync(at<int2>(work, L.xch), p->xchunks.data(),
-                             p->xchunks.size() * sizeof(int2), hipMemcpyHostToDevice, s));
-  if (!p->zchunks.empty())
-    SWEEP_HIP(hipMemcpyAsync(at<int2>(work, L.zch), p->zchunks.data(),
-                             p->zchunks.size() * sizeof(int2), hipMemcpyHostToDevice, s));
   return SWEEP_OK;
 }
 
@@ -290,7 +284,6 @@ int ac_fwd_step_args(sweep_plan* p, void* work, const AcLayout& L, int n, float*
   a.cur = cur;
   a.prev = prev;
   a.next = prev;
-  a.prev_adj = prev;
   set_aux(a, aux_ptrs(aux[n % 2], L, ns), aux_ptrs(aux[(n + 1) % 2], L, ns));
   const int k = p->ckpt;
   if (save && n % k == 0) {
@@ -317,7 +310,7 @@ int ac_forward_enqueue(sweep_plan* p, const float* model, const float* wavelet, 
   for (int n = 0; n < p->pb.nt; ++n) {
     AcStep a;
     if ((rc = ac_fwd_step_args(p, work, L, n, gathers, save, s, a))) return rc;
-    if ((rc = ac_launch_fwd(a, p->tune.rz, s, p->timer.take(kFwdMain, kFwdBand)))) return rc;
+    if ((rc = ac_launch_fwd(a, p->tune.rz, p->tune.pml_rz, s, p->timer.take(kFwdMain, kFwdBand)))) return rc;
   }
   return SWEEP_OK;
 }
@@ -359,7 +352,6 @@ AcStep ac_rec_step_args(sweep_plan* p, void* work, const AcLayout& L, int n, int
   a.cur = (m % 2 == 0) ? pB : pA;
   a.prev = prev;
   a.next = prev;
-  a.prev_adj = prev;
   set_aux(a, aux_ptrs(aux[m % 2], L, ns), aux_ptrs(aux[(m + 1) % 2], L, ns));
   a.B_out = at<float>(work, L.Bseg) + (size_t)m * ns * L.plane;
   return a;
@@ -380,7 +372,6 @@ AcStep ac_adj_step_args(sweep_plan* p, void* work, const AcLayout& L, const floa
   a.cur = (it % 2 == 0) ? lB : lA;
   a.prev = prev;
   a.next = prev;
-  a.prev_adj = prev;
   set_aux(a, aux_ptrs(adjaux[it % 2], L, ns), aux_ptrs(adjaux[(it + 1) % 2], L, ns));
   a.B_in = at<float>(work, L.Bseg) + (size_t)(n - n0) * ns * L.plane;
   a.g = at<float>(work, L.gpart);
@@ -410,11 +401,11 @@ int ac_backward_enqueue(sweep_plan* p, const float* resid, float* grad, void* wo
     if ((rc = ac_bwd_restore(p, work, L, sg, s))) return rc;
     for (int n = n0; n < n1; ++n) {
       const AcStep a = ac_rec_step_args(p, work, L, n, n - n0);
-      if ((rc = ac_launch_fwd(a, p->tune.rz, s, p->timer.take(kRecMain, kRecBand)))) return rc;
+      if ((rc = ac_launch_fwd(a, p->tune.rz, p->tune.pml_rz, s, p->timer.take(kRecMain, kRecBand)))) return rc;
     }
     for (int n = n1 - 1; n >= n0; --n) {
       const AcStep a = ac_adj_step_args(p, work, L, resid, n, n0, n1);
-      if ((rc = ac_launch_adj(a, p->tune.rz, s, p->timer.take(kAdjMain, kAdjBand)))) return rc;
+      if ((rc = ac_launch_adj(a, p->tune.rz, p->tune.pml_rz, s, p->timer.take(kAdjMain, kAdjBand)))) return rc;
     }
     if ((rc = ac_bwd_fold(p, work, L, s))) return rc;
   }
@@ -532,7 +523,7 @@ int batch_forward_enqueue(sweep_batch* b, const float* const* models, const floa
         return rc;
       ++cnt;
     }
-    if ((rc = ac_launch_fwd_batch(steps.data(), cnt, b->rz, s))) return rc;
+    if ((rc = ac_launch_fwd_batch(steps.data(), cnt, b->rz, b->prz, s))) return rc;
   }
   return SWEEP_OK;
 }
@@ -566,7 +557,7 @@ int batch_backward_enqueue(sweep_batch* b, const float* const* resids, float* co
       for (int q = 0; q < np; ++q)
         if (m < n1[q] - n0[q])
           steps[cnt++] = ac_rec_step_args(b->plans[q], at<char>(work, off[q]), L[q], n0[q] + m, m);
-      if ((rc = ac_launch_fwd_batch(steps.data(), cnt, b->rz, s))) return rc;
+      if ((rc = ac_launch_fwd_batch(steps.data(), cnt, b->rz, b->prz, s))) return rc;
     }
     for (int m = 0; m < lenmax; ++m) {
       int cnt = 0;
@@ -574,7 +565,7 @@ int batch_backward_enqueue(sweep_batch* b, const float* const* resids, float* co
         if (m < n1[q] - n0[q])
           steps[cnt++] = ac_adj_step_args(b->plans[q], at<char>(work, off[q]), L[q], resids[q],
                                           n1[q] - 1 - m, n0[q], n1[q]);
-      if ((rc = ac_launch_adj_batch(steps.data(), cnt, b->rz, s))) return rc;
+      if ((rc = ac_launch_adj_batch(steps.data(), cnt, b->rz, b->prz, s))) return rc;
     }
     for (int q = 0; q < np; ++q)
       if (n1[q] > n0[q] && (rc = ac_bwd_fold(b->plans[q], at<char>(work, off[q]), L[q], s)))
@@ -654,8 +645,8 @@ extern "C" int sweep_plan_create(const sweep_problem* pb, const int32_t* src_xz,
     }
     p->rec_cell[r] = (z + (pb->free_surface ? 0 : p->P)) * p->NX + x + p->P;
   }
-  p->tune.rz = 8;
-  p->tune.shots_per_block = 1;
+  p->tune.rz = 4;
+  p->tune.pml_rz = 4;
   p->tune.use_graph = 0;
   if (pb->physics == SWEEP_ACOUSTIC) {
     ac_build_tiling(p);
@@ -681,8 +672,10 @@ extern "C" int sweep_plan_set_tuning(sweep_plan* p, const sweep_tuning* t) {
     set_error("null argument");
     return SWEEP_EINVAL;
   }
-  if (!(t->rz == 1 || t->rz == 2 || t->rz == 4 || t->rz == 8) || t->shots_per_block != 1 ||
-      (t->use_graph != 0 && t->use_graph != 1)) {
+  const bool ok_rz = t->rz == 1 || t->rz == 2 || t->rz == 4 || t->rz == 8;
+  const bool ok_prz = (t->pml_rz == 1 || t->pml_rz == 2 || t->pml_rz == 4 || t->pml_rz == 8) &&
+                      t->pml_rz <= t->rz;
+  if (!ok_rz || !ok_prz || (t->use_graph != 0 && t->use_graph != 1)) {
     set_error("unsupported tuning");
     return SWEEP_EINVAL;
   }
@@ -722,6 +715,22 @@ extern "C" int sweep_plan_padded(const sweep_plan* p, int* NX, int* NZ) {
   }
   *NX = p->NX;
   *NZ = p->NZ;
+  return SWEEP_OK;
+}
+
+extern "C" int sweep_plan_tiles(const sweep_plan* p, int* interior_tiles, int* frame_tiles,
+                                int* tile_rows) {
+  if (!p || !interior_tiles || !frame_tiles || !tile_rows) {
+    set_error("null argument");
+    return SWEEP_EINVAL;
+  }
+  if (p->pb.physics != SWEEP_ACOUSTIC) {
+    set_error("sweep_plan_tiles: acoustic plans only");
+    return SWEEP_EINVAL;
+  }
+  *interior_tiles = p->n_int;
+  *frame_tiles = p->n_pml;
+  *tile_rows = p->TZ;
   return SWEEP_OK;
 }
 
@@ -793,8 +802,8 @@ extern "C" int sweep_batch_create(sweep_plan* const* plans, int nplans, sweep_ba
       set_error("sweep_batch_create: batches hold acoustic plans");
       return SWEEP_EINVAL;
     }
-    if (plans[q]->tune.rz != plans[0]->tune.rz) {
-      set_error("sweep_batch_create: all plans of a batch must use the same rz tuning");
+    if (plans[q]->tune.rz != plans[0]->tune.rz || plans[q]->tune.pml_rz != plans[0]->tune.pml_rz) {
+      set_error("sweep_batch_create: all plans of a batch must use the same rz and pml_rz");
       return SWEEP_EINVAL;
     }
   }
@@ -805,6 +814,7 @@ extern "C" int sweep_batch_create(sweep_plan* const* plans, int nplans, sweep_ba
   }
   b->plans.assign(plans, plans + nplans);
   b->rz = plans[0]->tune.rz;
+  b->prz = plans[0]->tune.pml_rz;
   *out = b;
   return SWEEP_OK;
 }
@@ -907,9 +917,9 @@ extern "C" int sweep_batch_backward(sweep_batch* b, const float* const* d_resids
 }
 
 // ----------------------------------------------------------------- autotuner
-// Times `steps` forward steps of the plan for every supported rz (main-kernel
-// rows per thread) and keeps the fastest; results are cached in a text file,
-// one line "arch physics NX NZ nshots rz microseconds_per_step".
+// Times `steps` forward steps of the plan for every supported (rz, pml_rz) pair
+// and keeps the fastest; results are cached in a text file, one line
+// "arch physics NX NZ nshots rz pml_rz microseconds_per_step".
 namespace {
 
 std::string tune_key(const sweep_plan* p) {
@@ -923,6 +933,8 @@ std::string tune_key(const sweep_plan* p) {
      << " " << p->NZ << " " << p->pb.nshots;
   return os.str();
 }
+
+bool rz_ok(int v) { return v == 1 || v == 2 || v == 4 || v == 8; }
 
 }  // namespace
 
@@ -947,11 +959,12 @@ extern "C" int sweep_plan_autotune(sweep_plan* p, const float* d_model, const fl
           line[key.size()] != ' ')
         continue;
       std::istringstream is(line.substr(key.size()));
-      int rz = 0;
+      int rz = 0, prz = 0;
       double us = 0;
-      if (is >> rz >> us && (rz == 1 || rz == 2 || rz == 4 || rz == 8)) {
+      if (is >> rz >> prz >> us && rz_ok(rz) && rz_ok(prz) && prz <= rz) {
         sweep_tuning t = p->tune;
         t.rz = rz;
+        t.pml_rz = prz;
         const int rc = sweep_plan_set_tuning(p, &t);
         if (rc) return rc;
         if (chosen_rz) *chosen_rz = rz;
@@ -970,32 +983,37 @@ extern "C" int sweep_plan_autotune(sweep_plan* p, const float* d_model, const fl
   SWEEP_HIP(hipEventCreate(&e0));
   SWEEP_HIP(hipEventCreate(&e1));
   const int cand[4] = {1, 2, 4, 8};
-  int best = keep.rz;
+  int best = keep.rz, best_p = keep.pml_rz;
   double best_us = 1e300;
-  std::ostringstream log;
+  const int nsteps = std::min(steps, p->pb.nt);
   for (int c : cand) {
-    p->tune.rz = c;
-    ac_build_tiling(p);
-    if ((rc = ac_upload_geometry(p, d_work, L, s))) break;
-    for (int rep = 0; rep < 2 && !rc; ++rep) {  // first pass warms up
-      rc = ac_fwd_prologue(p, d_model, d_wavelet, d_work, L, s);
-      if (rc) break;
-      SWEEP_HIP(hipEventRecord(e0, s));
-      for (int n = 0; n < std::min(steps, p->pb.nt) && !rc; ++n) {
-        AcStep a;
-        rc = ac_fwd_step_args(p, d_work, L, n, nullptr, 0, s, a);
-        if (!rc) rc = ac_launch_fwd(a, c, s, nullptr);
+    for (int cp : cand) {
+      if (cp > c || rc) continue;
+      p->tune.rz = c;
+      p->tune.pml_rz = cp;
+      ac_build_tiling(p);
+      if ((rc = ac_upload_geometry(p, d_work, L, s))) break;
+      for (int rep = 0; rep < 2 && !rc; ++rep) {  // first pass warms up
+        rc = ac_fwd_prologue(p, d_model, d_wavelet, d_work, L, s);
+        if (rc) break;
+        SWEEP_HIP(hipEventRecord(e0, s));
+        for (int n = 0; n < nsteps && !rc; ++n) {
+          AcStep a;
+          rc = ac_fwd_step_args(p, d_work, L, n, nullptr, 0, s, a);
+          if (!rc) rc = ac_launch_fwd(a, c, cp, s, nullptr);
+        }
+        SWEEP_HIP(hipEventRecord(e1, s));
+        SWEEP_HIP(hipEventSynchronize(e1));
       }
-      SWEEP_HIP(hipEventRecord(e1, s));
-      SWEEP_HIP(hipEventSynchronize(e1));
-    }
-    if (rc) break;
-    float ms = 0.0f;
-    SWEEP_HIP(hipEventElapsedTime(&ms, e0, e1));
-    const double us = 1e3 * ms / std::min(steps, p->pb.nt);
-    if (us < best_us) {
-      best_us = us;
-      best = c;
+      if (rc) break;
+      float ms = 0.0f;
+      SWEEP_HIP(hipEventElapsedTime(&ms, e0, e1));
+      const double us = 1e3 * ms / nsteps;
+      if (us < best_us) {
+        best_us = us;
+        best = c;
+        best_p = cp;
+      }
     }
   }
   (void)hipEventDestroy(e0);
@@ -1008,10 +1026,11 @@ extern "C" int sweep_plan_autotune(sweep_plan* p, const float* d_model, const fl
   }
   sweep_tuning t = keep;
   t.rz = best;
+  t.pml_rz = best_p;
   if ((rc = sweep_plan_set_tuning(p, &t))) return rc;
   if (cache_path && *cache_path) {
     std::ofstream out(cache_path, std::ios::app);
-    out << key << " " << best << " " << best_us << "\n";
+    out << key << " " << best << " " << best_p << " " << best_us << "\n";
   }
   if (chosen_rz) *chosen_rz = best;
   return SWEEP_OK;

@@ -48,11 +48,9 @@ struct AcStep {
   const float* bz;
   // forward: p^n (cur), p^{n-1} (prev), p^{n+1} (next, aliases prev)
   // adjoint: lambda^{n+1} (cur), lambda^{n+2} (prev), lambda^n (next, aliases prev)
-  // The band kernels update prev in place through prev_adj (same buffer).
   const float* cur;
   const float* prev;
   float* next;
-  float* prev_adj;
   // memory variables: read *_in (time n-1), write *_out (time n)
   const float* psx_in;
   float* psx_out;
@@ -75,11 +73,14 @@ struct AcStep {
   const float* B_in;      // B'^n of this step
   float* g;               // [nshots][NZ][NX] gradient partial
   int g_init;             // 1: g = P1 B (first step of a segment), 0: g += P1 B
-  // C-PML bands: (first column or row, count <= 48) pieces of the x and z bands
-  const int2* xchunks;
-  int n_xchunks;
-  const int2* zchunks;
-  int n_zchunks;
+  // tiles: the interior rectangle [itx0, itx1) x [itz0, itz1) of tile
+  // coordinates holds the n_int tiles without C-PML cells; the other n_pml
+  // tiles (the frame) take the PML kernel
+  int itx0, itx1, itz0, itz1;
+  int n_int, n_pml;
+  int n_xf, n_zf;  // frame tiles: left/right columns (x frame), above/below (z frame)
+  int tz;    // rows of a tile
+  int nsub;  // PML work-groups per frame tile (each takes tz / nsub rows)
 };
 
 // Several plans of different shapes advanced by one launch per kernel kind.
@@ -87,18 +88,18 @@ constexpr int kMaxBatch = 8;
 struct AcBatch {
   int nplans;
   int base[kMaxBatch + 1];  // first flat block of each plan in this launch
-  int gx[kMaxBatch], gy[kMaxBatch];
   AcStep step[kMaxBatch];
 };
 
-// Launchers (acoustic.hip). `rz` selects the main kernel variant (TZ = 4 rz).
+// Launchers (acoustic.hip). Tiles are 64 x 4 rz; the interior kernel keeps rz rows
+// per thread, the PML kernel prz (prz <= rz, a frame tile split into rz / prz pieces).
 int ac_launch_prep(const float* v, float* vpad, float* Cs, float* ax, float* bx, float* az,
                    float* bz, int nx, int nz, int P, double h, double dt, double vmax,
                    double f0, double R, hipStream_t s);
-int ac_launch_fwd(const AcStep& a, int rz, hipStream_t s, hipEvent_t* ev);
-int ac_launch_adj(const AcStep& a, int rz, hipStream_t s, hipEvent_t* ev);
-int ac_launch_fwd_batch(const AcStep* steps, int n, int rz, hipStream_t s);
-int ac_launch_adj_batch(const AcStep* steps, int n, int rz, hipStream_t s);
+int ac_launch_fwd(const AcStep& a, int rz, int prz, hipStream_t s, hipEvent_t* ev);
+int ac_launch_adj(const AcStep& a, int rz, int prz, hipStream_t s, hipEvent_t* ev);
+int ac_launch_fwd_batch(const AcStep* steps, int n, int rz, int prz, hipStream_t s);
+int ac_launch_adj_batch(const AcStep* steps, int n, int rz, int prz, hipStream_t s);
 int ac_launch_adj_init(float* lam_cur, float* lam_prev, size_t plane_elems, float* aux,
                        size_t aux_elems, const int* rec_cell, const float* resid, int nshots,
                        int nt, int nrec, hipStream_t s);

@@ -9,7 +9,7 @@
 namespace sweep {
 struct AcLayout {
   size_t plane, xs, zs, aux_elems;
-  size_t ax, bx, az, bz, vpad, Cs, wav, src_cell, rec_cell, rec_off, rec_ent, xch, zch;
+  size_t ax, bx, az, bz, vpad, Cs, wav, src_cell, rec_cell, rec_off, rec_ent;
   size_t pA, pB, aux[2];
   size_t fwd_end;
   int nseg;
@@ -22,7 +22,8 @@ struct AcLayout {
 // Optional per-launch timing of the step kernels (hipEvent pairs recorded on the
 // caller's stream around every launch of a kernel class).
 namespace sweep {
-// Main = whole-grid stencil kernel; Band = the two C-PML band kernels of a step.
+// Acoustic: Main = interior-tile kernel, Band = PML (frame-tile) kernel of a step;
+// elastic: one class per pass.
 enum KernelClass {
   kFwdMain = 0,
   kFwdBand = 1,
@@ -83,7 +84,8 @@ struct sweep_plan {
   std::vector<int> rec_cell;  // [nshots][nrec] padded linear index
   // tiling for the current tuning
   int TZ = 0, tiles_x = 0, tiles_z = 0, ntiles = 0;
-  std::vector<int2> xchunks, zchunks;  // C-PML band pieces (start, count <= 48)
+  // interior rectangle of tiles without C-PML cells (tile coordinates)
+  int itx0 = 0, itx1 = 0, itz0 = 0, itz1 = 0, n_int = 0, n_pml = 0, n_xf = 0, n_zf = 0;
   // elastic: receivers sorted by (shot, cell, r) for deterministic injection,
   // and the transposed z-taps of the first rows under a free surface
   std::vector<int4> rec_sorted;
@@ -114,7 +116,7 @@ int el_backward(sweep_plan* p, const float* resid, float* grad, void* work, size
 
 struct sweep_batch {
   std::vector<sweep_plan*> plans;  // owned by the caller
-  int rz = 8;
+  int rz = 8, prz = 2;
   bool use_graph = false;
   bool saved = false;
   const void* saved_work = nullptr;

@@ -99,16 +99,19 @@ class Plan:
     def tuning(self) -> dict:
         t = Tuning()
         check(lib().sweep_plan_get_tuning(self._h, ctypes.byref(t)))
-        return {"rz": t.rz, "shots_per_block": t.shots_per_block, "use_graph": t.use_graph}
+        return {"rz": t.rz, "pml_rz": t.pml_rz, "use_graph": t.use_graph}
 
-    def set_tuning(self, rz: int = 8, shots_per_block: int = 1, use_graph: int = 0):
-        t = Tuning(rz, shots_per_block, use_graph)
+    def set_tuning(self, rz: int = 4, pml_rz: Optional[int] = None, use_graph: int = 0):
+        """rz: rows per thread of the interior kernel (tiles of 64 x 4 rz);
+        pml_rz: rows per thread of the C-PML kernels (<= rz, default min(4, rz))."""
+        t = Tuning(rz, min(4, rz) if pml_rz is None else pml_rz, use_graph)
         check(lib().sweep_plan_set_tuning(self._h, ctypes.byref(t)))
         self._saved_id = -1
 
     def autotune(self, model: torch.Tensor, wavelet: torch.Tensor, steps: int = 20,
                  cache_path: Optional[str] = None) -> int:
-        """Pick the fastest main-kernel tiling for this plan (cached); returns rz."""
+        """Pick the fastest tiling (rz, pml_rz) for this plan (cached); returns rz
+        (both are in .tuning afterwards)."""
         if self.nparam == 1 and model.dim() == 2:
             model = model.unsqueeze(0)
         _need(model, self._model_shape(), "model")
@@ -126,6 +129,13 @@ class Plan:
         a, b = ctypes.c_int(), ctypes.c_int()
         check(lib().sweep_plan_padded(self._h, ctypes.byref(a), ctypes.byref(b)))
         return a.value, b.value
+
+    def tiles(self):
+        """(interior tiles, frame tiles, tile rows) of the acoustic tiling; tiles
+        are 64 columns wide and the interior ones hold no C-PML cell."""
+        a, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        check(lib().sweep_plan_tiles(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return a.value, b.value, c.value
 
     def workspace_bytes(self, for_backward: bool) -> int:
         return int(lib().sweep_plan_workspace_bytes(self._h, int(bool(for_backward))))
@@ -184,6 +194,8 @@ class Plan:
         return out
 
     # ---------------------------------------------------------------- timing
+    # acoustic: *_main = interior-tile kernel, *_band = PML (frame-tile) kernel;
+    # fwd = forward, rec = segment recomputation, adj = adjoint
     KERNEL_CLASSES = ("fwd_main", "fwd_band", "adj_main", "adj_band", "rec_main", "rec_band")
 
     def set_profiling(self, enable: bool):
@@ -238,6 +250,13 @@ class Batch:
 
     def set_graph(self, use_graph: bool):
         check(lib().sweep_batch_set_graph(self._h, int(bool(use_graph))))
+
+    def tiles(self):
+        """(interior tiles, frame tiles, tile rows) of the acoustic tiling; tiles
+        are 64 columns wide and the interior ones hold no C-PML cell."""
+        a, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        check(lib().sweep_plan_tiles(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return a.value, b.value, c.value
 
     def workspace_bytes(self, for_backward: bool) -> int:
         return int(lib().sweep_batch_workspace_bytes(self._h, int(bool(for_backward))))

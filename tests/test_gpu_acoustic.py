@@ -55,11 +55,16 @@ def test_forward_parity_ragged(sw, orc):
     assert err <= SEIS_TOL
 
 
-@pytest.mark.parametrize("rz", [1, 2, 4, 8])
-def test_forward_tilings_bitwise(sw, rz):
+# (interior rows per thread, C-PML rows per thread): the tile height moves the
+# boundary between interior and frame tiles and the frame kernel's split
+TILINGS = [(1, 1), (2, 1), (2, 2), (4, 1), (4, 4), (8, 1), (8, 2), (8, 8)]
+
+
+@pytest.mark.parametrize("rz,prz", TILINGS)
+def test_forward_tilings_bitwise(sw, rz, prz):
     case = random_case(2, nx=200, nz=140, pml=12, nt=120)
-    _, d0 = _gpu_forward(sw, case, tuning=dict(rz=8))
-    _, d1 = _gpu_forward(sw, case, tuning=dict(rz=rz))
+    _, d0 = _gpu_forward(sw, case, tuning=dict(rz=8, pml_rz=4))
+    _, d1 = _gpu_forward(sw, case, tuning=dict(rz=rz, pml_rz=prz))
     assert torch.equal(d0, d1)
 
 
@@ -119,13 +124,13 @@ def test_checkpoint_interval_invariance(sw):
     assert rel_l2(grads[2], grads[0]) <= 1e-6
 
 
-@pytest.mark.parametrize("rz", [1, 4])
-def test_gradient_tilings_bitwise(sw, rz):
+@pytest.mark.parametrize("rz,prz", [(1, 1), (4, 2), (8, 8)])
+def test_gradient_tilings_bitwise(sw, rz, prz):
     case = random_case(5, nx=170, nz=100, nt=90, ckpt=20)
     resid = _dev(synth.bandlimited_noise((case.nshots, case.nt, case.nrec), 15.0, case.dt, 3))
     out = []
-    for t in (8, rz):
-        plan, _ = _gpu_forward(sw, case, save=True, tuning=dict(rz=t))
+    for t, tp in ((8, 2), (rz, prz)):
+        plan, _ = _gpu_forward(sw, case, save=True, tuning=dict(rz=t, pml_rz=tp))
         out.append(plan.backward(resid).clone())
     assert torch.equal(out[0], out[1])
 
