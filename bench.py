@@ -132,6 +132,121 @@ def per_shot_compare(sw, torch, w, v0, wav, d_obs, nsample, tuning, t_batched):
             "speedup": round(est / t_batched, 2), "grad_rel_err_vs_batched": err}
 
 
+def _sync_time(torch, fn):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = fn()
+    torch.cuda.synchronize()
+    return out, time.perf_counter() - t0
+
+
+def batched_uneven(sw, torch, tuning):
+    """The eight uneven layered models (200x200 ... 1200x400, 16-48 shots, 2000-4000
+    steps, 256 shots): one FWI gradient of all of them through one Batch (one
+    launch per kernel kind and step for every model) against the per-shot path
+    (single-shot plans, kernels launched once per shot per step), timed on the
+    middle shot of each model and scaled by its shot count."""
+    import synth
+    from tests.helpers import case_from_workload
+    ws = synth.batched_workloads()
+    plans, v0s, wavs, dobs = [], [], [], []
+    for w in ws:
+        case = case_from_workload(w)
+        p = case.plan()
+        p.set_tuning(*tuning)
+        wav = torch.tensor(case.wav, dtype=torch.float32, device="cuda")
+        d = p.forward(torch.tensor(case.v, dtype=torch.float32, device="cuda"), wav).clone()
+        p.release_workspace()
+        plans.append(p)
+        v0s.append(torch.tensor(synth.smooth(case.v, 20.0), dtype=torch.float32, device="cuda"))
+        wavs.append(wav)
+        dobs.append(d)
+    batch = sw.Batch(plans)
+    # the workspace is allocated before timing (inputs and state resident in HBM)
+    batch._work = torch.empty(batch.workspace_bytes(True), dtype=torch.uint8, device="cuda")
+
+    def grad():
+        ds = batch.forward(v0s, wavs, save=True)
+        rs = [sw.l2_misfit(d, o)[0] for d, o in zip(ds, dobs)]
+        return batch.backward(rs)
+
+    _, t_batch = _sync_time(torch, grad)
+    batch._work = None
+    t_shot = 0.0
+    for w, v0, wav, do in zip(ws, v0s, wavs, dobs):
+        s = w.nshots // 2
+        p1 = case_from_workload(w, shots=[s]).plan()
+        p1.set_tuning(*tuning)
+
+        def one():
+            d = p1.forward(v0, wav[s:s + 1], save=True)
+            return p1.backward(sw.l2_misfit(d, do[s:s + 1])[0])
+
+        _, t1 = _sync_time(torch, one)
+        p1.release_workspace()
+        t_shot += t1 * w.nshots
+    cells = sum(2.0 * w.nshots * w.NX * w.NZ * w.nt for w in ws)
+    return {"models": len(ws), "shots": sum(w.nshots for w in ws),
+            "batched_gradient_s": round(t_batch, 3),
+            "batched_Gcell_per_s": round(cells / t_batch / 1e9, 2),
+            "per_shot_gradient_s_est": round(t_shot, 3), "speedup": round(t_shot / t_batch, 2),
+            "per_shot_sample": "middle shot of each model, scaled by its shot count"}
+
+
+def elastic_gradient(sw, torch):
+    """Elastic velocity-stress FWI gradient (vp, vs, rho) on the 600x300
+    free-surface workload: 32 shots, 4000 steps, checkpoints every 50."""
+    import synth
+    from tests.helpers import el_case_from_workload
+    w = synth.workload("elastic600x300")
+    case = el_case_from_workload(w)
+    plan = case.plan()
+    wav = torch.tensor(case.wav, dtype=torch.float32, device="cuda")
+    m_true = torch.tensor(case.model, dtype=torch.float32, device="cuda")
+    d_obs = plan.forward(m_true, wav).clone()
+    m0 = torch.tensor(np.stack([synth.smooth(c, 20.0) for c in case.model]), dtype=torch.float32,
+                      device="cuda")
+
+    def grad():
+        d = plan.forward(m0, wav, save=True)
+        return plan.backward(sw.l2_misfit(d, d_obs)[0])
+
+    grad()
+    _, t = _sync_time(torch, grad)
+    NX, NZ = plan.padded()
+    cells = 2.0 * w.nshots * NX * NZ * w.nt
+    plan.release_workspace()
+    return {"workload": "elastic600x300", "padded": f"{NX}x{NZ}", "shots": w.nshots,
+            "nt": w.nt, "gradient_s": round(t, 3), "Gcell_per_s": round(cells / t / 1e9, 2)}
+
+
+def mlp_throughput(torch):
+    """MLP velocity model at 300,000 points: forward, backward and Adam step
+    (bf16 MFMA, float32 accumulation)."""
+    import synth
+    from paper_2604_14189_amd.mlp import MLPVelocity
+    rng = np.random.default_rng(0)
+    P = 230657
+    theta = (rng.uniform(-1, 1, P) * 0.06).astype(np.float32)
+    net = MLPVelocity(1000, 300, synth.rff_frequencies(seed=0), theta)
+    dv = torch.full((300, 1000), 1e-3, device="cuda")
+    for _ in range(3):
+        net.forward()
+        net.step(net.backward(dv))
+    reps = 20
+    _, tf = _sync_time(torch, lambda: [net.forward() for _ in range(reps)])
+    _, tb = _sync_time(torch, lambda: [net.backward(dv) for _ in range(reps)])
+    g = net.backward(dv)
+    _, ta = _sync_time(torch, lambda: [net.step(g) for _ in range(reps)])
+    M = 300000
+    f_fwd = 2.0 * M * (128 * 256 + 3 * 256 * 256 + 256)
+    f_bwd = 2.0 * M * (128 * 256 + 3 * 256 * 256 + 256) + 2.0 * M * 3 * 256 * 256
+    return {"points": M, "forward_ms": round(tf / reps * 1e3, 3),
+            "backward_ms": round(tb / reps * 1e3, 3), "adam_ms": round(ta / reps * 1e3, 3),
+            "forward_TFLOPs": round(f_fwd / (tf / reps) / 1e12, 1),
+            "backward_TFLOPs": round(f_bwd / (tb / reps) / 1e12, 1)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -143,6 +258,8 @@ def main():
     ap.add_argument("--nt", type=int, default=0, help="override the step count (testing)")
     ap.add_argument("--per-shot-sample", type=int, default=4,
                     help="shots timed through the per-shot path (0: skip)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the elastic, batched-uneven and MLP measurements")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -263,6 +380,14 @@ def main():
         "kernels": kernels,
         "tiles": {"interior": n_int, "frame": n_pml, "rows": TZ},
     }
+    if not args.no_extras and not args.nt:
+        plan.release_workspace()
+        del plan
+        torch.cuda.empty_cache()
+        out["batched_uneven"] = batched_uneven(sw, torch, (args.rz, args.pml_rz))
+        torch.cuda.empty_cache()
+        out["elastic"] = elastic_gradient(sw, torch)
+        out["mlp"] = mlp_throughput(torch)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)

@@ -251,13 +251,6 @@ class Batch:
     def set_graph(self, use_graph: bool):
         check(lib().sweep_batch_set_graph(self._h, int(bool(use_graph))))
 
-    def tiles(self):
-        """(interior tiles, frame tiles, tile rows) of the acoustic tiling; tiles
-        are 64 columns wide and the interior ones hold no C-PML cell."""
-        a, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
-        check(lib().sweep_plan_tiles(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
-        return a.value, b.value, c.value
-
     def workspace_bytes(self, for_backward: bool) -> int:
         return int(lib().sweep_batch_workspace_bytes(self._h, int(bool(for_backward))))
 
