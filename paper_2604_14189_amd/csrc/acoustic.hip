@@ -124,17 +124,6 @@ __global__ void ac_tables_kernel(float* ax, float* bx, float* az, float* bz, int
 // ---------------------------------------------------------------------------
 // Tiles and work-group placement.
 // ---------------------------------------------------------------------------
-// Work-groups of one launch are dealt to the 8 XCDs round-robin by flat index,
-// and each XCD has its own L2. xcd_spread renumbers the flat index f of n so
-// that every XCD receives one contiguous run of the logical block order
-// (consecutive tiles of a shot, then the next shot): tiles that share halo
-// cache lines then run under the same L2. It is a bijection of [0, n).
-__device__ __forceinline__ int xcd_spread(int f, int n) {
-  const int x = f & 7, k = f >> 3;
-  const int q = n >> 3, r = n & 7;
-  return x * q + min(x, r) + k;
-}
-
 // Global tile index of the b-th interior tile (row-major in the rectangle
 // [itx0, itx1) x [itz0, itz1) of tile coordinates).
 __device__ __forceinline__ int interior_tile(const AcStep& a, int b) {

@@ -28,52 +28,6 @@ namespace {
 constexpr float C1 = 9.0f / 8.0f;
 constexpr float C2 = -1.0f / 24.0f;
 
-__device__ __forceinline__ float ld(const float* f, int i, int j, int NX, int NZ) {
-  return (i >= 0 && i < NX && j >= 0 && j < NZ) ? f[(size_t)j * NX + i] : 0.0f;
-}
-
-// forward x derivatives (unscaled)
-__device__ __forceinline__ float dxp(const float* f, int i, int j, int NX, int NZ) {
-  return fmaf(C2, ld(f, i + 2, j, NX, NZ) - ld(f, i - 1, j, NX, NZ),
-              C1 * (ld(f, i + 1, j, NX, NZ) - ld(f, i, j, NX, NZ)));
-}
-__device__ __forceinline__ float dxm(const float* f, int i, int j, int NX, int NZ) {
-  return fmaf(C2, ld(f, i + 1, j, NX, NZ) - ld(f, i - 2, j, NX, NZ),
-              C1 * (ld(f, i, j, NX, NZ) - ld(f, i - 1, j, NX, NZ)));
-}
-__device__ __forceinline__ float dzp(const float* f, int i, int j, int NX, int NZ) {
-  return fmaf(C2, ld(f, i, j + 2, NX, NZ) - ld(f, i, j - 1, NX, NZ),
-              C1 * (ld(f, i, j + 1, NX, NZ) - ld(f, i, j, NX, NZ)));
-}
-__device__ __forceinline__ float dzm(const float* f, int i, int j, int NX, int NZ) {
-  return fmaf(C2, ld(f, i, j + 1, NX, NZ) - ld(f, i, j - 2, NX, NZ),
-              C1 * (ld(f, i, j, NX, NZ) - ld(f, i, j - 1, NX, NZ)));
-}
-
-// z derivatives with the free-surface rules on rows 0 and 1
-__device__ __forceinline__ float dz_tzz(const float* f, int i, int j, int NX, int NZ, int fs) {
-  if (fs && j == 0)  // tzz[-1] = -tzz[1]
-    return fmaf(C2, ld(f, i, 2, NX, NZ), fmaf(C1 + C2, ld(f, i, 1, NX, NZ), -C1 * ld(f, i, 0, NX, NZ)));
-  return dzp(f, i, j, NX, NZ);
-}
-__device__ __forceinline__ float dz_txz(const float* f, int i, int j, int NX, int NZ, int fs) {
-  if (fs && j == 0)  // txz[-1] = -txz[0], txz[-2] = -txz[1]
-    return fmaf(2.0f * C2, ld(f, i, 1, NX, NZ), 2.0f * C1 * ld(f, i, 0, NX, NZ));
-  if (fs && j == 1)  // txz[-1] = -txz[0]
-    return fmaf(C2, ld(f, i, 2, NX, NZ),
-                fmaf(-C1 + C2, ld(f, i, 0, NX, NZ), C1 * ld(f, i, 1, NX, NZ)));
-  return dzm(f, i, j, NX, NZ);
-}
-__device__ __forceinline__ float dz_vx(const float* f, int i, int j, int NX, int NZ, int fs) {
-  if (fs && j == 0) return ld(f, i, 1, NX, NZ) - ld(f, i, 0, NX, NZ);
-  return dzp(f, i, j, NX, NZ);
-}
-__device__ __forceinline__ float dz_vz(const float* f, int i, int j, int NX, int NZ, int fs) {
-  if (fs && j == 0) return 0.0f;
-  if (fs && j == 1) return ld(f, i, 1, NX, NZ) - ld(f, i, 0, NX, NZ);
-  return dzm(f, i, j, NX, NZ);
-}
-
 // psi <- b psi + a G (only where a != 0); returns G + psi
 __device__ __forceinline__ float cpml(float* psi, size_t k, float G, float a, float b) {
   if (a == 0.0f) return G;
@@ -83,33 +37,148 @@ __device__ __forceinline__ float cpml(float* psi, size_t k, float G, float a, fl
 }
 
 // ---------------------------------------------------------------------------
+// Tiles: 64 columns x kElTZ rows per work-group, thread (lx, w) owns column lx
+// and rows [w kElRZ, w kElRZ + kElRZ). The fields (or derived quantities) a
+// kernel differentiates are staged in LDS on the tile plus a 2-cell halo, zero
+// outside the grid, so the stencils read LDS and every global load is
+// coalesced and issued once per tile.
+// ---------------------------------------------------------------------------
+constexpr int kElRZ = 4;
+constexpr int kElTZ = 4 * kElRZ;
+constexpr int kElBW = kTX + 4;
+constexpr int kElBH = kElTZ + 4;
+constexpr int kElBox = kElBW * kElBH;
+constexpr int kElK = (kElBox + kThreads - 1) / kThreads;
+
+// value at grid cell (i, j) of a staged box whose first cell is (x0-2, z0-2)
+struct Box {
+  const float* s;
+  int x0, z0;
+  __device__ __forceinline__ float operator()(int i, int j) const {
+    return s[(j - z0 + 2) * kElBW + (i - x0 + 2)];
+  }
+};
+
+template <class F>
+__device__ __forceinline__ float bdxp(const F& f, int i, int j) {
+  return fmaf(C2, f(i + 2, j) - f(i - 1, j), C1 * (f(i + 1, j) - f(i, j)));
+}
+template <class F>
+__device__ __forceinline__ float bdxm(const F& f, int i, int j) {
+  return fmaf(C2, f(i + 1, j) - f(i - 2, j), C1 * (f(i, j) - f(i - 1, j)));
+}
+template <class F>
+__device__ __forceinline__ float bdzp(const F& f, int i, int j) {
+  return fmaf(C2, f(i, j + 2) - f(i, j - 1), C1 * (f(i, j + 1) - f(i, j)));
+}
+template <class F>
+__device__ __forceinline__ float bdzm(const F& f, int i, int j) {
+  return fmaf(C2, f(i, j + 1) - f(i, j - 2), C1 * (f(i, j) - f(i, j - 1)));
+}
+// z derivatives with the free-surface rules on rows 0 and 1
+template <class F>
+__device__ __forceinline__ float bdz_tzz(const F& f, int i, int j, int fs) {
+  if (fs && j == 0)  // tzz[-1] = -tzz[1]
+    return fmaf(C2, f(i, 2), fmaf(C1 + C2, f(i, 1), -C1 * f(i, 0)));
+  return bdzp(f, i, j);
+}
+template <class F>
+__device__ __forceinline__ float bdz_txz(const F& f, int i, int j, int fs) {
+  if (fs && j == 0)  // txz[-1] = -txz[0], txz[-2] = -txz[1]
+    return fmaf(2.0f * C2, f(i, 1), 2.0f * C1 * f(i, 0));
+  if (fs && j == 1)  // txz[-1] = -txz[0]
+    return fmaf(C2, f(i, 2), fmaf(-C1 + C2, f(i, 0), C1 * f(i, 1)));
+  return bdzm(f, i, j);
+}
+template <class F>
+__device__ __forceinline__ float bdz_vx(const F& f, int i, int j, int fs) {
+  if (fs && j == 0) return f(i, 1) - f(i, 0);
+  return bdzp(f, i, j);
+}
+template <class F>
+__device__ __forceinline__ float bdz_vz(const F& f, int i, int j, int fs) {
+  if (fs && j == 0) return 0.0f;
+  if (fs && j == 1) return f(i, 1) - f(i, 0);
+  return bdzm(f, i, j);
+}
+
+// tile and shot of this work-group (1-D launch over tiles x shots)
+struct ElTile {
+  int x0, z0, shot;
+};
+__device__ __forceinline__ ElTile el_tile(const ElStep& a) {
+  const int f = xcd_spread(blockIdx.x, gridDim.x);
+  const int tx = (a.NX + kTX - 1) / kTX, tz = (a.NZ + kElTZ - 1) / kElTZ;
+  const int t = f % (tx * tz);
+  ElTile r;
+  r.shot = f / (tx * tz);
+  r.x0 = (t % tx) * kTX;
+  r.z0 = (t / tx) * kElTZ;
+  return r;
+}
+
+// Stages NF shot fields on the tile plus the halo: dst[q][box] = src[q][cell].
+template <int NF>
+__device__ __forceinline__ void el_stage(float (*dst)[kElBox], const float* const* src, int x0,
+                                         int z0, int NX, int NZ) {
+  float v[NF][kElK];
+#pragma unroll
+  for (int k = 0; k < kElK; ++k) {
+    const int e = threadIdx.x + k * kThreads;
+    const int r = e / kElBW, c = e - (e / kElBW) * kElBW;
+    const int gx = x0 - 2 + c, gz = z0 - 2 + r;
+    const bool ok = e < kElBox && gx >= 0 && gx < NX && gz >= 0 && gz < NZ;
+    const size_t q = ok ? (size_t)gz * NX + gx : 0;
+#pragma unroll
+    for (int f = 0; f < NF; ++f) v[f][k] = ok ? src[f][q] : 0.0f;
+  }
+#pragma unroll
+  for (int k = 0; k < kElK; ++k) {
+    const int e = threadIdx.x + k * kThreads;
+    if (e < kElBox) {
+#pragma unroll
+      for (int f = 0; f < NF; ++f) dst[f][e] = v[f][k];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // forward: velocity update  vx += dt bx (Dx+ txx + Dz- txz), vz += dt bz (Dx- txz + Dz+ tzz)
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void el_vel_kernel(ElStep a) {
-  const int i = blockIdx.x * 64 + (threadIdx.x & 63);
-  const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
+  __shared__ float sb[3][kElBox];
+  const ElTile T = el_tile(a);
   const int NX = a.NX, NZ = a.NZ;
-  if (i >= NX || j >= NZ) return;
   const size_t plane = (size_t)NX * NZ;
-  const size_t so = (size_t)blockIdx.z * plane;
-  const size_t k = (size_t)j * NX + i;
-  const float* txx = a.txx + so;
-  const float* tzz = a.tzz + so;
-  const float* txz = a.txz + so;
+  const size_t so = (size_t)T.shot * plane;
+  {
+    const float* src[3] = {a.txx + so, a.tzz + so, a.txz + so};
+    el_stage<3>(sb, src, T.x0, T.z0, NX, NZ);
+  }
+  __syncthreads();
+  const Box txx{sb[0], T.x0, T.z0}, tzz{sb[1], T.x0, T.z0}, txz{sb[2], T.x0, T.z0};
+  const int i = T.x0 + (threadIdx.x & 63);
+  const int jb = T.z0 + (threadIdx.x >> 6) * kElRZ;
   const float ih = a.ih;
-  const float Ga = dxp(txx, i, j, NX, NZ) * ih;
-  const float Gb = dz_txz(txz, i, j, NX, NZ, a.fs) * ih;
-  const float Gc = dxm(txz, i, j, NX, NZ) * ih;
-  const float Gd = dz_tzz(tzz, i, j, NX, NZ, a.fs) * ih;
-  const float fvx = cpml(a.ps[0] + so, k, Ga, a.axh[i], a.bxh[i]) +
-                    cpml(a.ps[1] + so, k, Gb, a.azi[j], a.bzi[j]);
-  const float fvz = cpml(a.ps[2] + so, k, Gc, a.axi[i], a.bxi[i]) +
-                    cpml(a.ps[3] + so, k, Gd, a.azh[j], a.bzh[j]);
-  a.vx[so + k] = fmaf(a.dt * a.bx[k], fvx, a.vx[so + k]);
-  a.vz[so + k] = fmaf(a.dt * a.bz[k], fvz, a.vz[so + k]);
-  if (a.tr[0]) {
-    a.tr[0][so + k] = fvx;
-    a.tr[1][so + k] = fvz;
+#pragma unroll
+  for (int r = 0; r < kElRZ; ++r) {
+    const int j = jb + r;
+    if (i >= NX || j >= NZ) continue;
+    const size_t k = (size_t)j * NX + i;
+    const float Ga = bdxp(txx, i, j) * ih;
+    const float Gb = bdz_txz(txz, i, j, a.fs) * ih;
+    const float Gc = bdxm(txz, i, j) * ih;
+    const float Gd = bdz_tzz(tzz, i, j, a.fs) * ih;
+    const float fvx = cpml(a.ps[0] + so, k, Ga, a.axh[i], a.bxh[i]) +
+                      cpml(a.ps[1] + so, k, Gb, a.azi[j], a.bzi[j]);
+    const float fvz = cpml(a.ps[2] + so, k, Gc, a.axi[i], a.bxi[i]) +
+                      cpml(a.ps[3] + so, k, Gd, a.azh[j], a.bzh[j]);
+    a.vx[so + k] = fmaf(a.dt * a.bx[k], fvx, a.vx[so + k]);
+    a.vz[so + k] = fmaf(a.dt * a.bz[k], fvz, a.vz[so + k]);
+    if (a.tr[0]) {
+      a.tr[0][so + k] = fvx;
+      a.tr[1][so + k] = fvz;
+    }
   }
 }
 
@@ -129,40 +198,49 @@ __global__ void el_record_kernel(ElStep a) {
 // forward: stress update and explosive source
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void el_str_kernel(ElStep a) {
-  const int i = blockIdx.x * 64 + (threadIdx.x & 63);
-  const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
+  __shared__ float sb[2][kElBox];
+  const ElTile T = el_tile(a);
   const int NX = a.NX, NZ = a.NZ;
-  if (i >= NX || j >= NZ) return;
   const size_t plane = (size_t)NX * NZ;
-  const int shot = blockIdx.z;
+  const int shot = T.shot;
   const size_t so = (size_t)shot * plane;
-  const size_t k = (size_t)j * NX + i;
-  const float* vx = a.vx + so;
-  const float* vz = a.vz + so;
-  const float ih = a.ih;
-  const float Ge = dxm(vx, i, j, NX, NZ) * ih;
-  const float Gf = dz_vz(vz, i, j, NX, NZ, a.fs) * ih;
-  const float Gg = dz_vx(vx, i, j, NX, NZ, a.fs) * ih;
-  const float Gh = dxp(vz, i, j, NX, NZ) * ih;
-  const float exx = cpml(a.ps[4] + so, k, Ge, a.axi[i], a.bxi[i]);
-  const float ezz = cpml(a.ps[5] + so, k, Gf, a.azi[j], a.bzi[j]);
-  const float exz = cpml(a.ps[6] + so, k, Gg, a.azh[j], a.bzh[j]) +
-                    cpml(a.ps[7] + so, k, Gh, a.axh[i], a.bxh[i]);
-  const float dt = a.dt;
-  float txx = a.txx[so + k] + dt * fmaf(a.cxx_x[k], exx, a.cxx_z[k] * ezz);
-  float tzz = a.tzz[so + k] + dt * fmaf(a.czz_x[k], exx, a.czz_z[k] * ezz);
-  if ((int)k == a.src_cell[shot]) {
-    const float s = a.w * a.wavelet[(size_t)shot * a.nt + a.n];
-    txx += s;
-    tzz += s * a.smask[k];
+  {
+    const float* src[2] = {a.vx + so, a.vz + so};
+    el_stage<2>(sb, src, T.x0, T.z0, NX, NZ);
   }
-  a.txx[so + k] = txx;
-  a.tzz[so + k] = tzz;
-  a.txz[so + k] = fmaf(dt * a.mxz[k], exz, a.txz[so + k]);
-  if (a.tr[2]) {
-    a.tr[2][so + k] = exx;
-    a.tr[3][so + k] = ezz;
-    a.tr[4][so + k] = exz;
+  __syncthreads();
+  const Box vx{sb[0], T.x0, T.z0}, vz{sb[1], T.x0, T.z0};
+  const int i = T.x0 + (threadIdx.x & 63);
+  const int jb = T.z0 + (threadIdx.x >> 6) * kElRZ;
+  const float ih = a.ih, dt = a.dt;
+#pragma unroll
+  for (int r = 0; r < kElRZ; ++r) {
+    const int j = jb + r;
+    if (i >= NX || j >= NZ) continue;
+    const size_t k = (size_t)j * NX + i;
+    const float Ge = bdxm(vx, i, j) * ih;
+    const float Gf = bdz_vz(vz, i, j, a.fs) * ih;
+    const float Gg = bdz_vx(vx, i, j, a.fs) * ih;
+    const float Gh = bdxp(vz, i, j) * ih;
+    const float exx = cpml(a.ps[4] + so, k, Ge, a.axi[i], a.bxi[i]);
+    const float ezz = cpml(a.ps[5] + so, k, Gf, a.azi[j], a.bzi[j]);
+    const float exz = cpml(a.ps[6] + so, k, Gg, a.azh[j], a.bzh[j]) +
+                      cpml(a.ps[7] + so, k, Gh, a.axh[i], a.bxh[i]);
+    float txx = a.txx[so + k] + dt * fmaf(a.cxx_x[k], exx, a.cxx_z[k] * ezz);
+    float tzz = a.tzz[so + k] + dt * fmaf(a.czz_x[k], exx, a.czz_z[k] * ezz);
+    if ((int)k == a.src_cell[shot]) {
+      const float s = a.w * a.wavelet[(size_t)shot * a.nt + a.n];
+      txx += s;
+      tzz += s * a.smask[k];
+    }
+    a.txx[so + k] = txx;
+    a.tzz[so + k] = tzz;
+    a.txz[so + k] = fmaf(dt * a.mxz[k], exz, a.txz[so + k]);
+    if (a.tr[2]) {
+      a.tr[2][so + k] = exx;
+      a.tr[3][so + k] = ezz;
+      a.tr[4][so + k] = exz;
+    }
   }
 }
 
@@ -173,7 +251,8 @@ __global__ __launch_bounds__(256) void el_str_kernel(ElStep a) {
 // ---------------------------------------------------------------------------
 
 // Transposed z-derivative of g at row j: standard (-Dz- or -Dz+) away from a
-// free surface, otherwise the host-derived taps of the first four rows.
+// free surface, otherwise the host-derived taps of the first four rows (their
+// offsets lie within two rows).
 template <class F>
 __device__ __forceinline__ float dzT(const ElStep& a, int kind, int j, F g, bool minus_dzm) {
   if (a.fs && j < 4) {
@@ -188,89 +267,112 @@ __device__ __forceinline__ float dzT(const ElStep& a, int kind, int j, F g, bool
   return -fmaf(C2, g(j + 2) - g(j - 1), C1 * (g(j + 1) - g(j)));
 }
 
-__global__ __launch_bounds__(256) void el_adj_s_kernel(ElStep a) {
-  const int i = blockIdx.x * 64 + (threadIdx.x & 63);
-  const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
+// Stages the derivative-input adjoints of the stress step on the tile plus the
+// halo: gbe (exx input), gbf (ezz), gbg (Dz vx of exz), gbh (Dx vz of exz).
+__device__ __forceinline__ void el_stage_adj_s(const ElStep& a, float (*sb)[kElBox], size_t so,
+                                               int x0, int z0) {
   const int NX = a.NX, NZ = a.NZ;
-  if (i >= NX || j >= NZ) return;
-  const size_t plane = (size_t)NX * NZ;
-  const size_t so = (size_t)blockIdx.z * plane;
-  const size_t k = (size_t)j * NX + i;
-  const float dt = a.dt, ih = a.ih;
-  const float* Txx = a.txx + so;
-  const float* Tzz = a.tzz + so;
-  const float* Txz = a.txz + so;
-  const float* Pe = a.ps_in[4] + so;
-  const float* Pf = a.ps_in[5] + so;
-  const float* Pg = a.ps_in[6] + so;
-  const float* Ph = a.ps_in[7] + so;
-  // derivative-input adjoints at any cell (zero outside the grid)
-  auto gbe = [&](int ii, int jj) -> float {
-    if (ii < 0 || ii >= NX || jj < 0 || jj >= NZ) return 0.0f;
-    const size_t q = (size_t)jj * NX + ii;
-    const float e = dt * fmaf(a.cxx_x[q], Txx[q], a.czz_x[q] * Tzz[q]);
-    const float ax = a.axi[ii];
-    return ax == 0.0f ? e : fmaf(ax, Pe[q] + e, e);
-  };
-  auto gbf = [&](int ii, int jj) -> float {
-    if (ii < 0 || ii >= NX || jj < 0 || jj >= NZ) return 0.0f;
-    const size_t q = (size_t)jj * NX + ii;
-    const float e = dt * fmaf(a.cxx_z[q], Txx[q], a.czz_z[q] * Tzz[q]);
-    const float az = a.azi[jj];
-    return az == 0.0f ? e : fmaf(az, Pf[q] + e, e);
-  };
-  auto gbg = [&](int ii, int jj) -> float {
-    if (ii < 0 || ii >= NX || jj < 0 || jj >= NZ) return 0.0f;
-    const size_t q = (size_t)jj * NX + ii;
-    const float e = dt * a.mxz[q] * Txz[q];
-    const float az = a.azh[jj];
-    return az == 0.0f ? e : fmaf(az, Pg[q] + e, e);
-  };
-  auto gbh = [&](int ii, int jj) -> float {
-    if (ii < 0 || ii >= NX || jj < 0 || jj >= NZ) return 0.0f;
-    const size_t q = (size_t)jj * NX + ii;
-    const float e = dt * a.mxz[q] * Txz[q];
-    const float ax = a.axh[ii];
-    return ax == 0.0f ? e : fmaf(ax, Ph[q] + e, e);
-  };
-  // Vx += (Dx-)^T gbe + (Dz+ of vx)^T gbg ;  (Dx-)^T = -Dx+
-  const float dxe = -fmaf(C2, gbe(i + 2, j) - gbe(i - 1, j), C1 * (gbe(i + 1, j) - gbe(i, j)));
-  const float dzg = dzT(a, 2, j, [&](int jj) { return gbg(i, jj); }, true);
-  // Vz += (Dz- of vz)^T gbf + (Dx+)^T gbh ;  (Dx+)^T = -Dx-
-  const float dzf = dzT(a, 3, j, [&](int jj) { return gbf(i, jj); }, false);
-  const float dxh = -fmaf(C2, gbh(i + 1, j) - gbh(i - 2, j), C1 * (gbh(i, j) - gbh(i - 1, j)));
-  a.vx[so + k] += (dxe + dzg) * ih;
-  a.vz[so + k] += (dzf + dxh) * ih;
-
-  // own cell: memory-variable adjoints and the coefficient gradients
-  const float txx = Txx[k], tzz = Tzz[k], txz = Txz[k];
-  const float ex = dt * fmaf(a.cxx_x[k], txx, a.czz_x[k] * tzz);
-  const float ez = dt * fmaf(a.cxx_z[k], txx, a.czz_z[k] * tzz);
-  const float exz = dt * a.mxz[k] * txz;
-  if (a.axi[i] != 0.0f) a.ps_out[4][so + k] = a.bxi[i] * (Pe[k] + ex);
-  if (a.azi[j] != 0.0f) a.ps_out[5][so + k] = a.bzi[j] * (Pf[k] + ez);
-  if (a.azh[j] != 0.0f) a.ps_out[6][so + k] = a.bzh[j] * (Pg[k] + exz);
-  if (a.axh[i] != 0.0f) a.ps_out[7][so + k] = a.bxh[i] * (Ph[k] + exz);
-  const float fexx = a.trc[2][so + k], fezz = a.trc[3][so + k], fexz = a.trc[4][so + k];
-  float glam, gmu;
-  if (a.fs && j == 0) {
-    // txx += dt M exx with M = 4 mu (lambda + mu) / (lambda + 2 mu)
-    const float gM = dt * txx * fexx;
-    glam = gM * a.dM_dl[i];
-    gmu = gM * a.dM_dm[i];
-  } else {
-    glam = dt * (txx + tzz) * (fexx + fezz);
-    gmu = 2.0f * dt * fmaf(txx, fexx, tzz * fezz);
+  const float dt = a.dt;
+  float txx[kElK], tzz[kElK], txz[kElK], cxx_x[kElK], czz_x[kElK], cxx_z[kElK], czz_z[kElK],
+      mxz[kElK];
+#pragma unroll
+  for (int k = 0; k < kElK; ++k) {
+    const int e = threadIdx.x + k * kThreads;
+    const int r = e / kElBW, c = e - (e / kElBW) * kElBW;
+    const int gx = x0 - 2 + c, gz = z0 - 2 + r;
+    const bool ok = e < kElBox && gx >= 0 && gx < NX && gz >= 0 && gz < NZ;
+    const size_t q = ok ? (size_t)gz * NX + gx : 0;
+    txx[k] = ok ? a.txx[so + q] : 0.0f;
+    tzz[k] = ok ? a.tzz[so + q] : 0.0f;
+    txz[k] = ok ? a.txz[so + q] : 0.0f;
+    cxx_x[k] = ok ? a.cxx_x[q] : 0.0f;
+    czz_x[k] = ok ? a.czz_x[q] : 0.0f;
+    cxx_z[k] = ok ? a.cxx_z[q] : 0.0f;
+    czz_z[k] = ok ? a.czz_z[q] : 0.0f;
+    mxz[k] = ok ? a.mxz[q] : 0.0f;
   }
-  const float gmxz = dt * txz * fexz;
-  if (a.g_init) {
-    a.g[0][so + k] = glam;
-    a.g[1][so + k] = gmu;
-    a.g[2][so + k] = gmxz;
-  } else {
-    a.g[0][so + k] += glam;
-    a.g[1][so + k] += gmu;
-    a.g[2][so + k] += gmxz;
+#pragma unroll
+  for (int k = 0; k < kElK; ++k) {
+    const int e = threadIdx.x + k * kThreads;
+    if (e >= kElBox) break;
+    const int r = e / kElBW, c = e - (e / kElBW) * kElBW;
+    const int gx = x0 - 2 + c, gz = z0 - 2 + r;
+    float ge = 0.0f, gf = 0.0f, gg = 0.0f, gh = 0.0f;
+    if (gx >= 0 && gx < NX && gz >= 0 && gz < NZ) {
+      const size_t q = so + (size_t)gz * NX + gx;
+      const float e1 = dt * fmaf(cxx_x[k], txx[k], czz_x[k] * tzz[k]);
+      const float e2 = dt * fmaf(cxx_z[k], txx[k], czz_z[k] * tzz[k]);
+      const float e3 = dt * mxz[k] * txz[k];
+      const float ax = a.axi[gx], az = a.azi[gz], azh = a.azh[gz], axh = a.axh[gx];
+      ge = ax == 0.0f ? e1 : fmaf(ax, a.ps_in[4][q] + e1, e1);
+      gf = az == 0.0f ? e2 : fmaf(az, a.ps_in[5][q] + e2, e2);
+      gg = azh == 0.0f ? e3 : fmaf(azh, a.ps_in[6][q] + e3, e3);
+      gh = axh == 0.0f ? e3 : fmaf(axh, a.ps_in[7][q] + e3, e3);
+    }
+    sb[0][e] = ge;
+    sb[1][e] = gf;
+    sb[2][e] = gg;
+    sb[3][e] = gh;
+  }
+}
+
+__global__ __launch_bounds__(256) void el_adj_s_kernel(ElStep a) {
+  __shared__ float sb[4][kElBox];
+  const ElTile T = el_tile(a);
+  const int NX = a.NX, NZ = a.NZ;
+  const size_t plane = (size_t)NX * NZ;
+  const size_t so = (size_t)T.shot * plane;
+  el_stage_adj_s(a, sb, so, T.x0, T.z0);
+  __syncthreads();
+  const Box gbe{sb[0], T.x0, T.z0}, gbf{sb[1], T.x0, T.z0}, gbg{sb[2], T.x0, T.z0},
+      gbh{sb[3], T.x0, T.z0};
+  const int i = T.x0 + (threadIdx.x & 63);
+  const int jb = T.z0 + (threadIdx.x >> 6) * kElRZ;
+  const float dt = a.dt, ih = a.ih;
+#pragma unroll
+  for (int r = 0; r < kElRZ; ++r) {
+    const int j = jb + r;
+    if (i >= NX || j >= NZ) continue;
+    const size_t k = (size_t)j * NX + i;
+    // Vx += (Dx-)^T gbe + (Dz+ of vx)^T gbg ;  (Dx-)^T = -Dx+
+    const float dxe = -fmaf(C2, gbe(i + 2, j) - gbe(i - 1, j), C1 * (gbe(i + 1, j) - gbe(i, j)));
+    const float dzg = dzT(a, 2, j, [&](int jj) { return gbg(i, jj); }, true);
+    // Vz += (Dz- of vz)^T gbf + (Dx+)^T gbh ;  (Dx+)^T = -Dx-
+    const float dzf = dzT(a, 3, j, [&](int jj) { return gbf(i, jj); }, false);
+    const float dxh = -fmaf(C2, gbh(i + 1, j) - gbh(i - 2, j), C1 * (gbh(i, j) - gbh(i - 1, j)));
+    a.vx[so + k] += (dxe + dzg) * ih;
+    a.vz[so + k] += (dzf + dxh) * ih;
+
+    // own cell: memory-variable adjoints and the coefficient gradients
+    const float txx = a.txx[so + k], tzz = a.tzz[so + k], txz = a.txz[so + k];
+    const float ex = dt * fmaf(a.cxx_x[k], txx, a.czz_x[k] * tzz);
+    const float ez = dt * fmaf(a.cxx_z[k], txx, a.czz_z[k] * tzz);
+    const float exz = dt * a.mxz[k] * txz;
+    if (a.axi[i] != 0.0f) a.ps_out[4][so + k] = a.bxi[i] * (a.ps_in[4][so + k] + ex);
+    if (a.azi[j] != 0.0f) a.ps_out[5][so + k] = a.bzi[j] * (a.ps_in[5][so + k] + ez);
+    if (a.azh[j] != 0.0f) a.ps_out[6][so + k] = a.bzh[j] * (a.ps_in[6][so + k] + exz);
+    if (a.axh[i] != 0.0f) a.ps_out[7][so + k] = a.bxh[i] * (a.ps_in[7][so + k] + exz);
+    const float fexx = a.trc[2][so + k], fezz = a.trc[3][so + k], fexz = a.trc[4][so + k];
+    float glam, gmu;
+    if (a.fs && j == 0) {
+      // txx += dt M exx with M = 4 mu (lambda + mu) / (lambda + 2 mu)
+      const float gM = dt * txx * fexx;
+      glam = gM * a.dM_dl[i];
+      gmu = gM * a.dM_dm[i];
+    } else {
+      glam = dt * (txx + tzz) * (fexx + fezz);
+      gmu = 2.0f * dt * fmaf(txx, fexx, tzz * fezz);
+    }
+    const float gmxz = dt * txz * fexz;
+    if (a.g_init) {
+      a.g[0][so + k] = glam;
+      a.g[1][so + k] = gmu;
+      a.g[2][so + k] = gmxz;
+    } else {
+      a.g[0][so + k] += glam;
+      a.g[1][so + k] += gmu;
+      a.g[2][so + k] += gmxz;
+    }
   }
 }
 
@@ -299,74 +401,93 @@ __global__ void el_inject_kernel(ElStep a, int n) {
   a.vz[k] = az;
 }
 
-__global__ __launch_bounds__(256) void el_adj_v_kernel(ElStep a) {
-  const int i = blockIdx.x * 64 + (threadIdx.x & 63);
-  const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
+// Stages the derivative-input adjoints of the velocity step: gba (Dx txx of
+// vx), gbb (Dz txz of vx), gbc (Dx txz of vz), gbd (Dz tzz of vz).
+__device__ __forceinline__ void el_stage_adj_v(const ElStep& a, float (*sb)[kElBox], size_t so,
+                                               int x0, int z0) {
   const int NX = a.NX, NZ = a.NZ;
-  if (i >= NX || j >= NZ) return;
-  const size_t plane = (size_t)NX * NZ;
-  const size_t so = (size_t)blockIdx.z * plane;
-  const size_t k = (size_t)j * NX + i;
-  const float dt = a.dt, ih = a.ih;
-  const float* Vx = a.vx + so;
-  const float* Vz = a.vz + so;
-  const float* Pa = a.ps_in[0] + so;
-  const float* Pb = a.ps_in[1] + so;
-  const float* Pc = a.ps_in[2] + so;
-  const float* Pd = a.ps_in[3] + so;
-  auto gba = [&](int ii, int jj) -> float {
-    if (ii < 0 || ii >= NX || jj < 0 || jj >= NZ) return 0.0f;
-    const size_t q = (size_t)jj * NX + ii;
-    const float kx = dt * a.bx[q] * Vx[q];
-    const float ax = a.axh[ii];
-    return ax == 0.0f ? kx : fmaf(ax, Pa[q] + kx, kx);
-  };
-  auto gbb = [&](int ii, int jj) -> float {
-    if (ii < 0 || ii >= NX || jj < 0 || jj >= NZ) return 0.0f;
-    const size_t q = (size_t)jj * NX + ii;
-    const float kx = dt * a.bx[q] * Vx[q];
-    const float az = a.azi[jj];
-    return az == 0.0f ? kx : fmaf(az, Pb[q] + kx, kx);
-  };
-  auto gbc = [&](int ii, int jj) -> float {
-    if (ii < 0 || ii >= NX || jj < 0 || jj >= NZ) return 0.0f;
-    const size_t q = (size_t)jj * NX + ii;
-    const float kz = dt * a.bz[q] * Vz[q];
-    const float ax = a.axi[ii];
-    return ax == 0.0f ? kz : fmaf(ax, Pc[q] + kz, kz);
-  };
-  auto gbd = [&](int ii, int jj) -> float {
-    if (ii < 0 || ii >= NX || jj < 0 || jj >= NZ) return 0.0f;
-    const size_t q = (size_t)jj * NX + ii;
-    const float kz = dt * a.bz[q] * Vz[q];
-    const float az = a.azh[jj];
-    return az == 0.0f ? kz : fmaf(az, Pd[q] + kz, kz);
-  };
-  // Txx += (Dx+)^T gba = -Dx- gba
-  const float dxa = -fmaf(C2, gba(i + 1, j) - gba(i - 2, j), C1 * (gba(i, j) - gba(i - 1, j)));
-  // Txz += (Dz- of txz)^T gbb + (Dx-)^T gbc = ... - Dx+ gbc
-  const float dzb = dzT(a, 1, j, [&](int jj) { return gbb(i, jj); }, false);
-  const float dxc = -fmaf(C2, gbc(i + 2, j) - gbc(i - 1, j), C1 * (gbc(i + 1, j) - gbc(i, j)));
-  // Tzz += (Dz+ of tzz)^T gbd
-  const float dzd = dzT(a, 0, j, [&](int jj) { return gbd(i, jj); }, true);
-  a.txx[so + k] += dxa * ih;
-  a.txz[so + k] += (dzb + dxc) * ih;
-  a.tzz[so + k] += dzd * ih;
+  const float dt = a.dt;
+  float vx[kElK], vz[kElK], bx[kElK], bz[kElK];
+#pragma unroll
+  for (int k = 0; k < kElK; ++k) {
+    const int e = threadIdx.x + k * kThreads;
+    const int r = e / kElBW, c = e - (e / kElBW) * kElBW;
+    const int gx = x0 - 2 + c, gz = z0 - 2 + r;
+    const bool ok = e < kElBox && gx >= 0 && gx < NX && gz >= 0 && gz < NZ;
+    const size_t q = ok ? (size_t)gz * NX + gx : 0;
+    vx[k] = ok ? a.vx[so + q] : 0.0f;
+    vz[k] = ok ? a.vz[so + q] : 0.0f;
+    bx[k] = ok ? a.bx[q] : 0.0f;
+    bz[k] = ok ? a.bz[q] : 0.0f;
+  }
+#pragma unroll
+  for (int k = 0; k < kElK; ++k) {
+    const int e = threadIdx.x + k * kThreads;
+    if (e >= kElBox) break;
+    const int r = e / kElBW, c = e - (e / kElBW) * kElBW;
+    const int gx = x0 - 2 + c, gz = z0 - 2 + r;
+    float ga = 0.0f, gb = 0.0f, gc = 0.0f, gd = 0.0f;
+    if (gx >= 0 && gx < NX && gz >= 0 && gz < NZ) {
+      const size_t q = so + (size_t)gz * NX + gx;
+      const float kx = dt * bx[k] * vx[k];
+      const float kz = dt * bz[k] * vz[k];
+      const float axh = a.axh[gx], az = a.azi[gz], ax = a.axi[gx], azh = a.azh[gz];
+      ga = axh == 0.0f ? kx : fmaf(axh, a.ps_in[0][q] + kx, kx);
+      gb = az == 0.0f ? kx : fmaf(az, a.ps_in[1][q] + kx, kx);
+      gc = ax == 0.0f ? kz : fmaf(ax, a.ps_in[2][q] + kz, kz);
+      gd = azh == 0.0f ? kz : fmaf(azh, a.ps_in[3][q] + kz, kz);
+    }
+    sb[0][e] = ga;
+    sb[1][e] = gb;
+    sb[2][e] = gc;
+    sb[3][e] = gd;
+  }
+}
 
-  const float vx = Vx[k], vz = Vz[k];
-  const float kx = dt * a.bx[k] * vx, kz = dt * a.bz[k] * vz;
-  if (a.axh[i] != 0.0f) a.ps_out[0][so + k] = a.bxh[i] * (Pa[k] + kx);
-  if (a.azi[j] != 0.0f) a.ps_out[1][so + k] = a.bzi[j] * (Pb[k] + kx);
-  if (a.axi[i] != 0.0f) a.ps_out[2][so + k] = a.bxi[i] * (Pc[k] + kz);
-  if (a.azh[j] != 0.0f) a.ps_out[3][so + k] = a.bzh[j] * (Pd[k] + kz);
-  const float gbx = dt * vx * a.trc[0][so + k];
-  const float gbz = dt * vz * a.trc[1][so + k];
-  if (a.g_init) {
-    a.g[3][so + k] = gbx;
-    a.g[4][so + k] = gbz;
-  } else {
-    a.g[3][so + k] += gbx;
-    a.g[4][so + k] += gbz;
+__global__ __launch_bounds__(256) void el_adj_v_kernel(ElStep a) {
+  __shared__ float sb[4][kElBox];
+  const ElTile T = el_tile(a);
+  const int NX = a.NX, NZ = a.NZ;
+  const size_t plane = (size_t)NX * NZ;
+  const size_t so = (size_t)T.shot * plane;
+  el_stage_adj_v(a, sb, so, T.x0, T.z0);
+  __syncthreads();
+  const Box gba{sb[0], T.x0, T.z0}, gbb{sb[1], T.x0, T.z0}, gbc{sb[2], T.x0, T.z0},
+      gbd{sb[3], T.x0, T.z0};
+  const int i = T.x0 + (threadIdx.x & 63);
+  const int jb = T.z0 + (threadIdx.x >> 6) * kElRZ;
+  const float dt = a.dt, ih = a.ih;
+#pragma unroll
+  for (int r = 0; r < kElRZ; ++r) {
+    const int j = jb + r;
+    if (i >= NX || j >= NZ) continue;
+    const size_t k = (size_t)j * NX + i;
+    // Txx += (Dx+)^T gba = -Dx- gba
+    const float dxa = -fmaf(C2, gba(i + 1, j) - gba(i - 2, j), C1 * (gba(i, j) - gba(i - 1, j)));
+    // Txz += (Dz- of txz)^T gbb + (Dx-)^T gbc = ... - Dx+ gbc
+    const float dzb = dzT(a, 1, j, [&](int jj) { return gbb(i, jj); }, false);
+    const float dxc = -fmaf(C2, gbc(i + 2, j) - gbc(i - 1, j), C1 * (gbc(i + 1, j) - gbc(i, j)));
+    // Tzz += (Dz+ of tzz)^T gbd
+    const float dzd = dzT(a, 0, j, [&](int jj) { return gbd(i, jj); }, true);
+    a.txx[so + k] += dxa * ih;
+    a.txz[so + k] += (dzb + dxc) * ih;
+    a.tzz[so + k] += dzd * ih;
+
+    const float vx = a.vx[so + k], vz = a.vz[so + k];
+    const float kx = dt * a.bx[k] * vx, kz = dt * a.bz[k] * vz;
+    if (a.axh[i] != 0.0f) a.ps_out[0][so + k] = a.bxh[i] * (a.ps_in[0][so + k] + kx);
+    if (a.azi[j] != 0.0f) a.ps_out[1][so + k] = a.bzi[j] * (a.ps_in[1][so + k] + kx);
+    if (a.axi[i] != 0.0f) a.ps_out[2][so + k] = a.bxi[i] * (a.ps_in[2][so + k] + kz);
+    if (a.azh[j] != 0.0f) a.ps_out[3][so + k] = a.bzh[j] * (a.ps_in[3][so + k] + kz);
+    const float gbx = dt * vx * a.trc[0][so + k];
+    const float gbz = dt * vz * a.trc[1][so + k];
+    if (a.g_init) {
+      a.g[3][so + k] = gbx;
+      a.g[4][so + k] = gbz;
+    } else {
+      a.g[3][so + k] += gbx;
+      a.g[4][so + k] += gbz;
+    }
   }
 }
 
@@ -541,7 +662,9 @@ __global__ void el_finish_kernel(const double* tot, ElCoef c, float* grad, int n
   grad[2 * mn + m] = (float)acc[2];
 }
 
-dim3 grid_of(const ElStep& a) { return dim3((a.NX + 63) / 64, (a.NZ + 3) / 4, a.nshots); }
+dim3 grid_of(const ElStep& a) {
+  return dim3(((a.NX + kTX - 1) / kTX) * ((a.NZ + kElTZ - 1) / kElTZ) * a.nshots);
+}
 
 }  // namespace
 

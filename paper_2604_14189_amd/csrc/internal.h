@@ -31,6 +31,17 @@ constexpr int kThreads = 256;
 
 inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
 
+// Work-groups of one launch are dealt to the 8 XCDs round-robin by flat index,
+// and each XCD has its own L2. xcd_spread renumbers the flat index f of n so
+// that every XCD receives one contiguous run of the logical block order
+// (consecutive tiles of a shot, then the next shot): tiles that share halo
+// cache lines then run under the same L2. It is a bijection of [0, n).
+__device__ __forceinline__ int xcd_spread(int f, int n) {
+  const int x = f & 7, k = f >> 3;
+  const int q = n >> 3, r = n & 7;
+  return x * q + min(x, r) + k;
+}
+
 // ------------------------------------------------------------------ acoustic
 // Device-side view of one time step of the acoustic recurrence (all shots of one
 // plan). Fields are [shot][NZ][NX]; x-strip memory variables [shot][NZ][2P]
