@@ -119,7 +119,10 @@ def _main(argv: Optional[list] = None):
     ap.add_argument("--lr-grid", type=float, default=10.0)
     ap.add_argument("--lr-mlp", type=float, default=1e-3)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--methods", default="grid,mlp",
+                    help="comma-separated subset of grid, mlp")
     args = ap.parse_args(argv)
+    methods = [m for m in args.methods.split(",") if m]
 
     w = synth.workload(args.workload)
     dev = torch.device("cuda:0")
@@ -144,8 +147,11 @@ def _main(argv: Optional[list] = None):
                       "rmse_start_grid": rmse(v0, v_true),
                       "rmse_start_mlp": rmse(net.forward(), v_true)}), flush=True)
 
-    runs = {"grid": GridFWI(plan, v0, wav, d_obs, lr=args.lr_grid),
-            "mlp": NeuralFWI(plan, net, wav, d_obs, lr=args.lr_mlp)}
+    runs = {}
+    if "grid" in methods:
+        runs["grid"] = GridFWI(plan, v0, wav, d_obs, lr=args.lr_grid)
+    if "mlp" in methods:
+        runs["mlp"] = NeuralFWI(plan, net, wav, d_obs, lr=args.lr_mlp)
     summary = {}
     for name, opt in runs.items():
         t0 = time.perf_counter()
@@ -162,11 +168,13 @@ def _main(argv: Optional[list] = None):
         _, Jf = l2_misfit(d, d_obs)
         summary[name] = {"J_rel_final": float(Jf.item()) / opt.J0, "rmse_final": rmse(vfin, v_true),
                          "s_per_iter": round((time.perf_counter() - t0) / args.iters, 3)}
-    summary["mlp_gain"] = {
-        "rmse_ratio_grid_over_mlp": summary["grid"]["rmse_final"] / summary["mlp"]["rmse_final"],
-        "misfit_ratio_grid_over_mlp": summary["grid"]["J_rel_final"] / summary["mlp"]["J_rel_final"]}
-    print(json.dumps({"summary": summary, "workload": args.workload, "iters": args.iters}),
-          flush=True)
+    if "grid" in summary and "mlp" in summary:
+        summary["mlp_gain"] = {
+            "rmse_ratio_grid_over_mlp": summary["grid"]["rmse_final"] / summary["mlp"]["rmse_final"],
+            "misfit_ratio_grid_over_mlp":
+                summary["grid"]["J_rel_final"] / summary["mlp"]["J_rel_final"]}
+    print(json.dumps({"summary": summary, "workload": args.workload, "iters": args.iters,
+                      "lr_grid": args.lr_grid, "lr_mlp": args.lr_mlp}), flush=True)
 
 
 def _init_theta(seed: int) -> np.ndarray:
