@@ -392,15 +392,17 @@ struct PmlGeom {
   static constexpr int BH = TZ + 2 * hz;
   static constexpr int XW = kTX + 8;     // x ring (4-column halo)
   static constexpr int ZH = TZ + 8;      // z ring (4-row halo)
-  // forward LDS: field box, psi_x ring, psi_z ring
+  // forward LDS: field box, psi_x ring, psi_z ring, C-PML (a, b) along the
+  // box columns and rows
   static constexpr int NB = BH * BW;
   static constexpr int NPX = HX ? TZ * XW : 0;
   static constexpr int NPZ = HZ ? ZH * kTX : 0;
-  static constexpr int kFwdFloats = NB + NPX + NPZ;
-  // adjoint LDS: Qbar_x (tile rows, x halo hx), Qbar_z (tile columns, z halo hz), T rings
+  static constexpr int kFwdFloats = NB + NPX + NPZ + 2 * BW + 2 * BH;
+  // adjoint LDS: Qbar_x (tile rows, x halo hx), Qbar_z (tile columns, z halo hz),
+  // T rings, C-PML (a, b) along the ring columns and rows
   static constexpr int NQX = TZ * BW;
   static constexpr int NQZ = BH * kTX;
-  static constexpr int kAdjFloats = NQX + NQZ + NPX + NPZ;
+  static constexpr int kAdjFloats = NQX + NQZ + NPX + NPZ + 2 * XW + 2 * ZH;
 };
 
 // LDS floats of the PML kernels: x frame (largest general variant, both axes)
@@ -441,6 +443,10 @@ __device__ __forceinline__ void ac_fwd_pml_body(const AcStep& a, const int tile,
   float* sb = lds;              // p^n: rows z0-hz .., columns x0-hx ..
   float* spx = lds + NB;        // psi_x^n: tile rows, columns x0-4 ..
   float* spz = lds + NB + NPX;  // psi_z^n: rows z0-4 .., tile columns
+  float* tax = spz + NPZ;       // a_x, b_x at the box columns; a_z, b_z at the box rows
+  float* tbx = tax + BW;
+  float* taz = tbx + BW;
+  float* tbz = taz + G::BH;
   const int tid = threadIdx.x;
   const int lx = tid & 63;
   const int zb = (tid >> 6) * RZ;
@@ -482,6 +488,21 @@ __device__ __forceinline__ void ac_fwd_pml_body(const AcStep& a, const int tile,
       opz[k] = row >= 0 ? a.psz_in[shot * zsp + (size_t)row * NX + gxx] : 0.0f;
     }
   }
+  // C-PML coefficients of the box columns (threads 0..BW-1) and rows (128..)
+  float ta = 0.0f, tb = 0.0f;
+  if (tid < BW) {
+    const int gxx = x0 - hx + tid;
+    if (HX && gxx >= 0 && gxx < NX) {
+      ta = a.ax[gxx];
+      tb = a.bx[gxx];
+    }
+  } else if (tid >= 128 && tid < 128 + G::BH) {
+    const int gz = z0 - hz + (tid - 128);
+    if (HZ && gz >= 0 && gz < NZ) {
+      ta = a.az[gz];
+      tb = a.bz[gz];
+    }
+  }
   const int xcol = (HX && gx < NX) ? xstrip_col(gx, NX, P) : -1;
   float pp[RZ], cs[RZ], zx[RZ], zz[RZ];
 #pragma unroll
@@ -500,6 +521,13 @@ __device__ __forceinline__ void ac_fwd_pml_body(const AcStep& a, const int tile,
     const int e = tid + k * kThreads;
     if (e < NB) sb[e] = vb[k];
   }
+  if (tid < BW) {
+    tax[tid] = ta;
+    tbx[tid] = tb;
+  } else if (tid >= 128 && tid < 128 + G::BH) {
+    taz[tid - 128] = ta;
+    tbz[tid - 128] = tb;
+  }
   __syncthreads();
 
   // memory variables on the halo rings (written back for the piece's own cells)
@@ -513,7 +541,7 @@ __device__ __forceinline__ void ac_fwd_pml_body(const AcStep& a, const int tile,
       const int col = (gz < NZ && gxx >= 0 && gxx < NX) ? xstrip_col(gxx, NX, P) : -1;
       float ps = 0.0f;
       if (col >= 0) {
-        ps = fmaf(a.ax[gxx], d1s(&sb[(r + hz) * BW + c + hx - 4], 1), a.bx[gxx] * opx[k]);
+        ps = fmaf(tax[c + hx - 4], d1s(&sb[(r + hz) * BW + c + hx - 4], 1), tbx[c + hx - 4] * opx[k]);
         if (c >= 4 && c < 4 + kTX) a.psx_out[shot * xsp + (size_t)gz * P2 + col] = ps;
       }
       spx[e] = ps;
@@ -529,13 +557,13 @@ __device__ __forceinline__ void ac_fwd_pml_body(const AcStep& a, const int tile,
       const int row = (gxx < NX && gz >= 0 && gz < NZ) ? zstrip_row(gz, NZ, P) : -1;
       float ps = 0.0f;
       if (row >= 0) {
-        ps = fmaf(a.az[gz], d1s(&sb[(r + hz - 4) * BW + c + hx], BW), a.bz[gz] * opz[k]);
+        ps = fmaf(taz[r + hz - 4], d1s(&sb[(r + hz - 4) * BW + c + hx], BW), tbz[r + hz - 4] * opz[k]);
         if (r >= 4 && r < 4 + TZ) a.psz_out[shot * zsp + (size_t)row * NX + gxx] = ps;
       }
       spz[e] = ps;
     }
   }
-  if constexpr (HX || HZ) __syncthreads();
+  __syncthreads();
 
   float win[RZ + 8];
 #pragma unroll
@@ -559,13 +587,13 @@ __device__ __forceinline__ void ac_fwd_pml_body(const AcStep& a, const int tile,
       const int idx = gz * NX + gx;
       const size_t gi = shot * plane + idx;
       if (HX && xcol >= 0) {
-        const float zeta = fmaf(a.ax[gx], Bx, a.bx[gx] * zx[r]);
+        const float zeta = fmaf(tax[lx + hx], Bx, tbx[lx + hx] * zx[r]);
         a.zex_out[shot * xsp + (size_t)gz * P2 + xcol] = zeta;
         Bx = Bx + zeta;
       }
       const int zrow = HZ ? zstrip_row(gz, NZ, P) : -1;
       if (zrow >= 0) {
-        const float zeta = fmaf(a.az[gz], Bz, a.bz[gz] * zz[r]);
+        const float zeta = fmaf(taz[zb + r + hz], Bz, tbz[zb + r + hz] * zz[r]);
         a.zez_out[shot * zsp + (size_t)zrow * NX + gx] = zeta;
         Bz = Bz + zeta;
       }
@@ -599,6 +627,10 @@ __device__ __forceinline__ void ac_adj_pml_body(const AcStep& a, const int tile,
   float* sqz = lds + NQX;               // Qbar_z: rows z0-hz .., tile columns
   float* stx = lds + NQX + NQZ;         // T_x: tile rows, columns x0-4 ..
   float* stz = lds + NQX + NQZ + NTX;   // T_z: rows z0-4 .., tile columns
+  float* tax = stz + NTZ;               // a_x, b_x at the ring columns, a_z, b_z at the ring rows
+  float* tbx = tax + XW;
+  float* taz = tbx + XW;
+  float* tbz = taz + G::ZH;
   const int tid = threadIdx.x;
   const int lx = tid & 63;
   const int zb = (tid >> 6) * RZ;
@@ -609,8 +641,23 @@ __device__ __forceinline__ void ac_adj_pml_body(const AcStep& a, const int tile,
   const int gx = x0 + lx;
   const float* cur = a.cur + shot * plane;
 
+  // C-PML coefficients of the ring columns (threads 0..XW-1) and rows (128..)
+  float ta = 0.0f, tb = 0.0f;
+  if (tid < XW) {
+    const int gxx = x0 - 4 + tid;
+    if (HX && gxx >= 0 && gxx < NX) {
+      ta = a.ax[gxx];
+      tb = a.bx[gxx];
+    }
+  } else if (tid >= 128 && tid < 128 + G::ZH) {
+    const int gz = z0 - 4 + (tid - 128);
+    if (HZ && gz >= 0 && gz < NZ) {
+      ta = a.az[gz];
+      tb = a.bz[gz];
+    }
+  }
   {
-    float lx_[KQX], cx_[KQX], zx_[HX ? KQX : 1];
+    float lx_[KQX], cx_[KQX], zx_[HX ? KQX : 1], ax_[HX ? KQX : 1], bx_[HX ? KQX : 1];
 #pragma unroll
     for (int k = 0; k < KQX; ++k) {
       const int e = tid + k * kThreads;
@@ -623,9 +670,11 @@ __device__ __forceinline__ void ac_adj_pml_body(const AcStep& a, const int tile,
       if constexpr (HX) {
         const int col = ok ? xstrip_col(gxx, NX, P) : -1;
         zx_[k] = col >= 0 ? a.zex_in[shot * xsp + (size_t)gz * P2 + col] : 0.0f;
+        ax_[k] = col >= 0 ? a.ax[gxx] : 0.0f;
+        bx_[k] = col >= 0 ? a.bx[gxx] : 0.0f;
       }
     }
-    float lz_[KQZ], cz_[KQZ], zz_[HZ ? KQZ : 1];
+    float lz_[KQZ], cz_[KQZ], zz_[HZ ? KQZ : 1], az_[HZ ? KQZ : 1], bz_[HZ ? KQZ : 1];
 #pragma unroll
     for (int k = 0; k < KQZ; ++k) {
       const int e = tid + k * kThreads;
@@ -638,6 +687,8 @@ __device__ __forceinline__ void ac_adj_pml_body(const AcStep& a, const int tile,
       if constexpr (HZ) {
         const int row = ok ? zstrip_row(gz, NZ, P) : -1;
         zz_[k] = row >= 0 ? a.zez_in[shot * zsp + (size_t)row * NX + gxx] : 0.0f;
+        az_[k] = row >= 0 ? a.az[gz] : 0.0f;
+        bz_[k] = row >= 0 ? a.bz[gz] : 0.0f;
       }
     }
 #pragma unroll
@@ -651,9 +702,9 @@ __device__ __forceinline__ void ac_adj_pml_body(const AcStep& a, const int tile,
         const int col = (gz < NZ && gxx >= 0 && gxx < NX) ? xstrip_col(gxx, NX, P) : -1;
         if (col >= 0) {
           const float zbar = zx_[k] + q;
-          q = q + a.ax[gxx] * zbar;
+          q = q + ax_[k] * zbar;
           if (c >= hx && c < hx + kTX)
-            a.zex_out[shot * xsp + (size_t)gz * P2 + col] = a.bx[gxx] * zbar;
+            a.zex_out[shot * xsp + (size_t)gz * P2 + col] = bx_[k] * zbar;
         }
       }
       sqx[e] = q;
@@ -669,9 +720,9 @@ __device__ __forceinline__ void ac_adj_pml_body(const AcStep& a, const int tile,
         const int row = (gxx < NX && gz >= 0 && gz < NZ) ? zstrip_row(gz, NZ, P) : -1;
         if (row >= 0) {
           const float zbar = zz_[k] + q;
-          q = q + a.az[gz] * zbar;
+          q = q + az_[k] * zbar;
           if (r >= hz && r < hz + TZ)
-            a.zez_out[shot * zsp + (size_t)row * NX + gxx] = a.bz[gz] * zbar;
+            a.zez_out[shot * zsp + (size_t)row * NX + gxx] = bz_[k] * zbar;
         }
       }
       sqz[e] = q;
@@ -712,6 +763,13 @@ __device__ __forceinline__ void ac_adj_pml_body(const AcStep& a, const int tile,
       if (!a.g_init) gg[r] = a.g[gi];
     }
   }
+  if (tid < XW) {
+    tax[tid] = ta;
+    tbx[tid] = tb;
+  } else if (tid >= 128 && tid < 128 + G::ZH) {
+    taz[tid - 128] = ta;
+    tbz[tid - 128] = tb;
+  }
   __syncthreads();
 
   if constexpr (HX) {
@@ -725,8 +783,8 @@ __device__ __forceinline__ void ac_adj_pml_body(const AcStep& a, const int tile,
       float t = 0.0f;
       if (col >= 0) {
         const float psb = ox[k] - d1s(&sqx[r * BW + c + hx - 4], 1);
-        t = a.ax[gxx] * psb;
-        if (c >= 4 && c < 4 + kTX) a.psx_out[shot * xsp + (size_t)gz * P2 + col] = a.bx[gxx] * psb;
+        t = tax[c] * psb;
+        if (c >= 4 && c < 4 + kTX) a.psx_out[shot * xsp + (size_t)gz * P2 + col] = tbx[c] * psb;
       }
       stx[e] = t;
     }
@@ -742,8 +800,8 @@ __device__ __forceinline__ void ac_adj_pml_body(const AcStep& a, const int tile,
       float t = 0.0f;
       if (row >= 0) {
         const float psb = oz[k] - d1s(&sqz[(r + hz - 4) * kTX + c], kTX);
-        t = a.az[gz] * psb;
-        if (r >= 4 && r < 4 + TZ) a.psz_out[shot * zsp + (size_t)row * NX + gxx] = a.bz[gz] * psb;
+        t = taz[r] * psb;
+        if (r >= 4 && r < 4 + TZ) a.psz_out[shot * zsp + (size_t)row * NX + gxx] = tbz[r] * psb;
       }
       stz[e] = t;
     }

@@ -67,11 +67,14 @@ class GridFWI:
 
 
 class NeuralFWI:
-    """Adam on the MLP parameters; the velocity is the network's output."""
+    """Adam on the MLP parameters; the velocity is the network's output. The
+    network's Adam state starts from zero (moments left by a pre-fit belong to
+    a different loss and would swamp the FWI gradients)."""
 
     def __init__(self, plan: Plan, net: MLPVelocity, wavelet: torch.Tensor, d_obs: torch.Tensor,
                  lr: float = 1e-3, eps: float = 1e-8):
         self.plan, self.net, self.wav, self.d_obs = plan, net, wavelet, d_obs
+        net.reset_optimizer()
         dev = net.theta.device
         self.d = torch.empty(plan.gathers_shape(), dtype=torch.float32, device=dev)
         self.g = torch.empty((1, net.nz, net.nx), dtype=torch.float32, device=dev)
@@ -97,8 +100,9 @@ class NeuralFWI:
 
 def prefit(net: MLPVelocity, target: torch.Tensor, steps: int, lr: float = 1e-3) -> float:
     """Fit the network to a velocity model by least squares (1/2 sum (v - target)^2),
-    with the same kernels; returns the final RMS misfit in m/s."""
+    with the same kernels, from a fresh Adam state; returns the final RMS misfit in m/s."""
     target = target.contiguous()
+    net.reset_optimizer()
     L = None
     for _ in range(steps):
         v = net.forward()

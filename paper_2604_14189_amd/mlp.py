@@ -132,6 +132,12 @@ class MLPVelocity:
         raw = self.work[off: off + 4 * n * 2].view(torch.int16).view(4, self.M, 256)
         return [(raw[l].to(torch.int32) << 16).view(torch.float32) for l in range(4)]
 
+    def reset_optimizer(self):
+        """Zero the Adam moments and step count (start of a new optimisation)."""
+        self.m.zero_()
+        self.v2.zero_()
+        self.t = 0
+
     def step(self, grad: torch.Tensor, lr: float = 1e-3, b1: float = 0.9, b2: float = 0.999,
              eps: float = 1e-8):
         """Adam on the float32 master weights, then refresh the bf16 copies."""
