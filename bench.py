@@ -33,7 +33,7 @@ METRIC = "Gcell-updates/s fwd+adj; batched vs per-shot FWI gradient time at 1e-4
 # WRITE_SIZE runs of this benchmark, each scaled by what the same counter reads
 # for a plain device copy of known size (--calibrate-copy). Keyed by kernel
 # class; valid only while the kernel source hashes to the recorded value.
-TRAFFIC = {"adj_main": {"bytes_per_launch": 981739276, "source": "c1407dd607838f67"}}
+TRAFFIC = {"adj_int": {"bytes_per_launch": 474894869, "source": "6e43a2568fd1faed"}}
 
 
 def _source_hash() -> str:
@@ -304,7 +304,7 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    plan.set_profiling(True)
+    plan.set_profiling(True, period=10)  # every 10th step's launches
     t0 = time.perf_counter()
     for _ in range(args.steps):
         g, J = step()
@@ -320,22 +320,28 @@ def main():
         per_shot = per_shot_compare(sw, torch, w, v0, wav, d_obs, args.per_shot_sample,
                                     (args.rz, args.pml_rz), dt)
 
-    # dominant kernel class by total time. Algorithmic bytes per cell-update:
+    # Dominant kernel by total time. Algorithmic bytes per cell-update:
     # interior kernel forward 16 B (read p^n, p^{n-1}, Cs; write p^{n+1}),
     # recompute 20 B (+ write B^n), adjoint 28 B (read lambda^{n+1},
     # lambda^{n+2}, Cs, B^n, g; write lambda^n, g), 24 B on the first step of a
-    # segment (g written, not read). The PML kernel moves the same per cell plus
-    # 16 B per C-PML axis at each strip cell (psi and zeta read and written).
+    # segment (g written, not read). The C-PML kernels move the same per cell
+    # plus 16 B per C-PML axis at each strip cell (psi and zeta read and written).
     k = w.ckpt_every
-    n_int, n_pml, TZ = plan.tiles()
-    int_cells = n_int * 64 * TZ
-    frame_cells = NX * NZ - int_cells
-    strip_cells = 2 * w.pml * NZ + 2 * w.pml * NX
+    t = plan.tiles()
+    TZ = t["rows"]
+    wz = (t["x1"] - t["x0"]) * 64                       # z-frame columns
+    int_cells = t["interior"] * 64 * TZ
+    z_cells = wz * (t["z0"] * TZ + NZ - t["z1"] * TZ) if t["interior"] else 0
+    x_cells = NX * NZ - int_cells - z_cells
+    P = w.pml
+    z_strip = 2 * P * wz if t["interior"] else 0        # z-strip cells in the z frame
+    x_strip = 2 * P * NZ + 2 * P * NX - z_strip         # strip cells (per axis) in the x frame
     base = {"fwd": 16.0, "rec": 20.0, "adj": (28.0 * (k - 1) + 24.0) / k}
     per_launch = {}
     for ph, b in base.items():
-        per_launch[ph + "_main"] = b * int_cells * w.nshots
-        per_launch[ph + "_band"] = (b * frame_cells + 16.0 * strip_cells) * w.nshots
+        per_launch[ph + "_int"] = b * int_cells * w.nshots
+        per_launch[ph + "_zpml"] = (b * z_cells + 16.0 * z_strip) * w.nshots
+        per_launch[ph + "_xpml"] = (b * x_cells + 16.0 * x_strip) * w.nshots
     shares = {kk: vv[1] for kk, vv in kt.items()}
     dom = max(shares, key=lambda kk: shares[kk])
     roof = None
@@ -378,7 +384,7 @@ def main():
         "roofline": roof,
         "per_shot": per_shot,
         "kernels": kernels,
-        "tiles": {"interior": n_int, "frame": n_pml, "rows": TZ},
+        "tiles": t,
     }
     if not args.no_extras and not args.nt:
         plan.release_workspace()

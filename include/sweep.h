@@ -113,12 +113,15 @@ size_t sweep_plan_workspace_bytes(const sweep_plan* plan, int for_backward);
 int sweep_plan_padded(const sweep_plan* plan, int* NX, int* NZ);
 
 /* Acoustic tiling under the current tuning: the padded grid is cut into tiles
- * of 64 columns x tile_rows rows. interior_tiles whole tiles hold no C-PML cell
- * (no cell within pml + 4 of an edge) and are advanced by the interior kernel
- * (16 bytes per cell-update forward); the frame_tiles others by the PML kernel.
- * EINVAL for an elastic plan or a null pointer. */
+ * of 64 columns x tile_rows rows. The interior tiles hold no C-PML cell (no
+ * cell within pml + 4 of an edge) and form the rectangle of tile columns
+ * [rect[0], rect[1]) x tile rows [rect[2], rect[3]) (all zero when empty);
+ * they are advanced by the interior kernel (16 bytes per cell-update forward).
+ * The frame_tiles others are advanced by the C-PML kernels: the z frame (the
+ * rectangle's columns above and below it) and the x frame (all other tile
+ * columns). rect may be NULL. EINVAL for an elastic plan or a null pointer. */
 int sweep_plan_tiles(const sweep_plan* plan, int* interior_tiles, int* frame_tiles,
-                     int* tile_rows);
+                     int* tile_rows, int* rect);
 
 /* Forward modelling of every shot.
  *   d_model   [nparam][nz][nx]: acoustic vp (nparam 1); elastic vp, vs, rho (3)
@@ -145,12 +148,14 @@ int sweep_backward(sweep_plan* plan, const float* d_resid, float* d_grad, void* 
 
 /* Kernel timing for measurement tools. When enabled, every launch of the step
  * kernels is bracketed by a pair of hipEvents recorded on the call's stream
- * (the events add a few microseconds per launch). Classes:
- *   0 forward main (whole-grid stencil), 1 forward C-PML bands (x and z band
- *   kernels of one step, timed together), 2 adjoint main, 3 adjoint bands,
- *   4 recompute main (also stores B^n), 5 recompute bands.
+ * (the events add a few microseconds per launch). Acoustic classes, for the
+ * forward (0-2), the adjoint (3-5) and the segment recompute that also stores
+ * B^n (6-8): interior-tile kernel, z-frame C-PML kernel, x-frame C-PML kernel.
+ * An elastic plan times each whole step (both of its kernels) in classes 0, 3
+ * and 6.
+ * enable: 0 off; n >= 1 times the launches of every n-th step (n = 1: all).
  * sweep_plan_set_profiling resets the counters; sweep_plan_kernel_time waits for
- * the recorded events and returns the number of launches and their summed
+ * the recorded events and returns the number of timed launches and their summed
  * duration in milliseconds since the reset. */
 int sweep_plan_set_profiling(sweep_plan* plan, int enable);
 int sweep_plan_kernel_time(sweep_plan* plan, int kernel_class, int* launches, double* total_ms);

@@ -54,7 +54,7 @@ _SIGS = {
                                          ctypes.POINTER(ctypes.c_int)]),
     "sweep_plan_tiles": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int),
                                         ctypes.POINTER(ctypes.c_int),
-                                        ctypes.POINTER(ctypes.c_int)]),
+                                        ctypes.POINTER(ctypes.c_int), ctypes.c_void_p]),
     "sweep_forward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
                                      ctypes.c_int, ctypes.c_void_p]),

@@ -56,6 +56,12 @@ __device__ __forceinline__ float d1c(float p1, float m1, float p2, float m2, flo
   return fmaf(kB4, p4 - m4, s);
 }
 
+// Per-cell streams that a step touches exactly once (p^{n-1} in, p^{n+1} out,
+// B^n, the gradient partial) carry the non-temporal hint, so they do not evict
+// the halo lines that neighbouring tiles read again from L2.
+__device__ __forceinline__ float ld_nt(const float* p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ void st_nt(float* p, float v) { __builtin_nontemporal_store(v, p); }
+
 // Stencils on a strided LDS array centred at f.
 __device__ __forceinline__ float d2s(const float* f, int st) {
   return d2c(f[0], f[st], f[-st], f[2 * st], f[-2 * st], f[3 * st], f[-3 * st], f[4 * st],
@@ -250,7 +256,7 @@ __device__ __forceinline__ void adj_store(const AcStep& a, int shot, int tile, i
 #pragma unroll
   for (int r = 0; r < RZ; ++r) {
     const int gz = z0 + zb + r;
-    if (gx < NX && gz < NZ) a.next[shot * plane + (size_t)gz * NX + gx] = out[r];
+    if (gx < NX && gz < NZ) st_nt(&a.next[shot * plane + (size_t)gz * NX + gx], out[r]);
   }
 }
 
@@ -282,10 +288,14 @@ __device__ __forceinline__ void ac_fwd_int_body(const AcStep& a, const int tile,
     cs[r] = 0.0f;
     if (inside || (gx < NX && gz < NZ)) {
       const int idx = gz * NX + gx;
-      pp[r] = a.prev[shot * plane + idx];
+      pp[r] = ld_nt(&a.prev[shot * plane + idx]);
       cs[r] = a.Cs[idx];
     }
   }
+  // source cell and sample with the first loads (a later wait on them would
+  // also wait for this tile's stores)
+  const int src = a.src_cell[shot];
+  const float sw = a.w * a.wavelet[(size_t)shot * a.nt + a.n];
   stage_box<RZ, false>(sp, a.cur + shot * plane, nullptr, x0, z0, NX, NZ, inside);
   __syncthreads();
 
@@ -293,8 +303,6 @@ __device__ __forceinline__ void ac_fwd_int_body(const AcStep& a, const int tile,
 #pragma unroll
   for (int m = 0; m < RZ + 8; ++m) win[m] = sp[(zb + m) * T::LW + lx + 4];
 
-  const int src = a.src_cell[shot];
-  const float sw = a.w * a.wavelet[(size_t)shot * a.nt + a.n];
   float out[RZ];
 #pragma unroll
   for (int r = 0; r < RZ; ++r) {
@@ -311,8 +319,8 @@ __device__ __forceinline__ void ac_fwd_int_body(const AcStep& a, const int tile,
       const size_t gi = shot * plane + idx;
       pn = fmaf(cs[r], L, 2.0f * c - pp[r]);
       if (idx == src) pn += sw;
-      a.next[gi] = pn;
-      if (a.B_out) a.B_out[gi] = L;
+      st_nt(&a.next[gi], pn);
+      if (a.B_out) st_nt(&a.B_out[gi], L);
     }
     out[r] = pn;
   }
@@ -342,9 +350,9 @@ __device__ __forceinline__ void ac_adj_int_body(const AcStep& a, const int tile,
     if (inside || (gx < NX && gz < NZ)) {
       const size_t gi = shot * plane + (size_t)gz * NX + gx;
       p1[r] = a.cur[gi];
-      pp[r] = a.prev[gi];
-      bb[r] = a.B_in[gi];
-      if (!a.g_init) gg[r] = a.g[gi];
+      pp[r] = ld_nt(&a.prev[gi]);
+      bb[r] = ld_nt(&a.B_in[gi]);
+      if (!a.g_init) gg[r] = ld_nt(&a.g[gi]);
     }
   }
   stage_box<RZ, true>(sq, a.cur + shot * plane, a.Cs, x0, z0, NX, NZ, inside);
@@ -367,7 +375,7 @@ __device__ __forceinline__ void ac_adj_int_body(const AcStep& a, const int tile,
     if (inside || (gx < NX && gz < NZ)) {
       const size_t gi = shot * plane + (size_t)gz * NX + gx;
       const float gb = p1[r] * bb[r];
-      a.g[gi] = a.g_init ? gb : gg[r] + gb;
+      st_nt(&a.g[gi], a.g_init ? gb : gg[r] + gb);
       lam = ((2.0f * p1[r] - pp[r]) + sxx) + szz;
     }
     out[r] = lam;
@@ -503,6 +511,8 @@ __device__ __forceinline__ void ac_fwd_pml_body(const AcStep& a, const int tile,
       tb = a.bz[gz];
     }
   }
+  const int src = a.src_cell[shot];
+  const float sw = a.w * a.wavelet[(size_t)shot * a.nt + a.n];
   const int xcol = (HX && gx < NX) ? xstrip_col(gx, NX, P) : -1;
   float pp[RZ], cs[RZ], zx[RZ], zz[RZ];
 #pragma unroll
@@ -510,7 +520,7 @@ __device__ __forceinline__ void ac_fwd_pml_body(const AcStep& a, const int tile,
     const int gz = z0 + zb + r;
     const bool ok = gx < NX && gz < NZ;
     const size_t idx = ok ? (size_t)gz * NX + gx : 0;
-    pp[r] = ok ? a.prev[shot * plane + idx] : 0.0f;
+    pp[r] = ok ? ld_nt(&a.prev[shot * plane + idx]) : 0.0f;
     cs[r] = ok ? a.Cs[idx] : 0.0f;
     zx[r] = (HX && ok && xcol >= 0) ? a.zex_in[shot * xsp + (size_t)gz * P2 + xcol] : 0.0f;
     const int zrow = (HZ && ok) ? zstrip_row(gz, NZ, P) : -1;
@@ -568,8 +578,6 @@ __device__ __forceinline__ void ac_fwd_pml_body(const AcStep& a, const int tile,
   float win[RZ + 8];
 #pragma unroll
   for (int m = 0; m < RZ + 8; ++m) win[m] = sb[(zb + hz - 4 + m) * BW + lx + hx];
-  const int src = a.src_cell[shot];
-  const float sw = a.w * a.wavelet[(size_t)shot * a.nt + a.n];
   float out[RZ];
 #pragma unroll
   for (int r = 0; r < RZ; ++r) {
@@ -600,8 +608,8 @@ __device__ __forceinline__ void ac_fwd_pml_body(const AcStep& a, const int tile,
       const float B = Bx + Bz;
       pn = fmaf(cs[r], B, 2.0f * c - pp[r]);
       if (idx == src) pn += sw;
-      a.next[gi] = pn;
-      if (a.B_out) a.B_out[gi] = B;
+      st_nt(&a.next[gi], pn);
+      if (a.B_out) st_nt(&a.B_out[gi], B);
     }
     out[r] = pn;
   }
@@ -758,9 +766,9 @@ __device__ __forceinline__ void ac_adj_pml_body(const AcStep& a, const int tile,
     if (gx < NX && gz < NZ) {
       const size_t gi = shot * plane + (size_t)gz * NX + gx;
       p1[r] = a.cur[gi];
-      pp[r] = a.prev[gi];
-      bb[r] = a.B_in[gi];
-      if (!a.g_init) gg[r] = a.g[gi];
+      pp[r] = ld_nt(&a.prev[gi]);
+      bb[r] = ld_nt(&a.B_in[gi]);
+      if (!a.g_init) gg[r] = ld_nt(&a.g[gi]);
     }
   }
   if (tid < XW) {
@@ -821,7 +829,7 @@ __device__ __forceinline__ void ac_adj_pml_body(const AcStep& a, const int tile,
     if (gx < NX && gz < NZ) {
       const size_t gi = shot * plane + (size_t)gz * NX + gx;
       const float gb = p1[r] * bb[r];
-      a.g[gi] = a.g_init ? gb : gg[r] + gb;
+      st_nt(&a.g[gi], a.g_init ? gb : gg[r] + gb);
       lam = ((2.0f * p1[r] - pp[r]) + dxx) + dzz;
       if constexpr (HX) lam = lam - tx;
       if constexpr (HZ) lam = lam - tz;
@@ -999,20 +1007,25 @@ void launch_frame_batch(const AcBatch& b, int prz, dim3 g, hipStream_t s) {
   }
 }
 
-// ev (optional): start/stop event pairs recorded around the interior launch
-// (ev[0], ev[1]) and the two frame launches (ev[2], ev[3]). a.nsub = a.tz / (4 prz).
+// ev (optional): start/stop event pairs around the interior launch (ev[0],
+// ev[1]), the z-frame launch (ev[2], ev[3]) and the x-frame launch (ev[4],
+// ev[5]); a null pair is not recorded. a.nsub = a.tz / (4 prz).
 template <bool kAdj>
 int launch_step(const AcStep& a, int rz, int prz, hipStream_t s, hipEvent_t* ev) {
-  if (a.n_xf + a.n_zf > 0) {
-    if (ev) SWEEP_HIP(hipEventRecord(ev[2], s));
-    if (a.n_zf > 0) launch_frame<kAdj, true>(a, prz, dim3(a.n_zf * a.nsub * a.nshots), s);
-    if (a.n_xf > 0) launch_frame<kAdj, false>(a, prz, dim3(a.n_xf * a.nsub * a.nshots), s);
-    if (ev) SWEEP_HIP(hipEventRecord(ev[3], s));
+  if (a.n_zf > 0) {
+    if (ev && ev[2]) SWEEP_HIP(hipEventRecord(ev[2], s));
+    launch_frame<kAdj, true>(a, prz, dim3(a.n_zf * a.nsub * a.nshots), s);
+    if (ev && ev[3]) SWEEP_HIP(hipEventRecord(ev[3], s));
+  }
+  if (a.n_xf > 0) {
+    if (ev && ev[4]) SWEEP_HIP(hipEventRecord(ev[4], s));
+    launch_frame<kAdj, false>(a, prz, dim3(a.n_xf * a.nsub * a.nshots), s);
+    if (ev && ev[5]) SWEEP_HIP(hipEventRecord(ev[5], s));
   }
   if (a.n_int > 0) {
-    if (ev) SWEEP_HIP(hipEventRecord(ev[0], s));
+    if (ev && ev[0]) SWEEP_HIP(hipEventRecord(ev[0], s));
     launch_interior<kAdj>(a, rz, dim3(a.n_int * a.nshots), s);
-    if (ev) SWEEP_HIP(hipEventRecord(ev[1], s));
+    if (ev && ev[1]) SWEEP_HIP(hipEventRecord(ev[1], s));
   }
   SWEEP_HIP(hipGetLastError());
   return SWEEP_OK;

@@ -29,12 +29,14 @@ KernelTimer::~KernelTimer() {
 
 void KernelTimer::reset() {
   for (int c = 0; c < kNumClasses; ++c) used[c] = 0;
+  calls = 0;
 }
 
-hipEvent_t* KernelTimer::take(int ci, int cf) {
-  if (!on) return nullptr;
-  const int cls[2] = {ci, cf};
-  for (int k = 0; k < 2; ++k) {
+hipEvent_t* KernelTimer::take(int ci, int cz, int cx) {
+  if (!on || (calls++ % period) != 0) return nullptr;
+  const int cls[3] = {ci, cz, cx};
+  for (int k = 0; k < 3; ++k) {
+    six[2 * k] = six[2 * k + 1] = nullptr;
     if (cls[k] < 0) continue;
     std::vector<hipEvent_t>& v = ev[cls[k]];
     while (v.size() < used[cls[k]] + 2) {
@@ -42,11 +44,11 @@ hipEvent_t* KernelTimer::take(int ci, int cf) {
       if (hipEventCreate(&e) != hipSuccess) return nullptr;
       v.push_back(e);
     }
-    quad[2 * k] = v[used[cls[k]]];
-    quad[2 * k + 1] = v[used[cls[k]] + 1];
+    six[2 * k] = v[used[cls[k]]];
+    six[2 * k + 1] = v[used[cls[k]] + 1];
     used[cls[k]] += 2;
   }
-  return quad;
+  return six;
 }
 
 // ------------------------------------------------------------------ layout
@@ -310,7 +312,7 @@ int ac_forward_enqueue(sweep_plan* p, const float* model, const float* wavelet, 
   for (int n = 0; n < p->pb.nt; ++n) {
     AcStep a;
     if ((rc = ac_fwd_step_args(p, work, L, n, gathers, save, s, a))) return rc;
-    if ((rc = ac_launch_fwd(a, p->tune.rz, p->tune.pml_rz, s, p->timer.take(kFwdMain, kFwdBand)))) return rc;
+    if ((rc = ac_launch_fwd(a, p->tune.rz, p->tune.pml_rz, s, p->timer.take(kFwdInt, kFwdZ, kFwdX)))) return rc;
   }
   return SWEEP_OK;
 }
@@ -401,11 +403,11 @@ int ac_backward_enqueue(sweep_plan* p, const float* resid, float* grad, void* wo
     if ((rc = ac_bwd_restore(p, work, L, sg, s))) return rc;
     for (int n = n0; n < n1; ++n) {
       const AcStep a = ac_rec_step_args(p, work, L, n, n - n0);
-      if ((rc = ac_launch_fwd(a, p->tune.rz, p->tune.pml_rz, s, p->timer.take(kRecMain, kRecBand)))) return rc;
+      if ((rc = ac_launch_fwd(a, p->tune.rz, p->tune.pml_rz, s, p->timer.take(kRecInt, kRecZ, kRecX)))) return rc;
     }
     for (int n = n1 - 1; n >= n0; --n) {
       const AcStep a = ac_adj_step_args(p, work, L, resid, n, n0, n1);
-      if ((rc = ac_launch_adj(a, p->tune.rz, p->tune.pml_rz, s, p->timer.take(kAdjMain, kAdjBand)))) return rc;
+      if ((rc = ac_launch_adj(a, p->tune.rz, p->tune.pml_rz, s, p->timer.take(kAdjInt, kAdjZ, kAdjX)))) return rc;
     }
     if ((rc = ac_bwd_fold(p, work, L, s))) return rc;
   }
@@ -719,7 +721,7 @@ extern "C" int sweep_plan_padded(const sweep_plan* p, int* NX, int* NZ) {
 }
 
 extern "C" int sweep_plan_tiles(const sweep_plan* p, int* interior_tiles, int* frame_tiles,
-                                int* tile_rows) {
+                                int* tile_rows, int* rect) {
   if (!p || !interior_tiles || !frame_tiles || !tile_rows) {
     set_error("null argument");
     return SWEEP_EINVAL;
@@ -731,6 +733,12 @@ extern "C" int sweep_plan_tiles(const sweep_plan* p, int* interior_tiles, int* f
   *interior_tiles = p->n_int;
   *frame_tiles = p->n_pml;
   *tile_rows = p->TZ;
+  if (rect) {
+    rect[0] = p->itx0;
+    rect[1] = p->itx1;
+    rect[2] = p->itz0;
+    rect[3] = p->itz1;
+  }
   return SWEEP_OK;
 }
 
@@ -765,7 +773,8 @@ extern "C" int sweep_plan_set_profiling(sweep_plan* p, int enable) {
     set_error("null plan");
     return SWEEP_EINVAL;
   }
-  p->timer.on = enable != 0;
+  p->timer.on = enable > 0;
+  p->timer.period = enable > 0 ? enable : 1;
   p->timer.reset();
   return SWEEP_OK;
 }

@@ -240,7 +240,7 @@ int el_forward(sweep_plan* p, const float* model, const float* wavelet, float* g
         return rc;
     ElStep a = base;
     a.n = n;
-    if ((rc = el_launch_fwd(a, s, p->timer.take(kFwdMain, -1)))) return rc;
+    if ((rc = el_launch_fwd(a, s, p->timer.take(kFwdInt, -1, -1)))) return rc;
   }
   p->saved = save != 0;
   p->saved_work = work;
@@ -298,7 +298,7 @@ int el_backward(sweep_plan* p, const float* resid, float* grad, void* work, size
       a.n = n;
       for (int q = 0; q < kTracePlanes; ++q)
         a.tr[q] = tr + ((size_t)(n - n0) * kTracePlanes + q) * nsplane;
-      if ((rc = el_launch_fwd(a, s, p->timer.take(kRecMain, -1)))) return rc;
+      if ((rc = el_launch_fwd(a, s, p->timer.take(kRecInt, -1, -1)))) return rc;
     }
     for (int n = n1 - 1; n >= n0; --n) {
       const int it = nt - 1 - n;
@@ -311,7 +311,7 @@ int el_backward(sweep_plan* p, const float* resid, float* grad, void* work, size
       for (int q = 0; q < kTracePlanes; ++q)
         a.trc[q] = tr + ((size_t)(n - n0) * kTracePlanes + q) * nsplane;
       a.g_init = (n == n1 - 1);
-      if ((rc = el_launch_adj(a, s, p->timer.take(kAdjMain, -1)))) return rc;
+      if ((rc = el_launch_adj(a, s, p->timer.take(kAdjInt, -1, -1)))) return rc;
     }
     if ((rc = el_launch_fold(tot, gpart, (int)ns, L.plane, s))) return rc;
   }

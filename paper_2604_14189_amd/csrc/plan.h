@@ -22,27 +22,33 @@ struct AcLayout {
 // Optional per-launch timing of the step kernels (hipEvent pairs recorded on the
 // caller's stream around every launch of a kernel class).
 namespace sweep {
-// Acoustic: Main = interior-tile kernel, Band = PML (frame-tile) kernel of a step;
-// elastic: one class per pass.
+// Acoustic: interior-tile kernel, z-frame and x-frame C-PML kernels of the
+// forward, adjoint and recompute; elastic: one class per pass (Int slots).
 enum KernelClass {
-  kFwdMain = 0,
-  kFwdBand = 1,
-  kAdjMain = 2,
-  kAdjBand = 3,
-  kRecMain = 4,
-  kRecBand = 5,
-  kNumClasses = 6
+  kFwdInt = 0,
+  kFwdZ = 1,
+  kFwdX = 2,
+  kAdjInt = 3,
+  kAdjZ = 4,
+  kAdjX = 5,
+  kRecInt = 6,
+  kRecZ = 7,
+  kRecX = 8,
+  kNumClasses = 9
 };
 struct KernelTimer {
   bool on = false;
+  int period = 1;     // time the launches of every period-th step
+  long long calls = 0;
   std::vector<hipEvent_t> ev[kNumClasses];  // start, stop, start, stop, ...
-  size_t used[kNumClasses] = {0, 0, 0, 0, 0, 0};
+  size_t used[kNumClasses] = {};
   ~KernelTimer();
   void reset();
-  // Four events for one main + band launch pair of classes (ci, cf; cf < 0 for
-  // a single class, which uses the first two), or null when timing is off.
-  hipEvent_t* take(int ci, int cf);
-  hipEvent_t quad[4];
+  // Six events: start/stop pairs for the classes (ci, cz, cx) of one step's
+  // interior, z-frame and x-frame launches (negative: not timed, its pair is
+  // null), or null when timing is off.
+  hipEvent_t* take(int ci, int cz, int cx);
+  hipEvent_t six[6];
 };
 }  // namespace sweep
 

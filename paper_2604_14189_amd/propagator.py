@@ -130,12 +130,16 @@ class Plan:
         check(lib().sweep_plan_padded(self._h, ctypes.byref(a), ctypes.byref(b)))
         return a.value, b.value
 
-    def tiles(self):
-        """(interior tiles, frame tiles, tile rows) of the acoustic tiling; tiles
-        are 64 columns wide and the interior ones hold no C-PML cell."""
+    def tiles(self) -> dict:
+        """The acoustic tiling: tiles are 64 columns x `rows` rows; the interior
+        ones (no C-PML cell) form the rectangle of tile columns [x0, x1) and
+        rows [z0, z1); the others are the frame."""
         a, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
-        check(lib().sweep_plan_tiles(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
-        return a.value, b.value, c.value
+        rect = (ctypes.c_int * 4)()
+        check(lib().sweep_plan_tiles(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c),
+                                     rect))
+        return {"interior": a.value, "frame": b.value, "rows": c.value,
+                "x0": rect[0], "x1": rect[1], "z0": rect[2], "z1": rect[3]}
 
     def workspace_bytes(self, for_backward: bool) -> int:
         return int(lib().sweep_plan_workspace_bytes(self._h, int(bool(for_backward))))
@@ -194,12 +198,15 @@ class Plan:
         return out
 
     # ---------------------------------------------------------------- timing
-    # acoustic: *_main = interior-tile kernel, *_band = PML (frame-tile) kernel;
-    # fwd = forward, rec = segment recomputation, adj = adjoint
-    KERNEL_CLASSES = ("fwd_main", "fwd_band", "adj_main", "adj_band", "rec_main", "rec_band")
+    # fwd = forward, adj = adjoint, rec = segment recomputation (stores B^n);
+    # acoustic: *_int = interior-tile kernel, *_zpml / *_xpml = z-frame / x-frame
+    # C-PML kernels; elastic: the whole step in the *_int slot
+    KERNEL_CLASSES = ("fwd_int", "fwd_zpml", "fwd_xpml", "adj_int", "adj_zpml", "adj_xpml",
+                      "rec_int", "rec_zpml", "rec_xpml")
 
-    def set_profiling(self, enable: bool):
-        check(lib().sweep_plan_set_profiling(self._h, int(bool(enable))))
+    def set_profiling(self, enable: bool, period: int = 1):
+        """Time the step kernels with HIP events (every `period`-th step)."""
+        check(lib().sweep_plan_set_profiling(self._h, max(1, int(period)) if enable else 0))
 
     def kernel_times(self) -> dict:
         """{class: (launches, total_ms)} since the last set_profiling()."""
