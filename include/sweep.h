@@ -74,6 +74,10 @@ typedef struct {
   int pml_rz;      /* rows per thread of the C-PML (frame-tile) kernels, <= rz: a
                       frame tile is split into rz / pml_rz work-groups (default 4) */
   int use_graph;   /* 1 = capture each forward/backward time loop as a hipGraph */
+  int tblock;      /* acoustic: 2 = advance the deep interior tiles (no C-PML cell
+                      within 4 cells, no source or receiver within 8, an 8-cell halo
+                      inside the grid) two time steps per pass, marching down runs of
+                      them; 1 = one step per pass (default 1) */
 } sweep_tuning;
 
 typedef struct sweep_plan sweep_plan;
@@ -117,9 +121,12 @@ int sweep_plan_padded(const sweep_plan* plan, int* NX, int* NZ);
  * cell within pml + 4 of an edge) and form the rectangle of tile columns
  * [rect[0], rect[1]) x tile rows [rect[2], rect[3]) (all zero when empty);
  * they are advanced by the interior kernel (16 bytes per cell-update forward).
- * The frame_tiles others are advanced by the C-PML kernels: the z frame (the
- * rectangle's columns above and below it) and the x frame (all other tile
- * columns). rect may be NULL. EINVAL for an elastic plan or a null pointer. */
+ * rect[4] receives how many of them are deep (no C-PML cell within 4 cells,
+ * no source or receiver within 8, their 8-cell halo inside the grid) and
+ * advance two steps per pass when tuning.tblock = 2 (0 when tblock = 1). The frame_tiles others are advanced
+ * by the C-PML kernels: the z frame (the rectangle's columns above and below
+ * it) and the x frame (all other tile columns). rect (5 ints) may be NULL.
+ * EINVAL for an elastic plan or a null pointer. */
 int sweep_plan_tiles(const sweep_plan* plan, int* interior_tiles, int* frame_tiles,
                      int* tile_rows, int* rect);
 
@@ -150,10 +157,14 @@ int sweep_backward(sweep_plan* plan, const float* d_resid, float* d_grad, void* 
  * kernels is bracketed by a pair of hipEvents recorded on the call's stream
  * (the events add a few microseconds per launch). Acoustic classes, for the
  * forward (0-2), the adjoint (3-5) and the segment recompute that also stores
- * B^n (6-8): interior-tile kernel, z-frame C-PML kernel, x-frame C-PML kernel.
- * An elastic plan times each whole step (both of its kernels) in classes 0, 3
- * and 6.
- * enable: 0 off; n >= 1 times the launches of every n-th step (n = 1: all).
+ * B^n (6-8): interior-tile kernel, z-frame C-PML kernel, x-frame C-PML kernel;
+ * with tuning.tblock = 2 the two-step passes over the deep tiles are classes 9
+ * (forward), 10 (adjoint) and 11 (recompute), and the interior classes then
+ * time the remaining interior tiles. An elastic plan times each whole step
+ * (both of its kernels) in classes 0, 3 and 6.
+ * enable: 0 off; n >= 1 times the launches of every n-th step (n = 1: all); a
+ * step pair of a two-step pass counts as three launch groups (deep pass, step
+ * n, step n+1).
  * sweep_plan_set_profiling resets the counters; sweep_plan_kernel_time waits for
  * the recorded events and returns the number of timed launches and their summed
  * duration in milliseconds since the reset. */

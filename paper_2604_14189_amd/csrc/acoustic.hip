@@ -62,6 +62,19 @@ __device__ __forceinline__ float d1c(float p1, float m1, float p2, float m2, flo
 __device__ __forceinline__ float ld_nt(const float* p) { return __builtin_nontemporal_load(p); }
 __device__ __forceinline__ void st_nt(float* p, float v) { __builtin_nontemporal_store(v, p); }
 
+// Guarded load: f[i] where ok, else 0. Every lane issues the load (from
+// `safe`, any valid address, where !ok) and the value is selected afterwards.
+// Written as a branch, a guarded load has to complete before the other path
+// writes its register, which serialises a sequence of them.
+__device__ __forceinline__ float ldz(const float* f, size_t i, bool ok, const float* safe) {
+  const float v = *(ok ? f + i : safe);
+  return ok ? v : 0.0f;
+}
+__device__ __forceinline__ float ldz_nt(const float* f, size_t i, bool ok, const float* safe) {
+  const float v = ld_nt(ok ? f + i : safe);
+  return ok ? v : 0.0f;
+}
+
 // Stencils on a strided LDS array centred at f.
 __device__ __forceinline__ float d2s(const float* f, int st) {
   return d2c(f[0], f[st], f[-st], f[2 * st], f[-2 * st], f[3 * st], f[-3 * st], f[4 * st],
@@ -130,13 +143,6 @@ __global__ void ac_tables_kernel(float* ax, float* bx, float* az, float* bz, int
 // ---------------------------------------------------------------------------
 // Tiles and work-group placement.
 // ---------------------------------------------------------------------------
-// Global tile index of the b-th interior tile (row-major in the rectangle
-// [itx0, itx1) x [itz0, itz1) of tile coordinates).
-__device__ __forceinline__ int interior_tile(const AcStep& a, int b) {
-  const int w = a.itx1 - a.itx0;
-  return (a.itz0 + b / w) * a.tiles_x + a.itx0 + b % w;
-}
-
 // The frame (tiles outside the interior rectangle) is split in two sets.
 // x frame: the tile columns left and right of the rectangle, all rows; these
 // are exactly the columns with an x-strip cell within 4 cells.
@@ -758,17 +764,28 @@ __device__ __forceinline__ void ac_adj_pml_body(const AcStep& a, const int tile,
       oz[k] = row >= 0 ? a.psz_in[shot * zsp + (size_t)row * NX + gxx] : 0.0f;
     }
   }
+  // per-cell operands: branch-free where the body has no x-strip cells (measured
+  // faster there); as a guarded block in the x-strip bodies (fewer registers)
   float p1[RZ], pp[RZ], bb[RZ], gg[RZ];
 #pragma unroll
   for (int r = 0; r < RZ; ++r) {
     const int gz = z0 + zb + r;
-    p1[r] = pp[r] = bb[r] = gg[r] = 0.0f;
-    if (gx < NX && gz < NZ) {
-      const size_t gi = shot * plane + (size_t)gz * NX + gx;
-      p1[r] = a.cur[gi];
-      pp[r] = ld_nt(&a.prev[gi]);
-      bb[r] = ld_nt(&a.B_in[gi]);
-      if (!a.g_init) gg[r] = ld_nt(&a.g[gi]);
+    const bool ok = gx < NX && gz < NZ;
+    if constexpr (!HX) {
+      const size_t gi = shot * plane + (ok ? (size_t)gz * NX + gx : 0);
+      p1[r] = ldz(a.cur, gi, ok, a.Cs);
+      pp[r] = ldz_nt(a.prev, gi, ok, a.Cs);
+      bb[r] = ldz_nt(a.B_in, gi, ok, a.Cs);
+      gg[r] = ldz_nt(a.g, gi, ok && !a.g_init, a.Cs);
+    } else {
+      p1[r] = pp[r] = bb[r] = gg[r] = 0.0f;
+      if (ok) {
+        const size_t gi = shot * plane + (size_t)gz * NX + gx;
+        p1[r] = a.cur[gi];
+        pp[r] = ld_nt(&a.prev[gi]);
+        bb[r] = ld_nt(&a.B_in[gi]);
+        if (!a.g_init) gg[r] = ld_nt(&a.g[gi]);
+      }
     }
   }
   if (tid < XW) {
@@ -840,13 +857,359 @@ __device__ __forceinline__ void ac_adj_pml_body(const AcStep& a, const int tile,
 }
 
 // ---------------------------------------------------------------------------
+// Deep runs: two time steps per pass. A deep tile has no C-PML cell within 4
+// cells and no source or receiver within 8 cells (for any shot), so the first
+// step can be recomputed on a 4-cell ring around it from the field with an
+// 8-cell halo. A run is a chunk of consecutive deep tiles of one tile column;
+// one work-group marches down it eight rows at a time. Per iteration it
+//   1. computes step 1 (p^{n+1} / lambda^n) on 8 new rows, 72 columns wide
+//      (the strip and its 4-column ring), from p^n rows held in LDS;
+//   2. computes step 2 (p^{n+2} / lambda^{n-1}) on the 8 rows above them;
+//   3. stores the 8 next rows of p^n (80 columns) that it loaded into
+//      registers at the start of the iteration.
+// LDS holds both levels in circular buffers of 24 rows. Rows move by 8 per
+// iteration, so a buffer's slots repeat every 3 iterations; the first 8 slots
+// are also written 24 rows further on, which keeps every 16-row stencil window
+// contiguous (32 rows allocated). Only the ring rows at the start of a run and
+// the 4-column side rings are computed twice, and only the 8-cell halo rows and
+// columns are read twice (from L2). The per-cell arithmetic is that of the
+// interior kernel, so both steps give the same bits as two single steps. HBM
+// traffic per cell and two steps: 20 bytes forward (28 saving B), 36 adjoint.
+// ---------------------------------------------------------------------------
+constexpr int kMH = 8;                                // rows per iteration
+constexpr int kMS = 3 * kMH;                          // slots of a circular buffer
+constexpr int kMA = kTX + 16;                         // level-n columns: x0-8 .. x0+71
+constexpr int kMB = kTX + 8;                          // step-1 columns: x0-4 .. x0+67
+constexpr int kNA = kMH * kMA;                        // cells of 8 level-n rows
+constexpr int kNB = kMH * kMB;                        // step-1 cells per iteration
+constexpr int kKA = (kNA + kThreads - 1) / kThreads;  // per thread
+constexpr int kKB = (kNB + kThreads - 1) / kThreads;
+static_assert(kThreads == 4 * kTX && kMH == 8, "step 2 maps 2 rows x 64 columns per wave");
+
+// Slot arithmetic, with z the row offset from the run's first row za:
+//   level-n row za-8+j is in slot j mod 24; step-1 row za-4+j in slot j mod 24.
+// Iteration i (rows r = za + 8i) reads level n rows [r, r+16) (window from slot
+// 8((i+1) mod 3)), writes step-1 rows [r+4, r+12) (from slot 8((i+1) mod 3)),
+// reads step-1 rows [r-4, r+12) (window from slot 8(i mod 3)) and stores level
+// n rows [r+16, r+24) (from slot 8(i mod 3)).
+__device__ __forceinline__ int mslot(int i) { return kMH * (i % 3); }
+
+// Loads 8 rows [z, z+8) x [x0-8, x0+72) of a level-n field. A run's 8-cell
+// halo lies inside the grid, so the loads need no guard; rows past zlim (which
+// only feed results that are not kept) are clamped to zlim - 1. The loads are
+// unconditional on purpose: a load under a per-lane condition must complete
+// before the other branch writes its register, which serialises them.
+__device__ __forceinline__ void march_load_a(const float* f, int z, int zlim, int x0, int NX,
+                                             float (&v)[kKA]) {
+#pragma unroll
+  for (int k = 0; k < kKA; ++k) {
+    const int e = threadIdx.x + k * kThreads;
+    const int r = e / kMA, c = e - (e / kMA) * kMA;
+    const int gz = min(z + r, zlim - 1), gx = x0 - 8 + c;
+    v[k] = f[(size_t)gz * NX + gx];
+  }
+}
+
+// Writes them to slot s (and s + 24 for the first 8 slots); with w, the
+// products w v (w loaded by march_load_a from the same rows).
+__device__ __forceinline__ void march_put_a(float* sa, int s, const float (&v)[kKA]) {
+#pragma unroll
+  for (int k = 0; k < kKA; ++k) {
+    const int e = threadIdx.x + k * kThreads;
+    if (e < kNA) {
+      sa[s * kMA + e] = v[k];
+      if (s == 0) sa[kMS * kMA + e] = v[k];
+    }
+  }
+}
+__device__ __forceinline__ void march_put_a(float* sa, int s, const float (&w)[kKA],
+                                            const float (&v)[kKA]) {
+#pragma unroll
+  for (int k = 0; k < kKA; ++k) {
+    const int e = threadIdx.x + k * kThreads;
+    if (e < kNA) {
+      const float q = w[k] * v[k];
+      sa[s * kMA + e] = q;
+      if (s == 0) sa[kMS * kMA + e] = q;
+    }
+  }
+}
+
+// Row and column of this thread's step-1 cells within an 8 x 72 block.
+struct MarchCells {
+  int r[kKB], c[kKB];
+  __device__ __forceinline__ MarchCells() {
+#pragma unroll
+    for (int k = 0; k < kKB; ++k) {
+      const int e = threadIdx.x + k * kThreads;
+      r[k] = e / kMB;
+      c[k] = e - (e / kMB) * kMB;
+    }
+  }
+  __device__ __forceinline__ bool live(int k) const { return threadIdx.x + k * kThreads < kNB; }
+};
+
+// Step-1 inputs of rows [z, z+8) (rows past zlim clamped, as above).
+__device__ __forceinline__ void march_load_b(const MarchCells& mc, const float* f, int z, int zlim,
+                                             int x0, int NX, bool nt, float (&v)[kKB]) {
+#pragma unroll
+  for (int k = 0; k < kKB; ++k) {
+    const int gz = min(z + mc.r[k], zlim - 1), gx = x0 - 4 + mc.c[k];
+    const float* p = &f[(size_t)gz * NX + gx];
+    v[k] = nt ? ld_nt(p) : *p;
+  }
+}
+
+// Geometry of one march (a run of one shot).
+struct March {
+  int NX, NZ, x0, za, zb, nit, alim, blim, lx, wz;
+  size_t base;
+  __device__ __forceinline__ March(const AcStep& a, const int2 run, const int shot) {
+    NX = a.NX;
+    NZ = a.NZ;
+    base = (size_t)shot * NX * NZ;
+    x0 = run.x * kTX;
+    za = (run.y & 0xffff) * a.tz;
+    zb = za + (run.y >> 16) * a.tz;
+    nit = (zb - za + kMH - 1) / kMH;
+    alim = zb + 8;
+    blim = zb + 4;
+    lx = threadIdx.x & 63;
+    wz = (threadIdx.x >> 6) * 2;
+  }
+};
+
+// p^{n+1} on step-1 rows [z, z+8) (level-n window from slot wa, whose first row
+// is z - 4; results to slot wb), stored at the run's own cells.
+__device__ __forceinline__ void march_fwd_step1(const AcStep& a, const March& m,
+                                                const MarchCells& mc, const float* sa, float* sb,
+                                                int wa, int wb, int z, const float (&pm)[kKB],
+                                                const float (&cs)[kKB]) {
+#pragma unroll
+  for (int k = 0; k < kKB; ++k) {
+    if (!mc.live(k)) continue;
+    const float* f = &sa[(wa + 4 + mc.r[k]) * kMA + mc.c[k] + 4];
+    const float L = d2s(f, 1) + d2s(f, kMA);
+    const float pn = fmaf(cs[k], L, 2.0f * f[0] - pm[k]);
+    const int s = wb + mc.r[k];
+    sb[s * kMB + mc.c[k]] = pn;
+    if (s < kMH) sb[(s + kMS) * kMB + mc.c[k]] = pn;
+    const int gz = z + mc.r[k];
+    if (gz >= m.za && gz < m.zb && mc.c[k] >= 4 && mc.c[k] < 4 + kTX) {
+      const size_t gi = m.base + (size_t)gz * m.NX + (m.x0 - 4 + mc.c[k]);
+      st_nt(&a.next[gi], pn);
+      if (a.B_out) st_nt(&a.B_out[gi], L);
+    }
+  }
+}
+
+// Iteration i of the forward march. pm/cs: step-1 inputs of this iteration,
+// refilled with those of iteration i+2; put: level-n rows stored at the end of
+// this iteration; load: filled with those of iteration i+1.
+__device__ __forceinline__ void march_fwd_iter(const AcStep& a, const March& m,
+                                               const MarchCells& mc, float* sa, float* sb, int i,
+                                               float (&pm)[kKB], float (&cs)[kKB],
+                                               const float (&put)[kKA], float (&load)[kKA]) {
+  const float* cur = a.cur + m.base;
+  const float* prev = a.prev + m.base;
+  const int r = m.za + kMH * i;
+  const int wa = mslot(i + 1), wb2 = mslot(i);
+  float c2[2];
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int gz = min(r + m.wz + j, m.zb - 1);
+    c2[j] = a.Cs[(size_t)gz * m.NX + m.x0 + m.lx];
+  }
+  march_fwd_step1(a, m, mc, sa, sb, wa, wa, r + 4, pm, cs);
+  march_load_b(mc, prev, r + 20, m.blim, m.x0, m.NX, true, pm);
+  march_load_b(mc, a.Cs, r + 20, m.blim, m.x0, m.NX, false, cs);
+  march_load_a(cur, r + 24, m.alim, m.x0, m.NX, load);
+  __syncthreads();
+  // step 2 on rows [r, r+8)
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int gz = r + m.wz + j;
+    if (gz >= m.zb) continue;
+    const float* f = &sb[(wb2 + 4 + m.wz + j) * kMB + m.lx + 4];
+    const float L = d2s(f, 1) + d2s(f, kMB);
+    const float pn = fmaf(c2[j], L, 2.0f * f[0] - sa[(wa + m.wz + j) * kMA + m.lx + 8]);
+    const size_t gi = m.base + (size_t)gz * m.NX + m.x0 + m.lx;
+    st_nt(&a.next2[gi], pn);
+    if (a.B_out2) st_nt(&a.B_out2[gi], L);
+  }
+  march_put_a(sa, wb2, put);
+  __syncthreads();
+}
+
+// The march keeps two sets of in-flight registers and alternates them between
+// iterations (a copy from one set to the other would wait for its loads).
+__device__ __forceinline__ void ac_march_fwd(const AcStep& a, const int2 run, const int shot) {
+  __shared__ float sa[(kMS + kMH) * kMA];  // p^n
+  __shared__ float sb[(kMS + kMH) * kMB];  // p^{n+1}
+  const March m(a, run, shot);
+  const MarchCells mc;
+  const float* cur = a.cur + m.base;
+  const float* prev = a.prev + m.base;
+
+  // prologue: level n rows [za-8, za+16), step 1 on rows [za-4, za+4)
+  float va[3][kKA], pm0[kKB], cs0[kKB], pm1[kKB], cs1[kKB], n0[kKA], n1[kKA];
+  march_load_a(cur, m.za - 8, m.alim, m.x0, m.NX, va[0]);
+  march_load_a(cur, m.za, m.alim, m.x0, m.NX, va[1]);
+  march_load_a(cur, m.za + 8, m.alim, m.x0, m.NX, va[2]);
+  march_load_b(mc, prev, m.za - 4, m.blim, m.x0, m.NX, true, pm1);
+  march_load_b(mc, a.Cs, m.za - 4, m.blim, m.x0, m.NX, false, cs1);
+  march_load_b(mc, prev, m.za + 4, m.blim, m.x0, m.NX, true, pm0);
+  march_load_b(mc, a.Cs, m.za + 4, m.blim, m.x0, m.NX, false, cs0);
+  march_load_a(cur, m.za + 16, m.alim, m.x0, m.NX, n0);
+  march_put_a(sa, 0, va[0]);
+  march_put_a(sa, 8, va[1]);
+  march_put_a(sa, 16, va[2]);
+  __syncthreads();
+  march_fwd_step1(a, m, mc, sa, sb, 0, 0, m.za - 4, pm1, cs1);
+  march_load_b(mc, prev, m.za + 12, m.blim, m.x0, m.NX, true, pm1);
+  march_load_b(mc, a.Cs, m.za + 12, m.blim, m.x0, m.NX, false, cs1);
+
+  for (int i = 0; i < m.nit; i += 2) {
+    march_fwd_iter(a, m, mc, sa, sb, i, pm0, cs0, n0, n1);
+    if (i + 1 < m.nit) march_fwd_iter(a, m, mc, sa, sb, i + 1, pm1, cs1, n1, n0);
+  }
+}
+
+// lambda^n on step-1 rows [z, z+8) from q = Cs lambda^{n+1} (window from slot
+// wa, first row z - 4): Cs lambda^n and lambda^n to slot wb, stored at the run's
+// own cells.
+__device__ __forceinline__ void march_adj_step1(const AcStep& a, const March& m,
+                                                const MarchCells& mc, const float* sq, float* sb,
+                                                float* sl, int wa, int wb, int z,
+                                                const float (&l1)[kKB], const float (&l2)[kKB],
+                                                const float (&cr)[kKB]) {
+#pragma unroll
+  for (int k = 0; k < kKB; ++k) {
+    if (!mc.live(k)) continue;
+    const float* f = &sq[(wa + 4 + mc.r[k]) * kMA + mc.c[k] + 4];
+    const float lam = ((2.0f * l1[k] - l2[k]) + d2s(f, 1)) + d2s(f, kMA);
+    const int s = wb + mc.r[k];
+    const float cl = cr[k] * lam;
+    sb[s * kMB + mc.c[k]] = cl;
+    if (s < kMH) sb[(s + kMS) * kMB + mc.c[k]] = cl;
+    if (mc.c[k] >= 4 && mc.c[k] < 4 + kTX) {
+      sl[s * kTX + mc.c[k] - 4] = lam;
+      if (s < kMH) sl[(s + kMS) * kTX + mc.c[k] - 4] = lam;
+      const int gz = z + mc.r[k];
+      if (gz >= m.za && gz < m.zb)
+        st_nt(&a.next[m.base + (size_t)gz * m.NX + (m.x0 - 4 + mc.c[k])], lam);
+    }
+  }
+}
+
+// Step-1 inputs of the adjoint: lambda^{n+1}, lambda^{n+2} and Cs.
+struct AdjIn {
+  float l1[kKB], l2[kKB], cr[kKB];
+};
+__device__ __forceinline__ void march_adj_load_b(const AcStep& a, const March& m,
+                                                 const MarchCells& mc, int z, AdjIn& v) {
+  march_load_b(mc, a.cur + m.base, z, m.blim, m.x0, m.NX, false, v.l1);
+  march_load_b(mc, a.prev + m.base, z, m.blim, m.x0, m.NX, true, v.l2);
+  march_load_b(mc, a.Cs, z, m.blim, m.x0, m.NX, false, v.cr);
+}
+// Level-n rows of the adjoint: lambda^{n+1} and Cs (multiplied when stored).
+struct AdjRows {
+  float l[kKA], c[kKA];
+};
+__device__ __forceinline__ void march_adj_load_a(const AcStep& a, const March& m, int z,
+                                                 AdjRows& v) {
+  march_load_a(a.cur + m.base, z, m.alim, m.x0, m.NX, v.l);
+  march_load_a(a.Cs, z, m.alim, m.x0, m.NX, v.c);
+}
+
+__device__ __forceinline__ void march_adj_iter(const AcStep& a, const March& m,
+                                               const MarchCells& mc, float* sq, float* sb,
+                                               float* sl, int i, AdjIn& in, const AdjRows& put,
+                                               AdjRows& load) {
+  const int r = m.za + kMH * i;
+  const int wa = mslot(i + 1), wb2 = mslot(i);
+  float p1[2], b1[2], b2[2], gg[2];
+  const bool gacc = !a.g_init;
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int gz = min(r + m.wz + j, m.zb - 1);
+    const size_t gi = m.base + (size_t)gz * m.NX + m.x0 + m.lx;
+    p1[j] = a.cur[gi];
+    b1[j] = ld_nt(&a.B_in[gi]);
+    b2[j] = ld_nt(&a.B_in2[gi]);
+    gg[j] = gacc ? ld_nt(&a.g[gi]) : 0.0f;
+  }
+  march_adj_step1(a, m, mc, sq, sb, sl, wa, wa, r + 4, in.l1, in.l2, in.cr);
+  march_adj_load_b(a, m, mc, r + 20, in);
+  march_adj_load_a(a, m, r + 24, load);
+  __syncthreads();
+  // step 2 on rows [r, r+8) and the gradient of both steps
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int gz = r + m.wz + j;
+    if (gz >= m.zb) continue;
+    const int s = wb2 + 4 + m.wz + j;
+    const float* f = &sb[s * kMB + m.lx + 4];
+    const float lam_n = sl[s * kTX + m.lx];
+    const float lam = ((2.0f * lam_n - p1[j]) + d2s(f, 1)) + d2s(f, kMB);
+    const size_t gi = m.base + (size_t)gz * m.NX + m.x0 + m.lx;
+    const float gb = p1[j] * b1[j];
+    const float g1 = a.g_init ? gb : gg[j] + gb;
+    st_nt(&a.g[gi], g1 + lam_n * b2[j]);
+    st_nt(&a.next2[gi], lam);
+  }
+  march_put_a(sq, wb2, put.c, put.l);
+  __syncthreads();
+}
+
+// Reverse steps n and n-1; g += lambda^{n+1} B'^n + lambda^n B'^{n-1}.
+__device__ __forceinline__ void ac_march_adj(const AcStep& a, const int2 run, const int shot) {
+  __shared__ float sq[(kMS + kMH) * kMA];  // q = Cs lambda^{n+1}
+  __shared__ float sb[(kMS + kMH) * kMB];  // Cs lambda^n
+  __shared__ float sl[(kMS + kMH) * kTX];  // lambda^n on the strip's own columns
+  const March m(a, run, shot);
+  const MarchCells mc;
+
+  AdjRows va[3], n0, n1;
+  AdjIn in0, in1;
+  march_adj_load_a(a, m, m.za - 8, va[0]);
+  march_adj_load_a(a, m, m.za, va[1]);
+  march_adj_load_a(a, m, m.za + 8, va[2]);
+  march_adj_load_b(a, m, mc, m.za - 4, in1);
+  march_adj_load_b(a, m, mc, m.za + 4, in0);
+  march_adj_load_a(a, m, m.za + 16, n0);
+  march_put_a(sq, 0, va[0].c, va[0].l);
+  march_put_a(sq, 8, va[1].c, va[1].l);
+  march_put_a(sq, 16, va[2].c, va[2].l);
+  __syncthreads();
+  march_adj_step1(a, m, mc, sq, sb, sl, 0, 0, m.za - 4, in1.l1, in1.l2, in1.cr);
+  march_adj_load_b(a, m, mc, m.za + 12, in1);
+
+  for (int i = 0; i < m.nit; i += 2) {
+    march_adj_iter(a, m, mc, sq, sb, sl, i, in0, n0, n1);
+    if (i + 1 < m.nit) march_adj_iter(a, m, mc, sq, sb, sl, i + 1, in1, n1, n0);
+  }
+}
+
+template <bool kAdj>
+__global__ __launch_bounds__(kThreads) void ac_march_kernel(AcStep a) {
+  const int l = xcd_spread(blockIdx.x, gridDim.x);
+  const int2 run = a.drun[l % a.n_run];
+  const int shot = l / a.n_run;
+  if (kAdj)
+    ac_march_adj(a, run, shot);
+  else
+    ac_march_fwd(a, run, shot);
+}
+
+// ---------------------------------------------------------------------------
 // Kernel entry points: one plan (1-D grid over kind tiles x shots) or a batch
 // of plans of different shapes in one launch (the flat block index is split by
 // the per-plan block counts of this launch).
 // ---------------------------------------------------------------------------
 template <int RZ, bool kAdj>
 __device__ __forceinline__ void run_interior(const AcStep& a, int l) {
-  const int tile = interior_tile(a, l % a.n_int);
+  const int tile = a.ilist[l % a.n_int];
   const int shot = l / a.n_int;
   if (kAdj)
     ac_adj_int_body<RZ>(a, tile, shot);
@@ -1072,6 +1435,19 @@ int ac_launch_prep(const float* v, float* vpad, float* Cs, float* ax, float* bx,
   const int nmax = NX > NZ ? NX : NZ;
   hipLaunchKernelGGL(ac_tables_kernel, dim3((nmax + 255) / 256), dim3(256), 0, s, ax, bx, az,
                      bz, NX, NZ, P, h, dt, vmax, f0, R);
+  SWEEP_HIP(hipGetLastError());
+  return SWEEP_OK;
+}
+
+int ac_launch_deep(const AcStep& a, bool adj, hipStream_t s, hipEvent_t* ev) {
+  if (a.n_run <= 0) return SWEEP_OK;
+  const dim3 g(a.n_run * a.nshots);
+  if (ev && ev[0]) SWEEP_HIP(hipEventRecord(ev[0], s));
+  if (adj)
+    hipLaunchKernelGGL((ac_march_kernel<true>), g, dim3(kThreads), 0, s, a);
+  else
+    hipLaunchKernelGGL((ac_march_kernel<false>), g, dim3(kThreads), 0, s, a);
+  if (ev && ev[1]) SWEEP_HIP(hipEventRecord(ev[1], s));
   SWEEP_HIP(hipGetLastError());
   return SWEEP_OK;
 }

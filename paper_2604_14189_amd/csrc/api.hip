@@ -85,8 +85,68 @@ void ac_build_tiling(sweep_plan* p) {
   p->n_pml = p->ntiles - p->n_int;
   p->n_xf = (itx0 + p->tiles_x - itx1) * p->tiles_z;
   p->n_zf = (itx1 - itx0) * (itz0 + p->tiles_z - itz1);
-  // receiver CSR over (shot, tile), entries sorted by (local cell, receiver)
   const int ns = p->pb.nshots, nr = p->pb.nrec;
+  // Deep tiles (two steps per pass): interior tiles with no C-PML band cell
+  // within 4 cells (the first step is recomputed on a 4-cell ring) and no
+  // source or receiver of any shot within 8 cells (no injection on the ring).
+  std::vector<char> near((size_t)p->ntiles, 0);
+  auto mark = [&](int c) {
+    const int gx = c % p->NX, gz = c / p->NX;
+    for (int tz = std::max(0, (gz - 8 - TZ + 1) / TZ - 1); tz <= (gz + 8) / TZ && tz < p->tiles_z; ++tz)
+      for (int tx = std::max(0, (gx - 8 - kTX + 1) / kTX - 1); tx <= (gx + 8) / kTX && tx < p->tiles_x;
+           ++tx) {
+        const int x0 = tx * kTX, z0 = tz * TZ;
+        if (gx >= x0 - 8 && gx < x0 + kTX + 8 && gz >= z0 - 8 && gz < z0 + TZ + 8)
+          near[(size_t)tz * p->tiles_x + tx] = 1;
+      }
+  };
+  for (int c : p->src_cell) mark(c);
+  for (int c : p->rec_cell) mark(c);
+  p->ilist_all.clear();
+  p->ilist_ring.clear();
+  p->dlist.clear();
+  std::vector<char> deep((size_t)p->ntiles, 0);
+  for (int tz = itz0; tz < itz1; ++tz)
+    for (int tx = itx0; tx < itx1; ++tx) {
+      const int t = tz * p->tiles_x + tx, x0 = tx * kTX, z0 = tz * TZ;
+      p->ilist_all.push_back(t);
+      const bool clear_band =
+          p->P == 0 || (x0 - 4 >= m && x0 + kTX + 4 <= p->NX - m && z0 - 4 >= m && z0 + TZ + 4 <= p->NZ - m);
+      // the two-step kernels read an 8-cell halo without bounds checks
+      const bool halo_in = x0 >= 8 && x0 + kTX + 8 <= p->NX && z0 >= 8 && z0 + TZ + 8 <= p->NZ;
+      deep[t] = clear_band && halo_in && !near[t];
+      if (deep[t])
+        p->dlist.push_back(t);
+      else
+        p->ilist_ring.push_back(t);
+    }
+  // Deep runs: the deep tiles of a tile column that follow each other in z, cut
+  // into chunks of about equal length, each marched by one work-group per shot.
+  // Chunks hold at least 64 rows (the first 8 rows of p^{n+1} above a chunk are
+  // recomputed) and are cut so that chunks x shots reaches about 2048 groups.
+  p->drun.clear();
+  if (!p->dlist.empty()) {
+    const long long want = 2048;
+    const int cmin = (64 + TZ - 1) / TZ;
+    const int cmax = (int)std::max<long long>(
+        cmin, ((long long)p->dlist.size() * std::max(ns, 1) + want - 1) / want);
+    for (int tx = itx0; tx < itx1; ++tx)
+      for (int tz = itz0; tz < itz1;) {
+        if (!deep[(size_t)tz * p->tiles_x + tx]) {
+          ++tz;
+          continue;
+        }
+        int e = tz;
+        while (e < itz1 && deep[(size_t)e * p->tiles_x + tx]) ++e;
+        const int len = e - tz, nch = (len + cmax - 1) / cmax;
+        for (int q = 0; q < nch; ++q) {
+          const int a0 = tz + len * q / nch, a1 = tz + len * (q + 1) / nch;
+          p->drun.push_back(make_int2(tx, a0 | ((a1 - a0) << 16)));
+        }
+        tz = e;
+      }
+  }
+  // receiver CSR over (shot, tile), entries sorted by (local cell, receiver)
   p->rec_off.assign((size_t)ns * p->ntiles + 1, 0);
   std::vector<std::pair<int64_t, int>> keys((size_t)ns * nr);
   for (int s = 0; s < ns; ++s)
@@ -134,8 +194,9 @@ void ac_layout(const sweep_plan* p, AcLayout& L) {
   L.rec_cell = c.take(ns * nr * sizeof(int));
   L.rec_off = c.take((ns * ac_max_tiles(p) + 1) * sizeof(int));
   L.rec_ent = c.take(std::max<size_t>(ns * nr, 1) * sizeof(int2));
-  L.pA = c.take(ns * plane * f);
-  L.pB = c.take(ns * plane * f);
+  L.tl_cap = ac_max_tiles(p);
+  L.tl = c.take(4 * L.tl_cap * sizeof(int));  // interior, ring, runs (int2)
+  for (int i = 0; i < 4; ++i) L.pf[i] = c.take(ns * plane * f);
   L.aux[0] = c.take(L.aux_elems * f);
   L.aux[1] = c.take(L.aux_elems * f);
   L.fwd_end = c.off;
@@ -144,8 +205,7 @@ void ac_layout(const sweep_plan* p, AcLayout& L) {
   L.slot_elems = 2 * ns * plane + L.aux_elems;
   L.ck = c.take((size_t)L.nseg * L.slot_elems * f);
   L.Bseg = c.take((size_t)k * ns * plane * f);
-  L.lA = c.take(ns * plane * f);
-  L.lB = c.take(ns * plane * f);
+  for (int i = 0; i < 4; ++i) L.lf[i] = c.take(ns * plane * f);
   L.adjaux[0] = c.take(L.aux_elems * f);
   L.adjaux[1] = c.take(L.aux_elems * f);
   L.gpart = c.take(ns * plane * f);
@@ -226,7 +286,10 @@ AcStep ac_base(const sweep_plan* p, void* work, const AcLayout& L) {
   a.itx1 = p->itx1;
   a.itz0 = p->itz0;
   a.itz1 = p->itz1;
-  a.n_int = p->n_int;
+  a.n_int = (int)p->ilist_all.size();
+  a.ilist = at<int>(work, L.tl);
+  a.drun = reinterpret_cast<const int2*>(at<int>(work, L.tl) + 2 * L.tl_cap);
+  a.n_run = 0;
   a.n_pml = p->n_pml;
   a.n_xf = p->n_xf;
   a.n_zf = p->n_zf;
@@ -246,6 +309,14 @@ int ac_upload_geometry(sweep_plan* p, void* work, const AcLayout& L, hipStream_t
   }
   SWEEP_HIP(hipMemcpyAsync(at<int>(work, L.rec_off), p->rec_off.data(),
                            p->rec_off.size() * sizeof(int), hipMemcpyHostToDevice, s));
+  const std::vector<int>* lists[2] = {&p->ilist_all, &p->ilist_ring};
+  for (int q = 0; q < 2; ++q)
+    if (!lists[q]->empty())
+      SWEEP_HIP(hipMemcpyAsync(at<int>(work, L.tl) + q * L.tl_cap, lists[q]->data(),
+                               lists[q]->size() * sizeof(int), hipMemcpyHostToDevice, s));
+  if (!p->drun.empty())
+    SWEEP_HIP(hipMemcpyAsync(at<int>(work, L.tl) + 2 * L.tl_cap, p->drun.data(),
+                             p->drun.size() * sizeof(int2), hipMemcpyHostToDevice, s));
   return SWEEP_OK;
 }
 
@@ -262,41 +333,88 @@ int ac_fwd_prologue(sweep_plan* p, const float* model, const float* wavelet, voi
     return rc;
   const size_t ns = pb.nshots;
   if ((rc = launch_copy(at<float>(work, L.wav), wavelet, ns * pb.nt, s))) return rc;
-  if ((rc = launch_fill(at<float>(work, L.pA), ns * L.plane, 0.0f, s))) return rc;
-  if ((rc = launch_fill(at<float>(work, L.pB), ns * L.plane, 0.0f, s))) return rc;
+  p->frot = Rot();
+  if ((rc = launch_fill(at<float>(work, L.pf[p->frot.prev]), ns * L.plane, 0.0f, s))) return rc;
+  if ((rc = launch_fill(at<float>(work, L.pf[p->frot.cur]), ns * L.plane, 0.0f, s))) return rc;
   if ((rc = launch_fill(at<float>(work, L.aux[0]), L.aux_elems, 0.0f, s))) return rc;
   if ((rc = launch_fill(at<float>(work, L.aux[1]), L.aux_elems, 0.0f, s))) return rc;
   return SWEEP_OK;
 }
 
-// Arguments of forward step n (and the checkpoint copy of the state entering
-// it, enqueued on s, when save and n is a multiple of k).
-int ac_fwd_step_args(sweep_plan* p, void* work, const AcLayout& L, int n, float* gathers,
-                     int save, hipStream_t s, AcStep& a) {
+// Checkpoint of the state entering forward step n (a multiple of k).
+int ac_checkpoint(sweep_plan* p, void* work, const AcLayout& L, int n, hipStream_t s) {
   const size_t ns = p->pb.nshots;
-  a = ac_base(p, work, L);
+  float* slot = at<float>(work, L.ck) + (size_t)(n / p->ckpt) * L.slot_elems;
+  int rc;
+  if ((rc = launch_copy(slot, at<float>(work, L.pf[p->frot.cur]), ns * L.plane, s))) return rc;
+  if ((rc = launch_copy(slot + ns * L.plane, at<float>(work, L.pf[p->frot.prev]), ns * L.plane, s)))
+    return rc;
+  return launch_copy(slot + 2 * ns * L.plane, at<float>(work, L.aux[n % 2]), L.aux_elems, s);
+}
+
+// One forward-type step n (forward, or recomputation when B_out is given):
+// fields (cur, prev) -> next, memory variables aux[par] -> aux[1 - par].
+AcStep ac_fwd_single(sweep_plan* p, void* work, const AcLayout& L, int n, int par, int cur,
+                     int prev, int next, float* gathers, float* B_out) {
+  const size_t ns = p->pb.nshots;
+  AcStep a = ac_base(p, work, L);
   a.wavelet = at<float>(work, L.wav);
   a.gathers = gathers;
   a.n = n;
-  float* pA = at<float>(work, L.pA);
-  float* pB = at<float>(work, L.pB);
+  a.cur = at<float>(work, L.pf[cur]);
+  a.prev = at<float>(work, L.pf[prev]);
+  a.next = at<float>(work, L.pf[next]);
   float* aux[2] = {at<float>(work, L.aux[0]), at<float>(work, L.aux[1])};
-  float* cur = (n % 2 == 0) ? pB : pA;
-  float* prev = (n % 2 == 0) ? pA : pB;
-  a.cur = cur;
-  a.prev = prev;
-  a.next = prev;
-  set_aux(a, aux_ptrs(aux[n % 2], L, ns), aux_ptrs(aux[(n + 1) % 2], L, ns));
-  const int k = p->ckpt;
-  if (save && n % k == 0) {
-    float* slot = at<float>(work, L.ck) + (size_t)(n / k) * L.slot_elems;
-    int rc;
-    if ((rc = launch_copy(slot, cur, ns * L.plane, s))) return rc;
-    if ((rc = launch_copy(slot + ns * L.plane, prev, ns * L.plane, s))) return rc;
-    if ((rc = launch_copy(slot + 2 * ns * L.plane, aux[n % 2], L.aux_elems, s))) return rc;
-  }
+  set_aux(a, aux_ptrs(aux[par], L, ns), aux_ptrs(aux[1 - par], L, ns));
+  a.B_out = B_out;
+  return a;
+}
+
+// Timer events for the launches of one step; a tile set with nothing to launch
+// gets no events (they would never be recorded).
+hipEvent_t* step_events(sweep_plan* p, const AcStep& a, int ci, int cz, int cx) {
+  return p->timer.take(a.n_int > 0 ? ci : -1, a.n_zf > 0 ? cz : -1, a.n_xf > 0 ? cx : -1);
+}
+
+// One forward-type step from the plan's rotation; advances it.
+int ac_fwd_one(sweep_plan* p, void* work, const AcLayout& L, int n, int par, float* gathers,
+               float* B_out, hipStream_t s, int ci, int cz, int cx) {
+  Rot& r = p->frot;
+  const int o = r.free_buf(0);
+  const AcStep a = ac_fwd_single(p, work, L, n, par, r.cur, r.prev, o, gathers, B_out);
+  const int rc = ac_launch_fwd(a, p->tune.rz, p->tune.pml_rz, s, step_events(p, a, ci, cz, cx));
+  r.prev = r.cur;
+  r.cur = o;
+  return rc;
+}
+
+// Forward-type steps n and n+1: the deep tiles in one two-step pass, the other
+// tiles (interior ring and frame) as two single steps; advances the rotation.
+int ac_fwd_two(sweep_plan* p, void* work, const AcLayout& L, int n, int par, float* gathers,
+               float* B_out, float* B_out2, hipStream_t s, bool rec) {
+  Rot& r = p->frot;
+  const int o1 = r.free_buf(0), o2 = r.free_buf(1);
+  AcStep d = ac_fwd_single(p, work, L, n, par, r.cur, r.prev, o1, gathers, B_out);
+  d.next2 = at<float>(work, L.pf[o2]);
+  d.B_out2 = B_out2;
+  d.n_run = (int)p->drun.size();
+  AcStep a0 = ac_fwd_single(p, work, L, n, par, r.cur, r.prev, o1, gathers, B_out);
+  AcStep a1 = ac_fwd_single(p, work, L, n + 1, 1 - par, o1, r.cur, o2, gathers, B_out2);
+  a0.ilist = a1.ilist = at<int>(work, L.tl) + L.tl_cap;
+  a0.n_int = a1.n_int = (int)p->ilist_ring.size();
+  const int rz = p->tune.rz, prz = p->tune.pml_rz;
+  int rc;
+  if ((rc = ac_launch_deep(d, false, s, p->timer.take(rec ? kRecDeep : kFwdDeep, -1, -1))))
+    return rc;
+  const int ci = rec ? kRecInt : kFwdInt, cz = rec ? kRecZ : kFwdZ, cx = rec ? kRecX : kFwdX;
+  if ((rc = ac_launch_fwd(a0, rz, prz, s, step_events(p, a0, ci, cz, cx)))) return rc;
+  if ((rc = ac_launch_fwd(a1, rz, prz, s, step_events(p, a1, ci, cz, cx)))) return rc;
+  r.prev = o1;
+  r.cur = o2;
   return SWEEP_OK;
 }
+
+bool ac_two_steps(const sweep_plan* p) { return p->tune.tblock == 2 && !p->dlist.empty(); }
 
 void ac_mark_saved(sweep_plan* p, void* work, const float* model, int save) {
   p->saved = save != 0;
@@ -309,10 +427,19 @@ int ac_forward_enqueue(sweep_plan* p, const float* model, const float* wavelet, 
                        void* work, const AcLayout& L, int save, hipStream_t s) {
   int rc;
   if ((rc = ac_fwd_prologue(p, model, wavelet, work, L, s))) return rc;
-  for (int n = 0; n < p->pb.nt; ++n) {
-    AcStep a;
-    if ((rc = ac_fwd_step_args(p, work, L, n, gathers, save, s, a))) return rc;
-    if ((rc = ac_launch_fwd(a, p->tune.rz, p->tune.pml_rz, s, p->timer.take(kFwdInt, kFwdZ, kFwdX)))) return rc;
+  const int nt = p->pb.nt, k = p->ckpt;
+  const bool two = ac_two_steps(p);
+  for (int n = 0; n < nt;) {
+    if (save && n % k == 0 && (rc = ac_checkpoint(p, work, L, n, s))) return rc;
+    // a pair never spans a checkpoint (the state entering step n+1 is not formed)
+    if (two && n + 1 < nt && (!save || (n + 1) % k != 0)) {
+      if ((rc = ac_fwd_two(p, work, L, n, n % 2, gathers, nullptr, nullptr, s, false))) return rc;
+      n += 2;
+    } else {
+      if ((rc = ac_fwd_one(p, work, L, n, n % 2, gathers, nullptr, s, kFwdInt, kFwdZ, kFwdX)))
+        return rc;
+      n += 1;
+    }
   }
   return SWEEP_OK;
 }
@@ -322,8 +449,9 @@ int ac_bwd_prologue(sweep_plan* p, const float* resid, void* work, const AcLayou
                     hipStream_t s) {
   const size_t ns = p->pb.nshots;
   int rc;
-  if ((rc = ac_launch_adj_init(at<float>(work, L.lB), at<float>(work, L.lA), ns * L.plane,
-                               at<float>(work, L.adjaux[0]), L.aux_elems,
+  p->arot = Rot();
+  if ((rc = ac_launch_adj_init(at<float>(work, L.lf[p->arot.cur]), at<float>(work, L.lf[p->arot.prev]),
+                               ns * L.plane, at<float>(work, L.adjaux[0]), L.aux_elems,
                                at<int>(work, L.rec_cell), resid, (int)ns, p->pb.nt, p->pb.nrec,
                                s)))
     return rc;
@@ -335,50 +463,72 @@ int ac_bwd_prologue(sweep_plan* p, const float* resid, void* work, const AcLayou
 int ac_bwd_restore(sweep_plan* p, void* work, const AcLayout& L, int sg, hipStream_t s) {
   const size_t ns = p->pb.nshots;
   float* slot = at<float>(work, L.ck) + (size_t)sg * L.slot_elems;
+  p->frot = Rot();
   int rc;
-  if ((rc = launch_copy(at<float>(work, L.pB), slot, ns * L.plane, s))) return rc;
-  if ((rc = launch_copy(at<float>(work, L.pA), slot + ns * L.plane, ns * L.plane, s))) return rc;
+  if ((rc = launch_copy(at<float>(work, L.pf[p->frot.cur]), slot, ns * L.plane, s))) return rc;
+  if ((rc = launch_copy(at<float>(work, L.pf[p->frot.prev]), slot + ns * L.plane, ns * L.plane, s)))
+    return rc;
   return launch_copy(at<float>(work, L.aux[0]), slot + 2 * ns * L.plane, L.aux_elems, s);
 }
 
-// recomputation of step n = n0 + m of a segment, storing B^n
-AcStep ac_rec_step_args(sweep_plan* p, void* work, const AcLayout& L, int n, int m) {
-  const size_t ns = p->pb.nshots;
-  AcStep a = ac_base(p, work, L);
-  a.n = n;
-  a.wavelet = at<float>(work, L.wav);
-  float* pA = at<float>(work, L.pA);
-  float* pB = at<float>(work, L.pB);
-  float* aux[2] = {at<float>(work, L.aux[0]), at<float>(work, L.aux[1])};
-  float* prev = (m % 2 == 0) ? pA : pB;
-  a.cur = (m % 2 == 0) ? pB : pA;
-  a.prev = prev;
-  a.next = prev;
-  set_aux(a, aux_ptrs(aux[m % 2], L, ns), aux_ptrs(aux[(m + 1) % 2], L, ns));
-  a.B_out = at<float>(work, L.Bseg) + (size_t)m * ns * L.plane;
-  return a;
+// B'^n of step n = n0 + m of the segment being reversed
+float* ac_bseg(void* work, const AcLayout& L, size_t ns, int m) {
+  return at<float>(work, L.Bseg) + (size_t)m * ns * L.plane;
 }
 
-// reverse of step n inside the segment starting at n0 and ending before n1
-AcStep ac_adj_step_args(sweep_plan* p, void* work, const AcLayout& L, const float* resid, int n,
-                        int n0, int n1) {
+// Reverse of step n inside the segment [n0, n1): fields (cur, prev) -> next,
+// adjoint memory variables by the parity of nt - 1 - n.
+AcStep ac_adj_single(sweep_plan* p, void* work, const AcLayout& L, const float* resid, int n,
+                     int n0, int n1, int cur, int prev, int next) {
   const size_t ns = p->pb.nshots;
   const int it = p->pb.nt - 1 - n;
   AcStep a = ac_base(p, work, L);
   a.n = n;
   a.resid = resid;
-  float* lA = at<float>(work, L.lA);
-  float* lB = at<float>(work, L.lB);
+  a.cur = at<float>(work, L.lf[cur]);
+  a.prev = at<float>(work, L.lf[prev]);
+  a.next = at<float>(work, L.lf[next]);
   float* adjaux[2] = {at<float>(work, L.adjaux[0]), at<float>(work, L.adjaux[1])};
-  float* prev = (it % 2 == 0) ? lA : lB;
-  a.cur = (it % 2 == 0) ? lB : lA;
-  a.prev = prev;
-  a.next = prev;
   set_aux(a, aux_ptrs(adjaux[it % 2], L, ns), aux_ptrs(adjaux[(it + 1) % 2], L, ns));
-  a.B_in = at<float>(work, L.Bseg) + (size_t)(n - n0) * ns * L.plane;
+  a.B_in = ac_bseg(work, L, ns, n - n0);
   a.g = at<float>(work, L.gpart);
   a.g_init = (n == n1 - 1);
   return a;
+}
+
+int ac_adj_one(sweep_plan* p, void* work, const AcLayout& L, const float* resid, int n, int n0,
+               int n1, hipStream_t s) {
+  Rot& r = p->arot;
+  const int o = r.free_buf(0);
+  const AcStep a = ac_adj_single(p, work, L, resid, n, n0, n1, r.cur, r.prev, o);
+  const int rc = ac_launch_adj(a, p->tune.rz, p->tune.pml_rz, s, step_events(p, a, kAdjInt, kAdjZ, kAdjX));
+  r.prev = r.cur;
+  r.cur = o;
+  return rc;
+}
+
+// Reverse steps n and n-1 (both inside [n0, n1)): deep tiles in one pass.
+int ac_adj_two(sweep_plan* p, void* work, const AcLayout& L, const float* resid, int n, int n0,
+               int n1, hipStream_t s) {
+  Rot& r = p->arot;
+  const size_t ns = p->pb.nshots;
+  const int o1 = r.free_buf(0), o2 = r.free_buf(1);
+  AcStep d = ac_adj_single(p, work, L, resid, n, n0, n1, r.cur, r.prev, o1);
+  d.next2 = at<float>(work, L.lf[o2]);
+  d.B_in2 = ac_bseg(work, L, ns, n - 1 - n0);
+  d.n_run = (int)p->drun.size();
+  AcStep a0 = ac_adj_single(p, work, L, resid, n, n0, n1, r.cur, r.prev, o1);
+  AcStep a1 = ac_adj_single(p, work, L, resid, n - 1, n0, n1, o1, r.cur, o2);
+  a0.ilist = a1.ilist = at<int>(work, L.tl) + L.tl_cap;
+  a0.n_int = a1.n_int = (int)p->ilist_ring.size();
+  const int rz = p->tune.rz, prz = p->tune.pml_rz;
+  int rc;
+  if ((rc = ac_launch_deep(d, true, s, p->timer.take(kAdjDeep, -1, -1)))) return rc;
+  if ((rc = ac_launch_adj(a0, rz, prz, s, step_events(p, a0, kAdjInt, kAdjZ, kAdjX)))) return rc;
+  if ((rc = ac_launch_adj(a1, rz, prz, s, step_events(p, a1, kAdjInt, kAdjZ, kAdjX)))) return rc;
+  r.prev = o1;
+  r.cur = o2;
+  return SWEEP_OK;
 }
 
 int ac_bwd_fold(sweep_plan* p, void* work, const AcLayout& L, hipStream_t s) {
@@ -396,18 +546,34 @@ int ac_bwd_finish(sweep_plan* p, void* work, const AcLayout& L, float* grad, hip
 int ac_backward_enqueue(sweep_plan* p, const float* resid, float* grad, void* work,
                         const AcLayout& L, hipStream_t s) {
   const int nt = p->pb.nt, k = p->ckpt;
+  const size_t ns = p->pb.nshots;
+  const bool two = ac_two_steps(p);
   int rc;
   if ((rc = ac_bwd_prologue(p, resid, work, L, s))) return rc;
   for (int sg = L.nseg - 1; sg >= 0; --sg) {
     const int n0 = sg * k, n1 = std::min(nt, n0 + k);
     if ((rc = ac_bwd_restore(p, work, L, sg, s))) return rc;
-    for (int n = n0; n < n1; ++n) {
-      const AcStep a = ac_rec_step_args(p, work, L, n, n - n0);
-      if ((rc = ac_launch_fwd(a, p->tune.rz, p->tune.pml_rz, s, p->timer.take(kRecInt, kRecZ, kRecX)))) return rc;
+    for (int m = 0; m < n1 - n0;) {
+      if (two && m + 1 < n1 - n0) {
+        if ((rc = ac_fwd_two(p, work, L, n0 + m, m % 2, nullptr, ac_bseg(work, L, ns, m),
+                             ac_bseg(work, L, ns, m + 1), s, true)))
+          return rc;
+        m += 2;
+      } else {
+        if ((rc = ac_fwd_one(p, work, L, n0 + m, m % 2, nullptr, ac_bseg(work, L, ns, m), s,
+                             kRecInt, kRecZ, kRecX)))
+          return rc;
+        m += 1;
+      }
     }
-    for (int n = n1 - 1; n >= n0; --n) {
-      const AcStep a = ac_adj_step_args(p, work, L, resid, n, n0, n1);
-      if ((rc = ac_launch_adj(a, p->tune.rz, p->tune.pml_rz, s, p->timer.take(kAdjInt, kAdjZ, kAdjX)))) return rc;
+    for (int n = n1 - 1; n >= n0;) {
+      if (two && n - 1 >= n0) {
+        if ((rc = ac_adj_two(p, work, L, resid, n, n0, n1, s))) return rc;
+        n -= 2;
+      } else {
+        if ((rc = ac_adj_one(p, work, L, resid, n, n0, n1, s))) return rc;
+        n -= 1;
+      }
     }
     if ((rc = ac_bwd_fold(p, work, L, s))) return rc;
   }
@@ -515,17 +681,27 @@ int batch_forward_enqueue(sweep_batch* b, const float* const* models, const floa
     maxnt = std::max(maxnt, b->plans[q]->pb.nt);
   }
   std::vector<AcStep> steps(np);
+  std::vector<int> who(np), nxt(np);
   for (int n = 0; n < maxnt; ++n) {
     int cnt = 0;
     for (int q = 0; q < np; ++q) {
       sweep_plan* p = b->plans[q];
       if (n >= p->pb.nt) continue;
-      if ((rc = ac_fwd_step_args(p, at<char>(work, off[q]), L[q], n, gathers[q], save, s,
-                                 steps[cnt])))
-        return rc;
+      void* wq = at<char>(work, off[q]);
+      if (save && n % p->ckpt == 0 && (rc = ac_checkpoint(p, wq, L[q], n, s))) return rc;
+      const int o = p->frot.free_buf(0);
+      steps[cnt] = ac_fwd_single(p, wq, L[q], n, n % 2, p->frot.cur, p->frot.prev, o, gathers[q],
+                                 nullptr);
+      who[cnt] = q;
+      nxt[cnt] = o;
       ++cnt;
     }
     if ((rc = ac_launch_fwd_batch(steps.data(), cnt, b->rz, b->prz, s))) return rc;
+    for (int c = 0; c < cnt; ++c) {
+      Rot& r = b->plans[who[c]]->frot;
+      r.prev = r.cur;
+      r.cur = nxt[c];
+    }
   }
   return SWEEP_OK;
 }
@@ -541,7 +717,7 @@ int batch_backward_enqueue(sweep_batch* b, const float* const* resids, float* co
     maxseg = std::max(maxseg, L[q].nseg);
   }
   std::vector<AcStep> steps(np);
-  std::vector<int> n0(np), n1(np);
+  std::vector<int> n0(np), n1(np), who(np), nxt(np);
   for (int r = 0; r < maxseg; ++r) {
     int lenmax = 0;
     for (int q = 0; q < np; ++q) {
@@ -556,18 +732,40 @@ int batch_backward_enqueue(sweep_batch* b, const float* const* resids, float* co
     }
     for (int m = 0; m < lenmax; ++m) {
       int cnt = 0;
-      for (int q = 0; q < np; ++q)
-        if (m < n1[q] - n0[q])
-          steps[cnt++] = ac_rec_step_args(b->plans[q], at<char>(work, off[q]), L[q], n0[q] + m, m);
+      for (int q = 0; q < np; ++q) {
+        if (m >= n1[q] - n0[q]) continue;
+        sweep_plan* p = b->plans[q];
+        void* wq = at<char>(work, off[q]);
+        const int o = p->frot.free_buf(0);
+        steps[cnt] = ac_fwd_single(p, wq, L[q], n0[q] + m, m % 2, p->frot.cur, p->frot.prev, o,
+                                   nullptr, ac_bseg(wq, L[q], p->pb.nshots, m));
+        who[cnt] = q;
+        nxt[cnt++] = o;
+      }
       if ((rc = ac_launch_fwd_batch(steps.data(), cnt, b->rz, b->prz, s))) return rc;
+      for (int c = 0; c < cnt; ++c) {
+        Rot& r = b->plans[who[c]]->frot;
+        r.prev = r.cur;
+        r.cur = nxt[c];
+      }
     }
     for (int m = 0; m < lenmax; ++m) {
       int cnt = 0;
-      for (int q = 0; q < np; ++q)
-        if (m < n1[q] - n0[q])
-          steps[cnt++] = ac_adj_step_args(b->plans[q], at<char>(work, off[q]), L[q], resids[q],
-                                          n1[q] - 1 - m, n0[q], n1[q]);
+      for (int q = 0; q < np; ++q) {
+        if (m >= n1[q] - n0[q]) continue;
+        sweep_plan* p = b->plans[q];
+        const int o = p->arot.free_buf(0);
+        steps[cnt] = ac_adj_single(p, at<char>(work, off[q]), L[q], resids[q], n1[q] - 1 - m,
+                                   n0[q], n1[q], p->arot.cur, p->arot.prev, o);
+        who[cnt] = q;
+        nxt[cnt++] = o;
+      }
       if ((rc = ac_launch_adj_batch(steps.data(), cnt, b->rz, b->prz, s))) return rc;
+      for (int c = 0; c < cnt; ++c) {
+        Rot& r = b->plans[who[c]]->arot;
+        r.prev = r.cur;
+        r.cur = nxt[c];
+      }
     }
     for (int q = 0; q < np; ++q)
       if (n1[q] > n0[q] && (rc = ac_bwd_fold(b->plans[q], at<char>(work, off[q]), L[q], s)))
@@ -649,6 +847,7 @@ extern "C" int sweep_plan_create(const sweep_problem* pb, const int32_t* src_xz,
   }
   p->tune.rz = 4;
   p->tune.pml_rz = 4;
+  p->tune.tblock = 1;
   p->tune.use_graph = 0;
   if (pb->physics == SWEEP_ACOUSTIC) {
     ac_build_tiling(p);
@@ -677,7 +876,8 @@ extern "C" int sweep_plan_set_tuning(sweep_plan* p, const sweep_tuning* t) {
   const bool ok_rz = t->rz == 1 || t->rz == 2 || t->rz == 4 || t->rz == 8;
   const bool ok_prz = (t->pml_rz == 1 || t->pml_rz == 2 || t->pml_rz == 4 || t->pml_rz == 8) &&
                       t->pml_rz <= t->rz;
-  if (!ok_rz || !ok_prz || (t->use_graph != 0 && t->use_graph != 1)) {
+  if (!ok_rz || !ok_prz || (t->use_graph != 0 && t->use_graph != 1) ||
+      (t->tblock != 1 && t->tblock != 2)) {
     set_error("unsupported tuning");
     return SWEEP_EINVAL;
   }
@@ -738,6 +938,7 @@ extern "C" int sweep_plan_tiles(const sweep_plan* p, int* interior_tiles, int* f
     rect[1] = p->itx1;
     rect[2] = p->itz0;
     rect[3] = p->itz1;
+    rect[4] = p->tune.tblock == 2 ? (int)p->dlist.size() : 0;
   }
   return SWEEP_OK;
 }
@@ -1006,10 +1207,15 @@ extern "C" int sweep_plan_autotune(sweep_plan* p, const float* d_model, const fl
         rc = ac_fwd_prologue(p, d_model, d_wavelet, d_work, L, s);
         if (rc) break;
         SWEEP_HIP(hipEventRecord(e0, s));
-        for (int n = 0; n < nsteps && !rc; ++n) {
-          AcStep a;
-          rc = ac_fwd_step_args(p, d_work, L, n, nullptr, 0, s, a);
-          if (!rc) rc = ac_launch_fwd(a, c, cp, s, nullptr);
+        const bool two = ac_two_steps(p);
+        for (int n = 0; n < nsteps && !rc;) {
+          if (two && n + 1 < nsteps) {
+            rc = ac_fwd_two(p, d_work, L, n, n % 2, nullptr, nullptr, nullptr, s, false);
+            n += 2;
+          } else {
+            rc = ac_fwd_one(p, d_work, L, n, n % 2, nullptr, nullptr, s, kFwdInt, kFwdZ, kFwdX);
+            n += 1;
+          }
         }
         SWEEP_HIP(hipEventRecord(e1, s));
         SWEEP_HIP(hipEventSynchronize(e1));

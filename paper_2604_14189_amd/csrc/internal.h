@@ -57,11 +57,14 @@ struct AcStep {
   const float* bx;
   const float* az;
   const float* bz;
-  // forward: p^n (cur), p^{n-1} (prev), p^{n+1} (next, aliases prev)
-  // adjoint: lambda^{n+1} (cur), lambda^{n+2} (prev), lambda^n (next, aliases prev)
+  // forward: p^n (cur), p^{n-1} (prev), p^{n+1} (next)
+  // adjoint: lambda^{n+1} (cur), lambda^{n+2} (prev), lambda^n (next)
+  // A pass of two steps over the deep tiles also writes p^{n+2} / lambda^{n-1}
+  // to next2. The kernels read prev and write next at a tile's own cells only.
   const float* cur;
   const float* prev;
   float* next;
+  float* next2;
   // memory variables: read *_in (time n-1), write *_out (time n)
   const float* psx_in;
   float* psx_out;
@@ -80,8 +83,10 @@ struct AcStep {
   const float* resid;     // adjoint: [nshots][nt][nrec] injected at step n-1
   // forward extras
   float* B_out;           // [nshots][NZ][NX] Laplacian term B'^n, or null
+  float* B_out2;          // B'^{n+1} (two-step pass), or null
   // adjoint extras
   const float* B_in;      // B'^n of this step
+  const float* B_in2;     // B'^{n-1} (two-step pass)
   float* g;               // [nshots][NZ][NX] gradient partial
   int g_init;             // 1: g = P1 B (first step of a segment), 0: g += P1 B
   // tiles: the interior rectangle [itx0, itx1) x [itz0, itz1) of tile
@@ -89,6 +94,10 @@ struct AcStep {
   // tiles (the frame) take the PML kernel
   int itx0, itx1, itz0, itz1;
   int n_int, n_pml;
+  const int* ilist;  // the n_int tiles the interior kernel takes
+  // runs of a two-step pass: (tile column, first tile row | tile rows << 16)
+  const int2* drun;
+  int n_run;
   int n_xf, n_zf;  // frame tiles: left/right columns (x frame), above/below (z frame)
   int tz;    // rows of a tile
   int nsub;  // PML work-groups per frame tile (each takes tz / nsub rows)
@@ -110,6 +119,8 @@ int ac_launch_prep(const float* v, float* vpad, float* Cs, float* ax, float* bx,
 int ac_launch_fwd(const AcStep& a, int rz, int prz, hipStream_t s, hipEvent_t* ev);
 int ac_launch_adj(const AcStep& a, int rz, int prz, hipStream_t s, hipEvent_t* ev);
 int ac_launch_fwd_batch(const AcStep* steps, int n, int rz, int prz, hipStream_t s);
+// Two steps over the deep runs (a.drun): forward n and n+1, or adjoint n and n-1.
+int ac_launch_deep(const AcStep& a, bool adj, hipStream_t s, hipEvent_t* ev);
 int ac_launch_adj_batch(const AcStep* steps, int n, int rz, int prz, hipStream_t s);
 int ac_launch_adj_init(float* lam_cur, float* lam_prev, size_t plane_elems, float* aux,
                        size_t aux_elems, const int* rec_cell, const float* resid, int nshots,

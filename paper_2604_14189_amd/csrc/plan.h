@@ -10,12 +10,26 @@ namespace sweep {
 struct AcLayout {
   size_t plane, xs, zs, aux_elems;
   size_t ax, bx, az, bz, vpad, Cs, wav, src_cell, rec_cell, rec_off, rec_ent;
-  size_t pA, pB, aux[2];
+  size_t tl, tl_cap;  // tile lists (all interior, ring, deep), tl_cap ints each
+  size_t pf[4], aux[2];  // forward field buffers (rotated), C-PML memory variables
   size_t fwd_end;
   int nseg;
   size_t slot_elems;
-  size_t ck, Bseg, lA, lB, adjaux[2], gpart, tot;
+  size_t ck, Bseg, lf[4], adjaux[2], gpart, tot;
   size_t bwd_end;
+};
+
+// Which of the four field buffers hold the current and the previous field; a
+// step writes a free buffer, so no kernel overwrites values a neighbouring
+// tile may still read.
+struct Rot {
+  int cur = 1, prev = 0;
+  int free_buf(int k) const {
+    int f[2], c = 0;
+    for (int i = 0; i < 4; ++i)
+      if (i != cur && i != prev) f[c++] = i;
+    return f[k];
+  }
 };
 }  // namespace sweep
 
@@ -34,7 +48,10 @@ enum KernelClass {
   kRecInt = 6,
   kRecZ = 7,
   kRecX = 8,
-  kNumClasses = 9
+  kFwdDeep = 9,   // two-step passes over the deep tiles
+  kAdjDeep = 10,
+  kRecDeep = 11,
+  kNumClasses = 12
 };
 struct KernelTimer {
   bool on = false;
@@ -92,6 +109,10 @@ struct sweep_plan {
   int TZ = 0, tiles_x = 0, tiles_z = 0, ntiles = 0;
   // interior rectangle of tiles without C-PML cells (tile coordinates)
   int itx0 = 0, itx1 = 0, itz0 = 0, itz1 = 0, n_int = 0, n_pml = 0, n_xf = 0, n_zf = 0;
+  // interior tiles; those advanced two steps per pass (deep) and the others
+  std::vector<int> ilist_all, ilist_ring, dlist;
+  std::vector<int2> drun;  // deep tiles as chunks of tile-column runs
+  sweep::Rot frot, arot;  // forward / adjoint buffer rotation
   // elastic: receivers sorted by (shot, cell, r) for deterministic injection,
   // and the transposed z-taps of the first rows under a free surface
   std::vector<int4> rec_sorted;

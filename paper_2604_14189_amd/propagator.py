@@ -99,12 +99,14 @@ class Plan:
     def tuning(self) -> dict:
         t = Tuning()
         check(lib().sweep_plan_get_tuning(self._h, ctypes.byref(t)))
-        return {"rz": t.rz, "pml_rz": t.pml_rz, "use_graph": t.use_graph}
+        return {"rz": t.rz, "pml_rz": t.pml_rz, "use_graph": t.use_graph, "tblock": t.tblock}
 
-    def set_tuning(self, rz: int = 4, pml_rz: Optional[int] = None, use_graph: int = 0):
+    def set_tuning(self, rz: int = 4, pml_rz: Optional[int] = None, use_graph: int = 0,
+                   tblock: int = 1):
         """rz: rows per thread of the interior kernel (tiles of 64 x 4 rz);
-        pml_rz: rows per thread of the C-PML kernels (<= rz, default min(4, rz))."""
-        t = Tuning(rz, min(4, rz) if pml_rz is None else pml_rz, use_graph)
+        pml_rz: rows per thread of the C-PML kernels (<= rz, default min(4, rz));
+        tblock: time steps per pass over the deep interior tiles (1 or 2)."""
+        t = Tuning(rz, min(4, rz) if pml_rz is None else pml_rz, use_graph, tblock)
         check(lib().sweep_plan_set_tuning(self._h, ctypes.byref(t)))
         self._saved_id = -1
 
@@ -133,13 +135,14 @@ class Plan:
     def tiles(self) -> dict:
         """The acoustic tiling: tiles are 64 columns x `rows` rows; the interior
         ones (no C-PML cell) form the rectangle of tile columns [x0, x1) and
-        rows [z0, z1); the others are the frame."""
+        rows [z0, z1), `deep` of them advancing two steps per pass; the others
+        are the frame."""
         a, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
-        rect = (ctypes.c_int * 4)()
+        rect = (ctypes.c_int * 5)()
         check(lib().sweep_plan_tiles(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c),
                                      rect))
         return {"interior": a.value, "frame": b.value, "rows": c.value,
-                "x0": rect[0], "x1": rect[1], "z0": rect[2], "z1": rect[3]}
+                "x0": rect[0], "x1": rect[1], "z0": rect[2], "z1": rect[3], "deep": rect[4]}
 
     def workspace_bytes(self, for_backward: bool) -> int:
         return int(lib().sweep_plan_workspace_bytes(self._h, int(bool(for_backward))))
@@ -199,10 +202,11 @@ class Plan:
 
     # ---------------------------------------------------------------- timing
     # fwd = forward, adj = adjoint, rec = segment recomputation (stores B^n);
-    # acoustic: *_int = interior-tile kernel, *_zpml / *_xpml = z-frame / x-frame
-    # C-PML kernels; elastic: the whole step in the *_int slot
+    # acoustic: *_int = interior-tile kernel (single steps), *_zpml / *_xpml =
+    # z-frame / x-frame C-PML kernels, *_deep = two-step passes over the deep
+    # interior tiles; elastic: the whole step in the *_int slot
     KERNEL_CLASSES = ("fwd_int", "fwd_zpml", "fwd_xpml", "adj_int", "adj_zpml", "adj_xpml",
-                      "rec_int", "rec_zpml", "rec_xpml")
+                      "rec_int", "rec_zpml", "rec_xpml", "fwd_deep", "adj_deep", "rec_deep")
 
     def set_profiling(self, enable: bool, period: int = 1):
         """Time the step kernels with HIP events (every `period`-th step)."""

@@ -135,6 +135,25 @@ def test_gradient_tilings_bitwise(sw, rz, prz):
     assert torch.equal(out[0], out[1])
 
 
+@pytest.mark.parametrize("rz,ckpt", [(4, 50), (4, 17), (8, 17)])
+def test_two_step_passes_bitwise(sw, rz, ckpt):
+    """Deep interior tiles advanced two steps per pass give the same bits as
+    single steps: gathers and gradient, with checkpoint intervals that leave
+    single-step remainders (odd segment lengths)."""
+    w = synth.workload("interface200")
+    case = case_from_workload(w, nt=230)
+    case.ckpt = ckpt
+    resid = _dev(synth.bandlimited_noise((case.nshots, case.nt, case.nrec), 10.0, case.dt, 5))
+    out = []
+    for tb in (1, 2):
+        plan, d = _gpu_forward(sw, case, save=True, tuning=dict(rz=rz, pml_rz=4, tblock=tb))
+        if tb == 2:
+            assert plan.tiles()["deep"] > 0
+        out.append((d.clone(), plan.backward(resid).clone()))
+    assert torch.equal(out[0][0], out[1][0])
+    assert torch.equal(out[0][1], out[1][1])
+
+
 def test_repeatable(sw):
     case = random_case(6, nt=100, ckpt=30)
     resid = _dev(synth.bandlimited_noise((case.nshots, case.nt, case.nrec), 15.0, case.dt, 4))
