@@ -70,14 +70,15 @@ typedef struct {
  * independent of every field here. */
 typedef struct {
   int rz;          /* acoustic tiles are 64 x 4 rz cells; rows per thread of the
-                      interior kernel: 1, 2, 4 or 8 (default 4) */
+                      interior kernel: 1, 2, 4 or 8 (default 8) */
   int pml_rz;      /* rows per thread of the C-PML (frame-tile) kernels, <= rz: a
                       frame tile is split into rz / pml_rz work-groups (default 4) */
   int use_graph;   /* 1 = capture each forward/backward time loop as a hipGraph */
   int tblock;      /* acoustic: 2 = advance the deep interior tiles (no C-PML cell
                       within 4 cells, no source or receiver within 8, an 8-cell halo
                       inside the grid) two time steps per pass, marching down runs of
-                      them; 1 = one step per pass (default 1) */
+                      them; 1 = one step per pass (default 2). Batches take single
+                      steps whatever this field says */
 } sweep_tuning;
 
 typedef struct sweep_plan sweep_plan;
@@ -99,9 +100,11 @@ int sweep_plan_set_tuning(sweep_plan* plan, const sweep_tuning* t);
 int sweep_plan_get_tuning(const sweep_plan* plan, sweep_tuning* t);
 
 /* Autotuner: runs `steps` forward steps of this plan for every supported tile
- * choice (rz and pml_rz in 1, 2, 4, 8 with pml_rz <= rz), keeps the fastest and
- * stores it in the plan; `cache_path` (may be NULL) is a text file of previous
- * results, one line "arch physics NX NZ nshots rz pml_rz us_per_step", keyed by
+ * choice (rz and pml_rz in 1, 2, 4, 8 with pml_rz <= rz) and time-blocking
+ * depth (tblock 1 or 2; 2 only where the tiling has deep tiles), keeps the
+ * fastest and stores it in the plan; `cache_path` (may be NULL) is a text file
+ * of previous results, one line
+ * "arch physics NX NZ nshots rz pml_rz tblock us_per_step", keyed by
  * (GPU arch, physics, NX, NZ, nshots), read first and appended to. Synchronises `stream`. d_work needs the forward-only
  * workspace. Results never depend on the choice (bitwise). *chosen_rz (may be
  * NULL) receives the selected value. */

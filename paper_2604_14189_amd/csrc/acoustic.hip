@@ -861,40 +861,47 @@ __device__ __forceinline__ void ac_adj_pml_body(const AcStep& a, const int tile,
 // cells and no source or receiver within 8 cells (for any shot), so the first
 // step can be recomputed on a 4-cell ring around it from the field with an
 // 8-cell halo. A run is a chunk of consecutive deep tiles of one tile column;
-// one work-group marches down it eight rows at a time. Per iteration it
-//   1. computes step 1 (p^{n+1} / lambda^n) on 8 new rows, 72 columns wide
+// one work-group marches down it H rows at a time (H = kMH). Per iteration it
+//   1. computes step 1 (p^{n+1} / lambda^n) on H new rows, 72 columns wide
 //      (the strip and its 4-column ring), from p^n rows held in LDS;
-//   2. computes step 2 (p^{n+2} / lambda^{n-1}) on the 8 rows above them;
-//   3. stores the 8 next rows of p^n (80 columns) that it loaded into
-//      registers at the start of the iteration.
-// LDS holds both levels in circular buffers of 24 rows. Rows move by 8 per
-// iteration, so a buffer's slots repeat every 3 iterations; the first 8 slots
-// are also written 24 rows further on, which keeps every 16-row stencil window
-// contiguous (32 rows allocated). Only the ring rows at the start of a run and
-// the 4-column side rings are computed twice, and only the 8-cell halo rows and
-// columns are read twice (from L2). The per-cell arithmetic is that of the
-// interior kernel, so both steps give the same bits as two single steps. HBM
-// traffic per cell and two steps: 20 bytes forward (28 saving B), 36 adjoint.
+//   2. computes step 2 (p^{n+2} / lambda^{n-1}) on the H rows starting 4 above;
+//   3. stores the next H rows of p^n (80 columns), loaded into registers one
+//      iteration earlier.
+// LDS holds both levels in circular buffers of 3H slots. Rows move by H per
+// iteration, so the slots repeat every 3 iterations; the first slots are also
+// written 3H rows further on, which keeps every stencil window contiguous.
+// Only the ring rows at the start of a run and the 4-column side rings are
+// computed twice, and only the 8-cell halo rows and columns are read twice
+// (from L2). The per-cell arithmetic is that of the interior kernel, so both
+// steps give the same bits as two single steps. HBM traffic per cell and two
+// steps: 20 bytes forward (28 saving B), 36 adjoint.
 // ---------------------------------------------------------------------------
-constexpr int kMH = 8;                                // rows per iteration
+constexpr int kMH = 16;                               // rows per iteration
 constexpr int kMS = 3 * kMH;                          // slots of a circular buffer
 constexpr int kMA = kTX + 16;                         // level-n columns: x0-8 .. x0+71
 constexpr int kMB = kTX + 8;                          // step-1 columns: x0-4 .. x0+67
-constexpr int kNA = kMH * kMA;                        // cells of 8 level-n rows
-constexpr int kNB = kMH * kMB;                        // step-1 cells per iteration
+constexpr int kNA = kMH * kMA;                        // cells of H level-n rows
 constexpr int kKA = (kNA + kThreads - 1) / kThreads;  // per thread
-constexpr int kKB = (kNB + kThreads - 1) / kThreads;
-static_assert(kThreads == 4 * kTX && kMH == 8, "step 2 maps 2 rows x 64 columns per wave");
+constexpr int kR2 = kMH / 4;                          // step-2 rows per thread
+constexpr int kPB = (kMH + 16) / kMH;                 // level-n blocks of the prologue
+static_assert(kThreads == 4 * kTX && (kMH == 8 || kMH == 16), "march geometry");
 
-// Slot arithmetic, with z the row offset from the run's first row za:
-//   level-n row za-8+j is in slot j mod 24; step-1 row za-4+j in slot j mod 24.
-// Iteration i (rows r = za + 8i) reads level n rows [r, r+16) (window from slot
-// 8((i+1) mod 3)), writes step-1 rows [r+4, r+12) (from slot 8((i+1) mod 3)),
-// reads step-1 rows [r-4, r+12) (window from slot 8(i mod 3)) and stores level
-// n rows [r+16, r+24) (from slot 8(i mod 3)).
-__device__ __forceinline__ int mslot(int i) { return kMH * (i % 3); }
+// Slot arithmetic, with rows relative to the run's first row za:
+//   level-n row za-8+j is in slot j mod 3H, step-1 row za-4+j in slot j mod 3H.
+// Iteration i (rows r = za + H i):
+//   step 1 writes rows [r+4, r+H+4) from slot (8 + H i) mod 3H (wrapping), and
+//     reads level n rows [r, r+H+8), a window from the same slot;
+//   step 2 reads step-1 rows [r-4, r+H+4), a window from slot H i mod 3H, and
+//     level n rows [r, r+H);
+//   level n rows [r+H+8, r+2H+8) are stored as one block from slot
+//     (16 + H (i+1)) mod 3H, a multiple of H.
+// Level-n slots [0, H) are duplicated at 3H, step-1 slots [0, 8) at 3H; every
+// window then stays below 3H + H (level n) or 3H + 8 (step 1).
+__device__ __forceinline__ int m_win1(int i) { return (8 + kMH * i) % kMS; }
+__device__ __forceinline__ int m_win2(int i) { return (kMH * i) % kMS; }
+__device__ __forceinline__ int m_put(int i) { return (16 + kMH * (i + 1)) % kMS; }
 
-// Loads 8 rows [z, z+8) x [x0-8, x0+72) of a level-n field. A run's 8-cell
+// Loads H rows [z, z+H) x [x0-8, x0+72) of a level-n field. A run's 8-cell
 // halo lies inside the grid, so the loads need no guard; rows past zlim (which
 // only feed results that are not kept) are clamped to zlim - 1. The loads are
 // unconditional on purpose: a load under a per-lane condition must complete
@@ -906,11 +913,11 @@ __device__ __forceinline__ void march_load_a(const float* f, int z, int zlim, in
     const int e = threadIdx.x + k * kThreads;
     const int r = e / kMA, c = e - (e / kMA) * kMA;
     const int gz = min(z + r, zlim - 1), gx = x0 - 8 + c;
-    v[k] = f[(size_t)gz * NX + gx];
+    v[k] = f[(unsigned)(gz * NX + gx)];
   }
 }
 
-// Writes them to slot s (and s + 24 for the first 8 slots); with w, the
+// Writes them to slot s (a multiple of H; slot 0 also at 3H); with w, the
 // products w v (w loaded by march_load_a from the same rows).
 __device__ __forceinline__ void march_put_a(float* sa, int s, const float (&v)[kKA]) {
 #pragma unroll
@@ -935,32 +942,29 @@ __device__ __forceinline__ void march_put_a(float* sa, int s, const float (&w)[k
   }
 }
 
-// Row and column of this thread's step-1 cells within an 8 x 72 block.
+// Step-1 cells of an H x 72 block. The 64 strip columns go to the threads as
+// in step 2 (column lx, rows wz .. wz+H/4-1), so a wave reads consecutive LDS
+// words and takes the vertical stencil from a register window. The 8 ring
+// columns (4 each side) are spread over the first 2H lanes of every wave.
+constexpr int kRL = 2 * kMH;  // ring lanes per wave
 struct MarchCells {
-  int r[kKB], c[kKB];
+  int rr, rc;   // this lane's ring cell: row, step-1 column (0..3, 68..71)
+  bool ring;    // lane takes a ring cell
   __device__ __forceinline__ MarchCells() {
-#pragma unroll
-    for (int k = 0; k < kKB; ++k) {
-      const int e = threadIdx.x + k * kThreads;
-      r[k] = e / kMB;
-      c[k] = e - (e / kMB) * kMB;
-    }
+    const int lane = threadIdx.x & 63;
+    const int q = (lane & (kRL - 1)) + kRL * (threadIdx.x >> 6);
+    ring = lane < kRL;
+    rr = q >> 3;
+    const int c = q & 7;
+    rc = c < 4 ? c : c + kTX;
   }
-  __device__ __forceinline__ bool live(int k) const { return threadIdx.x + k * kThreads < kNB; }
 };
 
-// Step-1 inputs of rows [z, z+8) (rows past zlim clamped, as above).
-__device__ __forceinline__ void march_load_b(const MarchCells& mc, const float* f, int z, int zlim,
-                                             int x0, int NX, bool nt, float (&v)[kKB]) {
-#pragma unroll
-  for (int k = 0; k < kKB; ++k) {
-    const int gz = min(z + mc.r[k], zlim - 1), gx = x0 - 4 + mc.c[k];
-    const float* p = &f[(size_t)gz * NX + gx];
-    v[k] = nt ? ld_nt(p) : *p;
-  }
-}
-
 // Geometry of one march (a run of one shot).
+// Plane offsets fit in 32 bits; the per-shot planes are addressed from
+// work-group-uniform base pointers. wz is uniform within a wave (a wave is 64
+// consecutive threads), which readfirstlane tells the compiler, so branches on
+// it are scalar.
 struct March {
   int NX, NZ, x0, za, zb, nit, alim, blim, lx, wz;
   size_t base;
@@ -975,31 +979,81 @@ struct March {
     alim = zb + 8;
     blim = zb + 4;
     lx = threadIdx.x & 63;
-    wz = (threadIdx.x >> 6) * 2;
+    wz = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6) * kR2);
   }
 };
 
-// p^{n+1} on step-1 rows [z, z+8) (level-n window from slot wa, whose first row
-// is z - 4; results to slot wb), stored at the run's own cells.
+// Per-thread step-1 inputs of one field for rows [z, z+H): the strip cells
+// (column lx, rows wz..) and the ring cell (rows past zlim clamped, as above).
+struct StepIn {
+  float v[kR2], ring;
+};
+__device__ __forceinline__ void march_load_b(const March& m, const MarchCells& mc, const float* f,
+                                             int z, bool nt, StepIn& in) {
+#pragma unroll
+  for (int j = 0; j < kR2; ++j) {
+    const int gz = min(z + m.wz + j, m.blim - 1);
+    const float* p = &f[(unsigned)(gz * m.NX + m.x0 + m.lx)];
+    in.v[j] = nt ? ld_nt(p) : *p;
+  }
+  const int gz = min(z + mc.rr, m.blim - 1);
+  const float* p = &f[(unsigned)(gz * m.NX + m.x0 - 4 + mc.rc)];
+  in.ring = nt ? ld_nt(p) : *p;
+}
+
+// Slot of step-1 row offset r from window slot w (wrapping at 3H).
+__device__ __forceinline__ int m_wrap(int w, int r) {
+  const int s = w + r;
+  return s >= kMS ? s - kMS : s;
+}
+
+// Laplacian parts of the interior update at the cell of LDS row `row` (a
+// pointer to the cell), with the vertical neighbours from the register window
+// w (centre w[j + 4]); the same operations in the same order as d2s.
+template <int NW>
+__device__ __forceinline__ float lap_x(const float* row, const float (&w)[NW], int j) {
+  return d2c(w[j + 4], row[1], row[-1], row[2], row[-2], row[3], row[-3], row[4], row[-4]);
+}
+template <int NW>
+__device__ __forceinline__ float lap_z(const float (&w)[NW], int j) {
+  return d2c(w[j + 4], w[j + 5], w[j + 3], w[j + 6], w[j + 2], w[j + 7], w[j + 1], w[j + 8], w[j]);
+}
+
+// p^{n+1} on step-1 rows [z, z+nrows) (level-n window from slot wa, whose first
+// row is z - 4; results from slot wb), stored at the run's own cells.
 __device__ __forceinline__ void march_fwd_step1(const AcStep& a, const March& m,
                                                 const MarchCells& mc, const float* sa, float* sb,
-                                                int wa, int wb, int z, const float (&pm)[kKB],
-                                                const float (&cs)[kKB]) {
+                                                int wa, int wb, int z, int nrows,
+                                                const StepIn& pm, const StepIn& cs) {
+  // strip cells
+  float w[kR2 + 8];
 #pragma unroll
-  for (int k = 0; k < kKB; ++k) {
-    if (!mc.live(k)) continue;
-    const float* f = &sa[(wa + 4 + mc.r[k]) * kMA + mc.c[k] + 4];
-    const float L = d2s(f, 1) + d2s(f, kMA);
-    const float pn = fmaf(cs[k], L, 2.0f * f[0] - pm[k]);
-    const int s = wb + mc.r[k];
-    sb[s * kMB + mc.c[k]] = pn;
-    if (s < kMH) sb[(s + kMS) * kMB + mc.c[k]] = pn;
-    const int gz = z + mc.r[k];
-    if (gz >= m.za && gz < m.zb && mc.c[k] >= 4 && mc.c[k] < 4 + kTX) {
-      const size_t gi = m.base + (size_t)gz * m.NX + (m.x0 - 4 + mc.c[k]);
-      st_nt(&a.next[gi], pn);
-      if (a.B_out) st_nt(&a.B_out[gi], L);
+  for (int t = 0; t < kR2 + 8; ++t) w[t] = sa[(wa + m.wz + t) * kMA + m.lx + 8];
+#pragma unroll
+  for (int j = 0; j < kR2; ++j) {
+    const int rj = m.wz + j;
+    if (rj >= nrows) continue;
+    const float* row = &sa[(wa + 4 + rj) * kMA + m.lx + 8];
+    const float L = lap_x(row, w, j) + lap_z(w, j);
+    const float pn = fmaf(cs.v[j], L, 2.0f * w[j + 4] - pm.v[j]);
+    const int s = m_wrap(wb, rj);
+    sb[s * kMB + m.lx + 4] = pn;
+    if (s < 8) sb[(s + kMS) * kMB + m.lx + 4] = pn;
+    const int gz = z + rj;
+    if (gz >= m.za && gz < m.zb) {
+      const unsigned gi = gz * m.NX + m.x0 + m.lx;
+      st_nt(&(a.next + m.base)[gi], pn);
+      if (a.B_out) st_nt(&(a.B_out + m.base)[gi], L);
     }
+  }
+  // ring cells (not stored: they belong to neighbouring strips)
+  if (mc.ring && mc.rr < nrows) {
+    const float* f = &sa[(wa + 4 + mc.rr) * kMA + mc.rc + 4];
+    const float L = d2s(f, 1) + d2s(f, kMA);
+    const float pn = fmaf(cs.ring, L, 2.0f * f[0] - pm.ring);
+    const int s = m_wrap(wb, mc.rr);
+    sb[s * kMB + mc.rc] = pn;
+    if (s < 8) sb[(s + kMS) * kMB + mc.rc] = pn;
   }
 }
 
@@ -1008,36 +1062,39 @@ __device__ __forceinline__ void march_fwd_step1(const AcStep& a, const March& m,
 // this iteration; load: filled with those of iteration i+1.
 __device__ __forceinline__ void march_fwd_iter(const AcStep& a, const March& m,
                                                const MarchCells& mc, float* sa, float* sb, int i,
-                                               float (&pm)[kKB], float (&cs)[kKB],
-                                               const float (&put)[kKA], float (&load)[kKA]) {
+                                               StepIn& pm, StepIn& cs, const float (&put)[kKA],
+                                               float (&load)[kKA]) {
   const float* cur = a.cur + m.base;
   const float* prev = a.prev + m.base;
   const int r = m.za + kMH * i;
-  const int wa = mslot(i + 1), wb2 = mslot(i);
-  float c2[2];
+  const int w1 = m_win1(i), w2 = m_win2(i);
+  float c2[kR2];
 #pragma unroll
-  for (int j = 0; j < 2; ++j) {
+  for (int j = 0; j < kR2; ++j) {
     const int gz = min(r + m.wz + j, m.zb - 1);
-    c2[j] = a.Cs[(size_t)gz * m.NX + m.x0 + m.lx];
+    c2[j] = a.Cs[(unsigned)(gz * m.NX + m.x0 + m.lx)];
   }
-  march_fwd_step1(a, m, mc, sa, sb, wa, wa, r + 4, pm, cs);
-  march_load_b(mc, prev, r + 20, m.blim, m.x0, m.NX, true, pm);
-  march_load_b(mc, a.Cs, r + 20, m.blim, m.x0, m.NX, false, cs);
-  march_load_a(cur, r + 24, m.alim, m.x0, m.NX, load);
+  march_fwd_step1(a, m, mc, sa, sb, w1, w1, r + 4, kMH, pm, cs);
+  march_load_b(m, mc, prev, r + 2 * kMH + 4, true, pm);
+  march_load_b(m, mc, a.Cs, r + 2 * kMH + 4, false, cs);
+  march_load_a(cur, r + 2 * kMH + 8, m.alim, m.x0, m.NX, load);
   __syncthreads();
-  // step 2 on rows [r, r+8)
+  // step 2 on rows [r, r+H)
+  float w[kR2 + 8];
 #pragma unroll
-  for (int j = 0; j < 2; ++j) {
+  for (int t = 0; t < kR2 + 8; ++t) w[t] = sb[(w2 + m.wz + t) * kMB + m.lx + 4];
+#pragma unroll
+  for (int j = 0; j < kR2; ++j) {
     const int gz = r + m.wz + j;
     if (gz >= m.zb) continue;
-    const float* f = &sb[(wb2 + 4 + m.wz + j) * kMB + m.lx + 4];
-    const float L = d2s(f, 1) + d2s(f, kMB);
-    const float pn = fmaf(c2[j], L, 2.0f * f[0] - sa[(wa + m.wz + j) * kMA + m.lx + 8]);
-    const size_t gi = m.base + (size_t)gz * m.NX + m.x0 + m.lx;
-    st_nt(&a.next2[gi], pn);
-    if (a.B_out2) st_nt(&a.B_out2[gi], L);
+    const float* row = &sb[(w2 + 4 + m.wz + j) * kMB + m.lx + 4];
+    const float L = lap_x(row, w, j) + lap_z(w, j);
+    const float pn = fmaf(c2[j], L, 2.0f * w[j + 4] - sa[(w1 + m.wz + j) * kMA + m.lx + 8]);
+    const unsigned gi = gz * m.NX + m.x0 + m.lx;
+    st_nt(&(a.next2 + m.base)[gi], pn);
+    if (a.B_out2) st_nt(&(a.B_out2 + m.base)[gi], L);
   }
-  march_put_a(sa, wb2, put);
+  march_put_a(sa, m_put(i), put);
   __syncthreads();
 }
 
@@ -1045,29 +1102,28 @@ __device__ __forceinline__ void march_fwd_iter(const AcStep& a, const March& m,
 // iterations (a copy from one set to the other would wait for its loads).
 __device__ __forceinline__ void ac_march_fwd(const AcStep& a, const int2 run, const int shot) {
   __shared__ float sa[(kMS + kMH) * kMA];  // p^n
-  __shared__ float sb[(kMS + kMH) * kMB];  // p^{n+1}
+  __shared__ float sb[(kMS + 8) * kMB];    // p^{n+1}
   const March m(a, run, shot);
   const MarchCells mc;
   const float* cur = a.cur + m.base;
   const float* prev = a.prev + m.base;
 
-  // prologue: level n rows [za-8, za+16), step 1 on rows [za-4, za+4)
-  float va[3][kKA], pm0[kKB], cs0[kKB], pm1[kKB], cs1[kKB], n0[kKA], n1[kKA];
-  march_load_a(cur, m.za - 8, m.alim, m.x0, m.NX, va[0]);
-  march_load_a(cur, m.za, m.alim, m.x0, m.NX, va[1]);
-  march_load_a(cur, m.za + 8, m.alim, m.x0, m.NX, va[2]);
-  march_load_b(mc, prev, m.za - 4, m.blim, m.x0, m.NX, true, pm1);
-  march_load_b(mc, a.Cs, m.za - 4, m.blim, m.x0, m.NX, false, cs1);
-  march_load_b(mc, prev, m.za + 4, m.blim, m.x0, m.NX, true, pm0);
-  march_load_b(mc, a.Cs, m.za + 4, m.blim, m.x0, m.NX, false, cs0);
-  march_load_a(cur, m.za + 16, m.alim, m.x0, m.NX, n0);
-  march_put_a(sa, 0, va[0]);
-  march_put_a(sa, 8, va[1]);
-  march_put_a(sa, 16, va[2]);
+  // prologue: level n rows [za-8, za+H+8), step 1 on rows [za-4, za+4)
+  float va[kPB][kKA], n0[kKA], n1[kKA];
+  StepIn pm0, cs0, pm1, cs1;
+#pragma unroll
+  for (int b = 0; b < kPB; ++b) march_load_a(cur, m.za - 8 + kMH * b, m.alim, m.x0, m.NX, va[b]);
+  march_load_b(m, mc, prev, m.za - 4, true, pm1);
+  march_load_b(m, mc, a.Cs, m.za - 4, false, cs1);
+  march_load_b(m, mc, prev, m.za + 4, true, pm0);
+  march_load_b(m, mc, a.Cs, m.za + 4, false, cs0);
+  march_load_a(cur, m.za + kMH + 8, m.alim, m.x0, m.NX, n0);
+#pragma unroll
+  for (int b = 0; b < kPB; ++b) march_put_a(sa, kMH * b, va[b]);
   __syncthreads();
-  march_fwd_step1(a, m, mc, sa, sb, 0, 0, m.za - 4, pm1, cs1);
-  march_load_b(mc, prev, m.za + 12, m.blim, m.x0, m.NX, true, pm1);
-  march_load_b(mc, a.Cs, m.za + 12, m.blim, m.x0, m.NX, false, cs1);
+  march_fwd_step1(a, m, mc, sa, sb, 0, 0, m.za - 4, 8, pm1, cs1);
+  march_load_b(m, mc, prev, m.za + kMH + 4, true, pm1);
+  march_load_b(m, mc, a.Cs, m.za + kMH + 4, false, cs1);
 
   for (int i = 0; i < m.nit; i += 2) {
     march_fwd_iter(a, m, mc, sa, sb, i, pm0, cs0, n0, n1);
@@ -1075,42 +1131,15 @@ __device__ __forceinline__ void ac_march_fwd(const AcStep& a, const int2 run, co
   }
 }
 
-// lambda^n on step-1 rows [z, z+8) from q = Cs lambda^{n+1} (window from slot
-// wa, first row z - 4): Cs lambda^n and lambda^n to slot wb, stored at the run's
-// own cells.
-__device__ __forceinline__ void march_adj_step1(const AcStep& a, const March& m,
-                                                const MarchCells& mc, const float* sq, float* sb,
-                                                float* sl, int wa, int wb, int z,
-                                                const float (&l1)[kKB], const float (&l2)[kKB],
-                                                const float (&cr)[kKB]) {
-#pragma unroll
-  for (int k = 0; k < kKB; ++k) {
-    if (!mc.live(k)) continue;
-    const float* f = &sq[(wa + 4 + mc.r[k]) * kMA + mc.c[k] + 4];
-    const float lam = ((2.0f * l1[k] - l2[k]) + d2s(f, 1)) + d2s(f, kMA);
-    const int s = wb + mc.r[k];
-    const float cl = cr[k] * lam;
-    sb[s * kMB + mc.c[k]] = cl;
-    if (s < kMH) sb[(s + kMS) * kMB + mc.c[k]] = cl;
-    if (mc.c[k] >= 4 && mc.c[k] < 4 + kTX) {
-      sl[s * kTX + mc.c[k] - 4] = lam;
-      if (s < kMH) sl[(s + kMS) * kTX + mc.c[k] - 4] = lam;
-      const int gz = z + mc.r[k];
-      if (gz >= m.za && gz < m.zb)
-        st_nt(&a.next[m.base + (size_t)gz * m.NX + (m.x0 - 4 + mc.c[k])], lam);
-    }
-  }
-}
-
 // Step-1 inputs of the adjoint: lambda^{n+1}, lambda^{n+2} and Cs.
 struct AdjIn {
-  float l1[kKB], l2[kKB], cr[kKB];
+  StepIn l1, l2, cr;
 };
 __device__ __forceinline__ void march_adj_load_b(const AcStep& a, const March& m,
                                                  const MarchCells& mc, int z, AdjIn& v) {
-  march_load_b(mc, a.cur + m.base, z, m.blim, m.x0, m.NX, false, v.l1);
-  march_load_b(mc, a.prev + m.base, z, m.blim, m.x0, m.NX, true, v.l2);
-  march_load_b(mc, a.Cs, z, m.blim, m.x0, m.NX, false, v.cr);
+  march_load_b(m, mc, a.cur + m.base, z, false, v.l1);
+  march_load_b(m, mc, a.prev + m.base, z, true, v.l2);
+  march_load_b(m, mc, a.Cs, z, false, v.cr);
 }
 // Level-n rows of the adjoint: lambda^{n+1} and Cs (multiplied when stored).
 struct AdjRows {
@@ -1122,68 +1151,106 @@ __device__ __forceinline__ void march_adj_load_a(const AcStep& a, const March& m
   march_load_a(a.Cs, z, m.alim, m.x0, m.NX, v.c);
 }
 
+// lambda^n on step-1 rows [z, z+nrows) from q = Cs lambda^{n+1} (window from
+// slot wa, first row z - 4): Cs lambda^n and lambda^n from slot wb, stored at
+// the run's own cells.
+__device__ __forceinline__ void march_adj_step1(const AcStep& a, const March& m,
+                                                const MarchCells& mc, const float* sq, float* sb,
+                                                float* sl, int wa, int wb, int z, int nrows,
+                                                const AdjIn& in) {
+  float w[kR2 + 8];
+#pragma unroll
+  for (int t = 0; t < kR2 + 8; ++t) w[t] = sq[(wa + m.wz + t) * kMA + m.lx + 8];
+#pragma unroll
+  for (int j = 0; j < kR2; ++j) {
+    const int rj = m.wz + j;
+    if (rj >= nrows) continue;
+    const float* row = &sq[(wa + 4 + rj) * kMA + m.lx + 8];
+    const float lam = ((2.0f * in.l1.v[j] - in.l2.v[j]) + lap_x(row, w, j)) + lap_z(w, j);
+    const int s = m_wrap(wb, rj);
+    const float cl = in.cr.v[j] * lam;
+    sb[s * kMB + m.lx + 4] = cl;
+    sl[s * kTX + m.lx] = lam;
+    if (s < 8) {
+      sb[(s + kMS) * kMB + m.lx + 4] = cl;
+      sl[(s + kMS) * kTX + m.lx] = lam;
+    }
+    const int gz = z + rj;
+    if (gz >= m.za && gz < m.zb) st_nt(&(a.next + m.base)[(unsigned)(gz * m.NX + m.x0 + m.lx)], lam);
+  }
+  if (mc.ring && mc.rr < nrows) {
+    const float* f = &sq[(wa + 4 + mc.rr) * kMA + mc.rc + 4];
+    const float lam = ((2.0f * in.l1.ring - in.l2.ring) + d2s(f, 1)) + d2s(f, kMA);
+    const int s = m_wrap(wb, mc.rr);
+    const float cl = in.cr.ring * lam;
+    sb[s * kMB + mc.rc] = cl;
+    if (s < 8) sb[(s + kMS) * kMB + mc.rc] = cl;
+  }
+}
+
 __device__ __forceinline__ void march_adj_iter(const AcStep& a, const March& m,
                                                const MarchCells& mc, float* sq, float* sb,
                                                float* sl, int i, AdjIn& in, const AdjRows& put,
                                                AdjRows& load) {
   const int r = m.za + kMH * i;
-  const int wa = mslot(i + 1), wb2 = mslot(i);
-  float p1[2], b1[2], b2[2], gg[2];
+  const int w1 = m_win1(i), w2 = m_win2(i);
+  float p1[kR2], b1[kR2], b2[kR2], gg[kR2];
   const bool gacc = !a.g_init;
 #pragma unroll
-  for (int j = 0; j < 2; ++j) {
+  for (int j = 0; j < kR2; ++j) {
     const int gz = min(r + m.wz + j, m.zb - 1);
-    const size_t gi = m.base + (size_t)gz * m.NX + m.x0 + m.lx;
-    p1[j] = a.cur[gi];
-    b1[j] = ld_nt(&a.B_in[gi]);
-    b2[j] = ld_nt(&a.B_in2[gi]);
-    gg[j] = gacc ? ld_nt(&a.g[gi]) : 0.0f;
+    const unsigned gi = gz * m.NX + m.x0 + m.lx;
+    p1[j] = (a.cur + m.base)[gi];
+    b1[j] = ld_nt(&(a.B_in + m.base)[gi]);
+    b2[j] = ld_nt(&(a.B_in2 + m.base)[gi]);
+    gg[j] = gacc ? ld_nt(&(a.g + m.base)[gi]) : 0.0f;
   }
-  march_adj_step1(a, m, mc, sq, sb, sl, wa, wa, r + 4, in.l1, in.l2, in.cr);
-  march_adj_load_b(a, m, mc, r + 20, in);
-  march_adj_load_a(a, m, r + 24, load);
+  march_adj_step1(a, m, mc, sq, sb, sl, w1, w1, r + 4, kMH, in);
+  march_adj_load_b(a, m, mc, r + 2 * kMH + 4, in);
+  march_adj_load_a(a, m, r + 2 * kMH + 8, load);
   __syncthreads();
-  // step 2 on rows [r, r+8) and the gradient of both steps
+  // step 2 on rows [r, r+H) and the gradient of both steps
+  float w[kR2 + 8];
 #pragma unroll
-  for (int j = 0; j < 2; ++j) {
+  for (int t = 0; t < kR2 + 8; ++t) w[t] = sb[(w2 + m.wz + t) * kMB + m.lx + 4];
+#pragma unroll
+  for (int j = 0; j < kR2; ++j) {
     const int gz = r + m.wz + j;
     if (gz >= m.zb) continue;
-    const int s = wb2 + 4 + m.wz + j;
-    const float* f = &sb[s * kMB + m.lx + 4];
+    const int s = w2 + 4 + m.wz + j;
+    const float* row = &sb[s * kMB + m.lx + 4];
     const float lam_n = sl[s * kTX + m.lx];
-    const float lam = ((2.0f * lam_n - p1[j]) + d2s(f, 1)) + d2s(f, kMB);
-    const size_t gi = m.base + (size_t)gz * m.NX + m.x0 + m.lx;
+    const float lam = ((2.0f * lam_n - p1[j]) + lap_x(row, w, j)) + lap_z(w, j);
+    const unsigned gi = gz * m.NX + m.x0 + m.lx;
     const float gb = p1[j] * b1[j];
     const float g1 = a.g_init ? gb : gg[j] + gb;
-    st_nt(&a.g[gi], g1 + lam_n * b2[j]);
-    st_nt(&a.next2[gi], lam);
+    st_nt(&(a.g + m.base)[gi], g1 + lam_n * b2[j]);
+    st_nt(&(a.next2 + m.base)[gi], lam);
   }
-  march_put_a(sq, wb2, put.c, put.l);
+  march_put_a(sq, m_put(i), put.c, put.l);
   __syncthreads();
 }
 
 // Reverse steps n and n-1; g += lambda^{n+1} B'^n + lambda^n B'^{n-1}.
 __device__ __forceinline__ void ac_march_adj(const AcStep& a, const int2 run, const int shot) {
   __shared__ float sq[(kMS + kMH) * kMA];  // q = Cs lambda^{n+1}
-  __shared__ float sb[(kMS + kMH) * kMB];  // Cs lambda^n
-  __shared__ float sl[(kMS + kMH) * kTX];  // lambda^n on the strip's own columns
+  __shared__ float sb[(kMS + 8) * kMB];    // Cs lambda^n
+  __shared__ float sl[(kMS + 8) * kTX];    // lambda^n on the strip's own columns
   const March m(a, run, shot);
   const MarchCells mc;
 
-  AdjRows va[3], n0, n1;
+  AdjRows va[kPB], n0, n1;
   AdjIn in0, in1;
-  march_adj_load_a(a, m, m.za - 8, va[0]);
-  march_adj_load_a(a, m, m.za, va[1]);
-  march_adj_load_a(a, m, m.za + 8, va[2]);
+#pragma unroll
+  for (int b = 0; b < kPB; ++b) march_adj_load_a(a, m, m.za - 8 + kMH * b, va[b]);
   march_adj_load_b(a, m, mc, m.za - 4, in1);
   march_adj_load_b(a, m, mc, m.za + 4, in0);
-  march_adj_load_a(a, m, m.za + 16, n0);
-  march_put_a(sq, 0, va[0].c, va[0].l);
-  march_put_a(sq, 8, va[1].c, va[1].l);
-  march_put_a(sq, 16, va[2].c, va[2].l);
+  march_adj_load_a(a, m, m.za + kMH + 8, n0);
+#pragma unroll
+  for (int b = 0; b < kPB; ++b) march_put_a(sq, kMH * b, va[b].c, va[b].l);
   __syncthreads();
-  march_adj_step1(a, m, mc, sq, sb, sl, 0, 0, m.za - 4, in1.l1, in1.l2, in1.cr);
-  march_adj_load_b(a, m, mc, m.za + 12, in1);
+  march_adj_step1(a, m, mc, sq, sb, sl, 0, 0, m.za - 4, 8, in1);
+  march_adj_load_b(a, m, mc, m.za + kMH + 4, in1);
 
   for (int i = 0; i < m.nit; i += 2) {
     march_adj_iter(a, m, mc, sq, sb, sl, i, in0, n0, n1);

@@ -41,7 +41,9 @@ hipEvent_t* KernelTimer::take(int ci, int cz, int cx) {
     std::vector<hipEvent_t>& v = ev[cls[k]];
     while (v.size() < used[cls[k]] + 2) {
       hipEvent_t e;
-      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      // timing only: no system-scope fence, which would write back and
+      // invalidate the caches and slow the launch that follows
+      if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
       v.push_back(e);
     }
     six[2 * k] = v[used[cls[k]]];
@@ -845,9 +847,9 @@ extern "C" int sweep_plan_create(const sweep_problem* pb, const int32_t* src_xz,
     }
     p->rec_cell[r] = (z + (pb->free_surface ? 0 : p->P)) * p->NX + x + p->P;
   }
-  p->tune.rz = 4;
+  p->tune.rz = 8;
   p->tune.pml_rz = 4;
-  p->tune.tblock = 1;
+  p->tune.tblock = 2;
   p->tune.use_graph = 0;
   if (pb->physics == SWEEP_ACOUSTIC) {
     ac_build_tiling(p);
@@ -1169,12 +1171,14 @@ extern "C" int sweep_plan_autotune(sweep_plan* p, const float* d_model, const fl
           line[key.size()] != ' ')
         continue;
       std::istringstream is(line.substr(key.size()));
-      int rz = 0, prz = 0;
+      int rz = 0, prz = 0, tb = 0;
       double us = 0;
-      if (is >> rz >> prz >> us && rz_ok(rz) && rz_ok(prz) && prz <= rz) {
+      if (is >> rz >> prz >> tb >> us && rz_ok(rz) && rz_ok(prz) && prz <= rz &&
+          (tb == 1 || tb == 2)) {
         sweep_tuning t = p->tune;
         t.rz = rz;
         t.pml_rz = prz;
+        t.tblock = tb;
         const int rc = sweep_plan_set_tuning(p, &t);
         if (rc) return rc;
         if (chosen_rz) *chosen_rz = rz;
@@ -1193,15 +1197,18 @@ extern "C" int sweep_plan_autotune(sweep_plan* p, const float* d_model, const fl
   SWEEP_HIP(hipEventCreate(&e0));
   SWEEP_HIP(hipEventCreate(&e1));
   const int cand[4] = {1, 2, 4, 8};
-  int best = keep.rz, best_p = keep.pml_rz;
+  int best = keep.rz, best_p = keep.pml_rz, best_t = keep.tblock;
   double best_us = 1e300;
   const int nsteps = std::min(steps, p->pb.nt);
   for (int c : cand) {
     for (int cp : cand) {
+     for (int tb = 1; tb <= 2; ++tb) {
       if (cp > c || rc) continue;
       p->tune.rz = c;
       p->tune.pml_rz = cp;
+      p->tune.tblock = tb;
       ac_build_tiling(p);
+      if (tb == 2 && !ac_two_steps(p)) continue;  // no deep tiles: same as tb = 1
       if ((rc = ac_upload_geometry(p, d_work, L, s))) break;
       for (int rep = 0; rep < 2 && !rc; ++rep) {  // first pass warms up
         rc = ac_fwd_prologue(p, d_model, d_wavelet, d_work, L, s);
@@ -1228,7 +1235,9 @@ extern "C" int sweep_plan_autotune(sweep_plan* p, const float* d_model, const fl
         best_us = us;
         best = c;
         best_p = cp;
+        best_t = tb;
       }
+     }
     }
   }
   (void)hipEventDestroy(e0);
@@ -1242,10 +1251,11 @@ extern "C" int sweep_plan_autotune(sweep_plan* p, const float* d_model, const fl
   sweep_tuning t = keep;
   t.rz = best;
   t.pml_rz = best_p;
+  t.tblock = best_t;
   if ((rc = sweep_plan_set_tuning(p, &t))) return rc;
   if (cache_path && *cache_path) {
     std::ofstream out(cache_path, std::ios::app);
-    out << key << " " << best << " " << best_p << " " << best_us << "\n";
+    out << key << " " << best << " " << best_p << " " << best_t << " " << best_us << "\n";
   }
   if (chosen_rz) *chosen_rz = best;
   return SWEEP_OK;

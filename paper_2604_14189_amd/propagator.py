@@ -101,8 +101,8 @@ class Plan:
         check(lib().sweep_plan_get_tuning(self._h, ctypes.byref(t)))
         return {"rz": t.rz, "pml_rz": t.pml_rz, "use_graph": t.use_graph, "tblock": t.tblock}
 
-    def set_tuning(self, rz: int = 4, pml_rz: Optional[int] = None, use_graph: int = 0,
-                   tblock: int = 1):
+    def set_tuning(self, rz: int = 8, pml_rz: Optional[int] = None, use_graph: int = 0,
+                   tblock: int = 2):
         """rz: rows per thread of the interior kernel (tiles of 64 x 4 rz);
         pml_rz: rows per thread of the C-PML kernels (<= rz, default min(4, rz));
         tblock: time steps per pass over the deep interior tiles (1 or 2)."""
@@ -112,8 +112,8 @@ class Plan:
 
     def autotune(self, model: torch.Tensor, wavelet: torch.Tensor, steps: int = 20,
                  cache_path: Optional[str] = None) -> int:
-        """Pick the fastest tiling (rz, pml_rz) for this plan (cached); returns rz
-        (both are in .tuning afterwards)."""
+        """Pick the fastest tiling (rz, pml_rz) and time-blocking depth (tblock)
+        for this plan (cached); returns rz (all three are in .tuning afterwards)."""
         if self.nparam == 1 and model.dim() == 2:
             model = model.unsqueeze(0)
         _need(model, self._model_shape(), "model")

@@ -102,7 +102,8 @@ def test_autotune_picks_a_tiling_and_caches(sw, tmp_path):
     with open(cache) as f:
         lines = f.read().strip().splitlines()
     f = lines[0].split() if len(lines) == 1 else []
-    assert f and f[-3] == str(rz) and f[-2] == str(plan.tuning["pml_rz"])
+    assert f and f[-4] == str(rz) and f[-3] == str(plan.tuning["pml_rz"])
+    assert f[-2] == str(plan.tuning["tblock"]) and f[-2] in ("1", "2")
     assert plan.tuning["pml_rz"] <= rz
     d1 = plan.forward(_dev(c.v), _dev(c.wav)).clone()
     plan2 = c.plan()
