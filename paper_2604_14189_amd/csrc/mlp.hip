@@ -70,29 +70,52 @@ __global__ void mlp_cast_kernel(const float* theta, uint16_t* wp) {
 // Work-group: 64 rows x 128 columns; wave w: rows (w&1)*32, columns (w>>1)*64
 // (two 32x32 accumulator tiles).
 // --------------------------------------------------------------------------
-template <int MODE>
+// R (the reduction length) is a template parameter so that the k loop unrolls.
+// The operands of 4 k-steps are loaded one chunk ahead of the matrix
+// instructions that use them (two register buffers), and the loads are
+// unconditional: rows past M are clamped to M - 1, computed and not stored (a
+// guarded load would become a per-lane branch that waits for every load).
+template <int MODE, int R>
 __global__ __launch_bounds__(256) void mlp_gemm_kernel(const uint16_t* __restrict__ X,
-                                                       const uint16_t* __restrict__ Bm, int R,
-                                                       int M, const float* __restrict__ bias,
+                                                       const uint16_t* __restrict__ Bm, int M,
+                                                       const float* __restrict__ bias,
                                                        const uint16_t* __restrict__ mask,
                                                        uint16_t* __restrict__ out) {
+  constexpr int C = 4, NC = R / 16 / C;  // k-steps per chunk, chunks
+  static_assert(R % (16 * C) == 0, "reduction length");
   const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int r0 = blockIdx.x * 64 + (w & 1) * 32;
   const int c0 = blockIdx.y * 128 + (w >> 1) * 64;
-  const int arow = r0 + (l & 31);
+  const int arow = min(r0 + (l & 31), M - 1);
   const int kofs = (l >> 5) * 8;
-  const bool aok = arow < M;
-  const uint16_t* ap = X + (size_t)(aok ? arow : 0) * R + kofs;
+  const uint16_t* ap = X + (size_t)arow * R + kofs;
   const uint16_t* bp0 = Bm + (size_t)(c0 + (l & 31)) * R + kofs;
   const uint16_t* bp1 = bp0 + (size_t)32 * R;
   floatx16 acc0 = {0}, acc1 = {0};
-  const bf16x8 zero = {0, 0, 0, 0, 0, 0, 0, 0};
-  for (int k = 0; k < R; k += 16) {
-    const bf16x8 a = aok ? load8(ap + k) : zero;
-    const bf16x8 b0 = load8(bp0 + k);
-    const bf16x8 b1 = load8(bp1 + k);
-    acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b0, acc0, 0, 0, 0);
-    acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b1, acc1, 0, 0, 0);
+  bf16x8 a[2][C], b0[2][C], b1[2][C];
+#pragma unroll
+  for (int s = 0; s < C; ++s) {
+    a[0][s] = load8(ap + 16 * s);
+    b0[0][s] = load8(bp0 + 16 * s);
+    b1[0][s] = load8(bp1 + 16 * s);
+  }
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const int u = c & 1;
+    if (c + 1 < NC) {
+#pragma unroll
+      for (int s = 0; s < C; ++s) {
+        const int k = 16 * (C * (c + 1) + s);
+        a[u ^ 1][s] = load8(ap + k);
+        b0[u ^ 1][s] = load8(bp0 + k);
+        b1[u ^ 1][s] = load8(bp1 + k);
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < C; ++s) {
+      acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[u][s], b0[u][s], acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[u][s], b1[u][s], acc1, 0, 0, 0);
+    }
   }
 #pragma unroll
   for (int t = 0; t < 2; ++t) {
@@ -135,38 +158,81 @@ __global__ void mlp_head_fwd_kernel(const uint16_t* __restrict__ H, const uint16
   v[m] = vmin + vscale / (1.0f + expf(-yy));
 }
 
+constexpr int kMlpThreads = 256;
+
+// Per-chunk reductions over rows: one work-group per chunk of kMlpChunk rows.
+// Thread t takes columns 4 (t % 64) .. +3 (8-byte loads) of rows g, g+4, g+8,
+// ... of the chunk (g = t / 64), so the rows' loads are independent; the four
+// row groups are added in LDS in a fixed order (results are deterministic).
+constexpr int kRowGroups = kMlpThreads / (kMlpWidth / 4);
+static_assert(kRowGroups == 4, "4 row groups of 64 column quads");
+__device__ __forceinline__ void unpack4(uint2 v, float (&f)[4]) {
+  f[0] = bf2f((uint16_t)(v.x & 0xffffu));
+  f[1] = bf2f((uint16_t)(v.x >> 16));
+  f[2] = bf2f((uint16_t)(v.y & 0xffffu));
+  f[3] = bf2f((uint16_t)(v.y >> 16));
+}
+__device__ __forceinline__ uint2 pack4(const float (&f)[4]) {
+  return make_uint2((uint32_t)f2bf(f[0]) | ((uint32_t)f2bf(f[1]) << 16),
+                    (uint32_t)f2bf(f[2]) | ((uint32_t)f2bf(f[3]) << 16));
+}
+// Sums red[g][c] over the row groups in order and writes them to dst[c].
+__device__ __forceinline__ void sum_groups(float (*red)[kMlpWidth + 1], float* dst, int n) {
+  __syncthreads();
+  for (int c = threadIdx.x; c < n; c += kMlpThreads)
+    dst[c] = ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
+}
+
 // dy_m = dv_m vscale s (1 - s); dZ4 = bf16(dy w5 [h4 > 0]); per-chunk partial
-// sums of dy h4 (-> grad w5) and of dy (-> grad b5). One work-group per chunk of
-// kMlpChunk rows, thread k = column.
-__global__ __launch_bounds__(256) void mlp_head_bwd_kernel(const float* dv, const float* y,
-                                                           const uint16_t* __restrict__ H,
-                                                           const uint16_t* w5, int M,
-                                                           float vscale, uint16_t* dZ,
-                                                           float* partial) {
-  const int k = threadIdx.x;
+// sums of dy h4 (-> grad w5) and of dy (-> grad b5).
+__global__ __launch_bounds__(kMlpThreads) void mlp_head_bwd_kernel(const float* dv, const float* y,
+                                                                   const uint16_t* __restrict__ H,
+                                                                   const uint16_t* w5, int M,
+                                                                   float vscale, uint16_t* dZ,
+                                                                   float* partial) {
+  __shared__ float red[kRowGroups][kMlpWidth + 1];
+  const int q = threadIdx.x & 63, g = threadIdx.x >> 6;
   const int m0 = blockIdx.x * kMlpChunk, m1 = min(M, m0 + kMlpChunk);
-  const float wk = bf2f(w5[k]);
-  float accw = 0.0f, accb = 0.0f;
-  for (int m = m0; m < m1; ++m) {
+  float wk[4], accw[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+  unpack4(*reinterpret_cast<const uint2*>(w5 + 4 * q), wk);
+  float accb = 0.0f;
+#pragma unroll 4
+  for (int m = m0 + g; m < m1; m += kRowGroups) {
     const float s = 1.0f / (1.0f + expf(-y[m]));
     const float dy = dv[m] * vscale * s * (1.0f - s);
-    const float h = bf2f(H[(size_t)m * kMlpWidth + k]);
-    accw = fmaf(dy, h, accw);
+    float h[4], z[4];
+    unpack4(*reinterpret_cast<const uint2*>(H + (size_t)m * kMlpWidth + 4 * q), h);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      accw[j] = fmaf(dy, h[j], accw[j]);
+      z[j] = h[j] > 0.0f ? dy * wk[j] : 0.0f;
+    }
     accb += dy;
-    dZ[(size_t)m * kMlpWidth + k] = f2bf(h > 0.0f ? dy * wk : 0.0f);
+    *reinterpret_cast<uint2*>(dZ + (size_t)m * kMlpWidth + 4 * q) = pack4(z);
   }
-  partial[(size_t)blockIdx.x * (kMlpWidth + 1) + k] = accw;
-  if (k == 0) partial[(size_t)blockIdx.x * (kMlpWidth + 1) + kMlpWidth] = accb;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) red[g][4 * q + j] = accw[j];
+  if (q == 0) red[g][kMlpWidth] = accb;
+  sum_groups(red, partial + (size_t)blockIdx.x * (kMlpWidth + 1), kMlpWidth + 1);
 }
 
 // per-chunk column sums of dZ (-> bias gradient)
-__global__ __launch_bounds__(256) void mlp_colsum_kernel(const uint16_t* __restrict__ dZ, int M,
-                                                         float* partial) {
-  const int k = threadIdx.x;
+__global__ __launch_bounds__(kMlpThreads) void mlp_colsum_kernel(const uint16_t* __restrict__ dZ,
+                                                                 int M, float* partial) {
+  __shared__ float red[kRowGroups][kMlpWidth + 1];
+  const int q = threadIdx.x & 63, g = threadIdx.x >> 6;
   const int m0 = blockIdx.x * kMlpChunk, m1 = min(M, m0 + kMlpChunk);
-  float acc = 0.0f;
-  for (int m = m0; m < m1; ++m) acc += bf2f(dZ[(size_t)m * kMlpWidth + k]);
-  partial[(size_t)blockIdx.x * kMlpWidth + k] = acc;
+  float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll 8
+  for (int m = m0 + g; m < m1; m += kRowGroups) {
+    float v[4];
+    unpack4(*reinterpret_cast<const uint2*>(dZ + (size_t)m * kMlpWidth + 4 * q), v);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[j] += v[j];
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) red[g][4 * q + j] = acc[j];
+  sum_groups(red, partial + (size_t)blockIdx.x * kMlpWidth, kMlpWidth);
 }
 
 // partial[chunk][n][k] = sum over the chunk's rows m of dZ[m][n] H[m][k]
@@ -205,23 +271,38 @@ __global__ __launch_bounds__(256) void mlp_dw_kernel(const uint16_t* __restrict_
     }
 }
 
-// dst[e] = sum over chunks c (in order) of partial[c][e], accumulated in float64
-__global__ void mlp_reduce_kernel(const float* partial, int nchunk, int len, float* dst) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= len) return;
-  double acc = 0.0;
-  for (int c = 0; c < nchunk; ++c) acc += (double)partial[(size_t)c * len + e];
-  dst[e] = (float)acc;
-}
-
-// split a strided partial array: dst[e] = sum_c partial[c * stride + off + e]
+// dst[e] = sum over chunks c of partial[c * stride + off + e], in float64: four
+// independent accumulators over c mod 4 (so the loads overlap), added in order.
 __global__ void mlp_reduce_strided_kernel(const float* partial, int nchunk, int stride, int off,
                                           int len, float* dst) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= len) return;
-  double acc = 0.0;
-  for (int c = 0; c < nchunk; ++c) acc += (double)partial[(size_t)c * stride + off + e];
-  dst[e] = (float)acc;
+  const float* p = partial + off + e;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  int c = 0;
+  for (; c + 4 <= nchunk; c += 4) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[j] += (double)p[(size_t)(c + j) * stride];
+  }
+#pragma unroll
+  for (int j = 0; j < 3; ++j)
+    if (c + j < nchunk) acc[j] += (double)p[(size_t)(c + j) * stride];
+  dst[e] = (float)(((acc[0] + acc[1]) + acc[2]) + acc[3]);
+}
+__global__ void mlp_reduce_kernel(const float* partial, int nchunk, int len, float* dst) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= len) return;
+  const float* p = partial + e;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  int c = 0;
+  for (; c + 4 <= nchunk; c += 4) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[j] += (double)p[(size_t)(c + j) * len];
+  }
+#pragma unroll
+  for (int j = 0; j < 3; ++j)
+    if (c + j < nchunk) acc[j] += (double)p[(size_t)(c + j) * len];
+  dst[e] = (float)(((acc[0] + acc[1]) + acc[2]) + acc[3]);
 }
 
 // Adam with bias correction: c1 = 1/(1-b1^t), c2 = 1/(1-b2^t)
@@ -288,11 +369,11 @@ int mlp_launch_cast(const float* theta, uint16_t* wp, hipStream_t s) {
 int mlp_launch_forward(const uint16_t* wp, const float* theta, const uint16_t* feats, int M,
                        float vmin, float vscale, float* v, const MlpWork& w, hipStream_t s) {
   const dim3 g((M + 63) / 64, kMlpWidth / 128);
-  hipLaunchKernelGGL(mlp_gemm_kernel<0>, g, dim3(256), 0, s, feats, wp + kWp1, kMlpFeat, M,
+  hipLaunchKernelGGL((mlp_gemm_kernel<0, kMlpFeat>), g, dim3(256), 0, s, feats, wp + kWp1, M,
                      theta + kThB1, (const uint16_t*)nullptr, w.H[0]);
   for (int l = 0; l < 3; ++l)
-    hipLaunchKernelGGL(mlp_gemm_kernel<0>, g, dim3(256), 0, s, (const uint16_t*)w.H[l],
-                       wp + kWpHidden[l], kMlpWidth, M, theta + kThBHidden[l],
+    hipLaunchKernelGGL((mlp_gemm_kernel<0, kMlpWidth>), g, dim3(256), 0, s,
+                       (const uint16_t*)w.H[l], wp + kWpHidden[l], M, theta + kThBHidden[l],
                        (const uint16_t*)nullptr, w.H[l + 1]);
   hipLaunchKernelGGL(mlp_head_fwd_kernel, dim3((M + 255) / 256), dim3(256), 0, s,
                      (const uint16_t*)w.H[3], wp + kWp5, theta + kThB5, M, vmin, vscale, w.y, v);
@@ -324,9 +405,9 @@ int mlp_launch_backward(const uint16_t* wp, const uint16_t* feats, int M, float 
                        kMlpWidth, grad + bofs);
     if (l > 0) {
       const dim3 g((M + 63) / 64, kMlpWidth / 128);
-      hipLaunchKernelGGL(mlp_gemm_kernel<1>, g, dim3(256), 0, s, dz, wp + kWpHiddenT[l - 1],
-                         kMlpWidth, M, (const float*)nullptr, (const uint16_t*)w.H[l - 1],
-                         w.dZ[l - 1]);
+      hipLaunchKernelGGL((mlp_gemm_kernel<1, kMlpWidth>), g, dim3(256), 0, s, dz,
+                         wp + kWpHiddenT[l - 1], M, (const float*)nullptr,
+                         (const uint16_t*)w.H[l - 1], w.dZ[l - 1]);
     }
   }
   SWEEP_HIP(hipGetLastError());
