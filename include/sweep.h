@@ -75,7 +75,7 @@ typedef struct {
                       frame tile is split into rz / pml_rz work-groups (default 4) */
   int use_graph;   /* 1 = capture each forward/backward time loop as a hipGraph */
   int tblock;      /* acoustic: 2 = advance the deep interior tiles (no C-PML cell
-                      within 4 cells, no source or receiver within 8, an 8-cell halo
+                      within 4 cells, no source or receiver within 4, an 8-cell halo
                       inside the grid) two time steps per pass, marching down runs of
                       them; 1 = one step per pass (default 2). Batches take single
                       steps whatever this field says */
@@ -125,7 +125,7 @@ int sweep_plan_padded(const sweep_plan* plan, int* NX, int* NZ);
  * [rect[0], rect[1]) x tile rows [rect[2], rect[3]) (all zero when empty);
  * they are advanced by the interior kernel (16 bytes per cell-update forward).
  * rect[4] receives how many of them are deep (no C-PML cell within 4 cells,
- * no source or receiver within 8, their 8-cell halo inside the grid) and
+ * no source or receiver within 4, their 8-cell halo inside the grid) and
  * advance two steps per pass when tuning.tblock = 2 (0 when tblock = 1). The frame_tiles others are advanced
  * by the C-PML kernels: the z frame (the rectangle's columns above and below
  * it) and the x frame (all other tile columns). rect (5 ints) may be NULL.

@@ -858,7 +858,7 @@ __device__ __forceinline__ void ac_adj_pml_body(const AcStep& a, const int tile,
 
 // ---------------------------------------------------------------------------
 // Deep runs: two time steps per pass. A deep tile has no C-PML cell within 4
-// cells and no source or receiver within 8 cells (for any shot), so the first
+// cells and no source or receiver within 4 cells (for any shot), so the first
 // step can be recomputed on a 4-cell ring around it from the field with an
 // 8-cell halo. A run is a chunk of consecutive deep tiles of one tile column;
 // one work-group marches down it H rows at a time (H = kMH). Per iteration it

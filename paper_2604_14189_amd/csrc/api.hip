@@ -90,15 +90,19 @@ void ac_build_tiling(sweep_plan* p) {
   const int ns = p->pb.nshots, nr = p->pb.nrec;
   // Deep tiles (two steps per pass): interior tiles with no C-PML band cell
   // within 4 cells (the first step is recomputed on a 4-cell ring) and no
-  // source or receiver of any shot within 8 cells (no injection on the ring).
+  // source or receiver of any shot on the tile or its 4-cell ring. The pass
+  // computes values only there: a source adds to p^{n+1} and a residual to
+  // lambda^n at its own cell, and a receiver records its own cell, so cells
+  // further out (the 8-cell halo is only read) need no injection or recording.
+  constexpr int R = 4;
   std::vector<char> near((size_t)p->ntiles, 0);
   auto mark = [&](int c) {
     const int gx = c % p->NX, gz = c / p->NX;
-    for (int tz = std::max(0, (gz - 8 - TZ + 1) / TZ - 1); tz <= (gz + 8) / TZ && tz < p->tiles_z; ++tz)
-      for (int tx = std::max(0, (gx - 8 - kTX + 1) / kTX - 1); tx <= (gx + 8) / kTX && tx < p->tiles_x;
+    for (int tz = std::max(0, (gz - R - TZ + 1) / TZ - 1); tz <= (gz + R) / TZ && tz < p->tiles_z; ++tz)
+      for (int tx = std::max(0, (gx - R - kTX + 1) / kTX - 1); tx <= (gx + R) / kTX && tx < p->tiles_x;
            ++tx) {
         const int x0 = tx * kTX, z0 = tz * TZ;
-        if (gx >= x0 - 8 && gx < x0 + kTX + 8 && gz >= z0 - 8 && gz < z0 + TZ + 8)
+        if (gx >= x0 - R && gx < x0 + kTX + R && gz >= z0 - R && gz < z0 + TZ + R)
           near[(size_t)tz * p->tiles_x + tx] = 1;
       }
   };

@@ -67,76 +67,99 @@ __global__ void mlp_cast_kernel(const float* theta, uint16_t* wp) {
 // out[M][256] = epilogue(X[M][R] . Bm[256][R]^T)
 //   mode 0 (forward): relu(acc + bias[c]) -> bf16
 //   mode 1 (backward dX): acc * [mask[m][c] > 0] -> bf16
-// Work-group: 64 rows x 128 columns; wave w: rows (w&1)*32, columns (w>>1)*64
-// (two 32x32 accumulator tiles).
+// Work-group: 128 rows x 128 columns; wave w: rows (w & 1) * 64, columns
+// (w >> 1) * 64, as 2 x 2 accumulator tiles of 32 x 32. The reduction runs in
+// chunks of 32: the A (128 x 32) and B (128 x 32) chunks are staged in LDS,
+// double-buffered, each loaded with 16-byte global loads one chunk ahead of
+// the matrix instructions that use it. LDS rows are padded to 40 bf16 (80 B),
+// so the 32 rows read by a half-wave fall in different banks. Rows past M are
+// clamped to M - 1, computed and not stored (no per-lane guard on the loads).
 // --------------------------------------------------------------------------
-// R (the reduction length) is a template parameter so that the k loop unrolls.
-// The operands of 4 k-steps are loaded one chunk ahead of the matrix
-// instructions that use them (two register buffers), and the loads are
-// unconditional: rows past M are clamped to M - 1, computed and not stored (a
-// guarded load would become a per-lane branch that waits for every load).
+constexpr int kGK = 32;       // reduction chunk
+constexpr int kGS = kGK + 8;  // LDS row stride (bf16)
+constexpr int kGL = 128 * kGK / 8 / 256;  // 16-byte loads per thread per operand and chunk
+
 template <int MODE, int R>
 __global__ __launch_bounds__(256) void mlp_gemm_kernel(const uint16_t* __restrict__ X,
                                                        const uint16_t* __restrict__ Bm, int M,
                                                        const float* __restrict__ bias,
                                                        const uint16_t* __restrict__ mask,
                                                        uint16_t* __restrict__ out) {
-  constexpr int C = 4, NC = R / 16 / C;  // k-steps per chunk, chunks
-  static_assert(R % (16 * C) == 0, "reduction length");
-  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int r0 = blockIdx.x * 64 + (w & 1) * 32;
-  const int c0 = blockIdx.y * 128 + (w >> 1) * 64;
-  const int arow = min(r0 + (l & 31), M - 1);
-  const int kofs = (l >> 5) * 8;
-  const uint16_t* ap = X + (size_t)arow * R + kofs;
-  const uint16_t* bp0 = Bm + (size_t)(c0 + (l & 31)) * R + kofs;
-  const uint16_t* bp1 = bp0 + (size_t)32 * R;
-  floatx16 acc0 = {0}, acc1 = {0};
-  bf16x8 a[2][C], b0[2][C], b1[2][C];
+  constexpr int NC = R / kGK;
+  static_assert(R % kGK == 0 && kGL == 2, "gemm geometry");
+  __shared__ __attribute__((aligned(16))) uint16_t sA[2][128 * kGS];
+  __shared__ __attribute__((aligned(16))) uint16_t sB[2][128 * kGS];
+  const int tid = threadIdx.x, l = tid & 63, w = tid >> 6;
+  const int rb = blockIdx.x * 128, cb = blockIdx.y * 128;
+  uint4 ga[kGL], gb[kGL];
+  auto gload = [&](int c) {
 #pragma unroll
-  for (int s = 0; s < C; ++s) {
-    a[0][s] = load8(ap + 16 * s);
-    b0[0][s] = load8(bp0 + 16 * s);
-    b1[0][s] = load8(bp1 + 16 * s);
-  }
+    for (int j = 0; j < kGL; ++j) {
+      const int sg = tid + 256 * j, row = sg >> 2, kk = c * kGK + 8 * (sg & 3);
+      ga[j] = *reinterpret_cast<const uint4*>(X + (size_t)min(rb + row, M - 1) * R + kk);
+      gb[j] = *reinterpret_cast<const uint4*>(Bm + (size_t)(cb + row) * R + kk);
+    }
+  };
+  auto lstore = [&](int buf) {
+#pragma unroll
+    for (int j = 0; j < kGL; ++j) {
+      const int sg = tid + 256 * j, row = sg >> 2, kk = 8 * (sg & 3);
+      *reinterpret_cast<uint4*>(&sA[buf][row * kGS + kk]) = ga[j];
+      *reinterpret_cast<uint4*>(&sB[buf][row * kGS + kk]) = gb[j];
+    }
+  };
+  floatx16 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = floatx16{0};
+  const int ar = (w & 1) * 64 + (l & 31), br = (w >> 1) * 64 + (l & 31);
+  gload(0);
+  lstore(0);
+  __syncthreads();
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
     const int u = c & 1;
-    if (c + 1 < NC) {
+    if (c + 1 < NC) gload(c + 1);
 #pragma unroll
-      for (int s = 0; s < C; ++s) {
-        const int k = 16 * (C * (c + 1) + s);
-        a[u ^ 1][s] = load8(ap + k);
-        b0[u ^ 1][s] = load8(bp0 + k);
-        b1[u ^ 1][s] = load8(bp1 + k);
-      }
+    for (int ks = 0; ks < kGK / 16; ++ks) {
+      const int ko = ks * 16 + 8 * (l >> 5);
+      const bf16x8 a0 = *reinterpret_cast<const bf16x8*>(&sA[u][ar * kGS + ko]);
+      const bf16x8 a1 = *reinterpret_cast<const bf16x8*>(&sA[u][(ar + 32) * kGS + ko]);
+      const bf16x8 b0 = *reinterpret_cast<const bf16x8*>(&sB[u][br * kGS + ko]);
+      const bf16x8 b1 = *reinterpret_cast<const bf16x8*>(&sB[u][(br + 32) * kGS + ko]);
+      acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b1, acc[1][1], 0, 0, 0);
     }
-#pragma unroll
-    for (int s = 0; s < C; ++s) {
-      acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[u][s], b0[u][s], acc0, 0, 0, 0);
-      acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[u][s], b1[u][s], acc1, 0, 0, 0);
-    }
+    // the other buffer was last read before the previous barrier
+    if (c + 1 < NC) lstore(u ^ 1);
+    __syncthreads();
   }
 #pragma unroll
-  for (int t = 0; t < 2; ++t) {
-    const floatx16& acc = t == 0 ? acc0 : acc1;
-    const int col = c0 + t * 32 + (l & 31);
+  for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int tj = 0; tj < 2; ++tj) {
+      const floatx16& a = acc[ti][tj];
+      const int r0 = rb + (w & 1) * 64 + 32 * ti;
+      const int col = cb + (w >> 1) * 64 + 32 * tj + (l & 31);
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int row = r0 + 8 * i + (l >> 5) * 4 + j;
-        if (row >= M) continue;
-        const size_t o = (size_t)row * kMlpWidth + col;
-        float v = acc[4 * i + j];
-        if (MODE == 0) {
-          v = fmaxf(v + bias[col], 0.0f);
-        } else {
-          v = bf2f(mask[o]) > 0.0f ? v : 0.0f;
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int row = r0 + 8 * i + (l >> 5) * 4 + j;
+          if (row >= M) continue;
+          const size_t o = (size_t)row * kMlpWidth + col;
+          float v = a[4 * i + j];
+          if (MODE == 0) {
+            v = fmaxf(v + bias[col], 0.0f);
+          } else {
+            v = bf2f(mask[o]) > 0.0f ? v : 0.0f;
+          }
+          out[o] = f2bf(v);
         }
-        out[o] = f2bf(v);
-      }
-  }
+    }
 }
 
 // y_m = h4_m . w5 + b5 (float32, fixed order), v_m = vmin + vscale sigmoid(y_m)
@@ -368,7 +391,7 @@ int mlp_launch_cast(const float* theta, uint16_t* wp, hipStream_t s) {
 
 int mlp_launch_forward(const uint16_t* wp, const float* theta, const uint16_t* feats, int M,
                        float vmin, float vscale, float* v, const MlpWork& w, hipStream_t s) {
-  const dim3 g((M + 63) / 64, kMlpWidth / 128);
+  const dim3 g((M + 127) / 128, kMlpWidth / 128);
   hipLaunchKernelGGL((mlp_gemm_kernel<0, kMlpFeat>), g, dim3(256), 0, s, feats, wp + kWp1, M,
                      theta + kThB1, (const uint16_t*)nullptr, w.H[0]);
   for (int l = 0; l < 3; ++l)
@@ -404,7 +427,7 @@ int mlp_launch_backward(const uint16_t* wp, const uint16_t* feats, int M, float 
     hipLaunchKernelGGL(mlp_reduce_kernel, dim3(1), dim3(256), 0, s, (const float*)w.pB, nch,
                        kMlpWidth, grad + bofs);
     if (l > 0) {
-      const dim3 g((M + 63) / 64, kMlpWidth / 128);
+      const dim3 g((M + 127) / 128, kMlpWidth / 128);
       hipLaunchKernelGGL((mlp_gemm_kernel<1, kMlpWidth>), g, dim3(256), 0, s, dz,
                          wp + kWpHiddenT[l - 1], M, (const float*)nullptr,
                          (const uint16_t*)w.H[l - 1], w.dZ[l - 1]);
