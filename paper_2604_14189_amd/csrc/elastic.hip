@@ -28,14 +28,6 @@ namespace {
 constexpr float C1 = 9.0f / 8.0f;
 constexpr float C2 = -1.0f / 24.0f;
 
-// psi <- b psi + a G (only where a != 0); returns G + psi
-__device__ __forceinline__ float cpml(float* psi, size_t k, float G, float a, float b) {
-  if (a == 0.0f) return G;
-  const float p = fmaf(a, G, b * psi[k]);
-  psi[k] = p;
-  return G + p;
-}
-
 // ---------------------------------------------------------------------------
 // Tiles: 64 columns x kElTZ rows per work-group, thread (lx, w) owns column lx
 // and rows [w kElRZ, w kElRZ + kElRZ). The fields (or derived quantities) a
@@ -117,6 +109,15 @@ __device__ __forceinline__ ElTile el_tile(const ElStep& a) {
   return r;
 }
 
+// Guarded load without a per-lane branch: every lane loads (from `safe`, any
+// valid address, where !ok) and the value is selected afterwards. Written as a
+// branch, a guarded load must complete before the other path writes its
+// register, which serialises a sequence of them.
+__device__ __forceinline__ float ldz(const float* f, size_t i, bool ok, const float* safe) {
+  const float v = *(ok ? f + i : safe);
+  return ok ? v : 0.0f;
+}
+
 // Stages NF shot fields on the tile plus the halo: dst[q][box] = src[q][cell].
 template <int NF>
 __device__ __forceinline__ void el_stage(float (*dst)[kElBox], const float* const* src, int x0,
@@ -130,7 +131,7 @@ __device__ __forceinline__ void el_stage(float (*dst)[kElBox], const float* cons
     const bool ok = e < kElBox && gx >= 0 && gx < NX && gz >= 0 && gz < NZ;
     const size_t q = ok ? (size_t)gz * NX + gx : 0;
 #pragma unroll
-    for (int f = 0; f < NF; ++f) v[f][k] = ok ? src[f][q] : 0.0f;
+    for (int f = 0; f < NF; ++f) v[f][k] = ldz(src[f], q, ok, src[f]);
   }
 #pragma unroll
   for (int k = 0; k < kElK; ++k) {
@@ -142,8 +143,33 @@ __device__ __forceinline__ void el_stage(float (*dst)[kElBox], const float* cons
   }
 }
 
+// Per-thread cell geometry of a tile: column i (clamped ic for loads), rows
+// jb .. jb + kElRZ - 1 (jb is the same for the whole wave, which readfirstlane
+// tells the compiler, so the row coefficients are scalar loads and branches on
+// them are uniform).
+struct ElCells {
+  int i, ic, jb;
+  __device__ __forceinline__ ElCells(const ElTile& T, int NX) {
+    i = T.x0 + (threadIdx.x & 63);
+    ic = min(i, NX - 1);
+    jb = T.z0 + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) * kElRZ;
+  }
+};
+
+// C-PML update with a preloaded memory variable: psi <- b psi + a G where
+// a != 0 (stored), returns G + psi; G elsewhere.
+__device__ __forceinline__ float cpml_p(float* psi, size_t k, float G, float a, float b, float p0,
+                                        bool store) {
+  if (a == 0.0f) return G;
+  const float p = fmaf(a, G, b * p0);
+  if (store) psi[k] = p;
+  return G + p;
+}
+
 // ---------------------------------------------------------------------------
 // forward: velocity update  vx += dt bx (Dx+ txx + Dz- txz), vz += dt bz (Dx- txz + Dz+ tzz)
+// All global loads of a thread (staging, then its cells' operands and memory
+// variables) are issued before its first store.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void el_vel_kernel(ElStep a) {
   __shared__ float sb[3][kElBox];
@@ -155,26 +181,48 @@ __global__ __launch_bounds__(256) void el_vel_kernel(ElStep a) {
     const float* src[3] = {a.txx + so, a.tzz + so, a.txz + so};
     el_stage<3>(sb, src, T.x0, T.z0, NX, NZ);
   }
+  const ElCells C(T, NX);
+  const float axh = a.axh[C.ic], bxh = a.bxh[C.ic], axi = a.axi[C.ic], bxi = a.bxi[C.ic];
+  const bool wxh = __any(axh != 0.0f), wxi = __any(axi != 0.0f);
+  float ovx[kElRZ], ovz[kElRZ], cbx[kElRZ], cbz[kElRZ], p0[kElRZ], p1[kElRZ], p2[kElRZ],
+      p3[kElRZ];
+  float azi[kElRZ], bzi[kElRZ], azh[kElRZ], bzh[kElRZ];
+#pragma unroll
+  for (int r = 0; r < kElRZ; ++r) {
+    const int jc = min(C.jb + r, NZ - 1);
+    const size_t k = (size_t)jc * NX + C.ic;
+    ovx[r] = a.vx[so + k];
+    ovz[r] = a.vz[so + k];
+    cbx[r] = a.bx[k];
+    cbz[r] = a.bz[k];
+    azi[r] = a.azi[jc];
+    bzi[r] = a.bzi[jc];
+    azh[r] = a.azh[jc];
+    bzh[r] = a.bzh[jc];
+    p0[r] = wxh ? a.ps[0][so + k] : 0.0f;
+    p1[r] = azi[r] != 0.0f ? a.ps[1][so + k] : 0.0f;
+    p2[r] = wxi ? a.ps[2][so + k] : 0.0f;
+    p3[r] = azh[r] != 0.0f ? a.ps[3][so + k] : 0.0f;
+  }
   __syncthreads();
   const Box txx{sb[0], T.x0, T.z0}, tzz{sb[1], T.x0, T.z0}, txz{sb[2], T.x0, T.z0};
-  const int i = T.x0 + (threadIdx.x & 63);
-  const int jb = T.z0 + (threadIdx.x >> 6) * kElRZ;
+  const int i = C.i;
   const float ih = a.ih;
 #pragma unroll
   for (int r = 0; r < kElRZ; ++r) {
-    const int j = jb + r;
+    const int j = C.jb + r;
     if (i >= NX || j >= NZ) continue;
     const size_t k = (size_t)j * NX + i;
     const float Ga = bdxp(txx, i, j) * ih;
     const float Gb = bdz_txz(txz, i, j, a.fs) * ih;
     const float Gc = bdxm(txz, i, j) * ih;
     const float Gd = bdz_tzz(tzz, i, j, a.fs) * ih;
-    const float fvx = cpml(a.ps[0] + so, k, Ga, a.axh[i], a.bxh[i]) +
-                      cpml(a.ps[1] + so, k, Gb, a.azi[j], a.bzi[j]);
-    const float fvz = cpml(a.ps[2] + so, k, Gc, a.axi[i], a.bxi[i]) +
-                      cpml(a.ps[3] + so, k, Gd, a.azh[j], a.bzh[j]);
-    a.vx[so + k] = fmaf(a.dt * a.bx[k], fvx, a.vx[so + k]);
-    a.vz[so + k] = fmaf(a.dt * a.bz[k], fvz, a.vz[so + k]);
+    const float fvx = cpml_p(a.ps[0] + so, k, Ga, axh, bxh, p0[r], true) +
+                      cpml_p(a.ps[1] + so, k, Gb, azi[r], bzi[r], p1[r], true);
+    const float fvz = cpml_p(a.ps[2] + so, k, Gc, axi, bxi, p2[r], true) +
+                      cpml_p(a.ps[3] + so, k, Gd, azh[r], bzh[r], p3[r], true);
+    a.vx[so + k] = fmaf(a.dt * cbx[r], fvx, ovx[r]);
+    a.vz[so + k] = fmaf(a.dt * cbz[r], fvz, ovz[r]);
     if (a.tr[0]) {
       a.tr[0][so + k] = fvx;
       a.tr[1][so + k] = fvz;
@@ -208,34 +256,61 @@ __global__ __launch_bounds__(256) void el_str_kernel(ElStep a) {
     const float* src[2] = {a.vx + so, a.vz + so};
     el_stage<2>(sb, src, T.x0, T.z0, NX, NZ);
   }
+  const ElCells C(T, NX);
+  const float axi = a.axi[C.ic], bxi = a.bxi[C.ic], axh = a.axh[C.ic], bxh = a.bxh[C.ic];
+  const bool wxi = __any(axi != 0.0f), wxh = __any(axh != 0.0f);
+  float otxx[kElRZ], otzz[kElRZ], otxz[kElRZ], cxx_x[kElRZ], cxx_z[kElRZ], czz_x[kElRZ],
+      czz_z[kElRZ], mxz[kElRZ], p4[kElRZ], p5[kElRZ], p6[kElRZ], p7[kElRZ];
+  float azi[kElRZ], bzi[kElRZ], azh[kElRZ], bzh[kElRZ];
+#pragma unroll
+  for (int r = 0; r < kElRZ; ++r) {
+    const int jc = min(C.jb + r, NZ - 1);
+    const size_t k = (size_t)jc * NX + C.ic;
+    otxx[r] = a.txx[so + k];
+    otzz[r] = a.tzz[so + k];
+    otxz[r] = a.txz[so + k];
+    cxx_x[r] = a.cxx_x[k];
+    cxx_z[r] = a.cxx_z[k];
+    czz_x[r] = a.czz_x[k];
+    czz_z[r] = a.czz_z[k];
+    mxz[r] = a.mxz[k];
+    azi[r] = a.azi[jc];
+    bzi[r] = a.bzi[jc];
+    azh[r] = a.azh[jc];
+    bzh[r] = a.bzh[jc];
+    p4[r] = wxi ? a.ps[4][so + k] : 0.0f;
+    p5[r] = azi[r] != 0.0f ? a.ps[5][so + k] : 0.0f;
+    p6[r] = azh[r] != 0.0f ? a.ps[6][so + k] : 0.0f;
+    p7[r] = wxh ? a.ps[7][so + k] : 0.0f;
+  }
+  const int src = a.src_cell[shot];
+  const float sw = a.w * a.wavelet[(size_t)shot * a.nt + a.n];
   __syncthreads();
   const Box vx{sb[0], T.x0, T.z0}, vz{sb[1], T.x0, T.z0};
-  const int i = T.x0 + (threadIdx.x & 63);
-  const int jb = T.z0 + (threadIdx.x >> 6) * kElRZ;
+  const int i = C.i;
   const float ih = a.ih, dt = a.dt;
 #pragma unroll
   for (int r = 0; r < kElRZ; ++r) {
-    const int j = jb + r;
+    const int j = C.jb + r;
     if (i >= NX || j >= NZ) continue;
     const size_t k = (size_t)j * NX + i;
     const float Ge = bdxm(vx, i, j) * ih;
     const float Gf = bdz_vz(vz, i, j, a.fs) * ih;
     const float Gg = bdz_vx(vx, i, j, a.fs) * ih;
     const float Gh = bdxp(vz, i, j) * ih;
-    const float exx = cpml(a.ps[4] + so, k, Ge, a.axi[i], a.bxi[i]);
-    const float ezz = cpml(a.ps[5] + so, k, Gf, a.azi[j], a.bzi[j]);
-    const float exz = cpml(a.ps[6] + so, k, Gg, a.azh[j], a.bzh[j]) +
-                      cpml(a.ps[7] + so, k, Gh, a.axh[i], a.bxh[i]);
-    float txx = a.txx[so + k] + dt * fmaf(a.cxx_x[k], exx, a.cxx_z[k] * ezz);
-    float tzz = a.tzz[so + k] + dt * fmaf(a.czz_x[k], exx, a.czz_z[k] * ezz);
-    if ((int)k == a.src_cell[shot]) {
-      const float s = a.w * a.wavelet[(size_t)shot * a.nt + a.n];
-      txx += s;
-      tzz += s * a.smask[k];
+    const float exx = cpml_p(a.ps[4] + so, k, Ge, axi, bxi, p4[r], true);
+    const float ezz = cpml_p(a.ps[5] + so, k, Gf, azi[r], bzi[r], p5[r], true);
+    const float exz = cpml_p(a.ps[6] + so, k, Gg, azh[r], bzh[r], p6[r], true) +
+                      cpml_p(a.ps[7] + so, k, Gh, axh, bxh, p7[r], true);
+    float txx = otxx[r] + dt * fmaf(cxx_x[r], exx, cxx_z[r] * ezz);
+    float tzz = otzz[r] + dt * fmaf(czz_x[r], exx, czz_z[r] * ezz);
+    if ((int)k == src) {
+      txx += sw;
+      tzz += sw * a.smask[k];
     }
     a.txx[so + k] = txx;
     a.tzz[so + k] = tzz;
-    a.txz[so + k] = fmaf(dt * a.mxz[k], exz, a.txz[so + k]);
+    a.txz[so + k] = fmaf(dt * mxz[r], exz, otxz[r]);
     if (a.tr[2]) {
       a.tr[2][so + k] = exx;
       a.tr[3][so + k] = ezz;
@@ -274,7 +349,8 @@ __device__ __forceinline__ void el_stage_adj_s(const ElStep& a, float (*sb)[kElB
   const int NX = a.NX, NZ = a.NZ;
   const float dt = a.dt;
   float txx[kElK], tzz[kElK], txz[kElK], cxx_x[kElK], czz_x[kElK], cxx_z[kElK], czz_z[kElK],
-      mxz[kElK];
+      mxz[kElK], ax[kElK], az[kElK], azh[kElK], axh[kElK], q4[kElK], q5[kElK], q6[kElK],
+      q7[kElK];
 #pragma unroll
   for (int k = 0; k < kElK; ++k) {
     const int e = threadIdx.x + k * kThreads;
@@ -282,37 +358,37 @@ __device__ __forceinline__ void el_stage_adj_s(const ElStep& a, float (*sb)[kElB
     const int gx = x0 - 2 + c, gz = z0 - 2 + r;
     const bool ok = e < kElBox && gx >= 0 && gx < NX && gz >= 0 && gz < NZ;
     const size_t q = ok ? (size_t)gz * NX + gx : 0;
-    txx[k] = ok ? a.txx[so + q] : 0.0f;
-    tzz[k] = ok ? a.tzz[so + q] : 0.0f;
-    txz[k] = ok ? a.txz[so + q] : 0.0f;
-    cxx_x[k] = ok ? a.cxx_x[q] : 0.0f;
-    czz_x[k] = ok ? a.czz_x[q] : 0.0f;
-    cxx_z[k] = ok ? a.cxx_z[q] : 0.0f;
-    czz_z[k] = ok ? a.czz_z[q] : 0.0f;
-    mxz[k] = ok ? a.mxz[q] : 0.0f;
+    const int cx = ok ? gx : 0, cz = ok ? gz : 0;
+    txx[k] = ldz(a.txx + so, q, ok, a.txx);
+    tzz[k] = ldz(a.tzz + so, q, ok, a.tzz);
+    txz[k] = ldz(a.txz + so, q, ok, a.txz);
+    cxx_x[k] = ldz(a.cxx_x, q, ok, a.cxx_x);
+    czz_x[k] = ldz(a.czz_x, q, ok, a.czz_x);
+    cxx_z[k] = ldz(a.cxx_z, q, ok, a.cxx_z);
+    czz_z[k] = ldz(a.czz_z, q, ok, a.czz_z);
+    mxz[k] = ldz(a.mxz, q, ok, a.mxz);
+    ax[k] = ldz(a.axi, cx, ok, a.axi);
+    az[k] = ldz(a.azi, cz, ok, a.azi);
+    azh[k] = ldz(a.azh, cz, ok, a.azh);
+    axh[k] = ldz(a.axh, cx, ok, a.axh);
+    // memory variables only where a wave has a C-PML cell (wave-uniform branch)
+    q4[k] = __any(ax[k] != 0.0f) ? ldz(a.ps_in[4] + so, q, ok, a.ps_in[4]) : 0.0f;
+    q5[k] = __any(az[k] != 0.0f) ? ldz(a.ps_in[5] + so, q, ok, a.ps_in[5]) : 0.0f;
+    q6[k] = __any(azh[k] != 0.0f) ? ldz(a.ps_in[6] + so, q, ok, a.ps_in[6]) : 0.0f;
+    q7[k] = __any(axh[k] != 0.0f) ? ldz(a.ps_in[7] + so, q, ok, a.ps_in[7]) : 0.0f;
   }
 #pragma unroll
   for (int k = 0; k < kElK; ++k) {
     const int e = threadIdx.x + k * kThreads;
     if (e >= kElBox) break;
-    const int r = e / kElBW, c = e - (e / kElBW) * kElBW;
-    const int gx = x0 - 2 + c, gz = z0 - 2 + r;
-    float ge = 0.0f, gf = 0.0f, gg = 0.0f, gh = 0.0f;
-    if (gx >= 0 && gx < NX && gz >= 0 && gz < NZ) {
-      const size_t q = so + (size_t)gz * NX + gx;
-      const float e1 = dt * fmaf(cxx_x[k], txx[k], czz_x[k] * tzz[k]);
-      const float e2 = dt * fmaf(cxx_z[k], txx[k], czz_z[k] * tzz[k]);
-      const float e3 = dt * mxz[k] * txz[k];
-      const float ax = a.axi[gx], az = a.azi[gz], azh = a.azh[gz], axh = a.axh[gx];
-      ge = ax == 0.0f ? e1 : fmaf(ax, a.ps_in[4][q] + e1, e1);
-      gf = az == 0.0f ? e2 : fmaf(az, a.ps_in[5][q] + e2, e2);
-      gg = azh == 0.0f ? e3 : fmaf(azh, a.ps_in[6][q] + e3, e3);
-      gh = axh == 0.0f ? e3 : fmaf(axh, a.ps_in[7][q] + e3, e3);
-    }
-    sb[0][e] = ge;
-    sb[1][e] = gf;
-    sb[2][e] = gg;
-    sb[3][e] = gh;
+    const float e1 = dt * fmaf(cxx_x[k], txx[k], czz_x[k] * tzz[k]);
+    const float e2 = dt * fmaf(cxx_z[k], txx[k], czz_z[k] * tzz[k]);
+    const float e3 = dt * mxz[k] * txz[k];
+    // outside the grid every operand is 0, so every value below is 0 too
+    sb[0][e] = ax[k] == 0.0f ? e1 : fmaf(ax[k], q4[k] + e1, e1);
+    sb[1][e] = az[k] == 0.0f ? e2 : fmaf(az[k], q5[k] + e2, e2);
+    sb[2][e] = azh[k] == 0.0f ? e3 : fmaf(azh[k], q6[k] + e3, e3);
+    sb[3][e] = axh[k] == 0.0f ? e3 : fmaf(axh[k], q7[k] + e3, e3);
   }
 }
 
@@ -323,15 +399,52 @@ __global__ __launch_bounds__(256) void el_adj_s_kernel(ElStep a) {
   const size_t plane = (size_t)NX * NZ;
   const size_t so = (size_t)T.shot * plane;
   el_stage_adj_s(a, sb, so, T.x0, T.z0);
+  const ElCells C(T, NX);
+  const float axi = a.axi[C.ic], bxi = a.bxi[C.ic], axh = a.axh[C.ic], bxh = a.bxh[C.ic];
+  const bool wxi = __any(axi != 0.0f), wxh = __any(axh != 0.0f);
+  const bool gacc = !a.g_init;
+  float ovx[kElRZ], ovz[kElRZ], txx[kElRZ], tzz[kElRZ], txz[kElRZ], cxx_x[kElRZ], czz_x[kElRZ],
+      cxx_z[kElRZ], czz_z[kElRZ], mxz[kElRZ], q4[kElRZ], q5[kElRZ], q6[kElRZ], q7[kElRZ],
+      fexx[kElRZ], fezz[kElRZ], fexz[kElRZ], g0[kElRZ], g1[kElRZ], g2[kElRZ];
+  float azi[kElRZ], bzi[kElRZ], azh[kElRZ], bzh[kElRZ];
+#pragma unroll
+  for (int r = 0; r < kElRZ; ++r) {
+    const int jc = min(C.jb + r, NZ - 1);
+    const size_t k = (size_t)jc * NX + C.ic;
+    ovx[r] = a.vx[so + k];
+    ovz[r] = a.vz[so + k];
+    txx[r] = a.txx[so + k];
+    tzz[r] = a.tzz[so + k];
+    txz[r] = a.txz[so + k];
+    cxx_x[r] = a.cxx_x[k];
+    czz_x[r] = a.czz_x[k];
+    cxx_z[r] = a.cxx_z[k];
+    czz_z[r] = a.czz_z[k];
+    mxz[r] = a.mxz[k];
+    azi[r] = a.azi[jc];
+    bzi[r] = a.bzi[jc];
+    azh[r] = a.azh[jc];
+    bzh[r] = a.bzh[jc];
+    q4[r] = wxi ? a.ps_in[4][so + k] : 0.0f;
+    q5[r] = azi[r] != 0.0f ? a.ps_in[5][so + k] : 0.0f;
+    q6[r] = azh[r] != 0.0f ? a.ps_in[6][so + k] : 0.0f;
+    q7[r] = wxh ? a.ps_in[7][so + k] : 0.0f;
+    fexx[r] = a.trc[2][so + k];
+    fezz[r] = a.trc[3][so + k];
+    fexz[r] = a.trc[4][so + k];
+    g0[r] = gacc ? a.g[0][so + k] : 0.0f;
+    g1[r] = gacc ? a.g[1][so + k] : 0.0f;
+    g2[r] = gacc ? a.g[2][so + k] : 0.0f;
+  }
+  const float dml = a.fs ? a.dM_dl[C.ic] : 0.0f, dmm = a.fs ? a.dM_dm[C.ic] : 0.0f;
   __syncthreads();
   const Box gbe{sb[0], T.x0, T.z0}, gbf{sb[1], T.x0, T.z0}, gbg{sb[2], T.x0, T.z0},
       gbh{sb[3], T.x0, T.z0};
-  const int i = T.x0 + (threadIdx.x & 63);
-  const int jb = T.z0 + (threadIdx.x >> 6) * kElRZ;
+  const int i = C.i;
   const float dt = a.dt, ih = a.ih;
 #pragma unroll
   for (int r = 0; r < kElRZ; ++r) {
-    const int j = jb + r;
+    const int j = C.jb + r;
     if (i >= NX || j >= NZ) continue;
     const size_t k = (size_t)j * NX + i;
     // Vx += (Dx-)^T gbe + (Dz+ of vx)^T gbg ;  (Dx-)^T = -Dx+
@@ -340,38 +453,36 @@ __global__ __launch_bounds__(256) void el_adj_s_kernel(ElStep a) {
     // Vz += (Dz- of vz)^T gbf + (Dx+)^T gbh ;  (Dx+)^T = -Dx-
     const float dzf = dzT(a, 3, j, [&](int jj) { return gbf(i, jj); }, false);
     const float dxh = -fmaf(C2, gbh(i + 1, j) - gbh(i - 2, j), C1 * (gbh(i, j) - gbh(i - 1, j)));
-    a.vx[so + k] += (dxe + dzg) * ih;
-    a.vz[so + k] += (dzf + dxh) * ih;
+    a.vx[so + k] = ovx[r] + (dxe + dzg) * ih;
+    a.vz[so + k] = ovz[r] + (dzf + dxh) * ih;
 
     // own cell: memory-variable adjoints and the coefficient gradients
-    const float txx = a.txx[so + k], tzz = a.tzz[so + k], txz = a.txz[so + k];
-    const float ex = dt * fmaf(a.cxx_x[k], txx, a.czz_x[k] * tzz);
-    const float ez = dt * fmaf(a.cxx_z[k], txx, a.czz_z[k] * tzz);
-    const float exz = dt * a.mxz[k] * txz;
-    if (a.axi[i] != 0.0f) a.ps_out[4][so + k] = a.bxi[i] * (a.ps_in[4][so + k] + ex);
-    if (a.azi[j] != 0.0f) a.ps_out[5][so + k] = a.bzi[j] * (a.ps_in[5][so + k] + ez);
-    if (a.azh[j] != 0.0f) a.ps_out[6][so + k] = a.bzh[j] * (a.ps_in[6][so + k] + exz);
-    if (a.axh[i] != 0.0f) a.ps_out[7][so + k] = a.bxh[i] * (a.ps_in[7][so + k] + exz);
-    const float fexx = a.trc[2][so + k], fezz = a.trc[3][so + k], fexz = a.trc[4][so + k];
+    const float ex = dt * fmaf(cxx_x[r], txx[r], czz_x[r] * tzz[r]);
+    const float ez = dt * fmaf(cxx_z[r], txx[r], czz_z[r] * tzz[r]);
+    const float exz = dt * mxz[r] * txz[r];
+    if (axi != 0.0f) a.ps_out[4][so + k] = bxi * (q4[r] + ex);
+    if (azi[r] != 0.0f) a.ps_out[5][so + k] = bzi[r] * (q5[r] + ez);
+    if (azh[r] != 0.0f) a.ps_out[6][so + k] = bzh[r] * (q6[r] + exz);
+    if (axh != 0.0f) a.ps_out[7][so + k] = bxh * (q7[r] + exz);
     float glam, gmu;
     if (a.fs && j == 0) {
       // txx += dt M exx with M = 4 mu (lambda + mu) / (lambda + 2 mu)
-      const float gM = dt * txx * fexx;
-      glam = gM * a.dM_dl[i];
-      gmu = gM * a.dM_dm[i];
+      const float gM = dt * txx[r] * fexx[r];
+      glam = gM * dml;
+      gmu = gM * dmm;
     } else {
-      glam = dt * (txx + tzz) * (fexx + fezz);
-      gmu = 2.0f * dt * fmaf(txx, fexx, tzz * fezz);
+      glam = dt * (txx[r] + tzz[r]) * (fexx[r] + fezz[r]);
+      gmu = 2.0f * dt * fmaf(txx[r], fexx[r], tzz[r] * fezz[r]);
     }
-    const float gmxz = dt * txz * fexz;
+    const float gmxz = dt * txz[r] * fexz[r];
     if (a.g_init) {
       a.g[0][so + k] = glam;
       a.g[1][so + k] = gmu;
       a.g[2][so + k] = gmxz;
     } else {
-      a.g[0][so + k] += glam;
-      a.g[1][so + k] += gmu;
-      a.g[2][so + k] += gmxz;
+      a.g[0][so + k] = g0[r] + glam;
+      a.g[1][so + k] = g1[r] + gmu;
+      a.g[2][so + k] = g2[r] + gmxz;
     }
   }
 }
@@ -407,7 +518,8 @@ __device__ __forceinline__ void el_stage_adj_v(const ElStep& a, float (*sb)[kElB
                                                int x0, int z0) {
   const int NX = a.NX, NZ = a.NZ;
   const float dt = a.dt;
-  float vx[kElK], vz[kElK], bx[kElK], bz[kElK];
+  float vx[kElK], vz[kElK], bx[kElK], bz[kElK], axh[kElK], az[kElK], ax[kElK], azh[kElK],
+      q0[kElK], q1[kElK], q2[kElK], q3[kElK];
 #pragma unroll
   for (int k = 0; k < kElK; ++k) {
     const int e = threadIdx.x + k * kThreads;
@@ -415,32 +527,30 @@ __device__ __forceinline__ void el_stage_adj_v(const ElStep& a, float (*sb)[kElB
     const int gx = x0 - 2 + c, gz = z0 - 2 + r;
     const bool ok = e < kElBox && gx >= 0 && gx < NX && gz >= 0 && gz < NZ;
     const size_t q = ok ? (size_t)gz * NX + gx : 0;
-    vx[k] = ok ? a.vx[so + q] : 0.0f;
-    vz[k] = ok ? a.vz[so + q] : 0.0f;
-    bx[k] = ok ? a.bx[q] : 0.0f;
-    bz[k] = ok ? a.bz[q] : 0.0f;
+    const int cx = ok ? gx : 0, cz = ok ? gz : 0;
+    vx[k] = ldz(a.vx + so, q, ok, a.vx);
+    vz[k] = ldz(a.vz + so, q, ok, a.vz);
+    bx[k] = ldz(a.bx, q, ok, a.bx);
+    bz[k] = ldz(a.bz, q, ok, a.bz);
+    axh[k] = ldz(a.axh, cx, ok, a.axh);
+    az[k] = ldz(a.azi, cz, ok, a.azi);
+    ax[k] = ldz(a.axi, cx, ok, a.axi);
+    azh[k] = ldz(a.azh, cz, ok, a.azh);
+    q0[k] = __any(axh[k] != 0.0f) ? ldz(a.ps_in[0] + so, q, ok, a.ps_in[0]) : 0.0f;
+    q1[k] = __any(az[k] != 0.0f) ? ldz(a.ps_in[1] + so, q, ok, a.ps_in[1]) : 0.0f;
+    q2[k] = __any(ax[k] != 0.0f) ? ldz(a.ps_in[2] + so, q, ok, a.ps_in[2]) : 0.0f;
+    q3[k] = __any(azh[k] != 0.0f) ? ldz(a.ps_in[3] + so, q, ok, a.ps_in[3]) : 0.0f;
   }
 #pragma unroll
   for (int k = 0; k < kElK; ++k) {
     const int e = threadIdx.x + k * kThreads;
     if (e >= kElBox) break;
-    const int r = e / kElBW, c = e - (e / kElBW) * kElBW;
-    const int gx = x0 - 2 + c, gz = z0 - 2 + r;
-    float ga = 0.0f, gb = 0.0f, gc = 0.0f, gd = 0.0f;
-    if (gx >= 0 && gx < NX && gz >= 0 && gz < NZ) {
-      const size_t q = so + (size_t)gz * NX + gx;
-      const float kx = dt * bx[k] * vx[k];
-      const float kz = dt * bz[k] * vz[k];
-      const float axh = a.axh[gx], az = a.azi[gz], ax = a.axi[gx], azh = a.azh[gz];
-      ga = axh == 0.0f ? kx : fmaf(axh, a.ps_in[0][q] + kx, kx);
-      gb = az == 0.0f ? kx : fmaf(az, a.ps_in[1][q] + kx, kx);
-      gc = ax == 0.0f ? kz : fmaf(ax, a.ps_in[2][q] + kz, kz);
-      gd = azh == 0.0f ? kz : fmaf(azh, a.ps_in[3][q] + kz, kz);
-    }
-    sb[0][e] = ga;
-    sb[1][e] = gb;
-    sb[2][e] = gc;
-    sb[3][e] = gd;
+    const float kx = dt * bx[k] * vx[k];
+    const float kz = dt * bz[k] * vz[k];
+    sb[0][e] = axh[k] == 0.0f ? kx : fmaf(axh[k], q0[k] + kx, kx);
+    sb[1][e] = az[k] == 0.0f ? kx : fmaf(az[k], q1[k] + kx, kx);
+    sb[2][e] = ax[k] == 0.0f ? kz : fmaf(ax[k], q2[k] + kz, kz);
+    sb[3][e] = azh[k] == 0.0f ? kz : fmaf(azh[k], q3[k] + kz, kz);
   }
 }
 
@@ -451,15 +561,45 @@ __global__ __launch_bounds__(256) void el_adj_v_kernel(ElStep a) {
   const size_t plane = (size_t)NX * NZ;
   const size_t so = (size_t)T.shot * plane;
   el_stage_adj_v(a, sb, so, T.x0, T.z0);
+  const ElCells C(T, NX);
+  const float axh = a.axh[C.ic], bxh = a.bxh[C.ic], axi = a.axi[C.ic], bxi = a.bxi[C.ic];
+  const bool wxh = __any(axh != 0.0f), wxi = __any(axi != 0.0f);
+  const bool gacc = !a.g_init;
+  float otxx[kElRZ], otzz[kElRZ], otxz[kElRZ], vx[kElRZ], vz[kElRZ], bx[kElRZ], bz[kElRZ],
+      q0[kElRZ], q1[kElRZ], q2[kElRZ], q3[kElRZ], f0[kElRZ], f1[kElRZ], g3[kElRZ], g4[kElRZ];
+  float azi[kElRZ], bzi[kElRZ], azh[kElRZ], bzh[kElRZ];
+#pragma unroll
+  for (int r = 0; r < kElRZ; ++r) {
+    const int jc = min(C.jb + r, NZ - 1);
+    const size_t k = (size_t)jc * NX + C.ic;
+    otxx[r] = a.txx[so + k];
+    otzz[r] = a.tzz[so + k];
+    otxz[r] = a.txz[so + k];
+    vx[r] = a.vx[so + k];
+    vz[r] = a.vz[so + k];
+    bx[r] = a.bx[k];
+    bz[r] = a.bz[k];
+    azi[r] = a.azi[jc];
+    bzi[r] = a.bzi[jc];
+    azh[r] = a.azh[jc];
+    bzh[r] = a.bzh[jc];
+    q0[r] = wxh ? a.ps_in[0][so + k] : 0.0f;
+    q1[r] = azi[r] != 0.0f ? a.ps_in[1][so + k] : 0.0f;
+    q2[r] = wxi ? a.ps_in[2][so + k] : 0.0f;
+    q3[r] = azh[r] != 0.0f ? a.ps_in[3][so + k] : 0.0f;
+    f0[r] = a.trc[0][so + k];
+    f1[r] = a.trc[1][so + k];
+    g3[r] = gacc ? a.g[3][so + k] : 0.0f;
+    g4[r] = gacc ? a.g[4][so + k] : 0.0f;
+  }
   __syncthreads();
   const Box gba{sb[0], T.x0, T.z0}, gbb{sb[1], T.x0, T.z0}, gbc{sb[2], T.x0, T.z0},
       gbd{sb[3], T.x0, T.z0};
-  const int i = T.x0 + (threadIdx.x & 63);
-  const int jb = T.z0 + (threadIdx.x >> 6) * kElRZ;
+  const int i = C.i;
   const float dt = a.dt, ih = a.ih;
 #pragma unroll
   for (int r = 0; r < kElRZ; ++r) {
-    const int j = jb + r;
+    const int j = C.jb + r;
     if (i >= NX || j >= NZ) continue;
     const size_t k = (size_t)j * NX + i;
     // Txx += (Dx+)^T gba = -Dx- gba
@@ -469,24 +609,23 @@ __global__ __launch_bounds__(256) void el_adj_v_kernel(ElStep a) {
     const float dxc = -fmaf(C2, gbc(i + 2, j) - gbc(i - 1, j), C1 * (gbc(i + 1, j) - gbc(i, j)));
     // Tzz += (Dz+ of tzz)^T gbd
     const float dzd = dzT(a, 0, j, [&](int jj) { return gbd(i, jj); }, true);
-    a.txx[so + k] += dxa * ih;
-    a.txz[so + k] += (dzb + dxc) * ih;
-    a.tzz[so + k] += dzd * ih;
+    a.txx[so + k] = otxx[r] + dxa * ih;
+    a.txz[so + k] = otxz[r] + (dzb + dxc) * ih;
+    a.tzz[so + k] = otzz[r] + dzd * ih;
 
-    const float vx = a.vx[so + k], vz = a.vz[so + k];
-    const float kx = dt * a.bx[k] * vx, kz = dt * a.bz[k] * vz;
-    if (a.axh[i] != 0.0f) a.ps_out[0][so + k] = a.bxh[i] * (a.ps_in[0][so + k] + kx);
-    if (a.azi[j] != 0.0f) a.ps_out[1][so + k] = a.bzi[j] * (a.ps_in[1][so + k] + kx);
-    if (a.axi[i] != 0.0f) a.ps_out[2][so + k] = a.bxi[i] * (a.ps_in[2][so + k] + kz);
-    if (a.azh[j] != 0.0f) a.ps_out[3][so + k] = a.bzh[j] * (a.ps_in[3][so + k] + kz);
-    const float gbx = dt * vx * a.trc[0][so + k];
-    const float gbz = dt * vz * a.trc[1][so + k];
+    const float kx = dt * bx[r] * vx[r], kz = dt * bz[r] * vz[r];
+    if (axh != 0.0f) a.ps_out[0][so + k] = bxh * (q0[r] + kx);
+    if (azi[r] != 0.0f) a.ps_out[1][so + k] = bzi[r] * (q1[r] + kx);
+    if (axi != 0.0f) a.ps_out[2][so + k] = bxi * (q2[r] + kz);
+    if (azh[r] != 0.0f) a.ps_out[3][so + k] = bzh[r] * (q3[r] + kz);
+    const float gbx = dt * vx[r] * f0[r];
+    const float gbz = dt * vz[r] * f1[r];
     if (a.g_init) {
       a.g[3][so + k] = gbx;
       a.g[4][so + k] = gbz;
     } else {
-      a.g[3][so + k] += gbx;
-      a.g[4][so + k] += gbz;
+      a.g[3][so + k] = g3[r] + gbx;
+      a.g[4][so + k] = g4[r] + gbz;
     }
   }
 }
