@@ -77,8 +77,8 @@ typedef struct {
   int tblock;      /* acoustic: 2 = advance the deep interior tiles (no C-PML cell
                       within 4 cells, no source or receiver within 4, an 8-cell halo
                       inside the grid) two time steps per pass, marching down runs of
-                      them; 1 = one step per pass (default 2). Batches take single
-                      steps whatever this field says */
+                      them; 1 = one step per pass (default 2). In a batch each
+                      plan follows its own setting */
 } sweep_tuning;
 
 typedef struct sweep_plan sweep_plan;

@@ -1356,6 +1356,19 @@ __global__ __launch_bounds__(kThreads) void ac_pml_batch_kernel(AcBatch b) {
   run_frame<RZ, kAdj, kZ>(b.step[p], f, lds);
 }
 
+template <bool kAdj>
+__global__ __launch_bounds__(kThreads) void ac_march_batch_kernel(AcBatch b) {
+  int f = xcd_spread(blockIdx.x, gridDim.x);
+  const int p = batch_plan(b, f);
+  const AcStep& a = b.step[p];
+  const int2 run = a.drun[f % a.n_run];
+  const int shot = f / a.n_run;
+  if (kAdj)
+    ac_march_adj(a, run, shot);
+  else
+    ac_march_fwd(a, run, shot);
+}
+
 // ---------------------------------------------------------------------------
 // Adjoint start: lambda^{nt}[rec] += r_{nt-1} (receiver order, so coincident
 // receivers add up deterministically), after the state was zero-filled.
@@ -1515,6 +1528,29 @@ int ac_launch_deep(const AcStep& a, bool adj, hipStream_t s, hipEvent_t* ev) {
   else
     hipLaunchKernelGGL((ac_march_kernel<false>), g, dim3(kThreads), 0, s, a);
   if (ev && ev[1]) SWEEP_HIP(hipEventRecord(ev[1], s));
+  SWEEP_HIP(hipGetLastError());
+  return SWEEP_OK;
+}
+
+// Two-step passes of several plans in one launch (plans with no deep run are
+// left out).
+int ac_launch_deep_batch(const AcStep* steps, int n, bool adj, hipStream_t s) {
+  AcBatch b;
+  b.nplans = 0;
+  b.base[0] = 0;
+  for (int q = 0; q < n; ++q) {
+    const AcStep& a = steps[q];
+    if (a.n_run <= 0) continue;
+    const int k = b.nplans++;
+    b.step[k] = a;
+    b.base[k + 1] = b.base[k] + a.n_run * a.nshots;
+  }
+  if (b.nplans == 0) return SWEEP_OK;
+  const dim3 g(b.base[b.nplans]);
+  if (adj)
+    hipLaunchKernelGGL((ac_march_batch_kernel<true>), g, dim3(kThreads), 0, s, b);
+  else
+    hipLaunchKernelGGL((ac_march_batch_kernel<false>), g, dim3(kThreads), 0, s, b);
   SWEEP_HIP(hipGetLastError());
   return SWEEP_OK;
 }

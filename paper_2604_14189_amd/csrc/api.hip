@@ -394,30 +394,43 @@ int ac_fwd_one(sweep_plan* p, void* work, const AcLayout& L, int n, int par, flo
   return rc;
 }
 
+// The launches of a step pair: the two-step pass over the deep tiles (d), then
+// steps a0 and a1 of the other tiles (interior ring and frame), in that order.
+struct StepPair {
+  AcStep d, a0, a1;
+};
+
+// Forward-type steps n and n+1 from the plan's rotation; advances it.
+StepPair ac_fwd_pair(sweep_plan* p, void* work, const AcLayout& L, int n, int par,
+                     float* gathers, float* B_out, float* B_out2) {
+  Rot& r = p->frot;
+  const int o1 = r.free_buf(0), o2 = r.free_buf(1);
+  StepPair P;
+  P.d = ac_fwd_single(p, work, L, n, par, r.cur, r.prev, o1, gathers, B_out);
+  P.d.next2 = at<float>(work, L.pf[o2]);
+  P.d.B_out2 = B_out2;
+  P.d.n_run = (int)p->drun.size();
+  P.a0 = ac_fwd_single(p, work, L, n, par, r.cur, r.prev, o1, gathers, B_out);
+  P.a1 = ac_fwd_single(p, work, L, n + 1, 1 - par, o1, r.cur, o2, gathers, B_out2);
+  P.a0.ilist = P.a1.ilist = at<int>(work, L.tl) + L.tl_cap;
+  P.a0.n_int = P.a1.n_int = (int)p->ilist_ring.size();
+  r.prev = o1;
+  r.cur = o2;
+  return P;
+}
+
 // Forward-type steps n and n+1: the deep tiles in one two-step pass, the other
 // tiles (interior ring and frame) as two single steps; advances the rotation.
 int ac_fwd_two(sweep_plan* p, void* work, const AcLayout& L, int n, int par, float* gathers,
                float* B_out, float* B_out2, hipStream_t s, bool rec) {
-  Rot& r = p->frot;
-  const int o1 = r.free_buf(0), o2 = r.free_buf(1);
-  AcStep d = ac_fwd_single(p, work, L, n, par, r.cur, r.prev, o1, gathers, B_out);
-  d.next2 = at<float>(work, L.pf[o2]);
-  d.B_out2 = B_out2;
-  d.n_run = (int)p->drun.size();
-  AcStep a0 = ac_fwd_single(p, work, L, n, par, r.cur, r.prev, o1, gathers, B_out);
-  AcStep a1 = ac_fwd_single(p, work, L, n + 1, 1 - par, o1, r.cur, o2, gathers, B_out2);
-  a0.ilist = a1.ilist = at<int>(work, L.tl) + L.tl_cap;
-  a0.n_int = a1.n_int = (int)p->ilist_ring.size();
+  const StepPair P = ac_fwd_pair(p, work, L, n, par, gathers, B_out, B_out2);
   const int rz = p->tune.rz, prz = p->tune.pml_rz;
   int rc;
-  if ((rc = ac_launch_deep(d, false, s, p->timer.take(rec ? kRecDeep : kFwdDeep, -1, -1))))
+  if ((rc = ac_launch_deep(P.d, false, s, p->timer.take(rec ? kRecDeep : kFwdDeep, -1, -1))))
     return rc;
   const int ci = rec ? kRecInt : kFwdInt, cz = rec ? kRecZ : kFwdZ, cx = rec ? kRecX : kFwdX;
-  if ((rc = ac_launch_fwd(a0, rz, prz, s, step_events(p, a0, ci, cz, cx)))) return rc;
-  if ((rc = ac_launch_fwd(a1, rz, prz, s, step_events(p, a1, ci, cz, cx)))) return rc;
-  r.prev = o1;
-  r.cur = o2;
-  return SWEEP_OK;
+  if ((rc = ac_launch_fwd(P.a0, rz, prz, s, step_events(p, P.a0, ci, cz, cx)))) return rc;
+  return ac_launch_fwd(P.a1, rz, prz, s, step_events(p, P.a1, ci, cz, cx));
 }
 
 bool ac_two_steps(const sweep_plan* p) { return p->tune.tblock == 2 && !p->dlist.empty(); }
@@ -513,28 +526,37 @@ int ac_adj_one(sweep_plan* p, void* work, const AcLayout& L, const float* resid,
   return rc;
 }
 
-// Reverse steps n and n-1 (both inside [n0, n1)): deep tiles in one pass.
-int ac_adj_two(sweep_plan* p, void* work, const AcLayout& L, const float* resid, int n, int n0,
-               int n1, hipStream_t s) {
+// Reverse steps n and n-1 (both inside [n0, n1)) from the plan's rotation;
+// advances it.
+StepPair ac_adj_pair(sweep_plan* p, void* work, const AcLayout& L, const float* resid, int n,
+                     int n0, int n1) {
   Rot& r = p->arot;
   const size_t ns = p->pb.nshots;
   const int o1 = r.free_buf(0), o2 = r.free_buf(1);
-  AcStep d = ac_adj_single(p, work, L, resid, n, n0, n1, r.cur, r.prev, o1);
-  d.next2 = at<float>(work, L.lf[o2]);
-  d.B_in2 = ac_bseg(work, L, ns, n - 1 - n0);
-  d.n_run = (int)p->drun.size();
-  AcStep a0 = ac_adj_single(p, work, L, resid, n, n0, n1, r.cur, r.prev, o1);
-  AcStep a1 = ac_adj_single(p, work, L, resid, n - 1, n0, n1, o1, r.cur, o2);
-  a0.ilist = a1.ilist = at<int>(work, L.tl) + L.tl_cap;
-  a0.n_int = a1.n_int = (int)p->ilist_ring.size();
-  const int rz = p->tune.rz, prz = p->tune.pml_rz;
-  int rc;
-  if ((rc = ac_launch_deep(d, true, s, p->timer.take(kAdjDeep, -1, -1)))) return rc;
-  if ((rc = ac_launch_adj(a0, rz, prz, s, step_events(p, a0, kAdjInt, kAdjZ, kAdjX)))) return rc;
-  if ((rc = ac_launch_adj(a1, rz, prz, s, step_events(p, a1, kAdjInt, kAdjZ, kAdjX)))) return rc;
+  StepPair P;
+  P.d = ac_adj_single(p, work, L, resid, n, n0, n1, r.cur, r.prev, o1);
+  P.d.next2 = at<float>(work, L.lf[o2]);
+  P.d.B_in2 = ac_bseg(work, L, ns, n - 1 - n0);
+  P.d.n_run = (int)p->drun.size();
+  P.a0 = ac_adj_single(p, work, L, resid, n, n0, n1, r.cur, r.prev, o1);
+  P.a1 = ac_adj_single(p, work, L, resid, n - 1, n0, n1, o1, r.cur, o2);
+  P.a0.ilist = P.a1.ilist = at<int>(work, L.tl) + L.tl_cap;
+  P.a0.n_int = P.a1.n_int = (int)p->ilist_ring.size();
   r.prev = o1;
   r.cur = o2;
-  return SWEEP_OK;
+  return P;
+}
+
+// Reverse steps n and n-1 (both inside [n0, n1)): deep tiles in one pass.
+int ac_adj_two(sweep_plan* p, void* work, const AcLayout& L, const float* resid, int n, int n0,
+               int n1, hipStream_t s) {
+  const StepPair P = ac_adj_pair(p, work, L, resid, n, n0, n1);
+  const int rz = p->tune.rz, prz = p->tune.pml_rz;
+  int rc;
+  if ((rc = ac_launch_deep(P.d, true, s, p->timer.take(kAdjDeep, -1, -1)))) return rc;
+  if ((rc = ac_launch_adj(P.a0, rz, prz, s, step_events(p, P.a0, kAdjInt, kAdjZ, kAdjX))))
+    return rc;
+  return ac_launch_adj(P.a1, rz, prz, s, step_events(p, P.a1, kAdjInt, kAdjZ, kAdjX));
 }
 
 int ac_bwd_fold(sweep_plan* p, void* work, const AcLayout& L, hipStream_t s) {
@@ -676,6 +698,46 @@ int batch_layouts(const sweep_batch* b, int for_backward, std::vector<AcLayout>&
   return SWEEP_OK;
 }
 
+// One batched time-step pair: the two-step passes of the plans that pair
+// (deep), then every plan's step n (s0), then step n+1 (s1). Plans that do not
+// pair take two single steps; their step n+1 is built only after step n is
+// enqueued (`later`), so that a checkpoint can come between the two.
+struct BatchPair {
+  std::vector<AcStep> deep, s0, s1;
+  std::vector<int> later;
+  void clear() {
+    deep.clear();
+    s0.clear();
+    s1.clear();
+    later.clear();
+  }
+  void add(const StepPair& P) {
+    deep.push_back(P.d);
+    s0.push_back(P.a0);
+    s1.push_back(P.a1);
+  }
+};
+
+// Single forward-type step from the plan's rotation (built, not launched).
+AcStep fwd_single_rot(sweep_plan* p, void* work, const AcLayout& L, int n, int par,
+                      float* gathers, float* B_out) {
+  Rot& r = p->frot;
+  const int o = r.free_buf(0);
+  const AcStep a = ac_fwd_single(p, work, L, n, par, r.cur, r.prev, o, gathers, B_out);
+  r.prev = r.cur;
+  r.cur = o;
+  return a;
+}
+AcStep adj_single_rot(sweep_plan* p, void* work, const AcLayout& L, const float* resid, int n,
+                      int n0, int n1) {
+  Rot& r = p->arot;
+  const int o = r.free_buf(0);
+  const AcStep a = ac_adj_single(p, work, L, resid, n, n0, n1, r.cur, r.prev, o);
+  r.prev = r.cur;
+  r.cur = o;
+  return a;
+}
+
 int batch_forward_enqueue(sweep_batch* b, const float* const* models, const float* const* wavs,
                           float* const* gathers, void* work, const std::vector<AcLayout>& L,
                           const std::vector<size_t>& off, int save, hipStream_t s) {
@@ -686,28 +748,36 @@ int batch_forward_enqueue(sweep_batch* b, const float* const* models, const floa
       return rc;
     maxnt = std::max(maxnt, b->plans[q]->pb.nt);
   }
-  std::vector<AcStep> steps(np);
-  std::vector<int> who(np), nxt(np);
-  for (int n = 0; n < maxnt; ++n) {
-    int cnt = 0;
+  BatchPair B;
+  for (int n = 0; n < maxnt; n += 2) {
+    B.clear();
     for (int q = 0; q < np; ++q) {
       sweep_plan* p = b->plans[q];
-      if (n >= p->pb.nt) continue;
+      const int nt = p->pb.nt, k = p->ckpt;
+      if (n >= nt) continue;
       void* wq = at<char>(work, off[q]);
-      if (save && n % p->ckpt == 0 && (rc = ac_checkpoint(p, wq, L[q], n, s))) return rc;
-      const int o = p->frot.free_buf(0);
-      steps[cnt] = ac_fwd_single(p, wq, L[q], n, n % 2, p->frot.cur, p->frot.prev, o, gathers[q],
-                                 nullptr);
-      who[cnt] = q;
-      nxt[cnt] = o;
-      ++cnt;
+      if (save && n % k == 0 && (rc = ac_checkpoint(p, wq, L[q], n, s))) return rc;
+      const bool has1 = n + 1 < nt;
+      // a pair never spans a checkpoint (the state entering step n+1 is not formed)
+      if (ac_two_steps(p) && has1 && (!save || (n + 1) % k != 0)) {
+        B.add(ac_fwd_pair(p, wq, L[q], n, n % 2, gathers[q], nullptr, nullptr));
+      } else {
+        B.s0.push_back(fwd_single_rot(p, wq, L[q], n, n % 2, gathers[q], nullptr));
+        if (has1) B.later.push_back(q);
+      }
     }
-    if ((rc = ac_launch_fwd_batch(steps.data(), cnt, b->rz, b->prz, s))) return rc;
-    for (int c = 0; c < cnt; ++c) {
-      Rot& r = b->plans[who[c]]->frot;
-      r.prev = r.cur;
-      r.cur = nxt[c];
+    if ((rc = ac_launch_deep_batch(B.deep.data(), (int)B.deep.size(), false, s))) return rc;
+    if ((rc = ac_launch_fwd_batch(B.s0.data(), (int)B.s0.size(), b->rz, b->prz, s))) return rc;
+    for (int q : B.later) {
+      sweep_plan* p = b->plans[q];
+      void* wq = at<char>(work, off[q]);
+      if (save && (n + 1) % p->ckpt == 0 && (rc = ac_checkpoint(p, wq, L[q], n + 1, s)))
+        return rc;
+      B.s1.push_back(fwd_single_rot(p, wq, L[q], n + 1, (n + 1) % 2, gathers[q], nullptr));
     }
+    if (!B.s1.empty() &&
+        (rc = ac_launch_fwd_batch(B.s1.data(), (int)B.s1.size(), b->rz, b->prz, s)))
+      return rc;
   }
   return SWEEP_OK;
 }
@@ -722,8 +792,8 @@ int batch_backward_enqueue(sweep_batch* b, const float* const* resids, float* co
       return rc;
     maxseg = std::max(maxseg, L[q].nseg);
   }
-  std::vector<AcStep> steps(np);
-  std::vector<int> n0(np), n1(np), who(np), nxt(np);
+  std::vector<int> n0(np), n1(np);
+  BatchPair B;
   for (int r = 0; r < maxseg; ++r) {
     int lenmax = 0;
     for (int q = 0; q < np; ++q) {
@@ -736,42 +806,62 @@ int batch_backward_enqueue(sweep_batch* b, const float* const* resids, float* co
       lenmax = std::max(lenmax, n1[q] - n0[q]);
       if ((rc = ac_bwd_restore(p, at<char>(work, off[q]), L[q], sg, s))) return rc;
     }
-    for (int m = 0; m < lenmax; ++m) {
-      int cnt = 0;
+    // recompute the segments, storing B^n
+    for (int m = 0; m < lenmax; m += 2) {
+      B.clear();
       for (int q = 0; q < np; ++q) {
-        if (m >= n1[q] - n0[q]) continue;
+        const int len = n1[q] - n0[q];
+        if (m >= len) continue;
         sweep_plan* p = b->plans[q];
         void* wq = at<char>(work, off[q]);
-        const int o = p->frot.free_buf(0);
-        steps[cnt] = ac_fwd_single(p, wq, L[q], n0[q] + m, m % 2, p->frot.cur, p->frot.prev, o,
-                                   nullptr, ac_bseg(wq, L[q], p->pb.nshots, m));
-        who[cnt] = q;
-        nxt[cnt++] = o;
+        const size_t ns = p->pb.nshots;
+        if (ac_two_steps(p) && m + 1 < len) {
+          B.add(ac_fwd_pair(p, wq, L[q], n0[q] + m, m % 2, nullptr, ac_bseg(wq, L[q], ns, m),
+                            ac_bseg(wq, L[q], ns, m + 1)));
+        } else {
+          B.s0.push_back(fwd_single_rot(p, wq, L[q], n0[q] + m, m % 2, nullptr,
+                                        ac_bseg(wq, L[q], ns, m)));
+          if (m + 1 < len) B.later.push_back(q);
+        }
       }
-      if ((rc = ac_launch_fwd_batch(steps.data(), cnt, b->rz, b->prz, s))) return rc;
-      for (int c = 0; c < cnt; ++c) {
-        Rot& r = b->plans[who[c]]->frot;
-        r.prev = r.cur;
-        r.cur = nxt[c];
-      }
-    }
-    for (int m = 0; m < lenmax; ++m) {
-      int cnt = 0;
-      for (int q = 0; q < np; ++q) {
-        if (m >= n1[q] - n0[q]) continue;
+      if ((rc = ac_launch_deep_batch(B.deep.data(), (int)B.deep.size(), false, s))) return rc;
+      if ((rc = ac_launch_fwd_batch(B.s0.data(), (int)B.s0.size(), b->rz, b->prz, s))) return rc;
+      for (int q : B.later) {
         sweep_plan* p = b->plans[q];
-        const int o = p->arot.free_buf(0);
-        steps[cnt] = ac_adj_single(p, at<char>(work, off[q]), L[q], resids[q], n1[q] - 1 - m,
-                                   n0[q], n1[q], p->arot.cur, p->arot.prev, o);
-        who[cnt] = q;
-        nxt[cnt++] = o;
+        void* wq = at<char>(work, off[q]);
+        B.s1.push_back(fwd_single_rot(p, wq, L[q], n0[q] + m + 1, (m + 1) % 2, nullptr,
+                                      ac_bseg(wq, L[q], p->pb.nshots, m + 1)));
       }
-      if ((rc = ac_launch_adj_batch(steps.data(), cnt, b->rz, b->prz, s))) return rc;
-      for (int c = 0; c < cnt; ++c) {
-        Rot& r = b->plans[who[c]]->arot;
-        r.prev = r.cur;
-        r.cur = nxt[c];
+      if (!B.s1.empty() &&
+          (rc = ac_launch_fwd_batch(B.s1.data(), (int)B.s1.size(), b->rz, b->prz, s)))
+        return rc;
+    }
+    // reverse steps n1-1 .. n0
+    for (int m = 0; m < lenmax; m += 2) {
+      B.clear();
+      for (int q = 0; q < np; ++q) {
+        const int len = n1[q] - n0[q];
+        if (m >= len) continue;
+        sweep_plan* p = b->plans[q];
+        void* wq = at<char>(work, off[q]);
+        const int n = n1[q] - 1 - m;
+        if (ac_two_steps(p) && m + 1 < len) {
+          B.add(ac_adj_pair(p, wq, L[q], resids[q], n, n0[q], n1[q]));
+        } else {
+          B.s0.push_back(adj_single_rot(p, wq, L[q], resids[q], n, n0[q], n1[q]));
+          if (m + 1 < len) B.later.push_back(q);
+        }
       }
+      if ((rc = ac_launch_deep_batch(B.deep.data(), (int)B.deep.size(), true, s))) return rc;
+      if ((rc = ac_launch_adj_batch(B.s0.data(), (int)B.s0.size(), b->rz, b->prz, s))) return rc;
+      for (int q : B.later) {
+        sweep_plan* p = b->plans[q];
+        B.s1.push_back(adj_single_rot(p, at<char>(work, off[q]), L[q], resids[q],
+                                      n1[q] - 2 - m, n0[q], n1[q]));
+      }
+      if (!B.s1.empty() &&
+          (rc = ac_launch_adj_batch(B.s1.data(), (int)B.s1.size(), b->rz, b->prz, s)))
+        return rc;
     }
     for (int q = 0; q < np; ++q)
       if (n1[q] > n0[q] && (rc = ac_bwd_fold(b->plans[q], at<char>(work, off[q]), L[q], s)))

@@ -121,6 +121,8 @@ int ac_launch_adj(const AcStep& a, int rz, int prz, hipStream_t s, hipEvent_t* e
 int ac_launch_fwd_batch(const AcStep* steps, int n, int rz, int prz, hipStream_t s);
 // Two steps over the deep runs (a.drun): forward n and n+1, or adjoint n and n-1.
 int ac_launch_deep(const AcStep& a, bool adj, hipStream_t s, hipEvent_t* ev);
+// The same for several plans in one launch (steps[q].n_run == 0: no pass).
+int ac_launch_deep_batch(const AcStep* steps, int n, bool adj, hipStream_t s);
 int ac_launch_adj_batch(const AcStep* steps, int n, int rz, int prz, hipStream_t s);
 int ac_launch_adj_init(float* lam_cur, float* lam_prev, size_t plane_elems, float* aux,
                        size_t aux_elems, const int* rec_cell, const float* resid, int nshots,

@@ -71,6 +71,32 @@ def test_batch_equals_single_plans(sw, graph):
         _ = (torch.randn(1000, device="cuda") * 2).sum().item()
 
 
+def test_batch_two_step_passes(sw):
+    """Plans with deep tiles take batched two-step passes (ragged step counts and
+    odd checkpoint intervals force single steps in between); the results are
+    bitwise those of each plan alone with single steps."""
+    cases = [random_case(51, nx=300, nz=200, nt=101, nshots=2, nrec=6, ckpt=17),
+             random_case(52, nx=260, nz=150, nt=76, nshots=3, nrec=5, ckpt=25),
+             random_case(53, nx=120, nz=90, nt=90, nshots=2, nrec=4, ckpt=50)]
+    resids = _resids(cases)
+    ref = []
+    for c, r in zip(cases, resids):
+        p = c.plan()
+        p.set_tuning(rz=4, pml_rz=4, tblock=1)
+        ref.append((p.forward(_dev(c.v), _dev(c.wav), save=True).clone(), p.backward(r).clone()))
+    plans = [c.plan() for c in cases]
+    for p in plans:
+        p.set_tuning(rz=4, pml_rz=4, tblock=2)
+    assert sum(p.tiles()["deep"] > 0 for p in plans) >= 2
+    batch = sw.Batch(plans)
+    ds = batch.forward([_dev(c.v) for c in cases], [_dev(c.wav) for c in cases], save=True)
+    gs = batch.backward(resids)
+    torch.cuda.synchronize()
+    for q in range(len(cases)):
+        assert torch.equal(ds[q], ref[q][0]), q
+        assert torch.equal(gs[q], ref[q][1]), q
+
+
 def test_plan_graph_replays_match_eager(sw):
     c = random_case(31, nt=140, ckpt=25)
     r = _dev(synth.bandlimited_noise((c.nshots, c.nt, c.nrec), 15.0, c.dt, 3))
