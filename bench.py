@@ -144,12 +144,15 @@ def _sync_time(torch, fn):
     return out, time.perf_counter() - t0
 
 
-def batched_uneven(sw, torch, tuning):
+def batched_uneven(sw, torch, tuning=None):
     """The eight uneven layered models (200x200 ... 1200x400, 16-48 shots, 2000-4000
     steps, 256 shots): one FWI gradient of all of them through one Batch (one
     launch per kernel kind and step for every model) against the per-shot path
     (single-shot plans, kernels launched once per shot per step), timed on the
-    middle shot of each model and scaled by its shot count."""
+    middle shot of each model and scaled by its shot count. The tiling and
+    time-blocking depth come from the batch autotuner (before timing) unless
+    `tuning` (rz, pml_rz, use_graph, tblock) is given; the per-shot plans use the
+    same."""
     import synth
     from tests.helpers import case_from_workload
     ws = synth.batched_workloads()
@@ -157,7 +160,8 @@ def batched_uneven(sw, torch, tuning):
     for w in ws:
         case = case_from_workload(w)
         p = case.plan()
-        p.set_tuning(*tuning)
+        if tuning is not None:
+            p.set_tuning(*tuning)
         wav = torch.tensor(case.wav, dtype=torch.float32, device="cuda")
         d = p.forward(torch.tensor(case.v, dtype=torch.float32, device="cuda"), wav).clone()
         p.release_workspace()
@@ -166,7 +170,11 @@ def batched_uneven(sw, torch, tuning):
         wavs.append(wav)
         dobs.append(d)
     batch = sw.Batch(plans)
+    if tuning is None:
+        ch = batch.autotune(v0s, wavs, steps=20)
+        tuning = (ch["rz"], ch["pml_rz"], 0, ch["tblock"])
     # the workspace is allocated before timing (inputs and state resident in HBM)
+    batch._work = None
     batch._work = torch.empty(batch.workspace_bytes(True), dtype=torch.uint8, device="cuda")
 
     def grad():
@@ -194,6 +202,7 @@ def batched_uneven(sw, torch, tuning):
             "batched_gradient_s": round(t_batch, 3),
             "batched_Gcell_per_s": round(cells / t_batch / 1e9, 2),
             "per_shot_gradient_s_est": round(t_shot, 3), "speedup": round(t_shot / t_batch, 2),
+            "tuning": {"rz": tuning[0], "pml_rz": tuning[1], "tblock": tuning[3]},
             "per_shot_sample": "middle shot of each model, scaled by its shot count"}
 
 
@@ -415,8 +424,7 @@ def main():
         plan.release_workspace()
         del plan
         torch.cuda.empty_cache()
-        # the fastest tiling of this batch (measured): rz = pml_rz = 4, two-step passes
-        out["batched_uneven"] = batched_uneven(sw, torch, (4, 4, 0, 2))
+        out["batched_uneven"] = batched_uneven(sw, torch)
         torch.cuda.empty_cache()
         out["elastic"] = elastic_gradient(sw, torch)
         out["mlp"] = mlp_throughput(torch)

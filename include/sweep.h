@@ -195,6 +195,24 @@ int sweep_batch_forward(sweep_batch* batch, const float* const* d_models,
 int sweep_batch_backward(sweep_batch* batch, const float* const* d_resids, float* const* d_grads,
                          void* d_work, size_t work_bytes, void* stream);
 
+/* Batch autotuner: for every tile choice (rz, pml_rz as for sweep_plan_autotune)
+ * and time-blocking depth (tblock 1 or 2; 2 only where some plan has deep
+ * tiles) it times `steps` batched forward steps (nothing recorded, no
+ * checkpoints) and, with for_backward = 1, the recomputation and reversal of
+ * the first `steps` steps too (at most one checkpoint segment, no residual),
+ * which is the step mix of a gradient; it sets the fastest on every plan of
+ * the batch. `cache_path` (may be NULL) is a text file of previous results,
+ * one line "arch batch[-gradient] NXxNZxNSHOTS ... rz pml_rz tblock
+ * us_per_step" keyed by the arch, the mode and all plans' shapes, read first
+ * and appended to. Synchronises `stream`; d_work needs the batch's workspace
+ * for_backward. Results never depend on the choice (bitwise); the fields of the
+ * workspace hold no result afterwards. chosen (3 ints: rz, pml_rz, tblock; may
+ * be NULL) receives it. */
+int sweep_batch_autotune(sweep_batch* batch, const float* const* d_models,
+                         const float* const* d_wavelets, void* d_work, size_t work_bytes,
+                         int steps, int for_backward, const char* cache_path, void* stream,
+                         int* chosen);
+
 /* L2 misfit: d_resid[i] = d_pred[i] - d_obs[i] and *d_J = 0.5 * sum resid^2
  * (float64, device). Deterministic two-stage reduction; d_scratch must hold
  * sweep_l2_misfit_scratch_bytes(n) bytes. d_resid may alias d_pred. */

@@ -80,6 +80,11 @@ _SIGS = {
     "sweep_batch_backward": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p),
                                             ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p,
                                             ctypes.c_size_t, ctypes.c_void_p]),
+    "sweep_batch_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p),
+                                            ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p,
+                                            ctypes.c_size_t, ctypes.c_int, ctypes.c_int,
+                                            ctypes.c_char_p, ctypes.c_void_p,
+                                            ctypes.POINTER(ctypes.c_int)]),
     "sweep_l2_misfit_scratch_bytes": (ctypes.c_size_t, [ctypes.c_size_t]),
     "sweep_l2_misfit": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                        ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,

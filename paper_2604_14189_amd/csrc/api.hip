@@ -3,6 +3,7 @@
 // recomputation and the reverse sweep on the caller's stream.
 #include <algorithm>
 #include <cstdio>
+#include <climits>
 #include <fstream>
 #include <sstream>
 #include <cmath>
@@ -738,9 +739,11 @@ AcStep adj_single_rot(sweep_plan* p, void* work, const AcLayout& L, const float*
   return a;
 }
 
+// nmax: stop after that many steps (the autotuner's short runs).
 int batch_forward_enqueue(sweep_batch* b, const float* const* models, const float* const* wavs,
                           float* const* gathers, void* work, const std::vector<AcLayout>& L,
-                          const std::vector<size_t>& off, int save, hipStream_t s) {
+                          const std::vector<size_t>& off, int save, hipStream_t s,
+                          int nmax = INT_MAX) {
   const int np = (int)b->plans.size();
   int rc, maxnt = 0;
   for (int q = 0; q < np; ++q) {
@@ -748,6 +751,7 @@ int batch_forward_enqueue(sweep_batch* b, const float* const* models, const floa
       return rc;
     maxnt = std::max(maxnt, b->plans[q]->pb.nt);
   }
+  maxnt = std::min(maxnt, nmax);
   BatchPair B;
   for (int n = 0; n < maxnt; n += 2) {
     B.clear();
@@ -757,7 +761,7 @@ int batch_forward_enqueue(sweep_batch* b, const float* const* models, const floa
       if (n >= nt) continue;
       void* wq = at<char>(work, off[q]);
       if (save && n % k == 0 && (rc = ac_checkpoint(p, wq, L[q], n, s))) return rc;
-      const bool has1 = n + 1 < nt;
+      const bool has1 = n + 1 < std::min(nt, maxnt);
       // a pair never spans a checkpoint (the state entering step n+1 is not formed)
       if (ac_two_steps(p) && has1 && (!save || (n + 1) % k != 0)) {
         B.add(ac_fwd_pair(p, wq, L[q], n, n % 2, gathers[q], nullptr, nullptr));
@@ -777,6 +781,75 @@ int batch_forward_enqueue(sweep_batch* b, const float* const* models, const floa
     }
     if (!B.s1.empty() &&
         (rc = ac_launch_fwd_batch(B.s1.data(), (int)B.s1.size(), b->rz, b->prz, s)))
+      return rc;
+  }
+  return SWEEP_OK;
+}
+
+// Recompute steps [n0, n1) of every plan (storing B^n) and reverse them, as
+// batched step pairs. resids[q] may be null (nothing injected: timing runs).
+int batch_segment_enqueue(sweep_batch* b, const float* const* resids, void* work,
+                          const std::vector<AcLayout>& L, const std::vector<size_t>& off,
+                          const std::vector<int>& n0, const std::vector<int>& n1, int lenmax,
+                          hipStream_t s) {
+  const int np = (int)b->plans.size();
+  int rc;
+  BatchPair B;
+  // recompute the segments, storing B^n
+  for (int m = 0; m < lenmax; m += 2) {
+    B.clear();
+    for (int q = 0; q < np; ++q) {
+      const int len = n1[q] - n0[q];
+      if (m >= len) continue;
+      sweep_plan* p = b->plans[q];
+      void* wq = at<char>(work, off[q]);
+      const size_t ns = p->pb.nshots;
+      if (ac_two_steps(p) && m + 1 < len) {
+        B.add(ac_fwd_pair(p, wq, L[q], n0[q] + m, m % 2, nullptr, ac_bseg(wq, L[q], ns, m),
+                          ac_bseg(wq, L[q], ns, m + 1)));
+      } else {
+        B.s0.push_back(fwd_single_rot(p, wq, L[q], n0[q] + m, m % 2, nullptr,
+                                      ac_bseg(wq, L[q], ns, m)));
+        if (m + 1 < len) B.later.push_back(q);
+      }
+    }
+    if ((rc = ac_launch_deep_batch(B.deep.data(), (int)B.deep.size(), false, s))) return rc;
+    if ((rc = ac_launch_fwd_batch(B.s0.data(), (int)B.s0.size(), b->rz, b->prz, s))) return rc;
+    for (int q : B.later) {
+      sweep_plan* p = b->plans[q];
+      void* wq = at<char>(work, off[q]);
+      B.s1.push_back(fwd_single_rot(p, wq, L[q], n0[q] + m + 1, (m + 1) % 2, nullptr,
+                                    ac_bseg(wq, L[q], p->pb.nshots, m + 1)));
+    }
+    if (!B.s1.empty() &&
+        (rc = ac_launch_fwd_batch(B.s1.data(), (int)B.s1.size(), b->rz, b->prz, s)))
+      return rc;
+  }
+  // reverse steps n1-1 .. n0
+  for (int m = 0; m < lenmax; m += 2) {
+    B.clear();
+    for (int q = 0; q < np; ++q) {
+      const int len = n1[q] - n0[q];
+      if (m >= len) continue;
+      sweep_plan* p = b->plans[q];
+      void* wq = at<char>(work, off[q]);
+      const int n = n1[q] - 1 - m;
+      if (ac_two_steps(p) && m + 1 < len) {
+        B.add(ac_adj_pair(p, wq, L[q], resids[q], n, n0[q], n1[q]));
+      } else {
+        B.s0.push_back(adj_single_rot(p, wq, L[q], resids[q], n, n0[q], n1[q]));
+        if (m + 1 < len) B.later.push_back(q);
+      }
+    }
+    if ((rc = ac_launch_deep_batch(B.deep.data(), (int)B.deep.size(), true, s))) return rc;
+    if ((rc = ac_launch_adj_batch(B.s0.data(), (int)B.s0.size(), b->rz, b->prz, s))) return rc;
+    for (int q : B.later) {
+      sweep_plan* p = b->plans[q];
+      B.s1.push_back(adj_single_rot(p, at<char>(work, off[q]), L[q], resids[q],
+                                    n1[q] - 2 - m, n0[q], n1[q]));
+    }
+    if (!B.s1.empty() &&
+        (rc = ac_launch_adj_batch(B.s1.data(), (int)B.s1.size(), b->rz, b->prz, s)))
       return rc;
   }
   return SWEEP_OK;
@@ -806,63 +879,7 @@ int batch_backward_enqueue(sweep_batch* b, const float* const* resids, float* co
       lenmax = std::max(lenmax, n1[q] - n0[q]);
       if ((rc = ac_bwd_restore(p, at<char>(work, off[q]), L[q], sg, s))) return rc;
     }
-    // recompute the segments, storing B^n
-    for (int m = 0; m < lenmax; m += 2) {
-      B.clear();
-      for (int q = 0; q < np; ++q) {
-        const int len = n1[q] - n0[q];
-        if (m >= len) continue;
-        sweep_plan* p = b->plans[q];
-        void* wq = at<char>(work, off[q]);
-        const size_t ns = p->pb.nshots;
-        if (ac_two_steps(p) && m + 1 < len) {
-          B.add(ac_fwd_pair(p, wq, L[q], n0[q] + m, m % 2, nullptr, ac_bseg(wq, L[q], ns, m),
-                            ac_bseg(wq, L[q], ns, m + 1)));
-        } else {
-          B.s0.push_back(fwd_single_rot(p, wq, L[q], n0[q] + m, m % 2, nullptr,
-                                        ac_bseg(wq, L[q], ns, m)));
-          if (m + 1 < len) B.later.push_back(q);
-        }
-      }
-      if ((rc = ac_launch_deep_batch(B.deep.data(), (int)B.deep.size(), false, s))) return rc;
-      if ((rc = ac_launch_fwd_batch(B.s0.data(), (int)B.s0.size(), b->rz, b->prz, s))) return rc;
-      for (int q : B.later) {
-        sweep_plan* p = b->plans[q];
-        void* wq = at<char>(work, off[q]);
-        B.s1.push_back(fwd_single_rot(p, wq, L[q], n0[q] + m + 1, (m + 1) % 2, nullptr,
-                                      ac_bseg(wq, L[q], p->pb.nshots, m + 1)));
-      }
-      if (!B.s1.empty() &&
-          (rc = ac_launch_fwd_batch(B.s1.data(), (int)B.s1.size(), b->rz, b->prz, s)))
-        return rc;
-    }
-    // reverse steps n1-1 .. n0
-    for (int m = 0; m < lenmax; m += 2) {
-      B.clear();
-      for (int q = 0; q < np; ++q) {
-        const int len = n1[q] - n0[q];
-        if (m >= len) continue;
-        sweep_plan* p = b->plans[q];
-        void* wq = at<char>(work, off[q]);
-        const int n = n1[q] - 1 - m;
-        if (ac_two_steps(p) && m + 1 < len) {
-          B.add(ac_adj_pair(p, wq, L[q], resids[q], n, n0[q], n1[q]));
-        } else {
-          B.s0.push_back(adj_single_rot(p, wq, L[q], resids[q], n, n0[q], n1[q]));
-          if (m + 1 < len) B.later.push_back(q);
-        }
-      }
-      if ((rc = ac_launch_deep_batch(B.deep.data(), (int)B.deep.size(), true, s))) return rc;
-      if ((rc = ac_launch_adj_batch(B.s0.data(), (int)B.s0.size(), b->rz, b->prz, s))) return rc;
-      for (int q : B.later) {
-        sweep_plan* p = b->plans[q];
-        B.s1.push_back(adj_single_rot(p, at<char>(work, off[q]), L[q], resids[q],
-                                      n1[q] - 2 - m, n0[q], n1[q]));
-      }
-      if (!B.s1.empty() &&
-          (rc = ac_launch_adj_batch(B.s1.data(), (int)B.s1.size(), b->rz, b->prz, s)))
-        return rc;
-    }
+    if ((rc = batch_segment_enqueue(b, resids, work, L, off, n0, n1, lenmax, s))) return rc;
     for (int q = 0; q < np; ++q)
       if (n1[q] > n0[q] && (rc = ac_bwd_fold(b->plans[q], at<char>(work, off[q]), L[q], s)))
         return rc;
@@ -1352,5 +1369,150 @@ extern "C" int sweep_plan_autotune(sweep_plan* p, const float* d_model, const fl
     out << key << " " << best << " " << best_p << " " << best_t << " " << best_us << "\n";
   }
   if (chosen_rz) *chosen_rz = best;
+  return SWEEP_OK;
+}
+
+extern "C" int sweep_batch_autotune(sweep_batch* b, const float* const* d_models,
+                                    const float* const* d_wavelets, void* d_work,
+                                    size_t work_bytes, int steps, int for_backward,
+                                    const char* cache_path, void* stream, int* chosen) {
+  if (!b || !d_models || !d_wavelets || !d_work || steps < 1) {
+    set_error("sweep_batch_autotune: bad argument");
+    return SWEEP_EINVAL;
+  }
+  const int np = (int)b->plans.size();
+  for (int q = 0; q < np; ++q)
+    if (!d_models[q] || !d_wavelets[q]) {
+      set_error("sweep_batch_autotune: null pointer for plan " + std::to_string(q));
+      return SWEEP_EINVAL;
+    }
+  hipStream_t s = (hipStream_t)stream;
+  std::string key = tune_key(b->plans[0]);
+  key = key.substr(0, key.find(' ')) + (for_backward ? " batch-gradient" : " batch");
+  for (sweep_plan* p : b->plans)
+    key += " " + std::to_string(p->NX) + "x" + std::to_string(p->NZ) + "x" +
+           std::to_string(p->pb.nshots);
+  auto apply = [&](int rz, int prz, int tb) {
+    for (sweep_plan* p : b->plans) {
+      sweep_tuning t = p->tune;
+      t.rz = rz;
+      t.pml_rz = prz;
+      t.tblock = tb;
+      const int rc = sweep_plan_set_tuning(p, &t);
+      if (rc) return rc;
+    }
+    b->rz = rz;
+    b->prz = prz;
+    b->saved = false;
+    b->gfwd.reset();
+    b->gbwd.reset();
+    if (chosen) {
+      chosen[0] = rz;
+      chosen[1] = prz;
+      chosen[2] = tb;
+    }
+    return SWEEP_OK;
+  };
+  if (cache_path && *cache_path) {
+    std::ifstream in(cache_path);
+    std::string line;
+    while (std::getline(in, line)) {
+      if (line.compare(0, key.size(), key) != 0 || line.size() <= key.size() ||
+          line[key.size()] != ' ')
+        continue;
+      std::istringstream is(line.substr(key.size()));
+      int rz = 0, prz = 0, tb = 0;
+      double us = 0;
+      if (is >> rz >> prz >> tb >> us && rz_ok(rz) && rz_ok(prz) && prz <= rz &&
+          (tb == 1 || tb == 2))
+        return apply(rz, prz, tb);
+    }
+  }
+  std::vector<AcLayout> L;
+  std::vector<size_t> off;
+  size_t total = 0;
+  batch_layouts(b, for_backward ? 1 : 0, L, off, total);
+  if (work_bytes < total) {
+    set_error("workspace too small: need " + std::to_string(total) + " bytes");
+    return SWEEP_ENOMEM;
+  }
+  // the gradient mix: recompute and reverse the first `steps` steps (at most a
+  // segment) of every plan after the forward steps; the values are not used
+  std::vector<int> n0(np, 0), n1(np, 0);
+  std::vector<const float*> noresid(np, nullptr);
+  int lenmax = 0;
+  for (int q = 0; q < np; ++q) {
+    sweep_plan* p = b->plans[q];
+    n1[q] = std::min(std::min(steps, p->pb.nt), p->ckpt);
+    lenmax = std::max(lenmax, n1[q]);
+  }
+  std::vector<bool> timing(np);
+  for (int q = 0; q < np; ++q) {
+    timing[q] = b->plans[q]->timer.on;
+    b->plans[q]->timer.on = false;
+  }
+  std::vector<float*> nogathers(np, nullptr);
+  hipEvent_t e0, e1;
+  SWEEP_HIP(hipEventCreate(&e0));
+  SWEEP_HIP(hipEventCreate(&e1));
+  const int cand[4] = {1, 2, 4, 8};
+  int best[3] = {b->rz, b->prz, b->plans[0]->tune.tblock};
+  double best_us = 1e300;
+  int rc = SWEEP_OK;
+  for (int c : cand)
+    for (int cp : cand)
+      for (int tb = 1; tb <= 2 && !rc; ++tb) {
+        if (cp > c) continue;
+        if ((rc = apply(c, cp, tb))) break;
+        bool deep = false;
+        for (sweep_plan* p : b->plans) deep = deep || ac_two_steps(p);
+        if (tb == 2 && !deep) continue;  // no deep tiles: the same as tblock = 1
+        for (int q = 0; q < np && !rc; ++q)
+          rc = ac_upload_geometry(b->plans[q], at<char>(d_work, off[q]), L[q], s);
+        for (int rep = 0; rep < 2 && !rc; ++rep) {  // the first pass warms up
+          if ((rc = hipEventRecord(e0, s) == hipSuccess ? SWEEP_OK : SWEEP_EHIP)) break;
+          rc = batch_forward_enqueue(b, d_models, d_wavelets, nogathers.data(), d_work, L, off, 0,
+                                     s, steps);
+          for (int q = 0; q < np && !rc && for_backward; ++q) {
+            sweep_plan* p = b->plans[q];
+            void* wq = at<char>(d_work, off[q]);
+            p->arot = Rot();
+            for (int k = 0; k < 2 && !rc; ++k)
+              rc = launch_fill(at<float>(wq, L[q].adjaux[k]), L[q].aux_elems, 0.0f, s);
+            for (int k = 0; k < 4 && !rc; ++k)
+              rc = launch_fill(at<float>(wq, L[q].lf[k]), p->pb.nshots * L[q].plane, 0.0f, s);
+            if (!rc) rc = ac_bwd_restore(p, wq, L[q], 0, s);
+          }
+          if (!rc && for_backward)
+            rc = batch_segment_enqueue(b, noresid.data(), d_work, L, off, n0, n1, lenmax, s);
+          if (!rc && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess))
+            rc = SWEEP_EHIP;
+        }
+        if (rc) break;
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+          rc = SWEEP_EHIP;
+          break;
+        }
+        if (ms < best_us) {
+          best_us = ms;
+          best[0] = c;
+          best[1] = cp;
+          best[2] = tb;
+        }
+      }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  for (int q = 0; q < np; ++q) b->plans[q]->timer.on = timing[q];
+  if (rc) {
+    if (rc == SWEEP_EHIP) set_error("sweep_batch_autotune: HIP error while timing");
+    return rc;
+  }
+  if ((rc = apply(best[0], best[1], best[2]))) return rc;
+  if (cache_path && *cache_path) {
+    std::ofstream out(cache_path, std::ios::app);
+    out << key << " " << best[0] << " " << best[1] << " " << best[2] << " "
+        << 1e3 * best_us / steps << "\n";
+  }
   return SWEEP_OK;
 }

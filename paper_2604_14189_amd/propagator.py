@@ -265,6 +265,35 @@ class Batch:
     def workspace_bytes(self, for_backward: bool) -> int:
         return int(lib().sweep_batch_workspace_bytes(self._h, int(bool(for_backward))))
 
+    def autotune(self, models, wavelets, steps: int = 10, gradient: bool = True,
+                 cache_path: Optional[str] = None) -> dict:
+        """Pick the fastest tiling (rz, pml_rz) and time-blocking depth (tblock)
+        for the whole batch (cached) and set it on every plan; returns it. With
+        `gradient` the timed steps are the mix of a gradient (forward,
+        recomputation and reverse steps), else forward steps only."""
+        ms, ws = [], []
+        for p, m, w in zip(self.plans, models, wavelets):
+            if p.nparam == 1 and m.dim() == 2:
+                m = m.unsqueeze(0)
+            _need(m, p._model_shape(), "model")
+            _need(w, (p.nshots, p.nt), "wavelet")
+            ms.append(m)
+            ws.append(w)
+        need = self.workspace_bytes(gradient)
+        if self._work is None or self._work.numel() < need:
+            self._work = None
+            torch.cuda.synchronize()
+            self._work = torch.empty(need, dtype=torch.uint8, device=ms[0].device)
+        chosen = (ctypes.c_int * 3)()
+        check(lib().sweep_batch_autotune(self._h, _ptr_array(ms), _ptr_array(ws), _ptr(self._work),
+                                         self._work.numel(), steps, int(bool(gradient)),
+                                         cache_path.encode() if cache_path else None,
+                                         _stream(), chosen))
+        self._saved = False
+        for p in self.plans:
+            p._saved_id = -1
+        return {"rz": chosen[0], "pml_rz": chosen[1], "tblock": chosen[2]}
+
     def forward(self, models, wavelets, save: bool = False):
         outs = []
         ms, ws = [], []

@@ -97,6 +97,35 @@ def test_batch_two_step_passes(sw):
         assert torch.equal(gs[q], ref[q][1]), q
 
 
+def test_batch_autotune_picks_and_caches(sw, tmp_path):
+    """The batch autotuner sets one tuning on every plan, caches it under the
+    batch's shapes, and the results keep the bits of single-step plans."""
+    cases = [random_case(61, nx=260, nz=150, nt=40, nshots=2, nrec=5, ckpt=20),
+             random_case(62, nx=120, nz=90, nt=30, nshots=2, nrec=4, ckpt=50)]
+    plans = [c.plan() for c in cases]
+    batch = sw.Batch(plans)
+    cache = str(tmp_path / "btune.txt")
+    vs, ws = [_dev(c.v) for c in cases], [_dev(c.wav) for c in cases]
+    t = batch.autotune(vs, ws, steps=6, cache_path=cache)
+    assert t["rz"] in (1, 2, 4, 8) and t["pml_rz"] <= t["rz"] and t["tblock"] in (1, 2)
+    for p in plans:
+        tp = p.tuning
+        assert (tp["rz"], tp["pml_rz"], tp["tblock"]) == (t["rz"], t["pml_rz"], t["tblock"])
+    with open(cache) as f:
+        lines = f.read().strip().splitlines()
+    assert len(lines) == 1 and " batch-gradient " in lines[0]
+    assert lines[0].split()[-4:-1] == [str(t["rz"]), str(t["pml_rz"]), str(t["tblock"])]
+    assert sw.Batch([c.plan() for c in cases]).autotune(vs, ws, steps=6, cache_path=cache) == t
+    resids = _resids(cases)
+    ds = batch.forward(vs, ws, save=True)
+    gs = batch.backward(resids)
+    for q, (c, r) in enumerate(zip(cases, resids)):
+        p = c.plan()
+        p.set_tuning(rz=4, pml_rz=4, tblock=1)
+        assert torch.equal(ds[q], p.forward(vs[q], ws[q], save=True)), q
+        assert torch.equal(gs[q], p.backward(r)), q
+
+
 def test_plan_graph_replays_match_eager(sw):
     c = random_case(31, nt=140, ckpt=25)
     r = _dev(synth.bandlimited_noise((c.nshots, c.nt, c.nrec), 15.0, c.dt, 3))
