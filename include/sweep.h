@@ -147,6 +147,25 @@ int sweep_forward(sweep_plan* plan, const float* d_model, const float* d_wavelet
                   float* d_gathers, void* d_work, size_t work_bytes, int save_for_backward,
                   void* stream);
 
+/* Born (tangent-linear) modelling of every shot, Eq. 16 (acoustic plans only):
+ *   d_dgathers = (d gathers / d vp) . d_dmodel
+ *   d_model, d_dmodel [nz][nx]: background vp and its perturbation dvp
+ *   d_wavelet  [nshots][nt] as in sweep_forward
+ *   d_dgathers [nshots][nt][nrec] out: the perturbation dp at step n+1
+ *   d_work     workspace of at least sweep_plan_workspace_bytes(plan, 1) bytes
+ * The background recurrence of sweep_forward runs with a perturbation field dp
+ * that obeys the same recurrence (C-PML included) without the source and with
+ * dC B^n added at every cell, dC = 2 vp dvp dt^2 (dvp edge-replicated into the
+ * pad like vp). Its transpose is sweep_backward: the adjoint of Born modelling
+ * (the migration / least-squares RTM image) is the model gradient for the
+ * residual given. Single steps only (the tuning's tblock is not used). Leaves
+ * no state for sweep_backward (a following backward needs a new forward).
+ * Errors: SWEEP_EINVAL (null pointer, elastic plan), SWEEP_ENOMEM (workspace
+ * too small), SWEEP_EHIP. All pointers are caller-owned device memory. */
+int sweep_born_forward(sweep_plan* plan, const float* d_model, const float* d_dmodel,
+                       const float* d_wavelet, float* d_dgathers, void* d_work,
+                       size_t work_bytes, void* stream);
+
 /* Adjoint: given d_resid = dJ/d(gathers) (layout of d_gathers), writes
  * d_grad [nparam][nz][nx] = dJ/d(model) summed over shots. Requires the
  * preceding sweep_forward(save_for_backward = 1) on the same plan, model and

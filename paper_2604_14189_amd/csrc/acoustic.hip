@@ -115,6 +115,20 @@ __global__ void ac_prep_kernel(const float* __restrict__ v, float* __restrict__ 
   Cs[(size_t)j * NX + i] = (float)(c * c);
 }
 
+// Born model perturbation on the padded grid: dCs = d(Cs)/dv . dv =
+// 2 v dv (dt/h)^2, with dv edge-replicated into the pad like v.
+__global__ void ac_born_prep_kernel(const float* __restrict__ v, const float* __restrict__ dv,
+                                    float* __restrict__ dCs, int nx, int nz, int P, double r) {
+  const int NX = nx + 2 * P, NZ = nz + 2 * P;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (i >= NX || j >= NZ) return;
+  const int ii = min(max(i - P, 0), nx - 1);
+  const int jj = min(max(j - P, 0), nz - 1);
+  const size_t k = (size_t)jj * nx + ii;
+  dCs[(size_t)j * NX + i] = (float)(2.0 * (double)v[k] * (double)dv[k] * r * r);
+}
+
 // C-PML recursion coefficients at integer node i of an axis of length n with
 // `pad` absorbing cells at both ends (Collino-Tsogka / Komatitsch-Martin form,
 // quadratic damping, linearly decreasing alpha, kappa = 1).
@@ -271,7 +285,8 @@ __device__ __forceinline__ void adj_store(const AcStep& a, int shot, int tile, i
 // lx and rows [w RZ, w RZ + RZ), kept as a register window for the z stencil.
 // ---------------------------------------------------------------------------
 // p^{n+1} = 2 p^n - p^{n-1} + Cs D2' p^n (+ source); B'^n = D2' p^n if kept.
-template <int RZ>
+// kBorn: the perturbation step of Born modelling, p^{n+1} += dCs B'^n_background.
+template <int RZ, bool kBorn = false>
 __device__ __forceinline__ void ac_fwd_int_body(const AcStep& a, const int tile, const int shot) {
   using T = MainTile<RZ>;
   __shared__ float sp[T::LH * T::LW];
@@ -286,16 +301,21 @@ __device__ __forceinline__ void ac_fwd_int_body(const AcStep& a, const int tile,
 
   // the per-cell operands are fetched first so their latency overlaps the
   // staging of the halo tile
-  float pp[RZ], cs[RZ];
+  float pp[RZ], cs[RZ], bd[kBorn ? RZ : 1], bb[kBorn ? RZ : 1];
 #pragma unroll
   for (int r = 0; r < RZ; ++r) {
     const int gz = z0 + zb + r;
     pp[r] = 0.0f;
     cs[r] = 0.0f;
+    if (kBorn) bd[r] = bb[r] = 0.0f;
     if (inside || (gx < NX && gz < NZ)) {
       const int idx = gz * NX + gx;
       pp[r] = ld_nt(&a.prev[shot * plane + idx]);
       cs[r] = a.Cs[idx];
+      if (kBorn) {
+        bd[r] = a.bdC[idx];
+        bb[r] = ld_nt(&a.bB[shot * plane + idx]);
+      }
     }
   }
   // source cell and sample with the first loads (a later wait on them would
@@ -324,6 +344,7 @@ __device__ __forceinline__ void ac_fwd_int_body(const AcStep& a, const int tile,
       const int idx = gz * NX + gx;
       const size_t gi = shot * plane + idx;
       pn = fmaf(cs[r], L, 2.0f * c - pp[r]);
+      if (kBorn) pn += bd[r] * bb[r];
       if (idx == src) pn += sw;
       st_nt(&a.next[gi], pn);
       if (a.B_out) st_nt(&a.B_out[gi], L);
@@ -446,7 +467,7 @@ __device__ __forceinline__ bool near_zstrip(int z0, int TZ, int NZ, int P) {
 // outside the strips); then per cell
 //   Bx = D2x' p + D1x' psi_x (+ zeta_x^n, zeta_x^n = b_x zeta_x^{n-1} + a_x (D2x' p + D1x' psi_x)
 //   in the x strip), Bz likewise, B' = Bx + Bz, p^{n+1} = 2 p^n - p^{n-1} + Cs B'.
-template <int RZ, bool HX, bool HZ>
+template <int RZ, bool HX, bool HZ, bool kBorn = false>
 __device__ __forceinline__ void ac_fwd_pml_body(const AcStep& a, const int tile, const int shot,
                                                 const int row0, float* lds) {
   using G = PmlGeom<RZ, HX, HZ>;
@@ -520,7 +541,7 @@ __device__ __forceinline__ void ac_fwd_pml_body(const AcStep& a, const int tile,
   const int src = a.src_cell[shot];
   const float sw = a.w * a.wavelet[(size_t)shot * a.nt + a.n];
   const int xcol = (HX && gx < NX) ? xstrip_col(gx, NX, P) : -1;
-  float pp[RZ], cs[RZ], zx[RZ], zz[RZ];
+  float pp[RZ], cs[RZ], zx[RZ], zz[RZ], bd[kBorn ? RZ : 1], bb[kBorn ? RZ : 1];
 #pragma unroll
   for (int r = 0; r < RZ; ++r) {
     const int gz = z0 + zb + r;
@@ -528,6 +549,10 @@ __device__ __forceinline__ void ac_fwd_pml_body(const AcStep& a, const int tile,
     const size_t idx = ok ? (size_t)gz * NX + gx : 0;
     pp[r] = ok ? ld_nt(&a.prev[shot * plane + idx]) : 0.0f;
     cs[r] = ok ? a.Cs[idx] : 0.0f;
+    if (kBorn) {
+      bd[r] = ok ? a.bdC[idx] : 0.0f;
+      bb[r] = ok ? ld_nt(&a.bB[shot * plane + idx]) : 0.0f;
+    }
     zx[r] = (HX && ok && xcol >= 0) ? a.zex_in[shot * xsp + (size_t)gz * P2 + xcol] : 0.0f;
     const int zrow = (HZ && ok) ? zstrip_row(gz, NZ, P) : -1;
     zz[r] = zrow >= 0 ? a.zez_in[shot * zsp + (size_t)zrow * NX + gx] : 0.0f;
@@ -613,6 +638,7 @@ __device__ __forceinline__ void ac_fwd_pml_body(const AcStep& a, const int tile,
       }
       const float B = Bx + Bz;
       pn = fmaf(cs[r], B, 2.0f * c - pp[r]);
+      if (kBorn) pn += bd[r] * bb[r];
       if (idx == src) pn += sw;
       st_nt(&a.next[gi], pn);
       if (a.B_out) st_nt(&a.B_out[gi], B);
@@ -1274,19 +1300,19 @@ __global__ __launch_bounds__(kThreads) void ac_march_kernel(AcStep a) {
 // of plans of different shapes in one launch (the flat block index is split by
 // the per-plan block counts of this launch).
 // ---------------------------------------------------------------------------
-template <int RZ, bool kAdj>
+template <int RZ, bool kAdj, bool kBorn = false>
 __device__ __forceinline__ void run_interior(const AcStep& a, int l) {
   const int tile = a.ilist[l % a.n_int];
   const int shot = l / a.n_int;
   if (kAdj)
     ac_adj_int_body<RZ>(a, tile, shot);
   else
-    ac_fwd_int_body<RZ>(a, tile, shot);
+    ac_fwd_int_body<RZ, kBorn>(a, tile, shot);
 }
 
 // Frame pieces: kZ selects the z frame (its pieces meet z strips only) or the
 // x frame (general body, specialised on the strips near the piece).
-template <int RZ, bool kAdj, bool kZ>
+template <int RZ, bool kAdj, bool kZ, bool kBorn = false>
 __device__ __forceinline__ void run_frame(const AcStep& a, int l, float* lds) {
   const int nk = (kZ ? a.n_zf : a.n_xf) * a.nsub;
   const int t = l % nk, shot = l / nk;
@@ -1296,7 +1322,7 @@ __device__ __forceinline__ void run_frame(const AcStep& a, int l, float* lds) {
     if (kAdj)
       ac_adj_pml_body<RZ, false, true>(a, tile, shot, row0, lds);
     else
-      ac_fwd_pml_body<RZ, false, true>(a, tile, shot, row0, lds);
+      ac_fwd_pml_body<RZ, false, true, kBorn>(a, tile, shot, row0, lds);
     return;
   }
   const int x0 = (tile % a.tiles_x) * kTX, z0 = (tile / a.tiles_x) * a.tz + row0;
@@ -1312,13 +1338,13 @@ __device__ __forceinline__ void run_frame(const AcStep& a, int l, float* lds) {
       ac_adj_pml_body<RZ, false, false>(a, tile, shot, row0, lds);
   } else {
     if (hx && hz)
-      ac_fwd_pml_body<RZ, true, true>(a, tile, shot, row0, lds);
+      ac_fwd_pml_body<RZ, true, true, kBorn>(a, tile, shot, row0, lds);
     else if (hx)
-      ac_fwd_pml_body<RZ, true, false>(a, tile, shot, row0, lds);
+      ac_fwd_pml_body<RZ, true, false, kBorn>(a, tile, shot, row0, lds);
     else if (hz)
-      ac_fwd_pml_body<RZ, false, true>(a, tile, shot, row0, lds);
+      ac_fwd_pml_body<RZ, false, true, kBorn>(a, tile, shot, row0, lds);
     else
-      ac_fwd_pml_body<RZ, false, false>(a, tile, shot, row0, lds);
+      ac_fwd_pml_body<RZ, false, false, kBorn>(a, tile, shot, row0, lds);
   }
 }
 
@@ -1331,6 +1357,19 @@ template <int RZ, bool kAdj, bool kZ>
 __global__ __launch_bounds__(kThreads) void ac_pml_kernel(AcStep a) {
   __shared__ float lds[PmlLds<RZ>::get(kAdj, kZ)];
   run_frame<RZ, kAdj, kZ>(a, xcd_spread(blockIdx.x, gridDim.x), lds);
+}
+
+// Born perturbation steps (single steps; the frame and interior tile sets as
+// in the forward).
+template <int RZ>
+__global__ __launch_bounds__(kThreads) void ac_born_int_kernel(AcStep a) {
+  run_interior<RZ, false, true>(a, xcd_spread(blockIdx.x, gridDim.x));
+}
+
+template <int RZ, bool kZ>
+__global__ __launch_bounds__(kThreads) void ac_born_pml_kernel(AcStep a) {
+  __shared__ float lds[PmlLds<RZ>::get(false, kZ)];
+  run_frame<RZ, false, kZ, true>(a, xcd_spread(blockIdx.x, gridDim.x), lds);
 }
 
 // plan of flat block f in a batched launch, and f's index inside that plan
@@ -1566,6 +1605,49 @@ int ac_launch_fwd(const AcStep& a, int rz, int prz, hipStream_t s, hipEvent_t* e
     return SWEEP_EINVAL;
   }
   return launch_step<false>(a, rz, prz, s, ev);
+}
+
+template <bool kZ>
+void launch_born_frame(const AcStep& a, int prz, dim3 g, hipStream_t s) {
+  switch (prz) {
+    case 1: hipLaunchKernelGGL((ac_born_pml_kernel<1, kZ>), g, dim3(kThreads), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((ac_born_pml_kernel<2, kZ>), g, dim3(kThreads), 0, s, a); break;
+    case 4: hipLaunchKernelGGL((ac_born_pml_kernel<4, kZ>), g, dim3(kThreads), 0, s, a); break;
+    default: hipLaunchKernelGGL((ac_born_pml_kernel<8, kZ>), g, dim3(kThreads), 0, s, a); break;
+  }
+}
+
+int ac_launch_born(const AcStep& a, int rz, int prz, hipStream_t s) {
+  if (!valid_rz(rz, prz)) {
+    set_error("unsupported rz / pml_rz");
+    return SWEEP_EINVAL;
+  }
+  if (!a.bdC || !a.bB) {
+    set_error("Born step without its perturbation operands");
+    return SWEEP_EINVAL;
+  }
+  if (a.n_zf > 0) launch_born_frame<true>(a, prz, dim3(a.n_zf * a.nsub * a.nshots), s);
+  if (a.n_xf > 0) launch_born_frame<false>(a, prz, dim3(a.n_xf * a.nsub * a.nshots), s);
+  if (a.n_int > 0) {
+    const dim3 g(a.n_int * a.nshots);
+    switch (rz) {
+      case 1: hipLaunchKernelGGL((ac_born_int_kernel<1>), g, dim3(kThreads), 0, s, a); break;
+      case 2: hipLaunchKernelGGL((ac_born_int_kernel<2>), g, dim3(kThreads), 0, s, a); break;
+      case 4: hipLaunchKernelGGL((ac_born_int_kernel<4>), g, dim3(kThreads), 0, s, a); break;
+      default: hipLaunchKernelGGL((ac_born_int_kernel<8>), g, dim3(kThreads), 0, s, a); break;
+    }
+  }
+  SWEEP_HIP(hipGetLastError());
+  return SWEEP_OK;
+}
+
+int ac_launch_born_prep(const float* v, const float* dv, float* dCs, int nx, int nz, int P,
+                        double h, double dt, hipStream_t s) {
+  const int NX = nx + 2 * P, NZ = nz + 2 * P;
+  hipLaunchKernelGGL(ac_born_prep_kernel, dim3((NX + 255) / 256, NZ), dim3(256), 0, s, v, dv, dCs,
+                     nx, nz, P, dt / h);
+  SWEEP_HIP(hipGetLastError());
+  return SWEEP_OK;
 }
 
 int ac_launch_adj(const AcStep& a, int rz, int prz, hipStream_t s, hipEvent_t* ev) {

@@ -664,6 +664,58 @@ int ac_forward(sweep_plan* p, const float* model, const float* wavelet, float* g
   return SWEEP_OK;
 }
 
+// Born (tangent-linear) modelling, Eq. 16. The background field p and the
+// perturbation dp advance step by step: the background step (single steps
+// over every tile set) stores B'^n in one plane per shot, and the
+// perturbation step, the same recurrence with no source, adds dCs B'^n at
+// every cell and records dp^{n+1} at the receivers. The perturbation state
+// lives in the adjoint half of the workspace (its four time-level buffers
+// and two memory-variable sets), B'^n in the first slot of the segment
+// buffer and dCs in the first plane of the gradient partial.
+int ac_born(sweep_plan* p, const float* model, const float* dmodel, const float* wavelet,
+            float* dgathers, void* work, size_t bytes, hipStream_t s) {
+  AcLayout L;
+  ac_layout(p, L);
+  int rc = check_work(p, L.bwd_end, work, bytes);
+  if (rc) return rc;
+  if ((rc = ac_upload_geometry(p, work, L, s))) return rc;
+  if ((rc = ac_fwd_prologue(p, model, wavelet, work, L, s))) return rc;
+  const sweep_problem& pb = p->pb;
+  const size_t ns = pb.nshots;
+  float* dCs = at<float>(work, L.gpart);
+  float* Bn = at<float>(work, L.Bseg);
+  if ((rc = ac_launch_born_prep(model, dmodel, dCs, pb.nx, pb.nz, p->P, pb.h, pb.dt, s)))
+    return rc;
+  Rot br;
+  if ((rc = launch_fill(at<float>(work, L.lf[br.prev]), ns * L.plane, 0.0f, s))) return rc;
+  if ((rc = launch_fill(at<float>(work, L.lf[br.cur]), ns * L.plane, 0.0f, s))) return rc;
+  float* daux[2] = {at<float>(work, L.adjaux[0]), at<float>(work, L.adjaux[1])};
+  if ((rc = launch_fill(daux[0], L.aux_elems, 0.0f, s))) return rc;
+  if ((rc = launch_fill(daux[1], L.aux_elems, 0.0f, s))) return rc;
+  const int rz = p->tune.rz, prz = p->tune.pml_rz;
+  for (int n = 0; n < pb.nt; ++n) {
+    const int par = n % 2;
+    if ((rc = ac_fwd_one(p, work, L, n, par, nullptr, Bn, s, -1, -1, -1))) return rc;
+    const int o = br.free_buf(0);
+    AcStep d = ac_base(p, work, L);
+    d.wavelet = at<float>(work, L.wav);
+    d.w = 0.0f;  // no source term in the perturbation
+    d.gathers = dgathers;
+    d.n = n;
+    d.cur = at<float>(work, L.lf[br.cur]);
+    d.prev = at<float>(work, L.lf[br.prev]);
+    d.next = at<float>(work, L.lf[o]);
+    set_aux(d, aux_ptrs(daux[par], L, ns), aux_ptrs(daux[1 - par], L, ns));
+    d.bdC = dCs;
+    d.bB = Bn;
+    if ((rc = ac_launch_born(d, rz, prz, s))) return rc;
+    br.prev = br.cur;
+    br.cur = o;
+  }
+  p->saved = false;
+  return SWEEP_OK;
+}
+
 int ac_backward(sweep_plan* p, const float* resid, float* grad, void* work, size_t bytes,
                 hipStream_t s) {
   if (!p->saved || p->saved_work != work || p->saved_rz != p->tune.rz) {
@@ -1069,6 +1121,22 @@ extern "C" int sweep_forward(sweep_plan* p, const float* d_model, const float* d
                       (hipStream_t)stream);
   return ac_forward(p, d_model, d_wavelet, d_gathers, d_work, work_bytes, save_for_backward,
                     (hipStream_t)stream);
+}
+
+extern "C" int sweep_born_forward(sweep_plan* p, const float* d_model, const float* d_dmodel,
+                                  const float* d_wavelet, float* d_dgathers, void* d_work,
+                                  size_t work_bytes, void* stream) {
+  if (!p || !d_model || !d_dmodel || !d_wavelet || (!d_dgathers && p->pb.nrec > 0)) {
+    set_error("sweep_born_forward: null argument");
+    return SWEEP_EINVAL;
+  }
+  if (p->pb.physics != SWEEP_ACOUSTIC) {
+    set_error("sweep_born_forward: acoustic plans only");
+    return SWEEP_EINVAL;
+  }
+  p->saved = false;
+  return ac_born(p, d_model, d_dmodel, d_wavelet, d_dgathers, d_work, work_bytes,
+                 (hipStream_t)stream);
 }
 
 extern "C" int sweep_backward(sweep_plan* p, const float* d_resid, float* d_grad, void* d_work,

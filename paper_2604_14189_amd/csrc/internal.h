@@ -89,6 +89,9 @@ struct AcStep {
   const float* B_in2;     // B'^{n-1} (two-step pass)
   float* g;               // [nshots][NZ][NX] gradient partial
   int g_init;             // 1: g = P1 B (first step of a segment), 0: g += P1 B
+  // Born (tangent-linear) step, Eq. 16: p^{n+1} += dCs * bB at every cell
+  const float* bdC;       // [NZ][NX] dCs = 2 v dv (dt/h)^2
+  const float* bB;        // [nshots][NZ][NX] background B'^n
   // tiles: the interior rectangle [itx0, itx1) x [itz0, itz1) of tile
   // coordinates holds the n_int tiles without C-PML cells; the other n_pml
   // tiles (the frame) take the PML kernel
@@ -118,6 +121,11 @@ int ac_launch_prep(const float* v, float* vpad, float* Cs, float* ax, float* bx,
                    double f0, double R, hipStream_t s);
 int ac_launch_fwd(const AcStep& a, int rz, int prz, hipStream_t s, hipEvent_t* ev);
 int ac_launch_adj(const AcStep& a, int rz, int prz, hipStream_t s, hipEvent_t* ev);
+// Born perturbation step (a.bdC, a.bB set; single steps over all tile sets)
+// and its model perturbation dCs[NZ][NX] from v, dv [nz][nx].
+int ac_launch_born(const AcStep& a, int rz, int prz, hipStream_t s);
+int ac_launch_born_prep(const float* v, const float* dv, float* dCs, int nx, int nz, int P,
+                        double h, double dt, hipStream_t s);
 int ac_launch_fwd_batch(const AcStep* steps, int n, int rz, int prz, hipStream_t s);
 // Two steps over the deep runs (a.drun): forward n and n+1, or adjoint n and n-1.
 int ac_launch_deep(const AcStep& a, bool adj, hipStream_t s, hipEvent_t* ev);

@@ -185,6 +185,29 @@ class Plan:
         self._saved_id = self._fwd_id if save else -1
         return out
 
+    def born(self, model: torch.Tensor, dmodel: torch.Tensor, wavelet: torch.Tensor,
+             out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """Born (tangent-linear) gathers [nshots, nt, nrec] = (d gathers / d vp)
+        . dmodel (Eq. 16), acoustic plans only. The adjoint of this map is
+        backward(). Uses the backward-sized workspace and leaves no saved
+        forward state."""
+        if self.nparam != 1:
+            raise ValueError("born() is defined for acoustic plans")
+        model = model.unsqueeze(0) if model.dim() == 2 else model
+        dmodel = dmodel.unsqueeze(0) if dmodel.dim() == 2 else dmodel
+        _need(model, self._model_shape(), "model")
+        _need(dmodel, self._model_shape(), "dmodel")
+        _need(wavelet, (self.nshots, self.nt), "wavelet")
+        if out is None:
+            out = torch.empty(self.gathers_shape(), dtype=torch.float32, device=model.device)
+        _need(out, self.gathers_shape(), "out")
+        work = self._workspace(True)
+        check(lib().sweep_born_forward(self._h, _ptr(model), _ptr(dmodel), _ptr(wavelet),
+                                       _ptr(out), _ptr(work), work.numel(), _stream()))
+        self._fwd_id += 1
+        self._saved_id = -1
+        return out
+
     def backward(self, resid: torch.Tensor, out: Optional[torch.Tensor] = None,
                  forward_id: Optional[int] = None) -> torch.Tensor:
         """d(loss)/d(model) [nparam, nz, nx] for d(loss)/d(gathers) = resid."""
