@@ -41,10 +41,13 @@ TRAFFIC = {
 
 
 def _source_hash() -> str:
+    """Hash of the acoustic kernel source and the step-argument header it
+    compiles against (the traffic figures hold only for that code)."""
     import hashlib
     h = hashlib.sha256()
-    with open(os.path.join(ROOT, "paper_2604_14189_amd", "csrc", "acoustic.hip"), "rb") as f:
-        h.update(f.read())
+    for name in ("acoustic.hip", "internal.h"):
+        with open(os.path.join(ROOT, "paper_2604_14189_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
     return h.hexdigest()[:16]
 
 
@@ -233,6 +236,38 @@ def elastic_gradient(sw, torch):
             "nt": w.nt, "gradient_s": round(t, 3), "Gcell_per_s": round(cells / t / 1e9, 2)}
 
 
+def born_modelling(sw, torch, case, w, v_true, v0, wav):
+    """Born (tangent-linear) modelling on the 1000x300 workload, all shots:
+    the background and the perturbation (dv = true - smooth model) advance
+    step by step in single steps; and one least-squares RTM iteration (Born
+    gathers, background forward with checkpoints, gradient of the Born
+    residual)."""
+    plan = case.plan()
+    dv = (v_true - v0).contiguous()
+
+    def born():
+        return plan.born(v0, dv, wav)
+
+    born()
+    _, t_born = _sync_time(torch, born)
+
+    def lsrtm():
+        dd = plan.born(v0, dv, wav)
+        plan.forward(v0, wav, save=True)
+        return plan.backward(dd)
+
+    _, t_it = _sync_time(torch, lsrtm)
+    NX, NZ = plan.padded()
+    plan.release_workspace()
+    cells = float(w.nshots) * NX * NZ * w.nt
+    return {"workload": "layered1000x300", "shots": w.nshots, "nt": w.nt,
+            "born_s": round(t_born, 3),
+            "born_Gcell_per_s": round(cells / t_born / 1e9, 2),
+            "wavefield_Gcell_per_s": round(2.0 * cells / t_born / 1e9, 2),
+            "lsrtm_iteration_s": round(t_it, 3),
+            "note": "a Born cell-step advances the background and the perturbation"}
+
+
 def mlp_throughput(torch):
     """MLP velocity model at 300,000 points: forward, backward and Adam step
     (bf16 MFMA, float32 accumulation)."""
@@ -273,7 +308,9 @@ def main():
     ap.add_argument("--per-shot-sample", type=int, default=4,
                     help="shots timed through the per-shot path (0: skip)")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the elastic, batched-uneven and MLP measurements")
+                    help="skip the Born, batched-uneven, elastic and MLP measurements")
+    ap.add_argument("--only", choices=["born", "batched_uneven", "elastic", "mlp"],
+                    help="run one of the extra measurements alone (profiling) and print it")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -291,6 +328,23 @@ def main():
     import paper_2604_14189_amd as sw
     import synth
     from tests.helpers import case_from_workload
+
+    if args.only:
+        if args.only == "born":
+            wb = synth.workload(WORKLOAD)
+            cb = case_from_workload(wb)
+            vt = torch.tensor(cb.v, dtype=torch.float32, device="cuda")
+            vs = torch.tensor(synth.smooth(cb.v, 20.0), dtype=torch.float32, device="cuda")
+            wv = torch.tensor(cb.wav, dtype=torch.float32, device="cuda")
+            res = born_modelling(sw, torch, cb, wb, vt, vs, wv)
+        elif args.only == "batched_uneven":
+            res = batched_uneven(sw, torch)
+        elif args.only == "elastic":
+            res = elastic_gradient(sw, torch)
+        else:
+            res = mlp_throughput(torch)
+        print(json.dumps({args.only: res}), flush=True)
+        return
 
     w = synth.workload(WORKLOAD)
     if args.nt:
@@ -423,6 +477,8 @@ def main():
     if not args.no_extras and not args.nt:
         plan.release_workspace()
         del plan
+        torch.cuda.empty_cache()
+        out["born"] = born_modelling(sw, torch, case, w, v_true, v0, wav)
         torch.cuda.empty_cache()
         out["batched_uneven"] = batched_uneven(sw, torch)
         torch.cuda.empty_cache()

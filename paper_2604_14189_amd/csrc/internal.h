@@ -89,9 +89,6 @@ struct AcStep {
   const float* B_in2;     // B'^{n-1} (two-step pass)
   float* g;               // [nshots][NZ][NX] gradient partial
   int g_init;             // 1: g = P1 B (first step of a segment), 0: g += P1 B
-  // Born (tangent-linear) step, Eq. 16: p^{n+1} += dCs * bB at every cell
-  const float* bdC;       // [NZ][NX] dCs = 2 v dv (dt/h)^2
-  const float* bB;        // [nshots][NZ][NX] background B'^n
   // tiles: the interior rectangle [itx0, itx1) x [itz0, itz1) of tile
   // coordinates holds the n_int tiles without C-PML cells; the other n_pml
   // tiles (the frame) take the PML kernel
@@ -104,6 +101,10 @@ struct AcStep {
   int n_xf, n_zf;  // frame tiles: left/right columns (x frame), above/below (z frame)
   int tz;    // rows of a tile
   int nsub;  // PML work-groups per frame tile (each takes tz / nsub rows)
+  // Born (tangent-linear) step, Eq. 16: p^{n+1} += dCs * bB at every cell
+  // (last, so the other fields keep their kernel-argument offsets)
+  const float* bdC;       // [NZ][NX] dCs = 2 v dv (dt/h)^2
+  const float* bB;        // [nshots][NZ][NX] background B'^n
 };
 
 // Several plans of different shapes advanced by one launch per kernel kind.
