@@ -166,7 +166,8 @@ int sweep_born_forward(sweep_plan* plan, const float* d_model, const float* d_dm
                        const float* d_wavelet, float* d_dgathers, void* d_work,
                        size_t work_bytes, void* stream);
 
-/* Adjoint: given d_resid = dJ/d(gathers) (layout of d_gathers), writes
+/* Adjoint: given d_resid = dJ/d(gathers) (layout of d_gathers; may be null
+ * when nrec = 0, and the gradient is then zero), writes
  * d_grad [nparam][nz][nx] = dJ/d(model) summed over shots. Requires the
  * preceding sweep_forward(save_for_backward = 1) on the same plan, model and
  * workspace (SWEEP_ESTATE otherwise). The result is the exact transpose of the

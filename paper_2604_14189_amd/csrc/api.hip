@@ -1141,7 +1141,7 @@ extern "C" int sweep_born_forward(sweep_plan* p, const float* d_model, const flo
 
 extern "C" int sweep_backward(sweep_plan* p, const float* d_resid, float* d_grad, void* d_work,
                               size_t work_bytes, void* stream) {
-  if (!p || !d_resid || !d_grad) {
+  if (!p || (!d_resid && p->pb.nrec > 0) || !d_grad) {
     set_error("sweep_backward: null argument");
     return SWEEP_EINVAL;
   }
@@ -1295,7 +1295,7 @@ extern "C" int sweep_batch_backward(sweep_batch* b, const float* const* d_resids
   }
   std::vector<const void*> key = {d_work};
   for (size_t q = 0; q < b->plans.size(); ++q) {
-    if (!d_resids[q] || !d_grads[q]) {
+    if ((!d_resids[q] && b->plans[q]->pb.nrec > 0) || !d_grads[q]) {
       set_error("sweep_batch_backward: null pointer for plan " + std::to_string(q));
       return SWEEP_EINVAL;
     }
