@@ -1353,8 +1353,11 @@ __global__ __launch_bounds__(kThreads) void ac_int_kernel(AcStep a) {
   run_interior<RZ, kAdj>(a, xcd_spread(blockIdx.x, gridDim.x));
 }
 
+// The forward x-frame kernel at prz = 4 needs 97 VGPRs (4 waves per SIMD);
+// capped at 96 it holds 5 with no spill. The adjoint kernels would spill.
 template <int RZ, bool kAdj, bool kZ>
-__global__ __launch_bounds__(kThreads) void ac_pml_kernel(AcStep a) {
+__global__ __launch_bounds__(kThreads)
+__attribute__((amdgpu_waves_per_eu(!kZ && !kAdj && RZ == 4 ? 5 : 1))) void ac_pml_kernel(AcStep a) {
   __shared__ float lds[PmlLds<RZ>::get(kAdj, kZ)];
   run_frame<RZ, kAdj, kZ>(a, xcd_spread(blockIdx.x, gridDim.x), lds);
 }
