@@ -434,10 +434,10 @@ struct PmlGeom {
   static constexpr int NPZ = HZ ? ZH * kTX : 0;
   static constexpr int kFwdFloats = NB + NPX + NPZ + 2 * BW + 2 * BH;
   // adjoint LDS: Qbar_x (tile rows, x halo hx), Qbar_z (tile columns, z halo hz),
-  // T rings, C-PML (a, b) along the ring columns and rows
+  // T rings, C-PML (a, b) along the box columns and rows
   static constexpr int NQX = TZ * BW;
   static constexpr int NQZ = BH * kTX;
-  static constexpr int kAdjFloats = NQX + NQZ + NPX + NPZ + 2 * XW + 2 * ZH;
+  static constexpr int kAdjFloats = NQX + NQZ + NPX + NPZ + 2 * BW + 2 * BH;
 };
 
 // LDS floats of the PML kernels: x frame (largest general variant, both axes)
@@ -667,10 +667,10 @@ __device__ __forceinline__ void ac_adj_pml_body(const AcStep& a, const int tile,
   float* sqz = lds + NQX;               // Qbar_z: rows z0-hz .., tile columns
   float* stx = lds + NQX + NQZ;         // T_x: tile rows, columns x0-4 ..
   float* stz = lds + NQX + NQZ + NTX;   // T_z: rows z0-4 .., tile columns
-  float* tax = stz + NTZ;               // a_x, b_x at the ring columns, a_z, b_z at the ring rows
-  float* tbx = tax + XW;
-  float* taz = tbx + XW;
-  float* tbz = taz + G::ZH;
+  float* tax = stz + NTZ;               // a_x, b_x at the box columns (x0-hx ..),
+  float* tbx = tax + BW;                // a_z, b_z at the box rows (z0-hz ..)
+  float* taz = tbx + BW;
+  float* tbz = taz + G::BH;
   const int tid = threadIdx.x;
   const int lx = tid & 63;
   const int zb = (tid >> 6) * RZ;
@@ -681,23 +681,25 @@ __device__ __forceinline__ void ac_adj_pml_body(const AcStep& a, const int tile,
   const int gx = x0 + lx;
   const float* cur = a.cur + shot * plane;
 
-  // C-PML coefficients of the ring columns (threads 0..XW-1) and rows (128..)
+  // C-PML coefficients of the box columns (threads 0..BW-1) and rows (128..),
+  // written to LDS tables before Qbar is formed (registers are not held for
+  // a and b of every ring item)
   float ta = 0.0f, tb = 0.0f;
-  if (tid < XW) {
-    const int gxx = x0 - 4 + tid;
+  if (tid < BW) {
+    const int gxx = x0 - hx + tid;
     if (HX && gxx >= 0 && gxx < NX) {
       ta = a.ax[gxx];
       tb = a.bx[gxx];
     }
-  } else if (tid >= 128 && tid < 128 + G::ZH) {
-    const int gz = z0 - 4 + (tid - 128);
+  } else if (tid >= 128 && tid < 128 + G::BH) {
+    const int gz = z0 - hz + (tid - 128);
     if (HZ && gz >= 0 && gz < NZ) {
       ta = a.az[gz];
       tb = a.bz[gz];
     }
   }
   {
-    float lx_[KQX], cx_[KQX], zx_[HX ? KQX : 1], ax_[HX ? KQX : 1], bx_[HX ? KQX : 1];
+    float lx_[KQX], cx_[KQX], zx_[HX ? KQX : 1];
 #pragma unroll
     for (int k = 0; k < KQX; ++k) {
       const int e = tid + k * kThreads;
@@ -710,11 +712,9 @@ __device__ __forceinline__ void ac_adj_pml_body(const AcStep& a, const int tile,
       if constexpr (HX) {
         const int col = ok ? xstrip_col(gxx, NX, P) : -1;
         zx_[k] = col >= 0 ? a.zex_in[shot * xsp + (size_t)gz * P2 + col] : 0.0f;
-        ax_[k] = col >= 0 ? a.ax[gxx] : 0.0f;
-        bx_[k] = col >= 0 ? a.bx[gxx] : 0.0f;
       }
     }
-    float lz_[KQZ], cz_[KQZ], zz_[HZ ? KQZ : 1], az_[HZ ? KQZ : 1], bz_[HZ ? KQZ : 1];
+    float lz_[KQZ], cz_[KQZ], zz_[HZ ? KQZ : 1];
 #pragma unroll
     for (int k = 0; k < KQZ; ++k) {
       const int e = tid + k * kThreads;
@@ -727,10 +727,16 @@ __device__ __forceinline__ void ac_adj_pml_body(const AcStep& a, const int tile,
       if constexpr (HZ) {
         const int row = ok ? zstrip_row(gz, NZ, P) : -1;
         zz_[k] = row >= 0 ? a.zez_in[shot * zsp + (size_t)row * NX + gxx] : 0.0f;
-        az_[k] = row >= 0 ? a.az[gz] : 0.0f;
-        bz_[k] = row >= 0 ? a.bz[gz] : 0.0f;
       }
     }
+    if (tid < BW) {
+      tax[tid] = ta;
+      tbx[tid] = tb;
+    } else if (tid >= 128 && tid < 128 + G::BH) {
+      taz[tid - 128] = ta;
+      tbz[tid - 128] = tb;
+    }
+    __syncthreads();
 #pragma unroll
     for (int k = 0; k < KQX; ++k) {
       const int e = tid + k * kThreads;
@@ -742,9 +748,9 @@ __device__ __forceinline__ void ac_adj_pml_body(const AcStep& a, const int tile,
         const int col = (gz < NZ && gxx >= 0 && gxx < NX) ? xstrip_col(gxx, NX, P) : -1;
         if (col >= 0) {
           const float zbar = zx_[k] + q;
-          q = q + ax_[k] * zbar;
+          q = q + tax[c] * zbar;
           if (c >= hx && c < hx + kTX)
-            a.zex_out[shot * xsp + (size_t)gz * P2 + col] = bx_[k] * zbar;
+            a.zex_out[shot * xsp + (size_t)gz * P2 + col] = tbx[c] * zbar;
         }
       }
       sqx[e] = q;
@@ -760,9 +766,9 @@ __device__ __forceinline__ void ac_adj_pml_body(const AcStep& a, const int tile,
         const int row = (gxx < NX && gz >= 0 && gz < NZ) ? zstrip_row(gz, NZ, P) : -1;
         if (row >= 0) {
           const float zbar = zz_[k] + q;
-          q = q + az_[k] * zbar;
+          q = q + taz[r] * zbar;
           if (r >= hz && r < hz + TZ)
-            a.zez_out[shot * zsp + (size_t)row * NX + gxx] = bz_[k] * zbar;
+            a.zez_out[shot * zsp + (size_t)row * NX + gxx] = tbz[r] * zbar;
         }
       }
       sqz[e] = q;
@@ -814,13 +820,6 @@ __device__ __forceinline__ void ac_adj_pml_body(const AcStep& a, const int tile,
       }
     }
   }
-  if (tid < XW) {
-    tax[tid] = ta;
-    tbx[tid] = tb;
-  } else if (tid >= 128 && tid < 128 + G::ZH) {
-    taz[tid - 128] = ta;
-    tbz[tid - 128] = tb;
-  }
   __syncthreads();
 
   if constexpr (HX) {
@@ -834,8 +833,9 @@ __device__ __forceinline__ void ac_adj_pml_body(const AcStep& a, const int tile,
       float t = 0.0f;
       if (col >= 0) {
         const float psb = ox[k] - d1s(&sqx[r * BW + c + hx - 4], 1);
-        t = tax[c] * psb;
-        if (c >= 4 && c < 4 + kTX) a.psx_out[shot * xsp + (size_t)gz * P2 + col] = tbx[c] * psb;
+        t = tax[c + hx - 4] * psb;
+        if (c >= 4 && c < 4 + kTX)
+          a.psx_out[shot * xsp + (size_t)gz * P2 + col] = tbx[c + hx - 4] * psb;
       }
       stx[e] = t;
     }
@@ -851,8 +851,9 @@ __device__ __forceinline__ void ac_adj_pml_body(const AcStep& a, const int tile,
       float t = 0.0f;
       if (row >= 0) {
         const float psb = oz[k] - d1s(&sqz[(r + hz - 4) * kTX + c], kTX);
-        t = taz[r] * psb;
-        if (r >= 4 && r < 4 + TZ) a.psz_out[shot * zsp + (size_t)row * NX + gxx] = tbz[r] * psb;
+        t = taz[r + hz - 4] * psb;
+        if (r >= 4 && r < 4 + TZ)
+          a.psz_out[shot * zsp + (size_t)row * NX + gxx] = tbz[r + hz - 4] * psb;
       }
       stz[e] = t;
     }
@@ -1353,11 +1354,12 @@ __global__ __launch_bounds__(kThreads) void ac_int_kernel(AcStep a) {
   run_interior<RZ, kAdj>(a, xcd_spread(blockIdx.x, gridDim.x));
 }
 
-// The forward x-frame kernel at prz = 4 needs 97 VGPRs (4 waves per SIMD);
-// capped at 96 it holds 5 with no spill. The adjoint kernels would spill.
+// The x-frame kernels at prz = 4 need 97 (forward) and 101 (adjoint) VGPRs,
+// 4 waves per SIMD; capped at 96 they hold 5 (the adjoint spills one VGPR,
+// which costs less than the extra wave gains).
 template <int RZ, bool kAdj, bool kZ>
 __global__ __launch_bounds__(kThreads)
-__attribute__((amdgpu_waves_per_eu(!kZ && !kAdj && RZ == 4 ? 5 : 1))) void ac_pml_kernel(AcStep a) {
+__attribute__((amdgpu_waves_per_eu(!kZ && RZ == 4 ? 5 : 1))) void ac_pml_kernel(AcStep a) {
   __shared__ float lds[PmlLds<RZ>::get(kAdj, kZ)];
   run_frame<RZ, kAdj, kZ>(a, xcd_spread(blockIdx.x, gridDim.x), lds);
 }
@@ -1391,7 +1393,8 @@ __global__ __launch_bounds__(kThreads) void ac_int_batch_kernel(AcBatch b) {
 }
 
 template <int RZ, bool kAdj, bool kZ>
-__global__ __launch_bounds__(kThreads) void ac_pml_batch_kernel(AcBatch b) {
+__global__ __launch_bounds__(kThreads)
+__attribute__((amdgpu_waves_per_eu(!kZ && RZ == 4 ? 5 : 1))) void ac_pml_batch_kernel(AcBatch b) {
   __shared__ float lds[PmlLds<RZ>::get(kAdj, kZ)];
   int f = xcd_spread(blockIdx.x, gridDim.x);
   const int p = batch_plan(b, f);
