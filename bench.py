@@ -268,6 +268,35 @@ def born_modelling(sw, torch, case, w, v_true, v0, wav):
             "note": "a Born cell-step advances the background and the perturbation"}
 
 
+def acoustic_vd_gradient(sw, torch):
+    """First-order variable-density acoustic FWI gradient (vp, rho) on the
+    1000x300 layered workload (64 shots, 3000 steps, 40-cell C-PML), with
+    rho = 310 vp^0.25: the staggered kernels with vs = 0."""
+    import synth
+    w = synth.workload(WORKLOAD)
+    vp = np.asarray(w.true_model(), np.float32)
+    model = torch.tensor(np.stack([vp, 310.0 * vp ** 0.25]), dtype=torch.float32, device="cuda")
+    m0 = torch.tensor(np.stack([synth.smooth(c, 20.0) for c in model.cpu().numpy()]),
+                      dtype=torch.float32, device="cuda")
+    plan = sw.Plan(nx=w.nx, nz=w.nz, h=w.h, dt=w.dt, nt=w.nt, pml=w.pml, src_xz=w.sources(),
+                   rec_xz=w.receivers(), pml_vmax=w.pml_vmax(), pml_f0=w.f0, pml_R=w.pml_R,
+                   ckpt_every=w.ckpt_every, physics=sw.ACOUSTIC_VD)
+    wav = torch.tensor(w.wavelets(np.float32), device="cuda")
+    d_obs = plan.forward(model, wav).clone()
+
+    def grad():
+        d = plan.forward(m0, wav, save=True)
+        return plan.backward(sw.l2_misfit(d, d_obs)[0])
+
+    grad()
+    _, t = _sync_time(torch, grad)
+    NX, NZ = plan.padded()
+    plan.release_workspace()
+    cells = 2.0 * w.nshots * NX * NZ * w.nt
+    return {"workload": "layered1000x300, rho = 310 vp^0.25", "shots": w.nshots, "nt": w.nt,
+            "gradient_s": round(t, 3), "Gcell_per_s": round(cells / t / 1e9, 2)}
+
+
 def mlp_throughput(torch):
     """MLP velocity model at 300,000 points: forward, backward and Adam step
     (bf16 MFMA, float32 accumulation)."""
@@ -309,7 +338,7 @@ def main():
                     help="shots timed through the per-shot path (0: skip)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the Born, batched-uneven, elastic and MLP measurements")
-    ap.add_argument("--only", choices=["born", "batched_uneven", "elastic", "mlp"],
+    ap.add_argument("--only", choices=["born", "batched_uneven", "elastic", "acoustic_vd", "mlp"],
                     help="run one of the extra measurements alone (profiling) and print it")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration)")
@@ -341,6 +370,8 @@ def main():
             res = batched_uneven(sw, torch)
         elif args.only == "elastic":
             res = elastic_gradient(sw, torch)
+        elif args.only == "acoustic_vd":
+            res = acoustic_vd_gradient(sw, torch)
         else:
             res = mlp_throughput(torch)
         print(json.dumps({args.only: res}), flush=True)
@@ -483,6 +514,8 @@ def main():
         out["batched_uneven"] = batched_uneven(sw, torch)
         torch.cuda.empty_cache()
         out["elastic"] = elastic_gradient(sw, torch)
+        torch.cuda.empty_cache()
+        out["acoustic_vd"] = acoustic_vd_gradient(sw, torch)
         out["mlp"] = mlp_throughput(torch)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)

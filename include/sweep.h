@@ -46,15 +46,23 @@ extern "C" {
 
 #define SWEEP_ACOUSTIC 0 /* Eq. 2: 2nd order in time, 8th order in space, C-PML */
 #define SWEEP_ELASTIC 1  /* Eq. 12: staggered velocity-stress, 4th order, C-PML */
+/* Eq. 1: first-order variable-density acoustic (particle velocity and
+ * pressure). Computed by the SWEEP_ELASTIC scheme with shear modulus 0: the
+ * two normal stresses then both equal -p and the shear stress stays 0, which
+ * is the first-order acoustic system on the same staggered grid. Model
+ * (vp, rho), gathers (vx, vz), gradients (vp, rho); free_surface = 1 is the
+ * pressure-release top. */
+#define SWEEP_ACOUSTIC_VD 2
 
 /* Problem description. The padded grid adds `pml` absorbing cells on each side
  * (and none on top when free_surface = 1, elastic only); the model is
  * replicated from its edge cells into the pad. */
 typedef struct {
-  int physics;      /* SWEEP_ACOUSTIC or SWEEP_ELASTIC */
+  int physics;      /* SWEEP_ACOUSTIC, SWEEP_ELASTIC or SWEEP_ACOUSTIC_VD */
   int nx, nz;       /* model grid (cells) */
   int pml;          /* absorbing pad width (cells), >= 0 */
-  int free_surface; /* elastic: 1 = traction-free top row; acoustic: must be 0 */
+  int free_surface; /* elastic: 1 = traction-free top row (acoustic_vd: p = 0
+                       there); acoustic: must be 0 */
   double h;         /* grid spacing dx = dz (m) */
   double dt;        /* time step (s) */
   int nt;           /* time steps */
@@ -134,7 +142,8 @@ int sweep_plan_tiles(const sweep_plan* plan, int* interior_tiles, int* frame_til
                      int* tile_rows, int* rect);
 
 /* Forward modelling of every shot.
- *   d_model   [nparam][nz][nx]: acoustic vp (nparam 1); elastic vp, vs, rho (3)
+ *   d_model   [nparam][nz][nx]: acoustic vp (nparam 1); elastic vp, vs, rho (3);
+ *             acoustic_vd vp, rho (2)
  *   d_wavelet [nshots][nt]: source time function, sample n injected at step n
  *   d_gathers [nshots][nt][nrec][ncomp] out: acoustic p (ncomp 1) at step n+1;
  *             elastic (vx, vz) (ncomp 2)

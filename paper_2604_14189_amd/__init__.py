@@ -5,4 +5,5 @@ with C-PML and a free surface), its exact adjoint and the resulting FWI
 gradients, in hand-written HIP kernels behind the C-ABI of include/sweep.h.
 """
 from ._lib import SweepError, lib  # noqa: F401
-from .propagator import ACOUSTIC, ELASTIC, Batch, Plan, WaveFn, l2_misfit  # noqa: F401
+from .propagator import (ACOUSTIC, ACOUSTIC_VD, ELASTIC, Batch, Plan, WaveFn,  # noqa: F401
+                         l2_misfit)

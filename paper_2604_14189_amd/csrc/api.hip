@@ -953,7 +953,8 @@ extern "C" int sweep_plan_create(const sweep_problem* pb, const int32_t* src_xz,
     return SWEEP_EINVAL;
   }
   *out = nullptr;
-  if (pb->physics != SWEEP_ACOUSTIC && pb->physics != SWEEP_ELASTIC) {
+  if (pb->physics != SWEEP_ACOUSTIC && pb->physics != SWEEP_ELASTIC &&
+      pb->physics != SWEEP_ACOUSTIC_VD) {
     set_error("unknown physics");
     return SWEEP_EINVAL;
   }
@@ -1065,7 +1066,7 @@ extern "C" int sweep_plan_get_tuning(const sweep_plan* p, sweep_tuning* t) {
 
 extern "C" size_t sweep_plan_workspace_bytes(const sweep_plan* p, int for_backward) {
   if (!p) return 0;
-  if (p->pb.physics == SWEEP_ELASTIC) {
+  if (p->pb.physics != SWEEP_ACOUSTIC) {
     ElLayout E;
     el_layout(p, E);
     return for_backward ? E.bwd_end : E.fwd_end;
@@ -1116,7 +1117,7 @@ extern "C" int sweep_forward(sweep_plan* p, const float* d_model, const float* d
     return SWEEP_EINVAL;
   }
   p->saved = false;
-  if (p->pb.physics == SWEEP_ELASTIC)
+  if (p->pb.physics != SWEEP_ACOUSTIC)
     return el_forward(p, d_model, d_wavelet, d_gathers, d_work, work_bytes, save_for_backward,
                       (hipStream_t)stream);
   return ac_forward(p, d_model, d_wavelet, d_gathers, d_work, work_bytes, save_for_backward,
@@ -1145,7 +1146,7 @@ extern "C" int sweep_backward(sweep_plan* p, const float* d_resid, float* d_grad
     set_error("sweep_backward: null argument");
     return SWEEP_EINVAL;
   }
-  if (p->pb.physics == SWEEP_ELASTIC)
+  if (p->pb.physics != SWEEP_ACOUSTIC)
     return el_backward(p, d_resid, d_grad, d_work, work_bytes, (hipStream_t)stream);
   return ac_backward(p, d_resid, d_grad, d_work, work_bytes, (hipStream_t)stream);
 }

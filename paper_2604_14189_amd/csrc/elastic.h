@@ -43,12 +43,14 @@ struct ElStep {
   float tt_w[4][4][8];
 };
 
-int el_launch_prep(const float* model, const ElCoef& c, int nx, int nz, int P, int fs, double h,
-                   double dt, double vmax, double f0, double R, hipStream_t s);
+// fluid: the model is (vp, rho) and vs = 0 (first-order acoustic); the
+// gradient then has the planes (vp, rho).
+int el_launch_prep(const float* model, const ElCoef& c, int nx, int nz, int P, int fs, int fluid,
+                   double h, double dt, double vmax, double f0, double R, hipStream_t s);
 int el_launch_fwd(const ElStep& a, hipStream_t s, hipEvent_t* ev);
 int el_launch_adj(const ElStep& a, hipStream_t s, hipEvent_t* ev);
 int el_launch_fold(double* tot, const float* gpart, int nshots, size_t plane, hipStream_t s);
 int el_launch_finish(const double* tot, const ElCoef& c, float* grad, int nx, int nz, int P,
-                     int fs, hipStream_t s);
+                     int fs, int fluid, hipStream_t s);
 
 }  // namespace sweep

@@ -633,16 +633,24 @@ __global__ __launch_bounds__(256) void el_adj_v_kernel(ElStep a) {
 // ---------------------------------------------------------------------------
 // Material preparation: padded vp, vs, rho, lambda, mu; buoyancies; harmonic
 // mu at txz nodes; stress coefficients (free-surface row uses M); C-PML tables.
+// A fluid model holds (vp, rho) and has vs = 0.
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ double el_vs(const float* model, size_t mn, size_t m, int fluid) {
+  return fluid ? 0.0 : (double)model[mn + m];
+}
+__device__ __forceinline__ double el_rho(const float* model, size_t mn, size_t m, int fluid) {
+  return (double)model[(fluid ? 1 : 2) * mn + m];
+}
+
 __global__ void el_prep_kernel(const float* model, ElCoef c, int nx, int nz, int P, int top,
-                               int NX, int NZ, int fs) {
+                               int NX, int NZ, int fs, int fluid) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y;
   if (i >= NX || j >= NZ) return;
   const size_t mn = (size_t)nx * nz;
   const int ii = min(max(i - P, 0), nx - 1), jj = min(max(j - top, 0), nz - 1);
   const size_t m = (size_t)jj * nx + ii, k = (size_t)j * NX + i;
-  const double vp = model[m], vs = model[mn + m], rho = model[2 * mn + m];
+  const double vp = model[m], vs = el_vs(model, mn, m, fluid), rho = el_rho(model, mn, m, fluid);
   const double mu = rho * vs * vs, lam = rho * (vp * vp - 2.0 * vs * vs);
   c.vp[k] = (float)vp;
   c.vs[k] = (float)vs;
@@ -671,17 +679,17 @@ __device__ __forceinline__ size_t el_model_index(int i, int j, int nx, int nz, i
 }
 
 __global__ void el_prep2_kernel(const float* model, ElCoef c, int nx, int nz, int P, int top,
-                                int NX, int NZ) {
+                                int NX, int NZ, int fluid) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y;
   if (i >= NX || j >= NZ) return;
   const size_t mn = (size_t)nx * nz;
   auto rho_at = [&](int ii, int jj) -> double {
-    return (double)model[2 * mn + el_model_index(ii, jj, nx, nz, P, top)];
+    return el_rho(model, mn, el_model_index(ii, jj, nx, nz, P, top), fluid);
   };
   auto mu_at = [&](int ii, int jj) -> double {
     const size_t m = el_model_index(ii, jj, nx, nz, P, top);
-    const double vs = model[mn + m], rho = model[2 * mn + m];
+    const double vs = el_vs(model, mn, m, fluid), rho = el_rho(model, mn, m, fluid);
     return rho * vs * vs;
   };
   const int i1 = min(i + 1, NX - 1), j1 = min(j + 1, NZ - 1);
@@ -779,7 +787,7 @@ __device__ void el_chain_cell(const double* tot, size_t plane, const ElCoef& c, 
 }
 
 __global__ void el_finish_kernel(const double* tot, ElCoef c, float* grad, int nx, int nz, int P,
-                                 int top, int NX, int NZ) {
+                                 int top, int NX, int NZ, int fluid) {
   const int ii = blockIdx.x * blockDim.x + threadIdx.x;
   const int jj = blockIdx.y;
   if (ii >= nx || jj >= nz) return;
@@ -797,8 +805,12 @@ __global__ void el_finish_kernel(const double* tot, ElCoef c, float* grad, int n
     }
   const size_t mn = (size_t)nx * nz, m = (size_t)jj * nx + ii;
   grad[m] = (float)acc[0];
-  grad[mn + m] = (float)acc[1];
-  grad[2 * mn + m] = (float)acc[2];
+  if (fluid) {  // (vp, rho); the vs term vanishes at vs = 0
+    grad[mn + m] = (float)acc[2];
+  } else {
+    grad[mn + m] = (float)acc[1];
+    grad[2 * mn + m] = (float)acc[2];
+  }
 }
 
 dim3 grid_of(const ElStep& a) {
@@ -807,14 +819,14 @@ dim3 grid_of(const ElStep& a) {
 
 }  // namespace
 
-int el_launch_prep(const float* model, const ElCoef& c, int nx, int nz, int P, int fs, double h,
-                   double dt, double vmax, double f0, double R, hipStream_t s) {
+int el_launch_prep(const float* model, const ElCoef& c, int nx, int nz, int P, int fs, int fluid,
+                   double h, double dt, double vmax, double f0, double R, hipStream_t s) {
   const int top = fs ? 0 : P;
   const int NX = nx + 2 * P, NZ = nz + top + P;
   hipLaunchKernelGGL(el_prep_kernel, dim3((NX + 255) / 256, NZ), dim3(256), 0, s, model, c, nx,
-                     nz, P, top, NX, NZ, fs);
+                     nz, P, top, NX, NZ, fs, fluid);
   hipLaunchKernelGGL(el_prep2_kernel, dim3((NX + 255) / 256, NZ), dim3(256), 0, s, model, c, nx,
-                     nz, P, top, NX, NZ);
+                     nz, P, top, NX, NZ, fluid);
   const int nmax = NX > NZ ? NX : NZ;
   hipLaunchKernelGGL(el_tables_kernel, dim3((nmax + 255) / 256), dim3(256), 0, s, c, NX, NZ, P,
                      top, h, dt, vmax, f0, R);
@@ -854,11 +866,11 @@ int el_launch_fold(double* tot, const float* gpart, int nshots, size_t plane, hi
 }
 
 int el_launch_finish(const double* tot, const ElCoef& c, float* grad, int nx, int nz, int P,
-                     int fs, hipStream_t s) {
+                     int fs, int fluid, hipStream_t s) {
   const int top = fs ? 0 : P;
   const int NX = nx + 2 * P, NZ = nz + top + P;
   hipLaunchKernelGGL(el_finish_kernel, dim3((nx + 255) / 256, nz), dim3(256), 0, s, tot, c, grad,
-                     nx, nz, P, top, NX, NZ);
+                     nx, nz, P, top, NX, NZ, fluid);
   SWEEP_HIP(hipGetLastError());
   return SWEEP_OK;
 }

@@ -222,8 +222,9 @@ int el_forward(sweep_plan* p, const float* model, const float* wavelet, float* g
                              p->rec_sorted.size() * sizeof(int4), hipMemcpyHostToDevice, s));
   }
   const ElCoef c = coef_ptrs(p, work, L);
-  if ((rc = el_launch_prep(model, c, pb.nx, pb.nz, p->P, pb.free_surface, pb.h, pb.dt,
-                           pb.pml_vmax, pb.pml_f0, pb.pml_R, s)))
+  if ((rc = el_launch_prep(model, c, pb.nx, pb.nz, p->P, pb.free_surface,
+                           pb.physics == SWEEP_ACOUSTIC_VD, pb.h, pb.dt, pb.pml_vmax, pb.pml_f0,
+                           pb.pml_R, s)))
     return rc;
   if ((rc = launch_copy(at<float>(work, L.wav), wavelet, ns * pb.nt, s))) return rc;
   float* st = at<float>(work, L.state);
@@ -315,7 +316,8 @@ int el_backward(sweep_plan* p, const float* resid, float* grad, void* work, size
     }
     if ((rc = el_launch_fold(tot, gpart, (int)ns, L.plane, s))) return rc;
   }
-  return el_launch_finish(tot, c, grad, pb.nx, pb.nz, p->P, pb.free_surface, s);
+  return el_launch_finish(tot, c, grad, pb.nx, pb.nz, p->P, pb.free_surface,
+                          pb.physics == SWEEP_ACOUSTIC_VD, s);
 }
 
 }  // namespace sweep

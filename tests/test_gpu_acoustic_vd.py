@@ -1,0 +1,91 @@
+"""GPU parity: first-order variable-density acoustic (Eq. 1), computed by the
+staggered elastic kernels with vs = 0, against the FP64 oracle (the same
+scheme with vs = 0). Model (vp, rho), gathers (vx, vz), gradients (vp, rho).
+
+Tolerances as for the other physics: gathers <= 1e-5, gradients <= 1e-4
+relative L2. The mode must also give exactly the elastic plan's results for
+vs = 0 (the same kernels).
+"""
+import numpy as np
+import pytest
+
+import synth
+from tests.helpers import f32, rel_l2
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+SEIS_TOL = 1e-5
+GRAD_TOL = 1e-4
+
+
+def _dev(a):
+    return torch.as_tensor(np.asarray(a, dtype=np.float32), device="cuda").contiguous()
+
+
+def _host(t):
+    torch.cuda.synchronize()
+    return t.double().cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def sw():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2604_14189_amd as sw
+    sw.lib()
+    return sw
+
+
+def _case(fs, seed=1, nx=110, nz=70, nt=260, nshots=3, nrec=17):
+    rng = np.random.default_rng(seed)
+    vp = f32(synth.layered_anomaly(nx, nz, 1500.0, 3500.0, seed + 30))
+    rho = f32(310.0 * vp ** 0.25)
+    src = np.stack([rng.integers(0, nx, nshots), rng.integers(0, nz, nshots)], 1).astype(np.int32)
+    src[0] = [0, 0]
+    rec = np.stack([rng.integers(0, nx, (nshots, nrec)), rng.integers(0, nz, (nshots, nrec))],
+                   2).astype(np.int32)
+    rec[:, 1] = rec[:, 0]
+    wav = f32(np.stack([synth.ricker(20.0 + 2 * s, nt, 0.5e-3) for s in range(nshots)]))
+    return dict(nx=nx, nz=nz, pml=10, h=5.0, dt=0.5e-3, nt=nt, f0=20.0, vmax=3500.0, fs=fs,
+                vp=vp, rho=rho, src=src, rec=rec, wav=wav, ckpt=23)
+
+
+def _plan(sw, c, physics):
+    return sw.Plan(nx=c["nx"], nz=c["nz"], h=c["h"], dt=c["dt"], nt=c["nt"], pml=c["pml"],
+                   src_xz=c["src"], rec_xz=c["rec"], pml_vmax=c["vmax"], pml_f0=c["f0"],
+                   ckpt_every=c["ckpt"], physics=physics, free_surface=c["fs"])
+
+
+@pytest.mark.parametrize("fs", [0, 1])
+def test_vd_parity(sw, orc, fs):
+    c = _case(fs)
+    plan = _plan(sw, c, sw.ACOUSTIC_VD)
+    d = plan.forward(_dev(np.stack([c["vp"], c["rho"]])), _dev(c["wav"]), save=True)
+    resid = f32(np.random.default_rng(9).standard_normal(tuple(d.shape)))
+    g = _host(plan.backward(_dev(resid)))
+    m3 = np.stack([c["vp"], np.zeros_like(c["vp"]), c["rho"]])
+    pb = orc.problem(c["nx"], c["nz"], c["pml"], c["h"], c["dt"], c["nt"], c["vmax"], c["f0"],
+                     1e-3, nshots=len(c["src"]), nrec=c["rec"].shape[1], free_surface=fs,
+                     ckpt_every=c["ckpt"])
+    gref, _, dref = orc.el_gradient(pb, m3, c["src"], c["wav"], c["rec"], resid,
+                                    want_gathers=True)
+    e_d = rel_l2(_host(d), dref)
+    e_v, e_r = rel_l2(g[0], gref[0]), rel_l2(g[1], gref[2])
+    print("acoustic_vd fs", fs, "gathers", e_d, "grad vp", e_v, "grad rho", e_r, flush=True)
+    assert tuple(g.shape) == (2, c["nz"], c["nx"])
+    assert e_d <= SEIS_TOL and e_v <= GRAD_TOL and e_r <= GRAD_TOL
+
+
+def test_vd_is_the_elastic_scheme_at_vs_zero(sw):
+    c = _case(1, seed=4, nt=150)
+    vd = _plan(sw, c, sw.ACOUSTIC_VD)
+    el = _plan(sw, c, sw.ELASTIC)
+    wav = _dev(c["wav"])
+    d1 = vd.forward(_dev(np.stack([c["vp"], c["rho"]])), wav, save=True)
+    d3 = el.forward(_dev(np.stack([c["vp"], np.zeros_like(c["vp"]), c["rho"]])), wav, save=True)
+    assert torch.equal(d1, d3)
+    r = _dev(np.random.default_rng(2).standard_normal(tuple(d1.shape)))
+    g1, g3 = vd.backward(r), el.backward(r)
+    assert torch.equal(g1[0], g3[0]) and torch.equal(g1[1], g3[2])
+    assert not torch.any(g3[1])
