@@ -268,6 +268,41 @@ def born_modelling(sw, torch, case, w, v_true, v0, wav):
             "note": "a Born cell-step advances the background and the perturbation"}
 
 
+def encoded_gradient(sw, torch, nsuper=8):
+    """Source encoding on the 1000x300 layered workload: its 64 sources, with
+    random signs, encoded into `nsuper` supershots of 64/nsuper sources each
+    (every receiver of the line records every supershot), 3000 steps. One FWI
+    gradient (observed data: the same encoding on the true model)."""
+    import synth
+    from tests.helpers import case_from_workload
+    w = synth.workload(WORKLOAD)
+    case = case_from_workload(w)
+    k = w.nshots // nsuper
+    src = case.src.reshape(nsuper, k, 2)
+    signs = np.random.default_rng(7).choice([-1.0, 1.0], size=(nsuper, k, 1))
+    wav = torch.tensor((case.wav.reshape(nsuper, k, w.nt) * signs).astype(np.float32),
+                       device="cuda")
+    plan = sw.Plan(nx=w.nx, nz=w.nz, h=w.h, dt=w.dt, nt=w.nt, pml=w.pml, src_xz=src,
+                   rec_xz=case.rec[:nsuper], pml_vmax=case.vmax, pml_f0=w.f0, pml_R=w.pml_R,
+                   ckpt_every=w.ckpt_every)
+    v_true = torch.tensor(case.v, dtype=torch.float32, device="cuda")
+    v0 = torch.tensor(synth.smooth(case.v, 20.0), dtype=torch.float32, device="cuda")
+    d_obs = plan.forward(v_true, wav).clone()
+
+    def grad():
+        d = plan.forward(v0, wav, save=True)
+        return plan.backward(sw.l2_misfit(d, d_obs)[0])
+
+    grad()
+    _, t = _sync_time(torch, grad)
+    NX, NZ = plan.padded()
+    plan.release_workspace()
+    cells = 2.0 * nsuper * NX * NZ * w.nt
+    return {"workload": "layered1000x300", "sources": w.nshots, "supershots": nsuper,
+            "sources_per_supershot": k, "nt": w.nt, "gradient_s": round(t, 3),
+            "Gcell_per_s": round(cells / t / 1e9, 2)}
+
+
 def acoustic_vd_gradient(sw, torch):
     """First-order variable-density acoustic FWI gradient (vp, rho) on the
     1000x300 layered workload (64 shots, 3000 steps, 40-cell C-PML), with
@@ -338,7 +373,8 @@ def main():
                     help="shots timed through the per-shot path (0: skip)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the Born, batched-uneven, elastic and MLP measurements")
-    ap.add_argument("--only", choices=["born", "batched_uneven", "elastic", "acoustic_vd", "mlp"],
+    ap.add_argument("--only", choices=["born", "encoded", "batched_uneven", "elastic",
+                                       "acoustic_vd", "mlp"],
                     help="run one of the extra measurements alone (profiling) and print it")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration)")
@@ -372,6 +408,8 @@ def main():
             res = elastic_gradient(sw, torch)
         elif args.only == "acoustic_vd":
             res = acoustic_vd_gradient(sw, torch)
+        elif args.only == "encoded":
+            res = encoded_gradient(sw, torch)
         else:
             res = mlp_throughput(torch)
         print(json.dumps({args.only: res}), flush=True)
@@ -510,6 +548,8 @@ def main():
         del plan
         torch.cuda.empty_cache()
         out["born"] = born_modelling(sw, torch, case, w, v_true, v0, wav)
+        torch.cuda.empty_cache()
+        out["encoded"] = encoded_gradient(sw, torch)
         torch.cuda.empty_cache()
         out["batched_uneven"] = batched_uneven(sw, torch)
         torch.cuda.empty_cache()

@@ -72,6 +72,12 @@ typedef struct {
   int ckpt_every;   /* checkpoint interval k (steps) for backward(); 0 = default 50 */
   int nshots;       /* shots advanced together */
   int nrec;         /* receivers per shot */
+  int nsrc;         /* sources per shot, 0 or 1 = one. Acoustic only: > 1 makes
+                       every shot an encoded shot (source encoding, Sec. 1: one
+                       simulation of several sources, each with its own wavelet,
+                       e.g. one shot's wavelet times a random sign). Source k of
+                       a shot adds its term after the update, in the order k = 0
+                       .. nsrc-1. Plans with nsrc > 1 do not join batches */
 } sweep_problem;
 
 /* Tile / launch choices (what the autotuner searches). Results are bitwise
@@ -94,8 +100,9 @@ typedef struct sweep_plan sweep_plan;
 /* Message describing the last error on the calling thread ("" if none). */
 const char* sweep_last_error(void);
 
-/* Create a plan. src_xz: host [nshots][2]; rec_xz: host [nshots][nrec][2]
- * (model-grid cells, x then z). The arrays are copied. Fails with SWEEP_EINVAL on
+/* Create a plan. src_xz: host [nshots][nsrc][2] ([nshots][2] for one source);
+ * rec_xz: host [nshots][nrec][2] (model-grid cells, x then z); the wavelets of
+ * sweep_forward are then [nshots][nsrc][nt]. The arrays are copied. Fails with SWEEP_EINVAL on
  * inconsistent sizes or positions outside the model, SWEEP_ECFL when
  * pml_vmax*dt/h exceeds 0.5546 (acoustic, 8th order) or 0.6061 (elastic, 4th).
  * Does not touch the GPU. */

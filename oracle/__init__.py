@@ -150,6 +150,28 @@ def ac_gradient(pb: Problem, v, src, wavelet, rec, resid, want_wavelet=False,
     return g, gw, ga
 
 
+def ac_forward_encoded(pb: Problem, v, src, wavelet, rec) -> np.ndarray:
+    """Encoded shots: src [nshots][nsrc][2], wavelet [nshots][nsrc][nt]."""
+    v, src, wavelet, rec = _f64(v), _i32(src), _f64(wavelet), _i32(rec)
+    nsrc = src.shape[1]
+    assert src.shape == (pb.nshots, nsrc, 2) and wavelet.shape == (pb.nshots, nsrc, pb.nt)
+    out = np.zeros((pb.nshots, pb.nt, pb.nrec))
+    _check(lib().orc_ac_forward_encoded(ctypes.byref(pb), ctypes.c_int(nsrc), _d(v), _i(src),
+                                        _d(wavelet), _i(rec), _d(out)), "ac_forward_encoded")
+    return out
+
+
+def ac_gradient_encoded(pb: Problem, v, src, wavelet, rec, resid) -> np.ndarray:
+    v, src, wavelet, rec, resid = _f64(v), _i32(src), _f64(wavelet), _i32(rec), _f64(resid)
+    nsrc = src.shape[1]
+    assert src.shape == (pb.nshots, nsrc, 2) and wavelet.shape == (pb.nshots, nsrc, pb.nt)
+    g = np.zeros((pb.nz, pb.nx))
+    _check(lib().orc_ac_gradient_encoded(ctypes.byref(pb), ctypes.c_int(nsrc), _d(v), _i(src),
+                                         _d(wavelet), _i(rec), _d(resid), _d(g)),
+           "ac_gradient_encoded")
+    return g
+
+
 def ac_born(pb: Problem, v, dv, src, wavelet, rec) -> np.ndarray:
     v, dv, src, wavelet, rec = _f64(v), _f64(dv), _i32(src), _f64(wavelet), _i32(rec)
     out = np.zeros((pb.nshots, pb.nt, pb.nrec))

@@ -126,12 +126,15 @@ struct AcSetup {
   int P = 0, nx = 0, nz = 0, nt = 0, nshots = 0, nrec = 0;
   double h = 0, dt = 0, w = 0;  // w = dt^2 / h^2 : source scaling
   Arr vpad, C, ax, bx, az, bz;
-  std::vector<size_t> src;  // [nshots] padded cell index
+  int nsrc = 1;             // sources per shot
+  std::vector<size_t> src;  // [nshots][nsrc] padded cell index
   std::vector<size_t> rec;  // [nshots][nrec] padded cell index
 };
 
 int make_setup(const orc_problem* pb, const double* v, const int* src_xz, const int* rec_xz,
-               AcSetup& S) {
+               AcSetup& S, int nsrc = 1) {
+  if (nsrc < 1) return -1;
+  S.nsrc = nsrc;
   if (!pb || !v || pb->nx <= 0 || pb->nz <= 0 || pb->pml < 0 || pb->nt < 1 || pb->h <= 0 ||
       pb->dt <= 0 || pb->nshots < 1 || pb->nrec < 0)
     return -1;
@@ -166,11 +169,11 @@ int make_setup(const orc_problem* pb, const double* v, const int* src_xz, const 
   orc_pml_profile(g.NZ, S.P, S.P, 0.0, pb->h, pb->dt, pb->pml_vmax, pb->pml_f0, pb->pml_R,
                   S.az.data(), S.bz.data());
   if (src_xz) {
-    S.src.resize(S.nshots);
-    for (int s = 0; s < S.nshots; ++s) {
-      const int x = src_xz[2 * s], z = src_xz[2 * s + 1];
+    S.src.resize((size_t)S.nshots * nsrc);
+    for (size_t q = 0; q < S.src.size(); ++q) {
+      const int x = src_xz[2 * q], z = src_xz[2 * q + 1];
       if (x < 0 || x >= pb->nx || z < 0 || z >= pb->nz) return -1;
-      S.src[s] = g.idx(x + S.P, z + S.P);
+      S.src[q] = g.idx(x + S.P, z + S.P);
     }
   }
   if (rec_xz) {
@@ -202,11 +205,12 @@ struct AcState {
 //   Q_x      = D2x p^n + D1x psi_x^n                   (and z)
 //   zeta_x^n = b_x zeta_x^{n-1} + a_x Q_x              (and z)
 //   B^n      = Q_x + zeta_x^n + Q_z + zeta_z^n
-//   p^{n+1}  = 2 p^n - p^{n-1} + C B^n + (dt^2/h^2) s_n e_src  [+ extra]
-// `extra` (may be null) is an additional field added to p^{n+1} (Born source);
-// `Bout` (may be null) receives B^n.
-void ac_step(const AcSetup& S, AcState& st, size_t src, double s_n, const Arr* extra, Arr* Bout,
-             bool par) {
+//   p^{n+1}  = 2 p^n - p^{n-1} + C B^n  [+ extra]  + (dt^2/h^2) s_{k,n} e_{src k}
+// with the source terms added in the order k = 0 .. ns-1 (several sources per
+// simulation: an encoded shot). `extra` (may be null) is an additional field
+// added to p^{n+1} (Born source); `Bout` (may be null) receives B^n.
+void ac_step_multi(const AcSetup& S, AcState& st, const size_t* src, const double* s_n, int ns,
+                   const Arr* extra, Arr* Bout, bool par) {
   const Grid2& g = S.g;
   const double h = S.h;
   Arr psx(g.size()), psz(g.size()), pn(g.size());
@@ -230,11 +234,30 @@ void ac_step(const AcSetup& S, AcState& st, size_t src, double s_n, const Arr* e
       if (extra) pn[k] += (*extra)[k];
       if (Bout) (*Bout)[k] = B;
     }
-  pn[src] += S.w * s_n;
+  for (int k = 0; k < ns; ++k) pn[src[k]] += S.w * s_n[k];
   st.psx.swap(psx);
   st.psz.swap(psz);
   st.p0.swap(st.p1);
   st.p1.swap(pn);
+}
+
+void ac_step(const AcSetup& S, AcState& st, size_t src, double s_n, const Arr* extra, Arr* Bout,
+             bool par) {
+  ac_step_multi(S, st, &src, &s_n, 1, extra, Bout, par);
+}
+
+// Step n of shot s with its nsrc sources (wavelets wav[k][nt]).
+void ac_step_shot(const AcSetup& S, AcState& st, int s, const double* wav, int n, Arr* Bout,
+                  bool par) {
+  double sv[64];
+  std::vector<double> big;
+  double* v = sv;
+  if (S.nsrc > 64) {
+    big.resize(S.nsrc);
+    v = big.data();
+  }
+  for (int k = 0; k < S.nsrc; ++k) v[k] = wav[(size_t)k * S.nt + n];
+  ac_step_multi(S, st, &S.src[(size_t)s * S.nsrc], v, S.nsrc, nullptr, Bout, par);
 }
 
 // Adjoint state entering the reverse of step n: P1 = adjoint of p^{n+1},
@@ -312,7 +335,7 @@ void ac_forward_shot(const AcSetup& S, int s, const double* wav, double* gath, d
   st.zeros(S.g.size());
   const size_t* rec = S.rec.empty() ? nullptr : &S.rec[(size_t)s * S.nrec];
   for (int n = 0; n < S.nt; ++n) {
-    ac_step(S, st, S.src[s], wav[n], nullptr, nullptr, par);
+    ac_step_shot(S, st, s, wav, n, nullptr, par);
     if (gath)
       for (int r = 0; r < S.nrec; ++r) gath[(size_t)n * S.nrec + r] = st.p1[rec[r]];
     if (snaps) std::copy(st.p1.begin(), st.p1.end(), snaps + (size_t)n * S.g.size());
@@ -334,7 +357,7 @@ void ac_gradient_shot(const AcSetup& S, int s, const double* wav, const double* 
   st.zeros(g.size());
   for (int n = 0; n < nt; ++n) {
     if (n % k == 0) ck[n / k] = st;
-    ac_step(S, st, S.src[s], wav[n], nullptr, nullptr, par);
+    ac_step_shot(S, st, s, wav, n, nullptr, par);
     if (gath)
       for (int r = 0; r < S.nrec; ++r) gath[(size_t)n * S.nrec + r] = st.p1[rec[r]];
   }
@@ -346,10 +369,10 @@ void ac_gradient_shot(const AcSetup& S, int s, const double* wav, const double* 
   for (int sg = nseg - 1; sg >= 0; --sg) {
     const int n0 = sg * k, n1 = std::min(nt, n0 + k);
     AcState w = ck[sg];
-    for (int n = n0; n < n1; ++n) ac_step(S, w, S.src[s], wav[n], nullptr, &Bseg[n - n0], par);
+    for (int n = n0; n < n1; ++n) ac_step_shot(S, w, s, wav, n, &Bseg[n - n0], par);
     for (int n = n1 - 1; n >= n0; --n)
-      ac_adj_step(S, A, resid + (size_t)n * S.nrec, rec, S.src[s], Bseg[n - n0], gC,
-                  sbar ? sbar + n : nullptr, par);
+      ac_adj_step(S, A, resid + (size_t)n * S.nrec, rec, S.src[(size_t)s * S.nsrc], Bseg[n - n0],
+                  gC, sbar ? sbar + n : nullptr, par);
   }
 }
 
@@ -412,6 +435,44 @@ extern "C" int orc_ac_gradient(const orc_problem* pb, const double* v, const int
                      grad_wavelet ? grad_wavelet + (size_t)s * S.nt : nullptr,
                      gathers ? gathers + (size_t)s * S.nt * S.nrec : nullptr, inner);
   // sum over shots in shot order, then chain to v and fold the pad
+  Arr tot(S.g.size(), 0.0);
+  for (int s = 0; s < S.nshots; ++s)
+    for (size_t k = 0; k < tot.size(); ++k) tot[k] += gC[s][k];
+  std::fill(grad_v, grad_v + (size_t)S.nx * S.nz, 0.0);
+  fold_gradient(S, tot, grad_v);
+  return 0;
+}
+
+// Encoded shots: nsrc sources per simulation (src_xz [nshots][nsrc][2],
+// wavelet [nshots][nsrc][nt]).
+extern "C" int orc_ac_forward_encoded(const orc_problem* pb, int nsrc, const double* v,
+                                      const int* src_xz, const double* wavelet,
+                                      const int* rec_xz, double* gathers) {
+  AcSetup S;
+  if (!src_xz || !rec_xz || !wavelet || !gathers) return -1;
+  if (make_setup(pb, v, src_xz, rec_xz, S, nsrc)) return -1;
+  const int nth = default_threads(pb);
+  const bool inner = S.nshots == 1;
+#pragma omp parallel for schedule(dynamic) num_threads(nth) if (!inner)
+  for (int s = 0; s < S.nshots; ++s)
+    ac_forward_shot(S, s, wavelet + (size_t)s * nsrc * S.nt,
+                    gathers + (size_t)s * S.nt * S.nrec, nullptr, inner);
+  return 0;
+}
+
+extern "C" int orc_ac_gradient_encoded(const orc_problem* pb, int nsrc, const double* v,
+                                       const int* src_xz, const double* wavelet,
+                                       const int* rec_xz, const double* resid, double* grad_v) {
+  AcSetup S;
+  if (!src_xz || !rec_xz || !wavelet || !resid || !grad_v) return -1;
+  if (make_setup(pb, v, src_xz, rec_xz, S, nsrc)) return -1;
+  const int nth = default_threads(pb);
+  const bool inner = S.nshots == 1;
+  std::vector<Arr> gC(S.nshots);
+#pragma omp parallel for schedule(dynamic) num_threads(nth) if (!inner)
+  for (int s = 0; s < S.nshots; ++s)
+    ac_gradient_shot(S, s, wavelet + (size_t)s * nsrc * S.nt, resid + (size_t)s * S.nt * S.nrec,
+                     pb->ckpt_every, gC[s], nullptr, nullptr, inner);
   Arr tot(S.g.size(), 0.0);
   for (int s = 0; s < S.nshots; ++s)
     for (size_t k = 0; k < tot.size(); ++k) tot[k] += gC[s][k];

@@ -82,6 +82,16 @@ int orc_ac_gradient(const orc_problem* pb, const double* v, const int* src_xz,
                     const double* wavelet, const int* rec_xz, const double* resid,
                     double* grad_v, double* grad_wavelet, double* gathers);
 
+/* Encoded shots (source encoding: nsrc sources in one simulation):
+ * src_xz[nshots][nsrc][2], wavelet[nshots][nsrc][nt]; source k adds
+ * (dt^2/h^2) wavelet[s][k][n] at its cell after step n, in the order k = 0 ..
+ * nsrc-1. Gathers and grad_v as in orc_ac_forward / orc_ac_gradient. */
+int orc_ac_forward_encoded(const orc_problem* pb, int nsrc, const double* v, const int* src_xz,
+                           const double* wavelet, const int* rec_xz, double* gathers);
+int orc_ac_gradient_encoded(const orc_problem* pb, int nsrc, const double* v, const int* src_xz,
+                            const double* wavelet, const int* rec_xz, const double* resid,
+                            double* grad_v);
+
 /* Born / tangent-linear modelling (Eq. 16): dgathers = (d gathers / d v) . dv. */
 int orc_ac_born(const orc_problem* pb, const double* v, const double* dv,
                 const int* src_xz, const double* wavelet, const int* rec_xz,

@@ -30,7 +30,7 @@ class Problem(ctypes.Structure):
         ("pml", ctypes.c_int), ("free_surface", ctypes.c_int), ("h", ctypes.c_double),
         ("dt", ctypes.c_double), ("nt", ctypes.c_int), ("pml_vmax", ctypes.c_double),
         ("pml_f0", ctypes.c_double), ("pml_R", ctypes.c_double), ("ckpt_every", ctypes.c_int),
-        ("nshots", ctypes.c_int), ("nrec", ctypes.c_int),
+        ("nshots", ctypes.c_int), ("nrec", ctypes.c_int), ("nsrc", ctypes.c_int),
     ]
 
 

@@ -1426,6 +1426,32 @@ __global__ void ac_inject_last(float* lam, size_t plane, const int* rec_cell,
   for (int k = 0; k < nrec; ++k) lam[s * plane + rec_cell[(size_t)s * nrec + k]] += r[k];
 }
 
+// Encoded shots (several sources per simulation): after step n the step
+// kernels, which inject no source for such plans, have written p^{n+1}; one
+// thread per shot adds its sources' terms w s_{k,n} in the order k = 0 ..
+// nsrc-1 (coincident sources add up deterministically) and records again the
+// receivers that sit on a source cell (co_off / co_rec: CSR per shot).
+__global__ void ac_inject_encoded(float* next, size_t plane, const int* src_cell,
+                                  const float* wav, int nsrc, int nt, int n, float w, int nshots,
+                                  const int* co_off, const int* co_rec, const int* rec_cell,
+                                  float* gathers, int nrec) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nshots) return;
+  float* f = next + (size_t)s * plane;
+  const int* sc = src_cell + (size_t)s * nsrc;
+  const float* ws = wav + (size_t)s * nsrc * nt;
+  for (int k = 0; k < nsrc; ++k) {
+    const float sw = w * ws[(size_t)k * nt + n];
+    f[sc[k]] += sw;
+  }
+  if (!gathers) return;
+  float* g = gathers + ((size_t)s * nt + n) * nrec;
+  for (int e = co_off[s]; e < co_off[s + 1]; ++e) {
+    const int r = co_rec[e];
+    g[r] = f[rec_cell[(size_t)s * nrec + r]];
+  }
+}
+
 // tot[c] += sum_s gpart[s][c], shots in order (float64).
 __global__ void ac_fold_kernel(double* tot, const float* __restrict__ gpart, int nshots,
                                size_t plane) {
@@ -1675,6 +1701,17 @@ int ac_launch_adj_init(float* lam_cur, float* lam_prev, size_t plane_elems, floa
   if (nrec > 0)
     hipLaunchKernelGGL(ac_inject_last, dim3((nshots + 63) / 64), dim3(64), 0, s, lam_cur, plane,
                        rec_cell, resid, nshots, nt, nrec);
+  SWEEP_HIP(hipGetLastError());
+  return SWEEP_OK;
+}
+
+int ac_launch_inject_encoded(float* next, size_t plane, const int* src_cell, const float* wav,
+                             int nsrc, int nt, int n, float w, int nshots, const int* co_off,
+                             const int* co_rec, const int* rec_cell, float* gathers, int nrec,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(ac_inject_encoded, dim3((nshots + 63) / 64), dim3(64), 0, s, next, plane,
+                     src_cell, wav, nsrc, nt, n, w, nshots, co_off, co_rec, rec_cell, gathers,
+                     nrec);
   SWEEP_HIP(hipGetLastError());
   return SWEEP_OK;
 }

@@ -196,8 +196,11 @@ void ac_layout(const sweep_plan* p, AcLayout& L) {
   L.bz = c.take(p->NZ * f);
   L.vpad = c.take(plane * f);
   L.Cs = c.take(plane * f);
-  L.wav = c.take(ns * p->pb.nt * f);
-  L.src_cell = c.take(ns * sizeof(int));
+  const size_t nsrc = p->nsrc;
+  L.wav = c.take(ns * nsrc * p->pb.nt * f);
+  L.src_cell = c.take(ns * nsrc * sizeof(int));
+  L.co_off = c.take((ns + 1) * sizeof(int));
+  L.co_rec = c.take(std::max<size_t>(p->co_rec.size(), 1) * sizeof(int));
   L.rec_cell = c.take(ns * nr * sizeof(int));
   L.rec_off = c.take((ns * ac_max_tiles(p) + 1) * sizeof(int));
   L.rec_ent = c.take(std::max<size_t>(ns * nr, 1) * sizeof(int2));
@@ -280,7 +283,8 @@ AcStep ac_base(const sweep_plan* p, void* work, const AcLayout& L) {
   a.nshots = p->pb.nshots;
   a.tiles_x = p->tiles_x;
   a.ntiles = p->ntiles;
-  a.w = (float)((double)p->pb.dt * p->pb.dt / ((double)p->pb.h * p->pb.h));
+  // encoded shots: the step kernels inject nothing (ac_encode_sources does)
+  a.w = p->nsrc > 1 ? 0.0f : (float)((double)p->pb.dt * p->pb.dt / ((double)p->pb.h * p->pb.h));
   a.Cs = at<float>(work, L.Cs);
   a.ax = at<float>(work, L.ax);
   a.bx = at<float>(work, L.bx);
@@ -324,6 +328,13 @@ int ac_upload_geometry(sweep_plan* p, void* work, const AcLayout& L, hipStream_t
   if (!p->drun.empty())
     SWEEP_HIP(hipMemcpyAsync(at<int>(work, L.tl) + 2 * L.tl_cap, p->drun.data(),
                              p->drun.size() * sizeof(int2), hipMemcpyHostToDevice, s));
+  if (p->nsrc > 1) {
+    SWEEP_HIP(hipMemcpyAsync(at<int>(work, L.co_off), p->co_off.data(),
+                             p->co_off.size() * sizeof(int), hipMemcpyHostToDevice, s));
+    if (!p->co_rec.empty())
+      SWEEP_HIP(hipMemcpyAsync(at<int>(work, L.co_rec), p->co_rec.data(),
+                               p->co_rec.size() * sizeof(int), hipMemcpyHostToDevice, s));
+  }
   return SWEEP_OK;
 }
 
@@ -339,7 +350,7 @@ int ac_fwd_prologue(sweep_plan* p, const float* model, const float* wavelet, voi
                            pb.pml_f0, pb.pml_R, s)))
     return rc;
   const size_t ns = pb.nshots;
-  if ((rc = launch_copy(at<float>(work, L.wav), wavelet, ns * pb.nt, s))) return rc;
+  if ((rc = launch_copy(at<float>(work, L.wav), wavelet, ns * p->nsrc * pb.nt, s))) return rc;
   p->frot = Rot();
   if ((rc = launch_fill(at<float>(work, L.pf[p->frot.prev]), ns * L.plane, 0.0f, s))) return rc;
   if ((rc = launch_fill(at<float>(work, L.pf[p->frot.cur]), ns * L.plane, 0.0f, s))) return rc;
@@ -383,13 +394,27 @@ hipEvent_t* step_events(sweep_plan* p, const AcStep& a, int ci, int cz, int cx) 
   return p->timer.take(a.n_int > 0 ? ci : -1, a.n_zf > 0 ? cz : -1, a.n_xf > 0 ? cx : -1);
 }
 
+// Encoded shots: the sources of step n into p^{n+1} (next) and the receivers
+// on source cells recorded again; nothing for one source per shot.
+int ac_encode_sources(sweep_plan* p, void* work, const AcLayout& L, int n, float* next,
+                      float* gathers, hipStream_t s) {
+  if (p->nsrc <= 1) return SWEEP_OK;
+  const sweep_problem& pb = p->pb;
+  const float w = (float)((double)pb.dt * pb.dt / ((double)pb.h * pb.h));
+  return ac_launch_inject_encoded(next, L.plane, at<int>(work, L.src_cell),
+                                  at<float>(work, L.wav), p->nsrc, pb.nt, n, w, pb.nshots,
+                                  at<int>(work, L.co_off), at<int>(work, L.co_rec),
+                                  at<int>(work, L.rec_cell), gathers, pb.nrec, s);
+}
+
 // One forward-type step from the plan's rotation; advances it.
 int ac_fwd_one(sweep_plan* p, void* work, const AcLayout& L, int n, int par, float* gathers,
                float* B_out, hipStream_t s, int ci, int cz, int cx) {
   Rot& r = p->frot;
   const int o = r.free_buf(0);
   const AcStep a = ac_fwd_single(p, work, L, n, par, r.cur, r.prev, o, gathers, B_out);
-  const int rc = ac_launch_fwd(a, p->tune.rz, p->tune.pml_rz, s, step_events(p, a, ci, cz, cx));
+  int rc = ac_launch_fwd(a, p->tune.rz, p->tune.pml_rz, s, step_events(p, a, ci, cz, cx));
+  if (!rc) rc = ac_encode_sources(p, work, L, n, a.next, gathers, s);
   r.prev = r.cur;
   r.cur = o;
   return rc;
@@ -431,7 +456,9 @@ int ac_fwd_two(sweep_plan* p, void* work, const AcLayout& L, int n, int par, flo
     return rc;
   const int ci = rec ? kRecInt : kFwdInt, cz = rec ? kRecZ : kFwdZ, cx = rec ? kRecX : kFwdX;
   if ((rc = ac_launch_fwd(P.a0, rz, prz, s, step_events(p, P.a0, ci, cz, cx)))) return rc;
-  return ac_launch_fwd(P.a1, rz, prz, s, step_events(p, P.a1, ci, cz, cx));
+  if ((rc = ac_encode_sources(p, work, L, n, P.a0.next, gathers, s))) return rc;
+  if ((rc = ac_launch_fwd(P.a1, rz, prz, s, step_events(p, P.a1, ci, cz, cx)))) return rc;
+  return ac_encode_sources(p, work, L, n + 1, P.a1.next, gathers, s);
 }
 
 bool ac_two_steps(const sweep_plan* p) { return p->tune.tblock == 2 && !p->dlist.empty(); }
@@ -991,15 +1018,21 @@ extern "C" int sweep_plan_create(const sweep_problem* pb, const int32_t* src_xz,
   }
   p->ckpt = pb->ckpt_every > 0 ? pb->ckpt_every : 50;
   if (p->ckpt > pb->nt) p->ckpt = pb->nt;
-  p->src_cell.resize(pb->nshots);
-  for (int s = 0; s < pb->nshots; ++s) {
-    const int x = src_xz[2 * s], z = src_xz[2 * s + 1];
+  if (pb->nsrc < 0 || (pb->nsrc > 1 && pb->physics != SWEEP_ACOUSTIC)) {
+    delete p;
+    set_error("nsrc must be >= 0, and > 1 only for the acoustic physics");
+    return SWEEP_EINVAL;
+  }
+  p->nsrc = pb->nsrc > 1 ? pb->nsrc : 1;
+  p->src_cell.resize((size_t)pb->nshots * p->nsrc);
+  for (size_t q = 0; q < p->src_cell.size(); ++q) {
+    const int x = src_xz[2 * q], z = src_xz[2 * q + 1];
     if (x < 0 || x >= pb->nx || z < 0 || z >= pb->nz) {
       delete p;
-      set_error("source " + std::to_string(s) + " lies outside the model");
+      set_error("source " + std::to_string(q) + " lies outside the model");
       return SWEEP_EINVAL;
     }
-    p->src_cell[s] = (z + (pb->free_surface ? 0 : p->P)) * p->NX + x + p->P;
+    p->src_cell[q] = (z + (pb->free_surface ? 0 : p->P)) * p->NX + x + p->P;
   }
   p->rec_cell.resize((size_t)pb->nshots * pb->nrec);
   for (size_t r = 0; r < p->rec_cell.size(); ++r) {
@@ -1011,6 +1044,17 @@ extern "C" int sweep_plan_create(const sweep_problem* pb, const int32_t* src_xz,
     }
     p->rec_cell[r] = (z + (pb->free_surface ? 0 : p->P)) * p->NX + x + p->P;
   }
+  // encoded shots: the receivers that sit on a source cell of their shot
+  p->co_off.assign((size_t)pb->nshots + 1, 0);
+  p->co_rec.clear();
+  if (p->nsrc > 1)
+    for (int s = 0; s < pb->nshots; ++s) {
+      const int* sc = &p->src_cell[(size_t)s * p->nsrc];
+      for (int r = 0; r < pb->nrec; ++r)
+        if (std::find(sc, sc + p->nsrc, p->rec_cell[(size_t)s * pb->nrec + r]) != sc + p->nsrc)
+          p->co_rec.push_back(r);
+      p->co_off[s + 1] = (int)p->co_rec.size();
+    }
   p->tune.rz = 8;
   p->tune.pml_rz = 4;
   p->tune.tblock = 2;
@@ -1190,8 +1234,8 @@ extern "C" int sweep_batch_create(sweep_plan* const* plans, int nplans, sweep_ba
   }
   *out = nullptr;
   for (int q = 0; q < nplans; ++q) {
-    if (!plans[q] || plans[q]->pb.physics != SWEEP_ACOUSTIC) {
-      set_error("sweep_batch_create: batches hold acoustic plans");
+    if (!plans[q] || plans[q]->pb.physics != SWEEP_ACOUSTIC || plans[q]->nsrc > 1) {
+      set_error("sweep_batch_create: batches hold acoustic plans with one source per shot");
       return SWEEP_EINVAL;
     }
     if (plans[q]->tune.rz != plans[0]->tune.rz || plans[q]->tune.pml_rz != plans[0]->tune.pml_rz) {

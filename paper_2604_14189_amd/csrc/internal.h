@@ -125,6 +125,12 @@ int ac_launch_adj(const AcStep& a, int rz, int prz, hipStream_t s, hipEvent_t* e
 // Born perturbation step (a.bdC, a.bB set; single steps over all tile sets)
 // and its model perturbation dCs[NZ][NX] from v, dv [nz][nx].
 int ac_launch_born(const AcStep& a, int rz, int prz, hipStream_t s);
+// Encoded shots: adds the nsrc sources of every shot to p^{n+1} (next) after
+// step n and records again the receivers on source cells (gathers may be null).
+int ac_launch_inject_encoded(float* next, size_t plane, const int* src_cell, const float* wav,
+                             int nsrc, int nt, int n, float w, int nshots, const int* co_off,
+                             const int* co_rec, const int* rec_cell, float* gathers, int nrec,
+                             hipStream_t s);
 int ac_launch_born_prep(const float* v, const float* dv, float* dCs, int nx, int nz, int P,
                         double h, double dt, hipStream_t s);
 int ac_launch_fwd_batch(const AcStep* steps, int n, int rz, int prz, hipStream_t s);

@@ -10,6 +10,7 @@ namespace sweep {
 struct AcLayout {
   size_t plane, xs, zs, aux_elems;
   size_t ax, bx, az, bz, vpad, Cs, wav, src_cell, rec_cell, rec_off, rec_ent;
+  size_t co_off, co_rec;  // encoded shots: receivers on source cells (CSR per shot)
   size_t tl, tl_cap;  // tile lists (all interior, ring, deep), tl_cap ints each
   size_t pf[4], aux[2];  // forward field buffers (rotated), C-PML memory variables
   size_t fwd_end;
@@ -103,7 +104,9 @@ struct sweep_plan {
   sweep_problem pb;
   sweep_tuning tune;
   int P = 0, NX = 0, NZ = 0, ckpt = 50;
-  std::vector<int> src_cell;  // [nshots] padded linear index
+  std::vector<int> src_cell;  // [nshots][nsrc] padded linear index
+  int nsrc = 1;               // sources per shot (> 1: encoded shots, acoustic)
+  std::vector<int> co_off, co_rec;  // receivers on source cells, CSR per shot
   std::vector<int> rec_cell;  // [nshots][nrec] padded linear index
   // tiling for the current tuning
   int TZ = 0, tiles_x = 0, tiles_z = 0, ntiles = 0;

@@ -53,12 +53,17 @@ class Plan:
                  device: Optional[torch.device] = None):
         src = np.ascontiguousarray(src_xz, dtype=np.int32)
         rec = np.ascontiguousarray(rec_xz, dtype=np.int32)
-        if src.ndim != 2 or src.shape[1] != 2:
-            raise ValueError("src_xz must be [nshots, 2]")
+        if src.ndim == 3 and src.shape[2] == 2:
+            self.nsrc = src.shape[1]  # encoded shots: several sources per shot
+        elif src.ndim == 2 and src.shape[1] == 2:
+            self.nsrc = 1
+        else:
+            raise ValueError("src_xz must be [nshots, 2] or [nshots, nsrc, 2]")
+        self._src3 = src.ndim == 3
         if rec.ndim != 3 or rec.shape[0] != src.shape[0] or rec.shape[2] != 2:
             raise ValueError("rec_xz must be [nshots, nrec, 2]")
         self.pb = Problem(physics, nx, nz, pml, free_surface, h, dt, nt, pml_vmax, pml_f0,
-                          pml_R, ckpt_every, src.shape[0], rec.shape[1])
+                          pml_R, ckpt_every, src.shape[0], rec.shape[1], self.nsrc)
         self.nshots, self.nrec, self.nt, self.nx, self.nz = (src.shape[0], rec.shape[1], nt,
                                                                nx, nz)
         self.physics = physics
@@ -118,7 +123,7 @@ class Plan:
         if self.nparam == 1 and model.dim() == 2:
             model = model.unsqueeze(0)
         _need(model, self._model_shape(), "model")
-        _need(wavelet, (self.nshots, self.nt), "wavelet")
+        _need(wavelet, self.wavelet_shape(), "wavelet")
         work = self._workspace(False)
         rz = ctypes.c_int()
         check(lib().sweep_plan_autotune(self._h, _ptr(model), _ptr(wavelet), _ptr(work),
@@ -164,6 +169,13 @@ class Plan:
     def _model_shape(self):
         return (self.nparam, self.nz, self.nx)
 
+    def wavelet_shape(self):
+        """[nshots, nt], or [nshots, nsrc, nt] when the sources were given as
+        [nshots, nsrc, 2] (encoded shots)."""
+        if not self._src3:
+            return (self.nshots, self.nt)
+        return (self.nshots, self.nsrc, self.nt)
+
     def gathers_shape(self):
         if self.ncomp == 1:
             return (self.nshots, self.nt, self.nrec)
@@ -175,7 +187,7 @@ class Plan:
         if self.nparam == 1 and model.dim() == 2:
             model = model.unsqueeze(0)
         _need(model, self._model_shape(), "model")
-        _need(wavelet, (self.nshots, self.nt), "wavelet")
+        _need(wavelet, self.wavelet_shape(), "wavelet")
         if out is None:
             out = torch.empty(self.gathers_shape(), dtype=torch.float32, device=model.device)
         _need(out, self.gathers_shape(), "out")
@@ -198,7 +210,7 @@ class Plan:
         dmodel = dmodel.unsqueeze(0) if dmodel.dim() == 2 else dmodel
         _need(model, self._model_shape(), "model")
         _need(dmodel, self._model_shape(), "dmodel")
-        _need(wavelet, (self.nshots, self.nt), "wavelet")
+        _need(wavelet, self.wavelet_shape(), "wavelet")
         if out is None:
             out = torch.empty(self.gathers_shape(), dtype=torch.float32, device=model.device)
         _need(out, self.gathers_shape(), "out")
