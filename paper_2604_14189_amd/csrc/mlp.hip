@@ -137,6 +137,9 @@ __global__ __launch_bounds__(256) void mlp_gemm_kernel(const uint16_t* __restric
     if (c + 1 < NC) lstore(u ^ 1);
     __syncthreads();
   }
+  // mode 1: the 16 mask values of each accumulator tile are loaded together
+  // (rows past M clamped) before that tile's stores, instead of each waiting
+  // behind the previous stores
 #pragma unroll
   for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
@@ -144,20 +147,27 @@ __global__ __launch_bounds__(256) void mlp_gemm_kernel(const uint16_t* __restric
       const floatx16& a = acc[ti][tj];
       const int r0 = rb + (w & 1) * 64 + 32 * ti;
       const int col = cb + (w >> 1) * 64 + 32 * tj + (l & 31);
+      const float bc = MODE == 0 ? bias[col] : 0.0f;
+      uint16_t mk[16];
+      if (MODE == 1) {
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+          const int row = min(r0 + 8 * (q >> 2) + (l >> 5) * 4 + (q & 3), M - 1);
+          mk[q] = mask[(size_t)row * kMlpWidth + col];
+        }
+      }
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           const int row = r0 + 8 * i + (l >> 5) * 4 + j;
-          if (row >= M) continue;
-          const size_t o = (size_t)row * kMlpWidth + col;
           float v = a[4 * i + j];
           if (MODE == 0) {
-            v = fmaxf(v + bias[col], 0.0f);
+            v = fmaxf(v + bc, 0.0f);
           } else {
-            v = bf2f(mask[o]) > 0.0f ? v : 0.0f;
+            v = bf2f(mk[4 * i + j]) > 0.0f ? v : 0.0f;
           }
-          out[o] = f2bf(v);
+          if (row < M) out[(size_t)row * kMlpWidth + col] = f2bf(v);
         }
     }
 }
