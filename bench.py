@@ -367,6 +367,9 @@ def main():
     ap.add_argument("--rz", type=int, default=8)
     ap.add_argument("--pml-rz", type=int, default=4)
     ap.add_argument("--tblock", type=int, default=2, help="steps per pass on deep interior tiles")
+    ap.add_argument("--keep-b", type=int, default=-1,
+                    help="checkpoint segments whose B'^n the forward stores (-1: as many as "
+                         "fit in 80%% of free device memory)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--nt", type=int, default=0, help="override the step count (testing)")
     ap.add_argument("--per-shot-sample", type=int, default=4,
@@ -423,6 +426,16 @@ def main():
     plan = case.plan()
     plan.set_tuning(rz=args.rz, pml_rz=args.pml_rz, tblock=args.tblock)
     NX, NZ = plan.padded()
+    keep = args.keep_b
+    if keep < 0:
+        # use the HBM: store B'^n of as many checkpoint segments as fit, so that
+        # the backward recomputes only the rest
+        free, _ = torch.cuda.mem_get_info()
+        seg = w.ckpt_every * w.nshots * NX * NZ * 4
+        nseg = -(-w.nt // w.ckpt_every)
+        spare = 0.8 * free - plan.workspace_bytes(True) - (4 << 30)
+        keep = int(max(0, min(nseg, spare // seg)))
+    plan.set_tuning(rz=args.rz, pml_rz=args.pml_rz, tblock=args.tblock, keep_b=keep)
     v_true = torch.tensor(case.v, dtype=torch.float32, device=dev)
     v0 = torch.tensor(synth.smooth(case.v, 20.0), dtype=torch.float32, device=dev)
     wav = torch.tensor(case.wav, dtype=torch.float32, device=dev)
@@ -536,7 +549,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOAD, "nx": w.nx, "nz": w.nz, "padded": f"{NX}x{NZ}",
                    "nt": w.nt, "shots": w.nshots, "receivers": w.nrec, "pml": w.pml,
-                   "ckpt_every": w.ckpt_every, "rz": args.rz, "pml_rz": args.pml_rz, "tblock": args.tblock, "misfit_J": float(J.item())},
+                   "ckpt_every": w.ckpt_every, "keep_b": keep, "rz": args.rz, "pml_rz": args.pml_rz, "tblock": args.tblock, "misfit_J": float(J.item())},
         "model_grid_value": round(value * w.nx * w.nz / (NX * NZ), 3),
         "roofline": roof,
         "per_shot": per_shot,

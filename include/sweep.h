@@ -93,6 +93,12 @@ typedef struct {
                       inside the grid) two time steps per pass, marching down runs of
                       them; 1 = one step per pass (default 2). In a batch each
                       plan follows its own setting */
+  int keep_b;      /* acoustic plans (not batches): the saving forward stores B'^n
+                      of the last keep_b checkpoint segments in the workspace, and
+                      backward() reverses those segments without recomputing them
+                      (the same bits). Costs keep_b * ckpt_every * nshots * NX *
+                      NZ * 4 more workspace bytes (sweep_plan_workspace_bytes
+                      includes them); 0 = recompute every segment (default) */
 } sweep_tuning;
 
 typedef struct sweep_plan sweep_plan;

@@ -37,7 +37,8 @@ class Problem(ctypes.Structure):
 class Tuning(ctypes.Structure):
     """Mirror of sweep_tuning."""
     _fields_ = [("rz", ctypes.c_int), ("pml_rz", ctypes.c_int),
-                ("use_graph", ctypes.c_int), ("tblock", ctypes.c_int)]
+                ("use_graph", ctypes.c_int), ("tblock", ctypes.c_int),
+                ("keep_b", ctypes.c_int)]
 
 
 _lib = None

@@ -180,7 +180,7 @@ static size_t ac_max_tiles(const sweep_plan* p) {
   return (size_t)((p->NX + kTX - 1) / kTX) * (size_t)((p->NZ + 3) / 4);
 }
 
-void ac_layout(const sweep_plan* p, AcLayout& L) {
+void ac_layout(const sweep_plan* p, AcLayout& L, bool keep) {
   const size_t ns = p->pb.nshots, nr = p->pb.nrec;
   const size_t plane = (size_t)p->NX * p->NZ;
   const size_t xs = (size_t)p->NZ * 2 * p->P, zs = (size_t)2 * p->P * p->NX;
@@ -220,6 +220,8 @@ void ac_layout(const sweep_plan* p, AcLayout& L) {
   L.adjaux[1] = c.take(L.aux_elems * f);
   L.gpart = c.take(ns * plane * f);
   L.tot = c.take(plane * sizeof(double));
+  L.nkeep = keep ? std::min(std::max(p->tune.keep_b, 0), L.nseg) : 0;
+  L.Bkeep = c.take((size_t)L.nkeep * k * ns * plane * f);
   L.bwd_end = c.off;
 }
 
@@ -470,6 +472,18 @@ void ac_mark_saved(sweep_plan* p, void* work, const float* model, int save) {
   p->saved_rz = p->tune.rz;
 }
 
+// B'^n of step n = n0 + m of segment sg: in the stored segments (the last
+// L.nkeep, written by the saving forward) or in the segment buffer (written by
+// the recomputation)
+bool ac_kept(const AcLayout& L, int sg) { return sg >= L.nseg - L.nkeep; }
+float* ac_bseg(sweep_plan* p, void* work, const AcLayout& L, int sg, int m) {
+  const size_t ns = p->pb.nshots;
+  if (ac_kept(L, sg))
+    return at<float>(work, L.Bkeep) +
+           ((size_t)(sg - (L.nseg - L.nkeep)) * p->ckpt + m) * ns * L.plane;
+  return at<float>(work, L.Bseg) + (size_t)m * ns * L.plane;
+}
+
 int ac_forward_enqueue(sweep_plan* p, const float* model, const float* wavelet, float* gathers,
                        void* work, const AcLayout& L, int save, hipStream_t s) {
   int rc;
@@ -478,12 +492,22 @@ int ac_forward_enqueue(sweep_plan* p, const float* model, const float* wavelet, 
   const bool two = ac_two_steps(p);
   for (int n = 0; n < nt;) {
     if (save && n % k == 0 && (rc = ac_checkpoint(p, work, L, n, s))) return rc;
+    // steps of a stored segment also write B'^n (timed with the recomputation,
+    // whose launches they are)
+    const int sg = n / k, m = n - sg * k;
+    const bool keepB = save && ac_kept(L, sg);
     // a pair never spans a checkpoint (the state entering step n+1 is not formed)
     if (two && n + 1 < nt && (!save || (n + 1) % k != 0)) {
-      if ((rc = ac_fwd_two(p, work, L, n, n % 2, gathers, nullptr, nullptr, s, false))) return rc;
+      if ((rc = ac_fwd_two(p, work, L, n, n % 2, gathers,
+                           keepB ? ac_bseg(p, work, L, sg, m) : nullptr,
+                           keepB ? ac_bseg(p, work, L, sg, m + 1) : nullptr, s, keepB)))
+        return rc;
       n += 2;
     } else {
-      if ((rc = ac_fwd_one(p, work, L, n, n % 2, gathers, nullptr, s, kFwdInt, kFwdZ, kFwdX)))
+      if ((rc = keepB ? ac_fwd_one(p, work, L, n, n % 2, gathers, ac_bseg(p, work, L, sg, m), s,
+                                   kRecInt, kRecZ, kRecX)
+                      : ac_fwd_one(p, work, L, n, n % 2, gathers, nullptr, s, kFwdInt, kFwdZ,
+                                   kFwdX)))
         return rc;
       n += 1;
     }
@@ -518,10 +542,6 @@ int ac_bwd_restore(sweep_plan* p, void* work, const AcLayout& L, int sg, hipStre
   return launch_copy(at<float>(work, L.aux[0]), slot + 2 * ns * L.plane, L.aux_elems, s);
 }
 
-// B'^n of step n = n0 + m of the segment being reversed
-float* ac_bseg(void* work, const AcLayout& L, size_t ns, int m) {
-  return at<float>(work, L.Bseg) + (size_t)m * ns * L.plane;
-}
 
 // Reverse of step n inside the segment [n0, n1): fields (cur, prev) -> next,
 // adjoint memory variables by the parity of nt - 1 - n.
@@ -537,7 +557,7 @@ AcStep ac_adj_single(sweep_plan* p, void* work, const AcLayout& L, const float* 
   a.next = at<float>(work, L.lf[next]);
   float* adjaux[2] = {at<float>(work, L.adjaux[0]), at<float>(work, L.adjaux[1])};
   set_aux(a, aux_ptrs(adjaux[it % 2], L, ns), aux_ptrs(adjaux[(it + 1) % 2], L, ns));
-  a.B_in = ac_bseg(work, L, ns, n - n0);
+  a.B_in = ac_bseg(p, work, L, n0 / p->ckpt, n - n0);
   a.g = at<float>(work, L.gpart);
   a.g_init = (n == n1 - 1);
   return a;
@@ -564,7 +584,7 @@ StepPair ac_adj_pair(sweep_plan* p, void* work, const AcLayout& L, const float* 
   StepPair P;
   P.d = ac_adj_single(p, work, L, resid, n, n0, n1, r.cur, r.prev, o1);
   P.d.next2 = at<float>(work, L.lf[o2]);
-  P.d.B_in2 = ac_bseg(work, L, ns, n - 1 - n0);
+  P.d.B_in2 = ac_bseg(p, work, L, n0 / p->ckpt, n - 1 - n0);
   P.d.n_run = (int)p->drun.size();
   P.a0 = ac_adj_single(p, work, L, resid, n, n0, n1, r.cur, r.prev, o1);
   P.a1 = ac_adj_single(p, work, L, resid, n - 1, n0, n1, o1, r.cur, o2);
@@ -608,15 +628,16 @@ int ac_backward_enqueue(sweep_plan* p, const float* resid, float* grad, void* wo
   if ((rc = ac_bwd_prologue(p, resid, work, L, s))) return rc;
   for (int sg = L.nseg - 1; sg >= 0; --sg) {
     const int n0 = sg * k, n1 = std::min(nt, n0 + k);
-    if ((rc = ac_bwd_restore(p, work, L, sg, s))) return rc;
-    for (int m = 0; m < n1 - n0;) {
+    // a stored segment was written by the forward: nothing to recompute
+    if (!ac_kept(L, sg) && (rc = ac_bwd_restore(p, work, L, sg, s))) return rc;
+    for (int m = 0; m < n1 - n0 && !ac_kept(L, sg);) {
       if (two && m + 1 < n1 - n0) {
-        if ((rc = ac_fwd_two(p, work, L, n0 + m, m % 2, nullptr, ac_bseg(work, L, ns, m),
-                             ac_bseg(work, L, ns, m + 1), s, true)))
+        if ((rc = ac_fwd_two(p, work, L, n0 + m, m % 2, nullptr, ac_bseg(p, work, L, sg, m),
+                             ac_bseg(p, work, L, sg, m + 1), s, true)))
           return rc;
         m += 2;
       } else {
-        if ((rc = ac_fwd_one(p, work, L, n0 + m, m % 2, nullptr, ac_bseg(work, L, ns, m), s,
+        if ((rc = ac_fwd_one(p, work, L, n0 + m, m % 2, nullptr, ac_bseg(p, work, L, sg, m), s,
                              kRecInt, kRecZ, kRecX)))
           return rc;
         m += 1;
@@ -702,7 +723,7 @@ int ac_forward(sweep_plan* p, const float* model, const float* wavelet, float* g
 int ac_born(sweep_plan* p, const float* model, const float* dmodel, const float* wavelet,
             float* dgathers, void* work, size_t bytes, hipStream_t s) {
   AcLayout L;
-  ac_layout(p, L);
+  ac_layout(p, L, false);
   int rc = check_work(p, L.bwd_end, work, bytes);
   if (rc) return rc;
   if ((rc = ac_upload_geometry(p, work, L, s))) return rc;
@@ -771,7 +792,7 @@ int batch_layouts(const sweep_batch* b, int for_backward, std::vector<AcLayout>&
   off.resize(b->plans.size());
   total = 0;
   for (size_t q = 0; q < b->plans.size(); ++q) {
-    ac_layout(b->plans[q], L[q]);
+    ac_layout(b->plans[q], L[q], false);
     off[q] = total;
     total = align_up(total + (for_backward ? L[q].bwd_end : L[q].fwd_end));
   }
@@ -884,11 +905,12 @@ int batch_segment_enqueue(sweep_batch* b, const float* const* resids, void* work
       void* wq = at<char>(work, off[q]);
       const size_t ns = p->pb.nshots;
       if (ac_two_steps(p) && m + 1 < len) {
-        B.add(ac_fwd_pair(p, wq, L[q], n0[q] + m, m % 2, nullptr, ac_bseg(wq, L[q], ns, m),
-                          ac_bseg(wq, L[q], ns, m + 1)));
+        const int sg = n0[q] / p->ckpt;
+        B.add(ac_fwd_pair(p, wq, L[q], n0[q] + m, m % 2, nullptr, ac_bseg(p, wq, L[q], sg, m),
+                          ac_bseg(p, wq, L[q], sg, m + 1)));
       } else {
         B.s0.push_back(fwd_single_rot(p, wq, L[q], n0[q] + m, m % 2, nullptr,
-                                      ac_bseg(wq, L[q], ns, m)));
+                                      ac_bseg(p, wq, L[q], n0[q] / p->ckpt, m)));
         if (m + 1 < len) B.later.push_back(q);
       }
     }
@@ -898,7 +920,7 @@ int batch_segment_enqueue(sweep_batch* b, const float* const* resids, void* work
       sweep_plan* p = b->plans[q];
       void* wq = at<char>(work, off[q]);
       B.s1.push_back(fwd_single_rot(p, wq, L[q], n0[q] + m + 1, (m + 1) % 2, nullptr,
-                                    ac_bseg(wq, L[q], p->pb.nshots, m + 1)));
+                                    ac_bseg(p, wq, L[q], n0[q] / p->ckpt, m + 1)));
     }
     if (!B.s1.empty() &&
         (rc = ac_launch_fwd_batch(B.s1.data(), (int)B.s1.size(), b->rz, b->prz, s)))
@@ -1059,6 +1081,7 @@ extern "C" int sweep_plan_create(const sweep_problem* pb, const int32_t* src_xz,
   p->tune.pml_rz = 4;
   p->tune.tblock = 2;
   p->tune.use_graph = 0;
+  p->tune.keep_b = 0;
   if (pb->physics == SWEEP_ACOUSTIC) {
     ac_build_tiling(p);
   } else {
@@ -1087,7 +1110,7 @@ extern "C" int sweep_plan_set_tuning(sweep_plan* p, const sweep_tuning* t) {
   const bool ok_prz = (t->pml_rz == 1 || t->pml_rz == 2 || t->pml_rz == 4 || t->pml_rz == 8) &&
                       t->pml_rz <= t->rz;
   if (!ok_rz || !ok_prz || (t->use_graph != 0 && t->use_graph != 1) ||
-      (t->tblock != 1 && t->tblock != 2)) {
+      (t->tblock != 1 && t->tblock != 2) || t->keep_b < 0) {
     set_error("unsupported tuning");
     return SWEEP_EINVAL;
   }

@@ -17,6 +17,8 @@ struct AcLayout {
   int nseg;
   size_t slot_elems;
   size_t ck, Bseg, lf[4], adjaux[2], gpart, tot;
+  int nkeep;    // checkpoint segments (the last ones) whose B'^n the forward stores
+  size_t Bkeep;  // their B'^n: [nkeep][k][nshots][NZ][NX]
   size_t bwd_end;
 };
 
@@ -135,7 +137,9 @@ struct sweep_plan {
 
 namespace sweep {
 void ac_build_tiling(sweep_plan* p);
-void ac_layout(const sweep_plan* p, AcLayout& L);
+// keep: include the stored B'^n segments of tune.keep_b (single plans; a batch
+// layout and Born modelling use none)
+void ac_layout(const sweep_plan* p, AcLayout& L, bool keep = true);
 void el_layout(const sweep_plan* p, ElLayout& L);
 void el_build_tables(sweep_plan* p);
 int el_forward(sweep_plan* p, const float* model, const float* wavelet, float* gathers,

@@ -105,14 +105,18 @@ class Plan:
     def tuning(self) -> dict:
         t = Tuning()
         check(lib().sweep_plan_get_tuning(self._h, ctypes.byref(t)))
-        return {"rz": t.rz, "pml_rz": t.pml_rz, "use_graph": t.use_graph, "tblock": t.tblock}
+        return {"rz": t.rz, "pml_rz": t.pml_rz, "use_graph": t.use_graph, "tblock": t.tblock,
+                "keep_b": t.keep_b}
 
     def set_tuning(self, rz: int = 8, pml_rz: Optional[int] = None, use_graph: int = 0,
-                   tblock: int = 2):
+                   tblock: int = 2, keep_b: int = 0):
         """rz: rows per thread of the interior kernel (tiles of 64 x 4 rz);
         pml_rz: rows per thread of the C-PML kernels (<= rz, default min(4, rz));
-        tblock: time steps per pass over the deep interior tiles (1 or 2)."""
-        t = Tuning(rz, min(4, rz) if pml_rz is None else pml_rz, use_graph, tblock)
+        tblock: time steps per pass over the deep interior tiles (1 or 2);
+        keep_b: checkpoint segments (the last ones) whose B'^n the saving
+        forward stores, so that backward() does not recompute them (more
+        workspace, the same bits)."""
+        t = Tuning(rz, min(4, rz) if pml_rz is None else pml_rz, use_graph, tblock, keep_b)
         check(lib().sweep_plan_set_tuning(self._h, ctypes.byref(t)))
         self._saved_id = -1
 

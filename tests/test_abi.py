@@ -76,3 +76,28 @@ def test_argument_validation_needs_no_gpu(lib):
     assert rc == ECFL and msg
     rc, msg = create(physics=7)
     assert rc == EINVAL
+
+
+def test_stored_segments_workspace_accounting(lib):
+    """keep_b adds exactly its stored B'^n segments to the backward workspace
+    (host-side layout, no GPU): keep_b * ckpt * nshots * NX * NZ floats, up to
+    the carve alignment, and never more segments than the run has."""
+    import paper_2604_14189_amd as sw
+    nx, nz, pml, nt, k, ns = 70, 40, 10, 100, 17, 3
+    src = [[5 + 20 * s, 3] for s in range(ns)]
+    rec = [[[x, 2] for x in range(0, nx, 7)] for _ in range(ns)]
+    plan = sw.Plan(nx=nx, nz=nz, h=10.0, dt=1e-3, nt=nt, pml=pml, src_xz=src, rec_xz=rec,
+                   pml_vmax=3000.0, pml_f0=10.0, ckpt_every=k)
+    base = plan.workspace_bytes(True)
+    fwd = plan.workspace_bytes(False)
+    seg = k * ns * (nx + 2 * pml) * (nz + 2 * pml) * 4
+    nseg = -(-nt // k)
+    for keep in (1, 2, nseg, nseg + 5):
+        plan.set_tuning(keep_b=keep)
+        extra = plan.workspace_bytes(True) - base
+        want = min(keep, nseg) * seg
+        assert want <= extra < want + 4096, (keep, extra, want)
+        assert plan.workspace_bytes(False) == fwd
+        assert plan.tuning["keep_b"] == keep
+    with pytest.raises(sw.SweepError):
+        plan.set_tuning(keep_b=-1)

@@ -154,6 +154,46 @@ def test_two_step_passes_bitwise(sw, rz, ckpt):
     assert torch.equal(out[0][1], out[1][1])
 
 
+@pytest.mark.parametrize("keep,tblock", [(1, 2), (3, 2), (99, 2), (99, 1)])
+def test_stored_segments_bitwise(sw, keep, tblock):
+    """Segments whose B'^n the saving forward stores (keep_b) are reversed
+    without recomputation: gathers and gradient keep the bits of the full
+    recomputation. 230 steps in segments of 17 (a ragged last one); 99 stores
+    all of them."""
+    w = synth.workload("interface200")
+    case = case_from_workload(w, nt=230)
+    case.ckpt = 17
+    resid = _dev(synth.bandlimited_noise((case.nshots, case.nt, case.nrec), 10.0, case.dt, 6))
+    plan, d0 = _gpu_forward(sw, case, save=True, tuning=dict(rz=4, pml_rz=4, tblock=tblock))
+    d0, g0 = d0.clone(), plan.backward(resid).clone()
+    base = plan.workspace_bytes(True)
+    plan.release_workspace()
+    kp, d1 = _gpu_forward(sw, case, save=True,
+                          tuning=dict(rz=4, pml_rz=4, tblock=tblock, keep_b=keep))
+    assert kp.workspace_bytes(True) > base
+    assert torch.equal(d1, d0)
+    assert torch.equal(kp.backward(resid), g0)
+
+
+def test_stored_segments_graph_replays(sw):
+    case = random_case(32, nt=140, ckpt=25)
+    r = _dev(synth.bandlimited_noise((case.nshots, case.nt, case.nrec), 15.0, case.dt, 3))
+    eager = case.plan()
+    d0 = eager.forward(_dev(case.v), _dev(case.wav), save=True).clone()
+    g0 = eager.backward(r).clone()
+    gp = case.plan()
+    gp.set_tuning(rz=8, use_graph=1, keep_b=3)
+    v, w = _dev(case.v), _dev(case.wav)
+    out, grad = torch.empty_like(d0), torch.empty_like(g0)
+    for rep in range(3):
+        gp.forward(v, w, save=True, out=out)
+        gp.backward(r, out=grad)
+        torch.cuda.synchronize()
+        assert torch.equal(out, d0), rep
+        assert torch.equal(grad, g0), rep
+        assert torch.isfinite(torch.randn(4096, device="cuda").sum())
+
+
 def test_repeatable(sw):
     case = random_case(6, nt=100, ckpt=30)
     resid = _dev(synth.bandlimited_noise((case.nshots, case.nt, case.nrec), 15.0, case.dt, 4))
