@@ -97,12 +97,43 @@ def cpu_baseline(w, max_seconds=30.0):
                       f"{t:.1f} s wall"}
 
 
+def fit_keep_b(torch, plan, nshots, nt, ckpt, reserve=8 << 30):
+    """Use the HBM: store B'^n of as many checkpoint segments as the free
+    memory holds after the rest of the workspace and `reserve` bytes for the
+    gathers, residuals and temporaries, so that the backward recomputes only
+    the others. The workspace is allocated here; on an allocation failure the
+    count steps down. Returns the count set on the plan."""
+    NX, NZ = plan.padded()
+    t = dict(plan.tuning)
+    t["keep_b"] = 0
+    plan.set_tuning(**t)
+    seg = ckpt * nshots * NX * NZ * 4
+    nseg = -(-nt // ckpt)
+    plan.release_workspace()
+    torch.cuda.empty_cache()
+    free, _ = torch.cuda.mem_get_info()
+    keep = int(max(0, min(nseg, (free - plan.workspace_bytes(True) - reserve) // seg)))
+    while True:
+        t["keep_b"] = keep
+        plan.set_tuning(**t)
+        try:
+            plan.reserve_workspace(True)
+            return keep
+        except torch.OutOfMemoryError:
+            plan.release_workspace()
+            torch.cuda.empty_cache()
+            if keep == 0:
+                raise
+            keep = max(0, keep - 2)
+
+
 def per_shot_compare(sw, torch, w, v0, wav, d_obs, nsample, tuning, t_batched):
     """The same FWI gradient through the per-shot path: one single-shot plan
     per shot, its kernels launched once per shot per step (no batching, no
     graph), timed on `nsample` shots spread over the line and scaled to all
-    shots. Also checks that the per-shot gradients sum to the batched gradient
-    of the same shots."""
+    shots. A single shot's B'^n planes fit in HBM many times over, so each
+    single-shot plan stores them for all its segments. Also checks that the
+    per-shot gradients sum to the batched gradient of the same shots."""
     from tests.helpers import case_from_workload
     shots = sorted(set(np.linspace(0, w.nshots - 1, nsample).round().astype(int).tolist()))
     cs = case_from_workload(w, shots=shots)
@@ -114,10 +145,11 @@ def per_shot_compare(sw, torch, w, v0, wav, d_obs, nsample, tuning, t_batched):
     g_batch = bp.backward(r).double()
     bp.release_workspace()
     del bp
+    nseg = -(-w.nt // w.ckpt_every)
 
     def one(s):
         p1 = case_from_workload(w, shots=[s]).plan()
-        p1.set_tuning(*tuning)
+        p1.set_tuning(*tuning, keep_b=nseg)
         d = p1.forward(v0, wav[s:s + 1], save=True)
         r, _ = sw.l2_misfit(d, d_obs[s:s + 1])
         g = p1.backward(r)
@@ -250,6 +282,7 @@ def born_modelling(sw, torch, case, w, v_true, v0, wav):
 
     born()
     _, t_born = _sync_time(torch, born)
+    keep = fit_keep_b(torch, plan, w.nshots, w.nt, w.ckpt_every)
 
     def lsrtm():
         dd = plan.born(v0, dv, wav)
@@ -264,7 +297,7 @@ def born_modelling(sw, torch, case, w, v_true, v0, wav):
             "born_s": round(t_born, 3),
             "born_Gcell_per_s": round(cells / t_born / 1e9, 2),
             "wavefield_Gcell_per_s": round(2.0 * cells / t_born / 1e9, 2),
-            "lsrtm_iteration_s": round(t_it, 3),
+            "lsrtm_iteration_s": round(t_it, 3), "lsrtm_keep_b": keep,
             "note": "a Born cell-step advances the background and the perturbation"}
 
 
@@ -288,6 +321,7 @@ def encoded_gradient(sw, torch, nsuper=8):
     v_true = torch.tensor(case.v, dtype=torch.float32, device="cuda")
     v0 = torch.tensor(synth.smooth(case.v, 20.0), dtype=torch.float32, device="cuda")
     d_obs = plan.forward(v_true, wav).clone()
+    keep = fit_keep_b(torch, plan, nsuper, w.nt, w.ckpt_every)
 
     def grad():
         d = plan.forward(v0, wav, save=True)
@@ -299,7 +333,7 @@ def encoded_gradient(sw, torch, nsuper=8):
     plan.release_workspace()
     cells = 2.0 * nsuper * NX * NZ * w.nt
     return {"workload": "layered1000x300", "sources": w.nshots, "supershots": nsuper,
-            "sources_per_supershot": k, "nt": w.nt, "gradient_s": round(t, 3),
+            "sources_per_supershot": k, "nt": w.nt, "keep_b": keep, "gradient_s": round(t, 3),
             "Gcell_per_s": round(cells / t / 1e9, 2)}
 
 
@@ -426,16 +460,11 @@ def main():
     plan = case.plan()
     plan.set_tuning(rz=args.rz, pml_rz=args.pml_rz, tblock=args.tblock)
     NX, NZ = plan.padded()
-    keep = args.keep_b
-    if keep < 0:
-        # use the HBM: store B'^n of as many checkpoint segments as fit, so that
-        # the backward recomputes only the rest
-        free, _ = torch.cuda.mem_get_info()
-        seg = w.ckpt_every * w.nshots * NX * NZ * 4
-        nseg = -(-w.nt // w.ckpt_every)
-        spare = 0.8 * free - plan.workspace_bytes(True) - (4 << 30)
-        keep = int(max(0, min(nseg, spare // seg)))
-    plan.set_tuning(rz=args.rz, pml_rz=args.pml_rz, tblock=args.tblock, keep_b=keep)
+    if args.keep_b < 0:
+        keep = fit_keep_b(torch, plan, w.nshots, w.nt, w.ckpt_every)
+    else:
+        keep = args.keep_b
+        plan.set_tuning(rz=args.rz, pml_rz=args.pml_rz, tblock=args.tblock, keep_b=keep)
     v_true = torch.tensor(case.v, dtype=torch.float32, device=dev)
     v0 = torch.tensor(synth.smooth(case.v, 20.0), dtype=torch.float32, device=dev)
     wav = torch.tensor(case.wav, dtype=torch.float32, device=dev)
@@ -467,6 +496,8 @@ def main():
     value = cell_updates / dt / 1e9
     per_shot = None
     if args.per_shot_sample > 0:
+        plan.release_workspace()
+        torch.cuda.empty_cache()
         per_shot = per_shot_compare(sw, torch, w, v0, wav, d_obs, args.per_shot_sample,
                                     (args.rz, args.pml_rz, 0, args.tblock), dt)
 

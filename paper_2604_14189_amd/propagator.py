@@ -165,6 +165,12 @@ class Plan:
             self._work = torch.empty(need, dtype=torch.uint8, device=self.device)
         return self._work
 
+    def reserve_workspace(self, for_backward: bool = True) -> int:
+        """Allocate the workspace now rather than at the first forward (before
+        a timed or captured region, or to learn whether a tuning fits in
+        memory: torch.OutOfMemoryError if it does not). Returns its bytes."""
+        return self._workspace(for_backward).numel()
+
     def release_workspace(self):
         self._work = None
         self._saved_id = -1

@@ -183,6 +183,10 @@ def test_stored_segments_graph_replays(sw):
     g0 = eager.backward(r).clone()
     gp = case.plan()
     gp.set_tuning(rz=8, use_graph=1, keep_b=3)
+    # the workspace, stored segments included, allocated ahead of the first
+    # forward and used as it is by every call
+    assert gp.reserve_workspace(True) == gp.workspace_bytes(True)
+    block = gp._work.data_ptr()
     v, w = _dev(case.v), _dev(case.wav)
     out, grad = torch.empty_like(d0), torch.empty_like(g0)
     for rep in range(3):
@@ -191,6 +195,7 @@ def test_stored_segments_graph_replays(sw):
         torch.cuda.synchronize()
         assert torch.equal(out, d0), rep
         assert torch.equal(grad, g0), rep
+        assert gp._work.data_ptr() == block
         assert torch.isfinite(torch.randn(4096, device="cuda").sum())
 
 
