@@ -15,6 +15,7 @@ cells counted; recomputation is overhead, not work). Prints one JSON line.
 from __future__ import annotations
 
 import argparse
+import gc
 import json
 import os
 import sys
@@ -97,31 +98,47 @@ def cpu_baseline(w, max_seconds=30.0):
                       f"{t:.1f} s wall"}
 
 
-def fit_keep_b(torch, plan, nshots, nt, ckpt, reserve=8 << 30):
+FIT_LOG = []  # one entry per fit_keep_b call, reported with the results
+
+
+def fit_keep_b(torch, plan, nt, ckpt, reserve=8 << 30):
     """Use the HBM: store B'^n of as many checkpoint segments as the free
     memory holds after the rest of the workspace and `reserve` bytes for the
     gathers, residuals and temporaries, so that the backward recomputes only
     the others. The workspace is allocated here; on an allocation failure the
     count steps down. Returns the count set on the plan."""
-    NX, NZ = plan.padded()
     t = dict(plan.tuning)
+    nseg = -(-nt // ckpt)
+    t["keep_b"] = nseg
+    plan.set_tuning(**t)
+    ws_all = plan.workspace_bytes(True)
     t["keep_b"] = 0
     plan.set_tuning(**t)
-    seg = ckpt * nshots * NX * NZ * 4
-    nseg = -(-nt // ckpt)
+    ws_none = plan.workspace_bytes(True)
+    # a stored segment costs its B'^n planes less the checkpoint it no longer needs
+    seg = max(1, (ws_all - ws_none) // nseg)
     plan.release_workspace()
+    gc.collect()
+    torch.cuda.synchronize()
     torch.cuda.empty_cache()
     free, _ = torch.cuda.mem_get_info()
-    keep = int(max(0, min(nseg, (free - plan.workspace_bytes(True) - reserve) // seg)))
+    keep = int(max(0, min(nseg, (free - ws_none - reserve) // seg)))
+    log = {"free_GiB": round(free / 2**30, 1),
+           "torch_reserved_GiB": round(torch.cuda.memory_reserved() / 2**30, 1),
+           "torch_allocated_GiB": round(torch.cuda.memory_allocated() / 2**30, 1),
+           "first_try": keep, "failed_tries": 0}
+    FIT_LOG.append(log)
     while True:
         t["keep_b"] = keep
         plan.set_tuning(**t)
         try:
             plan.reserve_workspace(True)
+            log["keep_b"] = keep
             return keep
         except torch.OutOfMemoryError:
             plan.release_workspace()
             torch.cuda.empty_cache()
+            log["failed_tries"] += 1
             if keep == 0:
                 raise
             keep = max(0, keep - 2)
@@ -282,7 +299,7 @@ def born_modelling(sw, torch, case, w, v_true, v0, wav):
 
     born()
     _, t_born = _sync_time(torch, born)
-    keep = fit_keep_b(torch, plan, w.nshots, w.nt, w.ckpt_every)
+    keep = fit_keep_b(torch, plan, w.nt, w.ckpt_every)
 
     def lsrtm():
         dd = plan.born(v0, dv, wav)
@@ -321,7 +338,7 @@ def encoded_gradient(sw, torch, nsuper=8):
     v_true = torch.tensor(case.v, dtype=torch.float32, device="cuda")
     v0 = torch.tensor(synth.smooth(case.v, 20.0), dtype=torch.float32, device="cuda")
     d_obs = plan.forward(v_true, wav).clone()
-    keep = fit_keep_b(torch, plan, nsuper, w.nt, w.ckpt_every)
+    keep = fit_keep_b(torch, plan, w.nt, w.ckpt_every)
 
     def grad():
         d = plan.forward(v0, wav, save=True)
@@ -460,11 +477,6 @@ def main():
     plan = case.plan()
     plan.set_tuning(rz=args.rz, pml_rz=args.pml_rz, tblock=args.tblock)
     NX, NZ = plan.padded()
-    if args.keep_b < 0:
-        keep = fit_keep_b(torch, plan, w.nshots, w.nt, w.ckpt_every)
-    else:
-        keep = args.keep_b
-        plan.set_tuning(rz=args.rz, pml_rz=args.pml_rz, tblock=args.tblock, keep_b=keep)
     v_true = torch.tensor(case.v, dtype=torch.float32, device=dev)
     v0 = torch.tensor(synth.smooth(case.v, 20.0), dtype=torch.float32, device=dev)
     wav = torch.tensor(case.wav, dtype=torch.float32, device=dev)
@@ -473,6 +485,13 @@ def main():
     obs_plan.release_workspace()
     del obs_plan
     torch.cuda.synchronize()
+    # the workspace is reserved after the inputs so that, once released, its
+    # segment holds no other tensor and goes back to the device
+    if args.keep_b < 0:
+        keep = fit_keep_b(torch, plan, w.nt, w.ckpt_every)
+    else:
+        keep = args.keep_b
+        plan.set_tuning(rz=args.rz, pml_rz=args.pml_rz, tblock=args.tblock, keep_b=keep)
 
     def step():
         d = plan.forward(v0, wav, save=True)
@@ -601,6 +620,7 @@ def main():
         torch.cuda.empty_cache()
         out["acoustic_vd"] = acoustic_vd_gradient(sw, torch)
         out["mlp"] = mlp_throughput(torch)
+    out["keep_b_fits"] = FIT_LOG
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)

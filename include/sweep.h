@@ -96,9 +96,12 @@ typedef struct {
   int keep_b;      /* acoustic plans (not batches): the saving forward stores B'^n
                       of the last keep_b checkpoint segments in the workspace, and
                       backward() reverses those segments without recomputing them
-                      (the same bits). Costs keep_b * ckpt_every * nshots * NX *
-                      NZ * 4 more workspace bytes (sweep_plan_workspace_bytes
-                      includes them); 0 = recompute every segment (default) */
+                      (the same bits). A stored segment needs no checkpoint, so
+                      each one costs ckpt_every * nshots * NX * NZ * 4 workspace
+                      bytes less its checkpoint slot (2 * nshots * NX * NZ
+                      fields plus the C-PML memory variables, 4 bytes each);
+                      sweep_plan_workspace_bytes includes this. 0 = recompute
+                      every segment (default) */
 } sweep_tuning;
 
 typedef struct sweep_plan sweep_plan;

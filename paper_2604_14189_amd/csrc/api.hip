@@ -213,14 +213,15 @@ void ac_layout(const sweep_plan* p, AcLayout& L, bool keep) {
   const int k = p->ckpt;
   L.nseg = (p->pb.nt + k - 1) / k;
   L.slot_elems = 2 * ns * plane + L.aux_elems;
-  L.ck = c.take((size_t)L.nseg * L.slot_elems * f);
+  // a stored segment is never recomputed, so only the others need a checkpoint
+  L.nkeep = keep ? std::min(std::max(p->tune.keep_b, 0), L.nseg) : 0;
+  L.ck = c.take((size_t)(L.nseg - L.nkeep) * L.slot_elems * f);
   L.Bseg = c.take((size_t)k * ns * plane * f);
   for (int i = 0; i < 4; ++i) L.lf[i] = c.take(ns * plane * f);
   L.adjaux[0] = c.take(L.aux_elems * f);
   L.adjaux[1] = c.take(L.aux_elems * f);
   L.gpart = c.take(ns * plane * f);
   L.tot = c.take(plane * sizeof(double));
-  L.nkeep = keep ? std::min(std::max(p->tune.keep_b, 0), L.nseg) : 0;
   L.Bkeep = c.take((size_t)L.nkeep * k * ns * plane * f);
   L.bwd_end = c.off;
 }
@@ -491,7 +492,8 @@ int ac_forward_enqueue(sweep_plan* p, const float* model, const float* wavelet, 
   const int nt = p->pb.nt, k = p->ckpt;
   const bool two = ac_two_steps(p);
   for (int n = 0; n < nt;) {
-    if (save && n % k == 0 && (rc = ac_checkpoint(p, work, L, n, s))) return rc;
+    if (save && n % k == 0 && !ac_kept(L, n / k) && (rc = ac_checkpoint(p, work, L, n, s)))
+      return rc;
     // steps of a stored segment also write B'^n (timed with the recomputation,
     // whose launches they are)
     const int sg = n / k, m = n - sg * k;
