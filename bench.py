@@ -35,9 +35,9 @@ METRIC = "Gcell-updates/s fwd+adj; batched vs per-shot FWI gradient time at 1e-4
 # for a plain device copy of known size (--calibrate-copy). Keyed by kernel
 # class; valid only while the kernel source hashes to the recorded value.
 TRAFFIC = {
-    "adj_deep": {"bytes_per_launch": 605589419, "source": "ca308c7fec215422"},
-    "adj_zpml": {"bytes_per_launch": 293403827, "source": "ca308c7fec215422"},
-    "adj_xpml": {"bytes_per_launch": 129796649, "source": "ca308c7fec215422"},
+    "adj_deep": {"bytes_per_launch": 605979136, "source": "ca308c7fec215422"},
+    "adj_zpml": {"bytes_per_launch": 293570070, "source": "ca308c7fec215422"},
+    "adj_xpml": {"bytes_per_launch": 129839843, "source": "ca308c7fec215422"},
 }
 
 
