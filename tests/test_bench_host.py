@@ -1,0 +1,106 @@
+"""Host logic of the benchmark (no GPU): how many checkpoint segments it
+stores for a plan, and its refusal of more than one GPU.
+
+The workspace sizes come from the C library's host-side layout; the device
+calls (free memory, allocation) are stand-ins, so the sizing and the
+step-down after an allocation failure are checked exactly.
+"""
+import os
+import subprocess
+import sys
+import types
+
+import pytest
+
+torch = pytest.importorskip("torch")
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+GiB = 1 << 30
+
+
+@pytest.fixture(scope="module")
+def bench():
+    import paper_2604_14189_amd as sw
+    sw.lib()  # the plan's host-side layout comes from the built library
+    sys.path.insert(0, ROOT)
+    import bench as b
+    return b
+
+
+def _plan(nshots=64):
+    import synth
+    from tests.helpers import case_from_workload
+    w = synth.workload("layered1000x300")
+    p = case_from_workload(w, shots=list(range(nshots))).plan()
+    p.set_tuning(rz=8, pml_rz=4, tblock=2)
+    return w, p
+
+
+def _fake_torch(free_bytes):
+    cuda = types.SimpleNamespace(mem_get_info=lambda: (free_bytes, free_bytes),
+                                 empty_cache=lambda: None, synchronize=lambda: None,
+                                 memory_reserved=lambda: 0, memory_allocated=lambda: 0)
+    return types.SimpleNamespace(cuda=cuda, OutOfMemoryError=torch.OutOfMemoryError)
+
+
+def test_keep_b_fills_free_memory(bench):
+    w, plan = _plan()
+    nseg = -(-w.nt // w.ckpt_every)
+    sizes = {}
+    for k in (0, nseg):
+        plan.set_tuning(rz=8, pml_rz=4, tblock=2, keep_b=k)
+        sizes[k] = plan.workspace_bytes(True)
+    net = (sizes[nseg] - sizes[0]) // nseg
+    plan.set_tuning(rz=8, pml_rz=4, tblock=2)
+    plan.reserve_workspace = lambda fb=True: plan.workspace_bytes(fb)
+    free = 287 * GiB
+    keep = bench.fit_keep_b(_fake_torch(free), plan, w.nt, w.ckpt_every)
+    # the largest count whose workspace leaves the 8 GiB reserve free
+    assert keep == (free - sizes[0] - 8 * GiB) // net
+    assert plan.tuning["keep_b"] == keep
+    assert plan.workspace_bytes(True) <= free - 8 * GiB
+    plan.set_tuning(rz=8, pml_rz=4, tblock=2, keep_b=keep + 1)
+    assert plan.workspace_bytes(True) > free - 8 * GiB
+    # a stored segment costs less than its planes: its checkpoint is dropped
+    assert net < w.ckpt_every * w.nshots * w.NX * w.NZ * 4
+
+
+def test_keep_b_caps_at_the_segment_count(bench):
+    w, plan = _plan(nshots=8)
+    plan.reserve_workspace = lambda fb=True: plan.workspace_bytes(fb)
+    keep = bench.fit_keep_b(_fake_torch(287 * GiB), plan, w.nt, w.ckpt_every)
+    assert keep == -(-w.nt // w.ckpt_every)
+
+
+def test_keep_b_steps_down_on_allocation_failure(bench):
+    w, plan = _plan()
+    tried = []
+
+    def reserve(fb=True):
+        tried.append(plan.tuning["keep_b"])
+        if len(tried) < 3:
+            raise torch.OutOfMemoryError("stand-in")
+        return plan.workspace_bytes(fb)
+
+    plan.reserve_workspace = reserve
+    keep = bench.fit_keep_b(_fake_torch(287 * GiB), plan, w.nt, w.ckpt_every)
+    assert tried == [tried[0], tried[0] - 2, tried[0] - 4] and keep == tried[0] - 4
+    assert plan.tuning["keep_b"] == keep
+
+
+def test_keep_b_gives_up_at_zero(bench):
+    w, plan = _plan()
+
+    def reserve(fb=True):
+        raise torch.OutOfMemoryError("stand-in")
+
+    plan.reserve_workspace = reserve
+    with pytest.raises(torch.OutOfMemoryError):
+        bench.fit_keep_b(_fake_torch(40 * GiB), plan, w.nt, w.ckpt_every)
+
+
+def test_bench_refuses_several_gpus():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode != 0
+    assert "one GPU" in (r.stdout + r.stderr)
