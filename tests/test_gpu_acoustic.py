@@ -199,6 +199,28 @@ def test_stored_segments_graph_replays(sw):
         assert torch.isfinite(torch.randn(4096, device="cuda").sum())
 
 
+def test_stored_segments_after_born(sw):
+    """Born modelling on a plan with stored segments (Born lays out its state
+    without them) and then a saving forward and backward on the same
+    workspace: Born gathers and gradient equal those of a plan without stored
+    segments, bit for bit."""
+    case = random_case(33, nt=120, ckpt=20)
+    v, w = _dev(case.v), _dev(case.wav)
+    dv = _dev(np.random.default_rng(3).standard_normal((case.nz, case.nx)) * 10.0)
+    r = _dev(synth.bandlimited_noise((case.nshots, case.nt, case.nrec), 15.0, case.dt, 7))
+    ref = case.plan()
+    dd0 = ref.born(v, dv, w).clone()
+    ref.forward(v, w, save=True)
+    g0 = ref.backward(r).clone()
+    p = case.plan()
+    p.set_tuning(rz=8, keep_b=4)
+    p.reserve_workspace(True)
+    assert torch.equal(p.born(v, dv, w), dd0)
+    p.forward(v, w, save=True)
+    assert torch.equal(p.backward(r), g0)
+    assert torch.any(g0 != 0)
+
+
 def test_repeatable(sw):
     case = random_case(6, nt=100, ckpt=30)
     resid = _dev(synth.bandlimited_noise((case.nshots, case.nt, case.nrec), 15.0, case.dt, 4))
