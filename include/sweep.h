@@ -93,7 +93,8 @@ typedef struct {
                       inside the grid) two time steps per pass, marching down runs of
                       them; 1 = one step per pass (default 2). In a batch each
                       plan follows its own setting */
-  int keep_b;      /* acoustic plans (not batches): the saving forward stores B'^n
+  int keep_b;      /* acoustic plans, alone or in a batch (each plan its own
+                      count): the saving forward stores B'^n
                       of the last keep_b checkpoint segments in the workspace, and
                       backward() reverses those segments without recomputing them
                       (the same bits). A stored segment needs no checkpoint, so

@@ -794,7 +794,7 @@ int batch_layouts(const sweep_batch* b, int for_backward, std::vector<AcLayout>&
   off.resize(b->plans.size());
   total = 0;
   for (size_t q = 0; q < b->plans.size(); ++q) {
-    ac_layout(b->plans[q], L[q], false);
+    ac_layout(b->plans[q], L[q]);  // with each plan's stored segments
     off[q] = total;
     total = align_up(total + (for_backward ? L[q].bwd_end : L[q].fwd_end));
   }
@@ -862,13 +862,18 @@ int batch_forward_enqueue(sweep_batch* b, const float* const* models, const floa
       const int nt = p->pb.nt, k = p->ckpt;
       if (n >= nt) continue;
       void* wq = at<char>(work, off[q]);
-      if (save && n % k == 0 && (rc = ac_checkpoint(p, wq, L[q], n, s))) return rc;
+      const int sg = n / k, m = n - sg * k;
+      const bool keepB = save && ac_kept(L[q], sg);
+      if (save && n % k == 0 && !keepB && (rc = ac_checkpoint(p, wq, L[q], n, s))) return rc;
       const bool has1 = n + 1 < std::min(nt, maxnt);
       // a pair never spans a checkpoint (the state entering step n+1 is not formed)
       if (ac_two_steps(p) && has1 && (!save || (n + 1) % k != 0)) {
-        B.add(ac_fwd_pair(p, wq, L[q], n, n % 2, gathers[q], nullptr, nullptr));
+        B.add(ac_fwd_pair(p, wq, L[q], n, n % 2, gathers[q],
+                          keepB ? ac_bseg(p, wq, L[q], sg, m) : nullptr,
+                          keepB ? ac_bseg(p, wq, L[q], sg, m + 1) : nullptr));
       } else {
-        B.s0.push_back(fwd_single_rot(p, wq, L[q], n, n % 2, gathers[q], nullptr));
+        B.s0.push_back(fwd_single_rot(p, wq, L[q], n, n % 2, gathers[q],
+                                      keepB ? ac_bseg(p, wq, L[q], sg, m) : nullptr));
         if (has1) B.later.push_back(q);
       }
     }
@@ -877,9 +882,13 @@ int batch_forward_enqueue(sweep_batch* b, const float* const* models, const floa
     for (int q : B.later) {
       sweep_plan* p = b->plans[q];
       void* wq = at<char>(work, off[q]);
-      if (save && (n + 1) % p->ckpt == 0 && (rc = ac_checkpoint(p, wq, L[q], n + 1, s)))
+      const int sg = (n + 1) / p->ckpt, m = n + 1 - sg * p->ckpt;
+      const bool keepB = save && ac_kept(L[q], sg);
+      if (save && (n + 1) % p->ckpt == 0 && !keepB &&
+          (rc = ac_checkpoint(p, wq, L[q], n + 1, s)))
         return rc;
-      B.s1.push_back(fwd_single_rot(p, wq, L[q], n + 1, (n + 1) % 2, gathers[q], nullptr));
+      B.s1.push_back(fwd_single_rot(p, wq, L[q], n + 1, (n + 1) % 2, gathers[q],
+                                    keepB ? ac_bseg(p, wq, L[q], sg, m) : nullptr));
     }
     if (!B.s1.empty() &&
         (rc = ac_launch_fwd_batch(B.s1.data(), (int)B.s1.size(), b->rz, b->prz, s)))
@@ -897,12 +906,12 @@ int batch_segment_enqueue(sweep_batch* b, const float* const* resids, void* work
   const int np = (int)b->plans.size();
   int rc;
   BatchPair B;
-  // recompute the segments, storing B^n
+  // recompute the segments, storing B^n (not those the saving forward stored)
   for (int m = 0; m < lenmax; m += 2) {
     B.clear();
     for (int q = 0; q < np; ++q) {
       const int len = n1[q] - n0[q];
-      if (m >= len) continue;
+      if (m >= len || ac_kept(L[q], n0[q] / b->plans[q]->ckpt)) continue;
       sweep_plan* p = b->plans[q];
       void* wq = at<char>(work, off[q]);
       const size_t ns = p->pb.nshots;
@@ -980,7 +989,8 @@ int batch_backward_enqueue(sweep_batch* b, const float* const* resids, float* co
       n0[q] = sg * p->ckpt;
       n1[q] = std::min(p->pb.nt, n0[q] + p->ckpt);
       lenmax = std::max(lenmax, n1[q] - n0[q]);
-      if ((rc = ac_bwd_restore(p, at<char>(work, off[q]), L[q], sg, s))) return rc;
+      if (!ac_kept(L[q], sg) && (rc = ac_bwd_restore(p, at<char>(work, off[q]), L[q], sg, s)))
+        return rc;
     }
     if ((rc = batch_segment_enqueue(b, resids, work, L, off, n0, n1, lenmax, s))) return rc;
     for (int q = 0; q < np; ++q)

@@ -107,3 +107,25 @@ def test_stored_segments_workspace_accounting(lib):
         assert plan.tuning["keep_b"] == keep
     with pytest.raises(sw.SweepError):
         plan.set_tuning(keep_b=-1)
+
+
+def test_batch_stored_segments_workspace_accounting(lib):
+    """A batch lays out each plan with that plan's stored segments: its
+    backward workspace grows by exactly what each plan's own grows by, and
+    its forward part is unchanged (host-side layout, no GPU)."""
+    import paper_2604_14189_amd as sw
+    from tests.helpers import random_case
+    cases = [random_case(51, nx=300, nz=200, nt=101, nshots=2, nrec=6, ckpt=17),
+             random_case(52, nx=260, nz=150, nt=76, nshots=3, nrec=5, ckpt=25),
+             random_case(53, nx=120, nz=90, nt=90, nshots=2, nrec=4, ckpt=50)]
+    plans = [c.plan() for c in cases]
+    base, fbase = sw.Batch(plans).workspace_bytes(True), sw.Batch(plans).workspace_bytes(False)
+    want = 0
+    for p, keep in zip(plans, (2, 99, 0)):
+        w0 = p.workspace_bytes(True)
+        p.set_tuning(keep_b=keep)
+        want += p.workspace_bytes(True) - w0
+    b = sw.Batch(plans)
+    assert want > 0
+    assert b.workspace_bytes(True) - base == want
+    assert b.workspace_bytes(False) == fbase

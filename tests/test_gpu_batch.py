@@ -97,6 +97,35 @@ def test_batch_two_step_passes(sw):
         assert torch.equal(gs[q], ref[q][1]), q
 
 
+@pytest.mark.parametrize("graph", [False, True])
+def test_batch_stored_segments(sw, graph):
+    """Stored B'^n segments in a batch, each plan with its own count (some,
+    all, none; ragged last segments), with two-step passes and with graph
+    replays: gathers and gradients are bitwise those of each plan alone
+    recomputing every segment."""
+    cases = [random_case(51, nx=300, nz=200, nt=101, nshots=2, nrec=6, ckpt=17),
+             random_case(52, nx=260, nz=150, nt=76, nshots=3, nrec=5, ckpt=25),
+             random_case(53, nx=120, nz=90, nt=90, nshots=2, nrec=4, ckpt=50),
+             random_case(21, nx=150, nz=77, nt=130, nshots=3, ckpt=17)]
+    resids = _resids(cases)
+    ref = _single(cases, resids)
+    plans = [c.plan() for c in cases]
+    base = sw.Batch(plans).workspace_bytes(True)
+    for p, keep in zip(plans, (2, 99, 0, 3)):
+        p.set_tuning(rz=4, pml_rz=4, tblock=2, keep_b=keep)
+    assert sum(p.tiles()["deep"] > 0 for p in plans) >= 2
+    batch = sw.Batch(plans, use_graph=graph)
+    assert batch.workspace_bytes(True) > base
+    for rep in range(3 if graph else 1):
+        ds = batch.forward([_dev(c.v) for c in cases], [_dev(c.wav) for c in cases], save=True)
+        gs = batch.backward(resids)
+        torch.cuda.synchronize()
+        for q in range(len(cases)):
+            assert torch.equal(ds[q], ref[q][0]), (rep, q)
+            assert torch.equal(gs[q], ref[q][1]), (rep, q)
+        _ = (torch.randn(1000, device="cuda") * 2).sum().item()
+
+
 def test_batch_autotune_picks_and_caches(sw, tmp_path):
     """The batch autotuner sets one tuning on every plan, caches it under the
     batch's shapes, and the results keep the bits of single-step plans."""
