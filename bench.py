@@ -144,6 +144,52 @@ def fit_keep_b(torch, plan, nt, ckpt, reserve=8 << 30):
             keep = max(0, keep - 2)
 
 
+def fit_batch_keep_b(torch, batch, plans, nsegs, reserve=8 << 30):
+    """Stored segments for a batch: every plan stores the same fraction of its
+    checkpoint segments (rounded down), the largest fraction whose workspace
+    leaves `reserve` bytes of the free memory. The workspace is allocated
+    here; on an allocation failure the fraction steps down. Returns the
+    per-plan counts."""
+    tun = [dict(p.tuning) for p in plans]
+
+    def ws_at(f):
+        for p, t, ns in zip(plans, tun, nsegs):
+            t["keep_b"] = int(f * ns)
+            p.set_tuning(**t)
+        return batch.workspace_bytes(True)
+
+    batch._work = None
+    gc.collect()
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    free, _ = torch.cuda.mem_get_info()
+    lo, hi = 0.0, 1.0
+    if ws_at(1.0) <= free - reserve:
+        lo = 1.0
+    else:
+        for _ in range(30):
+            mid = 0.5 * (lo + hi)
+            lo, hi = (mid, hi) if ws_at(mid) <= free - reserve else (lo, mid)
+    log = {"batch": True, "free_GiB": round(free / 2**30, 1), "first_fraction": round(lo, 4),
+           "failed_tries": 0}
+    FIT_LOG.append(log)
+    f = lo
+    while True:
+        need = ws_at(f)
+        try:
+            batch._work = torch.empty(need, dtype=torch.uint8, device="cuda")
+            break
+        except torch.OutOfMemoryError:
+            batch._work = None
+            torch.cuda.empty_cache()
+            log["failed_tries"] += 1
+            if f == 0.0:
+                raise
+            f = max(0.0, f - 0.05)
+    log["keep_b"] = [p.tuning["keep_b"] for p in plans]
+    return log["keep_b"]
+
+
 def per_shot_compare(sw, torch, w, v0, wav, d_obs, nsample, tuning, t_batched):
     """The same FWI gradient through the per-shot path: one single-shot plan
     per shot, its kernels launched once per shot per step (no batching, no
@@ -225,9 +271,10 @@ def batched_uneven(sw, torch, tuning=None):
     if tuning is None:
         ch = batch.autotune(v0s, wavs, steps=20)
         tuning = (ch["rz"], ch["pml_rz"], 0, ch["tblock"])
-    # the workspace is allocated before timing (inputs and state resident in HBM)
-    batch._work = None
-    batch._work = torch.empty(batch.workspace_bytes(True), dtype=torch.uint8, device="cuda")
+    # the workspace, with as many stored segments as fit, is allocated before
+    # timing (inputs and state resident in HBM)
+    nsegs = [-(-w.nt // w.ckpt_every) for w in ws]
+    keeps = fit_batch_keep_b(torch, batch, plans, nsegs)
 
     def grad():
         ds = batch.forward(v0s, wavs, save=True)
@@ -237,10 +284,10 @@ def batched_uneven(sw, torch, tuning=None):
     _, t_batch = _sync_time(torch, grad)
     batch._work = None
     t_shot = 0.0
-    for w, v0, wav, do in zip(ws, v0s, wavs, dobs):
+    for w, v0, wav, do, nseg in zip(ws, v0s, wavs, dobs, nsegs):
         s = w.nshots // 2
         p1 = case_from_workload(w, shots=[s]).plan()
-        p1.set_tuning(*tuning)
+        p1.set_tuning(*tuning, keep_b=nseg)  # one shot's planes all fit
 
         def one():
             d = p1.forward(v0, wav[s:s + 1], save=True)
@@ -255,6 +302,7 @@ def batched_uneven(sw, torch, tuning=None):
             "batched_Gcell_per_s": round(cells / t_batch / 1e9, 2),
             "per_shot_gradient_s_est": round(t_shot, 3), "speedup": round(t_shot / t_batch, 2),
             "tuning": {"rz": tuning[0], "pml_rz": tuning[1], "tblock": tuning[3]},
+            "keep_b": keeps, "segments": nsegs,
             "per_shot_sample": "middle shot of each model, scaled by its shot count"}
 
 
