@@ -482,8 +482,8 @@ def main():
                     help="only run a 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU shot "
-                          "partitioning is described in DESIGN.md but not implemented",
+        print(json.dumps({"error": "this benchmark runs on one GPU only; partitioning "
+                          "the shots over several GPUs is not implemented",
                           "n_gpus": args.gpus}))
         sys.exit(2)
 
