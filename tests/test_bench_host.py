@@ -104,3 +104,63 @@ def test_bench_refuses_several_gpus():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode != 0
     assert "one GPU" in (r.stdout + r.stderr)
+
+
+class _FakeAlloc:
+    """torch stand-in whose allocations fail above `limit` bytes."""
+
+    def __init__(self, free_bytes, limit):
+        self.OutOfMemoryError = torch.OutOfMemoryError
+        self.uint8 = torch.uint8
+        self.cuda = _fake_torch(free_bytes).cuda
+        self.limit, self.tried = limit, []
+
+    def empty(self, n, dtype=None, device=None):
+        self.tried.append(n)
+        if n > self.limit:
+            raise torch.OutOfMemoryError("stand-in")
+        return types.SimpleNamespace(numel=lambda: n)
+
+
+def _batch():
+    import paper_2604_14189_amd as sw
+    import synth
+    from tests.helpers import case_from_workload
+    ws = synth.batched_workloads()
+    plans = [case_from_workload(w).plan() for w in ws]
+    return ws, plans, sw.Batch(plans), [-(-w.nt // w.ckpt_every) for w in ws]
+
+
+def test_batch_keep_b_same_fraction_that_fits(bench):
+    ws, plans, batch, nsegs = _batch()
+    free = 280 * GiB
+    t = _FakeAlloc(free, limit=free)
+    keeps = bench.fit_batch_keep_b(t, batch, plans, nsegs)
+    need = batch.workspace_bytes(True)
+    assert need <= free - 8 * GiB and t.tried == [need]
+    assert keeps == [p.tuning["keep_b"] for p in plans]
+    assert all(0 < k < n for k, n in zip(keeps, nsegs))
+    # one common fraction f (logged to 4 digits): each count is floor(f * nseg)
+    f = bench.FIT_LOG[-1]["first_fraction"]
+    assert all(abs(k - f * n) <= 1 for k, n in zip(keeps, nsegs))
+    # a slightly larger fraction would not fit
+    for p, n in zip(plans, nsegs):
+        p.set_tuning(**dict(p.tuning, keep_b=int((f + 0.01) * n)))
+    assert batch.workspace_bytes(True) > free - 8 * GiB
+
+
+def test_batch_keep_b_all_when_it_fits(bench):
+    ws, plans, batch, nsegs = _batch()
+    keeps = bench.fit_batch_keep_b(_FakeAlloc(4096 * GiB, 4096 * GiB), batch, plans, nsegs)
+    assert keeps == nsegs
+
+
+def test_batch_keep_b_steps_down_on_allocation_failure(bench):
+    ws, plans, batch, nsegs = _batch()
+    free = 280 * GiB
+    t = _FakeAlloc(free, limit=200 * GiB)
+    keeps = bench.fit_batch_keep_b(t, batch, plans, nsegs)
+    assert len(t.tried) > 1 and t.tried[-1] <= 200 * GiB < t.tried[0]
+    assert batch.workspace_bytes(True) == t.tried[-1]
+    assert bench.FIT_LOG[-1]["failed_tries"] == len(t.tried) - 1
+    assert keeps == [p.tuning["keep_b"] for p in plans]
