@@ -319,6 +319,7 @@ def elastic_gradient(sw, torch):
     d_obs = plan.forward(m_true, wav).clone()
     m0 = torch.tensor(np.stack([synth.smooth(c, 20.0) for c in case.model]), dtype=torch.float32,
                       device="cuda")
+    keep = fit_keep_b(torch, plan, w.nt, w.ckpt_every)
 
     def grad():
         d = plan.forward(m0, wav, save=True)
@@ -330,7 +331,8 @@ def elastic_gradient(sw, torch):
     cells = 2.0 * w.nshots * NX * NZ * w.nt
     plan.release_workspace()
     return {"workload": "elastic600x300", "padded": f"{NX}x{NZ}", "shots": w.nshots,
-            "nt": w.nt, "gradient_s": round(t, 3), "Gcell_per_s": round(cells / t / 1e9, 2)}
+            "nt": w.nt, "keep_b": keep, "gradient_s": round(t, 3),
+            "Gcell_per_s": round(cells / t / 1e9, 2)}
 
 
 def born_modelling(sw, torch, case, w, v_true, v0, wav):
@@ -417,6 +419,7 @@ def acoustic_vd_gradient(sw, torch):
                    ckpt_every=w.ckpt_every, physics=sw.ACOUSTIC_VD)
     wav = torch.tensor(w.wavelets(np.float32), device="cuda")
     d_obs = plan.forward(model, wav).clone()
+    keep = fit_keep_b(torch, plan, w.nt, w.ckpt_every)
 
     def grad():
         d = plan.forward(m0, wav, save=True)
@@ -428,7 +431,7 @@ def acoustic_vd_gradient(sw, torch):
     plan.release_workspace()
     cells = 2.0 * w.nshots * NX * NZ * w.nt
     return {"workload": "layered1000x300, rho = 310 vp^0.25", "shots": w.nshots, "nt": w.nt,
-            "gradient_s": round(t, 3), "Gcell_per_s": round(cells / t / 1e9, 2)}
+            "keep_b": keep, "gradient_s": round(t, 3), "Gcell_per_s": round(cells / t / 1e9, 2)}
 
 
 def mlp_throughput(torch):

@@ -93,16 +93,18 @@ typedef struct {
                       inside the grid) two time steps per pass, marching down runs of
                       them; 1 = one step per pass (default 2). In a batch each
                       plan follows its own setting */
-  int keep_b;      /* acoustic plans, alone or in a batch (each plan its own
-                      count): the saving forward stores B'^n
-                      of the last keep_b checkpoint segments in the workspace, and
-                      backward() reverses those segments without recomputing them
-                      (the same bits). A stored segment needs no checkpoint, so
-                      each one costs ckpt_every * nshots * NX * NZ * 4 workspace
-                      bytes less its checkpoint slot (2 * nshots * NX * NZ
-                      fields plus the C-PML memory variables, 4 bytes each);
-                      sweep_plan_workspace_bytes includes this. 0 = recompute
-                      every segment (default) */
+  int keep_b;      /* every physics; in a batch each plan its own count: the
+                      saving forward stores what the backward needs of the last
+                      keep_b checkpoint segments in the workspace, and backward()
+                      reverses those segments without recomputing them (the
+                      same bits). Acoustic: B'^n, and a stored segment needs no
+                      checkpoint, so each one costs ckpt_every * nshots * NX *
+                      NZ * 4 workspace bytes less its checkpoint slot (2 *
+                      nshots * NX * NZ fields plus the C-PML memory variables,
+                      4 bytes each). Elastic and variable-density acoustic: the
+                      five trace planes of each step, ckpt_every * 5 * nshots *
+                      NX * NZ * 4 bytes per segment. sweep_plan_workspace_bytes
+                      includes this. 0 = recompute every segment (default) */
 } sweep_tuning;
 
 typedef struct sweep_plan sweep_plan;

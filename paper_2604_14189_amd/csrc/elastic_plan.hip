@@ -117,10 +117,25 @@ void el_layout(const sweep_plan* p, ElLayout& L) {
   L.adj = take(off, kAdjPlanes * ns * plane * f);
   L.gpart = take(off, kGradPlanes * ns * plane * f);
   L.tot = take(off, kGradPlanes * plane * sizeof(double));
+  // stored segments: the traces of the last keep_b segments, written by the
+  // saving forward so that the backward does not recompute those segments
+  L.nkeep = std::min(std::max(p->tune.keep_b, 0), L.nseg);
+  L.trkeep = take(off, (size_t)L.nkeep * k * kTracePlanes * ns * plane * f);
   L.bwd_end = off;
 }
 
 namespace {
+
+bool el_kept(const ElLayout& L, int sg) { return sg >= L.nseg - L.nkeep; }
+
+// Trace plane q of step m of segment sg: its stored block for a stored
+// segment, else the one segment buffer that the recomputation fills.
+float* el_trace(void* work, const ElLayout& L, size_t nsplane, int k, int sg, int m, int q) {
+  if (el_kept(L, sg))
+    return at<float>(work, L.trkeep) +
+           (((size_t)(sg - (L.nseg - L.nkeep)) * k + m) * kTracePlanes + q) * nsplane;
+  return at<float>(work, L.trace) + ((size_t)m * kTracePlanes + q) * nsplane;
+}
 
 ElCoef coef_ptrs(const sweep_plan* p, void* work, const ElLayout& L) {
   ElCoef c;
@@ -241,7 +256,14 @@ int el_forward(sweep_plan* p, const float* model, const float* wavelet, float* g
         return rc;
     ElStep a = base;
     a.n = n;
-    if ((rc = el_launch_fwd(a, s, p->timer.take(kFwdInt, -1, -1)))) return rc;
+    // steps of a stored segment also write its traces (timed with the
+    // recomputation, whose work they do)
+    const int sg = n / k;
+    const bool keepT = save && el_kept(L, sg);
+    if (keepT)
+      for (int q = 0; q < kTracePlanes; ++q)
+        a.tr[q] = el_trace(work, L, nsplane, k, sg, n - sg * k, q);
+    if ((rc = el_launch_fwd(a, s, p->timer.take(keepT ? kRecInt : kFwdInt, -1, -1)))) return rc;
   }
   p->saved = save != 0;
   p->saved_work = work;
@@ -291,10 +313,12 @@ int el_backward(sweep_plan* p, const float* resid, float* grad, void* work, size
 
   for (int sg = L.nseg - 1; sg >= 0; --sg) {
     const int n0 = sg * k, n1 = std::min(nt, n0 + k);
-    if ((rc = launch_copy(st, ck + (size_t)sg * kStatePlanes * nsplane, kStatePlanes * nsplane,
+    // a stored segment's traces were written by the forward: nothing to recompute
+    if (!el_kept(L, sg) &&
+        (rc = launch_copy(st, ck + (size_t)sg * kStatePlanes * nsplane, kStatePlanes * nsplane,
                           s)))
       return rc;
-    for (int n = n0; n < n1; ++n) {
+    for (int n = n0; n < n1 && !el_kept(L, sg); ++n) {
       ElStep a = fbase;
       a.n = n;
       for (int q = 0; q < kTracePlanes; ++q)
@@ -310,7 +334,7 @@ int el_backward(sweep_plan* p, const float* resid, float* grad, void* work, size
         a.ps_out[q] = psbuf[(it + 1) % 2] + q * nsplane;
       }
       for (int q = 0; q < kTracePlanes; ++q)
-        a.trc[q] = tr + ((size_t)(n - n0) * kTracePlanes + q) * nsplane;
+        a.trc[q] = el_trace(work, L, nsplane, k, sg, n - n0, q);
       a.g_init = (n == n1 - 1);
       if ((rc = el_launch_adj(a, s, p->timer.take(kAdjInt, -1, -1)))) return rc;
     }

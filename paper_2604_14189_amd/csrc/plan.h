@@ -79,6 +79,8 @@ struct ElLayout {
   size_t fwd_end;
   int nseg;
   size_t ck, trace, adj, gpart, tot;
+  int nkeep;      // checkpoint segments (the last ones) whose traces the forward stores
+  size_t trkeep;  // their traces: [nkeep][k][5][nshots][NZ][NX]
   size_t bwd_end;
 };
 }  // namespace sweep

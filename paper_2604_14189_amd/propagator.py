@@ -113,9 +113,11 @@ class Plan:
         """rz: rows per thread of the interior kernel (tiles of 64 x 4 rz);
         pml_rz: rows per thread of the C-PML kernels (<= rz, default min(4, rz));
         tblock: time steps per pass over the deep interior tiles (1 or 2);
-        keep_b: checkpoint segments (the last ones) whose B'^n the saving
-        forward stores, so that backward() does not recompute them (more
-        workspace, the same bits; in a Batch each plan keeps its own count)."""
+        keep_b: checkpoint segments (the last ones) whose backward inputs
+        (acoustic: B'^n; elastic and variable density: the five trace planes)
+        the saving forward stores, so that backward() does not recompute them
+        (more workspace, the same bits; in a Batch each plan keeps its own
+        count)."""
         t = Tuning(rz, min(4, rz) if pml_rz is None else pml_rz, use_graph, tblock, keep_b)
         check(lib().sweep_plan_set_tuning(self._h, ctypes.byref(t)))
         self._saved_id = -1

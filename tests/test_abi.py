@@ -129,3 +129,20 @@ def test_batch_stored_segments_workspace_accounting(lib):
     assert want > 0
     assert b.workspace_bytes(True) - base == want
     assert b.workspace_bytes(False) == fbase
+
+
+def test_elastic_stored_segments_workspace_accounting(lib):
+    """Elastic plans store the five trace planes of each stored segment:
+    keep_b * ckpt * 5 * nshots * NX * NZ floats more backward workspace, the
+    forward part unchanged (host-side layout, no GPU)."""
+    from tests.helpers import random_el_case
+    c = random_el_case(5, fs=1, nt=300, ckpt=23)
+    p = c.plan()
+    NX, NZ = p.padded()
+    w0, f0 = p.workspace_bytes(True), p.workspace_bytes(False)
+    nseg = -(-c.nt // c.ckpt)
+    for keep in (2, nseg, nseg + 3):
+        p.set_tuning(keep_b=keep)
+        want = min(keep, nseg) * c.ckpt * 5 * c.nshots * NX * NZ * 4
+        assert abs(p.workspace_bytes(True) - w0 - want) < 4096, keep
+        assert p.workspace_bytes(False) == f0

@@ -108,3 +108,22 @@ def test_full_size_elastic_sampled_shot(sw):
     print("full-size elastic shot", s, "traces", e_d, "grad", errs, flush=True)
     assert e_d <= SEIS_TOL
     assert max(errs) <= GRAD_TOL
+
+
+@pytest.mark.parametrize("fs,keep", [(1, 3), (0, 99)])
+def test_stored_segments_bitwise(sw, fs, keep):
+    """Stored traces of the last `keep` checkpoint segments (some, or all of
+    them; a ragged last segment): the backward reverses them without
+    recomputing, and gathers and gradients equal those of the plan that
+    recomputes every segment, bit for bit."""
+    case = random_el_case(6, fs=fs, nt=250, ckpt=23)
+    m, w = _dev(case.model), _dev(case.wav)
+    ref = case.plan()
+    d0 = ref.forward(m, w, save=True).clone()
+    r = _dev(np.random.default_rng(11).standard_normal(tuple(d0.shape)))
+    g0 = ref.backward(r).clone()
+    p = case.plan()
+    p.set_tuning(keep_b=keep)
+    assert torch.equal(p.forward(m, w, save=True), d0)
+    assert torch.equal(p.backward(r), g0)
+    assert all(torch.any(g0[i] != 0) for i in range(3))
