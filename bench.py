@@ -70,7 +70,7 @@ def cpu_baseline(w, max_seconds=30.0):
     `ns` shots (one per host thread) for `nt_s` of the steps, forward + gradient,
     in the metric's unit (fwd+adj Gcell-updates/s)."""
     import oracle
-    from tests.helpers import case_from_workload, f32
+    from synth.cases import case_from_workload, f32
     import synth
 
     oracle.lib()
@@ -197,7 +197,7 @@ def per_shot_compare(sw, torch, w, v0, wav, d_obs, nsample, tuning, t_batched):
     shots. A single shot's B'^n planes fit in HBM many times over, so each
     single-shot plan stores them for all its segments. Also checks that the
     per-shot gradients sum to the batched gradient of the same shots."""
-    from tests.helpers import case_from_workload
+    from synth.cases import case_from_workload
     shots = sorted(set(np.linspace(0, w.nshots - 1, nsample).round().astype(int).tolist()))
     cs = case_from_workload(w, shots=shots)
     bp = cs.plan()
@@ -252,7 +252,7 @@ def batched_uneven(sw, torch, tuning=None):
     `tuning` (rz, pml_rz, use_graph, tblock) is given; the per-shot plans use the
     same."""
     import synth
-    from tests.helpers import case_from_workload
+    from synth.cases import case_from_workload
     ws = synth.batched_workloads()
     plans, v0s, wavs, dobs = [], [], [], []
     for w in ws:
@@ -310,7 +310,7 @@ def elastic_gradient(sw, torch):
     """Elastic velocity-stress FWI gradient (vp, vs, rho) on the 600x300
     free-surface workload: 32 shots, 4000 steps, checkpoints every 50."""
     import synth
-    from tests.helpers import el_case_from_workload
+    from synth.cases import el_case_from_workload
     w = synth.workload("elastic600x300")
     case = el_case_from_workload(w)
     plan = case.plan()
@@ -374,7 +374,7 @@ def encoded_gradient(sw, torch, nsuper=8):
     (every receiver of the line records every supershot), 3000 steps. One FWI
     gradient (observed data: the same encoding on the true model)."""
     import synth
-    from tests.helpers import case_from_workload
+    from synth.cases import case_from_workload
     w = synth.workload(WORKLOAD)
     case = case_from_workload(w)
     k = w.nshots // nsuper
@@ -497,7 +497,7 @@ def main():
     import torch
     import paper_2604_14189_amd as sw
     import synth
-    from tests.helpers import case_from_workload
+    from synth.cases import case_from_workload
 
     if args.only:
         if args.only == "born":

@@ -82,28 +82,29 @@ def forward(theta, gamma, vmin=1500.0, vscale=3200.0, emulate=True):
     return vmin + vscale * s, {"hs": hs, "y": y, "s": s}
 
 
-def backward(theta, cache, dv, vscale=3200.0, emulate=True):
+def backward(theta, cache, dv, vscale=3200.0, emulate=True, return_dz=False):
     """Gradient of sum(dv * v) with respect to the parameter vector.
 
-    cache may carry "dz": the four pre-activation gradients of hidden layers
-    1..4, used as given instead of being recomputed (to take the same bf16
-    rounding decisions as another implementation)."""
+    With return_dz, also returns the four pre-activation gradients of hidden
+    layers 1..4 (as stored: bf16-rounded when emulating)."""
     r = bf16 if emulate else (lambda a: np.asarray(a, dtype=np.float64))
     p = unpack(theta)
     hs, s = cache["hs"], cache["s"]
-    given = cache.get("dz")
     grads = [None] * len(p)
+    dzs = [None] * DEPTH
     dy = np.asarray(dv, dtype=np.float64) * vscale * s * (1.0 - s)
     w5 = r(p[2 * DEPTH])
     grads[2 * DEPTH] = hs[DEPTH].T @ dy
     grads[2 * DEPTH + 1] = np.array([dy.sum()])
-    dz = given[DEPTH - 1] if given else r(np.outer(dy, w5) * (hs[DEPTH] > 0))
+    dz = r(np.outer(dy, w5) * (hs[DEPTH] > 0))
     for l in range(DEPTH - 1, -1, -1):
+        dzs[l] = dz
         grads[2 * l] = dz.T @ hs[l]
         grads[2 * l + 1] = dz.sum(axis=0)
         if l > 0:
-            dz = given[l - 1] if given else r((dz @ r(p[2 * l])) * (hs[l] > 0))
-    return np.concatenate([g.ravel() for g in grads])
+            dz = r((dz @ r(p[2 * l])) * (hs[l] > 0))
+    g = np.concatenate([gr.ravel() for gr in grads])
+    return (g, dzs) if return_dz else g
 
 
 def adam(theta, m, v, g, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):

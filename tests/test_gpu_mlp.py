@@ -10,6 +10,7 @@ import pytest
 import synth
 from oracle import mlp as omlp
 from tests.helpers import f32, rel_l2
+from tests.mlp_decisions import gradient_on_decisions
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -130,8 +131,7 @@ def test_full_size_decisions_and_gradient(sw):
         print("backward dZ%d mismatch fraction" % l, bad.mean(), "valid", bool(ok.all()),
               flush=True)
         assert bad.mean() < 2e-3 and ok.all()
-    cache = {"hs": [feats] + hs, "y": y, "s": s, "dz": dzs}
-    gref = omlp.backward(theta, cache, dv.ravel())
+    gref = gradient_on_decisions(theta, [feats] + hs, s, dzs, dv.ravel())
     errs = [rel_l2(a, b) for a, b in zip(_blocks(g), _blocks(gref))]
     print("mlp full-size gradient (same decisions)", ["%.1e" % e for e in errs], flush=True)
     assert max(errs) <= 1e-4

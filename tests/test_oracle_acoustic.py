@@ -71,6 +71,28 @@ def test_pml_profile_shape(orc):
     assert a[0] == pytest.approx(b[0] - 1.0, rel=1e-14)
 
 
+def test_pml_profile_half_nodes(orc):
+    # Half nodes (shift 0.5, the staggered elastic grid) sample the same profile
+    # of position as the integer nodes: node i + 1/2 of an axis (n, P, h) is
+    # integer node 2i + 1 of the axis refined by two (2n - 1, 2P, h/2), whose
+    # pad has the same thickness and whose integer nodes are pinned above. A
+    # half-cell error in where shift places the node fails this.
+    n, P, h, dt, vmax, f0, R = 61, 12, 10.0, 1e-3, 3000.0, 10.0, 1e-3
+    for lo in (P, 0):  # both pads, and no top pad (free surface)
+        ah, bh = orc.pml_profile(n, lo, P, h, dt, vmax, f0, R, shift=0.5)
+        ar, br = orc.pml_profile(2 * n - 1, 2 * lo, 2 * P, h / 2, dt, vmax, f0, R)
+        np.testing.assert_allclose(ah[:-1], ar[1::2], rtol=1e-14, atol=0)
+        np.testing.assert_allclose(bh[:-1], br[1::2], rtol=1e-14, atol=0)
+    # with equal pads the half nodes i + 1/2 and (n - 2 - i) + 1/2 mirror each
+    # other about the centre of the axis
+    ah, bh = orc.pml_profile(n, P, P, h, dt, vmax, f0, R, shift=0.5)
+    np.testing.assert_allclose(ah[:-1], ah[-2::-1], rtol=1e-14, atol=0)
+    # the last half node of each pad sits half a cell in (damped, a < 0); the
+    # first half node past it is undamped
+    assert ah[P - 1] < 0.0 and ah[P] == 0.0
+    assert ah[n - 1 - P] < 0.0 and ah[n - 2 - P] == 0.0
+
+
 # ---------------------------------------------------------------- energy
 def test_discrete_energy_is_conserved(orc):
     # Without damping or source, leapfrog with a symmetric Laplacian L conserves

@@ -184,3 +184,33 @@ def test_pml_energy_decay(orc):
     d = orc.el_forward(pb, m, np.array([[50, 50]]), synth.ricker(20.0, nt, 0.5e-3)[None], rec)[0]
     e = np.sum(d ** 2, axis=(1, 2))
     assert e[-1] / e.max() < 1e-4
+
+
+def test_half_node_profiles_by_symmetry(orc):
+    # Homogeneous square grid, equal pads on all sides, source on the centre
+    # node. (i) Exchanging x and z maps vx onto vz, txx onto tzz and txz onto
+    # itself; every operation has its transposed twin, so this holds exactly
+    # and fails if any of the eight memory variables takes the profile of the
+    # wrong axis. (ii) The mirror x -> -x maps txx onto itself and vx (half
+    # nodes i + 1/2) onto -vx at (NX - 2 - i) + 1/2. It holds while each
+    # memory variable takes its profile at its derivative's output node
+    # (integer or half), up to the one vx node past the last integer node,
+    # whose mirror lies outside the grid; taking the integer-node profile at a
+    # half node instead (for the velocity or the stress terms) breaks it by
+    # 100-1000 times more than that edge effect on this narrow pad.
+    nx = nz = 41
+    P, nt, dt = 6, 500, 0.5e-3
+    m = np.stack([np.full((nz, nx), 3000.0), np.full((nz, nx), 1700.0),
+                  np.full((nz, nx), 2200.0)])
+    pb = orc.problem(nx, nz, P, 5.0, dt, nt, 3000.0, 20.0, 1e-3, nshots=1)
+    s = orc.el_wavefield(pb, m, np.array([[20, 20]]), synth.ricker(25.0, nt, dt)[None])
+    vx, vz, txx, tzz, txz = (s[:, k] for k in range(5))
+    assert np.array_equal(vx, np.transpose(vz, (0, 2, 1)))
+    assert np.array_equal(txx, np.transpose(tzz, (0, 2, 1)))
+    assert np.array_equal(txz, np.transpose(txz, (0, 2, 1)))
+    NX = nx + 2 * P
+    mod = slice(P, P + nx)
+    e_t = np.abs(txx - txx[:, :, ::-1])[:, mod, mod].max() / np.abs(txx[:, mod, mod]).max()
+    e_v = (np.abs(vx[:, :, :NX - 1] + vx[:, :, NX - 2::-1])[:, mod, P:P + nx - 1].max() /
+           np.abs(vx[:, mod, mod]).max())
+    assert e_t < 2e-5 and e_v < 1e-4, (e_t, e_v)

@@ -86,3 +86,42 @@ def test_adam_first_step_is_sign_step():
     g = rng.standard_normal(1000)
     new, m, v = mlp.adam(theta, np.zeros(1000), np.zeros(1000), g, 1, lr=1e-3, eps=1e-12)
     np.testing.assert_allclose(new - theta, -1e-3 * np.sign(g), rtol=1e-6)
+
+
+def test_encode_closed_form():
+    # one frequency per axis fixes the orientation, the point order
+    # (m = j nx + i) and the 2 pi: row 0 = (1, 0) gives cos / sin(2 pi i/(nx-1)),
+    # row 1 = (0, 1/2) gives cos / sin(pi j/(nz-1)); the other rows are 0
+    nx, nz = 5, 3
+    B = np.zeros((64, 2))
+    B[0] = (1.0, 0.0)
+    B[1] = (0.0, 0.5)
+    g = mlp.encode(B, nx, nz, emulate=False)
+    assert g.shape == (nx * nz, 128)
+    i = np.tile(np.arange(nx), nz)
+    j = np.repeat(np.arange(nz), nx)
+    cos_x = np.array([1.0, 0.0, -1.0, 0.0, 1.0])[i]
+    sin_x = np.array([0.0, 1.0, 0.0, -1.0, 0.0])[i]
+    cos_z = np.array([1.0, 0.0, -1.0])[j]
+    sin_z = np.array([0.0, 1.0, 0.0])[j]
+    np.testing.assert_allclose(g[:, 0], cos_x, atol=1e-15)
+    np.testing.assert_allclose(g[:, 64], sin_x, atol=1e-15)
+    np.testing.assert_allclose(g[:, 1], cos_z, atol=1e-15)
+    np.testing.assert_allclose(g[:, 65], sin_z, atol=1e-15)
+    assert np.all(g[:, 2:64] == 1.0) and np.all(g[:, 66:] == 0.0)
+    # the emulating encoder stores the same features rounded to bf16
+    assert np.array_equal(mlp.encode(B, nx, nz), mlp.bf16(g))
+
+
+def test_gradient_on_decisions_matches_oracle():
+    # the test-side gradient from stored decisions (used by the full-size GPU
+    # test) equals the oracle's backward when given the oracle's own decisions
+    from tests.mlp_decisions import gradient_on_decisions
+    theta = mlp.init_params(11)
+    theta[np.random.default_rng(12).integers(0, len(theta), 80)] += 0.2
+    g = mlp.encode(synth.rff_frequencies(seed=13), 17, 9)
+    v, cache = mlp.forward(theta, g)
+    dv = np.random.default_rng(14).standard_normal(len(v))
+    ref, dzs = mlp.backward(theta, cache, dv, return_dz=True)
+    got = gradient_on_decisions(theta, cache["hs"], cache["s"], dzs, dv)
+    np.testing.assert_allclose(got, ref, rtol=1e-13, atol=1e-15)
