@@ -26,6 +26,10 @@
  *  - Return value: SWEEP_OK (0) or a negative error code; sweep_last_error()
  *    gives a message for the calling thread. No C++ exception crosses the ABI.
  *  - Calls on one plan are not thread-safe; different plans are independent.
+ *  - Plans and batches created with a context run on the context's device:
+ *    each call makes that device current and restores the caller's device
+ *    before returning. Without a context (NULL) they run on the device current
+ *    at each call. The MLP, Adam and misfit calls run on the current device.
  */
 #ifndef SWEEP_H
 #define SWEEP_H
@@ -40,7 +44,8 @@ extern "C" {
 #define SWEEP_OK 0
 #define SWEEP_EINVAL (-1) /* bad shape, position outside the model, nt < 1, ... */
 #define SWEEP_EHIP (-2)   /* a HIP runtime call failed; the message names it */
-#define SWEEP_ENOMEM (-3) /* the workspace passed is smaller than required */
+#define SWEEP_ENOMEM (-3) /* the workspace passed is smaller than required, or host
+                             memory ran out inside the call */
 #define SWEEP_ECFL (-4)   /* pml_vmax * dt / h exceeds the scheme's stability limit */
 #define SWEEP_ESTATE (-5) /* call out of order (e.g. backward without a saved forward) */
 
@@ -108,21 +113,36 @@ typedef struct {
 } sweep_tuning;
 
 typedef struct sweep_plan sweep_plan;
+typedef struct sweep_ctx sweep_ctx;
 
 /* Message describing the last error on the calling thread ("" if none). */
 const char* sweep_last_error(void);
 
-/* Create a plan. src_xz: host [nshots][nsrc][2] ([nshots][2] for one source);
+/* Library context for HIP device `hip_device` (0 .. device count - 1): plans
+ * and batches created with it are bound to that device (Sec. 2.3 places one
+ * model replica per device; on one GPU a context is that device). Queries the
+ * device's properties; allocates no device memory. SWEEP_EINVAL for a device
+ * outside the range, SWEEP_EHIP if the runtime cannot be reached. The context
+ * must outlive the plans and batches created with it. */
+int sweep_ctx_create(sweep_ctx** out, int hip_device);
+void sweep_ctx_destroy(sweep_ctx* ctx);
+/* The context's device (-1 for NULL). */
+int sweep_ctx_device(const sweep_ctx* ctx);
+
+/* Create a plan on the context's device (ctx may be NULL: the plan then runs
+ * on whatever device is current at each call). src_xz: host [nshots][nsrc][2] ([nshots][2] for one source);
  * rec_xz: host [nshots][nrec][2] (model-grid cells, x then z); the wavelets of
  * sweep_forward are then [nshots][nsrc][nt]. The arrays are copied. Fails with SWEEP_EINVAL on
  * inconsistent sizes or positions outside the model, SWEEP_ECFL when
  * pml_vmax*dt/h exceeds 0.5546 (acoustic, 8th order) or 0.6061 (elastic, 4th).
  * Does not touch the GPU. */
-int sweep_plan_create(const sweep_problem* pb, const int32_t* src_xz, const int32_t* rec_xz,
-                      sweep_plan** out);
+int sweep_plan_create(const sweep_ctx* ctx, const sweep_problem* pb, const int32_t* src_xz,
+                      const int32_t* rec_xz, sweep_plan** out);
 void sweep_plan_destroy(sweep_plan* plan);
 
-/* Select tile / launch choices (validated; SWEEP_EINVAL if unsupported). */
+/* Select tile / launch choices (validated; SWEEP_EINVAL if unsupported). Every
+ * call discards the plan's saved forward state, and a batch holding the plan
+ * refuses its backward (SWEEP_ESTATE) until its next saving forward. */
 int sweep_plan_set_tuning(sweep_plan* plan, const sweep_tuning* t);
 int sweep_plan_get_tuning(const sweep_plan* plan, sweep_tuning* t);
 
@@ -227,13 +247,21 @@ int sweep_plan_kernel_time(sweep_plan* plan, int kernel_class, int* launches, do
  * plan in the batch is advanced by one launch per kernel kind (plans whose nt
  * is reached drop out), so k launches serve all of them instead of one set per
  * plan. Results are bitwise identical to running each plan alone. The plans
- * stay owned by the caller and must outlive the batch; they must share the
- * same rz tuning. At most 8 plans. With use_graph = 1 the whole forward (and
+ * stay owned by the caller and must outlive the batch; they must be distinct,
+ * bound to the batch's device (ctx, or the first plan's when ctx is NULL) and
+ * share the same rz and pml_rz tuning, which they must keep: forward and
+ * backward return SWEEP_EINVAL when a member's rz or pml_rz no longer matches
+ * the batch's, and backward returns SWEEP_ESTATE when any member's tuning
+ * changed after the saving forward. 1 .. 4096 plans; each launch carries up to
+ * 8 of them, so a batch of n plans takes ceil(n / 8) launches per kernel kind
+ * and step. With use_graph = 1 the whole forward (and
  * the whole backward) is captured once as a hipGraph and replayed while the
- * pointers passed are unchanged. Pointer arrays are host arrays of device
- * pointers, one per plan; the workspace is carved into one region per plan. */
+ * pointers passed and the plans' tunings are unchanged. Pointer arrays are
+ * host arrays of device pointers, one per plan; the workspace is carved into
+ * one region per plan. */
 typedef struct sweep_batch sweep_batch;
-int sweep_batch_create(sweep_plan* const* plans, int nplans, sweep_batch** out);
+int sweep_batch_create(const sweep_ctx* ctx, sweep_plan* const* plans, int nplans,
+                       sweep_batch** out);
 void sweep_batch_destroy(sweep_batch* batch);
 int sweep_batch_set_graph(sweep_batch* batch, int use_graph);
 size_t sweep_batch_workspace_bytes(const sweep_batch* batch, int for_backward);
@@ -261,9 +289,15 @@ int sweep_batch_autotune(sweep_batch* batch, const float* const* d_models,
                          int steps, int for_backward, const char* cache_path, void* stream,
                          int* chosen);
 
-/* L2 misfit: d_resid[i] = d_pred[i] - d_obs[i] and *d_J = 0.5 * sum resid^2
- * (float64, device). Deterministic two-stage reduction; d_scratch must hold
- * sweep_l2_misfit_scratch_bytes(n) bytes. d_resid may alias d_pred. */
+/* L2 misfit of FWI (Sec. 1: the inversion fits the data in the least-squares
+ * sense): d_resid[i] = d_pred[i] - d_obs[i] and *d_J = 0.5 * sum resid^2
+ * (float64, device), with no time-step weight. d_resid is the dJ/d(gathers)
+ * that sweep_backward takes. n elements of any layout (the gathers of one
+ * plan: nshots * nt * nrec * ncomp). Deterministic two-stage reduction (fixed
+ * contiguous chunks per block, then a fixed tree): the same n gives the same
+ * bits. d_scratch (caller-owned device memory) must hold
+ * sweep_l2_misfit_scratch_bytes(n) bytes of float64 partial sums. d_resid may
+ * alias d_pred. SWEEP_EINVAL for a null pointer. */
 size_t sweep_l2_misfit_scratch_bytes(size_t n);
 int sweep_l2_misfit(const float* d_pred, const float* d_obs, float* d_resid, double* d_J,
                     size_t n, void* d_scratch, void* stream);

@@ -45,8 +45,12 @@ _lib = None
 
 _SIGS = {
     "sweep_last_error": (ctypes.c_char_p, []),
-    "sweep_plan_create": (ctypes.c_int, [ctypes.POINTER(Problem), ctypes.c_void_p,
-                                         ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
+    "sweep_ctx_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int]),
+    "sweep_ctx_destroy": (None, [ctypes.c_void_p]),
+    "sweep_ctx_device": (ctypes.c_int, [ctypes.c_void_p]),
+    "sweep_plan_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Problem),
+                                         ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.POINTER(ctypes.c_void_p)]),
     "sweep_plan_destroy": (None, [ctypes.c_void_p]),
     "sweep_plan_set_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Tuning)]),
     "sweep_plan_get_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Tuning)]),
@@ -72,8 +76,8 @@ _SIGS = {
                                            ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int,
                                            ctypes.c_char_p, ctypes.c_void_p,
                                            ctypes.POINTER(ctypes.c_int)]),
-    "sweep_batch_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int,
-                                          ctypes.POINTER(ctypes.c_void_p)]),
+    "sweep_batch_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p),
+                                          ctypes.c_int, ctypes.POINTER(ctypes.c_void_p)]),
     "sweep_batch_destroy": (None, [ctypes.c_void_p]),
     "sweep_batch_set_graph": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "sweep_batch_workspace_bytes": (ctypes.c_size_t, [ctypes.c_void_p, ctypes.c_int]),
@@ -111,6 +115,21 @@ def lib():
                 fn.argtypes = args
         _lib = L
     return _lib
+
+
+_contexts = {}
+
+
+def context(device_index: int) -> ctypes.c_void_p:
+    """The library context of HIP device `device_index` (created once, kept
+    for the life of the process; plans and batches made with it run on that
+    device)."""
+    h = _contexts.get(device_index)
+    if h is None:
+        h = ctypes.c_void_p()
+        check(lib().sweep_ctx_create(ctypes.byref(h), int(device_index)))
+        _contexts[device_index] = h
+    return h
 
 
 def check(rc: int):

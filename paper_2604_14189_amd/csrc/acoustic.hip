@@ -1547,29 +1547,33 @@ int launch_step(const AcStep& a, int rz, int prz, hipStream_t s, hipEvent_t* ev)
 
 // One batched step over the active plans `steps[0..n)` (all with the same rz and
 // prz): one launch per tile set (z frame, x frame, interior) for all plans.
+// Plans with more than kPlansPerLaunch members with work take one launch per
+// group of kPlansPerLaunch of them, in plan order.
 template <bool kAdj>
 int launch_step_batch(const AcStep* steps, int n, int rz, int prz, hipStream_t s) {
   AcBatch b;
   for (int phase = 0; phase < 3; ++phase) {
-    b.nplans = 0;
-    b.base[0] = 0;
-    for (int q = 0; q < n; ++q) {
-      const AcStep& a = steps[q];
-      const int blocks =
-          (phase == 0 ? a.n_zf * a.nsub : phase == 1 ? a.n_xf * a.nsub : a.n_int) * a.nshots;
-      if (blocks <= 0) continue;
-      const int k = b.nplans++;
-      b.step[k] = a;
-      b.base[k + 1] = b.base[k] + blocks;
+    for (int q = 0; q < n;) {
+      b.nplans = 0;
+      b.base[0] = 0;
+      for (; q < n && b.nplans < kPlansPerLaunch; ++q) {
+        const AcStep& a = steps[q];
+        const int blocks =
+            (phase == 0 ? a.n_zf * a.nsub : phase == 1 ? a.n_xf * a.nsub : a.n_int) * a.nshots;
+        if (blocks <= 0) continue;
+        const int k = b.nplans++;
+        b.step[k] = a;
+        b.base[k + 1] = b.base[k] + blocks;
+      }
+      if (b.nplans == 0) continue;
+      const dim3 g(b.base[b.nplans]);
+      if (phase == 0)
+        launch_frame_batch<kAdj, true>(b, prz, g, s);
+      else if (phase == 1)
+        launch_frame_batch<kAdj, false>(b, prz, g, s);
+      else
+        launch_interior_batch<kAdj>(b, rz, g, s);
     }
-    if (b.nplans == 0) continue;
-    const dim3 g(b.base[b.nplans]);
-    if (phase == 0)
-      launch_frame_batch<kAdj, true>(b, prz, g, s);
-    else if (phase == 1)
-      launch_frame_batch<kAdj, false>(b, prz, g, s);
-    else
-      launch_interior_batch<kAdj>(b, rz, g, s);
   }
   SWEEP_HIP(hipGetLastError());
   return SWEEP_OK;
@@ -1607,21 +1611,23 @@ int ac_launch_deep(const AcStep& a, bool adj, hipStream_t s, hipEvent_t* ev) {
 // left out).
 int ac_launch_deep_batch(const AcStep* steps, int n, bool adj, hipStream_t s) {
   AcBatch b;
-  b.nplans = 0;
-  b.base[0] = 0;
-  for (int q = 0; q < n; ++q) {
-    const AcStep& a = steps[q];
-    if (a.n_run <= 0) continue;
-    const int k = b.nplans++;
-    b.step[k] = a;
-    b.base[k + 1] = b.base[k] + a.n_run * a.nshots;
+  for (int q = 0; q < n;) {
+    b.nplans = 0;
+    b.base[0] = 0;
+    for (; q < n && b.nplans < kPlansPerLaunch; ++q) {
+      const AcStep& a = steps[q];
+      if (a.n_run <= 0) continue;
+      const int k = b.nplans++;
+      b.step[k] = a;
+      b.base[k + 1] = b.base[k] + a.n_run * a.nshots;
+    }
+    if (b.nplans == 0) continue;
+    const dim3 g(b.base[b.nplans]);
+    if (adj)
+      hipLaunchKernelGGL((ac_march_batch_kernel<true>), g, dim3(kThreads), 0, s, b);
+    else
+      hipLaunchKernelGGL((ac_march_batch_kernel<false>), g, dim3(kThreads), 0, s, b);
   }
-  if (b.nplans == 0) return SWEEP_OK;
-  const dim3 g(b.base[b.nplans]);
-  if (adj)
-    hipLaunchKernelGGL((ac_march_batch_kernel<true>), g, dim3(kThreads), 0, s, b);
-  else
-    hipLaunchKernelGGL((ac_march_batch_kernel<false>), g, dim3(kThreads), 0, s, b);
   SWEEP_HIP(hipGetLastError());
   return SWEEP_OK;
 }

@@ -18,10 +18,14 @@
 namespace sweep {
 
 namespace {
-thread_local std::string g_last_error;
+thread_local char g_last_error[1024] = "";
 }
 
-void set_error(const std::string& msg) { g_last_error = msg; }
+void set_error_c(const char* msg) noexcept {
+  std::snprintf(g_last_error, sizeof(g_last_error), "%s", msg ? msg : "");
+}
+
+void set_error(const std::string& msg) { set_error_c(msg.c_str()); }
 
 KernelTimer::~KernelTimer() {
   for (auto& v : ev)
@@ -1005,10 +1009,11 @@ int batch_backward_enqueue(sweep_batch* b, const float* const* resids, float* co
 }  // namespace
 
 // ====================================================================== C-ABI
-extern "C" const char* sweep_last_error(void) { return g_last_error.c_str(); }
+extern "C" const char* sweep_last_error(void) { return g_last_error; }
 
-extern "C" int sweep_plan_create(const sweep_problem* pb, const int32_t* src_xz,
-                                 const int32_t* rec_xz, sweep_plan** out) {
+extern "C" int sweep_plan_create(const sweep_ctx* ctx, const sweep_problem* pb,
+                                 const int32_t* src_xz, const int32_t* rec_xz,
+                                 sweep_plan** out) try {
   if (!pb || !out || !src_xz || (pb->nrec > 0 && !rec_xz)) {
     set_error("sweep_plan_create: null argument");
     return SWEEP_EINVAL;
@@ -1042,6 +1047,10 @@ extern "C" int sweep_plan_create(const sweep_problem* pb, const int32_t* src_xz,
     return SWEEP_EINVAL;
   }
   p->pb = *pb;
+  if (ctx) {
+    p->device = ctx->device;
+    p->arch = ctx->arch;
+  }
   p->P = pb->pml;
   p->NX = pb->nx + 2 * pb->pml;
   p->NZ = pb->nz + (pb->free_surface ? 1 : 2) * pb->pml;
@@ -1110,10 +1119,11 @@ extern "C" int sweep_plan_create(const sweep_problem* pb, const int32_t* src_xz,
   *out = p;
   return SWEEP_OK;
 }
+SWEEP_ABI_CATCH("sweep_plan_create")
 
 extern "C" void sweep_plan_destroy(sweep_plan* plan) { delete plan; }
 
-extern "C" int sweep_plan_set_tuning(sweep_plan* p, const sweep_tuning* t) {
+extern "C" int sweep_plan_set_tuning(sweep_plan* p, const sweep_tuning* t) try {
   if (!p || !t) {
     set_error("null argument");
     return SWEEP_EINVAL;
@@ -1127,14 +1137,16 @@ extern "C" int sweep_plan_set_tuning(sweep_plan* p, const sweep_tuning* t) {
     return SWEEP_EINVAL;
   }
   p->tune = *t;
+  ++p->tune_gen;
   if (p->pb.physics == SWEEP_ACOUSTIC) ac_build_tiling(p);
   p->saved = false;
   p->gfwd.reset();
   p->gbwd.reset();
   return SWEEP_OK;
 }
+SWEEP_ABI_CATCH("sweep_plan_set_tuning")
 
-extern "C" int sweep_plan_get_tuning(const sweep_plan* p, sweep_tuning* t) {
+extern "C" int sweep_plan_get_tuning(const sweep_plan* p, sweep_tuning* t) try {
   if (!p || !t) {
     set_error("null argument");
     return SWEEP_EINVAL;
@@ -1142,8 +1154,9 @@ extern "C" int sweep_plan_get_tuning(const sweep_plan* p, sweep_tuning* t) {
   *t = p->tune;
   return SWEEP_OK;
 }
+SWEEP_ABI_CATCH("sweep_plan_get_tuning")
 
-extern "C" size_t sweep_plan_workspace_bytes(const sweep_plan* p, int for_backward) {
+extern "C" size_t sweep_plan_workspace_bytes(const sweep_plan* p, int for_backward) try {
   if (!p) return 0;
   if (p->pb.physics != SWEEP_ACOUSTIC) {
     ElLayout E;
@@ -1154,8 +1167,9 @@ extern "C" size_t sweep_plan_workspace_bytes(const sweep_plan* p, int for_backwa
   ac_layout(p, L);
   return for_backward ? L.bwd_end : L.fwd_end;
 }
+SWEEP_ABI_CATCH_SIZE("sweep_plan_workspace_bytes")
 
-extern "C" int sweep_plan_padded(const sweep_plan* p, int* NX, int* NZ) {
+extern "C" int sweep_plan_padded(const sweep_plan* p, int* NX, int* NZ) try {
   if (!p || !NX || !NZ) {
     set_error("null argument");
     return SWEEP_EINVAL;
@@ -1164,9 +1178,10 @@ extern "C" int sweep_plan_padded(const sweep_plan* p, int* NX, int* NZ) {
   *NZ = p->NZ;
   return SWEEP_OK;
 }
+SWEEP_ABI_CATCH("sweep_plan_padded")
 
 extern "C" int sweep_plan_tiles(const sweep_plan* p, int* interior_tiles, int* frame_tiles,
-                                int* tile_rows, int* rect) {
+                                int* tile_rows, int* rect) try {
   if (!p || !interior_tiles || !frame_tiles || !tile_rows) {
     set_error("null argument");
     return SWEEP_EINVAL;
@@ -1187,13 +1202,19 @@ extern "C" int sweep_plan_tiles(const sweep_plan* p, int* interior_tiles, int* f
   }
   return SWEEP_OK;
 }
+SWEEP_ABI_CATCH("sweep_plan_tiles")
 
 extern "C" int sweep_forward(sweep_plan* p, const float* d_model, const float* d_wavelet,
                              float* d_gathers, void* d_work, size_t work_bytes,
-                             int save_for_backward, void* stream) {
+                             int save_for_backward, void* stream) try {
   if (!p || !d_model || !d_wavelet || (!d_gathers && p->pb.nrec > 0)) {
     set_error("sweep_forward: null argument");
     return SWEEP_EINVAL;
+  }
+  DeviceGuard dg_(p->device);
+  if (!dg_.ok) {
+    set_error("cannot make the plan's device current");
+    return SWEEP_EHIP;
   }
   p->saved = false;
   if (p->pb.physics != SWEEP_ACOUSTIC)
@@ -1202,10 +1223,11 @@ extern "C" int sweep_forward(sweep_plan* p, const float* d_model, const float* d
   return ac_forward(p, d_model, d_wavelet, d_gathers, d_work, work_bytes, save_for_backward,
                     (hipStream_t)stream);
 }
+SWEEP_ABI_CATCH("sweep_forward")
 
 extern "C" int sweep_born_forward(sweep_plan* p, const float* d_model, const float* d_dmodel,
                                   const float* d_wavelet, float* d_dgathers, void* d_work,
-                                  size_t work_bytes, void* stream) {
+                                  size_t work_bytes, void* stream) try {
   if (!p || !d_model || !d_dmodel || !d_wavelet || (!d_dgathers && p->pb.nrec > 0)) {
     set_error("sweep_born_forward: null argument");
     return SWEEP_EINVAL;
@@ -1214,23 +1236,35 @@ extern "C" int sweep_born_forward(sweep_plan* p, const float* d_model, const flo
     set_error("sweep_born_forward: acoustic plans only");
     return SWEEP_EINVAL;
   }
+  DeviceGuard dg_(p->device);
+  if (!dg_.ok) {
+    set_error("cannot make the plan's device current");
+    return SWEEP_EHIP;
+  }
   p->saved = false;
   return ac_born(p, d_model, d_dmodel, d_wavelet, d_dgathers, d_work, work_bytes,
                  (hipStream_t)stream);
 }
+SWEEP_ABI_CATCH("sweep_born_forward")
 
 extern "C" int sweep_backward(sweep_plan* p, const float* d_resid, float* d_grad, void* d_work,
-                              size_t work_bytes, void* stream) {
+                              size_t work_bytes, void* stream) try {
   if (!p || (!d_resid && p->pb.nrec > 0) || !d_grad) {
     set_error("sweep_backward: null argument");
     return SWEEP_EINVAL;
+  }
+  DeviceGuard dg_(p->device);
+  if (!dg_.ok) {
+    set_error("cannot make the plan's device current");
+    return SWEEP_EHIP;
   }
   if (p->pb.physics != SWEEP_ACOUSTIC)
     return el_backward(p, d_resid, d_grad, d_work, work_bytes, (hipStream_t)stream);
   return ac_backward(p, d_resid, d_grad, d_work, work_bytes, (hipStream_t)stream);
 }
+SWEEP_ABI_CATCH("sweep_backward")
 
-extern "C" int sweep_plan_set_profiling(sweep_plan* p, int enable) {
+extern "C" int sweep_plan_set_profiling(sweep_plan* p, int enable) try {
   if (!p) {
     set_error("null plan");
     return SWEEP_EINVAL;
@@ -1240,12 +1274,18 @@ extern "C" int sweep_plan_set_profiling(sweep_plan* p, int enable) {
   p->timer.reset();
   return SWEEP_OK;
 }
+SWEEP_ABI_CATCH("sweep_plan_set_profiling")
 
 extern "C" int sweep_plan_kernel_time(sweep_plan* p, int kernel_class, int* launches,
-                                      double* total_ms) {
+                                      double* total_ms) try {
   if (!p || !launches || !total_ms || kernel_class < 0 || kernel_class >= kNumClasses) {
     set_error("sweep_plan_kernel_time: bad argument");
     return SWEEP_EINVAL;
+  }
+  DeviceGuard dg_(p->device);
+  if (!dg_.ok) {
+    set_error("cannot make the plan's device current");
+    return SWEEP_EHIP;
   }
   const std::vector<hipEvent_t>& v = p->timer.ev[kernel_class];
   const size_t n = p->timer.used[kernel_class];
@@ -1260,11 +1300,34 @@ extern "C" int sweep_plan_kernel_time(sweep_plan* p, int kernel_class, int* laun
   *total_ms = tot;
   return SWEEP_OK;
 }
+SWEEP_ABI_CATCH("sweep_plan_kernel_time")
 
 // ----------------------------------------------------------------- batch C-ABI
-extern "C" int sweep_batch_create(sweep_plan* const* plans, int nplans, sweep_batch** out) {
-  if (!plans || !out || nplans < 1 || nplans > kMaxBatch) {
-    set_error("sweep_batch_create: need 1.." + std::to_string(kMaxBatch) + " plans");
+namespace {
+// The batch launches one template per (rz, pml_rz) over every plan's tile
+// lists, so every member must still have the batch's tiling: a member whose
+// tuning changed since (sweep_plan_set_tuning) is refused until the batch is
+// re-tuned or re-created.
+int batch_check_members(const sweep_batch* b) {
+  for (size_t q = 0; q < b->plans.size(); ++q) {
+    const sweep_plan* p = b->plans[q];
+    if (p->tune.rz != b->rz || p->tune.pml_rz != b->prz) {
+      set_error("batch plan " + std::to_string(q) + " has rz/pml_rz " +
+                std::to_string(p->tune.rz) + "/" + std::to_string(p->tune.pml_rz) +
+                " but the batch was made for " + std::to_string(b->rz) + "/" +
+                std::to_string(b->prz) + " (set the same tiling on every plan, or re-create "
+                "the batch)");
+      return SWEEP_EINVAL;
+    }
+  }
+  return SWEEP_OK;
+}
+}  // namespace
+
+extern "C" int sweep_batch_create(const sweep_ctx* ctx, sweep_plan* const* plans, int nplans,
+                                  sweep_batch** out) try {
+  if (!plans || !out || nplans < 1 || nplans > kMaxBatchPlans) {
+    set_error("sweep_batch_create: need 1.." + std::to_string(kMaxBatchPlans) + " plans");
     return SWEEP_EINVAL;
   }
   *out = nullptr;
@@ -1277,22 +1340,29 @@ extern "C" int sweep_batch_create(sweep_plan* const* plans, int nplans, sweep_ba
       set_error("sweep_batch_create: all plans of a batch must use the same rz and pml_rz");
       return SWEEP_EINVAL;
     }
+    if (plans[q]->device != (ctx ? ctx->device : plans[0]->device)) {
+      set_error("sweep_batch_create: all plans of a batch must be bound to the batch's device");
+      return SWEEP_EINVAL;
+    }
+    for (int r = 0; r < q; ++r)
+      if (plans[r] == plans[q]) {
+        set_error("sweep_batch_create: a plan appears twice");
+        return SWEEP_EINVAL;
+      }
   }
-  sweep_batch* b = new (std::nothrow) sweep_batch();
-  if (!b) {
-    set_error("out of host memory");
-    return SWEEP_EINVAL;
-  }
+  sweep_batch* b = new sweep_batch();
   b->plans.assign(plans, plans + nplans);
+  b->device = ctx ? ctx->device : plans[0]->device;
   b->rz = plans[0]->tune.rz;
   b->prz = plans[0]->tune.pml_rz;
   *out = b;
   return SWEEP_OK;
 }
+SWEEP_ABI_CATCH("sweep_batch_create")
 
 extern "C" void sweep_batch_destroy(sweep_batch* b) { delete b; }
 
-extern "C" int sweep_batch_set_graph(sweep_batch* b, int use_graph) {
+extern "C" int sweep_batch_set_graph(sweep_batch* b, int use_graph) try {
   if (!b) {
     set_error("null batch");
     return SWEEP_EINVAL;
@@ -1302,8 +1372,9 @@ extern "C" int sweep_batch_set_graph(sweep_batch* b, int use_graph) {
   b->gbwd.reset();
   return SWEEP_OK;
 }
+SWEEP_ABI_CATCH("sweep_batch_set_graph")
 
-extern "C" size_t sweep_batch_workspace_bytes(const sweep_batch* b, int for_backward) {
+extern "C" size_t sweep_batch_workspace_bytes(const sweep_batch* b, int for_backward) try {
   if (!b) return 0;
   std::vector<AcLayout> L;
   std::vector<size_t> off;
@@ -1311,16 +1382,25 @@ extern "C" size_t sweep_batch_workspace_bytes(const sweep_batch* b, int for_back
   batch_layouts(b, for_backward, L, off, total);
   return total;
 }
+SWEEP_ABI_CATCH_SIZE("sweep_batch_workspace_bytes")
 
 extern "C" int sweep_batch_forward(sweep_batch* b, const float* const* d_models,
                                    const float* const* d_wavelets, float* const* d_gathers,
                                    void* d_work, size_t work_bytes, int save_for_backward,
-                                   void* stream) {
+                                   void* stream) try {
   if (!b || !d_models || !d_wavelets || !d_gathers || !d_work) {
     set_error("sweep_batch_forward: null argument");
     return SWEEP_EINVAL;
   }
   hipStream_t s = (hipStream_t)stream;
+  b->saved = false;
+  int rc = batch_check_members(b);
+  if (rc) return rc;
+  DeviceGuard dg_(b->device);
+  if (!dg_.ok) {
+    set_error("cannot make the batch's device current");
+    return SWEEP_EHIP;
+  }
   std::vector<AcLayout> L;
   std::vector<size_t> off;
   size_t total = 0;
@@ -1330,8 +1410,14 @@ extern "C" int sweep_batch_forward(sweep_batch* b, const float* const* d_models,
     return SWEEP_ENOMEM;
   }
   const int np = (int)b->plans.size();
-  int rc;
+  // the captured graph holds the plans' tilings and stored-segment layouts:
+  // their tuning generations are part of its key
   std::vector<const void*> key = {d_work, (const void*)(size_t)save_for_backward};
+  std::vector<unsigned> gen(np);
+  for (int q = 0; q < np; ++q) {
+    gen[q] = b->plans[q]->tune_gen;
+    key.push_back((const void*)(size_t)gen[q]);
+  }
   for (int q = 0; q < np; ++q) {
     if (!d_models[q] || !d_wavelets[q] || (!d_gathers[q] && b->plans[q]->pb.nrec > 0)) {
       set_error("sweep_batch_forward: null pointer for plan " + std::to_string(q));
@@ -1350,12 +1436,14 @@ extern "C" int sweep_batch_forward(sweep_batch* b, const float* const* d_models,
   if (rc) return rc;
   b->saved = save_for_backward != 0;
   b->saved_work = d_work;
+  b->saved_gen = gen;
   return SWEEP_OK;
 }
+SWEEP_ABI_CATCH("sweep_batch_forward")
 
 extern "C" int sweep_batch_backward(sweep_batch* b, const float* const* d_resids,
                                     float* const* d_grads, void* d_work, size_t work_bytes,
-                                    void* stream) {
+                                    void* stream) try {
   if (!b || !d_resids || !d_grads || !d_work) {
     set_error("sweep_batch_backward: null argument");
     return SWEEP_EINVAL;
@@ -1364,6 +1452,19 @@ extern "C" int sweep_batch_backward(sweep_batch* b, const float* const* d_resids
     set_error("sweep_batch_backward needs a preceding sweep_batch_forward(save_for_backward=1) "
               "on the same workspace");
     return SWEEP_ESTATE;
+  }
+  for (size_t q = 0; q < b->plans.size(); ++q)
+    if (b->plans[q]->tune_gen != b->saved_gen[q]) {
+      set_error("sweep_batch_backward: the tuning of plan " + std::to_string(q) +
+                " changed after the saving forward (its saved layout no longer holds)");
+      return SWEEP_ESTATE;
+    }
+  int rc0 = batch_check_members(b);
+  if (rc0) return rc0;
+  DeviceGuard dg_(b->device);
+  if (!dg_.ok) {
+    set_error("cannot make the batch's device current");
+    return SWEEP_EHIP;
   }
   std::vector<AcLayout> L;
   std::vector<size_t> off;
@@ -1374,6 +1475,7 @@ extern "C" int sweep_batch_backward(sweep_batch* b, const float* const* d_resids
     return SWEEP_ENOMEM;
   }
   std::vector<const void*> key = {d_work};
+  for (size_t q = 0; q < b->plans.size(); ++q) key.push_back((const void*)(size_t)b->saved_gen[q]);
   for (size_t q = 0; q < b->plans.size(); ++q) {
     if ((!d_resids[q] && b->plans[q]->pb.nrec > 0) || !d_grads[q]) {
       set_error("sweep_batch_backward: null pointer for plan " + std::to_string(q));
@@ -1386,6 +1488,7 @@ extern "C" int sweep_batch_backward(sweep_batch* b, const float* const* d_resids
     return batch_backward_enqueue(b, d_resids, d_grads, d_work, L, off, st);
   });
 }
+SWEEP_ABI_CATCH("sweep_batch_backward")
 
 // ----------------------------------------------------------------- autotuner
 // Times `steps` forward steps of the plan for every supported (rz, pml_rz) pair
@@ -1396,8 +1499,9 @@ namespace {
 std::string tune_key(const sweep_plan* p) {
   int dev = 0;
   hipDeviceProp_t prop;
-  std::string arch = "unknown";
-  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+  std::string arch = p->arch.empty() ? "unknown" : p->arch;
+  if (p->arch.empty() && hipGetDevice(&dev) == hipSuccess &&
+      hipGetDeviceProperties(&prop, dev) == hipSuccess)
     arch = std::string(prop.gcnArchName).substr(0, std::string(prop.gcnArchName).find(':'));
   std::ostringstream os;
   os << arch << " " << (p->pb.physics == SWEEP_ACOUSTIC ? "acoustic" : "elastic") << " " << p->NX
@@ -1411,10 +1515,15 @@ bool rz_ok(int v) { return v == 1 || v == 2 || v == 4 || v == 8; }
 
 extern "C" int sweep_plan_autotune(sweep_plan* p, const float* d_model, const float* d_wavelet,
                                    void* d_work, size_t work_bytes, int steps,
-                                   const char* cache_path, void* stream, int* chosen_rz) {
+                                   const char* cache_path, void* stream, int* chosen_rz) try {
   if (!p || !d_model || !d_wavelet || !d_work || steps < 1) {
     set_error("sweep_plan_autotune: bad argument");
     return SWEEP_EINVAL;
+  }
+  DeviceGuard dg_(p->device);
+  if (!dg_.ok) {
+    set_error("cannot make the plan's device current");
+    return SWEEP_EHIP;
   }
   if (p->pb.physics != SWEEP_ACOUSTIC) {  // the elastic kernels have no tile choice
     if (chosen_rz) *chosen_rz = p->tune.rz;
@@ -1519,11 +1628,12 @@ extern "C" int sweep_plan_autotune(sweep_plan* p, const float* d_model, const fl
   if (chosen_rz) *chosen_rz = best;
   return SWEEP_OK;
 }
+SWEEP_ABI_CATCH("sweep_plan_autotune")
 
 extern "C" int sweep_batch_autotune(sweep_batch* b, const float* const* d_models,
                                     const float* const* d_wavelets, void* d_work,
                                     size_t work_bytes, int steps, int for_backward,
-                                    const char* cache_path, void* stream, int* chosen) {
+                                    const char* cache_path, void* stream, int* chosen) try {
   if (!b || !d_models || !d_wavelets || !d_work || steps < 1) {
     set_error("sweep_batch_autotune: bad argument");
     return SWEEP_EINVAL;
@@ -1535,6 +1645,11 @@ extern "C" int sweep_batch_autotune(sweep_batch* b, const float* const* d_models
       return SWEEP_EINVAL;
     }
   hipStream_t s = (hipStream_t)stream;
+  DeviceGuard dg_(b->device);
+  if (!dg_.ok) {
+    set_error("cannot make the batch's device current");
+    return SWEEP_EHIP;
+  }
   std::string key = tune_key(b->plans[0]);
   key = key.substr(0, key.find(' ')) + (for_backward ? " batch-gradient" : " batch");
   for (sweep_plan* p : b->plans)
@@ -1664,3 +1779,4 @@ extern "C" int sweep_batch_autotune(sweep_batch* b, const float* const* d_models
   }
   return SWEEP_OK;
 }
+SWEEP_ABI_CATCH("sweep_batch_autotune")

@@ -112,14 +112,15 @@ void el_layout(const sweep_plan* p, ElLayout& L) {
   L.fwd_end = off;
   const int k = p->ckpt;
   L.nseg = (p->pb.nt + k - 1) / k;
-  L.ck = take(off, (size_t)L.nseg * kStatePlanes * ns * plane * f);
+  // stored segments: the traces of the last keep_b segments, written by the
+  // saving forward so that the backward does not recompute those segments;
+  // they are never restored, so only the other segments have a checkpoint
+  L.nkeep = std::min(std::max(p->tune.keep_b, 0), L.nseg);
+  L.ck = take(off, (size_t)(L.nseg - L.nkeep) * kStatePlanes * ns * plane * f);
   L.trace = take(off, (size_t)k * kTracePlanes * ns * plane * f);
   L.adj = take(off, kAdjPlanes * ns * plane * f);
   L.gpart = take(off, kGradPlanes * ns * plane * f);
   L.tot = take(off, kGradPlanes * plane * sizeof(double));
-  // stored segments: the traces of the last keep_b segments, written by the
-  // saving forward so that the backward does not recompute those segments
-  L.nkeep = std::min(std::max(p->tune.keep_b, 0), L.nseg);
   L.trkeep = take(off, (size_t)L.nkeep * k * kTracePlanes * ns * plane * f);
   L.bwd_end = off;
 }
@@ -250,7 +251,7 @@ int el_forward(sweep_plan* p, const float* model, const float* wavelet, float* g
   const int k = p->ckpt;
   float* ck = at<float>(work, L.ck);
   for (int n = 0; n < pb.nt; ++n) {
-    if (save && n % k == 0)
+    if (save && n % k == 0 && !el_kept(L, n / k))
       if ((rc = launch_copy(ck + (size_t)(n / k) * kStatePlanes * nsplane, st,
                             kStatePlanes * nsplane, s)))
         return rc;

@@ -6,6 +6,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <new>
 #include <string>
 #include <vector>
 
@@ -14,7 +15,60 @@
 namespace sweep {
 
 // ------------------------------------------------------------------ errors
+// The message of the last error on the calling thread. set_error_c never
+// throws (it copies into a fixed thread-local buffer), so the ABI's catch
+// clauses can call it.
 void set_error(const std::string& msg);
+void set_error_c(const char* msg) noexcept;
+
+// Catch clauses closing the function-try-block of every extern "C" entry
+// point, so that no C++ exception crosses the ABI: host allocation failure is
+// reported as SWEEP_ENOMEM, anything else as SWEEP_EINVAL; entry points that
+// return a size report 0.
+#define SWEEP_ABI_CATCH(fn)                                              \
+  catch (const std::bad_alloc&) {                                        \
+    ::sweep::set_error_c(fn ": out of host memory");                    \
+    return SWEEP_ENOMEM;                                                 \
+  }                                                                      \
+  catch (...) {                                                          \
+    ::sweep::set_error_c(fn ": unexpected C++ exception");              \
+    return SWEEP_EINVAL;                                                 \
+  }
+#define SWEEP_ABI_CATCH_SIZE(fn)                                         \
+  catch (...) {                                                          \
+    ::sweep::set_error_c(fn ": unexpected C++ exception");              \
+    return 0;                                                            \
+  }
+#define SWEEP_ABI_CATCH_VOID(fn) \
+  catch (...) {                  \
+    ::sweep::set_error_c(fn ": unexpected C++ exception"); \
+  }
+
+// Makes `dev` the current HIP device for the lifetime of the guard and
+// restores the previous one afterwards; dev < 0 leaves the current device.
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = true;
+  explicit DeviceGuard(int dev) {
+    if (dev < 0) return;
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess) {
+      ok = false;
+      return;
+    }
+    if (cur == dev) return;
+    if (hipSetDevice(dev) != hipSuccess) {
+      ok = false;
+      return;
+    }
+    prev = cur;
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+  DeviceGuard(const DeviceGuard&) = delete;
+  DeviceGuard& operator=(const DeviceGuard&) = delete;
+};
 #define SWEEP_HIP(call)                                                              \
   do {                                                                               \
     hipError_t e_ = (call);                                                          \
@@ -108,11 +162,14 @@ struct AcStep {
 };
 
 // Several plans of different shapes advanced by one launch per kernel kind.
-constexpr int kMaxBatch = 8;
+// A launch carries the step descriptors of up to kPlansPerLaunch plans in its
+// kernel arguments; a batch of more plans takes one launch per group of them.
+constexpr int kPlansPerLaunch = 8;
+constexpr int kMaxBatchPlans = 4096;
 struct AcBatch {
   int nplans;
-  int base[kMaxBatch + 1];  // first flat block of each plan in this launch
-  AcStep step[kMaxBatch];
+  int base[kPlansPerLaunch + 1];  // first flat block of each plan in this launch
+  AcStep step[kPlansPerLaunch];
 };
 
 // Launchers (acoustic.hip). Tiles are 64 x 4 rz; the interior kernel keeps rz rows

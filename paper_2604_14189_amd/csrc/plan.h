@@ -1,6 +1,7 @@
 // Host-side plan object and workspace layout (not part of the C-ABI).
 #pragma once
 
+#include <string>
 #include <vector>
 
 #include "internal.h"
@@ -104,9 +105,20 @@ struct GraphCache {
 };
 }  // namespace sweep
 
+// A library context: the HIP device its plans and batches run on.
+struct sweep_ctx {
+  int device = 0;
+  std::string arch;  // gcnArchName without feature suffixes, e.g. "gfx950"
+};
+
 struct sweep_plan {
   sweep_problem pb;
   sweep_tuning tune;
+  int device = -1;  // the context's device (-1: the device current at each call)
+  std::string arch;  // the context's arch ("": queried at each autotune)
+  // incremented by every tuning change; a batch refuses a backward (or the
+  // replay of a captured graph) after a member plan's tuning changed
+  unsigned tune_gen = 0;
   int P = 0, NX = 0, NZ = 0, ckpt = 50;
   std::vector<int> src_cell;  // [nshots][nsrc] padded linear index
   int nsrc = 1;               // sources per shot (> 1: encoded shots, acoustic)
@@ -152,9 +164,11 @@ int el_backward(sweep_plan* p, const float* resid, float* grad, void* work, size
 
 struct sweep_batch {
   std::vector<sweep_plan*> plans;  // owned by the caller
+  int device = -1;                 // the plans' device (-1: current at each call)
   int rz = 8, prz = 2;
   bool use_graph = false;
   bool saved = false;
   const void* saved_work = nullptr;
+  std::vector<unsigned> saved_gen;  // the plans' tuning generations at the saving forward
   sweep::GraphCache gfwd, gbwd;
 };

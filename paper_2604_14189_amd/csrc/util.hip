@@ -104,12 +104,13 @@ int launch_copy(float* dst, const float* src, size_t n, hipStream_t s) {
 
 }  // namespace sweep
 
-extern "C" size_t sweep_l2_misfit_scratch_bytes(size_t) {
+extern "C" size_t sweep_l2_misfit_scratch_bytes(size_t) try {
   return sweep::kMisfitBlocks * sizeof(double);
 }
+SWEEP_ABI_CATCH_SIZE("sweep_l2_misfit_scratch_bytes")
 
 extern "C" int sweep_l2_misfit(const float* d_pred, const float* d_obs, float* d_resid,
-                               double* d_J, size_t n, void* d_scratch, void* stream) {
+                               double* d_J, size_t n, void* d_scratch, void* stream) try {
   using namespace sweep;
   if (!d_pred || !d_obs || !d_resid || !d_J || !d_scratch) {
     set_error("sweep_l2_misfit: null pointer");
@@ -124,3 +125,4 @@ extern "C" int sweep_l2_misfit(const float* d_pred, const float* d_obs, float* d
   SWEEP_HIP(hipGetLastError());
   return SWEEP_OK;
 }
+SWEEP_ABI_CATCH("sweep_l2_misfit")

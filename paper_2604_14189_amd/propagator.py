@@ -72,8 +72,17 @@ class Plan:
         self.ncomp = 1 if physics == ACOUSTIC else 2
         self.device = torch.device(device) if device is not None else torch.device("cuda")
         self._src, self._rec = src, rec
+        if torch.cuda.is_available():
+            if self.device.index is None:
+                self.device = torch.device("cuda", torch.cuda.current_device())
+            self._ctx = _lib.context(self.device.index)
+        else:
+            # host-side use only (workspace sizes, tilings): the plan is bound
+            # to no device, and its first GPU call fails in the library
+            self._ctx = None
         h_ = ctypes.c_void_p()
-        check(lib().sweep_plan_create(ctypes.byref(self.pb), src.ctypes.data_as(ctypes.c_void_p),
+        check(lib().sweep_plan_create(self._ctx, ctypes.byref(self.pb),
+                                      src.ctypes.data_as(ctypes.c_void_p),
                                       rec.ctypes.data_as(ctypes.c_void_p), ctypes.byref(h_)))
         self._h = h_
         self._work = None
@@ -108,17 +117,27 @@ class Plan:
         return {"rz": t.rz, "pml_rz": t.pml_rz, "use_graph": t.use_graph, "tblock": t.tblock,
                 "keep_b": t.keep_b}
 
-    def set_tuning(self, rz: int = 8, pml_rz: Optional[int] = None, use_graph: int = 0,
-                   tblock: int = 2, keep_b: int = 0):
-        """rz: rows per thread of the interior kernel (tiles of 64 x 4 rz);
-        pml_rz: rows per thread of the C-PML kernels (<= rz, default min(4, rz));
+    def set_tuning(self, rz: Optional[int] = None, pml_rz: Optional[int] = None,
+                   use_graph: Optional[int] = None, tblock: Optional[int] = None,
+                   keep_b: Optional[int] = None):
+        """Change the given fields of the tuning and keep the others:
+        rz: rows per thread of the interior kernel (tiles of 64 x 4 rz);
+        pml_rz: rows per thread of the C-PML kernels (<= rz; when only rz is
+        given, min(4, rz));
         tblock: time steps per pass over the deep interior tiles (1 or 2);
         keep_b: checkpoint segments (the last ones) whose backward inputs
         (acoustic: B'^n; elastic and variable density: the five trace planes)
         the saving forward stores, so that backward() does not recompute them
         (more workspace, the same bits; in a Batch each plan keeps its own
-        count)."""
-        t = Tuning(rz, min(4, rz) if pml_rz is None else pml_rz, use_graph, tblock, keep_b)
+        count, and a batch refuses a backward after a member's tuning changed
+        since its saving forward)."""
+        cur = self.tuning
+        if rz is not None and pml_rz is None:
+            pml_rz = min(4, rz)
+        t = Tuning(cur["rz"] if rz is None else rz, cur["pml_rz"] if pml_rz is None else pml_rz,
+                   cur["use_graph"] if use_graph is None else int(use_graph),
+                   cur["tblock"] if tblock is None else tblock,
+                   cur["keep_b"] if keep_b is None else keep_b)
         check(lib().sweep_plan_set_tuning(self._h, ctypes.byref(t)))
         self._saved_id = -1
 
@@ -292,7 +311,8 @@ class Batch:
         self.plans = list(plans)
         arr = (ctypes.c_void_p * len(self.plans))(*[p._h.value for p in self.plans])
         h = ctypes.c_void_p()
-        check(lib().sweep_batch_create(arr, len(self.plans), ctypes.byref(h)))
+        self._ctx = self.plans[0]._ctx if self.plans else None
+        check(lib().sweep_batch_create(self._ctx, arr, len(self.plans), ctypes.byref(h)))
         self._h = h
         self._work = None
         self._saved = False

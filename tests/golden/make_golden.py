@@ -10,6 +10,13 @@ acoustic workload (64 shots, 1000 receivers at depth 5, 8 Hz Ricker). Stores
 8 complete receiver traces and the model gradient for a band-limited seeded
 residual on that shot (20 000 sampled cells plus the full gradient norm).
 
+batch_uneven8_short.npz: the eight uneven batched workloads (grids 200x200 ...
+1200x400, 16 ... 48 shots each, 40-cell pads) with their runs shortened to
+125 ... 250 steps (the full 2000 ... 4000 spread divided by 16, so segments of
+50 steps end ragged). For the middle shot of each model: 8 complete receiver
+traces and the model gradient for a band-limited seeded residual on that shot
+(4000 sampled cells plus the gradient norm).
+
 elastic600x300_shot11.npz: shot 11 of the 600x300 / 4000-step elastic workload
 (30-cell pad, free surface, 32 explosive 15 Hz shots, 600 two-component
 receivers): 8 complete (vx, vz) traces and the (vp, vs, rho) gradient for a
@@ -26,7 +33,7 @@ sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
 import oracle  # noqa: E402
 import synth  # noqa: E402
-from tests.helpers import case_from_workload, f32  # noqa: E402
+from synth.cases import case_from_workload, f32  # noqa: E402
 
 
 def layered_shot37(path):
@@ -47,7 +54,7 @@ def layered_shot37(path):
 
 
 def elastic_shot11(path):
-    from tests.helpers import el_case_from_workload
+    from synth.cases import el_case_from_workload
     w = synth.workload("elastic600x300")
     s = 11
     case = el_case_from_workload(w, shots=[s])
@@ -64,10 +71,37 @@ def elastic_shot11(path):
                         grad_cells=cells, grad=np.stack([g[c].ravel()[cells] for c in range(3)]))
 
 
+def batch_short_nt(m: int) -> int:
+    """Shortened run of batched workload m (125 ... 250 steps)."""
+    return 125 + int(round(125 * m / 7))
+
+
+def batch_uneven8_short(path):
+    out = {}
+    t = time.time()
+    for m, w in enumerate(synth.batched_workloads()):
+        nt = batch_short_nt(m)
+        s = w.nshots // 2
+        case = case_from_workload(w.replace(nt=nt), shots=[s])
+        pb = case.oracle_problem(oracle)
+        resid = f32(synth.bandlimited_noise((1, nt, w.nrec), w.f0, w.dt, 100 + m))
+        g, _, d = oracle.ac_gradient(pb, case.v, case.src, case.wav, case.rec, resid,
+                                     want_gathers=True)
+        trace_idx = np.linspace(0, w.nrec - 1, 8).round().astype(np.int64)
+        cells = np.random.default_rng(200 + m).choice(g.size, 4000, replace=False)
+        out.update({f"m{m}_shot": s, f"m{m}_nt": nt, f"m{m}_trace_idx": trace_idx,
+                    f"m{m}_traces": d[0][:, trace_idx], f"m{m}_grad_cells": cells,
+                    f"m{m}_grad": g.ravel()[cells], f"m{m}_grad_norm": np.linalg.norm(g)})
+    print("oracle batch gradients took %.1f s" % (time.time() - t), flush=True)
+    np.savez_compressed(path, **out)
+
+
 if __name__ == "__main__":
     oracle.build(force=False)
-    which = sys.argv[1:] or ["layered", "elastic"]
+    which = sys.argv[1:] or ["layered", "elastic", "batch"]
     if "layered" in which:
         layered_shot37(os.path.join(HERE, "layered1000x300_shot37.npz"))
     if "elastic" in which:
         elastic_shot11(os.path.join(HERE, "elastic600x300_shot11.npz"))
+    if "batch" in which:
+        batch_uneven8_short(os.path.join(HERE, "batch_uneven8_short.npz"))

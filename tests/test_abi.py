@@ -53,8 +53,8 @@ def test_no_undeclared_c_exports():
 def test_argument_validation_needs_no_gpu(lib):
     from paper_2604_14189_amd._lib import Problem, EINVAL, ECFL
     lib.sweep_plan_create.restype = ctypes.c_int
-    lib.sweep_plan_create.argtypes = [ctypes.POINTER(Problem), ctypes.c_void_p, ctypes.c_void_p,
-                                      ctypes.POINTER(ctypes.c_void_p)]
+    lib.sweep_plan_create.argtypes = [ctypes.c_void_p, ctypes.POINTER(Problem), ctypes.c_void_p,
+                                      ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]
     lib.sweep_last_error.restype = ctypes.c_char_p
     src = (ctypes.c_int32 * 2)(5, 5)
     rec = (ctypes.c_int32 * 2)(7, 5)
@@ -64,7 +64,7 @@ def test_argument_validation_needs_no_gpu(lib):
                   pml_vmax=2000.0, pml_f0=10.0, pml_R=1e-3, ckpt_every=5, nshots=1, nrec=1)
         pb.update(kw)
         out = ctypes.c_void_p()
-        rc = lib.sweep_plan_create(ctypes.byref(Problem(**pb)), src, rec, ctypes.byref(out))
+        rc = lib.sweep_plan_create(None, ctypes.byref(Problem(**pb)), src, rec, ctypes.byref(out))
         return rc, lib.sweep_last_error().decode()
 
     rc, msg = create(nt=0)
@@ -132,9 +132,11 @@ def test_batch_stored_segments_workspace_accounting(lib):
 
 
 def test_elastic_stored_segments_workspace_accounting(lib):
-    """Elastic plans store the five trace planes of each stored segment:
-    keep_b * ckpt * 5 * nshots * NX * NZ floats more backward workspace, the
-    forward part unchanged (host-side layout, no GPU)."""
+    """Elastic plans store the five trace planes of each stored segment and
+    need no checkpoint for it: per stored segment ckpt * 5 * nshots * NX * NZ
+    floats more backward workspace, less one 13-plane state checkpoint
+    (5 fields and 8 memory variables per shot), the forward part unchanged
+    (host-side layout, no GPU)."""
     from tests.helpers import random_el_case
     c = random_el_case(5, fs=1, nt=300, ckpt=23)
     p = c.plan()
@@ -143,6 +145,52 @@ def test_elastic_stored_segments_workspace_accounting(lib):
     nseg = -(-c.nt // c.ckpt)
     for keep in (2, nseg, nseg + 3):
         p.set_tuning(keep_b=keep)
-        want = min(keep, nseg) * c.ckpt * 5 * c.nshots * NX * NZ * 4
+        want = min(keep, nseg) * (c.ckpt * 5 - 13) * c.nshots * NX * NZ * 4
         assert abs(p.workspace_bytes(True) - w0 - want) < 4096, keep
         assert p.workspace_bytes(False) == f0
+
+
+def test_batch_membership_and_tuning_checks(lib):
+    """Batches hold any number of distinct plans of one tiling (launches carry
+    up to eight plans each), and refuse (before any device call) a forward
+    whose member changed its tiling, and a backward after a member's tuning
+    changed since the saving forward (host-side checks, no GPU)."""
+    import paper_2604_14189_amd as sw
+    from tests.helpers import random_case
+    plans = [random_case(70 + q, nx=90 + 7 * q, nz=60, nt=40, nshots=1, nrec=3, ckpt=20).plan()
+             for q in range(12)]
+    b = sw.Batch(plans)
+    assert b.workspace_bytes(True) >= sum(p.workspace_bytes(True) for p in plans)
+    with pytest.raises(sw.SweepError) as e:
+        sw.Batch([plans[0], plans[1], plans[0]])
+    assert e.value.rc == sw._lib.EINVAL
+    plans[3].set_tuning(rz=4)
+    with pytest.raises(sw.SweepError):
+        sw.Batch(plans)
+    # the batch was made for rz 8: its forward refuses the changed member
+    fake = ctypes.c_void_p(256)
+    arr = (ctypes.c_void_p * len(plans))(*([256] * len(plans)))
+    L = sw.lib()
+    rc = L.sweep_batch_forward(b._h, arr, arr, arr, fake, 1 << 40, 1, None)
+    assert rc == sw._lib.EINVAL and b"rz" in L.sweep_last_error()
+    rc = L.sweep_batch_backward(b._h, arr, arr, fake, 1 << 40, None)
+    assert rc == sw._lib.ESTATE
+
+
+def test_set_tuning_keeps_unnamed_fields(lib):
+    from tests.helpers import random_case
+    p = random_case(3, nt=40).plan()
+    p.set_tuning(rz=4, pml_rz=2, tblock=1)
+    p.set_tuning(keep_b=2)
+    t = p.tuning
+    assert (t["rz"], t["pml_rz"], t["tblock"], t["keep_b"]) == (4, 2, 1, 2)
+    p.set_tuning(rz=8)
+    assert (p.tuning["rz"], p.tuning["pml_rz"], p.tuning["keep_b"]) == (8, 4, 2)
+
+
+def test_context_outside_device_range_is_an_error(lib):
+    import paper_2604_14189_amd as sw
+    h = ctypes.c_void_p()
+    rc = sw.lib().sweep_ctx_create(ctypes.byref(h), 1 << 20)
+    assert rc in (sw._lib.EINVAL, sw._lib.EHIP) and not h.value
+    assert sw.lib().sweep_last_error()

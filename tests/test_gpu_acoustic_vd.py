@@ -89,3 +89,22 @@ def test_vd_is_the_elastic_scheme_at_vs_zero(sw):
     g1, g3 = vd.backward(r), el.backward(r)
     assert torch.equal(g1[0], g3[0]) and torch.equal(g1[1], g3[2])
     assert not torch.any(g3[1])
+
+
+@pytest.mark.parametrize("fs,keep", [(0, 3), (1, 3), (0, 99), (1, 99)])
+def test_vd_stored_segments_bitwise(sw, fs, keep):
+    """Stored traces of the last `keep` checkpoint segments (some, or all of
+    them; 260 steps in segments of 23, so the last one is ragged): gathers and
+    (vp, rho) gradients equal those of the plan that recomputes every segment,
+    bit for bit."""
+    c = _case(fs, seed=6)
+    m, wav = _dev(np.stack([c["vp"], c["rho"]])), _dev(c["wav"])
+    ref = _plan(sw, c, sw.ACOUSTIC_VD)
+    d0 = ref.forward(m, wav, save=True).clone()
+    r = _dev(np.random.default_rng(12).standard_normal(tuple(d0.shape)))
+    g0 = ref.backward(r).clone()
+    p = _plan(sw, c, sw.ACOUSTIC_VD)
+    p.set_tuning(keep_b=keep)
+    assert torch.equal(p.forward(m, wav, save=True), d0)
+    assert torch.equal(p.backward(r), g0)
+    assert torch.any(g0[0] != 0) and torch.any(g0[1] != 0)

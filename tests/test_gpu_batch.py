@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 
 import synth
-from tests.helpers import f32, random_case, rel_l2
+from tests.helpers import case_from_workload, f32, random_case, rel_l2
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -194,3 +194,93 @@ def test_autotune_picks_a_tiling_and_caches(sw, tmp_path):
     assert plan2.autotune(_dev(c.v), _dev(c.wav), steps=10, cache_path=cache) == rz
     d0 = c.plan().forward(_dev(c.v), _dev(c.wav))
     assert torch.equal(d0, d1)
+
+
+# ------------------------------------------------- the eight uneven workloads
+BATCH_GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "batch_uneven8_short.npz")
+
+
+@pytest.mark.skipif(not os.path.exists(BATCH_GOLDEN), reason="golden file not generated")
+@pytest.mark.parametrize("graph", [False, True])
+def test_batch_uneven8_against_oracle(sw, graph):
+    """The eight uneven workloads (grids 200x200 ... 1200x400 with 40-cell
+    pads, 16 ... 48 shots, 256 shots in all) in one batch with the benchmark's
+    launch configuration (rz 8, pml_rz 4, two-step passes, stored segments on
+    half of the plans), their runs shortened to 125 ... 250 steps. The middle
+    shot of each model is compared with the oracle's traces and gradient
+    samples (written by tests/golden/make_golden.py); the residual is non-zero
+    on that shot only, so the batch gradient is that shot's gradient. With a
+    captured graph, three replays with eager work between them each match."""
+    from tests.golden.make_golden import batch_short_nt
+    gold = np.load(BATCH_GOLDEN)
+    ws = synth.batched_workloads()
+    cases, plans, models, wavs, resids = [], [], [], [], []
+    for m, w in enumerate(ws):
+        nt = batch_short_nt(m)
+        assert int(gold[f"m{m}_nt"]) == nt
+        c = case_from_workload(w.replace(nt=nt))
+        p = c.plan()
+        p.set_tuning(rz=8, pml_rz=4, tblock=2, keep_b=m % 2)
+        s = int(gold[f"m{m}_shot"])
+        r = np.zeros((c.nshots, nt, c.nrec), np.float32)
+        r[s] = synth.bandlimited_noise((1, nt, w.nrec), w.f0, w.dt, 100 + m)[0]
+        cases.append(c)
+        plans.append(p)
+        models.append(_dev(c.v))
+        wavs.append(_dev(c.wav))
+        resids.append(_dev(r))
+    assert sum(c.nshots for c in cases) == 256
+    batch = sw.Batch(plans, use_graph=graph)
+    first = None
+    for rep in range(3 if graph else 1):
+        print("batch uneven8 graph", graph, "replay", rep, flush=True)
+        ds = batch.forward(models, wavs, save=True)
+        gs = batch.backward(resids)
+        torch.cuda.synchronize()
+        if first is None:
+            first = [(d.clone(), g.clone()) for d, g in zip(ds, gs)]
+            for m in range(len(ws)):
+                s = int(gold[f"m{m}_shot"])
+                tr = torch.as_tensor(gold[f"m{m}_trace_idx"], device="cuda")
+                e_d = rel_l2(ds[m][s][:, tr].double().cpu().numpy(), gold[f"m{m}_traces"])
+                g = gs[m][0].double().cpu().numpy()
+                cells = gold[f"m{m}_grad_cells"]
+                e_g = rel_l2(g.ravel()[cells], gold[f"m{m}_grad"])
+                gn = float(gold[f"m{m}_grad_norm"])
+                e_n = abs(np.linalg.norm(g) - gn) / gn
+                print("model", m, "shot", s, "traces", e_d, "gradient", e_g, "norm", e_n,
+                      flush=True)
+                assert e_d <= 1e-5 and e_g <= 1e-4 and e_n <= 1e-4, m
+        else:
+            for m in range(len(ws)):
+                assert torch.equal(ds[m], first[m][0]) and torch.equal(gs[m], first[m][1])
+        _ = (torch.randn(1000, device="cuda") * 2).sum().item()
+
+
+def test_batch_refuses_member_tuning_changes(sw):
+    """A member's tuning change after the saving forward makes the batch's
+    backward fail (its saved layout no longer holds) instead of reading
+    checkpoints the forward never wrote; a changed tiling makes the forward
+    fail; re-tuning every plan alike restores the batch's results."""
+    cases = _cases()
+    resids = _resids(cases)
+    ref = _single(cases, resids)
+    plans = [c.plan() for c in cases]
+    batch = sw.Batch(plans)
+    models, wavs = [_dev(c.v) for c in cases], [_dev(c.wav) for c in cases]
+    batch.forward(models, wavs, save=True)
+    plans[1].set_tuning(keep_b=2)
+    with pytest.raises(sw.SweepError) as e:
+        batch.backward(resids)
+    assert e.value.rc == sw._lib.ESTATE
+    plans[0].set_tuning(rz=4)
+    with pytest.raises(sw.SweepError) as e:
+        batch.forward(models, wavs, save=True)
+    assert e.value.rc == sw._lib.EINVAL
+    for p in plans:
+        p.set_tuning(rz=8)
+    ds = batch.forward(models, wavs, save=True)
+    gs = batch.backward(resids)
+    torch.cuda.synchronize()
+    for q in range(len(cases)):
+        assert torch.equal(ds[q], ref[q][0]) and torch.equal(gs[q], ref[q][1])
