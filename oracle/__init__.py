@@ -20,7 +20,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
-_SOURCES = ["acoustic.cpp", "elastic.cpp"]
+_SOURCES = ["acoustic.cpp", "elastic.cpp", "vti.cpp"]
 
 
 def build(force: bool = True) -> str:
@@ -221,3 +221,27 @@ def el_born(pb: Problem, model, dmodel, src, wavelet, rec) -> np.ndarray:
     _check(lib().orc_el_born(ctypes.byref(pb), _d(model), _d(dmodel), _i(src), _d(wavelet),
                              _i(rec), _d(out)), "el_born")
     return out
+
+
+# ---------------------------------------------------------------- VTI
+def vti_forward(pb: Problem, model, src, wavelet, rec) -> np.ndarray:
+    """model [3][nz][nx] = (vv, v, eta)."""
+    model, src, wavelet, rec = _f64(model), _i32(src), _f64(wavelet), _i32(rec)
+    out = np.zeros((pb.nshots, pb.nt, pb.nrec))
+    _check(lib().orc_vti_forward(ctypes.byref(pb), _d(model), _i(src), _d(wavelet), _i(rec),
+                                 _d(out)), "vti_forward")
+    return out
+
+
+def vti_gradient(pb: Problem, model, src, wavelet, rec, resid, want_wavelet=False,
+                 want_gathers=False):
+    """Returns (grad [3][nz][nx] = dJ/d(vv, v, eta), grad_wavelet or None, gathers or None)."""
+    model, src, wavelet, rec, resid = (_f64(model), _i32(src), _f64(wavelet), _i32(rec),
+                                       _f64(resid))
+    g = np.zeros((3, pb.nz, pb.nx))
+    gw = np.zeros((pb.nshots, pb.nt)) if want_wavelet else None
+    ga = np.zeros((pb.nshots, pb.nt, pb.nrec)) if want_gathers else None
+    _check(lib().orc_vti_gradient(ctypes.byref(pb), _d(model), _i(src), _d(wavelet), _i(rec),
+                                  _d(resid), _d(g), _d(gw) if gw is not None else None,
+                                  _d(ga) if ga is not None else None), "vti_gradient")
+    return g, gw, ga

@@ -15,7 +15,9 @@
  *     rounding), the model gradient of an L2 misfit, and the Born
  *     (tangent-linear) operator of Eq. 16;
  *   - isotropic elastic velocity-stress system (Sec. 3.5, Eq. 12) on a staggered
- *     grid, 4th order in space, C-PML, free surface; its adjoint and gradients.
+ *     grid, 4th order in space, C-PML, free surface; its adjoint and gradients;
+ *   - the pseudo-acoustic wave equation of VTI media (Sec. 3.3.1, Eq. 5) with
+ *     the acoustic scheme's operators and pad, its adjoint and gradients.
  *
  * Everything is double precision, plain loops, no blocking, no fusion. OpenMP is
  * used only over independent shots (or over rows when there is a single shot).
@@ -118,6 +120,21 @@ int orc_el_gradient(const orc_problem* pb, const double* model, const int* src_x
 int orc_el_born(const orc_problem* pb, const double* model, const double* dmodel,
                 const int* src_xz, const double* wavelet, const int* rec_xz,
                 double* dgathers);
+
+/* ---- pseudo-acoustic VTI (Sec. 3.3.1, Eq. 5) ---- */
+
+/* model = [3][nz][nx] holding vv (vertical P velocity), v (NMO velocity) and
+ * eta >= 0 (anisotropy); free_surface must be 0. The pad replicates vv and v
+ * from the edge cells and holds eta = 0. wavelet[nshots][nt]; gathers
+ * [nshots][nt][nrec] = P^{n+1} at the receivers. The scheme (both fields by
+ * leapfrog, F_xxzz = D2x D2z F) is written out in vti.cpp. */
+int orc_vti_forward(const orc_problem* pb, const double* model, const int* src_xz,
+                    const double* wavelet, const int* rec_xz, double* gathers);
+
+/* grad[3][nz][nx] = dJ/d(vv, v, eta); grad_wavelet / gathers optional. */
+int orc_vti_gradient(const orc_problem* pb, const double* model, const int* src_xz,
+                     const double* wavelet, const int* rec_xz, const double* resid,
+                     double* grad, double* grad_wavelet, double* gathers);
 
 #ifdef __cplusplus
 }
