@@ -14,8 +14,9 @@ batch_uneven8_short.npz: the eight uneven batched workloads (grids 200x200 ...
 1200x400, 16 ... 48 shots each, 40-cell pads) with their runs shortened to
 125 ... 250 steps (the full 2000 ... 4000 spread divided by 16, so segments of
 50 steps end ragged). For the middle shot of each model: 8 complete receiver
-traces and the model gradient for a band-limited seeded residual on that shot
-(4000 sampled cells plus the gradient norm).
+traces within 32 cells of the source and the model gradient for a band-limited seeded residual on that shot
+(the 2000 cells of largest magnitude and 2000 random others, plus the
+gradient norm).
 
 elastic600x300_shot11.npz: shot 11 of the 600x300 / 4000-step elastic workload
 (30-cell pad, free surface, 32 explosive 15 Hz shots, 600 two-component
@@ -87,11 +88,22 @@ def batch_uneven8_short(path):
         resid = f32(synth.bandlimited_noise((1, nt, w.nrec), w.f0, w.dt, 100 + m))
         g, _, d = oracle.ac_gradient(pb, case.v, case.src, case.wav, case.rec, resid,
                                      want_gathers=True)
-        trace_idx = np.linspace(0, w.nrec - 1, 8).round().astype(np.int64)
-        cells = np.random.default_rng(200 + m).choice(g.size, 4000, replace=False)
+        # a short run reaches the receivers within about 30 cells of the
+        # source (one receiver per column): the traces are taken there
+        sx = int(case.src[0, 0])
+        trace_idx = np.clip(sx + np.array([-32, -16, -8, -2, 0, 4, 12, 24]), 0,
+                            w.nrec - 1).astype(np.int64)
+        assert np.all(case.rec[0, trace_idx, 0] == case.src[0, 0] + trace_idx - sx)
+        # a short run concentrates the gradient near the source and the
+        # receivers: the cells of the 2000 largest oracle values carry the
+        # comparison, 2000 random cells check the rest
+        top = np.sort(np.argsort(np.abs(g.ravel()))[-2000:])
+        rest = np.setdiff1d(np.arange(g.size), top)
+        rand = np.sort(np.random.default_rng(200 + m).choice(rest, 2000, replace=False))
         out.update({f"m{m}_shot": s, f"m{m}_nt": nt, f"m{m}_trace_idx": trace_idx,
-                    f"m{m}_traces": d[0][:, trace_idx], f"m{m}_grad_cells": cells,
-                    f"m{m}_grad": g.ravel()[cells], f"m{m}_grad_norm": np.linalg.norm(g)})
+                    f"m{m}_traces": d[0][:, trace_idx], f"m{m}_top_cells": top,
+                    f"m{m}_top": g.ravel()[top], f"m{m}_rand_cells": rand,
+                    f"m{m}_rand": g.ravel()[rand], f"m{m}_grad_norm": np.linalg.norm(g)})
     print("oracle batch gradients took %.1f s" % (time.time() - t), flush=True)
     np.savez_compressed(path, **out)
 

@@ -208,7 +208,8 @@ def test_batch_uneven8_against_oracle(sw, graph):
     launch configuration (rz 8, pml_rz 4, two-step passes, stored segments on
     half of the plans), their runs shortened to 125 ... 250 steps. The middle
     shot of each model is compared with the oracle's traces and gradient
-    samples (written by tests/golden/make_golden.py); the residual is non-zero
+    samples (written by tests/golden/make_golden.py: the largest cells, and
+    random others measured against the gradient's norm); the residual is non-zero
     on that shot only, so the batch gradient is that shot's gradient. With a
     captured graph, three replays with eager work between them each match."""
     from tests.golden.make_golden import batch_short_nt
@@ -243,14 +244,19 @@ def test_batch_uneven8_against_oracle(sw, graph):
                 s = int(gold[f"m{m}_shot"])
                 tr = torch.as_tensor(gold[f"m{m}_trace_idx"], device="cuda")
                 e_d = rel_l2(ds[m][s][:, tr].double().cpu().numpy(), gold[f"m{m}_traces"])
-                g = gs[m][0].double().cpu().numpy()
-                cells = gold[f"m{m}_grad_cells"]
-                e_g = rel_l2(g.ravel()[cells], gold[f"m{m}_grad"])
+                g = gs[m][0].double().cpu().numpy().ravel()
                 gn = float(gold[f"m{m}_grad_norm"])
+                # the 2000 largest cells carry the gradient's norm; the random
+                # others' error, scaled to the cells they stand for, is their
+                # estimated share of the whole gradient's relative L2
+                e_top = rel_l2(g[gold[f"m{m}_top_cells"]], gold[f"m{m}_top"])
+                rc = gold[f"m{m}_rand_cells"]
+                e_rest = (np.linalg.norm(g[rc] - gold[f"m{m}_rand"]) *
+                          np.sqrt((g.size - 2000) / len(rc)) / gn)
                 e_n = abs(np.linalg.norm(g) - gn) / gn
-                print("model", m, "shot", s, "traces", e_d, "gradient", e_g, "norm", e_n,
-                      flush=True)
-                assert e_d <= 1e-5 and e_g <= 1e-4 and e_n <= 1e-4, m
+                print("model", m, "shot", s, "traces", e_d, "gradient top", e_top, "rest", e_rest,
+                      "norm", e_n, flush=True)
+                assert e_d <= 1e-5 and e_top <= 1e-4 and e_rest <= 1e-4 and e_n <= 1e-4, m
         else:
             for m in range(len(ws)):
                 assert torch.equal(ds[m], first[m][0]) and torch.equal(gs[m], first[m][1])
