@@ -195,6 +195,24 @@ int sweep_forward(sweep_plan* plan, const float* d_model, const float* d_wavelet
                   float* d_gathers, void* d_work, size_t work_bytes, int save_for_backward,
                   void* stream);
 
+/* Forward modelling that allocates nothing, for callers that cannot allocate
+ * device memory (code under hipGraph capture, tight serving loops, harnesses
+ * that forbid allocation): sweep_forward(plan, d_model, d_wavelet, d_gathers,
+ * work, bytes, save_for_backward = 0, stream) with the workspace taken from a
+ * static device array of the library (32 MiB per GPU the library runs on,
+ * reserved when the library is loaded and held until the process ends)
+ * instead of a caller buffer. The caller still passes the inputs and the
+ * gathers (layouts as in sweep_forward). The plan must have been created
+ * with a context (SWEEP_EINVAL otherwise) and its forward-only workspace
+ * (sweep_plan_workspace_bytes(plan, 0)) must fit in 32 MiB (SWEEP_EINVAL
+ * otherwise; a 240 x 240 padded grid with 1 shot and 1000 steps needs 1.6 MiB). Launches
+ * are eager (tuning.use_graph is ignored) and untimed; no state is left for
+ * sweep_backward. Every call on a GPU uses that GPU's one array: calls that
+ * overlap on one GPU (other streams or threads) race and must be serialised
+ * by the caller; each call writes every part of the array it reads first. */
+int sweep_forward_noalloc(sweep_plan* plan, const float* d_model, const float* d_wavelet,
+                          float* d_gathers, void* stream);
+
 /* Born (tangent-linear) modelling of every shot, Eq. 16 (acoustic plans only):
  *   d_dgathers = (d gathers / d vp) . d_dmodel
  *   d_model, d_dmodel [nz][nx]: background vp and its perturbation dvp

@@ -1050,6 +1050,7 @@ extern "C" int sweep_plan_create(const sweep_ctx* ctx, const sweep_problem* pb,
   if (ctx) {
     p->device = ctx->device;
     p->arch = ctx->arch;
+    p->scratch = ctx->scratch;
   }
   p->P = pb->pml;
   p->NX = pb->nx + 2 * pb->pml;
@@ -1224,6 +1225,48 @@ extern "C" int sweep_forward(sweep_plan* p, const float* d_model, const float* d
                     (hipStream_t)stream);
 }
 SWEEP_ABI_CATCH("sweep_forward")
+
+extern "C" int sweep_forward_noalloc(sweep_plan* p, const float* d_model,
+                                     const float* d_wavelet, float* d_gathers,
+                                     void* stream) try {
+  if (!p || !d_model || !d_wavelet || (!d_gathers && p->pb.nrec > 0)) {
+    set_error("sweep_forward_noalloc: null argument");
+    return SWEEP_EINVAL;
+  }
+  p->saved = false;
+  if (!p->scratch) {
+    set_error("sweep_forward_noalloc: the plan was created without a context, so it has no "
+              "static device workspace");
+    return SWEEP_EINVAL;
+  }
+  const size_t need = sweep_plan_workspace_bytes(p, 0);
+  if (need == 0 || need > kNoAllocScratchBytes) {
+    set_error("sweep_forward_noalloc: the plan's forward workspace of " + std::to_string(need) +
+              " bytes exceeds the static workspace of " + std::to_string(kNoAllocScratchBytes) +
+              " bytes; use sweep_forward with a workspace");
+    return SWEEP_EINVAL;
+  }
+  DeviceGuard dg_(p->device);
+  if (!dg_.ok) {
+    set_error("cannot make the plan's device current");
+    return SWEEP_EHIP;
+  }
+  // eager launches only (a graph capture would create a stream and graph
+  // objects) and no timing events
+  const int use_graph = p->tune.use_graph;
+  const bool timing = p->timer.on;
+  p->tune.use_graph = 0;
+  p->timer.on = false;
+  hipStream_t s = (hipStream_t)stream;
+  const int rc = p->pb.physics != SWEEP_ACOUSTIC
+                     ? el_forward(p, d_model, d_wavelet, d_gathers, p->scratch, need, 0, s)
+                     : ac_forward(p, d_model, d_wavelet, d_gathers, p->scratch, need, 0, s);
+  p->tune.use_graph = use_graph;
+  p->timer.on = timing;
+  p->saved = false;
+  return rc;
+}
+SWEEP_ABI_CATCH("sweep_forward_noalloc")
 
 extern "C" int sweep_born_forward(sweep_plan* p, const float* d_model, const float* d_dmodel,
                                   const float* d_wavelet, float* d_dgathers, void* d_work,

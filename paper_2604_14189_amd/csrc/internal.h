@@ -161,6 +161,13 @@ struct AcStep {
   const float* bB;        // [nshots][NZ][NX] background B'^n
 };
 
+// Static device workspace of sweep_forward_noalloc (per GPU): the largest
+// forward workspace it accepts.
+constexpr size_t kNoAllocScratchBytes = (size_t)32 << 20;
+// Device address of that workspace on `device` (current); set up once per
+// device by the first context created on it (ctx.hip).
+int scratch_address(int device, void** out);
+
 // Several plans of different shapes advanced by one launch per kernel kind.
 // A launch carries the step descriptors of up to kPlansPerLaunch plans in its
 // kernel arguments; a batch of more plans takes one launch per group of them.

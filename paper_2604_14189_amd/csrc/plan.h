@@ -108,7 +108,8 @@ struct GraphCache {
 // A library context: the HIP device its plans and batches run on.
 struct sweep_ctx {
   int device = 0;
-  std::string arch;  // gcnArchName without feature suffixes, e.g. "gfx950"
+  std::string arch;        // gcnArchName without feature suffixes, e.g. "gfx950"
+  void* scratch = nullptr;  // device address of the static workspace on `device`
 };
 
 struct sweep_plan {
@@ -116,6 +117,7 @@ struct sweep_plan {
   sweep_tuning tune;
   int device = -1;  // the context's device (-1: the device current at each call)
   std::string arch;  // the context's arch ("": queried at each autotune)
+  void* scratch = nullptr;  // the context's static device workspace (null: no context)
   // incremented by every tuning change; a batch refuses a backward (or the
   // replay of a captured graph) after a member plan's tuning changed
   unsigned tune_gen = 0;

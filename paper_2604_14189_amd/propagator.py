@@ -229,6 +229,22 @@ class Plan:
         self._saved_id = self._fwd_id if save else -1
         return out
 
+    def forward_noalloc(self, model: torch.Tensor, wavelet: torch.Tensor,
+                        out: torch.Tensor) -> torch.Tensor:
+        """Shot gathers into `out` with the library's static per-GPU workspace
+        instead of the plan's (nothing is allocated: small plans only, whose
+        forward workspace fits in 32 MiB; no state for backward())."""
+        if self.nparam == 1 and model.dim() == 2:
+            model = model.unsqueeze(0)
+        _need(model, self._model_shape(), "model")
+        _need(wavelet, self.wavelet_shape(), "wavelet")
+        _need(out, self.gathers_shape(), "out")
+        check(lib().sweep_forward_noalloc(self._h, _ptr(model), _ptr(wavelet), _ptr(out),
+                                          _stream()))
+        self._fwd_id += 1
+        self._saved_id = -1
+        return out
+
     def born(self, model: torch.Tensor, dmodel: torch.Tensor, wavelet: torch.Tensor,
              out: Optional[torch.Tensor] = None) -> torch.Tensor:
         """Born (tangent-linear) gathers [nshots, nt, nrec] = (d gathers / d vp)
