@@ -58,12 +58,25 @@ extern "C" {
  * (vp, rho), gathers (vx, vz), gradients (vp, rho); free_surface = 1 is the
  * pressure-release top. */
 #define SWEEP_ACOUSTIC_VD 2
+/* Eq. 5: pseudo-acoustic wave equation of VTI media, P_tt = (1 + 2 eta) v^2 P_xx
+ * + vv^2 P_zz - 2 eta v^2 vv^2 F_xxzz with P = F_tt (v the NMO velocity, vv the
+ * vertical velocity, eta >= 0 the anisotropy parameter). Both fields advance by
+ * the leapfrog of the acoustic scheme with its 8th-order operators (F_xxzz as
+ * D2x D2z F) and per-axis C-PML; the pad replicates vv and v and holds
+ * eta = 0 (an elliptic absorbing layer). Model (vv, v, eta), gathers P,
+ * gradients (vv, v, eta). pml_vmax must be at least the fastest horizontal
+ * speed v sqrt(1 + 2 eta) (the Courant limit is the acoustic one); eta < 0 is
+ * not supported (the scheme's two modes would not stay real). 64 x 16 tiles,
+ * single steps: tuning.rz must stay 4, keep_b 0 and use_graph 0. The source
+ * should sit where eta = 0, as the formulation asks (the paper's figure shows
+ * the artificial mode it otherwise excites). */
+#define SWEEP_VTI 3
 
 /* Problem description. The padded grid adds `pml` absorbing cells on each side
  * (and none on top when free_surface = 1, elastic only); the model is
  * replicated from its edge cells into the pad. */
 typedef struct {
-  int physics;      /* SWEEP_ACOUSTIC, SWEEP_ELASTIC or SWEEP_ACOUSTIC_VD */
+  int physics;      /* SWEEP_ACOUSTIC, SWEEP_ELASTIC, SWEEP_ACOUSTIC_VD or SWEEP_VTI */
   int nx, nz;       /* model grid (cells) */
   int pml;          /* absorbing pad width (cells), >= 0 */
   int free_surface; /* elastic: 1 = traction-free top row (acoustic_vd: p = 0
@@ -182,9 +195,9 @@ int sweep_plan_tiles(const sweep_plan* plan, int* interior_tiles, int* frame_til
 
 /* Forward modelling of every shot.
  *   d_model   [nparam][nz][nx]: acoustic vp (nparam 1); elastic vp, vs, rho (3);
- *             acoustic_vd vp, rho (2)
+ *             acoustic_vd vp, rho (2); vti vv, v, eta (3)
  *   d_wavelet [nshots][nt]: source time function, sample n injected at step n
- *   d_gathers [nshots][nt][nrec][ncomp] out: acoustic p (ncomp 1) at step n+1;
+ *   d_gathers [nshots][nt][nrec][ncomp] out: acoustic and vti p (ncomp 1) at step n+1;
  *             elastic (vx, vz) (ncomp 2)
  *   d_work    workspace of at least sweep_plan_workspace_bytes(plan, save) bytes
  *   save_for_backward: 1 stores checkpoints every ckpt_every steps in d_work

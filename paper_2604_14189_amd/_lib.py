@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsweep.so")
 
 OK, EINVAL, EHIP, ENOMEM, ECFL, ESTATE = 0, -1, -2, -3, -4, -5
-ACOUSTIC, ELASTIC, ACOUSTIC_VD = 0, 1, 2
+ACOUSTIC, ELASTIC, ACOUSTIC_VD, VTI = 0, 1, 2, 3
 
 
 class SweepError(RuntimeError):

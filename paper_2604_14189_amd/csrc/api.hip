@@ -1020,7 +1020,7 @@ extern "C" int sweep_plan_create(const sweep_ctx* ctx, const sweep_problem* pb,
   }
   *out = nullptr;
   if (pb->physics != SWEEP_ACOUSTIC && pb->physics != SWEEP_ELASTIC &&
-      pb->physics != SWEEP_ACOUSTIC_VD) {
+      pb->physics != SWEEP_ACOUSTIC_VD && pb->physics != SWEEP_VTI) {
     set_error("unknown physics");
     return SWEEP_EINVAL;
   }
@@ -1030,12 +1030,13 @@ extern "C" int sweep_plan_create(const sweep_ctx* ctx, const sweep_problem* pb,
     set_error("sweep_plan_create: invalid sizes or constants");
     return SWEEP_EINVAL;
   }
-  if (pb->physics == SWEEP_ACOUSTIC && pb->free_surface) {
+  if ((pb->physics == SWEEP_ACOUSTIC || pb->physics == SWEEP_VTI) && pb->free_surface) {
     set_error("free_surface is only supported for the elastic physics");
     return SWEEP_EINVAL;
   }
   const double cfl = (double)pb->pml_vmax * pb->dt / pb->h;
-  const double limit = pb->physics == SWEEP_ACOUSTIC ? 0.5546 : 0.6061;
+  const double limit =
+      pb->physics == SWEEP_ACOUSTIC || pb->physics == SWEEP_VTI ? 0.5546 : 0.6061;
   if (cfl > limit) {
     set_error("CFL number " + std::to_string(cfl) + " exceeds the stability limit " +
               std::to_string(limit));
@@ -1104,7 +1105,12 @@ extern "C" int sweep_plan_create(const sweep_ctx* ctx, const sweep_problem* pb,
   p->tune.tblock = 2;
   p->tune.use_graph = 0;
   p->tune.keep_b = 0;
-  if (pb->physics == SWEEP_ACOUSTIC) {
+  if (pb->physics == SWEEP_VTI) {
+    // 64 x 16 tiles: the tile CSR of the receivers is that of rz = 4
+    p->tune.rz = 4;
+    p->tune.tblock = 1;
+    ac_build_tiling(p);
+  } else if (pb->physics == SWEEP_ACOUSTIC) {
     ac_build_tiling(p);
   } else {
     el_build_tables(p);
@@ -1137,9 +1143,13 @@ extern "C" int sweep_plan_set_tuning(sweep_plan* p, const sweep_tuning* t) try {
     set_error("unsupported tuning");
     return SWEEP_EINVAL;
   }
+  if (p->pb.physics == SWEEP_VTI && (t->rz != 4 || t->keep_b != 0 || t->use_graph != 0)) {
+    set_error("VTI plans take 64 x 16 tiles (rz 4), no stored segments and no graph capture");
+    return SWEEP_EINVAL;
+  }
   p->tune = *t;
   ++p->tune_gen;
-  if (p->pb.physics == SWEEP_ACOUSTIC) ac_build_tiling(p);
+  if (p->pb.physics == SWEEP_ACOUSTIC || p->pb.physics == SWEEP_VTI) ac_build_tiling(p);
   p->saved = false;
   p->gfwd.reset();
   p->gbwd.reset();
@@ -1159,6 +1169,11 @@ SWEEP_ABI_CATCH("sweep_plan_get_tuning")
 
 extern "C" size_t sweep_plan_workspace_bytes(const sweep_plan* p, int for_backward) try {
   if (!p) return 0;
+  if (p->pb.physics == SWEEP_VTI) {
+    VtiLayout V;
+    vti_layout(p, V);
+    return for_backward ? V.bwd_end : V.fwd_end;
+  }
   if (p->pb.physics != SWEEP_ACOUSTIC) {
     ElLayout E;
     el_layout(p, E);
@@ -1218,6 +1233,9 @@ extern "C" int sweep_forward(sweep_plan* p, const float* d_model, const float* d
     return SWEEP_EHIP;
   }
   p->saved = false;
+  if (p->pb.physics == SWEEP_VTI)
+    return vti_forward(p, d_model, d_wavelet, d_gathers, d_work, work_bytes, save_for_backward,
+                       (hipStream_t)stream);
   if (p->pb.physics != SWEEP_ACOUSTIC)
     return el_forward(p, d_model, d_wavelet, d_gathers, d_work, work_bytes, save_for_backward,
                       (hipStream_t)stream);
@@ -1258,9 +1276,12 @@ extern "C" int sweep_forward_noalloc(sweep_plan* p, const float* d_model,
   p->tune.use_graph = 0;
   p->timer.on = false;
   hipStream_t s = (hipStream_t)stream;
-  const int rc = p->pb.physics != SWEEP_ACOUSTIC
-                     ? el_forward(p, d_model, d_wavelet, d_gathers, p->scratch, need, 0, s)
-                     : ac_forward(p, d_model, d_wavelet, d_gathers, p->scratch, need, 0, s);
+  const int rc =
+      p->pb.physics == SWEEP_VTI
+          ? vti_forward(p, d_model, d_wavelet, d_gathers, p->scratch, need, 0, s)
+      : p->pb.physics != SWEEP_ACOUSTIC
+          ? el_forward(p, d_model, d_wavelet, d_gathers, p->scratch, need, 0, s)
+          : ac_forward(p, d_model, d_wavelet, d_gathers, p->scratch, need, 0, s);
   p->tune.use_graph = use_graph;
   p->timer.on = timing;
   p->saved = false;
@@ -1301,6 +1322,8 @@ extern "C" int sweep_backward(sweep_plan* p, const float* d_resid, float* d_grad
     set_error("cannot make the plan's device current");
     return SWEEP_EHIP;
   }
+  if (p->pb.physics == SWEEP_VTI)
+    return vti_backward(p, d_resid, d_grad, d_work, work_bytes, (hipStream_t)stream);
   if (p->pb.physics != SWEEP_ACOUSTIC)
     return el_backward(p, d_resid, d_grad, d_work, work_bytes, (hipStream_t)stream);
   return ac_backward(p, d_resid, d_grad, d_work, work_bytes, (hipStream_t)stream);
@@ -1547,7 +1570,7 @@ std::string tune_key(const sweep_plan* p) {
       hipGetDeviceProperties(&prop, dev) == hipSuccess)
     arch = std::string(prop.gcnArchName).substr(0, std::string(prop.gcnArchName).find(':'));
   std::ostringstream os;
-  os << arch << " " << (p->pb.physics == SWEEP_ACOUSTIC ? "acoustic" : "elastic") << " " << p->NX
+  os << arch << " " << (p->pb.physics == SWEEP_ACOUSTIC ? "acoustic" : "other") << " " << p->NX
      << " " << p->NZ << " " << p->pb.nshots;
   return os.str();
 }

@@ -184,6 +184,9 @@ struct AcBatch {
 int ac_launch_prep(const float* v, float* vpad, float* Cs, float* ax, float* bx, float* az,
                    float* bz, int nx, int nz, int P, double h, double dt, double vmax,
                    double f0, double R, hipStream_t s);
+// C-PML tables a, b along x (NX) and z (NZ) of an acoustic-type padded grid.
+int ac_launch_tables(float* ax, float* bx, float* az, float* bz, int NX, int NZ, int P,
+                     double h, double dt, double vmax, double f0, double R, hipStream_t s);
 int ac_launch_fwd(const AcStep& a, int rz, int prz, hipStream_t s, hipEvent_t* ev);
 int ac_launch_adj(const AcStep& a, int rz, int prz, hipStream_t s, hipEvent_t* ev);
 // Born perturbation step (a.bdC, a.bB set; single steps over all tile sets)

@@ -87,6 +87,22 @@ struct ElLayout {
 }  // namespace sweep
 
 namespace sweep {
+// Pseudo-acoustic VTI plan: fields P (float32) and G = F / dt^2 (float64), two
+// buffers each (the new level overwriting the oldest), C-PML strips as in the
+// acoustic layout.
+struct VtiLayout {
+  size_t plane, xs, zs, aux_elems;
+  size_t ax, bx, az, bz, pad, cx, cz, cm, wav, src_cell, rec_cell, rec_off, rec_ent;
+  size_t pf[2], gf[2], aux[2];
+  size_t fwd_end;
+  int nseg;
+  size_t slot_elems;  // checkpoint (floats): P^n, P^{n-1}, G^n, G^{n-1} (2 each), memory variables
+  size_t ck, tr, lf[2], mf[2], adjaux[2], gpart, tot;
+  size_t bwd_end;
+};
+}  // namespace sweep
+
+namespace sweep {
 // An instantiated hipGraph of a forward or backward call, reused while the
 // pointers it was captured with are unchanged.
 struct GraphCache {
@@ -162,6 +178,11 @@ int el_forward(sweep_plan* p, const float* model, const float* wavelet, float* g
                void* work, size_t bytes, int save, hipStream_t s);
 int el_backward(sweep_plan* p, const float* resid, float* grad, void* work, size_t bytes,
                 hipStream_t s);
+void vti_layout(const sweep_plan* p, VtiLayout& L);
+int vti_forward(sweep_plan* p, const float* model, const float* wavelet, float* gathers,
+                void* work, size_t bytes, int save, hipStream_t s);
+int vti_backward(sweep_plan* p, const float* resid, float* grad, void* work, size_t bytes,
+                 hipStream_t s);
 }  // namespace sweep
 
 struct sweep_batch {

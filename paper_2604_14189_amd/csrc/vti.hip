@@ -1,0 +1,485 @@
+// Pseudo-acoustic VTI step kernels for gfx950 (Sec. 3.3.1, Eq. 5): the
+// acoustic scheme's 8th-order operators and per-axis C-PML with separate x and
+// z coefficients, the auxiliary field G = F / dt^2 advanced by the same
+// leapfrog, and the mixed term D2x' D2z' G; then the exact transpose for the
+// adjoint. Scaled form and data layout: vti.h.
+//
+// One work-group of 256 lanes takes one 64 x 16 tile of one shot. It stages
+// P^n with an 8-cell halo and G^n with a 4-cell halo in LDS (all global loads
+// of a lane are issued before its first LDS store), computes the C-PML memory
+// variables psi on a 4-cell ring only when a strip lies within 4 cells (a
+// block-uniform test), D2z' G on the tile rows and a 4-column ring, and then
+// each lane finishes its four cells from LDS. P^{n+1} and G^{n+1} overwrite
+// P^{n-1} and G^{n-1} at the lane's own cells (each is read there only).
+#include "fd.h"
+#include "internal.h"
+#include "vti.h"
+
+namespace sweep {
+namespace {
+
+constexpr int kTZ = kVtiTZ;            // tile rows
+constexpr int kRZ = kTZ / 4;           // rows per lane
+constexpr int PW = kTX + 16;           // 8-cell-halo box: 80 x 32
+constexpr int PH = kTZ + 16;
+constexpr int GW = kTX + 8;            // 4-cell-halo box: 72 x 24
+constexpr int GH = kTZ + 8;
+
+__device__ __forceinline__ bool in_grid(int gx, int gz, int NX, int NZ) {
+  return gx >= 0 && gx < NX && gz >= 0 && gz < NZ;
+}
+
+// Stage field f on the box [x0 - hx, x0 + 64 + hx) x [z0 - hz, z0 + 16 + hz)
+// of W x H cells, zero outside the grid; all loads of a lane first, then its
+// LDS stores.
+template <int W, int H, class T>
+__device__ __forceinline__ void stage(T* s, const T* __restrict__ f, int x0, int z0, int hx,
+                                      int hz, int NX, int NZ) {
+  constexpr int N = W * H;
+  constexpr int K = (N + kThreads - 1) / kThreads;
+  T v[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int e = threadIdx.x + k * kThreads;
+    const int r = e / W, c = e - r * W;
+    const int gx = x0 - hx + c, gz = z0 - hz + r;
+    const bool ok = e < N && in_grid(gx, gz, NX, NZ);
+    v[k] = ok ? f[(size_t)gz * NX + gx] : T(0);
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int e = threadIdx.x + k * kThreads;
+    if (e < N) s[e] = v[k];
+  }
+}
+
+// 8th-order centred-difference second derivative in float64 (for G).
+__device__ __forceinline__ double d2d(const double* f, int st) {
+  const double c = f[0];
+  double s = (8.0 / 5.0) * ((f[st] - c) + (f[-st] - c));
+  s = fma(-1.0 / 5.0, (f[2 * st] - c) + (f[-2 * st] - c), s);
+  s = fma(8.0 / 315.0, (f[3 * st] - c) + (f[-3 * st] - c), s);
+  return fma(-1.0 / 560.0, (f[4 * st] - c) + (f[-4 * st] - c), s);
+}
+
+// Receivers of (shot, tile) record the staged values st[local] (64 x 16).
+__device__ __forceinline__ void vti_record(const VtiStep& a, int shot, int tile,
+                                           const float* st) {
+  const int* ro = a.rec_off + (size_t)shot * a.ntiles + tile;
+  float* dst = a.gathers + ((size_t)shot * a.nt + a.n) * a.nrec;
+  for (int e = ro[0] + (int)threadIdx.x; e < ro[1]; e += kThreads) {
+    const int2 en = a.rec_ent[e];
+    dst[en.y] = st[en.x];
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void vti_fwd_kernel(VtiStep a) {
+  __shared__ float sP[PH * PW];    // P^n, 8-cell halo
+  __shared__ double sG[GH * GW];   // G^n (float64), 4-cell halo
+  __shared__ double sT[kTZ * GW];  // D2z' G^n on the tile rows, 4-column ring
+  __shared__ float sX[kTZ * GW];  // psi_x^n on the tile rows, 4-column ring
+  __shared__ float sZ[GH * kTX];  // psi_z^n on the tile columns, 4-row ring
+  const int f = xcd_spread(blockIdx.x, gridDim.x);
+  const int shot = f / a.ntiles, tile = f - shot * a.ntiles;
+  const int NX = a.NX, NZ = a.NZ, P = a.P, P2 = 2 * a.P;
+  const size_t plane = (size_t)NX * NZ, base = (size_t)shot * plane;
+  const int x0 = (tile % a.tiles_x) * kTX, z0 = (tile / a.tiles_x) * kTZ;
+  const int tid = threadIdx.x, lx = tid & 63, zb = (tid >> 6) * kRZ;
+  const bool hx = P > 0 && (x0 - 4 < P || x0 + kTX + 4 > NX - P);
+  const bool hz = P > 0 && (z0 - 4 < P || z0 + kTZ + 4 > NZ - P);
+  const int gx = x0 + lx;
+  const int xcol = gx < NX ? xstrip_col(gx, NX, P) : -1;
+
+  // own cells: old values, coefficients, zeta^{n-1}
+  float pold[kRZ], ccx[kRZ], ccz[kRZ], ccm[kRZ], zx[kRZ], zz[kRZ];
+  double gold[kRZ];
+#pragma unroll
+  for (int r = 0; r < kRZ; ++r) {
+    const int gz = z0 + zb + r;
+    const bool ok = gx < NX && gz < NZ;
+    const size_t idx = ok ? (size_t)gz * NX + gx : 0;
+    pold[r] = ok ? ld_nt(a.prev + base + idx) : 0.0f;
+    gold[r] = ok ? __builtin_nontemporal_load(a.gprev + base + idx) : 0.0;
+    ccx[r] = ok ? a.cx[idx] : 0.0f;
+    ccz[r] = ok ? a.cz[idx] : 0.0f;
+    ccm[r] = ok ? a.cm[idx] : 0.0f;
+    const int zrow = ok ? zstrip_row(gz, NZ, P) : -1;
+    zx[r] = ok && xcol >= 0 ? a.zex_in[((size_t)shot * NZ + gz) * P2 + xcol] : 0.0f;
+    zz[r] = zrow >= 0 ? a.zez_in[((size_t)shot * P2 + zrow) * NX + gx] : 0.0f;
+  }
+  stage<PW, PH>(sP, a.cur + base, x0, z0, 8, 8, NX, NZ);
+  stage<GW, GH>(sG, a.gcur + base, x0, z0, 4, 4, NX, NZ);
+  __syncthreads();
+
+  // psi^n = b psi^{n-1} + a D1' P^n on the rings (zero outside the strips)
+  if (hx) {
+    for (int e = tid; e < kTZ * GW; e += kThreads) {
+      const int r = e / GW, c = e - r * GW;
+      const int x = x0 - 4 + c, z = z0 + r;
+      const int col = in_grid(x, z, NX, NZ) ? xstrip_col(x, NX, P) : -1;
+      float psi = 0.0f;
+      if (col >= 0) {
+        const size_t si = ((size_t)shot * NZ + z) * P2 + col;
+        psi = fmaf(a.bx[x], a.psx_in[si], a.ax[x] * d1s(&sP[(r + 8) * PW + c + 4], 1));
+        if (c >= 4 && c < 4 + kTX) a.psx_out[si] = psi;
+      }
+      sX[e] = psi;
+    }
+  }
+  if (hz) {
+    for (int e = tid; e < GH * kTX; e += kThreads) {
+      const int r = e / kTX, c = e - r * kTX;
+      const int x = x0 + c, z = z0 - 4 + r;
+      const int row = in_grid(x, z, NX, NZ) ? zstrip_row(z, NZ, P) : -1;
+      float psi = 0.0f;
+      if (row >= 0) {
+        const size_t si = ((size_t)shot * P2 + row) * NX + x;
+        psi = fmaf(a.bz[z], a.psz_in[si], a.az[z] * d1s(&sP[(r + 4) * PW + c + 8], PW));
+        if (r >= 4 && r < 4 + kTZ) a.psz_out[si] = psi;
+      }
+      sZ[e] = psi;
+    }
+  }
+  for (int e = tid; e < kTZ * GW; e += kThreads) {
+    const int r = e / GW, c = e - r * GW;
+    sT[e] = d2d(&sG[(r + 4) * GW + c], GW);
+  }
+  __syncthreads();
+
+  const int src = a.src_cell[shot];
+  const float sw = a.w * a.wavelet[(size_t)shot * a.nt + a.n];
+  float out[kRZ];
+#pragma unroll
+  for (int rr = 0; rr < kRZ; ++rr) {
+    const int r = zb + rr, gz = z0 + r;
+    const bool ok = gx < NX && gz < NZ;
+    const size_t idx = ok ? (size_t)gz * NX + gx : 0;
+    const float* pc = &sP[(r + 8) * PW + lx + 8];
+    const float p0 = pc[0];
+    float qx = d2s(pc, 1), qz = d2s(pc, PW);
+    if (hx) qx += d1s(&sX[r * GW + lx + 4], 1);
+    if (hz) qz += d1s(&sZ[(r + 4) * kTX + lx], kTX);
+    float bxv = qx, bzv = qz;
+    if (ok && xcol >= 0) {
+      const float zn = fmaf(a.bx[gx], zx[rr], a.ax[gx] * qx);
+      a.zex_out[((size_t)shot * NZ + gz) * P2 + xcol] = zn;
+      bxv = qx + zn;
+    }
+    const int zrow = ok ? zstrip_row(gz, NZ, P) : -1;
+    if (zrow >= 0) {
+      const float zn = fmaf(a.bz[gz], zz[rr], a.az[gz] * qz);
+      a.zez_out[((size_t)shot * P2 + zrow) * NX + gx] = zn;
+      bzv = qz + zn;
+    }
+    const float m = (float)d2d(&sT[r * GW + lx + 4], 1);
+    float pn = 2.0f * p0 - pold[rr];
+    pn = fmaf(ccx[rr], bxv, pn);
+    pn = fmaf(ccz[rr], bzv, pn);
+    pn = fmaf(-ccm[rr], m, pn);
+    if (ok && (int)idx == src) pn += sw;
+    const double g0 = sG[(r + 4) * GW + lx + 4];
+    const double gn = (2.0 * g0 - gold[rr]) + (double)p0;
+    out[rr] = pn;
+    if (ok) {
+      st_nt(a.prev + base + idx, pn);
+      __builtin_nontemporal_store(gn, a.gprev + base + idx);
+      if (a.tr[0]) {
+        st_nt(a.tr[0] + base + idx, bxv);
+        st_nt(a.tr[1] + base + idx, bzv);
+        st_nt(a.tr[2] + base + idx, m);
+      }
+    }
+  }
+  const int* ro = a.rec_off + (size_t)shot * a.ntiles + tile;
+  if (a.gathers && ro[1] > ro[0]) {
+    __syncthreads();
+#pragma unroll
+    for (int rr = 0; rr < kRZ; ++rr) sP[(zb + rr) * kTX + lx] = out[rr];
+    __syncthreads();
+    vti_record(a, shot, tile, sP);
+  }
+}
+
+// Reverse of step n (exact transpose of the forward kernel). With
+// lambda^{n+1} = P1: qx = cx P1, Qbar_x = qx + a_x (Z_x + qx) in the x strip
+// (qx elsewhere) on the tile rows and an 8-column ring; psbar_x = Psi_x -
+// D1x' Qbar_x and T_x = a_x psbar_x on a 4-column ring; z likewise with cz;
+//   lambda^n = 2 P1 - lambda^{n+2} + D2x' Qbar_x + D2z' Qbar_z - D1x' T_x - D1z' T_z + mu^{n+1},
+//   mu^n     = 2 mu^{n+1} - mu^{n+2} - D2x' D2z' (cm P1),
+// Psi = b psbar, Z = b (Z + q); g += P1 (Bx', Bz', -D2x'D2z'G^n); then r_{n-1}
+// is added at the receivers.
+__global__ __launch_bounds__(kThreads) void vti_adj_kernel(VtiStep a) {
+  __shared__ float sL[PH * PW];    // lambda^{n+1}, 8-cell halo; staging at the end
+  __shared__ float sQx[kTZ * PW];  // Qbar_x on the tile rows, 8-column ring
+  __shared__ float sQz[PH * kTX];  // Qbar_z on the tile columns, 8-row ring
+  __shared__ double sM[GH * GW];   // cm lambda^{n+1} (float64), 4-cell halo
+  __shared__ double sU[kTZ * GW];  // D2z'(cm lambda^{n+1}) on the tile rows, 4-column ring
+  __shared__ float sTx[kTZ * GW];  // T_x on the tile rows, 4-column ring
+  __shared__ float sTz[GH * kTX];  // T_z on the tile columns, 4-row ring
+  const int f = xcd_spread(blockIdx.x, gridDim.x);
+  const int shot = f / a.ntiles, tile = f - shot * a.ntiles;
+  const int NX = a.NX, NZ = a.NZ, P = a.P, P2 = 2 * a.P;
+  const size_t plane = (size_t)NX * NZ, base = (size_t)shot * plane;
+  const int x0 = (tile % a.tiles_x) * kTX, z0 = (tile / a.tiles_x) * kTZ;
+  const int tid = threadIdx.x, lx = tid & 63, zb = (tid >> 6) * kRZ;
+  const bool hx = P > 0 && (x0 - 4 < P || x0 + kTX + 4 > NX - P);
+  const bool hz = P > 0 && (z0 - 4 < P || z0 + kTZ + 4 > NZ - P);
+  const int gx = x0 + lx;
+  const int xcol = gx < NX ? xstrip_col(gx, NX, P) : -1;
+
+  float l2[kRZ], ccx[kRZ], ccz[kRZ], zx[kRZ], zz[kRZ], t0[kRZ], t1[kRZ], t2[kRZ];
+  double m1[kRZ], m2[kRZ];
+#pragma unroll
+  for (int r = 0; r < kRZ; ++r) {
+    const int gz = z0 + zb + r;
+    const bool ok = gx < NX && gz < NZ;
+    const size_t idx = ok ? (size_t)gz * NX + gx : 0;
+    l2[r] = ok ? ld_nt(a.prev + base + idx) : 0.0f;
+    m1[r] = ok ? a.mcur[base + idx] : 0.0;
+    m2[r] = ok ? __builtin_nontemporal_load(a.mprev + base + idx) : 0.0;
+    ccx[r] = ok ? a.cx[idx] : 0.0f;
+    ccz[r] = ok ? a.cz[idx] : 0.0f;
+    t0[r] = ok ? ld_nt(a.trc[0] + base + idx) : 0.0f;
+    t1[r] = ok ? ld_nt(a.trc[1] + base + idx) : 0.0f;
+    t2[r] = ok ? ld_nt(a.trc[2] + base + idx) : 0.0f;
+    const int zrow = ok ? zstrip_row(gz, NZ, P) : -1;
+    zx[r] = ok && xcol >= 0 ? a.zex_in[((size_t)shot * NZ + gz) * P2 + xcol] : 0.0f;
+    zz[r] = zrow >= 0 ? a.zez_in[((size_t)shot * P2 + zrow) * NX + gx] : 0.0f;
+  }
+  stage<PW, PH>(sL, a.cur + base, x0, z0, 8, 8, NX, NZ);
+  __syncthreads();
+
+  // products with the coefficients, and the x / z memory terms of Qbar
+  for (int e = tid; e < kTZ * PW; e += kThreads) {
+    const int r = e / PW, c = e - r * PW;
+    const int x = x0 - 8 + c, z = z0 + r;
+    float q = 0.0f;
+    if (in_grid(x, z, NX, NZ)) {
+      q = a.cx[(size_t)z * NX + x] * sL[(r + 8) * PW + c];
+      const int col = hx ? xstrip_col(x, NX, P) : -1;
+      if (col >= 0) q = q + a.ax[x] * (a.zex_in[((size_t)shot * NZ + z) * P2 + col] + q);
+    }
+    sQx[e] = q;
+  }
+  for (int e = tid; e < PH * kTX; e += kThreads) {
+    const int r = e / kTX, c = e - r * kTX;
+    const int x = x0 + c, z = z0 - 8 + r;
+    float q = 0.0f;
+    if (in_grid(x, z, NX, NZ)) {
+      q = a.cz[(size_t)z * NX + x] * sL[r * PW + c + 8];
+      const int row = hz ? zstrip_row(z, NZ, P) : -1;
+      if (row >= 0) q = q + a.az[z] * (a.zez_in[((size_t)shot * P2 + row) * NX + x] + q);
+    }
+    sQz[e] = q;
+  }
+  for (int e = tid; e < GH * GW; e += kThreads) {
+    const int r = e / GW, c = e - r * GW;
+    const int x = x0 - 4 + c, z = z0 - 4 + r;
+    sM[e] = in_grid(x, z, NX, NZ)
+                ? (double)a.cm[(size_t)z * NX + x] * (double)sL[(r + 4) * PW + c + 4]
+                : 0.0;
+  }
+  __syncthreads();
+
+  if (hx) {
+    for (int e = tid; e < kTZ * GW; e += kThreads) {
+      const int r = e / GW, c = e - r * GW;
+      const int x = x0 - 4 + c, z = z0 + r;
+      const int col = in_grid(x, z, NX, NZ) ? xstrip_col(x, NX, P) : -1;
+      float t = 0.0f;
+      if (col >= 0) {
+        const size_t si = ((size_t)shot * NZ + z) * P2 + col;
+        const float psb = a.psx_in[si] - d1s(&sQx[r * PW + c + 4], 1);
+        t = a.ax[x] * psb;
+        if (c >= 4 && c < 4 + kTX) a.psx_out[si] = a.bx[x] * psb;
+      }
+      sTx[e] = t;
+    }
+  }
+  if (hz) {
+    for (int e = tid; e < GH * kTX; e += kThreads) {
+      const int r = e / kTX, c = e - r * kTX;
+      const int x = x0 + c, z = z0 - 4 + r;
+      const int row = in_grid(x, z, NX, NZ) ? zstrip_row(z, NZ, P) : -1;
+      float t = 0.0f;
+      if (row >= 0) {
+        const size_t si = ((size_t)shot * P2 + row) * NX + x;
+        const float psb = a.psz_in[si] - d1s(&sQz[(r + 4) * kTX + c], kTX);
+        t = a.az[z] * psb;
+        if (r >= 4 && r < 4 + kTZ) a.psz_out[si] = a.bz[z] * psb;
+      }
+      sTz[e] = t;
+    }
+  }
+  for (int e = tid; e < kTZ * GW; e += kThreads) {
+    const int r = e / GW, c = e - r * GW;
+    sU[e] = d2d(&sM[(r + 4) * GW + c], GW);
+  }
+  __syncthreads();
+
+  float out[kRZ];
+#pragma unroll
+  for (int rr = 0; rr < kRZ; ++rr) {
+    const int r = zb + rr, gz = z0 + r;
+    const bool ok = gx < NX && gz < NZ;
+    const size_t idx = ok ? (size_t)gz * NX + gx : 0;
+    const float l1 = sL[(r + 8) * PW + lx + 8];
+    float lam = 2.0f * l1 - l2[rr];
+    lam += d2s(&sQx[r * PW + lx + 8], 1);
+    lam += d2s(&sQz[(r + 8) * kTX + lx], kTX);
+    if (hx) lam -= d1s(&sTx[r * GW + lx + 4], 1);
+    if (hz) lam -= d1s(&sTz[(r + 4) * kTX + lx], kTX);
+    lam += (float)m1[rr];
+    const double mu = (2.0 * m1[rr] - m2[rr]) - d2d(&sU[r * GW + lx + 4], 1);
+    out[rr] = lam;
+    if (!ok) continue;
+    if (xcol >= 0)
+      a.zex_out[((size_t)shot * NZ + gz) * P2 + xcol] = a.bx[gx] * (zx[rr] + ccx[rr] * l1);
+    const int zrow = zstrip_row(gz, NZ, P);
+    if (zrow >= 0)
+      a.zez_out[((size_t)shot * P2 + zrow) * NX + gx] = a.bz[gz] * (zz[rr] + ccz[rr] * l1);
+    __builtin_nontemporal_store(mu, a.mprev + base + idx);
+    float* g0 = a.g + base + idx;
+    float* g1 = g0 + (size_t)a.nshots * plane;
+    float* g2 = g1 + (size_t)a.nshots * plane;
+    if (a.g_init) {
+      st_nt(g0, l1 * t0[rr]);
+      st_nt(g1, l1 * t1[rr]);
+      st_nt(g2, -(l1 * t2[rr]));
+    } else {
+      st_nt(g0, fmaf(l1, t0[rr], ld_nt(g0)));
+      st_nt(g1, fmaf(l1, t1[rr], ld_nt(g1)));
+      st_nt(g2, ld_nt(g2) - l1 * t2[rr]);
+    }
+  }
+  // r_{n-1} at the receivers of this (shot, tile), coincident receivers in
+  // receiver order, then lambda^n
+  const int* ro = a.rec_off + (size_t)shot * a.ntiles + tile;
+  if (a.resid && a.n >= 1 && ro[1] > ro[0]) {
+    __syncthreads();
+#pragma unroll
+    for (int rr = 0; rr < kRZ; ++rr) sL[(zb + rr) * kTX + lx] = out[rr];
+    __syncthreads();
+    const int e0 = ro[0], e1 = ro[1];
+    const float* rv = a.resid + ((size_t)shot * a.nt + (a.n - 1)) * a.nrec;
+    for (int e = e0 + tid; e < e1; e += kThreads) {
+      const int2 en = a.rec_ent[e];
+      if (e == e0 || a.rec_ent[e - 1].x != en.x) {
+        float acc = sL[en.x];
+        for (int k = e; k < e1 && a.rec_ent[k].x == en.x; ++k) acc += rv[a.rec_ent[k].y];
+        sL[en.x] = acc;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int rr = 0; rr < kRZ; ++rr) out[rr] = sL[(zb + rr) * kTX + lx];
+  }
+#pragma unroll
+  for (int rr = 0; rr < kRZ; ++rr) {
+    const int gz = z0 + zb + rr;
+    if (gx < NX && gz < NZ) st_nt(a.prev + base + (size_t)gz * NX + gx, out[rr]);
+  }
+}
+
+// Padded model (vv, v, eta; eta = 0 in the pad) and the coefficients, from
+// model [3][nz][nx] = (vv, v, eta); r = dt / h.
+__global__ void vti_prep_kernel(const float* __restrict__ model, float* __restrict__ pad,
+                                float* __restrict__ cx, float* __restrict__ cz,
+                                float* __restrict__ cm, int nx, int nz, int P, double r) {
+  const int NX = nx + 2 * P, NZ = nz + 2 * P;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (i >= NX || j >= NZ) return;
+  const int ii = min(max(i - P, 0), nx - 1), jj = min(max(j - P, 0), nz - 1);
+  const bool in_model = ii == i - P && jj == j - P;
+  const size_t m = (size_t)jj * nx + ii, mn = (size_t)nx * nz, k = (size_t)j * NX + i;
+  const size_t plane = (size_t)NX * NZ;
+  const double vv = model[m], vn = model[mn + m], eta = in_model ? (double)model[2 * mn + m] : 0.0;
+  pad[k] = (float)vv;
+  pad[plane + k] = (float)vn;
+  pad[2 * plane + k] = (float)eta;
+  const double ax = vn * r, az = vv * r;
+  cx[k] = (float)((1.0 + 2.0 * eta) * ax * ax);
+  cz[k] = (float)(az * az);
+  cm[k] = (float)(2.0 * eta * ax * ax * az * az);
+}
+
+__global__ void vti_fold_kernel(double* tot, const float* __restrict__ gpart, int nshots,
+                                size_t plane) {
+  const size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int q = blockIdx.y;
+  if (c >= plane) return;
+  double acc = tot[q * plane + c];
+  const float* gq = gpart + (size_t)q * nshots * plane;
+  for (int s = 0; s < nshots; ++s) acc += (double)gq[s * plane + c];
+  tot[q * plane + c] = acc;
+}
+
+// dJ/d(vv, v, eta) of model cell (ii, jj): the chain rule through (cx, cz, cm),
+// summed over the padded cells that replicate the cell (vv and v); eta only at
+// the cell itself (the pad holds eta = 0, which depends on no model value).
+__global__ void vti_finish_kernel(const double* tot, const float* pad, float* grad, int nx,
+                                  int nz, int P, double r) {
+  const int ii = blockIdx.x * blockDim.x + threadIdx.x;
+  const int jj = blockIdx.y;
+  if (ii >= nx || jj >= nz) return;
+  const int NX = nx + 2 * P, NZ = nz + 2 * P;
+  const size_t plane = (size_t)NX * NZ, mn = (size_t)nx * nz;
+  const int i0 = ii == 0 ? 0 : ii + P, i1 = ii == nx - 1 ? NX - 1 : ii + P;
+  const int j0 = jj == 0 ? 0 : jj + P, j1 = jj == nz - 1 ? NZ - 1 : jj + P;
+  const double r2 = r * r, r4 = r2 * r2;
+  double gvv = 0.0, gvn = 0.0, geta = 0.0;
+  for (int j = j0; j <= j1; ++j)
+    for (int i = i0; i <= i1; ++i) {
+      const size_t c = (size_t)j * NX + i;
+      const double vv = pad[c], vn = pad[plane + c], eta = pad[2 * plane + c];
+      const double gx = tot[c], gz = tot[plane + c], gm = tot[2 * plane + c];
+      gvv += gz * 2.0 * vv * r2 + gm * 4.0 * eta * vn * vn * vv * r4;
+      gvn += gx * 2.0 * (1.0 + 2.0 * eta) * vn * r2 + gm * 4.0 * eta * vn * vv * vv * r4;
+      if (i == ii + P && j == jj + P) geta += gx * 2.0 * vn * vn * r2 + gm * 2.0 * vn * vn * vv * vv * r4;
+    }
+  const size_t m = (size_t)jj * nx + ii;
+  grad[m] = (float)gvv;
+  grad[mn + m] = (float)gvn;
+  grad[2 * mn + m] = (float)geta;
+}
+
+}  // namespace
+
+int vti_launch_prep(const float* model, float* pad, float* cx, float* cz, float* cm, int nx,
+                    int nz, int P, double h, double dt, hipStream_t s) {
+  const int NX = nx + 2 * P, NZ = nz + 2 * P;
+  hipLaunchKernelGGL(vti_prep_kernel, dim3((NX + 255) / 256, NZ), dim3(256), 0, s, model, pad, cx,
+                     cz, cm, nx, nz, P, dt / h);
+  SWEEP_HIP(hipGetLastError());
+  return SWEEP_OK;
+}
+
+int vti_launch_fwd(const VtiStep& a, hipStream_t s) {
+  hipLaunchKernelGGL(vti_fwd_kernel, dim3(a.ntiles * a.nshots), dim3(kThreads), 0, s, a);
+  SWEEP_HIP(hipGetLastError());
+  return SWEEP_OK;
+}
+
+int vti_launch_adj(const VtiStep& a, hipStream_t s) {
+  hipLaunchKernelGGL(vti_adj_kernel, dim3(a.ntiles * a.nshots), dim3(kThreads), 0, s, a);
+  SWEEP_HIP(hipGetLastError());
+  return SWEEP_OK;
+}
+
+int vti_launch_fold(double* tot, const float* gpart, int nshots, size_t plane, hipStream_t s) {
+  hipLaunchKernelGGL(vti_fold_kernel, dim3((unsigned)((plane + 255) / 256), 3), dim3(256), 0, s,
+                     tot, gpart, nshots, plane);
+  SWEEP_HIP(hipGetLastError());
+  return SWEEP_OK;
+}
+
+int vti_launch_finish(const double* tot, const float* pad, float* grad, int nx, int nz, int P,
+                      double r, hipStream_t s) {
+  hipLaunchKernelGGL(vti_finish_kernel, dim3((nx + 255) / 256, nz), dim3(256), 0, s, tot, pad, grad,
+                     nx, nz, P, r);
+  SWEEP_HIP(hipGetLastError());
+  return SWEEP_OK;
+}
+
+}  // namespace sweep

@@ -1,0 +1,275 @@
+// Host-side scheduler of the pseudo-acoustic VTI path (Sec. 3.3.1, Eq. 5):
+// workspace layout, the forward time loop with checkpoints every k steps, and
+// the segment-wise recomputation (storing Bx', Bz' and D2x'D2z'G of each step)
+// and reverse sweep that accumulate dJ/d(cx, cz, cm), folded into FP64 per
+// segment and chained to dJ/d(vv, v, eta) at the end.
+#include <algorithm>
+#include <cstring>
+#include <string>
+
+#include "plan.h"
+#include "vti.h"
+
+namespace sweep {
+
+namespace {
+
+size_t take(size_t& off, size_t bytes) {
+  const size_t o = off;
+  off = align_up(off + bytes);
+  return o;
+}
+
+template <class T>
+T* at(void* base, size_t off) {
+  return reinterpret_cast<T*>(static_cast<char*>(base) + off);
+}
+
+}  // namespace
+
+void vti_layout(const sweep_plan* p, VtiLayout& L) {
+  const size_t ns = p->pb.nshots, nr = p->pb.nrec, f = sizeof(float);
+  const size_t plane = (size_t)p->NX * p->NZ;
+  L.plane = plane;
+  L.xs = (size_t)p->NZ * 2 * p->P;
+  L.zs = (size_t)2 * p->P * p->NX;
+  L.aux_elems = 2 * ns * L.xs + 2 * ns * L.zs;
+  size_t off = 0;
+  L.ax = take(off, p->NX * f);
+  L.bx = take(off, p->NX * f);
+  L.az = take(off, p->NZ * f);
+  L.bz = take(off, p->NZ * f);
+  L.pad = take(off, 3 * plane * f);
+  L.cx = take(off, plane * f);
+  L.cz = take(off, plane * f);
+  L.cm = take(off, plane * f);
+  L.wav = take(off, ns * p->pb.nt * f);
+  L.src_cell = take(off, ns * sizeof(int));
+  L.rec_cell = take(off, std::max<size_t>(ns * nr, 1) * sizeof(int));
+  L.rec_off = take(off, (ns * (size_t)p->ntiles + 1) * sizeof(int));
+  L.rec_ent = take(off, std::max<size_t>(ns * nr, 1) * sizeof(int2));
+  for (int i = 0; i < 2; ++i) L.pf[i] = take(off, ns * plane * f);
+  for (int i = 0; i < 2; ++i) L.gf[i] = take(off, ns * plane * sizeof(double));
+  for (int i = 0; i < 2; ++i) L.aux[i] = take(off, L.aux_elems * f);
+  L.fwd_end = off;
+  const int k = p->ckpt;
+  L.nseg = (p->pb.nt + k - 1) / k;
+  // in floats: P^n, P^{n-1} (float32), G^n, G^{n-1} (float64), memory variables
+  L.slot_elems = 6 * ns * plane + L.aux_elems;
+  L.ck = take(off, (size_t)L.nseg * L.slot_elems * f);
+  L.tr = take(off, (size_t)k * 3 * ns * plane * f);
+  for (int i = 0; i < 2; ++i) L.lf[i] = take(off, ns * plane * f);
+  for (int i = 0; i < 2; ++i) L.mf[i] = take(off, ns * plane * sizeof(double));
+  for (int i = 0; i < 2; ++i) L.adjaux[i] = take(off, L.aux_elems * f);
+  L.gpart = take(off, 3 * ns * plane * f);
+  L.tot = take(off, 3 * plane * sizeof(double));
+  L.bwd_end = off;
+}
+
+namespace {
+
+VtiStep vti_base(const sweep_plan* p, void* work, const VtiLayout& L) {
+  VtiStep a;
+  std::memset(&a, 0, sizeof(a));
+  a.NX = p->NX;
+  a.NZ = p->NZ;
+  a.P = p->P;
+  a.nt = p->pb.nt;
+  a.nrec = p->pb.nrec;
+  a.nshots = p->pb.nshots;
+  a.tiles_x = p->tiles_x;
+  a.ntiles = p->ntiles;
+  a.w = (float)((double)p->pb.dt * p->pb.dt / ((double)p->pb.h * p->pb.h));
+  a.cx = at<float>(work, L.cx);
+  a.cz = at<float>(work, L.cz);
+  a.cm = at<float>(work, L.cm);
+  a.ax = at<float>(work, L.ax);
+  a.bx = at<float>(work, L.bx);
+  a.az = at<float>(work, L.az);
+  a.bz = at<float>(work, L.bz);
+  a.src_cell = at<int>(work, L.src_cell);
+  a.wavelet = at<float>(work, L.wav);
+  a.rec_off = at<int>(work, L.rec_off);
+  a.rec_ent = at<int2>(work, L.rec_ent);
+  return a;
+}
+
+// the four memory-variable arrays of an aux block: psx, zex, psz, zez
+void set_aux(VtiStep& a, float* in, float* out, const VtiLayout& L, size_t ns) {
+  const size_t o[4] = {0, ns * L.xs, 2 * ns * L.xs, 2 * ns * L.xs + ns * L.zs};
+  a.psx_in = in + o[0];
+  a.zex_in = in + o[1];
+  a.psz_in = in + o[2];
+  a.zez_in = in + o[3];
+  a.psx_out = out + o[0];
+  a.zex_out = out + o[1];
+  a.psz_out = out + o[2];
+  a.zez_out = out + o[3];
+}
+
+int check_bytes(size_t need, void* work, size_t bytes) {
+  if (!work) {
+    set_error("workspace pointer is null");
+    return SWEEP_EINVAL;
+  }
+  if (bytes < need) {
+    set_error("workspace too small: need " + std::to_string(need) + " bytes, got " +
+              std::to_string(bytes));
+    return SWEEP_ENOMEM;
+  }
+  return SWEEP_OK;
+}
+
+// Forward step n from the buffer pair c (P^n in pf[c], P^{n-1} in pf[1-c]);
+// tr: the step's trace planes or null.
+int vti_fwd_step(sweep_plan* p, void* work, const VtiLayout& L, int n, int c, float* gathers,
+                 float* const* tr, hipStream_t s, int cls) {
+  const size_t ns = p->pb.nshots;
+  VtiStep a = vti_base(p, work, L);
+  a.n = n;
+  a.cur = at<float>(work, L.pf[c]);
+  a.prev = at<float>(work, L.pf[1 - c]);
+  a.gcur = at<double>(work, L.gf[c]);
+  a.gprev = at<double>(work, L.gf[1 - c]);
+  set_aux(a, at<float>(work, L.aux[n % 2]), at<float>(work, L.aux[1 - n % 2]), L, ns);
+  a.gathers = gathers;
+  if (tr)
+    for (int q = 0; q < 3; ++q) a.tr[q] = tr[q];
+  hipEvent_t* ev = p->timer.take(cls, -1, -1);
+  if (ev && ev[0]) SWEEP_HIP(hipEventRecord(ev[0], s));
+  const int rc = vti_launch_fwd(a, s);
+  if (ev && ev[1]) SWEEP_HIP(hipEventRecord(ev[1], s));
+  return rc;
+}
+
+}  // namespace
+
+int vti_forward(sweep_plan* p, const float* model, const float* wavelet, float* gathers,
+                void* work, size_t bytes, int save, hipStream_t s) {
+  VtiLayout L;
+  vti_layout(p, L);
+  int rc = check_bytes(save ? L.bwd_end : L.fwd_end, work, bytes);
+  if (rc) return rc;
+  const sweep_problem& pb = p->pb;
+  const size_t ns = pb.nshots, nsplane = ns * L.plane;
+  SWEEP_HIP(hipMemcpyAsync(at<int>(work, L.src_cell), p->src_cell.data(), ns * sizeof(int),
+                           hipMemcpyHostToDevice, s));
+  if (pb.nrec > 0) {
+    SWEEP_HIP(hipMemcpyAsync(at<int>(work, L.rec_cell), p->rec_cell.data(),
+                             p->rec_cell.size() * sizeof(int), hipMemcpyHostToDevice, s));
+    SWEEP_HIP(hipMemcpyAsync(at<int2>(work, L.rec_ent), p->rec_ent.data(),
+                             p->rec_ent.size() * sizeof(int2), hipMemcpyHostToDevice, s));
+  }
+  SWEEP_HIP(hipMemcpyAsync(at<int>(work, L.rec_off), p->rec_off.data(),
+                           p->rec_off.size() * sizeof(int), hipMemcpyHostToDevice, s));
+  if ((rc = ac_launch_tables(at<float>(work, L.ax), at<float>(work, L.bx), at<float>(work, L.az),
+                             at<float>(work, L.bz), p->NX, p->NZ, p->P, pb.h, pb.dt, pb.pml_vmax,
+                             pb.pml_f0, pb.pml_R, s)))
+    return rc;
+  if ((rc = vti_launch_prep(model, at<float>(work, L.pad), at<float>(work, L.cx),
+                            at<float>(work, L.cz), at<float>(work, L.cm), pb.nx, pb.nz, p->P,
+                            pb.h, pb.dt, s)))
+    return rc;
+  if ((rc = launch_copy(at<float>(work, L.wav), wavelet, ns * pb.nt, s))) return rc;
+  for (int i = 0; i < 2; ++i) {
+    if ((rc = launch_fill(at<float>(work, L.pf[i]), nsplane, 0.0f, s))) return rc;
+    if ((rc = launch_fill(at<float>(work, L.gf[i]), 2 * nsplane, 0.0f, s))) return rc;
+    if ((rc = launch_fill(at<float>(work, L.aux[i]), L.aux_elems, 0.0f, s))) return rc;
+  }
+  const int k = p->ckpt;
+  int c = 0;
+  for (int n = 0; n < pb.nt; ++n) {
+    if (save && n % k == 0) {
+      float* slot = at<float>(work, L.ck) + (size_t)(n / k) * L.slot_elems;
+      if ((rc = launch_copy(slot, at<float>(work, L.pf[c]), nsplane, s))) return rc;
+      if ((rc = launch_copy(slot + nsplane, at<float>(work, L.pf[1 - c]), nsplane, s))) return rc;
+      // G as raw bits: two floats per float64 value
+      if ((rc = launch_copy(slot + 2 * nsplane, at<float>(work, L.gf[c]), 2 * nsplane, s)))
+        return rc;
+      if ((rc = launch_copy(slot + 4 * nsplane, at<float>(work, L.gf[1 - c]), 2 * nsplane, s)))
+        return rc;
+      if ((rc = launch_copy(slot + 6 * nsplane, at<float>(work, L.aux[n % 2]), L.aux_elems, s)))
+        return rc;
+    }
+    if ((rc = vti_fwd_step(p, work, L, n, c, gathers, nullptr, s, kFwdInt))) return rc;
+    c = 1 - c;
+  }
+  p->saved = save != 0;
+  p->saved_work = work;
+  p->saved_model = model;
+  p->saved_rz = p->tune.rz;
+  return SWEEP_OK;
+}
+
+int vti_backward(sweep_plan* p, const float* resid, float* grad, void* work, size_t bytes,
+                 hipStream_t s) {
+  if (!p->saved || p->saved_work != work) {
+    set_error("sweep_backward needs a preceding sweep_forward(save_for_backward=1) on the "
+              "same workspace");
+    return SWEEP_ESTATE;
+  }
+  VtiLayout L;
+  vti_layout(p, L);
+  int rc = check_bytes(L.bwd_end, work, bytes);
+  if (rc) return rc;
+  const sweep_problem& pb = p->pb;
+  const int nt = pb.nt, k = p->ckpt;
+  const size_t ns = pb.nshots, nsplane = ns * L.plane;
+  int ac = 0;
+  if ((rc = ac_launch_adj_init(at<float>(work, L.lf[0]), at<float>(work, L.lf[1]), nsplane,
+                               at<float>(work, L.adjaux[0]), L.aux_elems,
+                               at<int>(work, L.rec_cell), resid, (int)ns, nt, pb.nrec, s)))
+    return rc;
+  for (int i = 0; i < 2; ++i)
+    if ((rc = launch_fill(at<float>(work, L.mf[i]), 2 * nsplane, 0.0f, s))) return rc;
+  if ((rc = launch_fill(at<float>(work, L.adjaux[1]), L.aux_elems, 0.0f, s))) return rc;
+  if ((rc = launch_fill_f64(at<double>(work, L.tot), 3 * L.plane, 0.0, s))) return rc;
+  float* trb = at<float>(work, L.tr);
+  for (int sg = L.nseg - 1; sg >= 0; --sg) {
+    const int n0 = sg * k, n1 = std::min(nt, n0 + k);
+    // restore the state entering step n0 into buffer pair 0 and aux[n0 % 2]
+    const float* slot = at<float>(work, L.ck) + (size_t)sg * L.slot_elems;
+    if ((rc = launch_copy(at<float>(work, L.pf[0]), slot, nsplane, s))) return rc;
+    if ((rc = launch_copy(at<float>(work, L.pf[1]), slot + nsplane, nsplane, s))) return rc;
+    if ((rc = launch_copy(at<float>(work, L.gf[0]), slot + 2 * nsplane, 2 * nsplane, s)))
+      return rc;
+    if ((rc = launch_copy(at<float>(work, L.gf[1]), slot + 4 * nsplane, 2 * nsplane, s)))
+      return rc;
+    if ((rc = launch_copy(at<float>(work, L.aux[n0 % 2]), slot + 6 * nsplane, L.aux_elems, s)))
+      return rc;
+    int c = 0;
+    for (int n = n0; n < n1; ++n) {
+      float* tr[3];
+      for (int q = 0; q < 3; ++q) tr[q] = trb + ((size_t)(n - n0) * 3 + q) * nsplane;
+      if ((rc = vti_fwd_step(p, work, L, n, c, nullptr, tr, s, kRecInt))) return rc;
+      c = 1 - c;
+    }
+    for (int n = n1 - 1; n >= n0; --n) {
+      const int it = nt - 1 - n;
+      VtiStep a = vti_base(p, work, L);
+      a.n = n;
+      a.resid = resid;
+      a.cur = at<float>(work, L.lf[ac]);
+      a.prev = at<float>(work, L.lf[1 - ac]);
+      a.mcur = at<double>(work, L.mf[ac]);
+      a.mprev = at<double>(work, L.mf[1 - ac]);
+      set_aux(a, at<float>(work, L.adjaux[it % 2]), at<float>(work, L.adjaux[(it + 1) % 2]), L,
+              ns);
+      for (int q = 0; q < 3; ++q) a.trc[q] = trb + ((size_t)(n - n0) * 3 + q) * nsplane;
+      a.g = at<float>(work, L.gpart);
+      a.g_init = (n == n1 - 1);
+      hipEvent_t* ev = p->timer.take(kAdjInt, -1, -1);
+      if (ev && ev[0]) SWEEP_HIP(hipEventRecord(ev[0], s));
+      if ((rc = vti_launch_adj(a, s))) return rc;
+      if (ev && ev[1]) SWEEP_HIP(hipEventRecord(ev[1], s));
+      ac = 1 - ac;
+    }
+    if ((rc = vti_launch_fold(at<double>(work, L.tot), at<float>(work, L.gpart), (int)ns, L.plane,
+                              s)))
+      return rc;
+  }
+  return vti_launch_finish(at<double>(work, L.tot), at<float>(work, L.pad), grad, pb.nx, pb.nz,
+                           p->P, pb.dt / pb.h, s);
+}
+
+}  // namespace sweep

@@ -15,9 +15,9 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import ACOUSTIC, ACOUSTIC_VD, ELASTIC, Problem, Tuning, check, lib
+from ._lib import ACOUSTIC, ACOUSTIC_VD, ELASTIC, VTI, Problem, Tuning, check, lib
 
-__all__ = ["Plan", "Batch", "WaveFn", "l2_misfit", "ACOUSTIC", "ELASTIC", "ACOUSTIC_VD"]
+__all__ = ["Plan", "Batch", "WaveFn", "l2_misfit", "ACOUSTIC", "ELASTIC", "ACOUSTIC_VD", "VTI"]
 
 
 def _stream() -> ctypes.c_void_p:
@@ -67,9 +67,10 @@ class Plan:
         self.nshots, self.nrec, self.nt, self.nx, self.nz = (src.shape[0], rec.shape[1], nt,
                                                                nx, nz)
         self.physics = physics
-        # acoustic: vp; elastic: vp, vs, rho; first-order variable density: vp, rho
-        self.nparam = {ACOUSTIC: 1, ELASTIC: 3, ACOUSTIC_VD: 2}[physics]
-        self.ncomp = 1 if physics == ACOUSTIC else 2
+        # acoustic: vp; elastic: vp, vs, rho; first-order variable density: vp, rho;
+        # VTI: vv (vertical velocity), v (NMO velocity), eta
+        self.nparam = {ACOUSTIC: 1, ELASTIC: 3, ACOUSTIC_VD: 2, VTI: 3}[physics]
+        self.ncomp = 1 if physics in (ACOUSTIC, VTI) else 2
         self.device = torch.device(device) if device is not None else torch.device("cuda")
         self._src, self._rec = src, rec
         if torch.cuda.is_available():

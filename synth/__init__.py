@@ -23,7 +23,7 @@ from typing import List, Optional, Tuple
 import numpy as np
 
 __all__ = [
-    "ricker", "bandlimited_noise", "rff_frequencies", "layered_anomaly", "interface_model", "smooth", "elastic_model",
+    "ricker", "bandlimited_noise", "rff_frequencies", "layered_anomaly", "interface_model", "smooth", "elastic_model", "vti_model",
     "surface_shots", "line_receivers", "Workload", "workload", "batched_workloads",
     "WORKLOADS",
 ]
@@ -91,6 +91,22 @@ def elastic_model(nx: int, nz: int, seed: int, vpmin: float = 1800.0, vpmax: flo
     return np.stack([vp, vs, rho])
 
 
+def vti_model(nx: int, nz: int, seed: int, vmin: float = 1500.0, vmax: float = 4700.0,
+              eta_max: float = 0.12, iso_rows: int = 20) -> np.ndarray:
+    """VTI model [3][nz][nx] = (vv, v, eta): vv from the layered generator, the
+    NMO velocity v up to 3 % above it (smooth seeded field), eta up to eta_max
+    growing with depth below an isotropic top zone of iso_rows rows (where the
+    sources and receivers of the workloads sit, as the pseudo-acoustic
+    formulation asks)."""
+    rng = np.random.default_rng(seed + 1000)
+    vv = layered_anomaly(nx, nz, vmin, vmax, seed)
+    vn = vv * (1.0 + 0.03 * smooth(rng.uniform(0.0, 1.0, (nz, nx)), 5.0) / 0.5)
+    vn = np.minimum(vn, vv * 1.03)
+    ramp = np.clip((np.arange(nz)[:, None] - iso_rows) / 40.0, 0.0, 1.0)
+    eta = eta_max * ramp * np.clip(smooth(rng.uniform(0.5, 1.0, (nz, nx)), 5.0), 0.0, 1.0)
+    return np.stack([vv, vn, eta])
+
+
 def surface_shots(nx: int, nshots: int, depth: int) -> np.ndarray:
     """Shot cells [nshots][2] = (x, z), x = floor((i + 1/2) nx / nshots)."""
     xs = np.floor((np.arange(nshots) + 0.5) * nx / nshots).astype(np.int32)
@@ -134,7 +150,7 @@ def rff_frequencies(nfreq: int = 64, sigma: float = 10.0, seed: int = 0) -> np.n
 class Workload:
     """One modelling problem: grid, time axis, absorbing pad, sources, receivers."""
     name: str
-    physics: str                 # "acoustic" or "elastic"
+    physics: str                 # "acoustic", "elastic" or "vti"
     nx: int
     nz: int
     h: float
@@ -157,6 +173,8 @@ class Workload:
     def true_model(self) -> np.ndarray:
         if self.name.startswith("interface"):
             return interface_model(self.nx, self.nz)
+        if self.physics == "vti":
+            return vti_model(self.nx, self.nz, self.seed, self.vmin, self.vmax)
         if self.physics == "elastic":
             return elastic_model(self.nx, self.nz, self.seed, self.vmin, self.vmax)
         return layered_anomaly(self.nx, self.nz, self.vmin, self.vmax, self.seed)
@@ -169,6 +187,8 @@ class Workload:
 
     def pml_vmax(self) -> float:
         m = self.true_model()
+        if self.physics == "vti":  # the fastest (horizontal) speed v sqrt(1 + 2 eta)
+            return float((m[1] * np.sqrt(1.0 + 2.0 * m[2])).max())
         return float(m[0].max() if m.ndim == 3 else m.max())
 
     def sources(self) -> np.ndarray:
@@ -208,6 +228,10 @@ WORKLOADS = {
     # 1000x300 acoustic FWI gradient, 64 shots, 1000 receivers, 3000 steps.
     "layered1000x300": Workload("layered1000x300", "acoustic", 1000, 300, 10.0, 1e-3, 3000,
                                 40, 8.0, 64, 1000, 5, 5),
+    # 1000x300 pseudo-acoustic VTI: the acoustic benchmark's grid, shots and
+    # receivers with an anisotropic model (eta up to 0.12 below the top 20 rows).
+    "vti1000x300": Workload("vti1000x300", "vti", 1000, 300, 10.0, 1e-3, 3000, 40, 8.0, 64,
+                            1000, 5, 5),
     # 600x300 elastic, free surface, 32 explosive shots, 600 2-component receivers.
     "elastic600x300": Workload("elastic600x300", "elastic", 600, 300, 5.0, 0.5e-3, 4000, 30,
                                15.0, 32, 600, 5, 5, free_surface=1, vmin=1800.0,
