@@ -46,7 +46,7 @@ def _source_hash() -> str:
     compiles against (the traffic figures hold only for that code)."""
     import hashlib
     h = hashlib.sha256()
-    for name in ("acoustic.hip", "internal.h"):
+    for name in ("acoustic.hip", "fd.h", "internal.h"):
         with open(os.path.join(ROOT, "paper_2604_14189_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -65,10 +65,22 @@ def calibrate_copy(nbytes=1 << 30, reps=3):
                       "reps": reps, "kernel": "torch copy_"}), flush=True)
 
 
-def cpu_baseline(w, max_seconds=30.0):
-    """The FP64 oracle on the host cores, on a bounded sample of the workload:
-    `ns` shots (one per host thread) for `nt_s` of the steps, forward + gradient,
-    in the metric's unit (fwd+adj Gcell-updates/s)."""
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(w, nt_s=100, reps=3):
+    """The FP64 oracle on the host cores, on a bounded sample of the workload,
+    in the metric's unit (fwd+adj Gcell-updates/s): `cores` shots (one per host
+    thread, up to 16) for `nt_s` of the steps, forward + checkpointed gradient,
+    the median of `reps` runs; and the same on one thread with one shot."""
     import oracle
     from synth.cases import case_from_workload, f32
     import synth
@@ -80,25 +92,40 @@ def cpu_baseline(w, max_seconds=30.0):
     except Exception:
         pass
     cores = max(1, min(cores, 16, w.nshots))
-    nt_s = 200
-    shots = list(range(0, w.nshots, max(1, w.nshots // cores)))[:cores]
-    case = case_from_workload(w, shots=shots, nt=nt_s)
-    case.nt = nt_s
-    pb = case.oracle_problem(oracle, nthreads=cores)
-    resid = f32(synth.bandlimited_noise((len(shots), nt_s, w.nrec), w.f0, w.dt, 5))
-    t0 = time.perf_counter()
-    oracle.ac_gradient(pb, case.v, case.src, case.wav, case.rec, resid)
-    t = time.perf_counter() - t0
     NX, NZ = w.NX, w.NZ
-    cells = 2.0 * len(shots) * NX * NZ * nt_s
-    return {"value": cells / t / 1e9, "unit": "Gcell-updates/s", "cores": cores,
-            "kind": "oracle",
-            "sample": f"{len(shots)} of {w.nshots} shots x {nt_s} of {w.nt} steps, "
-                      f"forward+checkpointed adjoint gradient (k=50), FP64, "
-                      f"{t:.1f} s wall"}
+
+    def rate(nshot, nthreads):
+        shots = list(range(0, w.nshots, max(1, w.nshots // nshot)))[:nshot]
+        case = case_from_workload(w, shots=shots, nt=nt_s)
+        case.nt = nt_s
+        pb = case.oracle_problem(oracle, nthreads=nthreads)
+        resid = f32(synth.bandlimited_noise((len(shots), nt_s, w.nrec), w.f0, w.dt, 5))
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            oracle.ac_gradient(pb, case.v, case.src, case.wav, case.rec, resid)
+            ts.append(time.perf_counter() - t0)
+        t = float(np.median(ts))
+        return 2.0 * len(shots) * NX * NZ * nt_s / t / 1e9, t
+
+    v, t = rate(cores, cores)
+    v1, t1 = rate(1, 1)
+    return {"value": v, "unit": "Gcell-updates/s", "cores": cores, "kind": "oracle",
+            "cpu": _cpu_model(), "one_thread_value": v1,
+            "sample": f"{cores} of {w.nshots} shots x {nt_s} of {w.nt} steps on {cores} "
+                      f"threads (one shot per thread), forward + checkpointed adjoint gradient "
+                      f"(k=50), FP64, median of {reps}: {t:.2f} s; one thread, one shot: "
+                      f"{t1:.2f} s"}
 
 
 FIT_LOG = []  # one entry per fit_keep_b call, reported with the results
+T_START = time.perf_counter()
+
+
+def progress(what: str):
+    """One line on stderr as each measurement ends (stdout holds only the
+    result line)."""
+    print(f"[bench {time.perf_counter() - T_START:7.1f} s] {what}", file=sys.stderr, flush=True)
 
 
 def fit_keep_b(torch, plan, nt, ckpt, reserve=8 << 30):
@@ -242,6 +269,15 @@ def _sync_time(torch, fn):
     return out, time.perf_counter() - t0
 
 
+def _median_time(torch, fn, reps=3):
+    """(last output, median seconds, all samples) of `reps` timed calls."""
+    ts, out = [], None
+    for _ in range(reps):
+        out, t = _sync_time(torch, fn)
+        ts.append(t)
+    return out, float(np.median(ts)), [round(x, 4) for x in ts]
+
+
 def batched_uneven(sw, torch, tuning=None):
     """The eight uneven layered models (200x200 ... 1200x400, 16-48 shots, 2000-4000
     steps, 256 shots): one FWI gradient of all of them through one Batch (one
@@ -276,12 +312,26 @@ def batched_uneven(sw, torch, tuning=None):
     nsegs = [-(-w.nt // w.ckpt_every) for w in ws]
     keeps = fit_batch_keep_b(torch, batch, plans, nsegs)
 
-    def grad():
-        ds = batch.forward(v0s, wavs, save=True)
-        rs = [sw.l2_misfit(d, o)[0] for d, o in zip(ds, dobs)]
-        return batch.backward(rs)
+    # fixed gathers, residual and gradient buffers: a captured graph stays valid
+    gath = [torch.empty(p.gathers_shape(), device="cuda") for p in plans]
+    res = [torch.empty_like(g) for g in gath]
+    grads = [torch.empty(p._model_shape(), device="cuda") for p in plans]
 
-    _, t_batch = _sync_time(torch, grad)
+    def grad():
+        ds = batch.forward(v0s, wavs, save=True, out=gath)
+        for d, o, r in zip(ds, dobs, res):
+            sw.l2_misfit(d, o, resid=r)
+        return batch.backward(res, out=grads)
+
+    grad()
+    _, t_batch, t_eager_all = _median_time(torch, grad)
+    g_eager = [g.clone() for g in grads]
+    batch.set_graph(True)
+    grad()  # capture
+    _, t_graph, t_graph_all = _median_time(torch, grad)
+    nodes = batch.graph_nodes()
+    same = all(bool(torch.equal(a, b)) for a, b in zip(g_eager, grads))
+    batch.set_graph(False)
     batch._work = None
     t_shot = 0.0
     for w, v0, wav, do, nseg in zip(ws, v0s, wavs, dobs, nsegs):
@@ -298,8 +348,13 @@ def batched_uneven(sw, torch, tuning=None):
         t_shot += t1 * w.nshots
     cells = sum(2.0 * w.nshots * w.NX * w.NZ * w.nt for w in ws)
     return {"models": len(ws), "shots": sum(w.nshots for w in ws),
-            "batched_gradient_s": round(t_batch, 3),
+            "batched_gradient_s": round(t_batch, 3), "samples_s": t_eager_all,
             "batched_Gcell_per_s": round(cells / t_batch / 1e9, 2),
+            "graph": {"gradient_s": round(t_graph, 3), "samples_s": t_graph_all,
+                      "Gcell_per_s": round(cells / t_graph / 1e9, 2),
+                      "launches_forward_graph": nodes[0], "launches_backward_graph": nodes[1],
+                      "graph_launches_per_gradient": 2,
+                      "bitwise_equal_to_eager": same},
             "per_shot_gradient_s_est": round(t_shot, 3), "speedup": round(t_shot / t_batch, 2),
             "tuning": {"rz": tuning[0], "pml_rz": tuning[1], "tblock": tuning[3]},
             "keep_b": keeps, "segments": nsegs,
@@ -326,12 +381,12 @@ def elastic_gradient(sw, torch):
         return plan.backward(sw.l2_misfit(d, d_obs)[0])
 
     grad()
-    _, t = _sync_time(torch, grad)
+    _, t, ts = _median_time(torch, grad)
     NX, NZ = plan.padded()
     cells = 2.0 * w.nshots * NX * NZ * w.nt
     plan.release_workspace()
     return {"workload": "elastic600x300", "padded": f"{NX}x{NZ}", "shots": w.nshots,
-            "nt": w.nt, "keep_b": keep, "gradient_s": round(t, 3),
+            "nt": w.nt, "keep_b": keep, "gradient_s": round(t, 3), "samples_s": ts,
             "Gcell_per_s": round(cells / t / 1e9, 2)}
 
 
@@ -348,7 +403,7 @@ def born_modelling(sw, torch, case, w, v_true, v0, wav):
         return plan.born(v0, dv, wav)
 
     born()
-    _, t_born = _sync_time(torch, born)
+    _, t_born, tb = _median_time(torch, born)
     keep = fit_keep_b(torch, plan, w.nt, w.ckpt_every)
 
     def lsrtm():
@@ -356,12 +411,13 @@ def born_modelling(sw, torch, case, w, v_true, v0, wav):
         plan.forward(v0, wav, save=True)
         return plan.backward(dd)
 
-    _, t_it = _sync_time(torch, lsrtm)
+    lsrtm()
+    _, t_it, ti = _median_time(torch, lsrtm)
     NX, NZ = plan.padded()
     plan.release_workspace()
     cells = float(w.nshots) * NX * NZ * w.nt
     return {"workload": "layered1000x300", "shots": w.nshots, "nt": w.nt,
-            "born_s": round(t_born, 3),
+            "born_s": round(t_born, 3), "born_samples_s": tb, "lsrtm_samples_s": ti,
             "born_Gcell_per_s": round(cells / t_born / 1e9, 2),
             "wavefield_Gcell_per_s": round(2.0 * cells / t_born / 1e9, 2),
             "lsrtm_iteration_s": round(t_it, 3), "lsrtm_keep_b": keep,
@@ -395,12 +451,13 @@ def encoded_gradient(sw, torch, nsuper=8):
         return plan.backward(sw.l2_misfit(d, d_obs)[0])
 
     grad()
-    _, t = _sync_time(torch, grad)
+    _, t, ts = _median_time(torch, grad)
     NX, NZ = plan.padded()
     plan.release_workspace()
     cells = 2.0 * nsuper * NX * NZ * w.nt
     return {"workload": "layered1000x300", "sources": w.nshots, "supershots": nsuper,
             "sources_per_supershot": k, "nt": w.nt, "keep_b": keep, "gradient_s": round(t, 3),
+            "samples_s": ts,
             "Gcell_per_s": round(cells / t / 1e9, 2)}
 
 
@@ -426,12 +483,65 @@ def acoustic_vd_gradient(sw, torch):
         return plan.backward(sw.l2_misfit(d, d_obs)[0])
 
     grad()
-    _, t = _sync_time(torch, grad)
+    _, t, ts = _median_time(torch, grad)
     NX, NZ = plan.padded()
     plan.release_workspace()
     cells = 2.0 * w.nshots * NX * NZ * w.nt
     return {"workload": "layered1000x300, rho = 310 vp^0.25", "shots": w.nshots, "nt": w.nt,
-            "keep_b": keep, "gradient_s": round(t, 3), "Gcell_per_s": round(cells / t / 1e9, 2)}
+            "keep_b": keep, "gradient_s": round(t, 3), "samples_s": ts,
+            "Gcell_per_s": round(cells / t / 1e9, 2)}
+
+
+def vti_gradient(sw, torch):
+    """Pseudo-acoustic VTI FWI gradient (vv, v, eta) on the 1000x300 grid with
+    the layered benchmark's shots and receivers (64 shots, 3000 steps, 40-cell
+    C-PML), eta up to 0.12 below an isotropic top zone; initial model the
+    20-cell smoothing of the true one. Checkpoints every 50 steps, every
+    segment recomputed (VTI plans store none)."""
+    import synth
+    w = synth.workload("vti1000x300")
+    m_true = np.asarray(w.true_model(), np.float32)
+    model = torch.tensor(m_true, device="cuda")
+    m0 = torch.tensor(np.stack([synth.smooth(c, 20.0) for c in m_true]).astype(np.float32),
+                      device="cuda")
+    plan = sw.Plan(nx=w.nx, nz=w.nz, h=w.h, dt=w.dt, nt=w.nt, pml=w.pml, src_xz=w.sources(),
+                   rec_xz=w.receivers(), pml_vmax=w.pml_vmax(), pml_f0=w.f0, pml_R=w.pml_R,
+                   ckpt_every=w.ckpt_every, physics=sw.VTI)
+    wav = torch.tensor(w.wavelets(np.float32), device="cuda")
+    d_obs = plan.forward(model, wav).clone()
+    plan.reserve_workspace(True)
+
+    def grad():
+        d = plan.forward(m0, wav, save=True)
+        return plan.backward(sw.l2_misfit(d, d_obs)[0])
+
+    grad()
+    plan.set_profiling(True, 10)
+    _, t, ts = _median_time(torch, grad)
+    kt = plan.kernel_times()
+    plan.set_profiling(False)
+    NX, NZ = plan.padded()
+    plan.release_workspace()
+    cells = 2.0 * w.nshots * NX * NZ * w.nt
+    per = w.nshots * NX * NZ
+    # algorithmic bytes per cell-update: forward reads P^{n-1}, cx, cz, cm
+    # (4 B each), G^{n-1} (8 B, float64), P^n (4) and G^n (8) once, writes
+    # P^{n+1} (4) and G^{n+1} (8): 48 B; the recompute also writes Bx', Bz',
+    # D2x'D2z'G (+12 B); the adjoint reads lambda^{n+1}, lambda^{n+2} (8 B),
+    # mu^{n+1}, mu^{n+2} (16, float64), cx, cz, cm (12), the three traces (12)
+    # and the partials g (12, written only on a segment's first step), and
+    # writes lambda^n (4), mu^n (8) and g (12): 84 B
+    kb = {"fwd_int": 48.0, "rec_int": 60.0, "adj_int": 84.0}
+    kern = {}
+    for name, b in kb.items():
+        n, ms = kt[name]
+        if n:
+            avg = ms / n / 1e3
+            kern[name] = {"avg_us": round(avg * 1e6, 1),
+                          "algorithmic_GBps": round(b * per / avg / 1e9, 1)}
+    return {"workload": "vti1000x300", "padded": f"{NX}x{NZ}", "shots": w.nshots, "nt": w.nt,
+            "gradient_s": round(t, 3), "samples_s": ts, "Gcell_per_s": round(cells / t / 1e9, 2),
+            "kernels": kern}
 
 
 def mlp_throughput(torch):
@@ -461,6 +571,127 @@ def mlp_throughput(torch):
             "backward_TFLOPs": round(f_bwd / (tb / reps) / 1e12, 1)}
 
 
+def kernel_report(plan, w, kt):
+    """Per-class kernel figures of an acoustic gradient and the roofline of the
+    dominant class (the most time per gradient), from the plan's sampled HIP
+    event timings `kt` ({class: (launches, total ms)})."""
+    NX, NZ = plan.padded()
+    # Algorithmic bytes per cell-update: interior kernel forward 16 B (read
+    # p^n, p^{n-1}, Cs; write p^{n+1}), recompute 20 B (+ write B^n), adjoint
+    # 28 B (read lambda^{n+1}, lambda^{n+2}, Cs, B^n, g; write lambda^n, g),
+    # 24 B on the first step of a segment (g written, not read). The C-PML
+    # kernels move the same per cell plus 16 B per C-PML axis at each strip cell
+    # (psi and zeta read and written). A two-step pass over a deep cell moves
+    # 20 B forward (read p^n, p^{n-1}, Cs; write p^{n+1}, p^{n+2}), 28 B in the
+    # recompute (+ B^n, B^{n+1}) and 36 B adjoint (read lambda^{n+1},
+    # lambda^{n+2}, Cs, B^n, B^{n-1}, g; write lambda^n, lambda^{n-1}, g), 32 B
+    # on a segment's first pair. Its "effective" rate counts the bytes of the
+    # two single steps it replaces.
+    k = w.ckpt_every
+    t = plan.tiles()
+    TZ = t["rows"]
+    wz = (t["x1"] - t["x0"]) * 64                       # z-frame columns
+    n_deep = t["deep"]
+    int_cells = t["interior"] * 64 * TZ
+    deep_cells = n_deep * 64 * TZ
+    ring_cells = int_cells - deep_cells
+    z_cells = wz * (t["z0"] * TZ + NZ - t["z1"] * TZ) if t["interior"] else 0
+    x_cells = NX * NZ - int_cells - z_cells
+    P = w.pml
+    z_strip = 2 * P * wz if t["interior"] else 0        # z-strip cells in the z frame
+    x_strip = 2 * P * NZ + 2 * P * NX - z_strip         # strip cells (per axis) in the x frame
+    base = {"fwd": 16.0, "rec": 20.0, "adj": (28.0 * (k - 1) + 24.0) / k}
+    pairs = k // 2
+    deep_b = {"fwd": 20.0, "rec": 28.0, "adj": (36.0 * (pairs - 1) + 32.0) / max(pairs, 1)}
+    per_launch, effective = {}, {}
+    for ph, b in base.items():
+        # single-step interior launches cover the ring tiles when two-step
+        # passes run (every launch of the class in this configuration)
+        per_launch[ph + "_int"] = b * (ring_cells if n_deep else int_cells) * w.nshots
+        per_launch[ph + "_zpml"] = (b * z_cells + 16.0 * z_strip) * w.nshots
+        per_launch[ph + "_xpml"] = (b * x_cells + 16.0 * x_strip) * w.nshots
+        per_launch[ph + "_deep"] = deep_b[ph] * deep_cells * w.nshots
+        effective[ph + "_deep"] = 2.0 * b * deep_cells * w.nshots
+    # Dominant kernel: largest time per gradient, average launch time x launches
+    # per gradient (a two-step pass runs once per two steps). The timer samples
+    # launches, so the sampled totals are not comparable between classes.
+    runs = {kk: (0.5 if kk.endswith("_deep") else 1.0) for kk in kt}
+    est = {kk: (vv[1] / vv[0]) * runs[kk] for kk, vv in kt.items() if vv[0] > 0}
+    dom = max(est, key=lambda kk: est[kk])
+    roof = None
+    if dom in per_launch and kt[dom][0] > 0:
+        launches, tot_ms = kt[dom]
+        avg_s = tot_ms / launches / 1e3
+        # algorithmic bytes per launch: the per-cell-update figure times the
+        # cell-updates one launch makes (two per cell for a two-step pass, T = 2;
+        # the fraction may then exceed what the pass itself moves)
+        T = 2 if dom.endswith("_deep") else 1
+        bytes_per_launch = effective.get(dom, per_launch[dom])
+        achieved = bytes_per_launch / avg_s / 1e9
+        tr = TRAFFIC.get(dom)
+        traffic = tr["bytes_per_launch"] if tr and tr["source"] == _source_hash() else None
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": dom, "T": T, "avg_launch_us": round(avg_s * 1e6, 2),
+                "algorithmic_bytes_per_launch": int(bytes_per_launch),
+                "pass_bytes_per_launch": int(per_launch[dom]),
+                "pass_frac": round(per_launch[dom] / avg_s / 1e9 / HBM_PEAK_GBS, 4)}
+    kernels = {}
+    for name, (nl, ms) in kt.items():
+        if nl > 0 and name in per_launch:
+            avg = ms / nl / 1e3
+            kernels[name] = {"launches": nl, "total_ms": round(ms, 3),
+                             "avg_us": round(avg * 1e6, 2),
+                             "algorithmic_GBps": round(per_launch[name] / avg / 1e9, 1)}
+            if name in effective:
+                kernels[name]["effective_step_GBps"] = round(effective[name] / avg / 1e9, 1)
+
+    return roof, kernels, t
+
+
+def cell_updates_of(plan, w) -> float:
+    """fwd+adj cell-updates of one gradient: 2 x shots x padded cells x steps."""
+    NX, NZ = plan.padded()
+    return 2.0 * w.nshots * NX * NZ * w.nt
+
+
+def shots256(sw, torch, args):
+    """The layered 1000x300 gradient with 256 shots (the workload's 64 shot
+    positions made four times as dense): the fields of one step (four planes of
+    256 x 1080 x 380) far exceed the 256 MB MALL, so the kernels stream from
+    HBM. Stored segments sized as for the headline; the dominant kernel's
+    roofline from sampled HIP events."""
+    import synth
+    from synth.cases import case_from_workload
+    w = synth.workload(WORKLOAD).replace(nshots=256)
+    case = case_from_workload(w)
+    plan = case.plan()
+    plan.set_tuning(rz=args.rz, pml_rz=args.pml_rz, tblock=args.tblock)
+    v_true = torch.tensor(case.v, dtype=torch.float32, device="cuda")
+    v0 = torch.tensor(synth.smooth(case.v, 20.0), dtype=torch.float32, device="cuda")
+    wav = torch.tensor(case.wav, dtype=torch.float32, device="cuda")
+    d_obs = plan.forward(v_true, wav).clone()
+    plan.release_workspace()
+    # 256 shots' gathers, residuals and the misfit's gathers take about 9 GiB
+    keep = fit_keep_b(torch, plan, w.nt, w.ckpt_every, reserve=16 << 30)
+
+    def step():
+        d = plan.forward(v0, wav, save=True)
+        return plan.backward(sw.l2_misfit(d, d_obs)[0])
+
+    step()
+    plan.set_profiling(True, period=10)
+    _, t, ts = _median_time(torch, step, reps=2)
+    kt = plan.kernel_times()
+    plan.set_profiling(False)
+    roof, kern, _ = kernel_report(plan, w, kt)
+    plan.release_workspace()
+    return {"workload": "layered1000x300, 256 shots", "shots": w.nshots, "nt": w.nt,
+            "keep_b": keep, "gradient_s": round(t, 3), "samples_s": ts,
+            "Gcell_per_s": round(cell_updates_of(plan, w) / t / 1e9, 2), "roofline": roof,
+            "kernels": {k: v["algorithmic_GBps"] for k, v in kern.items()}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -479,7 +710,7 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the Born, batched-uneven, elastic and MLP measurements")
     ap.add_argument("--only", choices=["born", "encoded", "batched_uneven", "elastic",
-                                       "acoustic_vd", "mlp"],
+                                       "acoustic_vd", "mlp", "vti", "shots256"],
                     help="run one of the extra measurements alone (profiling) and print it")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration)")
@@ -515,6 +746,10 @@ def main():
             res = acoustic_vd_gradient(sw, torch)
         elif args.only == "encoded":
             res = encoded_gradient(sw, torch)
+        elif args.only == "vti":
+            res = vti_gradient(sw, torch)
+        elif args.only == "shots256":
+            res = shots256(sw, torch, args)
         else:
             res = mlp_throughput(torch)
         print(json.dumps({args.only: res}), flush=True)
@@ -564,76 +799,29 @@ def main():
 
     cell_updates = 2.0 * w.nshots * NX * NZ * w.nt
     value = cell_updates / dt / 1e9
+    progress(f"headline: {args.steps} gradients, {dt:.3f} s each, {value:.1f} Gcell/s")
     per_shot = None
     if args.per_shot_sample > 0:
         plan.release_workspace()
         torch.cuda.empty_cache()
         per_shot = per_shot_compare(sw, torch, w, v0, wav, d_obs, args.per_shot_sample,
                                     (args.rz, args.pml_rz, 0, args.tblock), dt)
+        progress("per-shot path")
 
-    # Algorithmic bytes per cell-update: interior kernel forward 16 B (read
-    # p^n, p^{n-1}, Cs; write p^{n+1}), recompute 20 B (+ write B^n), adjoint
-    # 28 B (read lambda^{n+1}, lambda^{n+2}, Cs, B^n, g; write lambda^n, g),
-    # 24 B on the first step of a segment (g written, not read). The C-PML
-    # kernels move the same per cell plus 16 B per C-PML axis at each strip cell
-    # (psi and zeta read and written). A two-step pass over a deep cell moves
-    # 20 B forward (read p^n, p^{n-1}, Cs; write p^{n+1}, p^{n+2}), 28 B in the
-    # recompute (+ B^n, B^{n+1}) and 36 B adjoint (read lambda^{n+1},
-    # lambda^{n+2}, Cs, B^n, B^{n-1}, g; write lambda^n, lambda^{n-1}, g), 32 B
-    # on a segment's first pair. Its "effective" rate counts the bytes of the
-    # two single steps it replaces.
-    k = w.ckpt_every
-    t = plan.tiles()
-    TZ = t["rows"]
-    wz = (t["x1"] - t["x0"]) * 64                       # z-frame columns
-    n_deep = t["deep"]
-    int_cells = t["interior"] * 64 * TZ
-    deep_cells = n_deep * 64 * TZ
-    ring_cells = int_cells - deep_cells
-    z_cells = wz * (t["z0"] * TZ + NZ - t["z1"] * TZ) if t["interior"] else 0
-    x_cells = NX * NZ - int_cells - z_cells
-    P = w.pml
-    z_strip = 2 * P * wz if t["interior"] else 0        # z-strip cells in the z frame
-    x_strip = 2 * P * NZ + 2 * P * NX - z_strip         # strip cells (per axis) in the x frame
-    base = {"fwd": 16.0, "rec": 20.0, "adj": (28.0 * (k - 1) + 24.0) / k}
-    pairs = k // 2
-    deep_b = {"fwd": 20.0, "rec": 28.0, "adj": (36.0 * (pairs - 1) + 32.0) / max(pairs, 1)}
-    per_launch, effective = {}, {}
-    for ph, b in base.items():
-        # single-step interior launches cover the ring tiles when two-step
-        # passes run (every launch of the class in this configuration)
-        per_launch[ph + "_int"] = b * (ring_cells if n_deep else int_cells) * w.nshots
-        per_launch[ph + "_zpml"] = (b * z_cells + 16.0 * z_strip) * w.nshots
-        per_launch[ph + "_xpml"] = (b * x_cells + 16.0 * x_strip) * w.nshots
-        per_launch[ph + "_deep"] = deep_b[ph] * deep_cells * w.nshots
-        effective[ph + "_deep"] = 2.0 * b * deep_cells * w.nshots
-    # Dominant kernel: largest time per gradient, average launch time x launches
-    # per gradient (a two-step pass runs once per two steps). The timer samples
-    # launches, so the sampled totals are not comparable between classes.
-    runs = {kk: (0.5 if kk.endswith("_deep") else 1.0) for kk in kt}
-    est = {kk: (vv[1] / vv[0]) * runs[kk] for kk, vv in kt.items() if vv[0] > 0}
-    dom = max(est, key=lambda kk: est[kk])
-    roof = None
-    if dom in per_launch and kt[dom][0] > 0:
-        launches, tot_ms = kt[dom]
-        avg_s = tot_ms / launches / 1e3
-        bytes_per_launch = per_launch[dom]
-        achieved = bytes_per_launch / avg_s / 1e9
-        tr = TRAFFIC.get(dom)
-        traffic = tr["bytes_per_launch"] if tr and tr["source"] == _source_hash() else None
-        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": dom, "avg_launch_us": round(avg_s * 1e6, 2),
-                "algorithmic_bytes_per_launch": int(bytes_per_launch)}
-    kernels = {}
-    for name, (nl, ms) in kt.items():
-        if nl > 0 and name in per_launch:
-            avg = ms / nl / 1e3
-            kernels[name] = {"launches": nl, "total_ms": round(ms, 3),
-                             "avg_us": round(avg * 1e6, 2),
-                             "algorithmic_GBps": round(per_launch[name] / avg / 1e9, 1)}
-            if name in effective:
-                kernels[name]["effective_step_GBps"] = round(effective[name] / avg / 1e9, 1)
+    roof, kernels, t = kernel_report(plan, w, kt)
+
+    # the same gradient with every checkpoint segment recomputed (no stored B'^n)
+    recompute = None
+    if not args.nt:
+        plan.release_workspace()
+        torch.cuda.empty_cache()
+        plan.set_tuning(keep_b=0)
+        plan.reserve_workspace(True)
+        step()
+        _, t_rc, t_rc_all = _median_time(torch, step)
+        recompute = {"keep_b": 0, "gradient_s": round(t_rc, 3), "samples_s": t_rc_all,
+                     "Gcell_per_s": round(cell_updates_of(plan, w) / t_rc / 1e9, 2)}
+        progress(f"checkpoint-recompute gradient {t_rc:.3f} s")
 
     out = {
         "metric": METRIC,
@@ -654,6 +842,7 @@ def main():
         "model_grid_value": round(value * w.nx * w.nz / (NX * NZ), 3),
         "roofline": roof,
         "per_shot": per_shot,
+        "checkpoint_recompute": recompute,
         "kernels": kernels,
         "tiles": t,
     }
@@ -661,19 +850,32 @@ def main():
         plan.release_workspace()
         del plan
         torch.cuda.empty_cache()
+        out["shots256"] = shots256(sw, torch, args)
+        progress("256 shots")
+        torch.cuda.empty_cache()
         out["born"] = born_modelling(sw, torch, case, w, v_true, v0, wav)
+        progress("born")
         torch.cuda.empty_cache()
         out["encoded"] = encoded_gradient(sw, torch)
+        progress("encoded")
         torch.cuda.empty_cache()
         out["batched_uneven"] = batched_uneven(sw, torch)
+        progress("batched uneven")
         torch.cuda.empty_cache()
         out["elastic"] = elastic_gradient(sw, torch)
+        progress("elastic")
         torch.cuda.empty_cache()
         out["acoustic_vd"] = acoustic_vd_gradient(sw, torch)
+        progress("acoustic_vd")
+        torch.cuda.empty_cache()
+        out["vti"] = vti_gradient(sw, torch)
+        progress("vti")
         out["mlp"] = mlp_throughput(torch)
+        progress("mlp")
     out["keep_b_fits"] = FIT_LOG
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
+        progress("cpu baseline")
     print(json.dumps(out), flush=True)
 
 

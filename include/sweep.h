@@ -295,6 +295,10 @@ int sweep_batch_create(const sweep_ctx* ctx, sweep_plan* const* plans, int nplan
                        sweep_batch** out);
 void sweep_batch_destroy(sweep_batch* batch);
 int sweep_batch_set_graph(sweep_batch* batch, int use_graph);
+/* Number of nodes of the captured forward and backward graphs (each node is
+ * one kernel launch of the batch's time loop; 0 when nothing is captured), so
+ * that a caller can see how many launches one graph launch replaces. */
+int sweep_batch_graph_nodes(const sweep_batch* batch, size_t* fwd_nodes, size_t* bwd_nodes);
 size_t sweep_batch_workspace_bytes(const sweep_batch* batch, int for_backward);
 int sweep_batch_forward(sweep_batch* batch, const float* const* d_models,
                         const float* const* d_wavelets, float* const* d_gathers, void* d_work,

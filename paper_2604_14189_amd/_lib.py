@@ -83,6 +83,8 @@ _SIGS = {
     "sweep_batch_destroy": (None, [ctypes.c_void_p]),
     "sweep_batch_set_graph": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "sweep_batch_workspace_bytes": (ctypes.c_size_t, [ctypes.c_void_p, ctypes.c_int]),
+    "sweep_batch_graph_nodes": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t),
+                                               ctypes.POINTER(ctypes.c_size_t)]),
     "sweep_batch_forward": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p),
                                            ctypes.POINTER(ctypes.c_void_p),
                                            ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p,

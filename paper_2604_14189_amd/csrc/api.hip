@@ -688,6 +688,8 @@ int run_maybe_graph(GraphCache& gc, bool use_graph, const std::vector<const void
       set_error(std::string("hipStreamEndCapture failed: ") + hipGetErrorString(e));
       return SWEEP_EHIP;
     }
+    size_t nn = 0;
+    if (hipGraphGetNodes(graph, nullptr, &nn) != hipSuccess) nn = 0;
     const hipError_t e2 = hipGraphInstantiate(&gc.exec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (e2 != hipSuccess) {
@@ -696,6 +698,7 @@ int run_maybe_graph(GraphCache& gc, bool use_graph, const std::vector<const void
       return SWEEP_EHIP;
     }
     gc.key = key;
+    gc.nodes = nn;
   }
   SWEEP_HIP(hipGraphLaunch(gc.exec, s));
   return SWEEP_OK;
@@ -1439,6 +1442,18 @@ extern "C" int sweep_batch_set_graph(sweep_batch* b, int use_graph) try {
   return SWEEP_OK;
 }
 SWEEP_ABI_CATCH("sweep_batch_set_graph")
+
+extern "C" int sweep_batch_graph_nodes(const sweep_batch* b, size_t* fwd_nodes,
+                                       size_t* bwd_nodes) try {
+  if (!b || !fwd_nodes || !bwd_nodes) {
+    set_error("sweep_batch_graph_nodes: null argument");
+    return SWEEP_EINVAL;
+  }
+  *fwd_nodes = b->gfwd.exec ? b->gfwd.nodes : 0;
+  *bwd_nodes = b->gbwd.exec ? b->gbwd.nodes : 0;
+  return SWEEP_OK;
+}
+SWEEP_ABI_CATCH("sweep_batch_graph_nodes")
 
 extern "C" size_t sweep_batch_workspace_bytes(const sweep_batch* b, int for_backward) try {
   if (!b) return 0;

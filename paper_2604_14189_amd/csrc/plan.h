@@ -109,6 +109,7 @@ struct GraphCache {
   hipGraphExec_t exec = nullptr;
   hipStream_t stream = nullptr;
   std::vector<const void*> key;
+  size_t nodes = 0;  // nodes (kernel launches) of the captured graph
   ~GraphCache() {
     if (exec) (void)hipGraphExecDestroy(exec);
     if (stream) (void)hipStreamDestroy(stream);
@@ -117,6 +118,7 @@ struct GraphCache {
     if (exec) (void)hipGraphExecDestroy(exec);
     exec = nullptr;
     key.clear();
+    nodes = 0;
   }
 };
 }  // namespace sweep

@@ -350,6 +350,12 @@ class Batch:
     def workspace_bytes(self, for_backward: bool) -> int:
         return int(lib().sweep_batch_workspace_bytes(self._h, int(bool(for_backward))))
 
+    def graph_nodes(self):
+        """(forward, backward): kernel launches held by the captured graphs."""
+        f, b = ctypes.c_size_t(), ctypes.c_size_t()
+        check(lib().sweep_batch_graph_nodes(self._h, ctypes.byref(f), ctypes.byref(b)))
+        return f.value, b.value
+
     def autotune(self, models, wavelets, steps: int = 10, gradient: bool = True,
                  cache_path: Optional[str] = None) -> dict:
         """Pick the fastest tiling (rz, pml_rz) and time-blocking depth (tblock)
@@ -379,17 +385,23 @@ class Batch:
             p._saved_id = -1
         return {"rz": chosen[0], "pml_rz": chosen[1], "tblock": chosen[2]}
 
-    def forward(self, models, wavelets, save: bool = False):
+    def forward(self, models, wavelets, save: bool = False, out=None):
+        """Gathers of every plan; `out` (optional): the gathers tensors to
+        write (fixed buffers keep a captured graph valid across calls)."""
         outs = []
         ms, ws = [], []
-        for p, m, w in zip(self.plans, models, wavelets):
+        for q, (p, m, w) in enumerate(zip(self.plans, models, wavelets)):
             if p.nparam == 1 and m.dim() == 2:
                 m = m.unsqueeze(0)
             _need(m, p._model_shape(), "model")
             _need(w, (p.nshots, p.nt), "wavelet")
             ms.append(m)
             ws.append(w)
-            outs.append(torch.empty(p.gathers_shape(), dtype=torch.float32, device=m.device))
+            if out is None:
+                outs.append(torch.empty(p.gathers_shape(), dtype=torch.float32, device=m.device))
+            else:
+                _need(out[q], p.gathers_shape(), "out")
+                outs.append(out[q])
         need = self.workspace_bytes(save)
         if self._work is None or self._work.numel() < need:
             self._work = None
@@ -401,13 +413,17 @@ class Batch:
         self._saved = bool(save)
         return outs
 
-    def backward(self, resids):
+    def backward(self, resids, out=None):
         if not self._saved:
             raise RuntimeError("Batch.backward needs a preceding forward(save=True)")
         grads = []
-        for p, r in zip(self.plans, resids):
+        for q, (p, r) in enumerate(zip(self.plans, resids)):
             _need(r, p.gathers_shape(), "resid")
-            grads.append(torch.empty(p._model_shape(), dtype=torch.float32, device=r.device))
+            if out is None:
+                grads.append(torch.empty(p._model_shape(), dtype=torch.float32, device=r.device))
+            else:
+                _need(out[q], p._model_shape(), "out")
+                grads.append(out[q])
         check(lib().sweep_batch_backward(self._h, _ptr_array(list(resids)), _ptr_array(grads),
                                          _ptr(self._work), self._work.numel(), _stream()))
         return grads
@@ -433,14 +449,17 @@ class WaveFn(torch.autograd.Function):
         return grad, None, None
 
 
-def l2_misfit(pred: torch.Tensor, obs: torch.Tensor):
-    """(resid, J): resid = pred - obs, J = 0.5 sum resid^2 (float64 tensor on device)."""
+def l2_misfit(pred: torch.Tensor, obs: torch.Tensor, resid: Optional[torch.Tensor] = None):
+    """(resid, J): resid = pred - obs, J = 0.5 sum resid^2 (float64 tensor on
+    device); `resid` (optional) is the buffer to write."""
     if pred.shape != obs.shape:
         raise ValueError("pred and obs shapes differ")
     _need(pred, pred.shape, "pred")
     _need(obs, obs.shape, "obs")
     n = pred.numel()
-    resid = torch.empty_like(pred)
+    if resid is None:
+        resid = torch.empty_like(pred)
+    _need(resid, pred.shape, "resid")
     J = torch.empty((), dtype=torch.float64, device=pred.device)
     scratch = torch.empty(int(lib().sweep_l2_misfit_scratch_bytes(n)), dtype=torch.uint8,
                           device=pred.device)
