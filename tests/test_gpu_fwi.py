@@ -4,8 +4,9 @@ parameterisation and through the MLP velocity model.
 (1) Chain rule: dJ/dtheta from MLP forward -> modelling -> misfit -> adjoint ->
 MLP backward on the GPU against the same chain composed from the oracles (FP64
 acoustic gradient, bf16-emulating FP64 MLP), every input generated on the host.
-(2) A small inversion: both methods lower the misfit; the run reports what the
-network gains or loses against grid FWI on model error and data misfit.
+(2) Small inversions: grid FWI against the network (what the network gains
+over grid FWI on model error and data misfit), and multi-scale (frequency
+continuation) grid FWI against single-scale from a far start.
 """
 import numpy as np
 import pytest
@@ -74,28 +75,81 @@ def test_neural_gradient_chain_matches_oracles(sw, orc):
     assert e_gt <= 1e-3
 
 
-def test_grid_and_neural_fwi_reduce_misfit(sw):
-    sw_, mlp, fwi = sw
-    w = synth.Workload("fwi_small", "acoustic", 160, 60, 10.0, 1e-3, 700, 20, 10.0, 6, 160, 3, 3,
-                       seed=3)
+def _small_fwi(sw_, w, sigma):
     v_true = w.true_model()
-    v_init = synth.smooth(v_true, 8.0)
     plan = sw_.Plan.from_workload(w)
     wav = _dev(w.wavelets())
     d_obs = plan.forward(_dev(v_true), wav).clone()
-    v0 = _dev(v_init)
+    return v_true, plan, wav, d_obs, _dev(synth.smooth(v_true, sigma))
+
+
+def test_grid_and_neural_fwi(sw):
+    """The network against grid FWI on a small problem (160 x 60, 6 shots,
+    700 steps), both from the same smoothed model (the network pre-fitted to
+    it), 60 iterations each. Both lower the misfit; the network's model error
+    stays bounded at the learning rate used here (1e-5: at the stated 1e-3 the
+    first Adam steps move every weight by 1e-3 and the model error grows
+    tenfold, on this problem and at full size). The outcome on this problem:
+    the network gains nothing over grid FWI, which ends with the lower misfit
+    and the lower model error."""
+    sw_, mlp, fwi = sw
+    w = synth.Workload("fwi_small", "acoustic", 160, 60, 10.0, 1e-3, 700, 20, 10.0, 6, 160, 3, 3,
+                       seed=3)
+    v_true, plan, wav, d_obs, v0 = _small_fwi(sw_, w, 8.0)
     net = mlp.MLPVelocity(w.nx, w.nz, f32(synth.rff_frequencies(seed=0)),
                           f32(omlp.init_params(4)))
     fit = fwi.prefit(net, v0, 400)
     r0 = {"grid": fwi.rmse(v0, v_true), "mlp": fwi.rmse(net.forward(), v_true)}
     runs = {"grid": fwi.GridFWI(plan, v0, wav, d_obs, lr=10.0),
-            "mlp": fwi.NeuralFWI(plan, net, wav, d_obs, lr=1e-3)}
+            "mlp": fwi.NeuralFWI(plan, net, wav, d_obs, lr=1e-5)}
     out = {}
     for name, opt in runs.items():
-        Js = [opt.step() for _ in range(30)]
+        Js = [opt.step() for _ in range(60)]
         out[name] = {"J_rel": Js[-1] / Js[0], "rmse0": r0[name],
                      "rmse": fwi.rmse(opt.velocity, v_true)}
     print("prefit rms", fit, "fwi", out, flush=True)
     for name in out:
         assert np.isfinite(out[name]["J_rel"]) and out[name]["J_rel"] < 0.9, name
     assert out["grid"]["rmse"] < out["grid"]["rmse0"]
+    assert out["mlp"]["rmse"] < 1.1 * out["mlp"]["rmse0"]
+    assert out["grid"]["J_rel"] < out["mlp"]["J_rel"]
+    assert out["grid"]["rmse"] < out["mlp"]["rmse"]
+
+
+def test_multiscale_fwi_from_a_far_start(sw):
+    """Frequency continuation from a strongly smoothed start (sigma 20 cells):
+    4 Hz, 7 Hz, then the full band (10 Hz Ricker), 20 iterations each, against
+    60 full-band iterations of grid FWI. Multi-scale ends with the lower
+    full-band misfit and the lower model error."""
+    sw_, _, fwi = sw
+    w = synth.Workload("fwi_small", "acoustic", 160, 60, 10.0, 1e-3, 700, 20, 10.0, 6, 160, 3, 3,
+                       seed=3)
+    v_true, plan, wav, d_obs, v0 = _small_fwi(sw_, w, 20.0)
+    grid = fwi.GridFWI(plan, v0, wav, d_obs, lr=10.0)
+    Js = [grid.step() for _ in range(60)]
+    ms = fwi.MultiScaleFWI(plan, v0, wav, d_obs, [(4.0, 20), (7.0, 20), (None, 20)], dt=w.dt,
+                           lr=10.0)
+    v = ms.run()
+    _, J = sw_.l2_misfit(plan.forward(v, wav), d_obs)
+    res = {"grid_J_rel": Js[-1] / Js[0], "multiscale_J_rel": float(J.item()) / Js[0],
+           "rmse0": fwi.rmse(v0, v_true), "grid_rmse": fwi.rmse(grid.velocity, v_true),
+           "multiscale_rmse": fwi.rmse(v, v_true)}
+    stage_ratio = []
+    for k in range(3):
+        Jk = [h[3] for h in ms.history if h[0] == k]
+        stage_ratio.append(Jk[-1] / Jk[0])
+    print("multiscale", res, "band misfit ratio per stage", stage_ratio, flush=True)
+    assert res["multiscale_J_rel"] < 0.8 * res["grid_J_rel"]
+    assert res["multiscale_rmse"] < res["grid_rmse"] < res["rmse0"]
+
+
+def test_lowpass_is_zero_phase_and_band_limited(sw):
+    _, _, fwi = sw
+    dt, n = 1e-3, 2000
+    t = torch.arange(n, dtype=torch.float64, device="cuda") * dt
+    x = (torch.sin(2 * np.pi * 3.0 * t) + torch.sin(2 * np.pi * 40.0 * t)).float()[None]
+    y = fwi.lowpass(x, dt, 10.0)
+    low = torch.sin(2 * np.pi * 3.0 * t).float()[None]
+    # the 40 Hz part is removed and the 3 Hz part passes unshifted (away from
+    # the ends, where the periodic extension of the FFT differs)
+    assert float((y - low)[:, 200:-200].abs().max()) < 1e-3
