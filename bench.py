@@ -361,12 +361,15 @@ def batched_uneven(sw, torch, tuning=None):
             "per_shot_sample": "middle shot of each model, scaled by its shot count"}
 
 
-def elastic_gradient(sw, torch):
+def elastic_gradient(sw, torch, nt=0):
     """Elastic velocity-stress FWI gradient (vp, vs, rho) on the 600x300
-    free-surface workload: 32 shots, 4000 steps, checkpoints every 50."""
+    free-surface workload: 32 shots, 4000 steps (nt > 0: that many, for
+    profiling), checkpoints every 50."""
     import synth
     from synth.cases import el_case_from_workload
     w = synth.workload("elastic600x300")
+    if nt:
+        w = w.replace(nt=nt)
     case = el_case_from_workload(w)
     plan = case.plan()
     wav = torch.tensor(case.wav, dtype=torch.float32, device="cuda")
@@ -492,14 +495,17 @@ def acoustic_vd_gradient(sw, torch):
             "Gcell_per_s": round(cells / t / 1e9, 2)}
 
 
-def vti_gradient(sw, torch):
+def vti_gradient(sw, torch, nt=0):
     """Pseudo-acoustic VTI FWI gradient (vv, v, eta) on the 1000x300 grid with
-    the layered benchmark's shots and receivers (64 shots, 3000 steps, 40-cell
-    C-PML), eta up to 0.12 below an isotropic top zone; initial model the
-    20-cell smoothing of the true one. Checkpoints every 50 steps, every
-    segment recomputed (VTI plans store none)."""
+    the layered benchmark's shots and receivers (64 shots, 3000 steps (nt > 0:
+    that many, for profiling), 40-cell C-PML), eta up to 0.12 below an
+    isotropic top zone; initial model the 20-cell smoothing of the true one.
+    Checkpoints every 50 steps, every segment recomputed (VTI plans store
+    none)."""
     import synth
     w = synth.workload("vti1000x300")
+    if nt:
+        w = w.replace(nt=nt)
     m_true = np.asarray(w.true_model(), np.float32)
     model = torch.tensor(m_true, device="cuda")
     m0 = torch.tensor(np.stack([synth.smooth(c, 20.0) for c in m_true]).astype(np.float32),
@@ -741,13 +747,13 @@ def main():
         elif args.only == "batched_uneven":
             res = batched_uneven(sw, torch)
         elif args.only == "elastic":
-            res = elastic_gradient(sw, torch)
+            res = elastic_gradient(sw, torch, args.nt)
         elif args.only == "acoustic_vd":
             res = acoustic_vd_gradient(sw, torch)
         elif args.only == "encoded":
             res = encoded_gradient(sw, torch)
         elif args.only == "vti":
-            res = vti_gradient(sw, torch)
+            res = vti_gradient(sw, torch, args.nt)
         elif args.only == "shots256":
             res = shots256(sw, torch, args)
         else:

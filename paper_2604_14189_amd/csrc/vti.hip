@@ -209,11 +209,15 @@ __global__ __launch_bounds__(kThreads) void vti_fwd_kernel(VtiStep a) {
 // Psi = b psbar, Z = b (Z + q); g += P1 (Bx', Bz', -D2x'D2z'G^n); then r_{n-1}
 // is added at the receivers.
 __global__ __launch_bounds__(kThreads) void vti_adj_kernel(VtiStep a) {
-  __shared__ float sL[PH * PW];    // lambda^{n+1}, 8-cell halo; staging at the end
+  // lambda^{n+1} with an 8-cell halo; once the products are formed, the same
+  // memory holds D2z'(cm lambda^{n+1}) (float64, tile rows, 4-column ring),
+  // and at the end the staging of lambda^n for the residual injection
+  __shared__ __align__(16) float sL[PH * PW];
   __shared__ float sQx[kTZ * PW];  // Qbar_x on the tile rows, 8-column ring
   __shared__ float sQz[PH * kTX];  // Qbar_z on the tile columns, 8-row ring
   __shared__ double sM[GH * GW];   // cm lambda^{n+1} (float64), 4-cell halo
-  __shared__ double sU[kTZ * GW];  // D2z'(cm lambda^{n+1}) on the tile rows, 4-column ring
+  double* sU = reinterpret_cast<double*>(sL);
+  static_assert(kTZ * GW * sizeof(double) <= PH * PW * sizeof(float), "sU fits in sL");
   __shared__ float sTx[kTZ * GW];  // T_x on the tile rows, 4-column ring
   __shared__ float sTz[GH * kTX];  // T_z on the tile columns, 4-row ring
   const int f = xcd_spread(blockIdx.x, gridDim.x);
@@ -246,38 +250,68 @@ __global__ __launch_bounds__(kThreads) void vti_adj_kernel(VtiStep a) {
     zx[r] = ok && xcol >= 0 ? a.zex_in[((size_t)shot * NZ + gz) * P2 + xcol] : 0.0f;
     zz[r] = zrow >= 0 ? a.zez_in[((size_t)shot * P2 + zrow) * NX + gx] : 0.0f;
   }
+  // the coefficients of the three product boxes (and, in tiles near a strip,
+  // the zeta adjoints there) are loaded with the lambda box, before any LDS
+  // store, so a lane keeps all its loads in flight together
+  constexpr int NQX = kTZ * PW, KQX = (NQX + kThreads - 1) / kThreads;
+  constexpr int NQZ = PH * kTX, KQZ = (NQZ + kThreads - 1) / kThreads;
+  constexpr int NM = GH * GW, KM = (NM + kThreads - 1) / kThreads;
+  float vcx[KQX], vzx[KQX], vcz[KQZ], vzz[KQZ], vcm[KM];
+#pragma unroll
+  for (int k = 0; k < KQX; ++k) {
+    const int e = tid + k * kThreads, r = e / PW, c = e - r * PW;
+    const int x = x0 - 8 + c, z = z0 + r;
+    const bool ok = e < NQX && in_grid(x, z, NX, NZ);
+    vcx[k] = ok ? a.cx[(size_t)z * NX + x] : 0.0f;
+    const int col = ok && hx ? xstrip_col(x, NX, P) : -1;
+    vzx[k] = col >= 0 ? a.zex_in[((size_t)shot * NZ + z) * P2 + col] : 0.0f;
+  }
+#pragma unroll
+  for (int k = 0; k < KQZ; ++k) {
+    const int e = tid + k * kThreads, r = e / kTX, c = e - r * kTX;
+    const int x = x0 + c, z = z0 - 8 + r;
+    const bool ok = e < NQZ && in_grid(x, z, NX, NZ);
+    vcz[k] = ok ? a.cz[(size_t)z * NX + x] : 0.0f;
+    const int row = ok && hz ? zstrip_row(z, NZ, P) : -1;
+    vzz[k] = row >= 0 ? a.zez_in[((size_t)shot * P2 + row) * NX + x] : 0.0f;
+  }
+#pragma unroll
+  for (int k = 0; k < KM; ++k) {
+    const int e = tid + k * kThreads, r = e / GW, c = e - r * GW;
+    const int x = x0 - 4 + c, z = z0 - 4 + r;
+    vcm[k] = e < NM && in_grid(x, z, NX, NZ) ? a.cm[(size_t)z * NX + x] : 0.0f;
+  }
   stage<PW, PH>(sL, a.cur + base, x0, z0, 8, 8, NX, NZ);
   __syncthreads();
+  float l1v[kRZ];
+#pragma unroll
+  for (int rr = 0; rr < kRZ; ++rr) l1v[rr] = sL[(zb + rr + 8) * PW + lx + 8];
 
   // products with the coefficients, and the x / z memory terms of Qbar
-  for (int e = tid; e < kTZ * PW; e += kThreads) {
-    const int r = e / PW, c = e - r * PW;
-    const int x = x0 - 8 + c, z = z0 + r;
-    float q = 0.0f;
-    if (in_grid(x, z, NX, NZ)) {
-      q = a.cx[(size_t)z * NX + x] * sL[(r + 8) * PW + c];
-      const int col = hx ? xstrip_col(x, NX, P) : -1;
-      if (col >= 0) q = q + a.ax[x] * (a.zex_in[((size_t)shot * NZ + z) * P2 + col] + q);
-    }
-    sQx[e] = q;
+  // (outside the grid every operand is 0)
+#pragma unroll
+  for (int k = 0; k < KQX; ++k) {
+    const int e = tid + k * kThreads, r = e / PW, c = e - r * PW;
+    if (e >= NQX) break;
+    const float q = vcx[k] * sL[(r + 8) * PW + c];
+    const int x = x0 - 8 + c;
+    const int col = hx && x >= 0 && x < NX ? xstrip_col(x, NX, P) : -1;
+    sQx[e] = col >= 0 ? q + a.ax[x] * (vzx[k] + q) : q;
   }
-  for (int e = tid; e < PH * kTX; e += kThreads) {
-    const int r = e / kTX, c = e - r * kTX;
-    const int x = x0 + c, z = z0 - 8 + r;
-    float q = 0.0f;
-    if (in_grid(x, z, NX, NZ)) {
-      q = a.cz[(size_t)z * NX + x] * sL[r * PW + c + 8];
-      const int row = hz ? zstrip_row(z, NZ, P) : -1;
-      if (row >= 0) q = q + a.az[z] * (a.zez_in[((size_t)shot * P2 + row) * NX + x] + q);
-    }
-    sQz[e] = q;
+#pragma unroll
+  for (int k = 0; k < KQZ; ++k) {
+    const int e = tid + k * kThreads, r = e / kTX, c = e - r * kTX;
+    if (e >= NQZ) break;
+    const float q = vcz[k] * sL[r * PW + c + 8];
+    const int z = z0 - 8 + r;
+    const int row = hz && z >= 0 && z < NZ ? zstrip_row(z, NZ, P) : -1;
+    sQz[e] = row >= 0 ? q + a.az[z] * (vzz[k] + q) : q;
   }
-  for (int e = tid; e < GH * GW; e += kThreads) {
-    const int r = e / GW, c = e - r * GW;
-    const int x = x0 - 4 + c, z = z0 - 4 + r;
-    sM[e] = in_grid(x, z, NX, NZ)
-                ? (double)a.cm[(size_t)z * NX + x] * (double)sL[(r + 4) * PW + c + 4]
-                : 0.0;
+#pragma unroll
+  for (int k = 0; k < KM; ++k) {
+    const int e = tid + k * kThreads, r = e / GW, c = e - r * GW;
+    if (e >= NM) break;
+    sM[e] = (double)vcm[k] * (double)sL[(r + 4) * PW + c + 4];
   }
   __syncthreads();
 
@@ -323,7 +357,7 @@ __global__ __launch_bounds__(kThreads) void vti_adj_kernel(VtiStep a) {
     const int r = zb + rr, gz = z0 + r;
     const bool ok = gx < NX && gz < NZ;
     const size_t idx = ok ? (size_t)gz * NX + gx : 0;
-    const float l1 = sL[(r + 8) * PW + lx + 8];
+    const float l1 = l1v[rr];
     float lam = 2.0f * l1 - l2[rr];
     lam += d2s(&sQx[r * PW + lx + 8], 1);
     lam += d2s(&sQz[(r + 8) * kTX + lx], kTX);
