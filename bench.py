@@ -35,9 +35,9 @@ METRIC = "Gcell-updates/s fwd+adj; batched vs per-shot FWI gradient time at 1e-4
 # for a plain device copy of known size (--calibrate-copy). Keyed by kernel
 # class; valid only while the kernel source hashes to the recorded value.
 TRAFFIC = {
-    "adj_deep": {"bytes_per_launch": 605979136, "source": "ca308c7fec215422"},
-    "adj_zpml": {"bytes_per_launch": 293570070, "source": "ca308c7fec215422"},
-    "adj_xpml": {"bytes_per_launch": 129839843, "source": "ca308c7fec215422"},
+    "adj_deep": {"bytes_per_launch": 605895243, "source": "d085c20f2f747647"},
+    "adj_zpml": {"bytes_per_launch": 293324280, "source": "d085c20f2f747647"},
+    "adj_xpml": {"bytes_per_launch": 129790301, "source": "d085c20f2f747647"},
 }
 
 
@@ -361,6 +361,37 @@ def batched_uneven(sw, torch, tuning=None):
             "per_shot_sample": "middle shot of each model, scaled by its shot count"}
 
 
+# Algorithmic bytes per cell of one elastic step (interior cells; the C-PML
+# memory variables of the strips come on top): forward velocity kernel 36 B
+# (read txx, tzz, txz, vx, vz, bx, bz; write vx, vz) and stress kernel 44 B
+# (read vx, vz, txx, tzz, txz and the coefficients cxx_x, cxx_z, mxz; write the
+# stresses); the storing forward adds the five trace planes (20 B); the
+# reverse kernels 76 B (stress adjoints, three coefficients, velocity adjoints,
+# three traces and three gradient partials read; velocity adjoints and the
+# partials written) and 64 B (velocity adjoints, bx, bz, stress adjoints, two
+# traces and two partials read; stress adjoints and the partials written).
+EL_STEP_BYTES = {"fwd_int": 80, "rec_int": 100, "adj_int": 140}
+
+
+def el_step_kernels(torch, plan, grad, step_cells):
+    """Per-step kernel times of a staggered-grid plan (velocity + receivers +
+    stress, or the two reverse kernels and the residual injection), from one
+    more gradient timed every 10th step, with their algorithmic GB/s."""
+    plan.set_profiling(True, 10)
+    grad()
+    torch.cuda.synchronize()
+    kt = plan.kernel_times()
+    plan.set_profiling(False)
+    out = {}
+    for cls, nbytes in EL_STEP_BYTES.items():
+        n, ms = kt.get(cls, (0, 0.0))
+        if n:
+            us = 1e3 * ms / n
+            out[cls] = {"steps_timed": n, "avg_us": round(us, 1), "bytes_per_cell": nbytes,
+                        "algorithmic_GBps": round(nbytes * step_cells / us / 1e3, 1)}
+    return out
+
+
 def elastic_gradient(sw, torch, nt=0):
     """Elastic velocity-stress FWI gradient (vp, vs, rho) on the 600x300
     free-surface workload: 32 shots, 4000 steps (nt > 0: that many, for
@@ -387,10 +418,11 @@ def elastic_gradient(sw, torch, nt=0):
     _, t, ts = _median_time(torch, grad)
     NX, NZ = plan.padded()
     cells = 2.0 * w.nshots * NX * NZ * w.nt
+    kernels = el_step_kernels(torch, plan, grad, w.nshots * NX * NZ)
     plan.release_workspace()
     return {"workload": "elastic600x300", "padded": f"{NX}x{NZ}", "shots": w.nshots,
             "nt": w.nt, "keep_b": keep, "gradient_s": round(t, 3), "samples_s": ts,
-            "Gcell_per_s": round(cells / t / 1e9, 2)}
+            "Gcell_per_s": round(cells / t / 1e9, 2), "step_kernels": kernels}
 
 
 def born_modelling(sw, torch, case, w, v_true, v0, wav):
@@ -488,11 +520,12 @@ def acoustic_vd_gradient(sw, torch):
     grad()
     _, t, ts = _median_time(torch, grad)
     NX, NZ = plan.padded()
+    kernels = el_step_kernels(torch, plan, grad, w.nshots * NX * NZ)
     plan.release_workspace()
     cells = 2.0 * w.nshots * NX * NZ * w.nt
     return {"workload": "layered1000x300, rho = 310 vp^0.25", "shots": w.nshots, "nt": w.nt,
             "keep_b": keep, "gradient_s": round(t, 3), "samples_s": ts,
-            "Gcell_per_s": round(cells / t / 1e9, 2)}
+            "Gcell_per_s": round(cells / t / 1e9, 2), "step_kernels": kernels}
 
 
 def vti_gradient(sw, torch, nt=0):

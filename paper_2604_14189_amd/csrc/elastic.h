@@ -10,6 +10,8 @@ struct ElCoef {
   float *vp, *vs, *rho, *lam, *mu;              // [NZ][NX]
   float *bx, *bz, *mxz;                          // buoyancy at vx / vz nodes, mu at txz nodes
   float *cxx_x, *cxx_z, *czz_x, *czz_z, *smask;  // stress-update coefficients, tzz source mask
+                                                 // (the step kernels derive czz_x, czz_z from
+                                                 // cxx_z, cxx_x; see elastic.hip)
   float *dM_dl, *dM_dm;                          // [NX] free-surface modulus derivatives (row 0)
   float *axi, *bxi, *axh, *bxh;                  // [NX] C-PML, integer / half nodes
   float *azi, *bzi, *azh, *bzh;                  // [NZ]
@@ -19,7 +21,7 @@ struct ElCoef {
 struct ElStep {
   int NX, NZ, nt, nrec, nshots, n, fs;
   float dt, w, ih;  // time step, source scale dt/h^2, 1/h
-  const float *bx, *bz, *mxz, *cxx_x, *cxx_z, *czz_x, *czz_z, *smask, *dM_dl, *dM_dm;
+  const float *bx, *bz, *mxz, *cxx_x, *cxx_z, *smask, *dM_dl, *dM_dm;
   const float *axi, *bxi, *axh, *bxh, *azi, *bzi, *azh, *bzh;
   // fields [shot][NZ][NX]: forward state, or the adjoint state in the reverse pass
   float *vx, *vz, *txx, *tzz, *txz;

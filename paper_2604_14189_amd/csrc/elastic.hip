@@ -156,6 +156,15 @@ struct ElCells {
   }
 };
 
+// The stress update is txx += dt (cxx_x exx + cxx_z ezz), tzz += dt (czz_x exx +
+// czz_z ezz). Away from a free surface cxx_x = czz_z = lambda + 2 mu and
+// cxx_z = czz_x = lambda; on the free-surface row cxx_x = M and the other three
+// are 0. So czz_x = cxx_z everywhere, and czz_z (of row j) follows from cxx_x:
+// the kernels read two coefficient planes instead of four.
+__device__ __forceinline__ float czz_z(const ElStep& a, int j, float cxx_x) {
+  return a.fs && j == 0 ? 0.0f : cxx_x;
+}
+
 // C-PML update with a preloaded memory variable: psi <- b psi + a G where
 // a != 0 (stored), returns G + psi; G elsewhere.
 __device__ __forceinline__ float cpml_p(float* psi, size_t k, float G, float a, float b, float p0,
@@ -259,8 +268,8 @@ __global__ __launch_bounds__(256) void el_str_kernel(ElStep a) {
   const ElCells C(T, NX);
   const float axi = a.axi[C.ic], bxi = a.bxi[C.ic], axh = a.axh[C.ic], bxh = a.bxh[C.ic];
   const bool wxi = __any(axi != 0.0f), wxh = __any(axh != 0.0f);
-  float otxx[kElRZ], otzz[kElRZ], otxz[kElRZ], cxx_x[kElRZ], cxx_z[kElRZ], czz_x[kElRZ],
-      czz_z[kElRZ], mxz[kElRZ], p4[kElRZ], p5[kElRZ], p6[kElRZ], p7[kElRZ];
+  float otxx[kElRZ], otzz[kElRZ], otxz[kElRZ], cxx_x[kElRZ], cxx_z[kElRZ], mxz[kElRZ],
+      p4[kElRZ], p5[kElRZ], p6[kElRZ], p7[kElRZ];
   float azi[kElRZ], bzi[kElRZ], azh[kElRZ], bzh[kElRZ];
 #pragma unroll
   for (int r = 0; r < kElRZ; ++r) {
@@ -271,8 +280,6 @@ __global__ __launch_bounds__(256) void el_str_kernel(ElStep a) {
     otxz[r] = a.txz[so + k];
     cxx_x[r] = a.cxx_x[k];
     cxx_z[r] = a.cxx_z[k];
-    czz_x[r] = a.czz_x[k];
-    czz_z[r] = a.czz_z[k];
     mxz[r] = a.mxz[k];
     azi[r] = a.azi[jc];
     bzi[r] = a.bzi[jc];
@@ -303,7 +310,7 @@ __global__ __launch_bounds__(256) void el_str_kernel(ElStep a) {
     const float exz = cpml_p(a.ps[6] + so, k, Gg, azh[r], bzh[r], p6[r], true) +
                       cpml_p(a.ps[7] + so, k, Gh, axh, bxh, p7[r], true);
     float txx = otxx[r] + dt * fmaf(cxx_x[r], exx, cxx_z[r] * ezz);
-    float tzz = otzz[r] + dt * fmaf(czz_x[r], exx, czz_z[r] * ezz);
+    float tzz = otzz[r] + dt * fmaf(cxx_z[r], exx, czz_z(a, j, cxx_x[r]) * ezz);
     if ((int)k == src) {
       txx += sw;
       tzz += sw * a.smask[k];
@@ -342,54 +349,78 @@ __device__ __forceinline__ float dzT(const ElStep& a, int kind, int j, F g, bool
   return -fmaf(C2, g(j + 2) - g(j - 1), C1 * (g(j + 1) - g(j)));
 }
 
-// Stages the derivative-input adjoints of the stress step on the tile plus the
-// halo: gbe (exx input), gbf (ezz), gbg (Dz vx of exz), gbh (Dx vz of exz).
-__device__ __forceinline__ void el_stage_adj_s(const ElStep& a, float (*sb)[kElBox], size_t so,
-                                               int x0, int z0) {
-  const int NX = a.NX, NZ = a.NZ;
-  const float dt = a.dt;
-  float txx[kElK], tzz[kElK], txz[kElK], cxx_x[kElK], czz_x[kElK], cxx_z[kElK], czz_z[kElK],
-      mxz[kElK], ax[kElK], az[kElK], azh[kElK], axh[kElK], q4[kElK], q5[kElK], q6[kElK],
-      q7[kElK];
-#pragma unroll
-  for (int k = 0; k < kElK; ++k) {
-    const int e = threadIdx.x + k * kThreads;
-    const int r = e / kElBW, c = e - (e / kElBW) * kElBW;
-    const int gx = x0 - 2 + c, gz = z0 - 2 + r;
-    const bool ok = e < kElBox && gx >= 0 && gx < NX && gz >= 0 && gz < NZ;
-    const size_t q = ok ? (size_t)gz * NX + gx : 0;
-    const int cx = ok ? gx : 0, cz = ok ? gz : 0;
-    txx[k] = ldz(a.txx + so, q, ok, a.txx);
-    tzz[k] = ldz(a.tzz + so, q, ok, a.tzz);
-    txz[k] = ldz(a.txz + so, q, ok, a.txz);
-    cxx_x[k] = ldz(a.cxx_x, q, ok, a.cxx_x);
-    czz_x[k] = ldz(a.czz_x, q, ok, a.czz_x);
-    cxx_z[k] = ldz(a.cxx_z, q, ok, a.cxx_z);
-    czz_z[k] = ldz(a.czz_z, q, ok, a.czz_z);
-    mxz[k] = ldz(a.mxz, q, ok, a.mxz);
-    ax[k] = ldz(a.axi, cx, ok, a.axi);
-    az[k] = ldz(a.azi, cz, ok, a.azi);
-    azh[k] = ldz(a.azh, cz, ok, a.azh);
-    axh[k] = ldz(a.axh, cx, ok, a.axh);
-    // memory variables only where a wave has a C-PML cell (wave-uniform branch)
-    q4[k] = __any(ax[k] != 0.0f) ? ldz(a.ps_in[4] + so, q, ok, a.ps_in[4]) : 0.0f;
-    q5[k] = __any(az[k] != 0.0f) ? ldz(a.ps_in[5] + so, q, ok, a.ps_in[5]) : 0.0f;
-    q6[k] = __any(azh[k] != 0.0f) ? ldz(a.ps_in[6] + so, q, ok, a.ps_in[6]) : 0.0f;
-    q7[k] = __any(axh[k] != 0.0f) ? ldz(a.ps_in[7] + so, q, ok, a.ps_in[7]) : 0.0f;
-  }
-#pragma unroll
-  for (int k = 0; k < kElK; ++k) {
-    const int e = threadIdx.x + k * kThreads;
-    if (e >= kElBox) break;
-    const float e1 = dt * fmaf(cxx_x[k], txx[k], czz_x[k] * tzz[k]);
-    const float e2 = dt * fmaf(cxx_z[k], txx[k], czz_z[k] * tzz[k]);
-    const float e3 = dt * mxz[k] * txz[k];
-    // outside the grid every operand is 0, so every value below is 0 too
-    sb[0][e] = ax[k] == 0.0f ? e1 : fmaf(ax[k], q4[k] + e1, e1);
-    sb[1][e] = az[k] == 0.0f ? e2 : fmaf(az[k], q5[k] + e2, e2);
-    sb[2][e] = azh[k] == 0.0f ? e3 : fmaf(azh[k], q6[k] + e3, e3);
-    sb[3][e] = axh[k] == 0.0f ? e3 : fmaf(axh[k], q7[k] + e3, e3);
-  }
+// The reverse kernels split the box cells of a tile between the threads: a
+// thread stages its own cells (box column lx + 2, rows kElRZ w + 2 ..
+// kElRZ w + kElRZ + 1) and keeps their raw values in registers for its own
+// update, and up to kElKH of the kElHalo halo cells (the two rows above and
+// below the tile, the two columns left and right of it). Reading its own
+// cells again after the LDS phase would miss L2: by then the other resident
+// work-groups' reads have evicted them.
+constexpr int kElHalo = kElBox - kTX * kElTZ;
+constexpr int kElKH = (kElHalo + kThreads - 1) / kThreads;
+static_assert(kElBW == kTX + 4 && kElBH == kElTZ + 4 && kThreads == 4 * kTX, "tile geometry");
+
+// box index of halo cell h < kElHalo
+__device__ __forceinline__ int el_halo_cell(int h) {
+  if (h < 2 * kElBW) return h;                                // rows 0, 1
+  if (h < 4 * kElBW) return h + (kElBH - 4) * kElBW;          // the last two rows
+  const int q = h - 4 * kElBW, c = q & 3;                     // columns 0, 1, 66, 67
+  return (2 + (q >> 2)) * kElBW + (c < 2 ? c : kTX + c);
+}
+// box index of this thread's own cell in row r of its rows
+__device__ __forceinline__ int el_own_cell(int r) {
+  return ((int)(threadIdx.x >> 6) * kElRZ + r + 2) * kElBW + (int)(threadIdx.x & 63) + 2;
+}
+
+// Raw inputs of one box cell of the stress-adjoint staging (zero outside the
+// grid or where !valid; every lane takes part, as the C-PML tests are votes
+// of the wave).
+struct AdjS {
+  float txx, tzz, txz, cxx_x, czz_x, cxx_z, czz_z, mxz, ax, az, azh, axh, q4, q5, q6, q7;
+};
+__device__ __forceinline__ void adj_s_load(const ElStep& a, size_t so, int e, bool valid, int x0,
+                                           int z0, AdjS& v) {
+  const int r = e / kElBW, c = e - (e / kElBW) * kElBW;
+  const int gx = x0 - 2 + c, gz = z0 - 2 + r;
+  const bool ok = valid && gx >= 0 && gx < a.NX && gz >= 0 && gz < a.NZ;
+  const size_t q = ok ? (size_t)gz * a.NX + gx : 0;
+  const int cx = ok ? gx : 0, cz = ok ? gz : 0;
+  v.txx = ldz(a.txx + so, q, ok, a.txx);
+  v.tzz = ldz(a.tzz + so, q, ok, a.tzz);
+  v.txz = ldz(a.txz + so, q, ok, a.txz);
+  v.cxx_x = ldz(a.cxx_x, q, ok, a.cxx_x);
+  v.cxx_z = ldz(a.cxx_z, q, ok, a.cxx_z);
+  v.czz_x = v.cxx_z;
+  v.czz_z = czz_z(a, gz, v.cxx_x);
+  v.mxz = ldz(a.mxz, q, ok, a.mxz);
+  v.ax = ldz(a.axi, cx, ok, a.axi);
+  v.az = ldz(a.azi, cz, ok, a.azi);
+  v.azh = ldz(a.azh, cz, ok, a.azh);
+  v.axh = ldz(a.axh, cx, ok, a.axh);
+  // memory variables only where a wave has a C-PML cell (wave-uniform branch)
+  v.q4 = __any(v.ax != 0.0f) ? ldz(a.ps_in[4] + so, q, ok, a.ps_in[4]) : 0.0f;
+  v.q5 = __any(v.az != 0.0f) ? ldz(a.ps_in[5] + so, q, ok, a.ps_in[5]) : 0.0f;
+  v.q6 = __any(v.azh != 0.0f) ? ldz(a.ps_in[6] + so, q, ok, a.ps_in[6]) : 0.0f;
+  v.q7 = __any(v.axh != 0.0f) ? ldz(a.ps_in[7] + so, q, ok, a.ps_in[7]) : 0.0f;
+}
+// ebar of the three stress-step inputs: dt (stress coefficients) x (stress adjoints)
+__device__ __forceinline__ float adj_ex(const AdjS& v, float dt) {
+  return dt * fmaf(v.cxx_x, v.txx, v.czz_x * v.tzz);
+}
+__device__ __forceinline__ float adj_ez(const AdjS& v, float dt) {
+  return dt * fmaf(v.cxx_z, v.txx, v.czz_z * v.tzz);
+}
+__device__ __forceinline__ float adj_exz(const AdjS& v, float dt) { return dt * v.mxz * v.txz; }
+
+// derivative-input adjoints gbe (exx input), gbf (ezz), gbg (Dz vx of exz),
+// gbh (Dx vz of exz) of box cell e (outside the grid every operand is 0, so
+// every value is 0 too)
+__device__ __forceinline__ void adj_s_put(float (*sb)[kElBox], int e, float dt, const AdjS& v) {
+  const float e1 = adj_ex(v, dt), e2 = adj_ez(v, dt), e3 = adj_exz(v, dt);
+  sb[0][e] = v.ax == 0.0f ? e1 : fmaf(v.ax, v.q4 + e1, e1);
+  sb[1][e] = v.az == 0.0f ? e2 : fmaf(v.az, v.q5 + e2, e2);
+  sb[2][e] = v.azh == 0.0f ? e3 : fmaf(v.azh, v.q6 + e3, e3);
+  sb[3][e] = v.axh == 0.0f ? e3 : fmaf(v.axh, v.q7 + e3, e3);
 }
 
 __global__ __launch_bounds__(256) void el_adj_s_kernel(ElStep a) {
@@ -398,37 +429,35 @@ __global__ __launch_bounds__(256) void el_adj_s_kernel(ElStep a) {
   const int NX = a.NX, NZ = a.NZ;
   const size_t plane = (size_t)NX * NZ;
   const size_t so = (size_t)T.shot * plane;
-  el_stage_adj_s(a, sb, so, T.x0, T.z0);
+  const float dt = a.dt, ih = a.ih;
+  AdjS hv[kElKH], ov[kElRZ];
+#pragma unroll
+  for (int k = 0; k < kElKH; ++k) {
+    const int h = (int)threadIdx.x + k * kThreads;
+    adj_s_load(a, so, h < kElHalo ? el_halo_cell(h) : 0, h < kElHalo, T.x0, T.z0, hv[k]);
+  }
+#pragma unroll
+  for (int r = 0; r < kElRZ; ++r) adj_s_load(a, so, el_own_cell(r), true, T.x0, T.z0, ov[r]);
+#pragma unroll
+  for (int k = 0; k < kElKH; ++k) {
+    const int h = (int)threadIdx.x + k * kThreads;
+    if (h < kElHalo) adj_s_put(sb, el_halo_cell(h), dt, hv[k]);
+  }
+#pragma unroll
+  for (int r = 0; r < kElRZ; ++r) adj_s_put(sb, el_own_cell(r), dt, ov[r]);
   const ElCells C(T, NX);
-  const float axi = a.axi[C.ic], bxi = a.bxi[C.ic], axh = a.axh[C.ic], bxh = a.bxh[C.ic];
-  const bool wxi = __any(axi != 0.0f), wxh = __any(axh != 0.0f);
+  const float bxi = a.bxi[C.ic], bxh = a.bxh[C.ic];
   const bool gacc = !a.g_init;
-  float ovx[kElRZ], ovz[kElRZ], txx[kElRZ], tzz[kElRZ], txz[kElRZ], cxx_x[kElRZ], czz_x[kElRZ],
-      cxx_z[kElRZ], czz_z[kElRZ], mxz[kElRZ], q4[kElRZ], q5[kElRZ], q6[kElRZ], q7[kElRZ],
-      fexx[kElRZ], fezz[kElRZ], fexz[kElRZ], g0[kElRZ], g1[kElRZ], g2[kElRZ];
-  float azi[kElRZ], bzi[kElRZ], azh[kElRZ], bzh[kElRZ];
+  float ovx[kElRZ], ovz[kElRZ], fexx[kElRZ], fezz[kElRZ], fexz[kElRZ], g0[kElRZ], g1[kElRZ],
+      g2[kElRZ], bzi[kElRZ], bzh[kElRZ];
 #pragma unroll
   for (int r = 0; r < kElRZ; ++r) {
     const int jc = min(C.jb + r, NZ - 1);
     const size_t k = (size_t)jc * NX + C.ic;
     ovx[r] = a.vx[so + k];
     ovz[r] = a.vz[so + k];
-    txx[r] = a.txx[so + k];
-    tzz[r] = a.tzz[so + k];
-    txz[r] = a.txz[so + k];
-    cxx_x[r] = a.cxx_x[k];
-    czz_x[r] = a.czz_x[k];
-    cxx_z[r] = a.cxx_z[k];
-    czz_z[r] = a.czz_z[k];
-    mxz[r] = a.mxz[k];
-    azi[r] = a.azi[jc];
     bzi[r] = a.bzi[jc];
-    azh[r] = a.azh[jc];
     bzh[r] = a.bzh[jc];
-    q4[r] = wxi ? a.ps_in[4][so + k] : 0.0f;
-    q5[r] = azi[r] != 0.0f ? a.ps_in[5][so + k] : 0.0f;
-    q6[r] = azh[r] != 0.0f ? a.ps_in[6][so + k] : 0.0f;
-    q7[r] = wxh ? a.ps_in[7][so + k] : 0.0f;
     fexx[r] = a.trc[2][so + k];
     fezz[r] = a.trc[3][so + k];
     fexz[r] = a.trc[4][so + k];
@@ -441,7 +470,6 @@ __global__ __launch_bounds__(256) void el_adj_s_kernel(ElStep a) {
   const Box gbe{sb[0], T.x0, T.z0}, gbf{sb[1], T.x0, T.z0}, gbg{sb[2], T.x0, T.z0},
       gbh{sb[3], T.x0, T.z0};
   const int i = C.i;
-  const float dt = a.dt, ih = a.ih;
 #pragma unroll
   for (int r = 0; r < kElRZ; ++r) {
     const int j = C.jb + r;
@@ -457,24 +485,23 @@ __global__ __launch_bounds__(256) void el_adj_s_kernel(ElStep a) {
     a.vz[so + k] = ovz[r] + (dzf + dxh) * ih;
 
     // own cell: memory-variable adjoints and the coefficient gradients
-    const float ex = dt * fmaf(cxx_x[r], txx[r], czz_x[r] * tzz[r]);
-    const float ez = dt * fmaf(cxx_z[r], txx[r], czz_z[r] * tzz[r]);
-    const float exz = dt * mxz[r] * txz[r];
-    if (axi != 0.0f) a.ps_out[4][so + k] = bxi * (q4[r] + ex);
-    if (azi[r] != 0.0f) a.ps_out[5][so + k] = bzi[r] * (q5[r] + ez);
-    if (azh[r] != 0.0f) a.ps_out[6][so + k] = bzh[r] * (q6[r] + exz);
-    if (axh != 0.0f) a.ps_out[7][so + k] = bxh * (q7[r] + exz);
+    const AdjS& v = ov[r];
+    const float ex = adj_ex(v, dt), ez = adj_ez(v, dt), exz = adj_exz(v, dt);
+    if (v.ax != 0.0f) a.ps_out[4][so + k] = bxi * (v.q4 + ex);
+    if (v.az != 0.0f) a.ps_out[5][so + k] = bzi[r] * (v.q5 + ez);
+    if (v.azh != 0.0f) a.ps_out[6][so + k] = bzh[r] * (v.q6 + exz);
+    if (v.axh != 0.0f) a.ps_out[7][so + k] = bxh * (v.q7 + exz);
     float glam, gmu;
     if (a.fs && j == 0) {
       // txx += dt M exx with M = 4 mu (lambda + mu) / (lambda + 2 mu)
-      const float gM = dt * txx[r] * fexx[r];
+      const float gM = dt * v.txx * fexx[r];
       glam = gM * dml;
       gmu = gM * dmm;
     } else {
-      glam = dt * (txx[r] + tzz[r]) * (fexx[r] + fezz[r]);
-      gmu = 2.0f * dt * fmaf(txx[r], fexx[r], tzz[r] * fezz[r]);
+      glam = dt * (v.txx + v.tzz) * (fexx[r] + fezz[r]);
+      gmu = 2.0f * dt * fmaf(v.txx, fexx[r], v.tzz * fezz[r]);
     }
-    const float gmxz = dt * txz[r] * fexz[r];
+    const float gmxz = dt * v.txz * fexz[r];
     if (a.g_init) {
       a.g[0][so + k] = glam;
       a.g[1][so + k] = gmu;
@@ -512,46 +539,39 @@ __global__ void el_inject_kernel(ElStep a, int n) {
   a.vz[k] = az;
 }
 
-// Stages the derivative-input adjoints of the velocity step: gba (Dx txx of
-// vx), gbb (Dz txz of vx), gbc (Dx txz of vz), gbd (Dz tzz of vz).
-__device__ __forceinline__ void el_stage_adj_v(const ElStep& a, float (*sb)[kElBox], size_t so,
-                                               int x0, int z0) {
-  const int NX = a.NX, NZ = a.NZ;
-  const float dt = a.dt;
-  float vx[kElK], vz[kElK], bx[kElK], bz[kElK], axh[kElK], az[kElK], ax[kElK], azh[kElK],
-      q0[kElK], q1[kElK], q2[kElK], q3[kElK];
-#pragma unroll
-  for (int k = 0; k < kElK; ++k) {
-    const int e = threadIdx.x + k * kThreads;
-    const int r = e / kElBW, c = e - (e / kElBW) * kElBW;
-    const int gx = x0 - 2 + c, gz = z0 - 2 + r;
-    const bool ok = e < kElBox && gx >= 0 && gx < NX && gz >= 0 && gz < NZ;
-    const size_t q = ok ? (size_t)gz * NX + gx : 0;
-    const int cx = ok ? gx : 0, cz = ok ? gz : 0;
-    vx[k] = ldz(a.vx + so, q, ok, a.vx);
-    vz[k] = ldz(a.vz + so, q, ok, a.vz);
-    bx[k] = ldz(a.bx, q, ok, a.bx);
-    bz[k] = ldz(a.bz, q, ok, a.bz);
-    axh[k] = ldz(a.axh, cx, ok, a.axh);
-    az[k] = ldz(a.azi, cz, ok, a.azi);
-    ax[k] = ldz(a.axi, cx, ok, a.axi);
-    azh[k] = ldz(a.azh, cz, ok, a.azh);
-    q0[k] = __any(axh[k] != 0.0f) ? ldz(a.ps_in[0] + so, q, ok, a.ps_in[0]) : 0.0f;
-    q1[k] = __any(az[k] != 0.0f) ? ldz(a.ps_in[1] + so, q, ok, a.ps_in[1]) : 0.0f;
-    q2[k] = __any(ax[k] != 0.0f) ? ldz(a.ps_in[2] + so, q, ok, a.ps_in[2]) : 0.0f;
-    q3[k] = __any(azh[k] != 0.0f) ? ldz(a.ps_in[3] + so, q, ok, a.ps_in[3]) : 0.0f;
-  }
-#pragma unroll
-  for (int k = 0; k < kElK; ++k) {
-    const int e = threadIdx.x + k * kThreads;
-    if (e >= kElBox) break;
-    const float kx = dt * bx[k] * vx[k];
-    const float kz = dt * bz[k] * vz[k];
-    sb[0][e] = axh[k] == 0.0f ? kx : fmaf(axh[k], q0[k] + kx, kx);
-    sb[1][e] = az[k] == 0.0f ? kx : fmaf(az[k], q1[k] + kx, kx);
-    sb[2][e] = ax[k] == 0.0f ? kz : fmaf(ax[k], q2[k] + kz, kz);
-    sb[3][e] = azh[k] == 0.0f ? kz : fmaf(azh[k], q3[k] + kz, kz);
-  }
+// Raw inputs of one box cell of the velocity-adjoint staging (as AdjS).
+struct AdjV {
+  float vx, vz, bx, bz, axh, az, ax, azh, q0, q1, q2, q3;
+};
+__device__ __forceinline__ void adj_v_load(const ElStep& a, size_t so, int e, bool valid, int x0,
+                                           int z0, AdjV& v) {
+  const int r = e / kElBW, c = e - (e / kElBW) * kElBW;
+  const int gx = x0 - 2 + c, gz = z0 - 2 + r;
+  const bool ok = valid && gx >= 0 && gx < a.NX && gz >= 0 && gz < a.NZ;
+  const size_t q = ok ? (size_t)gz * a.NX + gx : 0;
+  const int cx = ok ? gx : 0, cz = ok ? gz : 0;
+  v.vx = ldz(a.vx + so, q, ok, a.vx);
+  v.vz = ldz(a.vz + so, q, ok, a.vz);
+  v.bx = ldz(a.bx, q, ok, a.bx);
+  v.bz = ldz(a.bz, q, ok, a.bz);
+  v.axh = ldz(a.axh, cx, ok, a.axh);
+  v.az = ldz(a.azi, cz, ok, a.azi);
+  v.ax = ldz(a.axi, cx, ok, a.axi);
+  v.azh = ldz(a.azh, cz, ok, a.azh);
+  v.q0 = __any(v.axh != 0.0f) ? ldz(a.ps_in[0] + so, q, ok, a.ps_in[0]) : 0.0f;
+  v.q1 = __any(v.az != 0.0f) ? ldz(a.ps_in[1] + so, q, ok, a.ps_in[1]) : 0.0f;
+  v.q2 = __any(v.ax != 0.0f) ? ldz(a.ps_in[2] + so, q, ok, a.ps_in[2]) : 0.0f;
+  v.q3 = __any(v.azh != 0.0f) ? ldz(a.ps_in[3] + so, q, ok, a.ps_in[3]) : 0.0f;
+}
+// derivative-input adjoints of the velocity step: gba (Dx txx of vx), gbb (Dz
+// txz of vx), gbc (Dx txz of vz), gbd (Dz tzz of vz)
+__device__ __forceinline__ void adj_v_put(float (*sb)[kElBox], int e, float dt, const AdjV& v) {
+  const float kx = dt * v.bx * v.vx;
+  const float kz = dt * v.bz * v.vz;
+  sb[0][e] = v.axh == 0.0f ? kx : fmaf(v.axh, v.q0 + kx, kx);
+  sb[1][e] = v.az == 0.0f ? kx : fmaf(v.az, v.q1 + kx, kx);
+  sb[2][e] = v.ax == 0.0f ? kz : fmaf(v.ax, v.q2 + kz, kz);
+  sb[3][e] = v.azh == 0.0f ? kz : fmaf(v.azh, v.q3 + kz, kz);
 }
 
 __global__ __launch_bounds__(256) void el_adj_v_kernel(ElStep a) {
@@ -560,14 +580,27 @@ __global__ __launch_bounds__(256) void el_adj_v_kernel(ElStep a) {
   const int NX = a.NX, NZ = a.NZ;
   const size_t plane = (size_t)NX * NZ;
   const size_t so = (size_t)T.shot * plane;
-  el_stage_adj_v(a, sb, so, T.x0, T.z0);
+  const float dt = a.dt, ih = a.ih;
+  AdjV hv[kElKH], ov[kElRZ];
+#pragma unroll
+  for (int k = 0; k < kElKH; ++k) {
+    const int h = (int)threadIdx.x + k * kThreads;
+    adj_v_load(a, so, h < kElHalo ? el_halo_cell(h) : 0, h < kElHalo, T.x0, T.z0, hv[k]);
+  }
+#pragma unroll
+  for (int r = 0; r < kElRZ; ++r) adj_v_load(a, so, el_own_cell(r), true, T.x0, T.z0, ov[r]);
+#pragma unroll
+  for (int k = 0; k < kElKH; ++k) {
+    const int h = (int)threadIdx.x + k * kThreads;
+    if (h < kElHalo) adj_v_put(sb, el_halo_cell(h), dt, hv[k]);
+  }
+#pragma unroll
+  for (int r = 0; r < kElRZ; ++r) adj_v_put(sb, el_own_cell(r), dt, ov[r]);
   const ElCells C(T, NX);
-  const float axh = a.axh[C.ic], bxh = a.bxh[C.ic], axi = a.axi[C.ic], bxi = a.bxi[C.ic];
-  const bool wxh = __any(axh != 0.0f), wxi = __any(axi != 0.0f);
+  const float bxh = a.bxh[C.ic], bxi = a.bxi[C.ic];
   const bool gacc = !a.g_init;
-  float otxx[kElRZ], otzz[kElRZ], otxz[kElRZ], vx[kElRZ], vz[kElRZ], bx[kElRZ], bz[kElRZ],
-      q0[kElRZ], q1[kElRZ], q2[kElRZ], q3[kElRZ], f0[kElRZ], f1[kElRZ], g3[kElRZ], g4[kElRZ];
-  float azi[kElRZ], bzi[kElRZ], azh[kElRZ], bzh[kElRZ];
+  float otxx[kElRZ], otzz[kElRZ], otxz[kElRZ], f0[kElRZ], f1[kElRZ], g3[kElRZ], g4[kElRZ],
+      bzi[kElRZ], bzh[kElRZ];
 #pragma unroll
   for (int r = 0; r < kElRZ; ++r) {
     const int jc = min(C.jb + r, NZ - 1);
@@ -575,18 +608,8 @@ __global__ __launch_bounds__(256) void el_adj_v_kernel(ElStep a) {
     otxx[r] = a.txx[so + k];
     otzz[r] = a.tzz[so + k];
     otxz[r] = a.txz[so + k];
-    vx[r] = a.vx[so + k];
-    vz[r] = a.vz[so + k];
-    bx[r] = a.bx[k];
-    bz[r] = a.bz[k];
-    azi[r] = a.azi[jc];
     bzi[r] = a.bzi[jc];
-    azh[r] = a.azh[jc];
     bzh[r] = a.bzh[jc];
-    q0[r] = wxh ? a.ps_in[0][so + k] : 0.0f;
-    q1[r] = azi[r] != 0.0f ? a.ps_in[1][so + k] : 0.0f;
-    q2[r] = wxi ? a.ps_in[2][so + k] : 0.0f;
-    q3[r] = azh[r] != 0.0f ? a.ps_in[3][so + k] : 0.0f;
     f0[r] = a.trc[0][so + k];
     f1[r] = a.trc[1][so + k];
     g3[r] = gacc ? a.g[3][so + k] : 0.0f;
@@ -596,7 +619,6 @@ __global__ __launch_bounds__(256) void el_adj_v_kernel(ElStep a) {
   const Box gba{sb[0], T.x0, T.z0}, gbb{sb[1], T.x0, T.z0}, gbc{sb[2], T.x0, T.z0},
       gbd{sb[3], T.x0, T.z0};
   const int i = C.i;
-  const float dt = a.dt, ih = a.ih;
 #pragma unroll
   for (int r = 0; r < kElRZ; ++r) {
     const int j = C.jb + r;
@@ -613,13 +635,14 @@ __global__ __launch_bounds__(256) void el_adj_v_kernel(ElStep a) {
     a.txz[so + k] = otxz[r] + (dzb + dxc) * ih;
     a.tzz[so + k] = otzz[r] + dzd * ih;
 
-    const float kx = dt * bx[r] * vx[r], kz = dt * bz[r] * vz[r];
-    if (axh != 0.0f) a.ps_out[0][so + k] = bxh * (q0[r] + kx);
-    if (azi[r] != 0.0f) a.ps_out[1][so + k] = bzi[r] * (q1[r] + kx);
-    if (axi != 0.0f) a.ps_out[2][so + k] = bxi * (q2[r] + kz);
-    if (azh[r] != 0.0f) a.ps_out[3][so + k] = bzh[r] * (q3[r] + kz);
-    const float gbx = dt * vx[r] * f0[r];
-    const float gbz = dt * vz[r] * f1[r];
+    const AdjV& v = ov[r];
+    const float kx = dt * v.bx * v.vx, kz = dt * v.bz * v.vz;
+    if (v.axh != 0.0f) a.ps_out[0][so + k] = bxh * (v.q0 + kx);
+    if (v.az != 0.0f) a.ps_out[1][so + k] = bzi[r] * (v.q1 + kx);
+    if (v.ax != 0.0f) a.ps_out[2][so + k] = bxi * (v.q2 + kz);
+    if (v.azh != 0.0f) a.ps_out[3][so + k] = bzh[r] * (v.q3 + kz);
+    const float gbx = dt * v.vx * f0[r];
+    const float gbz = dt * v.vz * f1[r];
     if (a.g_init) {
       a.g[3][so + k] = gbx;
       a.g[4][so + k] = gbz;

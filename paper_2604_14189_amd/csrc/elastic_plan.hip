@@ -178,8 +178,6 @@ ElStep step_base(const sweep_plan* p, void* work, const ElLayout& L, const ElCoe
   a.mxz = c.mxz;
   a.cxx_x = c.cxx_x;
   a.cxx_z = c.cxx_z;
-  a.czz_x = c.czz_x;
-  a.czz_z = c.czz_z;
   a.smask = c.smask;
   a.dM_dl = c.dM_dl;
   a.dM_dm = c.dM_dm;
