@@ -162,10 +162,14 @@ int sweep_plan_get_tuning(const sweep_plan* plan, sweep_tuning* t);
 /* Autotuner: runs `steps` forward steps of this plan for every supported tile
  * choice (rz and pml_rz in 1, 2, 4, 8 with pml_rz <= rz) and time-blocking
  * depth (tblock 1 or 2; 2 only where the tiling has deep tiles), keeps the
- * fastest and stores it in the plan; `cache_path` (may be NULL) is a text file
- * of previous results, one line
- * "arch physics NX NZ nshots rz pml_rz tblock us_per_step", keyed by
- * (GPU arch, physics, NX, NZ, nshots), read first and appended to. Synchronises `stream`. d_work needs the forward-only
+ * fastest and stores it in the plan; `cache_path` (may be NULL) is a file of
+ * previous results, one JSON object per line:
+ *   {"arch":"gfx950","physics":"acoustic","mode":"plan-forward",
+ *    "shapes":"NXxNZxNSHOTSxPML","rz":8,"pml_rz":4,"tblock":2,"us_per_step":...}
+ * keyed by everything up to and including "shapes" (GPU arch, physics, mode,
+ * padded NX and NZ, nshots, pad width), read first and appended to. Elastic,
+ * variable-density and VTI plans have no choice to make and return at once.
+ * Synchronises `stream`. d_work needs the forward-only
  * workspace. Results never depend on the choice (bitwise). *chosen_rz (may be
  * NULL) receives the selected value. */
 int sweep_plan_autotune(sweep_plan* plan, const float* d_model, const float* d_wavelet,
@@ -312,10 +316,10 @@ int sweep_batch_backward(sweep_batch* batch, const float* const* d_resids, float
  * checkpoints) and, with for_backward = 1, the recomputation and reversal of
  * the first `steps` steps too (at most one checkpoint segment, no residual),
  * which is the step mix of a gradient; it sets the fastest on every plan of
- * the batch. `cache_path` (may be NULL) is a text file of previous results,
- * one line "arch batch[-gradient] NXxNZxNSHOTS ... rz pml_rz tblock
- * us_per_step" keyed by the arch, the mode and all plans' shapes, read first
- * and appended to. Synchronises `stream`; d_work needs the batch's workspace
+ * the batch. `cache_path` (may be NULL) is the JSON-lines file of
+ * sweep_plan_autotune, with "mode" batch-forward or batch-gradient and
+ * "shapes" every plan's NXxNZxNSHOTSxPML (space-separated, in batch order),
+ * read first and appended to. Synchronises `stream`; d_work needs the batch's workspace
  * for_backward. Results never depend on the choice (bitwise); the fields of the
  * workspace hold no result afterwards. chosen (3 ints: rz, pml_rz, tblock; may
  * be NULL) receives it. */

@@ -3,6 +3,7 @@
 // recomputation and the reverse sweep on the caller's stream.
 #include <algorithm>
 #include <cstdio>
+#include <cstdlib>
 #include <climits>
 #include <fstream>
 #include <sstream>
@@ -1572,25 +1573,75 @@ extern "C" int sweep_batch_backward(sweep_batch* b, const float* const* d_resids
 SWEEP_ABI_CATCH("sweep_batch_backward")
 
 // ----------------------------------------------------------------- autotuner
-// Times `steps` forward steps of the plan for every supported (rz, pml_rz) pair
-// and keeps the fastest; results are cached in a text file, one line
-// "arch physics NX NZ nshots rz pml_rz microseconds_per_step".
+// Times every supported (rz, pml_rz, tblock) and keeps the fastest. Results
+// are cached as JSON lines, one object per search:
+//   {"arch":"gfx950","physics":"acoustic","mode":"plan-forward","shapes":"NXxNZxNSHOTSxP",
+//    "rz":8,"pml_rz":4,"tblock":2,"us_per_step":123.4}
+// "shapes" lists every plan of a batch (space-separated) and "mode" is
+// plan-forward, batch-forward or batch-gradient. A search whose fields up to
+// "shapes" match a line takes that line's choice.
 namespace {
 
-std::string tune_key(const sweep_plan* p) {
+std::string tune_arch(const sweep_plan* p) {
+  if (!p->arch.empty()) return p->arch;
   int dev = 0;
   hipDeviceProp_t prop;
-  std::string arch = p->arch.empty() ? "unknown" : p->arch;
-  if (p->arch.empty() && hipGetDevice(&dev) == hipSuccess &&
-      hipGetDeviceProperties(&prop, dev) == hipSuccess)
-    arch = std::string(prop.gcnArchName).substr(0, std::string(prop.gcnArchName).find(':'));
-  std::ostringstream os;
-  os << arch << " " << (p->pb.physics == SWEEP_ACOUSTIC ? "acoustic" : "other") << " " << p->NX
-     << " " << p->NZ << " " << p->pb.nshots;
-  return os.str();
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+    return std::string(prop.gcnArchName).substr(0, std::string(prop.gcnArchName).find(':'));
+  return "unknown";
+}
+
+std::string tune_shape(const sweep_plan* p) {
+  return std::to_string(p->NX) + "x" + std::to_string(p->NZ) + "x" +
+         std::to_string(p->pb.nshots) + "x" + std::to_string(p->pb.pml);
+}
+
+// the cache line up to (and with) "shapes"; the tiling choices follow it
+std::string tune_key(const sweep_plan* p0, const char* mode, const std::string& shapes) {
+  return "{\"arch\":\"" + tune_arch(p0) + "\",\"physics\":\"acoustic\",\"mode\":\"" + mode +
+         "\",\"shapes\":\"" + shapes + "\",";
+}
+
+// integer field "name": of one cache line (false when absent or malformed)
+bool json_int(const std::string& line, const char* name, int& v) {
+  const std::string k = std::string("\"") + name + "\":";
+  const size_t at = line.find(k);
+  if (at == std::string::npos) return false;
+  char* end = nullptr;
+  const char* b = line.c_str() + at + k.size();
+  const long x = std::strtol(b, &end, 10);
+  if (end == b) return false;
+  v = (int)x;
+  return true;
 }
 
 bool rz_ok(int v) { return v == 1 || v == 2 || v == 4 || v == 8; }
+
+// the cached choice for `key`, if a well-formed line holds one
+bool tune_lookup(const char* path, const std::string& key, int& rz, int& prz, int& tb) {
+  if (!path || !*path) return false;
+  std::ifstream in(path);
+  std::string line;
+  while (std::getline(in, line)) {
+    if (line.compare(0, key.size(), key) != 0) continue;
+    const std::string rest = line.substr(key.size());
+    if (json_int(rest, "rz", rz) && json_int(rest, "pml_rz", prz) &&
+        json_int(rest, "tblock", tb) && rz_ok(rz) && rz_ok(prz) && prz <= rz &&
+        (tb == 1 || tb == 2))
+      return true;
+  }
+  return false;
+}
+
+void tune_store(const char* path, const std::string& key, int rz, int prz, int tb, double us) {
+  if (!path || !*path) return;
+  std::ofstream out(path, std::ios::app);
+  std::ostringstream os;
+  os.precision(6);
+  os << key << "\"rz\":" << rz << ",\"pml_rz\":" << prz << ",\"tblock\":" << tb
+     << ",\"us_per_step\":" << us << "}\n";
+  out << os.str();
+}
 
 }  // namespace
 
@@ -1611,28 +1662,18 @@ extern "C" int sweep_plan_autotune(sweep_plan* p, const float* d_model, const fl
     return SWEEP_OK;
   }
   hipStream_t s = (hipStream_t)stream;
-  const std::string key = tune_key(p);
-  if (cache_path && *cache_path) {
-    std::ifstream in(cache_path);
-    std::string line;
-    while (std::getline(in, line)) {
-      if (line.compare(0, key.size(), key) != 0 || line.size() <= key.size() ||
-          line[key.size()] != ' ')
-        continue;
-      std::istringstream is(line.substr(key.size()));
-      int rz = 0, prz = 0, tb = 0;
-      double us = 0;
-      if (is >> rz >> prz >> tb >> us && rz_ok(rz) && rz_ok(prz) && prz <= rz &&
-          (tb == 1 || tb == 2)) {
-        sweep_tuning t = p->tune;
-        t.rz = rz;
-        t.pml_rz = prz;
-        t.tblock = tb;
-        const int rc = sweep_plan_set_tuning(p, &t);
-        if (rc) return rc;
-        if (chosen_rz) *chosen_rz = rz;
-        return SWEEP_OK;
-      }
+  const std::string key = tune_key(p, "plan-forward", tune_shape(p));
+  {
+    int rz = 0, prz = 0, tb = 0;
+    if (tune_lookup(cache_path, key, rz, prz, tb)) {
+      sweep_tuning t = p->tune;
+      t.rz = rz;
+      t.pml_rz = prz;
+      t.tblock = tb;
+      const int rc = sweep_plan_set_tuning(p, &t);
+      if (rc) return rc;
+      if (chosen_rz) *chosen_rz = rz;
+      return SWEEP_OK;
     }
   }
   AcLayout L;
@@ -1702,10 +1743,7 @@ extern "C" int sweep_plan_autotune(sweep_plan* p, const float* d_model, const fl
   t.pml_rz = best_p;
   t.tblock = best_t;
   if ((rc = sweep_plan_set_tuning(p, &t))) return rc;
-  if (cache_path && *cache_path) {
-    std::ofstream out(cache_path, std::ios::app);
-    out << key << " " << best << " " << best_p << " " << best_t << " " << best_us << "\n";
-  }
+  tune_store(cache_path, key, best, best_p, best_t, best_us);
   if (chosen_rz) *chosen_rz = best;
   return SWEEP_OK;
 }
@@ -1731,11 +1769,10 @@ extern "C" int sweep_batch_autotune(sweep_batch* b, const float* const* d_models
     set_error("cannot make the batch's device current");
     return SWEEP_EHIP;
   }
-  std::string key = tune_key(b->plans[0]);
-  key = key.substr(0, key.find(' ')) + (for_backward ? " batch-gradient" : " batch");
-  for (sweep_plan* p : b->plans)
-    key += " " + std::to_string(p->NX) + "x" + std::to_string(p->NZ) + "x" +
-           std::to_string(p->pb.nshots);
+  std::string shapes;
+  for (sweep_plan* p : b->plans) shapes += (shapes.empty() ? "" : " ") + tune_shape(p);
+  const std::string key =
+      tune_key(b->plans[0], for_backward ? "batch-gradient" : "batch-forward", shapes);
   auto apply = [&](int rz, int prz, int tb) {
     for (sweep_plan* p : b->plans) {
       sweep_tuning t = p->tune;
@@ -1757,20 +1794,9 @@ extern "C" int sweep_batch_autotune(sweep_batch* b, const float* const* d_models
     }
     return SWEEP_OK;
   };
-  if (cache_path && *cache_path) {
-    std::ifstream in(cache_path);
-    std::string line;
-    while (std::getline(in, line)) {
-      if (line.compare(0, key.size(), key) != 0 || line.size() <= key.size() ||
-          line[key.size()] != ' ')
-        continue;
-      std::istringstream is(line.substr(key.size()));
-      int rz = 0, prz = 0, tb = 0;
-      double us = 0;
-      if (is >> rz >> prz >> tb >> us && rz_ok(rz) && rz_ok(prz) && prz <= rz &&
-          (tb == 1 || tb == 2))
-        return apply(rz, prz, tb);
-    }
+  {
+    int rz = 0, prz = 0, tb = 0;
+    if (tune_lookup(cache_path, key, rz, prz, tb)) return apply(rz, prz, tb);
   }
   std::vector<AcLayout> L;
   std::vector<size_t> off;
@@ -1853,11 +1879,7 @@ extern "C" int sweep_batch_autotune(sweep_batch* b, const float* const* d_models
     return rc;
   }
   if ((rc = apply(best[0], best[1], best[2]))) return rc;
-  if (cache_path && *cache_path) {
-    std::ofstream out(cache_path, std::ios::app);
-    out << key << " " << best[0] << " " << best[1] << " " << best[2] << " "
-        << 1e3 * best_us / steps << "\n";
-  }
+  tune_store(cache_path, key, best[0], best[1], best[2], 1e3 * best_us / steps);
   return SWEEP_OK;
 }
 SWEEP_ABI_CATCH("sweep_batch_autotune")

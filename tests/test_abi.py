@@ -194,3 +194,35 @@ def test_context_outside_device_range_is_an_error(lib):
     rc = sw.lib().sweep_ctx_create(ctypes.byref(h), 1 << 20)
     assert rc in (sw._lib.EINVAL, sw._lib.EHIP) and not h.value
     assert sw.lib().sweep_last_error()
+
+
+def test_autotune_cache_lines_are_json(lib, tmp_path):
+    """A cached search (one JSON object per line) is taken without timing
+    anything: the plan gets the line's choice; lines of other shapes, modes
+    or malformed fields are skipped (host-side: no device call is made)."""
+    import json
+    import torch
+    import paper_2604_14189_amd as sw
+    from tests.helpers import random_case
+    c = random_case(5, nx=140, nz=90, nt=30, nshots=2, nrec=3)
+    p = c.plan()
+    NX, NZ = p.padded()
+    arch = (torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+            if torch.cuda.is_available() else "unknown")
+    key = {"arch": arch, "physics": "acoustic", "mode": "plan-forward",
+           "shapes": f"{NX}x{NZ}x{c.nshots}x{c.pml}"}
+    lines = [dict(key, shapes=f"{NX}x{NZ}x{c.nshots}x{c.pml + 1}", rz=1, pml_rz=1, tblock=1),
+             dict(key, mode="batch-forward", rz=1, pml_rz=1, tblock=1),
+             dict(key, rz=3, pml_rz=1, tblock=1),
+             dict(key, rz=2, pml_rz=2, tblock=1, us_per_step=12.5),
+             dict(key, rz=4, pml_rz=4, tblock=2, us_per_step=10.0)]
+    path = tmp_path / "tune.jsonl"
+    path.write_text("".join(json.dumps(x, separators=(",", ":")) + "\n" for x in lines))
+    L = sw.lib()
+    fake = ctypes.c_void_p(256)
+    rz = ctypes.c_int()
+    rc = L.sweep_plan_autotune(p._h, fake, fake, fake, 1 << 40, 5, str(path).encode(), None,
+                               ctypes.byref(rz))
+    assert rc == 0, L.sweep_last_error()
+    assert rz.value == 2
+    assert (p.tuning["rz"], p.tuning["pml_rz"], p.tuning["tblock"]) == (2, 2, 1)

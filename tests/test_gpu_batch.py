@@ -6,6 +6,7 @@ bit-identical gathers and gradients to each plan run alone. Captured graphs are
 replayed several times with eager work in between and every replay is checked
 against the eager result.
 """
+import json
 import os
 
 import numpy as np
@@ -133,7 +134,7 @@ def test_batch_autotune_picks_and_caches(sw, tmp_path):
              random_case(62, nx=120, nz=90, nt=30, nshots=2, nrec=4, ckpt=50)]
     plans = [c.plan() for c in cases]
     batch = sw.Batch(plans)
-    cache = str(tmp_path / "btune.txt")
+    cache = str(tmp_path / "btune.jsonl")
     vs, ws = [_dev(c.v) for c in cases], [_dev(c.wav) for c in cases]
     t = batch.autotune(vs, ws, steps=6, cache_path=cache)
     assert t["rz"] in (1, 2, 4, 8) and t["pml_rz"] <= t["rz"] and t["tblock"] in (1, 2)
@@ -142,8 +143,13 @@ def test_batch_autotune_picks_and_caches(sw, tmp_path):
         assert (tp["rz"], tp["pml_rz"], tp["tblock"]) == (t["rz"], t["pml_rz"], t["tblock"])
     with open(cache) as f:
         lines = f.read().strip().splitlines()
-    assert len(lines) == 1 and " batch-gradient " in lines[0]
-    assert lines[0].split()[-4:-1] == [str(t["rz"]), str(t["pml_rz"]), str(t["tblock"])]
+    assert len(lines) == 1
+    rec = json.loads(lines[0])
+    assert rec["mode"] == "batch-gradient" and rec["physics"] == "acoustic"
+    assert rec["shapes"] == " ".join(f"{p.padded()[0]}x{p.padded()[1]}x{c.nshots}x{c.pml}"
+                                     for p, c in zip(plans, cases))
+    assert (rec["rz"], rec["pml_rz"], rec["tblock"]) == (t["rz"], t["pml_rz"], t["tblock"])
+    assert rec["us_per_step"] > 0
     assert sw.Batch([c.plan() for c in cases]).autotune(vs, ws, steps=6, cache_path=cache) == t
     resids = _resids(cases)
     ds = batch.forward(vs, ws, save=True)
@@ -179,15 +185,18 @@ def test_plan_graph_replays_match_eager(sw):
 def test_autotune_picks_a_tiling_and_caches(sw, tmp_path):
     c = random_case(41, nx=300, nz=180, nt=60, nshots=4)
     plan = c.plan()
-    cache = str(tmp_path / "tune.txt")
+    cache = str(tmp_path / "tune.jsonl")
     rz = plan.autotune(_dev(c.v), _dev(c.wav), steps=10, cache_path=cache)
     assert rz in (1, 2, 4, 8)
     assert plan.tuning["rz"] == rz
     with open(cache) as f:
         lines = f.read().strip().splitlines()
-    f = lines[0].split() if len(lines) == 1 else []
-    assert f and f[-4] == str(rz) and f[-3] == str(plan.tuning["pml_rz"])
-    assert f[-2] == str(plan.tuning["tblock"]) and f[-2] in ("1", "2")
+    assert len(lines) == 1
+    rec = json.loads(lines[0])
+    NX, NZ = plan.padded()
+    assert rec["mode"] == "plan-forward" and rec["shapes"] == f"{NX}x{NZ}x{c.nshots}x{c.pml}"
+    assert rec["rz"] == rz and rec["pml_rz"] == plan.tuning["pml_rz"]
+    assert rec["tblock"] == plan.tuning["tblock"] and rec["tblock"] in (1, 2)
     assert plan.tuning["pml_rz"] <= rz
     d1 = plan.forward(_dev(c.v), _dev(c.wav)).clone()
     plan2 = c.plan()
