@@ -75,8 +75,12 @@ __device__ __forceinline__ void vti_record(const VtiStep& a, int shot, int tile,
 
 __global__ __launch_bounds__(kThreads) void vti_fwd_kernel(VtiStep a) {
   __shared__ float sP[PH * PW];    // P^n, 8-cell halo
-  __shared__ double sG[GH * GW];   // G^n (float64), 4-cell halo
-  __shared__ double sT[kTZ * GW];  // D2z' G^n on the tile rows, 4-column ring
+  // G^n (float64, 4-cell halo); once each lane holds its cells' G^n and its
+  // share of D2z' G^n (tile rows, 4-column ring) in registers, the same
+  // memory holds that D2z' G^n
+  __shared__ double sG[GH * GW];
+  double* sT = sG;
+  static_assert(kTZ * GW <= GH * GW, "D2z' G box fits in the G box");
   __shared__ float sX[kTZ * GW];  // psi_x^n on the tile rows, 4-column ring
   __shared__ float sZ[GH * kTX];  // psi_z^n on the tile columns, 4-row ring
   const int f = xcd_spread(blockIdx.x, gridDim.x);
@@ -140,9 +144,20 @@ __global__ __launch_bounds__(kThreads) void vti_fwd_kernel(VtiStep a) {
       sZ[e] = psi;
     }
   }
-  for (int e = tid; e < kTZ * GW; e += kThreads) {
-    const int r = e / GW, c = e - r * GW;
-    sT[e] = d2d(&sG[(r + 4) * GW + c], GW);
+  constexpr int KT = (kTZ * GW + kThreads - 1) / kThreads;
+  double tz[KT], g0[kRZ];
+#pragma unroll
+  for (int k = 0; k < KT; ++k) {
+    const int e = tid + k * kThreads, r = e / GW, c = e - r * GW;
+    tz[k] = e < kTZ * GW ? d2d(&sG[(r + 4) * GW + c], GW) : 0.0;
+  }
+#pragma unroll
+  for (int rr = 0; rr < kRZ; ++rr) g0[rr] = sG[(zb + rr + 4) * GW + lx + 4];
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < KT; ++k) {
+    const int e = tid + k * kThreads;
+    if (e < kTZ * GW) sT[e] = tz[k];
   }
   __syncthreads();
 
@@ -177,8 +192,7 @@ __global__ __launch_bounds__(kThreads) void vti_fwd_kernel(VtiStep a) {
     pn = fmaf(ccz[rr], bzv, pn);
     pn = fmaf(-ccm[rr], m, pn);
     if (ok && (int)idx == src) pn += sw;
-    const double g0 = sG[(r + 4) * GW + lx + 4];
-    const double gn = (2.0 * g0 - gold[rr]) + (double)p0;
+    const double gn = (2.0 * g0[rr] - gold[rr]) + (double)p0;
     out[rr] = pn;
     if (ok) {
       st_nt(a.prev + base + idx, pn);
