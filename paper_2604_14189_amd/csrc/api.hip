@@ -723,10 +723,10 @@ int ac_forward(sweep_plan* p, const float* model, const float* wavelet, float* g
 }
 
 // Born (tangent-linear) modelling, Eq. 16. The background field p and the
-// perturbation dp advance step by step: the background step (single steps
-// over every tile set) stores B'^n in one plane per shot, and the
-// perturbation step, the same recurrence with no source, adds dCs B'^n at
-// every cell and records dp^{n+1} at the receivers. The perturbation state
+// perturbation dp advance together: the background (two-step passes over the
+// deep tiles, as in the forward) stores B'^n in one plane per shot and step,
+// and the perturbation step, the same recurrence with no source, adds dCs B'^n
+// at every cell and records dp^{n+1} at the receivers. The perturbation state
 // lives in the adjoint half of the workspace (its four time-level buffers
 // and two memory-variable sets), B'^n in the first slot of the segment
 // buffer and dCs in the first plane of the gradient partial.
@@ -751,9 +751,9 @@ int ac_born(sweep_plan* p, const float* model, const float* dmodel, const float*
   if ((rc = launch_fill(daux[0], L.aux_elems, 0.0f, s))) return rc;
   if ((rc = launch_fill(daux[1], L.aux_elems, 0.0f, s))) return rc;
   const int rz = p->tune.rz, prz = p->tune.pml_rz;
-  for (int n = 0; n < pb.nt; ++n) {
+  // perturbation step n with the background's B'^n in B
+  auto dstep = [&](int n, const float* B) {
     const int par = n % 2;
-    if ((rc = ac_fwd_one(p, work, L, n, par, nullptr, Bn, s, -1, -1, -1))) return rc;
     const int o = br.free_buf(0);
     AcStep d = ac_base(p, work, L);
     d.wavelet = at<float>(work, L.wav);
@@ -765,10 +765,28 @@ int ac_born(sweep_plan* p, const float* model, const float* dmodel, const float*
     d.next = at<float>(work, L.lf[o]);
     set_aux(d, aux_ptrs(daux[par], L, ns), aux_ptrs(daux[1 - par], L, ns));
     d.bdC = dCs;
-    d.bB = Bn;
-    if ((rc = ac_launch_born(d, rz, prz, s))) return rc;
+    d.bB = B;
+    const int r = ac_launch_born(d, rz, prz, s);
     br.prev = br.cur;
     br.cur = o;
+    return r;
+  };
+  // the background takes the plan's two-step passes where it has deep tiles
+  // (B'^n and B'^{n+1} in the first two slots of the segment buffer, which
+  // holds ckpt >= 2 of them); the perturbation takes single steps
+  const bool two = ac_two_steps(p) && p->ckpt >= 2;
+  float* Bn2 = Bn + ns * L.plane;
+  for (int n = 0; n < pb.nt;) {
+    if (two && n + 1 < pb.nt) {
+      if ((rc = ac_fwd_two(p, work, L, n, n % 2, nullptr, Bn, Bn2, s, false))) return rc;
+      if ((rc = dstep(n, Bn))) return rc;
+      if ((rc = dstep(n + 1, Bn2))) return rc;
+      n += 2;
+    } else {
+      if ((rc = ac_fwd_one(p, work, L, n, n % 2, nullptr, Bn, s, -1, -1, -1))) return rc;
+      if ((rc = dstep(n, Bn))) return rc;
+      n += 1;
+    }
   }
   p->saved = false;
   return SWEEP_OK;

@@ -90,6 +90,23 @@ def test_born_tilings_bitwise(sw, rz, prz):
     assert torch.equal(p.born(v, dv, w), ref)
 
 
+def test_born_two_step_background_bitwise(sw):
+    """Where the plan has deep tiles, the background field takes two-step
+    passes (tblock 2) and the perturbation single steps; the Born gathers
+    equal those with single background steps (tblock 1) bit for bit."""
+    w = synth.batched_workloads()[1]  # 400 x 200, receivers and sources at depth 5
+    case = case_from_workload(w, shots=[0, 7], nt=121)
+    v, wv = _dev(case.v), _dev(case.wav)
+    dv = _dev(_dv(case.nz, case.nx, 9))
+    p2 = case.plan()
+    assert p2.tiles()["deep"] > 0
+    d2 = p2.born(v, dv, wv).clone()
+    p1 = case.plan()
+    p1.set_tuning(tblock=1)
+    assert torch.equal(p1.born(v, dv, wv), d2)
+    assert torch.any(d2 != 0)
+
+
 def test_born_linear_and_zero(sw):
     """A zero perturbation gives exactly zero gathers; doubling dv doubles them
     (every operation of the perturbation recurrence scales exactly by 2 except
