@@ -747,7 +747,9 @@ def main():
     ap.add_argument("--per-shot-sample", type=int, default=4,
                     help="shots timed through the per-shot path (0: skip)")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the Born, batched-uneven, elastic and MLP measurements")
+                    help="skip every measurement beside the headline gradient (the "
+                         "checkpoint-recompute figure, 256 shots, Born, encoded, batched, "
+                         "elastic, variable density, VTI, MLP)")
     ap.add_argument("--only", choices=["born", "encoded", "batched_uneven", "elastic",
                                        "acoustic_vd", "mlp", "vti", "shots256"],
                     help="run one of the extra measurements alone (profiling) and print it")
@@ -851,7 +853,7 @@ def main():
 
     # the same gradient with every checkpoint segment recomputed (no stored B'^n)
     recompute = None
-    if not args.nt:
+    if not args.nt and not args.no_extras:
         plan.release_workspace()
         torch.cuda.empty_cache()
         plan.set_tuning(keep_b=0)

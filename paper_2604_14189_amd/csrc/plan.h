@@ -93,6 +93,7 @@ namespace sweep {
 struct VtiLayout {
   size_t plane, xs, zs, aux_elems;
   size_t ax, bx, az, bz, pad, cx, cz, cm, wav, src_cell, rec_cell, rec_off, rec_ent;
+  size_t tl;  // tile list: the interior tiles, then the others (ntiles ints)
   size_t pf[2], gf[2], aux[2];
   size_t fwd_end;
   int nseg;
@@ -160,6 +161,10 @@ struct sweep_plan {
   float tt_w[4][4][8];
   std::vector<int> rec_off;
   std::vector<int2> rec_ent;
+  // VTI: the 64 x 16 tiles with no C-PML strip within 4 cells, then the
+  // others, and how many of the first kind (set by each forward)
+  std::vector<int> vti_tl;
+  int vti_nint = 0;
   // state of the last forward
   bool saved = false;
   const void* saved_work = nullptr;

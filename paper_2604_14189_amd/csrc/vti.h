@@ -24,6 +24,10 @@ constexpr int kVtiTZ = 16;
 
 struct VtiStep {
   int NX, NZ, P, nt, nrec, nshots, n, tiles_x, ntiles;
+  // tiles [0, n_int) of tl have no C-PML strip within 4 cells and take the
+  // interior kernels; tiles [n_int, n_int + n_pml) take the general ones
+  const int* tl;
+  int n_int, n_pml;
   float w;  // (dt/h)^2, source scale
   const float* cx;
   const float* cz;
@@ -63,6 +67,10 @@ struct VtiStep {
   float* g;              // adjoint: [3][nshots][NZ][NX] partials for cx, cz, cm
   int g_init;            // 1: g = ..., 0: g += ...
 };
+
+// interior (no C-PML strip within 4 cells of the 64 x 16 tile) or not, as the
+// kernels test it
+bool vti_near_strip(int x0, int z0, int NX, int NZ, int P);
 
 int vti_launch_prep(const float* model, float* pad, float* cx, float* cz, float* cm, int nx,
                     int nz, int P, double h, double dt, hipStream_t s);

@@ -84,7 +84,7 @@ __global__ __launch_bounds__(kThreads) void vti_fwd_kernel(VtiStep a) {
   __shared__ float sX[kTZ * GW];  // psi_x^n on the tile rows, 4-column ring
   __shared__ float sZ[GH * kTX];  // psi_z^n on the tile columns, 4-row ring
   const int f = xcd_spread(blockIdx.x, gridDim.x);
-  const int shot = f / a.ntiles, tile = f - shot * a.ntiles;
+  const int shot = f / a.n_pml, tile = a.tl[a.n_int + f - shot * a.n_pml];
   const int NX = a.NX, NZ = a.NZ, P = a.P, P2 = 2 * a.P;
   const size_t plane = (size_t)NX * NZ, base = (size_t)shot * plane;
   const int x0 = (tile % a.tiles_x) * kTX, z0 = (tile / a.tiles_x) * kTZ;
@@ -235,7 +235,7 @@ __global__ __launch_bounds__(kThreads) void vti_adj_kernel(VtiStep a) {
   __shared__ float sTx[kTZ * GW];  // T_x on the tile rows, 4-column ring
   __shared__ float sTz[GH * kTX];  // T_z on the tile columns, 4-row ring
   const int f = xcd_spread(blockIdx.x, gridDim.x);
-  const int shot = f / a.ntiles, tile = f - shot * a.ntiles;
+  const int shot = f / a.n_pml, tile = a.tl[a.n_int + f - shot * a.n_pml];
   const int NX = a.NX, NZ = a.NZ, P = a.P, P2 = 2 * a.P;
   const size_t plane = (size_t)NX * NZ, base = (size_t)shot * plane;
   const int x0 = (tile % a.tiles_x) * kTX, z0 = (tile / a.tiles_x) * kTZ;
@@ -429,6 +429,223 @@ __global__ __launch_bounds__(kThreads) void vti_adj_kernel(VtiStep a) {
   }
 }
 
+// Interior tiles: no C-PML strip within 4 cells, so every memory-variable
+// term of the general kernels is an exact zero there and the rings that carry
+// them are not needed. The same operations on the same values (so the same
+// bits), with P^n staged with a 4-cell halo: about half the LDS of the
+// general kernels and fewer registers, for more work-groups per CU.
+__global__ __launch_bounds__(kThreads) void vti_fwd_int_kernel(VtiStep a) {
+  __shared__ float sP[GH * GW];   // P^n, 4-cell halo
+  // G^n (float64, 4-cell halo), then D2z' G^n (tile rows, 4-column ring)
+  __shared__ double sG[GH * GW];
+  double* sT = sG;
+  const int f = xcd_spread(blockIdx.x, gridDim.x);
+  const int shot = f / a.n_int, tile = a.tl[f - shot * a.n_int];
+  const int NX = a.NX, NZ = a.NZ;
+  const size_t plane = (size_t)NX * NZ, base = (size_t)shot * plane;
+  const int x0 = (tile % a.tiles_x) * kTX, z0 = (tile / a.tiles_x) * kTZ;
+  const int tid = threadIdx.x, lx = tid & 63, zb = (tid >> 6) * kRZ;
+  const int gx = x0 + lx;
+
+  float pold[kRZ], ccx[kRZ], ccz[kRZ], ccm[kRZ];
+  double gold[kRZ];
+#pragma unroll
+  for (int r = 0; r < kRZ; ++r) {
+    const int gz = z0 + zb + r;
+    const bool ok = gx < NX && gz < NZ;
+    const size_t idx = ok ? (size_t)gz * NX + gx : 0;
+    pold[r] = ok ? ld_nt(a.prev + base + idx) : 0.0f;
+    gold[r] = ok ? __builtin_nontemporal_load(a.gprev + base + idx) : 0.0;
+    ccx[r] = ok ? a.cx[idx] : 0.0f;
+    ccz[r] = ok ? a.cz[idx] : 0.0f;
+    ccm[r] = ok ? a.cm[idx] : 0.0f;
+  }
+  stage<GW, GH>(sP, a.cur + base, x0, z0, 4, 4, NX, NZ);
+  stage<GW, GH>(sG, a.gcur + base, x0, z0, 4, 4, NX, NZ);
+  __syncthreads();
+  constexpr int KT = (kTZ * GW + kThreads - 1) / kThreads;
+  double tz[KT], g0[kRZ];
+#pragma unroll
+  for (int k = 0; k < KT; ++k) {
+    const int e = tid + k * kThreads, r = e / GW, c = e - r * GW;
+    tz[k] = e < kTZ * GW ? d2d(&sG[(r + 4) * GW + c], GW) : 0.0;
+  }
+#pragma unroll
+  for (int rr = 0; rr < kRZ; ++rr) g0[rr] = sG[(zb + rr + 4) * GW + lx + 4];
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < KT; ++k) {
+    const int e = tid + k * kThreads;
+    if (e < kTZ * GW) sT[e] = tz[k];
+  }
+  __syncthreads();
+
+  const int src = a.src_cell[shot];
+  const float sw = a.w * a.wavelet[(size_t)shot * a.nt + a.n];
+  float out[kRZ];
+#pragma unroll
+  for (int rr = 0; rr < kRZ; ++rr) {
+    const int r = zb + rr, gz = z0 + r;
+    const bool ok = gx < NX && gz < NZ;
+    const size_t idx = ok ? (size_t)gz * NX + gx : 0;
+    const float* pc = &sP[(r + 4) * GW + lx + 4];
+    const float p0 = pc[0];
+    const float bxv = d2s(pc, 1), bzv = d2s(pc, GW);
+    const float m = (float)d2d(&sT[r * GW + lx + 4], 1);
+    float pn = 2.0f * p0 - pold[rr];
+    pn = fmaf(ccx[rr], bxv, pn);
+    pn = fmaf(ccz[rr], bzv, pn);
+    pn = fmaf(-ccm[rr], m, pn);
+    if (ok && (int)idx == src) pn += sw;
+    const double gn = (2.0 * g0[rr] - gold[rr]) + (double)p0;
+    out[rr] = pn;
+    if (ok) {
+      st_nt(a.prev + base + idx, pn);
+      __builtin_nontemporal_store(gn, a.gprev + base + idx);
+      if (a.tr[0]) {
+        st_nt(a.tr[0] + base + idx, bxv);
+        st_nt(a.tr[1] + base + idx, bzv);
+        st_nt(a.tr[2] + base + idx, m);
+      }
+    }
+  }
+  const int* ro = a.rec_off + (size_t)shot * a.ntiles + tile;
+  if (a.gathers && ro[1] > ro[0]) {
+    __syncthreads();
+#pragma unroll
+    for (int rr = 0; rr < kRZ; ++rr) sP[(zb + rr) * kTX + lx] = out[rr];
+    __syncthreads();
+    vti_record(a, shot, tile, sP);
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void vti_adj_int_kernel(VtiStep a) {
+  __shared__ float sQx[kTZ * GW];  // cx lambda^{n+1} on the tile rows, 4-column ring
+  __shared__ float sQz[GH * kTX];  // cz lambda^{n+1} on the tile columns, 4-row ring
+  // cm lambda^{n+1} (float64, 4-cell halo), then D2z'(cm lambda^{n+1}) (tile
+  // rows, 4-column ring)
+  __shared__ double sM[GH * GW];
+  double* sU = sM;
+  const int f = xcd_spread(blockIdx.x, gridDim.x);
+  const int shot = f / a.n_int, tile = a.tl[f - shot * a.n_int];
+  const int NX = a.NX, NZ = a.NZ;
+  const size_t plane = (size_t)NX * NZ, base = (size_t)shot * plane;
+  const int x0 = (tile % a.tiles_x) * kTX, z0 = (tile / a.tiles_x) * kTZ;
+  const int tid = threadIdx.x, lx = tid & 63, zb = (tid >> 6) * kRZ;
+  const int gx = x0 + lx;
+
+  // the lambda^{n+1} box and its coefficients, then the own cells' operands,
+  // all before the first LDS store
+  constexpr int NB = GH * GW, KB = (NB + kThreads - 1) / kThreads;
+  float bl[KB], bcx[KB], bcz[KB], bcm[KB];
+#pragma unroll
+  for (int k = 0; k < KB; ++k) {
+    const int e = tid + k * kThreads, r = e / GW, c = e - r * GW;
+    const int x = x0 - 4 + c, z = z0 - 4 + r;
+    const bool ok = e < NB && in_grid(x, z, NX, NZ);
+    const size_t idx = ok ? (size_t)z * NX + x : 0;
+    bl[k] = ok ? a.cur[base + idx] : 0.0f;
+    bcx[k] = ok ? a.cx[idx] : 0.0f;
+    bcz[k] = ok ? a.cz[idx] : 0.0f;
+    bcm[k] = ok ? a.cm[idx] : 0.0f;
+  }
+  float l1v[kRZ], l2[kRZ], t0[kRZ], t1[kRZ], t2[kRZ];
+  double m1[kRZ], m2[kRZ];
+#pragma unroll
+  for (int r = 0; r < kRZ; ++r) {
+    const int gz = z0 + zb + r;
+    const bool ok = gx < NX && gz < NZ;
+    const size_t idx = ok ? (size_t)gz * NX + gx : 0;
+    l1v[r] = ok ? a.cur[base + idx] : 0.0f;
+    l2[r] = ok ? ld_nt(a.prev + base + idx) : 0.0f;
+    m1[r] = ok ? a.mcur[base + idx] : 0.0;
+    m2[r] = ok ? __builtin_nontemporal_load(a.mprev + base + idx) : 0.0;
+    t0[r] = ok ? ld_nt(a.trc[0] + base + idx) : 0.0f;
+    t1[r] = ok ? ld_nt(a.trc[1] + base + idx) : 0.0f;
+    t2[r] = ok ? ld_nt(a.trc[2] + base + idx) : 0.0f;
+  }
+  // products (outside the grid every operand is 0)
+#pragma unroll
+  for (int k = 0; k < KB; ++k) {
+    const int e = tid + k * kThreads, r = e / GW, c = e - r * GW;
+    if (e >= NB) break;
+    if (r >= 4 && r < 4 + kTZ) sQx[(r - 4) * GW + c] = bcx[k] * bl[k];
+    if (c >= 4 && c < 4 + kTX) sQz[r * kTX + c - 4] = bcz[k] * bl[k];
+    sM[e] = (double)bcm[k] * (double)bl[k];
+  }
+  __syncthreads();
+  constexpr int KT = (kTZ * GW + kThreads - 1) / kThreads;
+  double tu[KT];
+#pragma unroll
+  for (int k = 0; k < KT; ++k) {
+    const int e = tid + k * kThreads, r = e / GW, c = e - r * GW;
+    tu[k] = e < kTZ * GW ? d2d(&sM[(r + 4) * GW + c], GW) : 0.0;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < KT; ++k) {
+    const int e = tid + k * kThreads;
+    if (e < kTZ * GW) sU[e] = tu[k];
+  }
+  __syncthreads();
+
+  float out[kRZ];
+#pragma unroll
+  for (int rr = 0; rr < kRZ; ++rr) {
+    const int r = zb + rr, gz = z0 + r;
+    const bool ok = gx < NX && gz < NZ;
+    const size_t idx = ok ? (size_t)gz * NX + gx : 0;
+    const float l1 = l1v[rr];
+    float lam = 2.0f * l1 - l2[rr];
+    lam += d2s(&sQx[r * GW + lx + 4], 1);
+    lam += d2s(&sQz[(r + 4) * kTX + lx], kTX);
+    lam += (float)m1[rr];
+    const double mu = (2.0 * m1[rr] - m2[rr]) - d2d(&sU[r * GW + lx + 4], 1);
+    out[rr] = lam;
+    if (!ok) continue;
+    __builtin_nontemporal_store(mu, a.mprev + base + idx);
+    float* g0 = a.g + base + idx;
+    float* g1 = g0 + (size_t)a.nshots * plane;
+    float* g2 = g1 + (size_t)a.nshots * plane;
+    if (a.g_init) {
+      st_nt(g0, l1 * t0[rr]);
+      st_nt(g1, l1 * t1[rr]);
+      st_nt(g2, -(l1 * t2[rr]));
+    } else {
+      st_nt(g0, fmaf(l1, t0[rr], ld_nt(g0)));
+      st_nt(g1, fmaf(l1, t1[rr], ld_nt(g1)));
+      st_nt(g2, ld_nt(g2) - l1 * t2[rr]);
+    }
+  }
+  // r_{n-1} at the receivers of this (shot, tile), as in vti_adj_kernel
+  const int* ro = a.rec_off + (size_t)shot * a.ntiles + tile;
+  if (a.resid && a.n >= 1 && ro[1] > ro[0]) {
+    __syncthreads();
+    float* st = sQz;
+#pragma unroll
+    for (int rr = 0; rr < kRZ; ++rr) st[(zb + rr) * kTX + lx] = out[rr];
+    __syncthreads();
+    const int e0 = ro[0], e1 = ro[1];
+    const float* rv = a.resid + ((size_t)shot * a.nt + (a.n - 1)) * a.nrec;
+    for (int e = e0 + tid; e < e1; e += kThreads) {
+      const int2 en = a.rec_ent[e];
+      if (e == e0 || a.rec_ent[e - 1].x != en.x) {
+        float acc = st[en.x];
+        for (int k = e; k < e1 && a.rec_ent[k].x == en.x; ++k) acc += rv[a.rec_ent[k].y];
+        st[en.x] = acc;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int rr = 0; rr < kRZ; ++rr) out[rr] = st[(zb + rr) * kTX + lx];
+  }
+#pragma unroll
+  for (int rr = 0; rr < kRZ; ++rr) {
+    const int gz = z0 + zb + rr;
+    if (gx < NX && gz < NZ) st_nt(a.prev + base + (size_t)gz * NX + gx, out[rr]);
+  }
+}
+
 // Padded model (vv, v, eta; eta = 0 in the pad) and the coefficients, from
 // model [3][nz][nx] = (vv, v, eta); r = dt / h.
 __global__ void vti_prep_kernel(const float* __restrict__ model, float* __restrict__ pad,
@@ -503,14 +720,27 @@ int vti_launch_prep(const float* model, float* pad, float* cx, float* cz, float*
   return SWEEP_OK;
 }
 
+bool vti_near_strip(int x0, int z0, int NX, int NZ, int P) {
+  return P > 0 && (x0 - 4 < P || x0 + kTX + 4 > NX - P || z0 - 4 < P || z0 + kTZ + 4 > NZ - P);
+}
+
+// Within a step every tile reads only the current level around it and writes
+// its own cells of the other buffers, so the two tile sets may run in either
+// order.
 int vti_launch_fwd(const VtiStep& a, hipStream_t s) {
-  hipLaunchKernelGGL(vti_fwd_kernel, dim3(a.ntiles * a.nshots), dim3(kThreads), 0, s, a);
+  if (a.n_int > 0)
+    hipLaunchKernelGGL(vti_fwd_int_kernel, dim3(a.n_int * a.nshots), dim3(kThreads), 0, s, a);
+  if (a.n_pml > 0)
+    hipLaunchKernelGGL(vti_fwd_kernel, dim3(a.n_pml * a.nshots), dim3(kThreads), 0, s, a);
   SWEEP_HIP(hipGetLastError());
   return SWEEP_OK;
 }
 
 int vti_launch_adj(const VtiStep& a, hipStream_t s) {
-  hipLaunchKernelGGL(vti_adj_kernel, dim3(a.ntiles * a.nshots), dim3(kThreads), 0, s, a);
+  if (a.n_int > 0)
+    hipLaunchKernelGGL(vti_adj_int_kernel, dim3(a.n_int * a.nshots), dim3(kThreads), 0, s, a);
+  if (a.n_pml > 0)
+    hipLaunchKernelGGL(vti_adj_kernel, dim3(a.n_pml * a.nshots), dim3(kThreads), 0, s, a);
   SWEEP_HIP(hipGetLastError());
   return SWEEP_OK;
 }

@@ -48,6 +48,7 @@ void vti_layout(const sweep_plan* p, VtiLayout& L) {
   L.rec_cell = take(off, std::max<size_t>(ns * nr, 1) * sizeof(int));
   L.rec_off = take(off, (ns * (size_t)p->ntiles + 1) * sizeof(int));
   L.rec_ent = take(off, std::max<size_t>(ns * nr, 1) * sizeof(int2));
+  L.tl = take(off, std::max<size_t>(p->ntiles, 1) * sizeof(int));
   for (int i = 0; i < 2; ++i) L.pf[i] = take(off, ns * plane * f);
   for (int i = 0; i < 2; ++i) L.gf[i] = take(off, ns * plane * sizeof(double));
   for (int i = 0; i < 2; ++i) L.aux[i] = take(off, L.aux_elems * f);
@@ -91,7 +92,25 @@ VtiStep vti_base(const sweep_plan* p, void* work, const VtiLayout& L) {
   a.wavelet = at<float>(work, L.wav);
   a.rec_off = at<int>(work, L.rec_off);
   a.rec_ent = at<int2>(work, L.rec_ent);
+  a.tl = at<int>(work, L.tl);
+  a.n_int = p->vti_nint;
+  a.n_pml = p->ntiles - p->vti_nint;
   return a;
+}
+
+// The tile list of the step kernels (interior tiles first) on the plan.
+void vti_split_tiles(sweep_plan* p) {
+  std::vector<int> rest;
+  p->vti_tl.clear();
+  for (int t = 0; t < p->ntiles; ++t) {
+    const int x0 = (t % p->tiles_x) * kTX, z0 = (t / p->tiles_x) * kVtiTZ;
+    if (vti_near_strip(x0, z0, p->NX, p->NZ, p->P))
+      rest.push_back(t);
+    else
+      p->vti_tl.push_back(t);
+  }
+  p->vti_nint = (int)p->vti_tl.size();
+  p->vti_tl.insert(p->vti_tl.end(), rest.begin(), rest.end());
 }
 
 // the four memory-variable arrays of an aux block: psx, zex, psz, zez
@@ -162,6 +181,9 @@ int vti_forward(sweep_plan* p, const float* model, const float* wavelet, float* 
   }
   SWEEP_HIP(hipMemcpyAsync(at<int>(work, L.rec_off), p->rec_off.data(),
                            p->rec_off.size() * sizeof(int), hipMemcpyHostToDevice, s));
+  vti_split_tiles(p);
+  SWEEP_HIP(hipMemcpyAsync(at<int>(work, L.tl), p->vti_tl.data(), p->vti_tl.size() * sizeof(int),
+                           hipMemcpyHostToDevice, s));
   if ((rc = ac_launch_tables(at<float>(work, L.ax), at<float>(work, L.bx), at<float>(work, L.az),
                              at<float>(work, L.bz), p->NX, p->NZ, p->P, pb.h, pb.dt, pb.pml_vmax,
                              pb.pml_f0, pb.pml_R, s)))
