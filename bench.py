@@ -651,30 +651,45 @@ def kernel_report(plan, w, kt):
         per_launch[ph + "_xpml"] = (b * x_cells + 16.0 * x_strip) * w.nshots
         per_launch[ph + "_deep"] = deep_b[ph] * deep_cells * w.nshots
         effective[ph + "_deep"] = 2.0 * b * deep_cells * w.nshots
-    # Dominant kernel: largest time per gradient, average launch time x launches
-    # per gradient (a two-step pass runs once per two steps). The timer samples
-    # launches, so the sampled totals are not comparable between classes.
+    # Dominant kernel: the class with the largest time per step, its average
+    # launch time (the timer samples every 10th step's launches, so sampled
+    # totals are not comparable) halved for a two-step pass (one launch per
+    # two steps). Every adjoint class runs on all steps of the reverse sweep,
+    # so among them this orders the time per gradient; they lead it.
     runs = {kk: (0.5 if kk.endswith("_deep") else 1.0) for kk in kt}
     est = {kk: (vv[1] / vv[0]) * runs[kk] for kk, vv in kt.items() if vv[0] > 0}
-    dom = max(est, key=lambda kk: est[kk])
-    roof = None
-    if dom in per_launch and kt[dom][0] > 0:
-        launches, tot_ms = kt[dom]
+    ranked = sorted(est, key=lambda kk: -est[kk])
+
+    def roofline_of(cls):
+        launches, tot_ms = kt[cls]
         avg_s = tot_ms / launches / 1e3
         # algorithmic bytes per launch: the per-cell-update figure times the
         # cell-updates one launch makes (two per cell for a two-step pass, T = 2;
         # the fraction may then exceed what the pass itself moves)
-        T = 2 if dom.endswith("_deep") else 1
-        bytes_per_launch = effective.get(dom, per_launch[dom])
+        T = 2 if cls.endswith("_deep") else 1
+        bytes_per_launch = effective.get(cls, per_launch[cls])
         achieved = bytes_per_launch / avg_s / 1e9
-        tr = TRAFFIC.get(dom)
+        tr = TRAFFIC.get(cls)
         traffic = tr["bytes_per_launch"] if tr and tr["source"] == _source_hash() else None
-        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+        return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": dom, "T": T, "avg_launch_us": round(avg_s * 1e6, 2),
+                "kernel": cls, "T": T, "avg_launch_us": round(avg_s * 1e6, 2),
                 "algorithmic_bytes_per_launch": int(bytes_per_launch),
-                "pass_bytes_per_launch": int(per_launch[dom]),
-                "pass_frac": round(per_launch[dom] / avg_s / 1e9 / HBM_PEAK_GBS, 4)}
+                "pass_bytes_per_launch": int(per_launch[cls]),
+                "pass_frac": round(per_launch[cls] / avg_s / 1e9 / HBM_PEAK_GBS, 4)}
+
+    roof = None
+    if ranked and ranked[0] in per_launch:
+        roof = roofline_of(ranked[0])
+        # the adjoint two-step pass and the adjoint z-frame kernel take about
+        # the same time per gradient; the runner-up is reported beside the
+        # dominant class, with its time relative to it
+        if len(ranked) > 1 and ranked[1] in per_launch:
+            ru = roofline_of(ranked[1])
+            roof["runner_up"] = {"kernel": ru["kernel"], "frac": ru["frac"], "T": ru["T"],
+                                 "avg_launch_us": ru["avg_launch_us"],
+                                 "time_per_gradient_vs_dominant":
+                                     round(est[ranked[1]] / est[ranked[0]], 3)}
     kernels = {}
     for name, (nl, ms) in kt.items():
         if nl > 0 and name in per_launch:
