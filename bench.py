@@ -563,14 +563,14 @@ def vti_gradient(sw, torch, nt=0):
     plan.release_workspace()
     cells = 2.0 * w.nshots * NX * NZ * w.nt
     per = w.nshots * NX * NZ
-    # algorithmic bytes per cell-update: forward reads P^{n-1}, cx, cz, cm
-    # (4 B each), G^{n-1} (8 B, float64), P^n (4) and G^n (8) once, writes
-    # P^{n+1} (4) and G^{n+1} (8): 48 B; the recompute also writes Bx', Bz',
-    # D2x'D2z'G (+12 B); the adjoint reads lambda^{n+1}, lambda^{n+2} (8 B),
-    # mu^{n+1}, mu^{n+2} (16, float64), cx, cz, cm (12), the three traces (12)
-    # and the partials g (12, written only on a segment's first step), and
-    # writes lambda^n (4), mu^n (8) and g (12): 84 B
-    kb = {"fwd_int": 48.0, "rec_int": 60.0, "adj_int": 84.0}
+    # algorithmic bytes per cell-update: forward reads cx, cz, cm (4 B each),
+    # P^{n-1} and G^{n-1} (8 B each, float64), P^n and G^n (8 each) once, and
+    # writes P^{n+1} and G^{n+1} (8 each): 60 B; the recompute also writes
+    # Bx', Bz', D2x'D2z'G (+12 B); the adjoint reads lambda^{n+1},
+    # lambda^{n+2} (8 B), mu^{n+1}, mu^{n+2} (16, float64), cx, cz, cm (12),
+    # the three traces (12) and the partials g (12, written only on a
+    # segment's first step), and writes lambda^n (4), mu^n (8) and g (12): 84 B
+    kb = {"fwd_int": 60.0, "rec_int": 72.0, "adj_int": 84.0}
     kern = {}
     for name, b in kb.items():
         n, ms = kt[name]

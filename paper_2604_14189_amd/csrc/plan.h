@@ -87,7 +87,7 @@ struct ElLayout {
 }  // namespace sweep
 
 namespace sweep {
-// Pseudo-acoustic VTI plan: fields P (float32) and G = F / dt^2 (float64), two
+// Pseudo-acoustic VTI plan: fields P and G = F / dt^2 (both float64), two
 // buffers each (the new level overwriting the oldest), C-PML strips as in the
 // acoustic layout.
 struct VtiLayout {

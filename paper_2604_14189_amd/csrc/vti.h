@@ -18,6 +18,14 @@ namespace sweep {
 // so G, its update and D2x'D2z'G are held in float64 and only cm D2x'D2z'G is
 // rounded to float32. The adjoint of G, mu, accumulates D2x'D2z'(cm lambda)
 // twice over time in the same way, so it and that mixed term are float64 too.
+// P itself is float64 as well: rounding P^{n+1} to float32 every step injects
+// white noise that D2x'D2z'G turns into an error of about 1e-3 .. 1e-2 in the
+// eta gradient where eta = 0 (there no mixed term feeds back, and nothing
+// bounds the low-frequency part that G sums up). The stencils stay float32:
+// they take hi = float(P) and lo = P - hi (kept to bfloat16 in LDS, where
+// it needs only a few bits) separately, so their result holds P's low bits
+// too. The adjoint fields may stay float32 (their rounding moves the
+// gradients by about 1e-6).
 // Tiles are 64 x 16 cells; thread (lx, w) of a 256-thread work-group owns
 // column lx and rows 4w .. 4w+3 of its tile.
 constexpr int kVtiTZ = 16;
@@ -36,11 +44,13 @@ struct VtiStep {
   const float* bx;
   const float* az;
   const float* bz;
-  // forward: P^n (cur), P^{n-1} in / P^{n+1} out (prev); G likewise.
-  // adjoint: lambda^{n+1} (cur), lambda^{n+2} in / lambda^n out (prev); the
-  // adjoint of G (mu) likewise. prev is read and written at a thread's own
-  // cells only, so it is updated in place.
-  const float* cur;
+  // forward: P^n (pcur), P^{n-1} in / P^{n+1} out (pprev), both float64; G
+  // likewise. adjoint: lambda^{n+1} (cur), lambda^{n+2} in / lambda^n out
+  // (prev); the adjoint of G (mu) likewise. The second field of each pair is
+  // read and written at a thread's own cells only, so it is updated in place.
+  const double* pcur;  // forward: P (float64)
+  double* pprev;
+  const float* cur;    // adjoint: lambda
   float* prev;
   const double* gcur;  // forward: G (float64)
   double* gprev;

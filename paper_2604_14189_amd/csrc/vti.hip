@@ -5,8 +5,10 @@
 // adjoint. Scaled form and data layout: vti.h.
 //
 // One work-group of 256 lanes takes one 64 x 16 tile of one shot. It stages
-// P^n with an 8-cell halo and G^n with a 4-cell halo in LDS (all global loads
-// of a lane are issued before its first LDS store), computes the C-PML memory
+// P^n (float64 in memory) as its float32 part hi and the bfloat16 rounding of
+// the rest, lo, with an 8-cell halo, and G^n with a 4-cell halo in LDS (all
+// global loads of a lane are issued before its first LDS store), computes the
+// C-PML memory
 // variables psi on a 4-cell ring only when a strip lies within 4 cells (a
 // block-uniform test), D2z' G on the tile rows and a 4-column ring, and then
 // each lane finishes its four cells from LDS. P^{n+1} and G^{n+1} overwrite
@@ -53,6 +55,52 @@ __device__ __forceinline__ void stage(T* s, const T* __restrict__ f, int x0, int
   }
 }
 
+// P = hi + lo: hi = float(P), lo = P - hi rounded to bfloat16 (round to
+// nearest even; lo is finite and far from the float range's ends).
+__device__ __forceinline__ unsigned short bf16_bits(float x) {
+  const unsigned u = __float_as_uint(x);
+  return (unsigned short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+__device__ __forceinline__ float bf16_val(unsigned short b) {
+  return __uint_as_float((unsigned)b << 16);
+}
+
+// Stage float64 field f as hi (float) and lo (bfloat16) boxes, as stage does.
+template <int W, int H>
+__device__ __forceinline__ void stage_split(float* hi, unsigned short* lo,
+                                            const double* __restrict__ f, int x0, int z0, int hx,
+                                            int hz, int NX, int NZ) {
+  constexpr int N = W * H;
+  constexpr int K = (N + kThreads - 1) / kThreads;
+  double v[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int e = threadIdx.x + k * kThreads;
+    const int r = e / W, c = e - r * W;
+    const int gx = x0 - hx + c, gz = z0 - hz + r;
+    const bool ok = e < N && in_grid(gx, gz, NX, NZ);
+    v[k] = ok ? f[(size_t)gz * NX + gx] : 0.0;
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int e = threadIdx.x + k * kThreads;
+    if (e < N) {
+      const float h = (float)v[k];
+      hi[e] = h;
+      lo[e] = bf16_bits((float)(v[k] - (double)h));
+    }
+  }
+}
+
+// D2' of P from the hi and lo boxes (both centred on the same cell): the two
+// parts' second differences in float32, summed.
+__device__ __forceinline__ float d2p(const float* hi, const unsigned short* lo, int st) {
+  const float l = d2c(bf16_val(lo[0]), bf16_val(lo[st]), bf16_val(lo[-st]), bf16_val(lo[2 * st]),
+                      bf16_val(lo[-2 * st]), bf16_val(lo[3 * st]), bf16_val(lo[-3 * st]),
+                      bf16_val(lo[4 * st]), bf16_val(lo[-4 * st]));
+  return d2s(hi, st) + l;
+}
+
 // 8th-order centred-difference second derivative in float64 (for G).
 __device__ __forceinline__ double d2d(const double* f, int st) {
   const double c = f[0];
@@ -74,7 +122,8 @@ __device__ __forceinline__ void vti_record(const VtiStep& a, int shot, int tile,
 }
 
 __global__ __launch_bounds__(kThreads) void vti_fwd_kernel(VtiStep a) {
-  __shared__ float sP[PH * PW];    // P^n, 8-cell halo
+  __shared__ float sP[PH * PW];            // P^n: hi, 8-cell halo
+  __shared__ unsigned short sPl[PH * PW];  // and lo
   // G^n (float64, 4-cell halo); once each lane holds its cells' G^n and its
   // share of D2z' G^n (tile rows, 4-column ring) in registers, the same
   // memory holds that D2z' G^n
@@ -94,15 +143,16 @@ __global__ __launch_bounds__(kThreads) void vti_fwd_kernel(VtiStep a) {
   const int gx = x0 + lx;
   const int xcol = gx < NX ? xstrip_col(gx, NX, P) : -1;
 
-  // own cells: old values, coefficients, zeta^{n-1}
-  float pold[kRZ], ccx[kRZ], ccz[kRZ], ccm[kRZ], zx[kRZ], zz[kRZ];
-  double gold[kRZ];
+  // own cells: P^n, old values, coefficients, zeta^{n-1}
+  float ccx[kRZ], ccz[kRZ], ccm[kRZ], zx[kRZ], zz[kRZ];
+  double pown[kRZ], pold[kRZ], gold[kRZ];
 #pragma unroll
   for (int r = 0; r < kRZ; ++r) {
     const int gz = z0 + zb + r;
     const bool ok = gx < NX && gz < NZ;
     const size_t idx = ok ? (size_t)gz * NX + gx : 0;
-    pold[r] = ok ? ld_nt(a.prev + base + idx) : 0.0f;
+    pown[r] = ok ? a.pcur[base + idx] : 0.0;
+    pold[r] = ok ? __builtin_nontemporal_load(a.pprev + base + idx) : 0.0;
     gold[r] = ok ? __builtin_nontemporal_load(a.gprev + base + idx) : 0.0;
     ccx[r] = ok ? a.cx[idx] : 0.0f;
     ccz[r] = ok ? a.cz[idx] : 0.0f;
@@ -111,7 +161,7 @@ __global__ __launch_bounds__(kThreads) void vti_fwd_kernel(VtiStep a) {
     zx[r] = ok && xcol >= 0 ? a.zex_in[((size_t)shot * NZ + gz) * P2 + xcol] : 0.0f;
     zz[r] = zrow >= 0 ? a.zez_in[((size_t)shot * P2 + zrow) * NX + gx] : 0.0f;
   }
-  stage<PW, PH>(sP, a.cur + base, x0, z0, 8, 8, NX, NZ);
+  stage_split<PW, PH>(sP, sPl, a.pcur + base, x0, z0, 8, 8, NX, NZ);
   stage<GW, GH>(sG, a.gcur + base, x0, z0, 4, 4, NX, NZ);
   __syncthreads();
 
@@ -163,15 +213,15 @@ __global__ __launch_bounds__(kThreads) void vti_fwd_kernel(VtiStep a) {
 
   const int src = a.src_cell[shot];
   const float sw = a.w * a.wavelet[(size_t)shot * a.nt + a.n];
+  const int srow = src_row(src, NX, x0, z0 + zb, kRZ), scol = src_col(src, NX, x0);
   float out[kRZ];
 #pragma unroll
   for (int rr = 0; rr < kRZ; ++rr) {
     const int r = zb + rr, gz = z0 + r;
     const bool ok = gx < NX && gz < NZ;
     const size_t idx = ok ? (size_t)gz * NX + gx : 0;
-    const float* pc = &sP[(r + 8) * PW + lx + 8];
-    const float p0 = pc[0];
-    float qx = d2s(pc, 1), qz = d2s(pc, PW);
+    const int pe = (r + 8) * PW + lx + 8;
+    float qx = d2p(&sP[pe], &sPl[pe], 1), qz = d2p(&sP[pe], &sPl[pe], PW);
     if (hx) qx += d1s(&sX[r * GW + lx + 4], 1);
     if (hz) qz += d1s(&sZ[(r + 4) * kTX + lx], kTX);
     float bxv = qx, bzv = qz;
@@ -187,15 +237,16 @@ __global__ __launch_bounds__(kThreads) void vti_fwd_kernel(VtiStep a) {
       bzv = qz + zn;
     }
     const float m = (float)d2d(&sT[r * GW + lx + 4], 1);
-    float pn = 2.0f * p0 - pold[rr];
-    pn = fmaf(ccx[rr], bxv, pn);
-    pn = fmaf(ccz[rr], bzv, pn);
-    pn = fmaf(-ccm[rr], m, pn);
-    if (ok && (int)idx == src) pn += sw;
-    const double gn = (2.0 * g0[rr] - gold[rr]) + (double)p0;
-    out[rr] = pn;
+    const double p0 = pown[rr];
+    double pn = 2.0 * p0 - pold[rr];
+    pn = fma((double)ccx[rr], (double)bxv, pn);
+    pn = fma((double)ccz[rr], (double)bzv, pn);
+    pn = fma(-(double)ccm[rr], (double)m, pn);
+    if (ok && rr == srow && lx == scol) pn += (double)sw;
+    const double gn = (2.0 * g0[rr] - gold[rr]) + p0;
+    out[rr] = (float)pn;
     if (ok) {
-      st_nt(a.prev + base + idx, pn);
+      __builtin_nontemporal_store(pn, a.pprev + base + idx);
       __builtin_nontemporal_store(gn, a.gprev + base + idx);
       if (a.tr[0]) {
         st_nt(a.tr[0] + base + idx, bxv);
@@ -435,7 +486,8 @@ __global__ __launch_bounds__(kThreads) void vti_adj_kernel(VtiStep a) {
 // bits), with P^n staged with a 4-cell halo: about half the LDS of the
 // general kernels and fewer registers, for more work-groups per CU.
 __global__ __launch_bounds__(kThreads) void vti_fwd_int_kernel(VtiStep a) {
-  __shared__ float sP[GH * GW];   // P^n, 4-cell halo
+  __shared__ float sP[GH * GW];            // P^n: hi, 4-cell halo
+  __shared__ unsigned short sPl[GH * GW];  // and lo
   // G^n (float64, 4-cell halo), then D2z' G^n (tile rows, 4-column ring)
   __shared__ double sG[GH * GW];
   double* sT = sG;
@@ -447,20 +499,21 @@ __global__ __launch_bounds__(kThreads) void vti_fwd_int_kernel(VtiStep a) {
   const int tid = threadIdx.x, lx = tid & 63, zb = (tid >> 6) * kRZ;
   const int gx = x0 + lx;
 
-  float pold[kRZ], ccx[kRZ], ccz[kRZ], ccm[kRZ];
-  double gold[kRZ];
+  float ccx[kRZ], ccz[kRZ], ccm[kRZ];
+  double pown[kRZ], pold[kRZ], gold[kRZ];
 #pragma unroll
   for (int r = 0; r < kRZ; ++r) {
     const int gz = z0 + zb + r;
     const bool ok = gx < NX && gz < NZ;
     const size_t idx = ok ? (size_t)gz * NX + gx : 0;
-    pold[r] = ok ? ld_nt(a.prev + base + idx) : 0.0f;
+    pown[r] = ok ? a.pcur[base + idx] : 0.0;
+    pold[r] = ok ? __builtin_nontemporal_load(a.pprev + base + idx) : 0.0;
     gold[r] = ok ? __builtin_nontemporal_load(a.gprev + base + idx) : 0.0;
     ccx[r] = ok ? a.cx[idx] : 0.0f;
     ccz[r] = ok ? a.cz[idx] : 0.0f;
     ccm[r] = ok ? a.cm[idx] : 0.0f;
   }
-  stage<GW, GH>(sP, a.cur + base, x0, z0, 4, 4, NX, NZ);
+  stage_split<GW, GH>(sP, sPl, a.pcur + base, x0, z0, 4, 4, NX, NZ);
   stage<GW, GH>(sG, a.gcur + base, x0, z0, 4, 4, NX, NZ);
   __syncthreads();
   constexpr int KT = (kTZ * GW + kThreads - 1) / kThreads;
@@ -482,25 +535,26 @@ __global__ __launch_bounds__(kThreads) void vti_fwd_int_kernel(VtiStep a) {
 
   const int src = a.src_cell[shot];
   const float sw = a.w * a.wavelet[(size_t)shot * a.nt + a.n];
+  const int srow = src_row(src, NX, x0, z0 + zb, kRZ), scol = src_col(src, NX, x0);
   float out[kRZ];
 #pragma unroll
   for (int rr = 0; rr < kRZ; ++rr) {
     const int r = zb + rr, gz = z0 + r;
     const bool ok = gx < NX && gz < NZ;
     const size_t idx = ok ? (size_t)gz * NX + gx : 0;
-    const float* pc = &sP[(r + 4) * GW + lx + 4];
-    const float p0 = pc[0];
-    const float bxv = d2s(pc, 1), bzv = d2s(pc, GW);
+    const int pe = (r + 4) * GW + lx + 4;
+    const float bxv = d2p(&sP[pe], &sPl[pe], 1), bzv = d2p(&sP[pe], &sPl[pe], GW);
     const float m = (float)d2d(&sT[r * GW + lx + 4], 1);
-    float pn = 2.0f * p0 - pold[rr];
-    pn = fmaf(ccx[rr], bxv, pn);
-    pn = fmaf(ccz[rr], bzv, pn);
-    pn = fmaf(-ccm[rr], m, pn);
-    if (ok && (int)idx == src) pn += sw;
-    const double gn = (2.0 * g0[rr] - gold[rr]) + (double)p0;
-    out[rr] = pn;
+    const double p0 = pown[rr];
+    double pn = 2.0 * p0 - pold[rr];
+    pn = fma((double)ccx[rr], (double)bxv, pn);
+    pn = fma((double)ccz[rr], (double)bzv, pn);
+    pn = fma(-(double)ccm[rr], (double)m, pn);
+    if (ok && rr == srow && lx == scol) pn += (double)sw;
+    const double gn = (2.0 * g0[rr] - gold[rr]) + p0;
+    out[rr] = (float)pn;
     if (ok) {
-      st_nt(a.prev + base + idx, pn);
+      __builtin_nontemporal_store(pn, a.pprev + base + idx);
       __builtin_nontemporal_store(gn, a.gprev + base + idx);
       if (a.tr[0]) {
         st_nt(a.tr[0] + base + idx, bxv);

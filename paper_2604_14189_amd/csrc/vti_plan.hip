@@ -49,14 +49,14 @@ void vti_layout(const sweep_plan* p, VtiLayout& L) {
   L.rec_off = take(off, (ns * (size_t)p->ntiles + 1) * sizeof(int));
   L.rec_ent = take(off, std::max<size_t>(ns * nr, 1) * sizeof(int2));
   L.tl = take(off, std::max<size_t>(p->ntiles, 1) * sizeof(int));
-  for (int i = 0; i < 2; ++i) L.pf[i] = take(off, ns * plane * f);
+  for (int i = 0; i < 2; ++i) L.pf[i] = take(off, ns * plane * sizeof(double));
   for (int i = 0; i < 2; ++i) L.gf[i] = take(off, ns * plane * sizeof(double));
   for (int i = 0; i < 2; ++i) L.aux[i] = take(off, L.aux_elems * f);
   L.fwd_end = off;
   const int k = p->ckpt;
   L.nseg = (p->pb.nt + k - 1) / k;
-  // in floats: P^n, P^{n-1} (float32), G^n, G^{n-1} (float64), memory variables
-  L.slot_elems = 6 * ns * plane + L.aux_elems;
+  // in floats: P^n, P^{n-1}, G^n, G^{n-1} (float64), memory variables
+  L.slot_elems = 8 * ns * plane + L.aux_elems;
   L.ck = take(off, (size_t)L.nseg * L.slot_elems * f);
   L.tr = take(off, (size_t)k * 3 * ns * plane * f);
   for (int i = 0; i < 2; ++i) L.lf[i] = take(off, ns * plane * f);
@@ -146,8 +146,8 @@ int vti_fwd_step(sweep_plan* p, void* work, const VtiLayout& L, int n, int c, fl
   const size_t ns = p->pb.nshots;
   VtiStep a = vti_base(p, work, L);
   a.n = n;
-  a.cur = at<float>(work, L.pf[c]);
-  a.prev = at<float>(work, L.pf[1 - c]);
+  a.pcur = at<double>(work, L.pf[c]);
+  a.pprev = at<double>(work, L.pf[1 - c]);
   a.gcur = at<double>(work, L.gf[c]);
   a.gprev = at<double>(work, L.gf[1 - c]);
   set_aux(a, at<float>(work, L.aux[n % 2]), at<float>(work, L.aux[1 - n % 2]), L, ns);
@@ -194,7 +194,7 @@ int vti_forward(sweep_plan* p, const float* model, const float* wavelet, float* 
     return rc;
   if ((rc = launch_copy(at<float>(work, L.wav), wavelet, ns * pb.nt, s))) return rc;
   for (int i = 0; i < 2; ++i) {
-    if ((rc = launch_fill(at<float>(work, L.pf[i]), nsplane, 0.0f, s))) return rc;
+    if ((rc = launch_fill(at<float>(work, L.pf[i]), 2 * nsplane, 0.0f, s))) return rc;
     if ((rc = launch_fill(at<float>(work, L.gf[i]), 2 * nsplane, 0.0f, s))) return rc;
     if ((rc = launch_fill(at<float>(work, L.aux[i]), L.aux_elems, 0.0f, s))) return rc;
   }
@@ -203,14 +203,15 @@ int vti_forward(sweep_plan* p, const float* model, const float* wavelet, float* 
   for (int n = 0; n < pb.nt; ++n) {
     if (save && n % k == 0) {
       float* slot = at<float>(work, L.ck) + (size_t)(n / k) * L.slot_elems;
-      if ((rc = launch_copy(slot, at<float>(work, L.pf[c]), nsplane, s))) return rc;
-      if ((rc = launch_copy(slot + nsplane, at<float>(work, L.pf[1 - c]), nsplane, s))) return rc;
-      // G as raw bits: two floats per float64 value
-      if ((rc = launch_copy(slot + 2 * nsplane, at<float>(work, L.gf[c]), 2 * nsplane, s)))
+      // P and G as raw bits: two floats per float64 value
+      if ((rc = launch_copy(slot, at<float>(work, L.pf[c]), 2 * nsplane, s))) return rc;
+      if ((rc = launch_copy(slot + 2 * nsplane, at<float>(work, L.pf[1 - c]), 2 * nsplane, s)))
         return rc;
-      if ((rc = launch_copy(slot + 4 * nsplane, at<float>(work, L.gf[1 - c]), 2 * nsplane, s)))
+      if ((rc = launch_copy(slot + 4 * nsplane, at<float>(work, L.gf[c]), 2 * nsplane, s)))
         return rc;
-      if ((rc = launch_copy(slot + 6 * nsplane, at<float>(work, L.aux[n % 2]), L.aux_elems, s)))
+      if ((rc = launch_copy(slot + 6 * nsplane, at<float>(work, L.gf[1 - c]), 2 * nsplane, s)))
+        return rc;
+      if ((rc = launch_copy(slot + 8 * nsplane, at<float>(work, L.aux[n % 2]), L.aux_elems, s)))
         return rc;
     }
     if ((rc = vti_fwd_step(p, work, L, n, c, gathers, nullptr, s, kFwdInt))) return rc;
@@ -251,13 +252,14 @@ int vti_backward(sweep_plan* p, const float* resid, float* grad, void* work, siz
     const int n0 = sg * k, n1 = std::min(nt, n0 + k);
     // restore the state entering step n0 into buffer pair 0 and aux[n0 % 2]
     const float* slot = at<float>(work, L.ck) + (size_t)sg * L.slot_elems;
-    if ((rc = launch_copy(at<float>(work, L.pf[0]), slot, nsplane, s))) return rc;
-    if ((rc = launch_copy(at<float>(work, L.pf[1]), slot + nsplane, nsplane, s))) return rc;
-    if ((rc = launch_copy(at<float>(work, L.gf[0]), slot + 2 * nsplane, 2 * nsplane, s)))
+    if ((rc = launch_copy(at<float>(work, L.pf[0]), slot, 2 * nsplane, s))) return rc;
+    if ((rc = launch_copy(at<float>(work, L.pf[1]), slot + 2 * nsplane, 2 * nsplane, s)))
       return rc;
-    if ((rc = launch_copy(at<float>(work, L.gf[1]), slot + 4 * nsplane, 2 * nsplane, s)))
+    if ((rc = launch_copy(at<float>(work, L.gf[0]), slot + 4 * nsplane, 2 * nsplane, s)))
       return rc;
-    if ((rc = launch_copy(at<float>(work, L.aux[n0 % 2]), slot + 6 * nsplane, L.aux_elems, s)))
+    if ((rc = launch_copy(at<float>(work, L.gf[1]), slot + 6 * nsplane, 2 * nsplane, s)))
+      return rc;
+    if ((rc = launch_copy(at<float>(work, L.aux[n0 % 2]), slot + 8 * nsplane, L.aux_elems, s)))
       return rc;
     int c = 0;
     for (int n = n0; n < n1; ++n) {

@@ -22,6 +22,12 @@ elastic600x300_shot11.npz: shot 11 of the 600x300 / 4000-step elastic workload
 (30-cell pad, free surface, 32 explosive 15 Hz shots, 600 two-component
 receivers): 8 complete (vx, vz) traces and the (vp, vs, rho) gradient for a
 band-limited seeded residual on that shot at 20 000 sampled cells.
+
+vti1000x300_shot23.npz: shot 23 of the 1000x300 / 3000-step pseudo-acoustic
+VTI workload (the layered benchmark's grid, shots and receivers; eta up to
+0.12 below an isotropic top zone): 8 complete receiver traces and the
+(vv, v, eta) gradient for a band-limited seeded residual on that shot at
+20 000 sampled cells, with the norm of each gradient plane.
 """
 import os
 import sys
@@ -72,6 +78,25 @@ def elastic_shot11(path):
                         grad_cells=cells, grad=np.stack([g[c].ravel()[cells] for c in range(3)]))
 
 
+def vti_shot23(path):
+    w = synth.workload("vti1000x300")
+    s = 23
+    sl = slice(s, s + 1)
+    src, rec, wav = w.sources()[sl], w.receivers()[sl], f32(w.wavelets()[sl])
+    model = f32(w.true_model())
+    pb = oracle.problem(w.nx, w.nz, w.pml, w.h, w.dt, w.nt, w.pml_vmax(), w.f0, w.pml_R,
+                        nshots=1, nrec=w.nrec, ckpt_every=w.ckpt_every)
+    resid = f32(synth.bandlimited_noise((1, w.nt, w.nrec), w.f0, w.dt, 23))
+    t = time.time()
+    g, _, d = oracle.vti_gradient(pb, model, src, wav, rec, resid, want_gathers=True)
+    print("oracle VTI gradient took %.1f s" % (time.time() - t), flush=True)
+    trace_idx = np.linspace(0, w.nrec - 1, 8).round().astype(np.int64)
+    cells = np.random.default_rng(23).choice(g[0].size, 20000, replace=False)
+    np.savez_compressed(path, shot=s, trace_idx=trace_idx, traces=d[0][:, trace_idx],
+                        grad_cells=cells, grad=np.stack([g[c].ravel()[cells] for c in range(3)]),
+                        grad_norm=np.array([np.linalg.norm(g[c]) for c in range(3)]))
+
+
 def batch_short_nt(m: int) -> int:
     """Shortened run of batched workload m (125 ... 250 steps)."""
     return 125 + int(round(125 * m / 7))
@@ -110,10 +135,12 @@ def batch_uneven8_short(path):
 
 if __name__ == "__main__":
     oracle.build(force=False)
-    which = sys.argv[1:] or ["layered", "elastic", "batch"]
+    which = sys.argv[1:] or ["layered", "elastic", "batch", "vti"]
     if "layered" in which:
         layered_shot37(os.path.join(HERE, "layered1000x300_shot37.npz"))
     if "elastic" in which:
         elastic_shot11(os.path.join(HERE, "elastic600x300_shot11.npz"))
     if "batch" in which:
         batch_uneven8_short(os.path.join(HERE, "batch_uneven8_short.npz"))
+    if "vti" in which:
+        vti_shot23(os.path.join(HERE, "vti1000x300_shot23.npz"))

@@ -3,7 +3,10 @@ against the FP64 oracle. Gathers <= 1e-5 and each of the three gradients
 (vv, v, eta) <= 1e-4 relative L2, on a ragged grid with sources next to the
 pad, coincident receivers and a ragged last checkpoint segment; eta = 0 with
 v = vv gives the acoustic plan's results; edge cases (one step, a grid smaller
-than one tile, no pad, no receivers)."""
+than one tile, no pad, no receivers); and the full 1000x300 / 3000-step
+workload, one shot against stored oracle values."""
+import os
+
 import numpy as np
 import pytest
 
@@ -153,3 +156,35 @@ def test_vti_tuning_limits(sw):
     for bad in ({"rz": 8}, {"keep_b": 2}, {"use_graph": 1}):
         with pytest.raises(sw.SweepError):
             plan.set_tuning(**bad)
+
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "vti1000x300_shot23.npz")
+
+
+@pytest.mark.skipif(not os.path.exists(GOLDEN), reason="golden file not generated")
+def test_full_size_vti_sampled_shot(sw):
+    """All 64 shots of the 1000x300 / 3000-step VTI workload (the bench's
+    configuration: 64 x 16 tiles, interior and C-PML tile kernels, every
+    segment recomputed); shot 23 compared with stored oracle traces and with
+    gradient samples for a residual on that shot only."""
+    gold = np.load(GOLDEN)
+    w = synth.workload("vti1000x300")
+    plan = sw.Plan(nx=w.nx, nz=w.nz, h=w.h, dt=w.dt, nt=w.nt, pml=w.pml, src_xz=w.sources(),
+                   rec_xz=w.receivers(), pml_vmax=w.pml_vmax(), pml_f0=w.f0, pml_R=w.pml_R,
+                   ckpt_every=w.ckpt_every, physics=sw.VTI)
+    d = plan.forward(_dev(w.true_model()), _dev(w.wavelets()), save=True)
+    s = int(gold["shot"])
+    tr = torch.as_tensor(gold["trace_idx"], device="cuda")
+    e_d = rel_l2(_host(d[s][:, tr]), gold["traces"])
+    resid = np.zeros((w.nshots, w.nt, w.nrec), np.float32)
+    resid[s] = f32(synth.bandlimited_noise((1, w.nt, w.nrec), w.f0, w.dt, 23))[0]
+    g = _host(plan.backward(_dev(resid)))
+    cells = gold["grad_cells"]
+    errs = [rel_l2(g[c].ravel()[cells], gold["grad"][c]) for c in range(3)]
+    norms = [abs(np.linalg.norm(g[c]) / gold["grad_norm"][c] - 1.0) for c in range(3)]
+    print("full-size VTI shot", s, "traces", e_d, "grad (vv, v, eta)", errs, "norms", norms,
+          flush=True)
+    plan.release_workspace()
+    assert e_d <= SEIS_TOL
+    assert max(errs) <= GRAD_TOL
+    assert max(norms) <= GRAD_TOL
