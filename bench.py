@@ -35,9 +35,9 @@ METRIC = "Gcell-updates/s fwd+adj; batched vs per-shot FWI gradient time at 1e-4
 # for a plain device copy of known size (--calibrate-copy). Keyed by kernel
 # class; valid only while the kernel source hashes to the recorded value.
 TRAFFIC = {
-    "adj_deep": {"bytes_per_launch": 605850004, "source": "7602bcb06891f8f1"},
-    "adj_zpml": {"bytes_per_launch": 293464880, "source": "7602bcb06891f8f1"},
-    "adj_xpml": {"bytes_per_launch": 129800229, "source": "7602bcb06891f8f1"},
+    "adj_deep": {"bytes_per_launch": 605895243, "source": "d085c20f2f747647"},
+    "adj_zpml": {"bytes_per_launch": 293324280, "source": "d085c20f2f747647"},
+    "adj_xpml": {"bytes_per_launch": 129790301, "source": "d085c20f2f747647"},
 }
 
 

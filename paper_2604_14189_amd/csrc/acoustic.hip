@@ -250,7 +250,6 @@ __device__ __forceinline__ void ac_fwd_int_body(const AcStep& a, const int tile,
   // also wait for this tile's stores)
   const int src = a.src_cell[shot];
   const float sw = a.w * a.wavelet[(size_t)shot * a.nt + a.n];
-  const int srow = src_row(src, NX, x0, z0 + zb, RZ), scol = src_col(src, NX, x0);
   stage_box<RZ, false>(sp, a.cur + shot * plane, nullptr, x0, z0, NX, NZ, inside);
   __syncthreads();
 
@@ -274,7 +273,7 @@ __device__ __forceinline__ void ac_fwd_int_body(const AcStep& a, const int tile,
       const size_t gi = shot * plane + idx;
       pn = fmaf(cs[r], L, 2.0f * c - pp[r]);
       if (kBorn) pn += bd[r] * bb[r];
-      if (r == srow && lx == scol) pn += sw;
+      if (idx == src) pn += sw;
       st_nt(&a.next[gi], pn);
       if (a.B_out) st_nt(&a.B_out[gi], L);
     }
@@ -469,7 +468,6 @@ __device__ __forceinline__ void ac_fwd_pml_body(const AcStep& a, const int tile,
   }
   const int src = a.src_cell[shot];
   const float sw = a.w * a.wavelet[(size_t)shot * a.nt + a.n];
-  const int srow = src_row(src, NX, x0, z0 + zb, RZ), scol = src_col(src, NX, x0);
   const int xcol = (HX && gx < NX) ? xstrip_col(gx, NX, P) : -1;
   float pp[RZ], cs[RZ], zx[RZ], zz[RZ], bd[kBorn ? RZ : 1], bb[kBorn ? RZ : 1];
 #pragma unroll
@@ -569,7 +567,7 @@ __device__ __forceinline__ void ac_fwd_pml_body(const AcStep& a, const int tile,
       const float B = Bx + Bz;
       pn = fmaf(cs[r], B, 2.0f * c - pp[r]);
       if (kBorn) pn += bd[r] * bb[r];
-      if (r == srow && lx == scol) pn += sw;
+      if (idx == src) pn += sw;
       st_nt(&a.next[gi], pn);
       if (a.B_out) st_nt(&a.B_out[gi], B);
     }

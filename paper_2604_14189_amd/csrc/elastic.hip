@@ -292,7 +292,6 @@ __global__ __launch_bounds__(256) void el_str_kernel(ElStep a) {
   }
   const int src = a.src_cell[shot];
   const float sw = a.w * a.wavelet[(size_t)shot * a.nt + a.n];
-  const int srow = src_row(src, NX, T.x0, C.jb, kElRZ), scol = src_col(src, NX, T.x0);
   __syncthreads();
   const Box vx{sb[0], T.x0, T.z0}, vz{sb[1], T.x0, T.z0};
   const int i = C.i;
@@ -312,7 +311,7 @@ __global__ __launch_bounds__(256) void el_str_kernel(ElStep a) {
                       cpml_p(a.ps[7] + so, k, Gh, axh, bxh, p7[r], true);
     float txx = otxx[r] + dt * fmaf(cxx_x[r], exx, cxx_z[r] * ezz);
     float tzz = otzz[r] + dt * fmaf(cxx_z[r], exx, czz_z(a, j, cxx_x[r]) * ezz);
-    if (r == srow && (threadIdx.x & 63) == scol) {
+    if ((int)k == src) {
       txx += sw;
       tzz += sw * a.smask[k];
     }

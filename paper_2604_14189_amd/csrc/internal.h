@@ -96,22 +96,6 @@ __device__ __forceinline__ int xcd_spread(int f, int n) {
   return x * q + min(x, r) + k;
 }
 
-// Source scatter at wave level. A shot has one source cell `src` (linear index
-// on a grid NX wide); a wave owns columns [x0, x0 + 64) of rows [gz0, gz0 +
-// rows). src_row returns the row (0 .. rows-1) of those that holds the source,
-// or -1: its operands are uniform over the wave, so after readfirstlane it is
-// one scalar test per wave, and only the lane of column src_col then adds the
-// sample. Every other wave skips the test in all of its cells.
-__device__ __forceinline__ int src_row(int src, int NX, int x0, int gz0, int rows) {
-  const int sz = src / NX, sx = src - sz * NX;
-  const int r = sz - gz0;
-  return __builtin_amdgcn_readfirstlane(
-      (r >= 0 && r < rows && sx >= x0 && sx < x0 + kTX) ? r : -1);
-}
-__device__ __forceinline__ int src_col(int src, int NX, int x0) {
-  return __builtin_amdgcn_readfirstlane(src % NX - x0);
-}
-
 // ------------------------------------------------------------------ acoustic
 // Device-side view of one time step of the acoustic recurrence (all shots of one
 // plan). Fields are [shot][NZ][NX]; x-strip memory variables [shot][NZ][2P]

@@ -213,7 +213,6 @@ __global__ __launch_bounds__(kThreads) void vti_fwd_kernel(VtiStep a) {
 
   const int src = a.src_cell[shot];
   const float sw = a.w * a.wavelet[(size_t)shot * a.nt + a.n];
-  const int srow = src_row(src, NX, x0, z0 + zb, kRZ), scol = src_col(src, NX, x0);
   float out[kRZ];
 #pragma unroll
   for (int rr = 0; rr < kRZ; ++rr) {
@@ -242,7 +241,7 @@ __global__ __launch_bounds__(kThreads) void vti_fwd_kernel(VtiStep a) {
     pn = fma((double)ccx[rr], (double)bxv, pn);
     pn = fma((double)ccz[rr], (double)bzv, pn);
     pn = fma(-(double)ccm[rr], (double)m, pn);
-    if (ok && rr == srow && lx == scol) pn += (double)sw;
+    if (ok && (int)idx == src) pn += (double)sw;
     const double gn = (2.0 * g0[rr] - gold[rr]) + p0;
     out[rr] = (float)pn;
     if (ok) {
@@ -535,7 +534,6 @@ __global__ __launch_bounds__(kThreads) void vti_fwd_int_kernel(VtiStep a) {
 
   const int src = a.src_cell[shot];
   const float sw = a.w * a.wavelet[(size_t)shot * a.nt + a.n];
-  const int srow = src_row(src, NX, x0, z0 + zb, kRZ), scol = src_col(src, NX, x0);
   float out[kRZ];
 #pragma unroll
   for (int rr = 0; rr < kRZ; ++rr) {
@@ -550,7 +548,7 @@ __global__ __launch_bounds__(kThreads) void vti_fwd_int_kernel(VtiStep a) {
     pn = fma((double)ccx[rr], (double)bxv, pn);
     pn = fma((double)ccz[rr], (double)bzv, pn);
     pn = fma(-(double)ccm[rr], (double)m, pn);
-    if (ok && rr == srow && lx == scol) pn += (double)sw;
+    if (ok && (int)idx == src) pn += (double)sw;
     const double gn = (2.0 * g0[rr] - gold[rr]) + p0;
     out[rr] = (float)pn;
     if (ok) {
