@@ -371,9 +371,18 @@ def batched_uneven(sw, torch, tuning=None):
 # partials written) and 64 B (velocity adjoints, bx, bz, stress adjoints, two
 # traces and two partials read; stress adjoints and the partials written).
 EL_STEP_BYTES = {"fwd_int": 80, "rec_int": 100, "adj_int": 140}
+# The fluid kernels of the variable-density plans (vs = 0: no txz, mxz, exz or
+# mu partials): forward 32 + 32 B (velocity: txx, tzz, vx, vz, bx, bz read,
+# vx, vz written; stress: vx, vz, txx, tzz, cxx_x, cxx_z read, txx, tzz
+# written), storing forward + four trace planes (16 B), reverse 48 + 56 B
+# (stress adjoints, two coefficients, velocity adjoints, two traces and the
+# lambda partial read, velocity adjoints and the partial written; velocity
+# adjoints, bx, bz, stress adjoints, two traces and two partials read, stress
+# adjoints and the partials written).
+VD_STEP_BYTES = {"fwd_int": 64, "rec_int": 80, "adj_int": 104}
 
 
-def el_step_kernels(torch, plan, grad, step_cells):
+def el_step_kernels(torch, plan, grad, step_cells, step_bytes=EL_STEP_BYTES):
     """Per-step kernel times of a staggered-grid plan (velocity + receivers +
     stress, or the two reverse kernels and the residual injection), from one
     more gradient timed every 10th step, with their algorithmic GB/s."""
@@ -383,7 +392,7 @@ def el_step_kernels(torch, plan, grad, step_cells):
     kt = plan.kernel_times()
     plan.set_profiling(False)
     out = {}
-    for cls, nbytes in EL_STEP_BYTES.items():
+    for cls, nbytes in step_bytes.items():
         n, ms = kt.get(cls, (0, 0.0))
         if n:
             us = 1e3 * ms / n
@@ -499,7 +508,7 @@ def encoded_gradient(sw, torch, nsuper=8):
 def acoustic_vd_gradient(sw, torch):
     """First-order variable-density acoustic FWI gradient (vp, rho) on the
     1000x300 layered workload (64 shots, 3000 steps, 40-cell C-PML), with
-    rho = 310 vp^0.25: the staggered kernels with vs = 0."""
+    rho = 310 vp^0.25: the staggered kernels' fluid variants (vs = 0)."""
     import synth
     w = synth.workload(WORKLOAD)
     vp = np.asarray(w.true_model(), np.float32)
@@ -520,7 +529,7 @@ def acoustic_vd_gradient(sw, torch):
     grad()
     _, t, ts = _median_time(torch, grad)
     NX, NZ = plan.padded()
-    kernels = el_step_kernels(torch, plan, grad, w.nshots * NX * NZ)
+    kernels = el_step_kernels(torch, plan, grad, w.nshots * NX * NZ, VD_STEP_BYTES)
     plan.release_workspace()
     cells = 2.0 * w.nshots * NX * NZ * w.nt
     return {"workload": "layered1000x300, rho = 310 vp^0.25", "shots": w.nshots, "nt": w.nt,

@@ -20,6 +20,7 @@ struct ElCoef {
 // One time step (forward) or its reverse (adjoint) for all shots of a plan.
 struct ElStep {
   int NX, NZ, nt, nrec, nshots, n, fs;
+  int fluid;        // vs = 0 (first-order acoustic): the kernels' fluid variants
   float dt, w, ih;  // time step, source scale dt/h^2, 1/h
   const float *bx, *bz, *mxz, *cxx_x, *cxx_z, *smask, *dM_dl, *dM_dm;
   const float *axi, *bxi, *axh, *bxh, *azi, *bzi, *azh, *bzh;

@@ -14,7 +14,13 @@
 // where a != 0.
 //
 // Forward step: velocity kernel (vx, vz), receiver gather, stress kernel
-// (txx, tzz, txz, explosive source). Reverse step (gather form of the
+// (txx, tzz, txz, explosive source). Every step kernel has a fluid variant
+// (kFluid, the first-order acoustic system at vs = 0): there mu = 0, so txz
+// stays 0, and the shear stress, its four memory variables and the mu
+// partials of the adjoint enter only through products with 0. The variant
+// drops them; every other value is formed by the same operations, so it gives
+// the elastic kernels' results at vs = 0 while moving about a fifth fewer
+// bytes forward and a quarter fewer in reverse. Reverse step (gather form of the
 // transpose): adjoint-stress kernel (updates the velocity adjoints from the
 // stress adjoints), residual injection, adjoint-velocity kernel. Away from the
 // surface the transposes are (Dx+)^T = -Dx-, (Dx-)^T = -Dx+ (and along z); on the
@@ -180,15 +186,17 @@ __device__ __forceinline__ float cpml_p(float* psi, size_t k, float G, float a, 
 // All global loads of a thread (staging, then its cells' operands and memory
 // variables) are issued before its first store.
 // ---------------------------------------------------------------------------
+template <bool kFluid>
 __global__ __launch_bounds__(256) void el_vel_kernel(ElStep a) {
-  __shared__ float sb[3][kElBox];
+  constexpr int NF = kFluid ? 2 : 3;
+  __shared__ float sb[NF][kElBox];
   const ElTile T = el_tile(a);
   const int NX = a.NX, NZ = a.NZ;
   const size_t plane = (size_t)NX * NZ;
   const size_t so = (size_t)T.shot * plane;
   {
     const float* src[3] = {a.txx + so, a.tzz + so, a.txz + so};
-    el_stage<3>(sb, src, T.x0, T.z0, NX, NZ);
+    el_stage<NF>(sb, src, T.x0, T.z0, NX, NZ);
   }
   const ElCells C(T, NX);
   const float axh = a.axh[C.ic], bxh = a.bxh[C.ic], axi = a.axi[C.ic], bxi = a.bxi[C.ic];
@@ -209,12 +217,12 @@ __global__ __launch_bounds__(256) void el_vel_kernel(ElStep a) {
     azh[r] = a.azh[jc];
     bzh[r] = a.bzh[jc];
     p0[r] = wxh ? a.ps[0][so + k] : 0.0f;
-    p1[r] = azi[r] != 0.0f ? a.ps[1][so + k] : 0.0f;
-    p2[r] = wxi ? a.ps[2][so + k] : 0.0f;
+    p1[r] = !kFluid && azi[r] != 0.0f ? a.ps[1][so + k] : 0.0f;
+    p2[r] = !kFluid && wxi ? a.ps[2][so + k] : 0.0f;
     p3[r] = azh[r] != 0.0f ? a.ps[3][so + k] : 0.0f;
   }
   __syncthreads();
-  const Box txx{sb[0], T.x0, T.z0}, tzz{sb[1], T.x0, T.z0}, txz{sb[2], T.x0, T.z0};
+  const Box txx{sb[0], T.x0, T.z0}, tzz{sb[1], T.x0, T.z0}, txz{sb[NF - 1], T.x0, T.z0};
   const int i = C.i;
   const float ih = a.ih;
 #pragma unroll
@@ -223,13 +231,15 @@ __global__ __launch_bounds__(256) void el_vel_kernel(ElStep a) {
     if (i >= NX || j >= NZ) continue;
     const size_t k = (size_t)j * NX + i;
     const float Ga = bdxp(txx, i, j) * ih;
-    const float Gb = bdz_txz(txz, i, j, a.fs) * ih;
-    const float Gc = bdxm(txz, i, j) * ih;
     const float Gd = bdz_tzz(tzz, i, j, a.fs) * ih;
-    const float fvx = cpml_p(a.ps[0] + so, k, Ga, axh, bxh, p0[r], true) +
-                      cpml_p(a.ps[1] + so, k, Gb, azi[r], bzi[r], p1[r], true);
-    const float fvz = cpml_p(a.ps[2] + so, k, Gc, axi, bxi, p2[r], true) +
-                      cpml_p(a.ps[3] + so, k, Gd, azh[r], bzh[r], p3[r], true);
+    float fvx = cpml_p(a.ps[0] + so, k, Ga, axh, bxh, p0[r], true);
+    float fvz = cpml_p(a.ps[3] + so, k, Gd, azh[r], bzh[r], p3[r], true);
+    if (!kFluid) {
+      const float Gb = bdz_txz(txz, i, j, a.fs) * ih;
+      const float Gc = bdxm(txz, i, j) * ih;
+      fvx = fvx + cpml_p(a.ps[1] + so, k, Gb, azi[r], bzi[r], p1[r], true);
+      fvz = cpml_p(a.ps[2] + so, k, Gc, axi, bxi, p2[r], true) + fvz;
+    }
     a.vx[so + k] = fmaf(a.dt * cbx[r], fvx, ovx[r]);
     a.vz[so + k] = fmaf(a.dt * cbz[r], fvz, ovz[r]);
     if (a.tr[0]) {
@@ -254,6 +264,7 @@ __global__ void el_record_kernel(ElStep a) {
 // ---------------------------------------------------------------------------
 // forward: stress update and explosive source
 // ---------------------------------------------------------------------------
+template <bool kFluid>
 __global__ __launch_bounds__(256) void el_str_kernel(ElStep a) {
   __shared__ float sb[2][kElBox];
   const ElTile T = el_tile(a);
@@ -277,18 +288,18 @@ __global__ __launch_bounds__(256) void el_str_kernel(ElStep a) {
     const size_t k = (size_t)jc * NX + C.ic;
     otxx[r] = a.txx[so + k];
     otzz[r] = a.tzz[so + k];
-    otxz[r] = a.txz[so + k];
+    otxz[r] = kFluid ? 0.0f : a.txz[so + k];
     cxx_x[r] = a.cxx_x[k];
     cxx_z[r] = a.cxx_z[k];
-    mxz[r] = a.mxz[k];
+    mxz[r] = kFluid ? 0.0f : a.mxz[k];
     azi[r] = a.azi[jc];
     bzi[r] = a.bzi[jc];
     azh[r] = a.azh[jc];
     bzh[r] = a.bzh[jc];
     p4[r] = wxi ? a.ps[4][so + k] : 0.0f;
     p5[r] = azi[r] != 0.0f ? a.ps[5][so + k] : 0.0f;
-    p6[r] = azh[r] != 0.0f ? a.ps[6][so + k] : 0.0f;
-    p7[r] = wxh ? a.ps[7][so + k] : 0.0f;
+    p6[r] = !kFluid && azh[r] != 0.0f ? a.ps[6][so + k] : 0.0f;
+    p7[r] = !kFluid && wxh ? a.ps[7][so + k] : 0.0f;
   }
   const int src = a.src_cell[shot];
   const float sw = a.w * a.wavelet[(size_t)shot * a.nt + a.n];
@@ -303,12 +314,8 @@ __global__ __launch_bounds__(256) void el_str_kernel(ElStep a) {
     const size_t k = (size_t)j * NX + i;
     const float Ge = bdxm(vx, i, j) * ih;
     const float Gf = bdz_vz(vz, i, j, a.fs) * ih;
-    const float Gg = bdz_vx(vx, i, j, a.fs) * ih;
-    const float Gh = bdxp(vz, i, j) * ih;
     const float exx = cpml_p(a.ps[4] + so, k, Ge, axi, bxi, p4[r], true);
     const float ezz = cpml_p(a.ps[5] + so, k, Gf, azi[r], bzi[r], p5[r], true);
-    const float exz = cpml_p(a.ps[6] + so, k, Gg, azh[r], bzh[r], p6[r], true) +
-                      cpml_p(a.ps[7] + so, k, Gh, axh, bxh, p7[r], true);
     float txx = otxx[r] + dt * fmaf(cxx_x[r], exx, cxx_z[r] * ezz);
     float tzz = otzz[r] + dt * fmaf(cxx_z[r], exx, czz_z(a, j, cxx_x[r]) * ezz);
     if ((int)k == src) {
@@ -317,11 +324,17 @@ __global__ __launch_bounds__(256) void el_str_kernel(ElStep a) {
     }
     a.txx[so + k] = txx;
     a.tzz[so + k] = tzz;
-    a.txz[so + k] = fmaf(dt * mxz[r], exz, otxz[r]);
     if (a.tr[2]) {
       a.tr[2][so + k] = exx;
       a.tr[3][so + k] = ezz;
-      a.tr[4][so + k] = exz;
+    }
+    if (!kFluid) {
+      const float Gg = bdz_vx(vx, i, j, a.fs) * ih;
+      const float Gh = bdxp(vz, i, j) * ih;
+      const float exz = cpml_p(a.ps[6] + so, k, Gg, azh[r], bzh[r], p6[r], true) +
+                        cpml_p(a.ps[7] + so, k, Gh, axh, bxh, p7[r], true);
+      a.txz[so + k] = fmaf(dt * mxz[r], exz, otxz[r]);
+      if (a.tr[2]) a.tr[4][so + k] = exz;
     }
   }
 }
@@ -378,6 +391,7 @@ __device__ __forceinline__ int el_own_cell(int r) {
 struct AdjS {
   float txx, tzz, txz, cxx_x, czz_x, cxx_z, czz_z, mxz, ax, az, azh, axh, q4, q5, q6, q7;
 };
+template <bool kFluid>
 __device__ __forceinline__ void adj_s_load(const ElStep& a, size_t so, int e, bool valid, int x0,
                                            int z0, AdjS& v) {
   const int r = e / kElBW, c = e - (e / kElBW) * kElBW;
@@ -387,21 +401,21 @@ __device__ __forceinline__ void adj_s_load(const ElStep& a, size_t so, int e, bo
   const int cx = ok ? gx : 0, cz = ok ? gz : 0;
   v.txx = ldz(a.txx + so, q, ok, a.txx);
   v.tzz = ldz(a.tzz + so, q, ok, a.tzz);
-  v.txz = ldz(a.txz + so, q, ok, a.txz);
+  v.txz = kFluid ? 0.0f : ldz(a.txz + so, q, ok, a.txz);
   v.cxx_x = ldz(a.cxx_x, q, ok, a.cxx_x);
   v.cxx_z = ldz(a.cxx_z, q, ok, a.cxx_z);
   v.czz_x = v.cxx_z;
   v.czz_z = czz_z(a, gz, v.cxx_x);
-  v.mxz = ldz(a.mxz, q, ok, a.mxz);
+  v.mxz = kFluid ? 0.0f : ldz(a.mxz, q, ok, a.mxz);
   v.ax = ldz(a.axi, cx, ok, a.axi);
   v.az = ldz(a.azi, cz, ok, a.azi);
-  v.azh = ldz(a.azh, cz, ok, a.azh);
-  v.axh = ldz(a.axh, cx, ok, a.axh);
+  v.azh = kFluid ? 0.0f : ldz(a.azh, cz, ok, a.azh);
+  v.axh = kFluid ? 0.0f : ldz(a.axh, cx, ok, a.axh);
   // memory variables only where a wave has a C-PML cell (wave-uniform branch)
   v.q4 = __any(v.ax != 0.0f) ? ldz(a.ps_in[4] + so, q, ok, a.ps_in[4]) : 0.0f;
   v.q5 = __any(v.az != 0.0f) ? ldz(a.ps_in[5] + so, q, ok, a.ps_in[5]) : 0.0f;
-  v.q6 = __any(v.azh != 0.0f) ? ldz(a.ps_in[6] + so, q, ok, a.ps_in[6]) : 0.0f;
-  v.q7 = __any(v.axh != 0.0f) ? ldz(a.ps_in[7] + so, q, ok, a.ps_in[7]) : 0.0f;
+  v.q6 = !kFluid && __any(v.azh != 0.0f) ? ldz(a.ps_in[6] + so, q, ok, a.ps_in[6]) : 0.0f;
+  v.q7 = !kFluid && __any(v.axh != 0.0f) ? ldz(a.ps_in[7] + so, q, ok, a.ps_in[7]) : 0.0f;
 }
 // ebar of the three stress-step inputs: dt (stress coefficients) x (stress adjoints)
 __device__ __forceinline__ float adj_ex(const AdjS& v, float dt) {
@@ -415,16 +429,21 @@ __device__ __forceinline__ float adj_exz(const AdjS& v, float dt) { return dt * 
 // derivative-input adjoints gbe (exx input), gbf (ezz), gbg (Dz vx of exz),
 // gbh (Dx vz of exz) of box cell e (outside the grid every operand is 0, so
 // every value is 0 too)
+template <bool kFluid>
 __device__ __forceinline__ void adj_s_put(float (*sb)[kElBox], int e, float dt, const AdjS& v) {
-  const float e1 = adj_ex(v, dt), e2 = adj_ez(v, dt), e3 = adj_exz(v, dt);
+  const float e1 = adj_ex(v, dt), e2 = adj_ez(v, dt);
   sb[0][e] = v.ax == 0.0f ? e1 : fmaf(v.ax, v.q4 + e1, e1);
   sb[1][e] = v.az == 0.0f ? e2 : fmaf(v.az, v.q5 + e2, e2);
-  sb[2][e] = v.azh == 0.0f ? e3 : fmaf(v.azh, v.q6 + e3, e3);
-  sb[3][e] = v.axh == 0.0f ? e3 : fmaf(v.axh, v.q7 + e3, e3);
+  if (!kFluid) {
+    const float e3 = adj_exz(v, dt);
+    sb[2][e] = v.azh == 0.0f ? e3 : fmaf(v.azh, v.q6 + e3, e3);
+    sb[3][e] = v.axh == 0.0f ? e3 : fmaf(v.axh, v.q7 + e3, e3);
+  }
 }
 
+template <bool kFluid>
 __global__ __launch_bounds__(256) void el_adj_s_kernel(ElStep a) {
-  __shared__ float sb[4][kElBox];
+  __shared__ float sb[kFluid ? 2 : 4][kElBox];
   const ElTile T = el_tile(a);
   const int NX = a.NX, NZ = a.NZ;
   const size_t plane = (size_t)NX * NZ;
@@ -434,17 +453,19 @@ __global__ __launch_bounds__(256) void el_adj_s_kernel(ElStep a) {
 #pragma unroll
   for (int k = 0; k < kElKH; ++k) {
     const int h = (int)threadIdx.x + k * kThreads;
-    adj_s_load(a, so, h < kElHalo ? el_halo_cell(h) : 0, h < kElHalo, T.x0, T.z0, hv[k]);
+    adj_s_load<kFluid>(a, so, h < kElHalo ? el_halo_cell(h) : 0, h < kElHalo, T.x0, T.z0,
+                       hv[k]);
   }
 #pragma unroll
-  for (int r = 0; r < kElRZ; ++r) adj_s_load(a, so, el_own_cell(r), true, T.x0, T.z0, ov[r]);
+  for (int r = 0; r < kElRZ; ++r)
+    adj_s_load<kFluid>(a, so, el_own_cell(r), true, T.x0, T.z0, ov[r]);
 #pragma unroll
   for (int k = 0; k < kElKH; ++k) {
     const int h = (int)threadIdx.x + k * kThreads;
-    if (h < kElHalo) adj_s_put(sb, el_halo_cell(h), dt, hv[k]);
+    if (h < kElHalo) adj_s_put<kFluid>(sb, el_halo_cell(h), dt, hv[k]);
   }
 #pragma unroll
-  for (int r = 0; r < kElRZ; ++r) adj_s_put(sb, el_own_cell(r), dt, ov[r]);
+  for (int r = 0; r < kElRZ; ++r) adj_s_put<kFluid>(sb, el_own_cell(r), dt, ov[r]);
   const ElCells C(T, NX);
   const float bxi = a.bxi[C.ic], bxh = a.bxh[C.ic];
   const bool gacc = !a.g_init;
@@ -460,15 +481,15 @@ __global__ __launch_bounds__(256) void el_adj_s_kernel(ElStep a) {
     bzh[r] = a.bzh[jc];
     fexx[r] = a.trc[2][so + k];
     fezz[r] = a.trc[3][so + k];
-    fexz[r] = a.trc[4][so + k];
+    fexz[r] = kFluid ? 0.0f : a.trc[4][so + k];
     g0[r] = gacc ? a.g[0][so + k] : 0.0f;
-    g1[r] = gacc ? a.g[1][so + k] : 0.0f;
-    g2[r] = gacc ? a.g[2][so + k] : 0.0f;
+    g1[r] = !kFluid && gacc ? a.g[1][so + k] : 0.0f;
+    g2[r] = !kFluid && gacc ? a.g[2][so + k] : 0.0f;
   }
   const float dml = a.fs ? a.dM_dl[C.ic] : 0.0f, dmm = a.fs ? a.dM_dm[C.ic] : 0.0f;
   __syncthreads();
-  const Box gbe{sb[0], T.x0, T.z0}, gbf{sb[1], T.x0, T.z0}, gbg{sb[2], T.x0, T.z0},
-      gbh{sb[3], T.x0, T.z0};
+  const Box gbe{sb[0], T.x0, T.z0}, gbf{sb[1], T.x0, T.z0}, gbg{sb[kFluid ? 0 : 2], T.x0, T.z0},
+      gbh{sb[kFluid ? 1 : 3], T.x0, T.z0};
   const int i = C.i;
 #pragma unroll
   for (int r = 0; r < kElRZ; ++r) {
@@ -476,21 +497,28 @@ __global__ __launch_bounds__(256) void el_adj_s_kernel(ElStep a) {
     if (i >= NX || j >= NZ) continue;
     const size_t k = (size_t)j * NX + i;
     // Vx += (Dx-)^T gbe + (Dz+ of vx)^T gbg ;  (Dx-)^T = -Dx+
+    // (the exz terms are absent in a fluid)
     const float dxe = -fmaf(C2, gbe(i + 2, j) - gbe(i - 1, j), C1 * (gbe(i + 1, j) - gbe(i, j)));
-    const float dzg = dzT(a, 2, j, [&](int jj) { return gbg(i, jj); }, true);
     // Vz += (Dz- of vz)^T gbf + (Dx+)^T gbh ;  (Dx+)^T = -Dx-
     const float dzf = dzT(a, 3, j, [&](int jj) { return gbf(i, jj); }, false);
-    const float dxh = -fmaf(C2, gbh(i + 1, j) - gbh(i - 2, j), C1 * (gbh(i, j) - gbh(i - 1, j)));
-    a.vx[so + k] = ovx[r] + (dxe + dzg) * ih;
-    a.vz[so + k] = ovz[r] + (dzf + dxh) * ih;
+    if (kFluid) {
+      a.vx[so + k] = ovx[r] + dxe * ih;
+      a.vz[so + k] = ovz[r] + dzf * ih;
+    } else {
+      const float dzg = dzT(a, 2, j, [&](int jj) { return gbg(i, jj); }, true);
+      const float dxh =
+          -fmaf(C2, gbh(i + 1, j) - gbh(i - 2, j), C1 * (gbh(i, j) - gbh(i - 1, j)));
+      a.vx[so + k] = ovx[r] + (dxe + dzg) * ih;
+      a.vz[so + k] = ovz[r] + (dzf + dxh) * ih;
+    }
 
     // own cell: memory-variable adjoints and the coefficient gradients
     const AdjS& v = ov[r];
     const float ex = adj_ex(v, dt), ez = adj_ez(v, dt), exz = adj_exz(v, dt);
     if (v.ax != 0.0f) a.ps_out[4][so + k] = bxi * (v.q4 + ex);
     if (v.az != 0.0f) a.ps_out[5][so + k] = bzi[r] * (v.q5 + ez);
-    if (v.azh != 0.0f) a.ps_out[6][so + k] = bzh[r] * (v.q6 + exz);
-    if (v.axh != 0.0f) a.ps_out[7][so + k] = bxh * (v.q7 + exz);
+    if (!kFluid && v.azh != 0.0f) a.ps_out[6][so + k] = bzh[r] * (v.q6 + exz);
+    if (!kFluid && v.axh != 0.0f) a.ps_out[7][so + k] = bxh * (v.q7 + exz);
     float glam, gmu;
     if (a.fs && j == 0) {
       // txx += dt M exx with M = 4 mu (lambda + mu) / (lambda + 2 mu)
@@ -501,15 +529,21 @@ __global__ __launch_bounds__(256) void el_adj_s_kernel(ElStep a) {
       glam = dt * (v.txx + v.tzz) * (fexx[r] + fezz[r]);
       gmu = 2.0f * dt * fmaf(v.txx, fexx[r], v.tzz * fezz[r]);
     }
+    // a fluid has no mu partials (the gradient finish weighs them by vs = 0;
+    // their planes stay zero)
     const float gmxz = dt * v.txz * fexz[r];
     if (a.g_init) {
       a.g[0][so + k] = glam;
-      a.g[1][so + k] = gmu;
-      a.g[2][so + k] = gmxz;
+      if (!kFluid) {
+        a.g[1][so + k] = gmu;
+        a.g[2][so + k] = gmxz;
+      }
     } else {
       a.g[0][so + k] = g0[r] + glam;
-      a.g[1][so + k] = g1[r] + gmu;
-      a.g[2][so + k] = g2[r] + gmxz;
+      if (!kFluid) {
+        a.g[1][so + k] = g1[r] + gmu;
+        a.g[2][so + k] = g2[r] + gmxz;
+      }
     }
   }
 }
@@ -543,6 +577,7 @@ __global__ void el_inject_kernel(ElStep a, int n) {
 struct AdjV {
   float vx, vz, bx, bz, axh, az, ax, azh, q0, q1, q2, q3;
 };
+template <bool kFluid>
 __device__ __forceinline__ void adj_v_load(const ElStep& a, size_t so, int e, bool valid, int x0,
                                            int z0, AdjV& v) {
   const int r = e / kElBW, c = e - (e / kElBW) * kElBW;
@@ -555,27 +590,32 @@ __device__ __forceinline__ void adj_v_load(const ElStep& a, size_t so, int e, bo
   v.bx = ldz(a.bx, q, ok, a.bx);
   v.bz = ldz(a.bz, q, ok, a.bz);
   v.axh = ldz(a.axh, cx, ok, a.axh);
-  v.az = ldz(a.azi, cz, ok, a.azi);
-  v.ax = ldz(a.axi, cx, ok, a.axi);
+  v.az = kFluid ? 0.0f : ldz(a.azi, cz, ok, a.azi);
+  v.ax = kFluid ? 0.0f : ldz(a.axi, cx, ok, a.axi);
   v.azh = ldz(a.azh, cz, ok, a.azh);
   v.q0 = __any(v.axh != 0.0f) ? ldz(a.ps_in[0] + so, q, ok, a.ps_in[0]) : 0.0f;
-  v.q1 = __any(v.az != 0.0f) ? ldz(a.ps_in[1] + so, q, ok, a.ps_in[1]) : 0.0f;
-  v.q2 = __any(v.ax != 0.0f) ? ldz(a.ps_in[2] + so, q, ok, a.ps_in[2]) : 0.0f;
+  v.q1 = !kFluid && __any(v.az != 0.0f) ? ldz(a.ps_in[1] + so, q, ok, a.ps_in[1]) : 0.0f;
+  v.q2 = !kFluid && __any(v.ax != 0.0f) ? ldz(a.ps_in[2] + so, q, ok, a.ps_in[2]) : 0.0f;
   v.q3 = __any(v.azh != 0.0f) ? ldz(a.ps_in[3] + so, q, ok, a.ps_in[3]) : 0.0f;
 }
 // derivative-input adjoints of the velocity step: gba (Dx txx of vx), gbb (Dz
 // txz of vx), gbc (Dx txz of vz), gbd (Dz tzz of vz)
+// (a fluid keeps gba and gbd only, in planes 0 and 1)
+template <bool kFluid>
 __device__ __forceinline__ void adj_v_put(float (*sb)[kElBox], int e, float dt, const AdjV& v) {
   const float kx = dt * v.bx * v.vx;
   const float kz = dt * v.bz * v.vz;
   sb[0][e] = v.axh == 0.0f ? kx : fmaf(v.axh, v.q0 + kx, kx);
-  sb[1][e] = v.az == 0.0f ? kx : fmaf(v.az, v.q1 + kx, kx);
-  sb[2][e] = v.ax == 0.0f ? kz : fmaf(v.ax, v.q2 + kz, kz);
-  sb[3][e] = v.azh == 0.0f ? kz : fmaf(v.azh, v.q3 + kz, kz);
+  sb[kFluid ? 1 : 3][e] = v.azh == 0.0f ? kz : fmaf(v.azh, v.q3 + kz, kz);
+  if (!kFluid) {
+    sb[1][e] = v.az == 0.0f ? kx : fmaf(v.az, v.q1 + kx, kx);
+    sb[2][e] = v.ax == 0.0f ? kz : fmaf(v.ax, v.q2 + kz, kz);
+  }
 }
 
+template <bool kFluid>
 __global__ __launch_bounds__(256) void el_adj_v_kernel(ElStep a) {
-  __shared__ float sb[4][kElBox];
+  __shared__ float sb[kFluid ? 2 : 4][kElBox];
   const ElTile T = el_tile(a);
   const int NX = a.NX, NZ = a.NZ;
   const size_t plane = (size_t)NX * NZ;
@@ -585,17 +625,19 @@ __global__ __launch_bounds__(256) void el_adj_v_kernel(ElStep a) {
 #pragma unroll
   for (int k = 0; k < kElKH; ++k) {
     const int h = (int)threadIdx.x + k * kThreads;
-    adj_v_load(a, so, h < kElHalo ? el_halo_cell(h) : 0, h < kElHalo, T.x0, T.z0, hv[k]);
+    adj_v_load<kFluid>(a, so, h < kElHalo ? el_halo_cell(h) : 0, h < kElHalo, T.x0, T.z0,
+                       hv[k]);
   }
 #pragma unroll
-  for (int r = 0; r < kElRZ; ++r) adj_v_load(a, so, el_own_cell(r), true, T.x0, T.z0, ov[r]);
+  for (int r = 0; r < kElRZ; ++r)
+    adj_v_load<kFluid>(a, so, el_own_cell(r), true, T.x0, T.z0, ov[r]);
 #pragma unroll
   for (int k = 0; k < kElKH; ++k) {
     const int h = (int)threadIdx.x + k * kThreads;
-    if (h < kElHalo) adj_v_put(sb, el_halo_cell(h), dt, hv[k]);
+    if (h < kElHalo) adj_v_put<kFluid>(sb, el_halo_cell(h), dt, hv[k]);
   }
 #pragma unroll
-  for (int r = 0; r < kElRZ; ++r) adj_v_put(sb, el_own_cell(r), dt, ov[r]);
+  for (int r = 0; r < kElRZ; ++r) adj_v_put<kFluid>(sb, el_own_cell(r), dt, ov[r]);
   const ElCells C(T, NX);
   const float bxh = a.bxh[C.ic], bxi = a.bxi[C.ic];
   const bool gacc = !a.g_init;
@@ -607,7 +649,7 @@ __global__ __launch_bounds__(256) void el_adj_v_kernel(ElStep a) {
     const size_t k = (size_t)jc * NX + C.ic;
     otxx[r] = a.txx[so + k];
     otzz[r] = a.tzz[so + k];
-    otxz[r] = a.txz[so + k];
+    otxz[r] = kFluid ? 0.0f : a.txz[so + k];
     bzi[r] = a.bzi[jc];
     bzh[r] = a.bzh[jc];
     f0[r] = a.trc[0][so + k];
@@ -616,8 +658,8 @@ __global__ __launch_bounds__(256) void el_adj_v_kernel(ElStep a) {
     g4[r] = gacc ? a.g[4][so + k] : 0.0f;
   }
   __syncthreads();
-  const Box gba{sb[0], T.x0, T.z0}, gbb{sb[1], T.x0, T.z0}, gbc{sb[2], T.x0, T.z0},
-      gbd{sb[3], T.x0, T.z0};
+  const Box gba{sb[0], T.x0, T.z0}, gbb{sb[1], T.x0, T.z0}, gbc{sb[kFluid ? 0 : 2], T.x0, T.z0},
+      gbd{sb[kFluid ? 1 : 3], T.x0, T.z0};
   const int i = C.i;
 #pragma unroll
   for (int r = 0; r < kElRZ; ++r) {
@@ -626,20 +668,24 @@ __global__ __launch_bounds__(256) void el_adj_v_kernel(ElStep a) {
     const size_t k = (size_t)j * NX + i;
     // Txx += (Dx+)^T gba = -Dx- gba
     const float dxa = -fmaf(C2, gba(i + 1, j) - gba(i - 2, j), C1 * (gba(i, j) - gba(i - 1, j)));
-    // Txz += (Dz- of txz)^T gbb + (Dx-)^T gbc = ... - Dx+ gbc
-    const float dzb = dzT(a, 1, j, [&](int jj) { return gbb(i, jj); }, false);
-    const float dxc = -fmaf(C2, gbc(i + 2, j) - gbc(i - 1, j), C1 * (gbc(i + 1, j) - gbc(i, j)));
     // Tzz += (Dz+ of tzz)^T gbd
     const float dzd = dzT(a, 0, j, [&](int jj) { return gbd(i, jj); }, true);
     a.txx[so + k] = otxx[r] + dxa * ih;
-    a.txz[so + k] = otxz[r] + (dzb + dxc) * ih;
     a.tzz[so + k] = otzz[r] + dzd * ih;
+    if (!kFluid) {
+      // Txz += (Dz- of txz)^T gbb + (Dx-)^T gbc = ... - Dx+ gbc (a fluid's txz
+      // adjoint reaches nothing: its only use is weighed by mu = 0)
+      const float dzb = dzT(a, 1, j, [&](int jj) { return gbb(i, jj); }, false);
+      const float dxc =
+          -fmaf(C2, gbc(i + 2, j) - gbc(i - 1, j), C1 * (gbc(i + 1, j) - gbc(i, j)));
+      a.txz[so + k] = otxz[r] + (dzb + dxc) * ih;
+    }
 
     const AdjV& v = ov[r];
     const float kx = dt * v.bx * v.vx, kz = dt * v.bz * v.vz;
     if (v.axh != 0.0f) a.ps_out[0][so + k] = bxh * (v.q0 + kx);
-    if (v.az != 0.0f) a.ps_out[1][so + k] = bzi[r] * (v.q1 + kx);
-    if (v.ax != 0.0f) a.ps_out[2][so + k] = bxi * (v.q2 + kz);
+    if (!kFluid && v.az != 0.0f) a.ps_out[1][so + k] = bzi[r] * (v.q1 + kx);
+    if (!kFluid && v.ax != 0.0f) a.ps_out[2][so + k] = bxi * (v.q2 + kz);
     if (v.azh != 0.0f) a.ps_out[3][so + k] = bzh[r] * (v.q3 + kz);
     const float gbx = dt * v.vx * f0[r];
     const float gbz = dt * v.vz * f1[r];
@@ -859,11 +905,17 @@ int el_launch_prep(const float* model, const ElCoef& c, int nx, int nz, int P, i
 
 int el_launch_fwd(const ElStep& a, hipStream_t s, hipEvent_t* ev) {
   if (ev) SWEEP_HIP(hipEventRecord(ev[0], s));
-  hipLaunchKernelGGL(el_vel_kernel, grid_of(a), dim3(256), 0, s, a);
+  if (a.fluid)
+    hipLaunchKernelGGL(el_vel_kernel<true>, grid_of(a), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(el_vel_kernel<false>, grid_of(a), dim3(256), 0, s, a);
   if (a.gathers && a.nrec > 0)
     hipLaunchKernelGGL(el_record_kernel, dim3((a.nshots * a.nrec + 255) / 256), dim3(256), 0, s,
                        a);
-  hipLaunchKernelGGL(el_str_kernel, grid_of(a), dim3(256), 0, s, a);
+  if (a.fluid)
+    hipLaunchKernelGGL(el_str_kernel<true>, grid_of(a), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(el_str_kernel<false>, grid_of(a), dim3(256), 0, s, a);
   if (ev) SWEEP_HIP(hipEventRecord(ev[1], s));
   SWEEP_HIP(hipGetLastError());
   return SWEEP_OK;
@@ -871,11 +923,17 @@ int el_launch_fwd(const ElStep& a, hipStream_t s, hipEvent_t* ev) {
 
 int el_launch_adj(const ElStep& a, hipStream_t s, hipEvent_t* ev) {
   if (ev) SWEEP_HIP(hipEventRecord(ev[0], s));
-  hipLaunchKernelGGL(el_adj_s_kernel, grid_of(a), dim3(256), 0, s, a);
+  if (a.fluid)
+    hipLaunchKernelGGL(el_adj_s_kernel<true>, grid_of(a), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(el_adj_s_kernel<false>, grid_of(a), dim3(256), 0, s, a);
   if (a.nrec > 0)
     hipLaunchKernelGGL(el_inject_kernel, dim3((a.nshots * a.nrec + 255) / 256), dim3(256), 0, s,
                        a, a.n);
-  hipLaunchKernelGGL(el_adj_v_kernel, grid_of(a), dim3(256), 0, s, a);
+  if (a.fluid)
+    hipLaunchKernelGGL(el_adj_v_kernel<true>, grid_of(a), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(el_adj_v_kernel<false>, grid_of(a), dim3(256), 0, s, a);
   if (ev) SWEEP_HIP(hipEventRecord(ev[1], s));
   SWEEP_HIP(hipGetLastError());
   return SWEEP_OK;

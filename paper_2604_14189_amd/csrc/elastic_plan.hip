@@ -170,6 +170,7 @@ ElStep step_base(const sweep_plan* p, void* work, const ElLayout& L, const ElCoe
   a.nrec = p->pb.nrec;
   a.nshots = p->pb.nshots;
   a.fs = p->pb.free_surface;
+  a.fluid = p->pb.physics == SWEEP_ACOUSTIC_VD;
   a.dt = (float)p->pb.dt;
   a.w = (float)(p->pb.dt / (p->pb.h * p->pb.h));
   a.ih = (float)(1.0 / p->pb.h);
@@ -297,6 +298,10 @@ int el_backward(sweep_plan* p, const float* resid, float* grad, void* work, size
   double* tot = at<double>(work, L.tot);
   if ((rc = launch_fill(adj, kAdjPlanes * nsplane, 0.0f, s))) return rc;
   if ((rc = launch_fill_f64(tot, kGradPlanes * L.plane, 0.0, s))) return rc;
+  // the fluid kernels write no mu partials (planes 1 and 2): they fold as zeros
+  if (pb.physics == SWEEP_ACOUSTIC_VD &&
+      (rc = launch_fill(gpart + nsplane, 2 * nsplane, 0.0f, s)))
+    return rc;
 
   ElStep fbase = step_base(p, work, L, c);
   set_state(fbase, st, nsplane);
