@@ -505,12 +505,15 @@ def encoded_gradient(sw, torch, nsuper=8):
             "Gcell_per_s": round(cells / t / 1e9, 2)}
 
 
-def acoustic_vd_gradient(sw, torch):
+def acoustic_vd_gradient(sw, torch, nt=0):
     """First-order variable-density acoustic FWI gradient (vp, rho) on the
-    1000x300 layered workload (64 shots, 3000 steps, 40-cell C-PML), with
-    rho = 310 vp^0.25: the staggered kernels' fluid variants (vs = 0)."""
+    1000x300 layered workload (64 shots, 3000 steps (nt > 0: that many, for
+    profiling), 40-cell C-PML), with rho = 310 vp^0.25: the staggered kernels'
+    fluid variants (vs = 0)."""
     import synth
     w = synth.workload(WORKLOAD)
+    if nt:
+        w = w.replace(nt=nt)
     vp = np.asarray(w.true_model(), np.float32)
     model = torch.tensor(np.stack([vp, 310.0 * vp ** 0.25]), dtype=torch.float32, device="cuda")
     m0 = torch.tensor(np.stack([synth.smooth(c, 20.0) for c in model.cpu().numpy()]),
@@ -808,7 +811,7 @@ def main():
         elif args.only == "elastic":
             res = elastic_gradient(sw, torch, args.nt)
         elif args.only == "acoustic_vd":
-            res = acoustic_vd_gradient(sw, torch)
+            res = acoustic_vd_gradient(sw, torch, args.nt)
         elif args.only == "encoded":
             res = encoded_gradient(sw, torch)
         elif args.only == "vti":
