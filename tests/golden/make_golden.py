@@ -28,6 +28,12 @@ VTI workload (the layered benchmark's grid, shots and receivers; eta up to
 0.12 below an isotropic top zone): 8 complete receiver traces and the
 (vv, v, eta) gradient for a band-limited seeded residual on that shot at
 20 000 sampled cells, with the norm of each gradient plane.
+
+vd1000x300_shot41.npz: shot 41 of the 1000x300 / 3000-step layered workload
+as a first-order variable-density acoustic problem (rho = 310 vp^0.25, the
+elastic oracle with vs = 0, no free surface): 8 complete (vx, vz) traces and
+the (vp, rho) gradient for a band-limited seeded residual on that shot at
+20 000 sampled cells, with the norm of each gradient plane.
 """
 import os
 import sys
@@ -97,6 +103,30 @@ def vti_shot23(path):
                         grad_norm=np.array([np.linalg.norm(g[c]) for c in range(3)]))
 
 
+def vd_shot41(path):
+    """First-order variable-density acoustic: the elastic oracle with vs = 0."""
+    w = synth.workload("layered1000x300")
+    s = 41
+    sl = slice(s, s + 1)
+    vp = f32(w.true_model())
+    rho = f32(310.0 * vp.astype(np.float64) ** 0.25)
+    model = np.stack([vp, np.zeros_like(vp), rho])
+    src, rec, wav = w.sources()[sl], w.receivers()[sl], f32(w.wavelets()[sl])
+    pb = oracle.problem(w.nx, w.nz, w.pml, w.h, w.dt, w.nt, w.pml_vmax(), w.f0, w.pml_R,
+                        nshots=1, nrec=w.nrec, ckpt_every=w.ckpt_every)
+    resid = f32(synth.bandlimited_noise((1, w.nt, w.nrec * 2), w.f0, w.dt, 41)
+                .reshape(1, w.nt, w.nrec, 2))
+    t = time.time()
+    g, _, d = oracle.el_gradient(pb, model, src, wav, rec, resid, want_gathers=True)
+    print("oracle variable-density gradient took %.1f s" % (time.time() - t), flush=True)
+    trace_idx = np.linspace(0, w.nrec - 1, 8).round().astype(np.int64)
+    cells = np.random.default_rng(41).choice(g[0].size, 20000, replace=False)
+    gvd = np.stack([g[0], g[2]])  # (vp, rho)
+    np.savez_compressed(path, shot=s, trace_idx=trace_idx, traces=d[0][:, trace_idx, :],
+                        grad_cells=cells, grad=np.stack([gvd[c].ravel()[cells] for c in range(2)]),
+                        grad_norm=np.array([np.linalg.norm(gvd[c]) for c in range(2)]))
+
+
 def batch_short_nt(m: int) -> int:
     """Shortened run of batched workload m (125 ... 250 steps)."""
     return 125 + int(round(125 * m / 7))
@@ -135,7 +165,7 @@ def batch_uneven8_short(path):
 
 if __name__ == "__main__":
     oracle.build(force=False)
-    which = sys.argv[1:] or ["layered", "elastic", "batch", "vti"]
+    which = sys.argv[1:] or ["layered", "elastic", "batch", "vti", "vd"]
     if "layered" in which:
         layered_shot37(os.path.join(HERE, "layered1000x300_shot37.npz"))
     if "elastic" in which:
@@ -144,3 +174,5 @@ if __name__ == "__main__":
         batch_uneven8_short(os.path.join(HERE, "batch_uneven8_short.npz"))
     if "vti" in which:
         vti_shot23(os.path.join(HERE, "vti1000x300_shot23.npz"))
+    if "vd" in which:
+        vd_shot41(os.path.join(HERE, "vd1000x300_shot41.npz"))

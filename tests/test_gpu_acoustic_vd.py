@@ -1,11 +1,16 @@
 """GPU parity: first-order variable-density acoustic (Eq. 1), computed by the
-staggered elastic kernels with vs = 0, against the FP64 oracle (the same
-scheme with vs = 0). Model (vp, rho), gathers (vx, vz), gradients (vp, rho).
+fluid variants of the staggered elastic kernels, against the FP64 oracle (the
+same scheme with vs = 0). Model (vp, rho), gathers (vx, vz), gradients (vp,
+rho).
 
 Tolerances as for the other physics: gathers <= 1e-5, gradients <= 1e-4
 relative L2. The mode must also give exactly the elastic plan's results for
-vs = 0 (the same kernels).
+vs = 0 (the fluid variants drop only terms that are products with mu = 0).
+The full 1000x300 / 3000-step workload with 64 shots (the benchmark's
+configuration) is checked on one shot against stored oracle values.
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -108,3 +113,45 @@ def test_vd_stored_segments_bitwise(sw, fs, keep):
     assert torch.equal(p.forward(m, wav, save=True), d0)
     assert torch.equal(p.backward(r), g0)
     assert torch.any(g0[0] != 0) and torch.any(g0[1] != 0)
+
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "vd1000x300_shot41.npz")
+
+
+@pytest.mark.skipif(not os.path.exists(GOLDEN), reason="golden file not generated")
+@pytest.mark.parametrize("stored", [False, True])
+def test_full_size_vd_sampled_shot(sw, stored):
+    """All 64 shots of the 1000x300 / 3000-step layered workload with rho =
+    310 vp^0.25; shot 41 compared with stored oracle traces and gradient
+    samples for a residual on that shot only. `stored`: the benchmark's
+    configuration, the traces of as many of the last checkpoint segments as
+    the free HBM holds, the others recomputed."""
+    gold = np.load(GOLDEN)
+    w = synth.workload("layered1000x300")
+    vp = f32(w.true_model())
+    model = np.stack([vp, f32(310.0 * vp.astype(np.float64) ** 0.25)])
+    plan = sw.Plan(nx=w.nx, nz=w.nz, h=w.h, dt=w.dt, nt=w.nt, pml=w.pml, src_xz=w.sources(),
+                   rec_xz=w.receivers(), pml_vmax=w.pml_vmax(), pml_f0=w.f0, pml_R=w.pml_R,
+                   ckpt_every=w.ckpt_every, physics=sw.ACOUSTIC_VD)
+    if stored:
+        import bench
+        keep = bench.fit_keep_b(torch, plan, w.nt, w.ckpt_every)
+        print("stored segments", keep, "of", -(-w.nt // w.ckpt_every), flush=True)
+        assert keep >= 1
+    d = plan.forward(_dev(model), _dev(w.wavelets()), save=True)
+    s = int(gold["shot"])
+    tr = torch.as_tensor(gold["trace_idx"], device="cuda")
+    e_d = rel_l2(_host(d[s][:, tr, :]), gold["traces"])
+    resid = np.zeros((w.nshots, w.nt, w.nrec, 2), np.float32)
+    resid[s] = f32(synth.bandlimited_noise((1, w.nt, w.nrec * 2), w.f0, w.dt, 41)
+                   .reshape(w.nt, w.nrec, 2))
+    g = _host(plan.backward(_dev(resid)))
+    cells = gold["grad_cells"]
+    errs = [rel_l2(g[c].ravel()[cells], gold["grad"][c]) for c in range(2)]
+    norms = [abs(np.linalg.norm(g[c]) / gold["grad_norm"][c] - 1.0) for c in range(2)]
+    print("full-size variable-density shot", s, "traces", e_d, "grad (vp, rho)", errs, "norms",
+          norms, flush=True)
+    plan.release_workspace()
+    assert e_d <= SEIS_TOL
+    assert max(errs) <= GRAD_TOL
+    assert max(norms) <= GRAD_TOL
