@@ -52,6 +52,43 @@ def _source_hash() -> str:
     return h.hexdigest()[:16]
 
 
+# FP64 oracle values for one shot of the headline workload (traces and sampled
+# gradient cells, written by tests/golden/make_golden.py from the oracle alone)
+GOLDEN = os.path.join(ROOT, "tests", "golden", "layered1000x300_shot37.npz")
+
+
+def oracle_parity(torch, plan, w, v_true, wav):
+    """The timed configuration (the same plan: tiling, stored segments and
+    workspace) against the stored oracle values of one shot: a forward on the
+    true model and the gradient for a band-limited residual on that shot only,
+    compared on complete receiver traces and 20 000 sampled gradient cells
+    (relative L2), outside the timed region."""
+    import synth
+    if not os.path.exists(GOLDEN):
+        return None
+    gold = np.load(GOLDEN)
+    s = int(gold["shot"])
+    d = plan.forward(v_true, wav, save=True)
+    tr = torch.as_tensor(gold["trace_idx"], device="cuda")
+    dt_ = d[s][:, tr].double().cpu().numpy()
+    resid = torch.zeros_like(d)
+    resid[s] = torch.tensor(
+        synth.bandlimited_noise((1, w.nt, w.nrec), w.f0, w.dt, s)[0].astype(np.float32),
+        device="cuda")
+    g = plan.backward(resid).double().cpu().numpy()[0]
+    cells = gold["grad_cells"]
+
+    def rel(a, b):
+        return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+    gn = float(gold["grad_norm"])
+    return {"shot": s, "traces_rel_l2": rel(dt_, gold["traces"]),
+            "gradient_rel_l2": rel(g.ravel()[cells], gold["grad"]),
+            "gradient_norm_rel": abs(float(np.linalg.norm(g)) - gn) / gn, "tolerance": 1e-4,
+            "reference": "FP64 oracle, tests/golden/layered1000x300_shot37.npz: 8 complete "
+                         "traces, 20 000 sampled gradient cells and the gradient norm"}
+
+
 def calibrate_copy(nbytes=1 << 30, reps=3):
     """A plain device-to-device copy of known size, for scaling the HBM byte
     counters (run under rocprofv3 --pmc)."""
@@ -868,6 +905,12 @@ def main():
     cell_updates = 2.0 * w.nshots * NX * NZ * w.nt
     value = cell_updates / dt / 1e9
     progress(f"headline: {args.steps} gradients, {dt:.3f} s each, {value:.1f} Gcell/s")
+    parity = None
+    if not args.nt:
+        parity = oracle_parity(torch, plan, w, v_true, wav)
+        if parity:
+            progress(f"oracle parity: traces {parity['traces_rel_l2']:.2e}, "
+                     f"gradient {parity['gradient_rel_l2']:.2e}")
     per_shot = None
     if args.per_shot_sample > 0:
         plan.release_workspace()
@@ -909,6 +952,7 @@ def main():
                    "ckpt_every": w.ckpt_every, "keep_b": keep, "rz": args.rz, "pml_rz": args.pml_rz, "tblock": args.tblock, "misfit_J": float(J.item())},
         "model_grid_value": round(value * w.nx * w.nz / (NX * NZ), 3),
         "roofline": roof,
+        "oracle_parity": parity,
         "per_shot": per_shot,
         "checkpoint_recompute": recompute,
         "kernels": kernels,
