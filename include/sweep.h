@@ -67,7 +67,7 @@ extern "C" {
  * gradients (vv, v, eta). pml_vmax must be at least the fastest horizontal
  * speed v sqrt(1 + 2 eta) (the Courant limit is the acoustic one); eta < 0 is
  * not supported (the scheme's two modes would not stay real). 64 x 16 tiles,
- * single steps: tuning.rz must stay 4, keep_b 0 and use_graph 0. The source
+ * single steps: tuning.rz must stay 4 and use_graph 0. The source
  * should sit where eta = 0, as the formulation asks (the paper's figure shows
  * the artificial mode it otherwise excites). */
 #define SWEEP_VTI 3
@@ -121,8 +121,14 @@ typedef struct {
                       nshots * NX * NZ fields plus the C-PML memory variables,
                       4 bytes each). Elastic and variable-density acoustic: the
                       five trace planes of each step, ckpt_every * 5 * nshots *
-                      NX * NZ * 4 bytes per segment. sweep_plan_workspace_bytes
-                      includes this. 0 = recompute every segment (default) */
+                      NX * NZ * 4 bytes per segment. VTI: the three trace
+                      planes of each step (Bx', Bz', D2x'D2z'G), ckpt_every * 3
+                      * nshots * NX * NZ * 4 bytes per segment, less its
+                      checkpoint slot (P^n, P^{n-1}, G^n, G^{n-1} in float64 and
+                      the C-PML memory variables). Elastic, variable-density and
+                      VTI stored segments need no checkpoint either.
+                      sweep_plan_workspace_bytes includes this. 0 = recompute
+                      every segment (default) */
 } sweep_tuning;
 
 typedef struct sweep_plan sweep_plan;

@@ -1165,8 +1165,8 @@ extern "C" int sweep_plan_set_tuning(sweep_plan* p, const sweep_tuning* t) try {
     set_error("unsupported tuning");
     return SWEEP_EINVAL;
   }
-  if (p->pb.physics == SWEEP_VTI && (t->rz != 4 || t->keep_b != 0 || t->use_graph != 0)) {
-    set_error("VTI plans take 64 x 16 tiles (rz 4), no stored segments and no graph capture");
+  if (p->pb.physics == SWEEP_VTI && (t->rz != 4 || t->use_graph != 0)) {
+    set_error("VTI plans take 64 x 16 tiles (rz 4) and no graph capture");
     return SWEEP_EINVAL;
   }
   p->tune = *t;

@@ -99,6 +99,8 @@ struct VtiLayout {
   int nseg;
   size_t slot_elems;  // checkpoint (floats): P^n, P^{n-1}, G^n, G^{n-1} (2 each), memory variables
   size_t ck, tr, lf[2], mf[2], adjaux[2], gpart, tot;
+  int nkeep;      // checkpoint segments (the last ones) whose traces the forward stores
+  size_t trkeep;  // their traces: [nkeep][k][3][nshots][NZ][NX]
   size_t bwd_end;
 };
 }  // namespace sweep

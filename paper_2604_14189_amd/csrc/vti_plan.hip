@@ -2,7 +2,9 @@
 // workspace layout, the forward time loop with checkpoints every k steps, and
 // the segment-wise recomputation (storing Bx', Bz' and D2x'D2z'G of each step)
 // and reverse sweep that accumulate dJ/d(cx, cz, cm), folded into FP64 per
-// segment and chained to dJ/d(vv, v, eta) at the end.
+// segment and chained to dJ/d(vv, v, eta) at the end. The last keep_b
+// segments are stored instead: the saving forward writes their traces and
+// skips their checkpoints, and the backward reverses them without recomputing.
 #include <algorithm>
 #include <cstring>
 #include <string>
@@ -57,17 +59,32 @@ void vti_layout(const sweep_plan* p, VtiLayout& L) {
   L.nseg = (p->pb.nt + k - 1) / k;
   // in floats: P^n, P^{n-1}, G^n, G^{n-1} (float64), memory variables
   L.slot_elems = 8 * ns * plane + L.aux_elems;
-  L.ck = take(off, (size_t)L.nseg * L.slot_elems * f);
+  // stored segments are never restored: only the others have a checkpoint
+  L.nkeep = std::min(std::max(p->tune.keep_b, 0), L.nseg);
+  L.ck = take(off, (size_t)(L.nseg - L.nkeep) * L.slot_elems * f);
   L.tr = take(off, (size_t)k * 3 * ns * plane * f);
   for (int i = 0; i < 2; ++i) L.lf[i] = take(off, ns * plane * f);
   for (int i = 0; i < 2; ++i) L.mf[i] = take(off, ns * plane * sizeof(double));
   for (int i = 0; i < 2; ++i) L.adjaux[i] = take(off, L.aux_elems * f);
   L.gpart = take(off, 3 * ns * plane * f);
   L.tot = take(off, 3 * plane * sizeof(double));
+  L.trkeep = take(off, (size_t)L.nkeep * k * 3 * ns * plane * f);
   L.bwd_end = off;
 }
 
 namespace {
+
+bool vti_kept(const VtiLayout& L, int sg) { return sg >= L.nseg - L.nkeep; }
+
+// Trace plane q of step m of segment sg: its stored block for a stored
+// segment, else the one segment buffer that the recomputation fills.
+float* vti_trace(void* work, const VtiLayout& L, size_t nsplane, int k, int sg, int m, int q) {
+  if (vti_kept(L, sg))
+    return reinterpret_cast<float*>(static_cast<char*>(work) + L.trkeep) +
+           (((size_t)(sg - (L.nseg - L.nkeep)) * k + m) * 3 + q) * nsplane;
+  return reinterpret_cast<float*>(static_cast<char*>(work) + L.tr) +
+         ((size_t)m * 3 + q) * nsplane;
+}
 
 VtiStep vti_base(const sweep_plan* p, void* work, const VtiLayout& L) {
   VtiStep a;
@@ -201,7 +218,7 @@ int vti_forward(sweep_plan* p, const float* model, const float* wavelet, float* 
   const int k = p->ckpt;
   int c = 0;
   for (int n = 0; n < pb.nt; ++n) {
-    if (save && n % k == 0) {
+    if (save && n % k == 0 && !vti_kept(L, n / k)) {
       float* slot = at<float>(work, L.ck) + (size_t)(n / k) * L.slot_elems;
       // P and G as raw bits: two floats per float64 value
       if ((rc = launch_copy(slot, at<float>(work, L.pf[c]), 2 * nsplane, s))) return rc;
@@ -214,7 +231,16 @@ int vti_forward(sweep_plan* p, const float* model, const float* wavelet, float* 
       if ((rc = launch_copy(slot + 8 * nsplane, at<float>(work, L.aux[n % 2]), L.aux_elems, s)))
         return rc;
     }
-    if ((rc = vti_fwd_step(p, work, L, n, c, gathers, nullptr, s, kFwdInt))) return rc;
+    // steps of a stored segment also write its traces (timed with the
+    // recomputation, whose work they do)
+    const int sg = n / k;
+    if (save && vti_kept(L, sg)) {
+      float* tr[3];
+      for (int q = 0; q < 3; ++q) tr[q] = vti_trace(work, L, nsplane, k, sg, n - sg * k, q);
+      if ((rc = vti_fwd_step(p, work, L, n, c, gathers, tr, s, kRecInt))) return rc;
+    } else if ((rc = vti_fwd_step(p, work, L, n, c, gathers, nullptr, s, kFwdInt))) {
+      return rc;
+    }
     c = 1 - c;
   }
   p->saved = save != 0;
@@ -247,26 +273,28 @@ int vti_backward(sweep_plan* p, const float* resid, float* grad, void* work, siz
     if ((rc = launch_fill(at<float>(work, L.mf[i]), 2 * nsplane, 0.0f, s))) return rc;
   if ((rc = launch_fill(at<float>(work, L.adjaux[1]), L.aux_elems, 0.0f, s))) return rc;
   if ((rc = launch_fill_f64(at<double>(work, L.tot), 3 * L.plane, 0.0, s))) return rc;
-  float* trb = at<float>(work, L.tr);
   for (int sg = L.nseg - 1; sg >= 0; --sg) {
     const int n0 = sg * k, n1 = std::min(nt, n0 + k);
-    // restore the state entering step n0 into buffer pair 0 and aux[n0 % 2]
-    const float* slot = at<float>(work, L.ck) + (size_t)sg * L.slot_elems;
-    if ((rc = launch_copy(at<float>(work, L.pf[0]), slot, 2 * nsplane, s))) return rc;
-    if ((rc = launch_copy(at<float>(work, L.pf[1]), slot + 2 * nsplane, 2 * nsplane, s)))
-      return rc;
-    if ((rc = launch_copy(at<float>(work, L.gf[0]), slot + 4 * nsplane, 2 * nsplane, s)))
-      return rc;
-    if ((rc = launch_copy(at<float>(work, L.gf[1]), slot + 6 * nsplane, 2 * nsplane, s)))
-      return rc;
-    if ((rc = launch_copy(at<float>(work, L.aux[n0 % 2]), slot + 8 * nsplane, L.aux_elems, s)))
-      return rc;
-    int c = 0;
-    for (int n = n0; n < n1; ++n) {
-      float* tr[3];
-      for (int q = 0; q < 3; ++q) tr[q] = trb + ((size_t)(n - n0) * 3 + q) * nsplane;
-      if ((rc = vti_fwd_step(p, work, L, n, c, nullptr, tr, s, kRecInt))) return rc;
-      c = 1 - c;
+    // a stored segment's traces were written by the forward: nothing to recompute
+    if (!vti_kept(L, sg)) {
+      // restore the state entering step n0 into buffer pair 0 and aux[n0 % 2]
+      const float* slot = at<float>(work, L.ck) + (size_t)sg * L.slot_elems;
+      if ((rc = launch_copy(at<float>(work, L.pf[0]), slot, 2 * nsplane, s))) return rc;
+      if ((rc = launch_copy(at<float>(work, L.pf[1]), slot + 2 * nsplane, 2 * nsplane, s)))
+        return rc;
+      if ((rc = launch_copy(at<float>(work, L.gf[0]), slot + 4 * nsplane, 2 * nsplane, s)))
+        return rc;
+      if ((rc = launch_copy(at<float>(work, L.gf[1]), slot + 6 * nsplane, 2 * nsplane, s)))
+        return rc;
+      if ((rc = launch_copy(at<float>(work, L.aux[n0 % 2]), slot + 8 * nsplane, L.aux_elems, s)))
+        return rc;
+      int c = 0;
+      for (int n = n0; n < n1; ++n) {
+        float* tr[3];
+        for (int q = 0; q < 3; ++q) tr[q] = vti_trace(work, L, nsplane, k, sg, n - n0, q);
+        if ((rc = vti_fwd_step(p, work, L, n, c, nullptr, tr, s, kRecInt))) return rc;
+        c = 1 - c;
+      }
     }
     for (int n = n1 - 1; n >= n0; --n) {
       const int it = nt - 1 - n;
@@ -279,7 +307,7 @@ int vti_backward(sweep_plan* p, const float* resid, float* grad, void* work, siz
       a.mprev = at<double>(work, L.mf[1 - ac]);
       set_aux(a, at<float>(work, L.adjaux[it % 2]), at<float>(work, L.adjaux[(it + 1) % 2]), L,
               ns);
-      for (int q = 0; q < 3; ++q) a.trc[q] = trb + ((size_t)(n - n0) * 3 + q) * nsplane;
+      for (int q = 0; q < 3; ++q) a.trc[q] = vti_trace(work, L, nsplane, k, sg, n - n0, q);
       a.g = at<float>(work, L.gpart);
       a.g_init = (n == n1 - 1);
       hipEvent_t* ev = p->timer.take(kAdjInt, -1, -1);

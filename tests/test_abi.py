@@ -150,6 +150,30 @@ def test_elastic_stored_segments_workspace_accounting(lib):
         assert p.workspace_bytes(False) == f0
 
 
+def test_vti_stored_segments_workspace_accounting(lib):
+    """VTI plans store the three trace planes of each stored segment and need
+    no checkpoint for it: per stored segment ckpt * 3 * nshots * NX * NZ
+    floats more backward workspace, less one checkpoint slot (P^n, P^{n-1},
+    G^n, G^{n-1} in float64 and the four C-PML memory-variable strips), the
+    forward part unchanged (host-side layout, no GPU)."""
+    import paper_2604_14189_amd as sw
+    from tests.helpers import random_case
+    c = random_case(8, nx=150, nz=77, pml=10, nt=240, nshots=3, nrec=9, ckpt=17)
+    p = sw.Plan(nx=c.nx, nz=c.nz, h=c.h, dt=c.dt, nt=c.nt, pml=c.pml, src_xz=c.src,
+                rec_xz=c.rec, pml_vmax=c.vmax * 1.3, pml_f0=c.f0, ckpt_every=c.ckpt,
+                physics=sw.VTI)
+    NX, NZ = p.padded()
+    P = c.pml
+    w0, f0 = p.workspace_bytes(True), p.workspace_bytes(False)
+    nseg = -(-c.nt // c.ckpt)
+    slot = 8 * c.nshots * NX * NZ + c.nshots * (2 * NZ * 2 * P + 2 * 2 * P * NX)
+    for keep in (2, nseg, nseg + 3):
+        p.set_tuning(keep_b=keep)
+        want = min(keep, nseg) * (c.ckpt * 3 * c.nshots * NX * NZ - slot) * 4
+        assert abs(p.workspace_bytes(True) - w0 - want) < 4096, keep
+        assert p.workspace_bytes(False) == f0
+
+
 def test_batch_membership_and_tuning_checks(lib):
     """Batches hold any number of distinct plans of one tiling (launches carry
     up to eight plans each), and refuse (before any device call) a forward

@@ -3,8 +3,9 @@ against the FP64 oracle. Gathers <= 1e-5 and each of the three gradients
 (vv, v, eta) <= 1e-4 relative L2, on a ragged grid with sources next to the
 pad, coincident receivers and a ragged last checkpoint segment; eta = 0 with
 v = vv gives the acoustic plan's results; edge cases (one step, a grid smaller
-than one tile, no pad, no receivers); and the full 1000x300 / 3000-step
-workload, one shot against stored oracle values."""
+than one tile, no pad, no receivers); stored segments bitwise against
+recomputation; and the full 1000x300 / 3000-step workload, one shot against
+stored oracle values, with and without stored segments."""
 import os
 
 import numpy as np
@@ -153,25 +154,52 @@ def test_vti_no_receivers(sw):
 def test_vti_tuning_limits(sw):
     c = _vti_case(13, nt=20)
     plan = _plan(sw, c)
-    for bad in ({"rz": 8}, {"keep_b": 2}, {"use_graph": 1}):
+    for bad in ({"rz": 8}, {"use_graph": 1}):
         with pytest.raises(sw.SweepError):
             plan.set_tuning(**bad)
+
+
+@pytest.mark.parametrize("keep", [3, 99])
+def test_vti_stored_segments_bitwise(sw, keep):
+    """Stored traces of the last `keep` checkpoint segments (some, or all of
+    them; 240 steps in segments of 17, so the last one is ragged): gathers and
+    the three gradients equal those of the plan that recomputes every
+    segment, bit for bit."""
+    c = _vti_case(7)
+    m, w = _dev(c.model), _dev(c.wav)
+    ref = _plan(sw, c)
+    d0 = ref.forward(m, w, save=True).clone()
+    r = _dev(synth.bandlimited_noise((c.nshots, c.nt, c.nrec), 15.0, c.dt, 14))
+    g0 = ref.backward(r).clone()
+    p = _plan(sw, c)
+    p.set_tuning(keep_b=keep)
+    assert torch.equal(p.forward(m, w, save=True), d0)
+    assert torch.equal(p.backward(r), g0)
+    assert all(torch.any(g0[q] != 0) for q in range(3))
 
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "vti1000x300_shot23.npz")
 
 
 @pytest.mark.skipif(not os.path.exists(GOLDEN), reason="golden file not generated")
-def test_full_size_vti_sampled_shot(sw):
-    """All 64 shots of the 1000x300 / 3000-step VTI workload (the bench's
-    configuration: 64 x 16 tiles, interior and C-PML tile kernels, every
-    segment recomputed); shot 23 compared with stored oracle traces and with
-    gradient samples for a residual on that shot only."""
+@pytest.mark.parametrize("stored", [False, True])
+def test_full_size_vti_sampled_shot(sw, stored):
+    """All 64 shots of the 1000x300 / 3000-step VTI workload (64 x 16 tiles,
+    interior and C-PML tile kernels); shot 23 compared with stored oracle
+    traces and with gradient samples for a residual on that shot only.
+    `stored`: the bench's configuration, the traces of as many of the last
+    checkpoint segments as the free HBM holds (the bench's own sizing rule),
+    the others recomputed; otherwise every segment is recomputed."""
     gold = np.load(GOLDEN)
     w = synth.workload("vti1000x300")
     plan = sw.Plan(nx=w.nx, nz=w.nz, h=w.h, dt=w.dt, nt=w.nt, pml=w.pml, src_xz=w.sources(),
                    rec_xz=w.receivers(), pml_vmax=w.pml_vmax(), pml_f0=w.f0, pml_R=w.pml_R,
                    ckpt_every=w.ckpt_every, physics=sw.VTI)
+    if stored:
+        import bench
+        keep = bench.fit_keep_b(torch, plan, w.nt, w.ckpt_every)
+        print("stored segments", keep, "of", -(-w.nt // w.ckpt_every), flush=True)
+        assert keep >= 1
     d = plan.forward(_dev(w.true_model()), _dev(w.wavelets()), save=True)
     s = int(gold["shot"])
     tr = torch.as_tensor(gold["trace_idx"], device="cuda")
