@@ -54,7 +54,9 @@ extern "C" {
 /* Eq. 1: first-order variable-density acoustic (particle velocity and
  * pressure). Computed by the SWEEP_ELASTIC scheme with shear modulus 0: the
  * two normal stresses then both equal -p and the shear stress stays 0, which
- * is the first-order acoustic system on the same staggered grid. Model
+ * is the first-order acoustic system on the same staggered grid. The step
+ * kernels run their fluid variants, which leave out the shear stress and its
+ * terms (all products with mu = 0): the same results, fewer bytes. Model
  * (vp, rho), gathers (vx, vz), gradients (vp, rho); free_surface = 1 is the
  * pressure-release top. */
 #define SWEEP_ACOUSTIC_VD 2
