@@ -69,7 +69,7 @@ extern "C" {
  * gradients (vv, v, eta). pml_vmax must be at least the fastest horizontal
  * speed v sqrt(1 + 2 eta) (the Courant limit is the acoustic one); eta < 0 is
  * not supported (the scheme's two modes would not stay real). 64 x 16 tiles,
- * single steps: tuning.rz must stay 4 and use_graph 0. The source
+ * single steps: tuning.rz must stay 4. The source
  * should sit where eta = 0, as the formulation asks (the paper's figure shows
  * the artificial mode it otherwise excites). */
 #define SWEEP_VTI 3
@@ -107,7 +107,13 @@ typedef struct {
                       interior kernel: 1, 2, 4 or 8 (default 8) */
   int pml_rz;      /* rows per thread of the C-PML (frame-tile) kernels, <= rz: a
                       frame tile is split into rz / pml_rz work-groups (default 4) */
-  int use_graph;   /* 1 = capture each forward/backward time loop as a hipGraph */
+  int use_graph;   /* 1 = capture each forward/backward time loop as a hipGraph
+                      (every physics; the geometry upload and the state checks
+                      stay outside it). A graph is captured on the first call
+                      with given pointers (model, wavelets, gathers, workspace,
+                      save flag; residuals, gradient, workspace) and replayed
+                      by the next ones; a tuning change drops it. Calls with
+                      profiling on run eagerly */
   int tblock;      /* acoustic: 2 = advance the deep interior tiles (no C-PML cell
                       within 4 cells, no source or receiver within 4, an 8-cell halo
                       inside the grid) two time steps per pass, marching down runs of
@@ -283,6 +289,10 @@ int sweep_backward(sweep_plan* plan, const float* d_resid, float* d_grad, void* 
  * the recorded events and returns the number of timed launches and their summed
  * duration in milliseconds since the reset. */
 int sweep_plan_set_profiling(sweep_plan* plan, int enable);
+/* Number of nodes of the plan's captured forward and backward graphs
+ * (tuning.use_graph = 1; each node one kernel launch of the time loop; 0 when
+ * nothing is captured). */
+int sweep_plan_graph_nodes(const sweep_plan* plan, size_t* fwd_nodes, size_t* bwd_nodes);
 int sweep_plan_kernel_time(sweep_plan* plan, int kernel_class, int* launches, double* total_ms);
 
 /* ---- batches: several acoustic plans of different grids / shots / nt ----

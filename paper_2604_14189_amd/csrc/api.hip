@@ -1165,8 +1165,8 @@ extern "C" int sweep_plan_set_tuning(sweep_plan* p, const sweep_tuning* t) try {
     set_error("unsupported tuning");
     return SWEEP_EINVAL;
   }
-  if (p->pb.physics == SWEEP_VTI && (t->rz != 4 || t->use_graph != 0)) {
-    set_error("VTI plans take 64 x 16 tiles (rz 4) and no graph capture");
+  if (p->pb.physics == SWEEP_VTI && t->rz != 4) {
+    set_error("VTI plans take 64 x 16 tiles (rz 4)");
     return SWEEP_EINVAL;
   }
   p->tune = *t;
@@ -1255,14 +1255,31 @@ extern "C" int sweep_forward(sweep_plan* p, const float* d_model, const float* d
     return SWEEP_EHIP;
   }
   p->saved = false;
-  if (p->pb.physics == SWEEP_VTI)
-    return vti_forward(p, d_model, d_wavelet, d_gathers, d_work, work_bytes, save_for_backward,
-                       (hipStream_t)stream);
-  if (p->pb.physics != SWEEP_ACOUSTIC)
-    return el_forward(p, d_model, d_wavelet, d_gathers, d_work, work_bytes, save_for_backward,
+  if (p->pb.physics == SWEEP_ACOUSTIC)
+    return ac_forward(p, d_model, d_wavelet, d_gathers, d_work, work_bytes, save_for_backward,
                       (hipStream_t)stream);
-  return ac_forward(p, d_model, d_wavelet, d_gathers, d_work, work_bytes, save_for_backward,
-                    (hipStream_t)stream);
+  // staggered and VTI plans: host checks and copies, then the device work
+  // (eager, or captured once into a graph and replayed), then the saved state
+  const bool vti = p->pb.physics == SWEEP_VTI;
+  const hipStream_t s = (hipStream_t)stream;
+  int rc = vti ? vti_forward_prepare(p, d_work, work_bytes, save_for_backward, s)
+               : el_forward_prepare(p, d_work, work_bytes, save_for_backward, s);
+  if (rc) return rc;
+  const bool graph = p->tune.use_graph && !p->timer.on;
+  const std::vector<const void*> key = {d_model, d_wavelet, d_gathers, d_work,
+                                        (const void*)(size_t)save_for_backward};
+  rc = run_maybe_graph(p->gfwd, graph, key, s, [&](hipStream_t st) {
+    return vti ? vti_forward_enqueue(p, d_model, d_wavelet, d_gathers, d_work, save_for_backward,
+                                     st)
+               : el_forward_enqueue(p, d_model, d_wavelet, d_gathers, d_work, save_for_backward,
+                                    st);
+  });
+  if (rc) return rc;
+  if (vti)
+    vti_mark_saved(p, d_work, d_model, save_for_backward);
+  else
+    el_mark_saved(p, d_work, d_model, save_for_backward);
+  return SWEEP_OK;
 }
 SWEEP_ABI_CATCH("sweep_forward")
 
@@ -1344,11 +1361,18 @@ extern "C" int sweep_backward(sweep_plan* p, const float* d_resid, float* d_grad
     set_error("cannot make the plan's device current");
     return SWEEP_EHIP;
   }
-  if (p->pb.physics == SWEEP_VTI)
-    return vti_backward(p, d_resid, d_grad, d_work, work_bytes, (hipStream_t)stream);
-  if (p->pb.physics != SWEEP_ACOUSTIC)
-    return el_backward(p, d_resid, d_grad, d_work, work_bytes, (hipStream_t)stream);
-  return ac_backward(p, d_resid, d_grad, d_work, work_bytes, (hipStream_t)stream);
+  if (p->pb.physics == SWEEP_ACOUSTIC)
+    return ac_backward(p, d_resid, d_grad, d_work, work_bytes, (hipStream_t)stream);
+  const bool vti = p->pb.physics == SWEEP_VTI;
+  const int rc = vti ? vti_backward_check(p, d_work, work_bytes)
+                     : el_backward_check(p, d_work, work_bytes);
+  if (rc) return rc;
+  const bool graph = p->tune.use_graph && !p->timer.on;
+  const std::vector<const void*> key = {d_resid, d_grad, d_work};
+  return run_maybe_graph(p->gbwd, graph, key, (hipStream_t)stream, [&](hipStream_t st) {
+    return vti ? vti_backward_enqueue(p, d_resid, d_grad, d_work, st)
+               : el_backward_enqueue(p, d_resid, d_grad, d_work, st);
+  });
 }
 SWEEP_ABI_CATCH("sweep_backward")
 
@@ -1461,6 +1485,18 @@ extern "C" int sweep_batch_set_graph(sweep_batch* b, int use_graph) try {
   return SWEEP_OK;
 }
 SWEEP_ABI_CATCH("sweep_batch_set_graph")
+
+extern "C" int sweep_plan_graph_nodes(const sweep_plan* p, size_t* fwd_nodes,
+                                      size_t* bwd_nodes) try {
+  if (!p || !fwd_nodes || !bwd_nodes) {
+    set_error("sweep_plan_graph_nodes: null argument");
+    return SWEEP_EINVAL;
+  }
+  *fwd_nodes = p->gfwd.exec ? p->gfwd.nodes : 0;
+  *bwd_nodes = p->gbwd.exec ? p->gbwd.nodes : 0;
+  return SWEEP_OK;
+}
+SWEEP_ABI_CATCH("sweep_plan_graph_nodes")
 
 extern "C" int sweep_batch_graph_nodes(const sweep_batch* b, size_t* fwd_nodes,
                                        size_t* bwd_nodes) try {

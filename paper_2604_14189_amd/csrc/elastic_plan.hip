@@ -212,8 +212,9 @@ void set_state(ElStep& a, float* st, size_t nsplane) {
 
 }  // namespace
 
-int el_forward(sweep_plan* p, const float* model, const float* wavelet, float* gathers,
-               void* work, size_t bytes, int save, hipStream_t s) {
+// Workspace checks and the geometry upload (host copies, kept out of a
+// captured graph).
+int el_forward_prepare(sweep_plan* p, void* work, size_t bytes, int save, hipStream_t s) {
   ElLayout L;
   el_layout(p, L);
   const size_t need = save ? L.bwd_end : L.fwd_end;
@@ -226,8 +227,7 @@ int el_forward(sweep_plan* p, const float* model, const float* wavelet, float* g
     return SWEEP_ENOMEM;
   }
   const sweep_problem& pb = p->pb;
-  const size_t ns = pb.nshots, nsplane = ns * L.plane;
-  int rc;
+  const size_t ns = pb.nshots;
   SWEEP_HIP(hipMemcpyAsync(at<int>(work, L.src_cell), p->src_cell.data(), ns * sizeof(int),
                            hipMemcpyHostToDevice, s));
   if (pb.nrec > 0) {
@@ -236,6 +236,17 @@ int el_forward(sweep_plan* p, const float* model, const float* wavelet, float* g
     SWEEP_HIP(hipMemcpyAsync(at<int4>(work, L.rec_sorted), p->rec_sorted.data(),
                              p->rec_sorted.size() * sizeof(int4), hipMemcpyHostToDevice, s));
   }
+  return SWEEP_OK;
+}
+
+// The forward's device work (kernels only: it may be captured).
+int el_forward_enqueue(sweep_plan* p, const float* model, const float* wavelet, float* gathers,
+                       void* work, int save, hipStream_t s) {
+  ElLayout L;
+  el_layout(p, L);
+  const sweep_problem& pb = p->pb;
+  const size_t ns = pb.nshots, nsplane = ns * L.plane;
+  int rc;
   const ElCoef c = coef_ptrs(p, work, L);
   if ((rc = el_launch_prep(model, c, pb.nx, pb.nz, p->P, pb.free_surface,
                            pb.physics == SWEEP_ACOUSTIC_VD, pb.h, pb.dt, pb.pml_vmax, pb.pml_f0,
@@ -265,15 +276,25 @@ int el_forward(sweep_plan* p, const float* model, const float* wavelet, float* g
         a.tr[q] = el_trace(work, L, nsplane, k, sg, n - sg * k, q);
     if ((rc = el_launch_fwd(a, s, p->timer.take(keepT ? kRecInt : kFwdInt, -1, -1)))) return rc;
   }
+  return SWEEP_OK;
+}
+
+void el_mark_saved(sweep_plan* p, void* work, const float* model, int save) {
   p->saved = save != 0;
   p->saved_work = work;
   p->saved_model = model;
   p->saved_rz = p->tune.rz;
-  return SWEEP_OK;
 }
 
-int el_backward(sweep_plan* p, const float* resid, float* grad, void* work, size_t bytes,
-                hipStream_t s) {
+int el_forward(sweep_plan* p, const float* model, const float* wavelet, float* gathers,
+               void* work, size_t bytes, int save, hipStream_t s) {
+  int rc = el_forward_prepare(p, work, bytes, save, s);
+  if (!rc) rc = el_forward_enqueue(p, model, wavelet, gathers, work, save, s);
+  if (!rc) el_mark_saved(p, work, model, save);
+  return rc;
+}
+
+int el_backward_check(const sweep_plan* p, const void* work, size_t bytes) {
   if (!p->saved || p->saved_work != work) {
     set_error("sweep_backward needs a preceding sweep_forward(save_for_backward=1) on the "
               "same workspace");
@@ -285,6 +306,20 @@ int el_backward(sweep_plan* p, const float* resid, float* grad, void* work, size
     set_error("workspace too small for backward");
     return SWEEP_ENOMEM;
   }
+  return SWEEP_OK;
+}
+
+int el_backward(sweep_plan* p, const float* resid, float* grad, void* work, size_t bytes,
+                hipStream_t s) {
+  const int rc = el_backward_check(p, work, bytes);
+  return rc ? rc : el_backward_enqueue(p, resid, grad, work, s);
+}
+
+// The backward's device work (kernels only: it may be captured).
+int el_backward_enqueue(sweep_plan* p, const float* resid, float* grad, void* work,
+                        hipStream_t s) {
+  ElLayout L;
+  el_layout(p, L);
   const sweep_problem& pb = p->pb;
   const size_t ns = pb.nshots, nsplane = ns * L.plane;
   const int nt = pb.nt, k = p->ckpt;

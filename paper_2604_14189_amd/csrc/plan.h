@@ -183,15 +183,34 @@ void ac_build_tiling(sweep_plan* p);
 void ac_layout(const sweep_plan* p, AcLayout& L, bool keep = true);
 void el_layout(const sweep_plan* p, ElLayout& L);
 void el_build_tables(sweep_plan* p);
+// Forward and backward of the staggered (elastic, variable-density) and VTI
+// plans. Each is also split for graph capture: *_prepare / *_backward_check
+// (workspace checks and host-to-device geometry copies, not captured), then
+// *_enqueue (kernels only, which a graph may capture and replay), then
+// *_mark_saved (the plan's saved-forward state).
 int el_forward(sweep_plan* p, const float* model, const float* wavelet, float* gathers,
                void* work, size_t bytes, int save, hipStream_t s);
 int el_backward(sweep_plan* p, const float* resid, float* grad, void* work, size_t bytes,
                 hipStream_t s);
+int el_forward_prepare(sweep_plan* p, void* work, size_t bytes, int save, hipStream_t s);
+int el_forward_enqueue(sweep_plan* p, const float* model, const float* wavelet, float* gathers,
+                       void* work, int save, hipStream_t s);
+void el_mark_saved(sweep_plan* p, void* work, const float* model, int save);
+int el_backward_check(const sweep_plan* p, const void* work, size_t bytes);
+int el_backward_enqueue(sweep_plan* p, const float* resid, float* grad, void* work,
+                        hipStream_t s);
 void vti_layout(const sweep_plan* p, VtiLayout& L);
 int vti_forward(sweep_plan* p, const float* model, const float* wavelet, float* gathers,
                 void* work, size_t bytes, int save, hipStream_t s);
 int vti_backward(sweep_plan* p, const float* resid, float* grad, void* work, size_t bytes,
                  hipStream_t s);
+int vti_forward_prepare(sweep_plan* p, void* work, size_t bytes, int save, hipStream_t s);
+int vti_forward_enqueue(sweep_plan* p, const float* model, const float* wavelet,
+                        float* gathers, void* work, int save, hipStream_t s);
+void vti_mark_saved(sweep_plan* p, void* work, const float* model, int save);
+int vti_backward_check(const sweep_plan* p, const void* work, size_t bytes);
+int vti_backward_enqueue(sweep_plan* p, const float* resid, float* grad, void* work,
+                         hipStream_t s);
 }  // namespace sweep
 
 struct sweep_batch {

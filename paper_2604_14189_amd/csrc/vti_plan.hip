@@ -180,14 +180,15 @@ int vti_fwd_step(sweep_plan* p, void* work, const VtiLayout& L, int n, int c, fl
 
 }  // namespace
 
-int vti_forward(sweep_plan* p, const float* model, const float* wavelet, float* gathers,
-                void* work, size_t bytes, int save, hipStream_t s) {
+// Workspace checks, the tile lists and the geometry upload (host copies, kept
+// out of a captured graph).
+int vti_forward_prepare(sweep_plan* p, void* work, size_t bytes, int save, hipStream_t s) {
   VtiLayout L;
   vti_layout(p, L);
   int rc = check_bytes(save ? L.bwd_end : L.fwd_end, work, bytes);
   if (rc) return rc;
   const sweep_problem& pb = p->pb;
-  const size_t ns = pb.nshots, nsplane = ns * L.plane;
+  const size_t ns = pb.nshots;
   SWEEP_HIP(hipMemcpyAsync(at<int>(work, L.src_cell), p->src_cell.data(), ns * sizeof(int),
                            hipMemcpyHostToDevice, s));
   if (pb.nrec > 0) {
@@ -201,6 +202,17 @@ int vti_forward(sweep_plan* p, const float* model, const float* wavelet, float* 
   vti_split_tiles(p);
   SWEEP_HIP(hipMemcpyAsync(at<int>(work, L.tl), p->vti_tl.data(), p->vti_tl.size() * sizeof(int),
                            hipMemcpyHostToDevice, s));
+  return SWEEP_OK;
+}
+
+// The forward's device work (kernels only: it may be captured).
+int vti_forward_enqueue(sweep_plan* p, const float* model, const float* wavelet,
+                        float* gathers, void* work, int save, hipStream_t s) {
+  VtiLayout L;
+  vti_layout(p, L);
+  const sweep_problem& pb = p->pb;
+  const size_t ns = pb.nshots, nsplane = ns * L.plane;
+  int rc;
   if ((rc = ac_launch_tables(at<float>(work, L.ax), at<float>(work, L.bx), at<float>(work, L.az),
                              at<float>(work, L.bz), p->NX, p->NZ, p->P, pb.h, pb.dt, pb.pml_vmax,
                              pb.pml_f0, pb.pml_R, s)))
@@ -243,15 +255,25 @@ int vti_forward(sweep_plan* p, const float* model, const float* wavelet, float* 
     }
     c = 1 - c;
   }
+  return SWEEP_OK;
+}
+
+void vti_mark_saved(sweep_plan* p, void* work, const float* model, int save) {
   p->saved = save != 0;
   p->saved_work = work;
   p->saved_model = model;
   p->saved_rz = p->tune.rz;
-  return SWEEP_OK;
 }
 
-int vti_backward(sweep_plan* p, const float* resid, float* grad, void* work, size_t bytes,
-                 hipStream_t s) {
+int vti_forward(sweep_plan* p, const float* model, const float* wavelet, float* gathers,
+                void* work, size_t bytes, int save, hipStream_t s) {
+  int rc = vti_forward_prepare(p, work, bytes, save, s);
+  if (!rc) rc = vti_forward_enqueue(p, model, wavelet, gathers, work, save, s);
+  if (!rc) vti_mark_saved(p, work, model, save);
+  return rc;
+}
+
+int vti_backward_check(const sweep_plan* p, const void* work, size_t bytes) {
   if (!p->saved || p->saved_work != work) {
     set_error("sweep_backward needs a preceding sweep_forward(save_for_backward=1) on the "
               "same workspace");
@@ -259,8 +281,21 @@ int vti_backward(sweep_plan* p, const float* resid, float* grad, void* work, siz
   }
   VtiLayout L;
   vti_layout(p, L);
-  int rc = check_bytes(L.bwd_end, work, bytes);
-  if (rc) return rc;
+  return check_bytes(L.bwd_end, const_cast<void*>(work), bytes);
+}
+
+int vti_backward(sweep_plan* p, const float* resid, float* grad, void* work, size_t bytes,
+                 hipStream_t s) {
+  const int rc = vti_backward_check(p, work, bytes);
+  return rc ? rc : vti_backward_enqueue(p, resid, grad, work, s);
+}
+
+// The backward's device work (kernels only: it may be captured).
+int vti_backward_enqueue(sweep_plan* p, const float* resid, float* grad, void* work,
+                         hipStream_t s) {
+  VtiLayout L;
+  vti_layout(p, L);
+  int rc;
   const sweep_problem& pb = p->pb;
   const int nt = pb.nt, k = p->ckpt;
   const size_t ns = pb.nshots, nsplane = ns * L.plane;

@@ -296,6 +296,13 @@ class Plan:
         """Time the step kernels with HIP events (every `period`-th step)."""
         check(lib().sweep_plan_set_profiling(self._h, max(1, int(period)) if enable else 0))
 
+    def graph_nodes(self):
+        """(forward, backward): kernel launches held by the captured graphs
+        (tuning use_graph = 1)."""
+        f, b = ctypes.c_size_t(), ctypes.c_size_t()
+        check(lib().sweep_plan_graph_nodes(self._h, ctypes.byref(f), ctypes.byref(b)))
+        return f.value, b.value
+
     def kernel_times(self) -> dict:
         """{class: (launches, total_ms)} since the last set_profiling()."""
         out = {}

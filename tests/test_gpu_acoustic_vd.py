@@ -115,6 +115,31 @@ def test_vd_stored_segments_bitwise(sw, fs, keep):
     assert torch.any(g0[0] != 0) and torch.any(g0[1] != 0)
 
 
+def test_vd_graph_replays_match_eager(sw):
+    """use_graph = 1 on a variable-density plan (fluid kernels, pressure-release
+    top, stored segments): every replay of the captured forward and backward
+    equals the eager plan bit for bit."""
+    c = _case(1, seed=8, nt=150)
+    m, wav = _dev(np.stack([c["vp"], c["rho"]])), _dev(c["wav"])
+    eager = _plan(sw, c, sw.ACOUSTIC_VD)
+    d0 = eager.forward(m, wav, save=True).clone()
+    r = _dev(np.random.default_rng(6).standard_normal(tuple(d0.shape)))
+    g0 = eager.backward(r).clone()
+    gp = _plan(sw, c, sw.ACOUSTIC_VD)
+    gp.set_tuning(use_graph=1, keep_b=2)
+    gp.reserve_workspace(True)
+    out, grad = torch.empty_like(d0), torch.empty_like(g0)
+    for rep in range(3):
+        gp.forward(m, wav, save=True, out=out)
+        gp.backward(r, out=grad)
+        torch.cuda.synchronize()
+        assert torch.equal(out, d0), rep
+        assert torch.equal(grad, g0), rep
+        nf, nb = gp.graph_nodes()
+        assert nf > 0 and nb > 0, (nf, nb)
+        assert torch.isfinite(torch.randn(4096, device="cuda").sum())
+
+
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "vd1000x300_shot41.npz")
 
 
