@@ -28,7 +28,7 @@ import torch
 from .mlp import MLPVelocity, adam_step
 from .propagator import Plan, l2_misfit
 
-__all__ = ["GridFWI", "NeuralFWI", "MultiScaleFWI", "lowpass", "prefit", "rmse"]
+__all__ = ["GridFWI", "NeuralFWI", "MultiScaleFWI", "LSRTM", "lowpass", "prefit", "rmse"]
 
 
 def rmse(v: torch.Tensor, v_true: np.ndarray) -> float:
@@ -119,6 +119,57 @@ class MultiScaleFWI:
     @property
     def velocity(self) -> torch.Tensor:
         return self.v
+
+
+class LSRTM:
+    """Least-squares reverse-time migration: the model perturbation dv that
+    fits data d with Born modelling about a fixed background v0 (Eq. 16),
+    min 1/2 |L dv - d|^2 with L = plan.born(v0, ., wavelet), by conjugate
+    gradients on the normal equations (CGLS). L^T r is the adjoint gradient
+    plan.backward(r) after a saving forward on v0 (Born modelling leaves no
+    saved state, so each application re-runs it). Each iteration applies L
+    once and L^T once; the data residual |r| falls monotonically (up to the
+    operators' float32 rounding). Sums are taken in float64."""
+
+    def __init__(self, plan: Plan, v0: torch.Tensor, wavelet: torch.Tensor, d: torch.Tensor):
+        self.plan, self.v0, self.wav = plan, v0.contiguous(), wavelet
+        self.x = torch.zeros_like(self.v0)
+        self.r = d.clone().contiguous()
+        self.s = self._adjoint(self.r)
+        self.p = self.s.clone()
+        self.gamma = self._dot(self.s, self.s)
+        self.history = [self._norm(self.r)]  # |r| after each iteration, |d| first
+
+    @staticmethod
+    def _dot(a: torch.Tensor, b: torch.Tensor) -> float:
+        return float(torch.sum(a.double() * b.double()).item())
+
+    def _norm(self, a: torch.Tensor) -> float:
+        return self._dot(a, a) ** 0.5
+
+    def _adjoint(self, r: torch.Tensor) -> torch.Tensor:
+        self.plan.forward(self.v0, self.wav, save=True)
+        return self.plan.backward(r).reshape(self.v0.shape).clone()
+
+    def step(self) -> float:
+        """One CGLS iteration; returns the data residual norm |L dv - d|."""
+        q = self.plan.born(self.v0, self.p, self.wav)
+        qq = self._dot(q, q)
+        if qq == 0.0 or self.gamma == 0.0:
+            return self.history[-1]
+        alpha = self.gamma / qq
+        self.x.add_(self.p, alpha=alpha)
+        self.r.add_(q, alpha=-alpha)
+        self.s = self._adjoint(self.r)
+        gamma = self._dot(self.s, self.s)
+        self.p = self.s + (gamma / self.gamma) * self.p
+        self.gamma = gamma
+        self.history.append(self._norm(self.r))
+        return self.history[-1]
+
+    @property
+    def perturbation(self) -> torch.Tensor:
+        return self.x
 
 
 class NeuralFWI:
