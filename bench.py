@@ -35,9 +35,9 @@ METRIC = "Gcell-updates/s fwd+adj; batched vs per-shot FWI gradient time at 1e-4
 # for a plain device copy of known size (--calibrate-copy). Keyed by kernel
 # class; valid only while the kernel source hashes to the recorded value.
 TRAFFIC = {
-    "adj_deep": {"bytes_per_launch": 605895243, "source": "d085c20f2f747647"},
-    "adj_zpml": {"bytes_per_launch": 293324280, "source": "d085c20f2f747647"},
-    "adj_xpml": {"bytes_per_launch": 129790301, "source": "d085c20f2f747647"},
+    "adj_deep": {"bytes_per_launch": 605894423, "source": "57863fbc17cd4090"},
+    "adj_zpml": {"bytes_per_launch": 295713321, "source": "57863fbc17cd4090"},
+    "adj_xpml": {"bytes_per_launch": 128460981, "source": "57863fbc17cd4090"},
 }
 
 

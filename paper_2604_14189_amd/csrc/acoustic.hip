@@ -129,9 +129,9 @@ __device__ __forceinline__ void stage_box(float* s, const float* __restrict__ f,
     const int c = e - r * T::LW;
     const int gx = x0 - 4 + c, gz = z0 - 4 + r;
     const bool ok = e < N && (inside || (gx >= 0 && gx < NX && gz >= 0 && gz < NZ));
-    const size_t idx = ok ? (size_t)gz * NX + gx : 0;
-    v[k] = ok ? f[idx] : 0.0f;
-    if (kProduct) u[k] = ok ? g[idx] : 0.0f;
+    const unsigned idx = ok ? (unsigned)(gz * NX + gx) : 0u;
+    v[k] = ok ? u32at(f, idx) : 0.0f;
+    if (kProduct) u[k] = ok ? u32at(g, idx) : 0.0f;
   }
 #pragma unroll
   for (int k = 0; k < K; ++k) {
@@ -189,6 +189,7 @@ __device__ __forceinline__ void adj_store(const AcStep& a, int shot, int tile, i
   const int lx = threadIdx.x & 63, zb = (threadIdx.x >> 6) * RZ;
   const int NX = a.NX, NZ = a.NZ;
   const size_t plane = (size_t)NX * NZ;
+  float* next = a.next + shot * plane;
   const int* ro = a.rec_off + (size_t)shot * a.ntiles + tile;
   if (a.resid && a.n >= 1 && ro[1] > ro[0]) {  // no residual: nothing injected (timing runs)
     __syncthreads();
@@ -204,7 +205,7 @@ __device__ __forceinline__ void adj_store(const AcStep& a, int shot, int tile, i
 #pragma unroll
   for (int r = 0; r < RZ; ++r) {
     const int gz = z0 + zb + r;
-    if (gx < NX && gz < NZ) st_nt(&a.next[shot * plane + (size_t)gz * NX + gx], out[r]);
+    if (gx < NX && gz < NZ) st_nt(&u32at(next, (unsigned)(gz * NX + gx)), out[r]);
   }
 }
 
@@ -237,12 +238,12 @@ __device__ __forceinline__ void ac_fwd_int_body(const AcStep& a, const int tile,
     cs[r] = 0.0f;
     if (kBorn) bd[r] = bb[r] = 0.0f;
     if (inside || (gx < NX && gz < NZ)) {
-      const int idx = gz * NX + gx;
-      pp[r] = ld_nt(&a.prev[shot * plane + idx]);
-      cs[r] = a.Cs[idx];
+      const unsigned idx = (unsigned)(gz * NX + gx);
+      pp[r] = ld_nt(&u32at(a.prev + shot * plane, idx));
+      cs[r] = u32at(a.Cs, idx);
       if (kBorn) {
-        bd[r] = a.bdC[idx];
-        bb[r] = ld_nt(&a.bB[shot * plane + idx]);
+        bd[r] = u32at(a.bdC, idx);
+        bb[r] = ld_nt(&u32at(a.bB + shot * plane, idx));
       }
     }
   }
@@ -270,12 +271,11 @@ __device__ __forceinline__ void ac_fwd_int_body(const AcStep& a, const int tile,
     float pn = 0.0f;
     if (inside || (gx < NX && gz < NZ)) {
       const int idx = gz * NX + gx;
-      const size_t gi = shot * plane + idx;
       pn = fmaf(cs[r], L, 2.0f * c - pp[r]);
       if (kBorn) pn += bd[r] * bb[r];
       if (idx == src) pn += sw;
-      st_nt(&a.next[gi], pn);
-      if (a.B_out) st_nt(&a.B_out[gi], L);
+      st_nt(&u32at(a.next + shot * plane, (unsigned)idx), pn);
+      if (a.B_out) st_nt(&u32at(a.B_out + shot * plane, (unsigned)idx), L);
     }
     out[r] = pn;
   }
@@ -303,11 +303,11 @@ __device__ __forceinline__ void ac_adj_int_body(const AcStep& a, const int tile,
     const int gz = z0 + zb + r;
     p1[r] = pp[r] = bb[r] = gg[r] = 0.0f;
     if (inside || (gx < NX && gz < NZ)) {
-      const size_t gi = shot * plane + (size_t)gz * NX + gx;
-      p1[r] = a.cur[gi];
-      pp[r] = ld_nt(&a.prev[gi]);
-      bb[r] = ld_nt(&a.B_in[gi]);
-      if (!a.g_init) gg[r] = ld_nt(&a.g[gi]);
+      const unsigned gi = (unsigned)(gz * NX + gx);
+      p1[r] = u32at(a.cur + shot * plane, gi);
+      pp[r] = ld_nt(&u32at(a.prev + shot * plane, gi));
+      bb[r] = ld_nt(&u32at(a.B_in + shot * plane, gi));
+      if (!a.g_init) gg[r] = ld_nt(&u32at(a.g + shot * plane, gi));
     }
   }
   stage_box<RZ, true>(sq, a.cur + shot * plane, a.Cs, x0, z0, NX, NZ, inside);
@@ -328,9 +328,9 @@ __device__ __forceinline__ void ac_adj_int_body(const AcStep& a, const int tile,
     const int gz = z0 + zb + r;
     float lam = 0.0f;
     if (inside || (gx < NX && gz < NZ)) {
-      const size_t gi = shot * plane + (size_t)gz * NX + gx;
+      const unsigned gi = (unsigned)(gz * NX + gx);
       const float gb = p1[r] * bb[r];
-      st_nt(&a.g[gi], a.g_init ? gb : gg[r] + gb);
+      st_nt(&u32at(a.g + shot * plane, gi), a.g_init ? gb : gg[r] + gb);
       lam = ((2.0f * p1[r] - pp[r]) + sxx) + szz;
     }
     out[r] = lam;
@@ -428,7 +428,7 @@ __device__ __forceinline__ void ac_fwd_pml_body(const AcStep& a, const int tile,
     const int r = e / BW, c = e - (e / BW) * BW;
     const int gz = z0 - hz + r, gxx = x0 - hx + c;
     const bool ok = e < NB && gxx >= 0 && gxx < NX && gz >= 0 && gz < NZ;
-    vb[k] = ok ? cur[(size_t)gz * NX + gxx] : 0.0f;
+    vb[k] = ok ? u32at(cur, (unsigned)(gz * NX + gxx)) : 0.0f;
   }
   float opx[HX ? KPX : 1], opz[HZ ? KPZ : 1];
   if constexpr (HX) {
@@ -438,7 +438,7 @@ __device__ __forceinline__ void ac_fwd_pml_body(const AcStep& a, const int tile,
       const int r = e / XW, c = e - (e / XW) * XW;
       const int gz = z0 + r, gxx = x0 - 4 + c;
       const int col = (e < NPX && gz < NZ && gxx >= 0 && gxx < NX) ? xstrip_col(gxx, NX, P) : -1;
-      opx[k] = col >= 0 ? a.psx_in[shot * xsp + (size_t)gz * P2 + col] : 0.0f;
+      opx[k] = col >= 0 ? u32at(a.psx_in + shot * xsp, (unsigned)(gz * P2 + col)) : 0.0f;
     }
   }
   if constexpr (HZ) {
@@ -448,7 +448,7 @@ __device__ __forceinline__ void ac_fwd_pml_body(const AcStep& a, const int tile,
       const int r = e >> 6, c = e & 63;
       const int gz = z0 - 4 + r, gxx = x0 + c;
       const int row = (e < NPZ && gxx < NX && gz >= 0 && gz < NZ) ? zstrip_row(gz, NZ, P) : -1;
-      opz[k] = row >= 0 ? a.psz_in[shot * zsp + (size_t)row * NX + gxx] : 0.0f;
+      opz[k] = row >= 0 ? u32at(a.psz_in + shot * zsp, (unsigned)(row * NX + gxx)) : 0.0f;
     }
   }
   // C-PML coefficients of the box columns (threads 0..BW-1) and rows (128..)
@@ -474,16 +474,16 @@ __device__ __forceinline__ void ac_fwd_pml_body(const AcStep& a, const int tile,
   for (int r = 0; r < RZ; ++r) {
     const int gz = z0 + zb + r;
     const bool ok = gx < NX && gz < NZ;
-    const size_t idx = ok ? (size_t)gz * NX + gx : 0;
-    pp[r] = ok ? ld_nt(&a.prev[shot * plane + idx]) : 0.0f;
-    cs[r] = ok ? a.Cs[idx] : 0.0f;
+    const unsigned idx = ok ? (unsigned)(gz * NX + gx) : 0u;
+    pp[r] = ok ? ld_nt(&u32at(a.prev + shot * plane, idx)) : 0.0f;
+    cs[r] = ok ? u32at(a.Cs, idx) : 0.0f;
     if (kBorn) {
-      bd[r] = ok ? a.bdC[idx] : 0.0f;
-      bb[r] = ok ? ld_nt(&a.bB[shot * plane + idx]) : 0.0f;
+      bd[r] = ok ? u32at(a.bdC, idx) : 0.0f;
+      bb[r] = ok ? ld_nt(&u32at(a.bB + shot * plane, idx)) : 0.0f;
     }
-    zx[r] = (HX && ok && xcol >= 0) ? a.zex_in[shot * xsp + (size_t)gz * P2 + xcol] : 0.0f;
+    zx[r] = (HX && ok && xcol >= 0) ? u32at(a.zex_in + shot * xsp, (unsigned)(gz * P2 + xcol)) : 0.0f;
     const int zrow = (HZ && ok) ? zstrip_row(gz, NZ, P) : -1;
-    zz[r] = zrow >= 0 ? a.zez_in[shot * zsp + (size_t)zrow * NX + gx] : 0.0f;
+    zz[r] = zrow >= 0 ? u32at(a.zez_in + shot * zsp, (unsigned)(zrow * NX + gx)) : 0.0f;
   }
 #pragma unroll
   for (int k = 0; k < KB; ++k) {
@@ -511,7 +511,7 @@ __device__ __forceinline__ void ac_fwd_pml_body(const AcStep& a, const int tile,
       float ps = 0.0f;
       if (col >= 0) {
         ps = fmaf(tax[c + hx - 4], d1s(&sb[(r + hz) * BW + c + hx - 4], 1), tbx[c + hx - 4] * opx[k]);
-        if (c >= 4 && c < 4 + kTX) a.psx_out[shot * xsp + (size_t)gz * P2 + col] = ps;
+        if (c >= 4 && c < 4 + kTX) u32at(a.psx_out + shot * xsp, (unsigned)(gz * P2 + col)) = ps;
       }
       spx[e] = ps;
     }
@@ -527,7 +527,7 @@ __device__ __forceinline__ void ac_fwd_pml_body(const AcStep& a, const int tile,
       float ps = 0.0f;
       if (row >= 0) {
         ps = fmaf(taz[r + hz - 4], d1s(&sb[(r + hz - 4) * BW + c + hx], BW), tbz[r + hz - 4] * opz[k]);
-        if (r >= 4 && r < 4 + TZ) a.psz_out[shot * zsp + (size_t)row * NX + gxx] = ps;
+        if (r >= 4 && r < 4 + TZ) u32at(a.psz_out + shot * zsp, (unsigned)(row * NX + gxx)) = ps;
       }
       spz[e] = ps;
     }
@@ -552,24 +552,23 @@ __device__ __forceinline__ void ac_fwd_pml_body(const AcStep& a, const int tile,
     float pn = 0.0f;
     if (gx < NX && gz < NZ) {
       const int idx = gz * NX + gx;
-      const size_t gi = shot * plane + idx;
       if (HX && xcol >= 0) {
         const float zeta = fmaf(tax[lx + hx], Bx, tbx[lx + hx] * zx[r]);
-        a.zex_out[shot * xsp + (size_t)gz * P2 + xcol] = zeta;
+        u32at(a.zex_out + shot * xsp, (unsigned)(gz * P2 + xcol)) = zeta;
         Bx = Bx + zeta;
       }
       const int zrow = HZ ? zstrip_row(gz, NZ, P) : -1;
       if (zrow >= 0) {
         const float zeta = fmaf(taz[zb + r + hz], Bz, tbz[zb + r + hz] * zz[r]);
-        a.zez_out[shot * zsp + (size_t)zrow * NX + gx] = zeta;
+        u32at(a.zez_out + shot * zsp, (unsigned)(zrow * NX + gx)) = zeta;
         Bz = Bz + zeta;
       }
       const float B = Bx + Bz;
       pn = fmaf(cs[r], B, 2.0f * c - pp[r]);
       if (kBorn) pn += bd[r] * bb[r];
       if (idx == src) pn += sw;
-      st_nt(&a.next[gi], pn);
-      if (a.B_out) st_nt(&a.B_out[gi], B);
+      st_nt(&u32at(a.next + shot * plane, (unsigned)idx), pn);
+      if (a.B_out) st_nt(&u32at(a.B_out + shot * plane, (unsigned)idx), B);
     }
     out[r] = pn;
   }
@@ -634,12 +633,12 @@ __device__ __forceinline__ void ac_adj_pml_body(const AcStep& a, const int tile,
       const int r = e / BW, c = e - (e / BW) * BW;
       const int gz = z0 + r, gxx = x0 - hx + c;
       const bool ok = e < NQX && gz < NZ && gxx >= 0 && gxx < NX;
-      const size_t idx = ok ? (size_t)gz * NX + gxx : 0;
-      lx_[k] = ok ? cur[idx] : 0.0f;
-      cx_[k] = ok ? a.Cs[idx] : 0.0f;
+      const unsigned idx = ok ? (unsigned)(gz * NX + gxx) : 0u;
+      lx_[k] = ok ? u32at(cur, idx) : 0.0f;
+      cx_[k] = ok ? u32at(a.Cs, idx) : 0.0f;
       if constexpr (HX) {
         const int col = ok ? xstrip_col(gxx, NX, P) : -1;
-        zx_[k] = col >= 0 ? a.zex_in[shot * xsp + (size_t)gz * P2 + col] : 0.0f;
+        zx_[k] = col >= 0 ? u32at(a.zex_in + shot * xsp, (unsigned)(gz * P2 + col)) : 0.0f;
       }
     }
     float lz_[KQZ], cz_[KQZ], zz_[HZ ? KQZ : 1];
@@ -649,12 +648,12 @@ __device__ __forceinline__ void ac_adj_pml_body(const AcStep& a, const int tile,
       const int r = e >> 6, c = e & 63;
       const int gz = z0 - hz + r, gxx = x0 + c;
       const bool ok = e < NQZ && gxx < NX && gz >= 0 && gz < NZ;
-      const size_t idx = ok ? (size_t)gz * NX + gxx : 0;
-      lz_[k] = ok ? cur[idx] : 0.0f;
-      cz_[k] = ok ? a.Cs[idx] : 0.0f;
+      const unsigned idx = ok ? (unsigned)(gz * NX + gxx) : 0u;
+      lz_[k] = ok ? u32at(cur, idx) : 0.0f;
+      cz_[k] = ok ? u32at(a.Cs, idx) : 0.0f;
       if constexpr (HZ) {
         const int row = ok ? zstrip_row(gz, NZ, P) : -1;
-        zz_[k] = row >= 0 ? a.zez_in[shot * zsp + (size_t)row * NX + gxx] : 0.0f;
+        zz_[k] = row >= 0 ? u32at(a.zez_in + shot * zsp, (unsigned)(row * NX + gxx)) : 0.0f;
       }
     }
     if (tid < BW) {
@@ -678,7 +677,7 @@ __device__ __forceinline__ void ac_adj_pml_body(const AcStep& a, const int tile,
           const float zbar = zx_[k] + q;
           q = q + tax[c] * zbar;
           if (c >= hx && c < hx + kTX)
-            a.zex_out[shot * xsp + (size_t)gz * P2 + col] = tbx[c] * zbar;
+            u32at(a.zex_out + shot * xsp, (unsigned)(gz * P2 + col)) = tbx[c] * zbar;
         }
       }
       sqx[e] = q;
@@ -696,7 +695,7 @@ __device__ __forceinline__ void ac_adj_pml_body(const AcStep& a, const int tile,
           const float zbar = zz_[k] + q;
           q = q + taz[r] * zbar;
           if (r >= hz && r < hz + TZ)
-            a.zez_out[shot * zsp + (size_t)row * NX + gxx] = tbz[r] * zbar;
+            u32at(a.zez_out + shot * zsp, (unsigned)(row * NX + gxx)) = tbz[r] * zbar;
         }
       }
       sqz[e] = q;
@@ -711,7 +710,7 @@ __device__ __forceinline__ void ac_adj_pml_body(const AcStep& a, const int tile,
       const int r = e / XW, c = e - (e / XW) * XW;
       const int gz = z0 + r, gxx = x0 - 4 + c;
       const int col = (e < NTX && gz < NZ && gxx >= 0 && gxx < NX) ? xstrip_col(gxx, NX, P) : -1;
-      ox[k] = col >= 0 ? a.psx_in[shot * xsp + (size_t)gz * P2 + col] : 0.0f;
+      ox[k] = col >= 0 ? u32at(a.psx_in + shot * xsp, (unsigned)(gz * P2 + col)) : 0.0f;
     }
   }
   if constexpr (HZ) {
@@ -721,7 +720,7 @@ __device__ __forceinline__ void ac_adj_pml_body(const AcStep& a, const int tile,
       const int r = e >> 6, c = e & 63;
       const int gz = z0 - 4 + r, gxx = x0 + c;
       const int row = (e < NTZ && gxx < NX && gz >= 0 && gz < NZ) ? zstrip_row(gz, NZ, P) : -1;
-      oz[k] = row >= 0 ? a.psz_in[shot * zsp + (size_t)row * NX + gxx] : 0.0f;
+      oz[k] = row >= 0 ? u32at(a.psz_in + shot * zsp, (unsigned)(row * NX + gxx)) : 0.0f;
     }
   }
   // per-cell operands: branch-free where the body has no x-strip cells (measured
@@ -732,19 +731,19 @@ __device__ __forceinline__ void ac_adj_pml_body(const AcStep& a, const int tile,
     const int gz = z0 + zb + r;
     const bool ok = gx < NX && gz < NZ;
     if constexpr (!HX) {
-      const size_t gi = shot * plane + (ok ? (size_t)gz * NX + gx : 0);
-      p1[r] = ldz(a.cur, gi, ok, a.Cs);
-      pp[r] = ldz_nt(a.prev, gi, ok, a.Cs);
-      bb[r] = ldz_nt(a.B_in, gi, ok, a.Cs);
-      gg[r] = ldz_nt(a.g, gi, ok && !a.g_init, a.Cs);
+      const unsigned gi = ok ? (unsigned)(gz * NX + gx) : 0u;
+      p1[r] = ldz32(cur, gi, ok);
+      pp[r] = ldz32_nt(a.prev + shot * plane, gi, ok);
+      bb[r] = ldz32_nt(a.B_in + shot * plane, gi, ok);
+      gg[r] = ldz32_nt(a.g + shot * plane, gi, ok && !a.g_init);
     } else {
       p1[r] = pp[r] = bb[r] = gg[r] = 0.0f;
       if (ok) {
-        const size_t gi = shot * plane + (size_t)gz * NX + gx;
-        p1[r] = a.cur[gi];
-        pp[r] = ld_nt(&a.prev[gi]);
-        bb[r] = ld_nt(&a.B_in[gi]);
-        if (!a.g_init) gg[r] = ld_nt(&a.g[gi]);
+        const unsigned gi = (unsigned)(gz * NX + gx);
+        p1[r] = u32at(cur, gi);
+        pp[r] = ld_nt(&u32at(a.prev + shot * plane, gi));
+        bb[r] = ld_nt(&u32at(a.B_in + shot * plane, gi));
+        if (!a.g_init) gg[r] = ld_nt(&u32at(a.g + shot * plane, gi));
       }
     }
   }
@@ -763,7 +762,7 @@ __device__ __forceinline__ void ac_adj_pml_body(const AcStep& a, const int tile,
         const float psb = ox[k] - d1s(&sqx[r * BW + c + hx - 4], 1);
         t = tax[c + hx - 4] * psb;
         if (c >= 4 && c < 4 + kTX)
-          a.psx_out[shot * xsp + (size_t)gz * P2 + col] = tbx[c + hx - 4] * psb;
+          u32at(a.psx_out + shot * xsp, (unsigned)(gz * P2 + col)) = tbx[c + hx - 4] * psb;
       }
       stx[e] = t;
     }
@@ -781,7 +780,7 @@ __device__ __forceinline__ void ac_adj_pml_body(const AcStep& a, const int tile,
         const float psb = oz[k] - d1s(&sqz[(r + hz - 4) * kTX + c], kTX);
         t = taz[r + hz - 4] * psb;
         if (r >= 4 && r < 4 + TZ)
-          a.psz_out[shot * zsp + (size_t)row * NX + gxx] = tbz[r + hz - 4] * psb;
+          u32at(a.psz_out + shot * zsp, (unsigned)(row * NX + gxx)) = tbz[r + hz - 4] * psb;
       }
       stz[e] = t;
     }
@@ -799,9 +798,9 @@ __device__ __forceinline__ void ac_adj_pml_body(const AcStep& a, const int tile,
     const int gz = z0 + zb + r;
     float lam = 0.0f;
     if (gx < NX && gz < NZ) {
-      const size_t gi = shot * plane + (size_t)gz * NX + gx;
+      const unsigned gi = (unsigned)(gz * NX + gx);
       const float gb = p1[r] * bb[r];
-      st_nt(&a.g[gi], a.g_init ? gb : gg[r] + gb);
+      st_nt(&u32at(a.g + shot * plane, gi), a.g_init ? gb : gg[r] + gb);
       lam = ((2.0f * p1[r] - pp[r]) + dxx) + dzz;
       if constexpr (HX) lam = lam - tx;
       if constexpr (HZ) lam = lam - tz;
@@ -917,7 +916,9 @@ struct MarchCells {
 
 // Geometry of one march (a run of one shot).
 // Plane offsets fit in 32 bits; the per-shot planes are addressed from
-// work-group-uniform base pointers. wz is uniform within a wave (a wave is 64
+// work-group-uniform base pointers. The march indexes them with a 32-bit
+// element index widened per lane: the scalar-base byte-offset form (u32at)
+// cut the adjoint pass's vector instructions by 16 % but made it 0.9 % slower. wz is uniform within a wave (a wave is 64
 // consecutive threads), which readfirstlane tells the compiler, so branches on
 // it are scalar.
 struct March {

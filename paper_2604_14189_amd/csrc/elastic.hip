@@ -118,7 +118,9 @@ __device__ __forceinline__ ElTile el_tile(const ElStep& a) {
 // Guarded load without a per-lane branch: every lane loads (from `safe`, any
 // valid address, where !ok) and the value is selected afterwards. Written as a
 // branch, a guarded load must complete before the other path writes its
-// register, which serialises a sequence of them.
+// register, which serialises a sequence of them. The reverse kernels address
+// with 64-bit per-lane offsets like this: the scalar-base form (u32at, as in
+// the forward kernels) made their step 3 % slower.
 __device__ __forceinline__ float ldz(const float* f, size_t i, bool ok, const float* safe) {
   const float v = *(ok ? f + i : safe);
   return ok ? v : 0.0f;
@@ -135,9 +137,9 @@ __device__ __forceinline__ void el_stage(float (*dst)[kElBox], const float* cons
     const int r = e / kElBW, c = e - (e / kElBW) * kElBW;
     const int gx = x0 - 2 + c, gz = z0 - 2 + r;
     const bool ok = e < kElBox && gx >= 0 && gx < NX && gz >= 0 && gz < NZ;
-    const size_t q = ok ? (size_t)gz * NX + gx : 0;
+    const unsigned q = ok ? (unsigned)(gz * NX + gx) : 0u;
 #pragma unroll
-    for (int f = 0; f < NF; ++f) v[f][k] = ldz(src[f], q, ok, src[f]);
+    for (int f = 0; f < NF; ++f) v[f][k] = ldz32(src[f], q, ok);
   }
 #pragma unroll
   for (int k = 0; k < kElK; ++k) {
@@ -173,11 +175,11 @@ __device__ __forceinline__ float czz_z(const ElStep& a, int j, float cxx_x) {
 
 // C-PML update with a preloaded memory variable: psi <- b psi + a G where
 // a != 0 (stored), returns G + psi; G elsewhere.
-__device__ __forceinline__ float cpml_p(float* psi, size_t k, float G, float a, float b, float p0,
+__device__ __forceinline__ float cpml_p(float* psi, unsigned k, float G, float a, float b, float p0,
                                         bool store) {
   if (a == 0.0f) return G;
   const float p = fmaf(a, G, b * p0);
-  if (store) psi[k] = p;
+  if (store) u32at(psi, k) = p;
   return G + p;
 }
 
@@ -207,19 +209,19 @@ __global__ __launch_bounds__(256) void el_vel_kernel(ElStep a) {
 #pragma unroll
   for (int r = 0; r < kElRZ; ++r) {
     const int jc = min(C.jb + r, NZ - 1);
-    const size_t k = (size_t)jc * NX + C.ic;
-    ovx[r] = a.vx[so + k];
-    ovz[r] = a.vz[so + k];
-    cbx[r] = a.bx[k];
-    cbz[r] = a.bz[k];
+    const unsigned k = (unsigned)(jc * NX + C.ic);
+    ovx[r] = u32at(a.vx + so, k);
+    ovz[r] = u32at(a.vz + so, k);
+    cbx[r] = u32at(a.bx, k);
+    cbz[r] = u32at(a.bz, k);
     azi[r] = a.azi[jc];
     bzi[r] = a.bzi[jc];
     azh[r] = a.azh[jc];
     bzh[r] = a.bzh[jc];
-    p0[r] = wxh ? a.ps[0][so + k] : 0.0f;
-    p1[r] = !kFluid && azi[r] != 0.0f ? a.ps[1][so + k] : 0.0f;
-    p2[r] = !kFluid && wxi ? a.ps[2][so + k] : 0.0f;
-    p3[r] = azh[r] != 0.0f ? a.ps[3][so + k] : 0.0f;
+    p0[r] = wxh ? u32at(a.ps[0] + so, k) : 0.0f;
+    p1[r] = !kFluid && azi[r] != 0.0f ? u32at(a.ps[1] + so, k) : 0.0f;
+    p2[r] = !kFluid && wxi ? u32at(a.ps[2] + so, k) : 0.0f;
+    p3[r] = azh[r] != 0.0f ? u32at(a.ps[3] + so, k) : 0.0f;
   }
   __syncthreads();
   const Box txx{sb[0], T.x0, T.z0}, tzz{sb[1], T.x0, T.z0}, txz{sb[NF - 1], T.x0, T.z0};
@@ -229,7 +231,7 @@ __global__ __launch_bounds__(256) void el_vel_kernel(ElStep a) {
   for (int r = 0; r < kElRZ; ++r) {
     const int j = C.jb + r;
     if (i >= NX || j >= NZ) continue;
-    const size_t k = (size_t)j * NX + i;
+    const unsigned k = (unsigned)(j * NX + i);
     const float Ga = bdxp(txx, i, j) * ih;
     const float Gd = bdz_tzz(tzz, i, j, a.fs) * ih;
     float fvx = cpml_p(a.ps[0] + so, k, Ga, axh, bxh, p0[r], true);
@@ -240,11 +242,11 @@ __global__ __launch_bounds__(256) void el_vel_kernel(ElStep a) {
       fvx = fvx + cpml_p(a.ps[1] + so, k, Gb, azi[r], bzi[r], p1[r], true);
       fvz = cpml_p(a.ps[2] + so, k, Gc, axi, bxi, p2[r], true) + fvz;
     }
-    a.vx[so + k] = fmaf(a.dt * cbx[r], fvx, ovx[r]);
-    a.vz[so + k] = fmaf(a.dt * cbz[r], fvz, ovz[r]);
+    u32at(a.vx + so, k) = fmaf(a.dt * cbx[r], fvx, ovx[r]);
+    u32at(a.vz + so, k) = fmaf(a.dt * cbz[r], fvz, ovz[r]);
     if (a.tr[0]) {
-      a.tr[0][so + k] = fvx;
-      a.tr[1][so + k] = fvz;
+      u32at(a.tr[0] + so, k) = fvx;
+      u32at(a.tr[1] + so, k) = fvz;
     }
   }
 }
@@ -285,21 +287,21 @@ __global__ __launch_bounds__(256) void el_str_kernel(ElStep a) {
 #pragma unroll
   for (int r = 0; r < kElRZ; ++r) {
     const int jc = min(C.jb + r, NZ - 1);
-    const size_t k = (size_t)jc * NX + C.ic;
-    otxx[r] = a.txx[so + k];
-    otzz[r] = a.tzz[so + k];
-    otxz[r] = kFluid ? 0.0f : a.txz[so + k];
-    cxx_x[r] = a.cxx_x[k];
-    cxx_z[r] = a.cxx_z[k];
-    mxz[r] = kFluid ? 0.0f : a.mxz[k];
+    const unsigned k = (unsigned)(jc * NX + C.ic);
+    otxx[r] = u32at(a.txx + so, k);
+    otzz[r] = u32at(a.tzz + so, k);
+    otxz[r] = kFluid ? 0.0f : u32at(a.txz + so, k);
+    cxx_x[r] = u32at(a.cxx_x, k);
+    cxx_z[r] = u32at(a.cxx_z, k);
+    mxz[r] = kFluid ? 0.0f : u32at(a.mxz, k);
     azi[r] = a.azi[jc];
     bzi[r] = a.bzi[jc];
     azh[r] = a.azh[jc];
     bzh[r] = a.bzh[jc];
-    p4[r] = wxi ? a.ps[4][so + k] : 0.0f;
-    p5[r] = azi[r] != 0.0f ? a.ps[5][so + k] : 0.0f;
-    p6[r] = !kFluid && azh[r] != 0.0f ? a.ps[6][so + k] : 0.0f;
-    p7[r] = !kFluid && wxh ? a.ps[7][so + k] : 0.0f;
+    p4[r] = wxi ? u32at(a.ps[4] + so, k) : 0.0f;
+    p5[r] = azi[r] != 0.0f ? u32at(a.ps[5] + so, k) : 0.0f;
+    p6[r] = !kFluid && azh[r] != 0.0f ? u32at(a.ps[6] + so, k) : 0.0f;
+    p7[r] = !kFluid && wxh ? u32at(a.ps[7] + so, k) : 0.0f;
   }
   const int src = a.src_cell[shot];
   const float sw = a.w * a.wavelet[(size_t)shot * a.nt + a.n];
@@ -311,7 +313,7 @@ __global__ __launch_bounds__(256) void el_str_kernel(ElStep a) {
   for (int r = 0; r < kElRZ; ++r) {
     const int j = C.jb + r;
     if (i >= NX || j >= NZ) continue;
-    const size_t k = (size_t)j * NX + i;
+    const unsigned k = (unsigned)(j * NX + i);
     const float Ge = bdxm(vx, i, j) * ih;
     const float Gf = bdz_vz(vz, i, j, a.fs) * ih;
     const float exx = cpml_p(a.ps[4] + so, k, Ge, axi, bxi, p4[r], true);
@@ -320,21 +322,21 @@ __global__ __launch_bounds__(256) void el_str_kernel(ElStep a) {
     float tzz = otzz[r] + dt * fmaf(cxx_z[r], exx, czz_z(a, j, cxx_x[r]) * ezz);
     if ((int)k == src) {
       txx += sw;
-      tzz += sw * a.smask[k];
+      tzz += sw * u32at(a.smask, k);
     }
-    a.txx[so + k] = txx;
-    a.tzz[so + k] = tzz;
+    u32at(a.txx + so, k) = txx;
+    u32at(a.tzz + so, k) = tzz;
     if (a.tr[2]) {
-      a.tr[2][so + k] = exx;
-      a.tr[3][so + k] = ezz;
+      u32at(a.tr[2] + so, k) = exx;
+      u32at(a.tr[3] + so, k) = ezz;
     }
     if (!kFluid) {
       const float Gg = bdz_vx(vx, i, j, a.fs) * ih;
       const float Gh = bdxp(vz, i, j) * ih;
       const float exz = cpml_p(a.ps[6] + so, k, Gg, azh[r], bzh[r], p6[r], true) +
                         cpml_p(a.ps[7] + so, k, Gh, axh, bxh, p7[r], true);
-      a.txz[so + k] = fmaf(dt * mxz[r], exz, otxz[r]);
-      if (a.tr[2]) a.tr[4][so + k] = exz;
+      u32at(a.txz + so, k) = fmaf(dt * mxz[r], exz, otxz[r]);
+      if (a.tr[2]) u32at(a.tr[4] + so, k) = exz;
     }
   }
 }

@@ -58,6 +58,12 @@ __device__ __forceinline__ float ldz_nt(const float* f, size_t i, bool ok, const
   return ok ? v : 0.0f;
 }
 
+// ldz32 with the non-temporal hint.
+__device__ __forceinline__ float ldz32_nt(const float* f, unsigned i, bool ok) {
+  const float v = ld_nt(&u32at(f, i));
+  return ok ? v : 0.0f;
+}
+
 // Stencils on a strided LDS array centred at f.
 __device__ __forceinline__ float d2s(const float* f, int st) {
   return d2c(f[0], f[st], f[-st], f[2 * st], f[-2 * st], f[3 * st], f[-3 * st], f[4 * st],

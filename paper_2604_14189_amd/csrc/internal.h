@@ -8,6 +8,7 @@
 #include <cstdint>
 #include <new>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "sweep.h"
@@ -94,6 +95,27 @@ __device__ __forceinline__ int xcd_spread(int f, int n) {
   const int x = f & 7, k = f >> 3;
   const int q = n >> 3, r = n & 7;
   return x * q + min(x, r) + k;
+}
+
+// f[i] for a base f that is the same for the whole work-group (a per-shot
+// plane, a model plane, a memory-variable strip) and a 32-bit lane index i.
+// Plans hold fewer than 2^29 cells per plane, so the byte offset (4 or 8 bytes
+// per cell) fits in 32 bits; formed there, it lets the access take the
+// scalar-base addressing form (32-bit lane offset, 64-bit base in scalar
+// registers) instead of a 64-bit address computed in every lane.
+template <class T>
+__device__ __forceinline__ T& u32at(T* f, unsigned i) {
+  using C = typename std::conditional<std::is_const<T>::value, const char, char>::type;
+  return *reinterpret_cast<T*>(reinterpret_cast<C*>(f) + i * (unsigned)sizeof(T));
+}
+
+// Guarded load through u32at: the caller passes an index that is valid (0
+// where !ok), so every lane loads and the value is selected afterwards (a
+// guarded load written as a branch must complete before the other path writes
+// its register, which serialises a sequence of them).
+__device__ __forceinline__ float ldz32(const float* f, unsigned i, bool ok) {
+  const float v = u32at(f, i);
+  return ok ? v : 0.0f;
 }
 
 // ------------------------------------------------------------------ acoustic

@@ -46,7 +46,7 @@ __device__ __forceinline__ void stage(T* s, const T* __restrict__ f, int x0, int
     const int r = e / W, c = e - r * W;
     const int gx = x0 - hx + c, gz = z0 - hz + r;
     const bool ok = e < N && in_grid(gx, gz, NX, NZ);
-    v[k] = ok ? f[(size_t)gz * NX + gx] : T(0);
+    v[k] = ok ? u32at(f, (unsigned)(gz * NX + gx)) : T(0);
   }
 #pragma unroll
   for (int k = 0; k < K; ++k) {
@@ -79,7 +79,7 @@ __device__ __forceinline__ void stage_split(float* hi, unsigned short* lo,
     const int r = e / W, c = e - r * W;
     const int gx = x0 - hx + c, gz = z0 - hz + r;
     const bool ok = e < N && in_grid(gx, gz, NX, NZ);
-    v[k] = ok ? f[(size_t)gz * NX + gx] : 0.0;
+    v[k] = ok ? u32at(f, (unsigned)(gz * NX + gx)) : 0.0;
   }
 #pragma unroll
   for (int k = 0; k < K; ++k) {
@@ -150,16 +150,16 @@ __global__ __launch_bounds__(kThreads) void vti_fwd_kernel(VtiStep a) {
   for (int r = 0; r < kRZ; ++r) {
     const int gz = z0 + zb + r;
     const bool ok = gx < NX && gz < NZ;
-    const size_t idx = ok ? (size_t)gz * NX + gx : 0;
-    pown[r] = ok ? a.pcur[base + idx] : 0.0;
-    pold[r] = ok ? __builtin_nontemporal_load(a.pprev + base + idx) : 0.0;
-    gold[r] = ok ? __builtin_nontemporal_load(a.gprev + base + idx) : 0.0;
-    ccx[r] = ok ? a.cx[idx] : 0.0f;
-    ccz[r] = ok ? a.cz[idx] : 0.0f;
-    ccm[r] = ok ? a.cm[idx] : 0.0f;
+    const unsigned idx = ok ? (unsigned)(gz * NX + gx) : 0u;
+    pown[r] = ok ? u32at(a.pcur + base, idx) : 0.0;
+    pold[r] = ok ? __builtin_nontemporal_load(&u32at(a.pprev + base, idx)) : 0.0;
+    gold[r] = ok ? __builtin_nontemporal_load(&u32at(a.gprev + base, idx)) : 0.0;
+    ccx[r] = ok ? u32at(a.cx, idx) : 0.0f;
+    ccz[r] = ok ? u32at(a.cz, idx) : 0.0f;
+    ccm[r] = ok ? u32at(a.cm, idx) : 0.0f;
     const int zrow = ok ? zstrip_row(gz, NZ, P) : -1;
-    zx[r] = ok && xcol >= 0 ? a.zex_in[((size_t)shot * NZ + gz) * P2 + xcol] : 0.0f;
-    zz[r] = zrow >= 0 ? a.zez_in[((size_t)shot * P2 + zrow) * NX + gx] : 0.0f;
+    zx[r] = ok && xcol >= 0 ? u32at(a.zex_in + (size_t)shot * NZ * P2, (unsigned)(gz * P2 + xcol)) : 0.0f;
+    zz[r] = zrow >= 0 ? u32at(a.zez_in + (size_t)shot * P2 * NX, (unsigned)(zrow * NX + gx)) : 0.0f;
   }
   stage_split<PW, PH>(sP, sPl, a.pcur + base, x0, z0, 8, 8, NX, NZ);
   stage<GW, GH>(sG, a.gcur + base, x0, z0, 4, 4, NX, NZ);
@@ -173,9 +173,9 @@ __global__ __launch_bounds__(kThreads) void vti_fwd_kernel(VtiStep a) {
       const int col = in_grid(x, z, NX, NZ) ? xstrip_col(x, NX, P) : -1;
       float psi = 0.0f;
       if (col >= 0) {
-        const size_t si = ((size_t)shot * NZ + z) * P2 + col;
-        psi = fmaf(a.bx[x], a.psx_in[si], a.ax[x] * d1s(&sP[(r + 8) * PW + c + 4], 1));
-        if (c >= 4 && c < 4 + kTX) a.psx_out[si] = psi;
+        const unsigned si = (unsigned)(z * P2 + col);
+        psi = fmaf(a.bx[x], u32at(a.psx_in + (size_t)shot * NZ * P2, si), a.ax[x] * d1s(&sP[(r + 8) * PW + c + 4], 1));
+        if (c >= 4 && c < 4 + kTX) u32at(a.psx_out + (size_t)shot * NZ * P2, si) = psi;
       }
       sX[e] = psi;
     }
@@ -187,9 +187,9 @@ __global__ __launch_bounds__(kThreads) void vti_fwd_kernel(VtiStep a) {
       const int row = in_grid(x, z, NX, NZ) ? zstrip_row(z, NZ, P) : -1;
       float psi = 0.0f;
       if (row >= 0) {
-        const size_t si = ((size_t)shot * P2 + row) * NX + x;
-        psi = fmaf(a.bz[z], a.psz_in[si], a.az[z] * d1s(&sP[(r + 4) * PW + c + 8], PW));
-        if (r >= 4 && r < 4 + kTZ) a.psz_out[si] = psi;
+        const unsigned si = (unsigned)(row * NX + x);
+        psi = fmaf(a.bz[z], u32at(a.psz_in + (size_t)shot * P2 * NX, si), a.az[z] * d1s(&sP[(r + 4) * PW + c + 8], PW));
+        if (r >= 4 && r < 4 + kTZ) u32at(a.psz_out + (size_t)shot * P2 * NX, si) = psi;
       }
       sZ[e] = psi;
     }
@@ -218,7 +218,7 @@ __global__ __launch_bounds__(kThreads) void vti_fwd_kernel(VtiStep a) {
   for (int rr = 0; rr < kRZ; ++rr) {
     const int r = zb + rr, gz = z0 + r;
     const bool ok = gx < NX && gz < NZ;
-    const size_t idx = ok ? (size_t)gz * NX + gx : 0;
+    const unsigned idx = ok ? (unsigned)(gz * NX + gx) : 0u;
     const int pe = (r + 8) * PW + lx + 8;
     float qx = d2p(&sP[pe], &sPl[pe], 1), qz = d2p(&sP[pe], &sPl[pe], PW);
     if (hx) qx += d1s(&sX[r * GW + lx + 4], 1);
@@ -226,13 +226,13 @@ __global__ __launch_bounds__(kThreads) void vti_fwd_kernel(VtiStep a) {
     float bxv = qx, bzv = qz;
     if (ok && xcol >= 0) {
       const float zn = fmaf(a.bx[gx], zx[rr], a.ax[gx] * qx);
-      a.zex_out[((size_t)shot * NZ + gz) * P2 + xcol] = zn;
+      u32at(a.zex_out + (size_t)shot * NZ * P2, (unsigned)(gz * P2 + xcol)) = zn;
       bxv = qx + zn;
     }
     const int zrow = ok ? zstrip_row(gz, NZ, P) : -1;
     if (zrow >= 0) {
       const float zn = fmaf(a.bz[gz], zz[rr], a.az[gz] * qz);
-      a.zez_out[((size_t)shot * P2 + zrow) * NX + gx] = zn;
+      u32at(a.zez_out + (size_t)shot * P2 * NX, (unsigned)(zrow * NX + gx)) = zn;
       bzv = qz + zn;
     }
     const float m = (float)d2d(&sT[r * GW + lx + 4], 1);
@@ -245,12 +245,12 @@ __global__ __launch_bounds__(kThreads) void vti_fwd_kernel(VtiStep a) {
     const double gn = (2.0 * g0[rr] - gold[rr]) + p0;
     out[rr] = (float)pn;
     if (ok) {
-      __builtin_nontemporal_store(pn, a.pprev + base + idx);
-      __builtin_nontemporal_store(gn, a.gprev + base + idx);
+      __builtin_nontemporal_store(pn, &u32at(a.pprev + base, idx));
+      __builtin_nontemporal_store(gn, &u32at(a.gprev + base, idx));
       if (a.tr[0]) {
-        st_nt(a.tr[0] + base + idx, bxv);
-        st_nt(a.tr[1] + base + idx, bzv);
-        st_nt(a.tr[2] + base + idx, m);
+        st_nt(&u32at(a.tr[0] + base, idx), bxv);
+        st_nt(&u32at(a.tr[1] + base, idx), bzv);
+        st_nt(&u32at(a.tr[2] + base, idx), m);
       }
     }
   }
@@ -301,18 +301,18 @@ __global__ __launch_bounds__(kThreads) void vti_adj_kernel(VtiStep a) {
   for (int r = 0; r < kRZ; ++r) {
     const int gz = z0 + zb + r;
     const bool ok = gx < NX && gz < NZ;
-    const size_t idx = ok ? (size_t)gz * NX + gx : 0;
-    l2[r] = ok ? ld_nt(a.prev + base + idx) : 0.0f;
-    m1[r] = ok ? a.mcur[base + idx] : 0.0;
-    m2[r] = ok ? __builtin_nontemporal_load(a.mprev + base + idx) : 0.0;
-    ccx[r] = ok ? a.cx[idx] : 0.0f;
-    ccz[r] = ok ? a.cz[idx] : 0.0f;
-    t0[r] = ok ? ld_nt(a.trc[0] + base + idx) : 0.0f;
-    t1[r] = ok ? ld_nt(a.trc[1] + base + idx) : 0.0f;
-    t2[r] = ok ? ld_nt(a.trc[2] + base + idx) : 0.0f;
+    const unsigned idx = ok ? (unsigned)(gz * NX + gx) : 0u;
+    l2[r] = ok ? ld_nt(&u32at(a.prev + base, idx)) : 0.0f;
+    m1[r] = ok ? u32at(a.mcur + base, idx) : 0.0;
+    m2[r] = ok ? __builtin_nontemporal_load(&u32at(a.mprev + base, idx)) : 0.0;
+    ccx[r] = ok ? u32at(a.cx, idx) : 0.0f;
+    ccz[r] = ok ? u32at(a.cz, idx) : 0.0f;
+    t0[r] = ok ? ld_nt(&u32at(a.trc[0] + base, idx)) : 0.0f;
+    t1[r] = ok ? ld_nt(&u32at(a.trc[1] + base, idx)) : 0.0f;
+    t2[r] = ok ? ld_nt(&u32at(a.trc[2] + base, idx)) : 0.0f;
     const int zrow = ok ? zstrip_row(gz, NZ, P) : -1;
-    zx[r] = ok && xcol >= 0 ? a.zex_in[((size_t)shot * NZ + gz) * P2 + xcol] : 0.0f;
-    zz[r] = zrow >= 0 ? a.zez_in[((size_t)shot * P2 + zrow) * NX + gx] : 0.0f;
+    zx[r] = ok && xcol >= 0 ? u32at(a.zex_in + (size_t)shot * NZ * P2, (unsigned)(gz * P2 + xcol)) : 0.0f;
+    zz[r] = zrow >= 0 ? u32at(a.zez_in + (size_t)shot * P2 * NX, (unsigned)(zrow * NX + gx)) : 0.0f;
   }
   // the coefficients of the three product boxes (and, in tiles near a strip,
   // the zeta adjoints there) are loaded with the lambda box, before any LDS
@@ -326,24 +326,24 @@ __global__ __launch_bounds__(kThreads) void vti_adj_kernel(VtiStep a) {
     const int e = tid + k * kThreads, r = e / PW, c = e - r * PW;
     const int x = x0 - 8 + c, z = z0 + r;
     const bool ok = e < NQX && in_grid(x, z, NX, NZ);
-    vcx[k] = ok ? a.cx[(size_t)z * NX + x] : 0.0f;
+    vcx[k] = ok ? u32at(a.cx, (unsigned)(z * NX + x)) : 0.0f;
     const int col = ok && hx ? xstrip_col(x, NX, P) : -1;
-    vzx[k] = col >= 0 ? a.zex_in[((size_t)shot * NZ + z) * P2 + col] : 0.0f;
+    vzx[k] = col >= 0 ? u32at(a.zex_in + (size_t)shot * NZ * P2, (unsigned)(z * P2 + col)) : 0.0f;
   }
 #pragma unroll
   for (int k = 0; k < KQZ; ++k) {
     const int e = tid + k * kThreads, r = e / kTX, c = e - r * kTX;
     const int x = x0 + c, z = z0 - 8 + r;
     const bool ok = e < NQZ && in_grid(x, z, NX, NZ);
-    vcz[k] = ok ? a.cz[(size_t)z * NX + x] : 0.0f;
+    vcz[k] = ok ? u32at(a.cz, (unsigned)(z * NX + x)) : 0.0f;
     const int row = ok && hz ? zstrip_row(z, NZ, P) : -1;
-    vzz[k] = row >= 0 ? a.zez_in[((size_t)shot * P2 + row) * NX + x] : 0.0f;
+    vzz[k] = row >= 0 ? u32at(a.zez_in + (size_t)shot * P2 * NX, (unsigned)(row * NX + x)) : 0.0f;
   }
 #pragma unroll
   for (int k = 0; k < KM; ++k) {
     const int e = tid + k * kThreads, r = e / GW, c = e - r * GW;
     const int x = x0 - 4 + c, z = z0 - 4 + r;
-    vcm[k] = e < NM && in_grid(x, z, NX, NZ) ? a.cm[(size_t)z * NX + x] : 0.0f;
+    vcm[k] = e < NM && in_grid(x, z, NX, NZ) ? u32at(a.cm, (unsigned)(z * NX + x)) : 0.0f;
   }
   stage<PW, PH>(sL, a.cur + base, x0, z0, 8, 8, NX, NZ);
   __syncthreads();
@@ -386,10 +386,10 @@ __global__ __launch_bounds__(kThreads) void vti_adj_kernel(VtiStep a) {
       const int col = in_grid(x, z, NX, NZ) ? xstrip_col(x, NX, P) : -1;
       float t = 0.0f;
       if (col >= 0) {
-        const size_t si = ((size_t)shot * NZ + z) * P2 + col;
-        const float psb = a.psx_in[si] - d1s(&sQx[r * PW + c + 4], 1);
+        const unsigned si = (unsigned)(z * P2 + col);
+        const float psb = u32at(a.psx_in + (size_t)shot * NZ * P2, si) - d1s(&sQx[r * PW + c + 4], 1);
         t = a.ax[x] * psb;
-        if (c >= 4 && c < 4 + kTX) a.psx_out[si] = a.bx[x] * psb;
+        if (c >= 4 && c < 4 + kTX) u32at(a.psx_out + (size_t)shot * NZ * P2, si) = a.bx[x] * psb;
       }
       sTx[e] = t;
     }
@@ -401,10 +401,10 @@ __global__ __launch_bounds__(kThreads) void vti_adj_kernel(VtiStep a) {
       const int row = in_grid(x, z, NX, NZ) ? zstrip_row(z, NZ, P) : -1;
       float t = 0.0f;
       if (row >= 0) {
-        const size_t si = ((size_t)shot * P2 + row) * NX + x;
-        const float psb = a.psz_in[si] - d1s(&sQz[(r + 4) * kTX + c], kTX);
+        const unsigned si = (unsigned)(row * NX + x);
+        const float psb = u32at(a.psz_in + (size_t)shot * P2 * NX, si) - d1s(&sQz[(r + 4) * kTX + c], kTX);
         t = a.az[z] * psb;
-        if (r >= 4 && r < 4 + kTZ) a.psz_out[si] = a.bz[z] * psb;
+        if (r >= 4 && r < 4 + kTZ) u32at(a.psz_out + (size_t)shot * P2 * NX, si) = a.bz[z] * psb;
       }
       sTz[e] = t;
     }
@@ -420,7 +420,7 @@ __global__ __launch_bounds__(kThreads) void vti_adj_kernel(VtiStep a) {
   for (int rr = 0; rr < kRZ; ++rr) {
     const int r = zb + rr, gz = z0 + r;
     const bool ok = gx < NX && gz < NZ;
-    const size_t idx = ok ? (size_t)gz * NX + gx : 0;
+    const unsigned idx = ok ? (unsigned)(gz * NX + gx) : 0u;
     const float l1 = l1v[rr];
     float lam = 2.0f * l1 - l2[rr];
     lam += d2s(&sQx[r * PW + lx + 8], 1);
@@ -432,14 +432,14 @@ __global__ __launch_bounds__(kThreads) void vti_adj_kernel(VtiStep a) {
     out[rr] = lam;
     if (!ok) continue;
     if (xcol >= 0)
-      a.zex_out[((size_t)shot * NZ + gz) * P2 + xcol] = a.bx[gx] * (zx[rr] + ccx[rr] * l1);
+      u32at(a.zex_out + (size_t)shot * NZ * P2, (unsigned)(gz * P2 + xcol)) = a.bx[gx] * (zx[rr] + ccx[rr] * l1);
     const int zrow = zstrip_row(gz, NZ, P);
     if (zrow >= 0)
-      a.zez_out[((size_t)shot * P2 + zrow) * NX + gx] = a.bz[gz] * (zz[rr] + ccz[rr] * l1);
-    __builtin_nontemporal_store(mu, a.mprev + base + idx);
-    float* g0 = a.g + base + idx;
-    float* g1 = g0 + (size_t)a.nshots * plane;
-    float* g2 = g1 + (size_t)a.nshots * plane;
+      u32at(a.zez_out + (size_t)shot * P2 * NX, (unsigned)(zrow * NX + gx)) = a.bz[gz] * (zz[rr] + ccz[rr] * l1);
+    __builtin_nontemporal_store(mu, &u32at(a.mprev + base, idx));
+    float* g0 = &u32at(a.g + base, idx);
+    float* g1 = &u32at(a.g + base + (size_t)a.nshots * plane, idx);
+    float* g2 = &u32at(a.g + base + 2 * (size_t)a.nshots * plane, idx);
     if (a.g_init) {
       st_nt(g0, l1 * t0[rr]);
       st_nt(g1, l1 * t1[rr]);
@@ -475,7 +475,7 @@ __global__ __launch_bounds__(kThreads) void vti_adj_kernel(VtiStep a) {
 #pragma unroll
   for (int rr = 0; rr < kRZ; ++rr) {
     const int gz = z0 + zb + rr;
-    if (gx < NX && gz < NZ) st_nt(a.prev + base + (size_t)gz * NX + gx, out[rr]);
+    if (gx < NX && gz < NZ) st_nt(&u32at(a.prev + base, (unsigned)(gz * NX + gx)), out[rr]);
   }
 }
 
@@ -504,13 +504,13 @@ __global__ __launch_bounds__(kThreads) void vti_fwd_int_kernel(VtiStep a) {
   for (int r = 0; r < kRZ; ++r) {
     const int gz = z0 + zb + r;
     const bool ok = gx < NX && gz < NZ;
-    const size_t idx = ok ? (size_t)gz * NX + gx : 0;
-    pown[r] = ok ? a.pcur[base + idx] : 0.0;
-    pold[r] = ok ? __builtin_nontemporal_load(a.pprev + base + idx) : 0.0;
-    gold[r] = ok ? __builtin_nontemporal_load(a.gprev + base + idx) : 0.0;
-    ccx[r] = ok ? a.cx[idx] : 0.0f;
-    ccz[r] = ok ? a.cz[idx] : 0.0f;
-    ccm[r] = ok ? a.cm[idx] : 0.0f;
+    const unsigned idx = ok ? (unsigned)(gz * NX + gx) : 0u;
+    pown[r] = ok ? u32at(a.pcur + base, idx) : 0.0;
+    pold[r] = ok ? __builtin_nontemporal_load(&u32at(a.pprev + base, idx)) : 0.0;
+    gold[r] = ok ? __builtin_nontemporal_load(&u32at(a.gprev + base, idx)) : 0.0;
+    ccx[r] = ok ? u32at(a.cx, idx) : 0.0f;
+    ccz[r] = ok ? u32at(a.cz, idx) : 0.0f;
+    ccm[r] = ok ? u32at(a.cm, idx) : 0.0f;
   }
   stage_split<GW, GH>(sP, sPl, a.pcur + base, x0, z0, 4, 4, NX, NZ);
   stage<GW, GH>(sG, a.gcur + base, x0, z0, 4, 4, NX, NZ);
@@ -539,7 +539,7 @@ __global__ __launch_bounds__(kThreads) void vti_fwd_int_kernel(VtiStep a) {
   for (int rr = 0; rr < kRZ; ++rr) {
     const int r = zb + rr, gz = z0 + r;
     const bool ok = gx < NX && gz < NZ;
-    const size_t idx = ok ? (size_t)gz * NX + gx : 0;
+    const unsigned idx = ok ? (unsigned)(gz * NX + gx) : 0u;
     const int pe = (r + 4) * GW + lx + 4;
     const float bxv = d2p(&sP[pe], &sPl[pe], 1), bzv = d2p(&sP[pe], &sPl[pe], GW);
     const float m = (float)d2d(&sT[r * GW + lx + 4], 1);
@@ -552,12 +552,12 @@ __global__ __launch_bounds__(kThreads) void vti_fwd_int_kernel(VtiStep a) {
     const double gn = (2.0 * g0[rr] - gold[rr]) + p0;
     out[rr] = (float)pn;
     if (ok) {
-      __builtin_nontemporal_store(pn, a.pprev + base + idx);
-      __builtin_nontemporal_store(gn, a.gprev + base + idx);
+      __builtin_nontemporal_store(pn, &u32at(a.pprev + base, idx));
+      __builtin_nontemporal_store(gn, &u32at(a.gprev + base, idx));
       if (a.tr[0]) {
-        st_nt(a.tr[0] + base + idx, bxv);
-        st_nt(a.tr[1] + base + idx, bzv);
-        st_nt(a.tr[2] + base + idx, m);
+        st_nt(&u32at(a.tr[0] + base, idx), bxv);
+        st_nt(&u32at(a.tr[1] + base, idx), bzv);
+        st_nt(&u32at(a.tr[2] + base, idx), m);
       }
     }
   }
@@ -595,11 +595,11 @@ __global__ __launch_bounds__(kThreads) void vti_adj_int_kernel(VtiStep a) {
     const int e = tid + k * kThreads, r = e / GW, c = e - r * GW;
     const int x = x0 - 4 + c, z = z0 - 4 + r;
     const bool ok = e < NB && in_grid(x, z, NX, NZ);
-    const size_t idx = ok ? (size_t)z * NX + x : 0;
-    bl[k] = ok ? a.cur[base + idx] : 0.0f;
-    bcx[k] = ok ? a.cx[idx] : 0.0f;
-    bcz[k] = ok ? a.cz[idx] : 0.0f;
-    bcm[k] = ok ? a.cm[idx] : 0.0f;
+    const unsigned idx = ok ? (unsigned)(z * NX + x) : 0u;
+    bl[k] = ok ? u32at(a.cur + base, idx) : 0.0f;
+    bcx[k] = ok ? u32at(a.cx, idx) : 0.0f;
+    bcz[k] = ok ? u32at(a.cz, idx) : 0.0f;
+    bcm[k] = ok ? u32at(a.cm, idx) : 0.0f;
   }
   float l1v[kRZ], l2[kRZ], t0[kRZ], t1[kRZ], t2[kRZ];
   double m1[kRZ], m2[kRZ];
@@ -607,14 +607,14 @@ __global__ __launch_bounds__(kThreads) void vti_adj_int_kernel(VtiStep a) {
   for (int r = 0; r < kRZ; ++r) {
     const int gz = z0 + zb + r;
     const bool ok = gx < NX && gz < NZ;
-    const size_t idx = ok ? (size_t)gz * NX + gx : 0;
-    l1v[r] = ok ? a.cur[base + idx] : 0.0f;
-    l2[r] = ok ? ld_nt(a.prev + base + idx) : 0.0f;
-    m1[r] = ok ? a.mcur[base + idx] : 0.0;
-    m2[r] = ok ? __builtin_nontemporal_load(a.mprev + base + idx) : 0.0;
-    t0[r] = ok ? ld_nt(a.trc[0] + base + idx) : 0.0f;
-    t1[r] = ok ? ld_nt(a.trc[1] + base + idx) : 0.0f;
-    t2[r] = ok ? ld_nt(a.trc[2] + base + idx) : 0.0f;
+    const unsigned idx = ok ? (unsigned)(gz * NX + gx) : 0u;
+    l1v[r] = ok ? u32at(a.cur + base, idx) : 0.0f;
+    l2[r] = ok ? ld_nt(&u32at(a.prev + base, idx)) : 0.0f;
+    m1[r] = ok ? u32at(a.mcur + base, idx) : 0.0;
+    m2[r] = ok ? __builtin_nontemporal_load(&u32at(a.mprev + base, idx)) : 0.0;
+    t0[r] = ok ? ld_nt(&u32at(a.trc[0] + base, idx)) : 0.0f;
+    t1[r] = ok ? ld_nt(&u32at(a.trc[1] + base, idx)) : 0.0f;
+    t2[r] = ok ? ld_nt(&u32at(a.trc[2] + base, idx)) : 0.0f;
   }
   // products (outside the grid every operand is 0)
 #pragma unroll
@@ -646,7 +646,7 @@ __global__ __launch_bounds__(kThreads) void vti_adj_int_kernel(VtiStep a) {
   for (int rr = 0; rr < kRZ; ++rr) {
     const int r = zb + rr, gz = z0 + r;
     const bool ok = gx < NX && gz < NZ;
-    const size_t idx = ok ? (size_t)gz * NX + gx : 0;
+    const unsigned idx = ok ? (unsigned)(gz * NX + gx) : 0u;
     const float l1 = l1v[rr];
     float lam = 2.0f * l1 - l2[rr];
     lam += d2s(&sQx[r * GW + lx + 4], 1);
@@ -655,10 +655,10 @@ __global__ __launch_bounds__(kThreads) void vti_adj_int_kernel(VtiStep a) {
     const double mu = (2.0 * m1[rr] - m2[rr]) - d2d(&sU[r * GW + lx + 4], 1);
     out[rr] = lam;
     if (!ok) continue;
-    __builtin_nontemporal_store(mu, a.mprev + base + idx);
-    float* g0 = a.g + base + idx;
-    float* g1 = g0 + (size_t)a.nshots * plane;
-    float* g2 = g1 + (size_t)a.nshots * plane;
+    __builtin_nontemporal_store(mu, &u32at(a.mprev + base, idx));
+    float* g0 = &u32at(a.g + base, idx);
+    float* g1 = &u32at(a.g + base + (size_t)a.nshots * plane, idx);
+    float* g2 = &u32at(a.g + base + 2 * (size_t)a.nshots * plane, idx);
     if (a.g_init) {
       st_nt(g0, l1 * t0[rr]);
       st_nt(g1, l1 * t1[rr]);
@@ -694,7 +694,7 @@ __global__ __launch_bounds__(kThreads) void vti_adj_int_kernel(VtiStep a) {
 #pragma unroll
   for (int rr = 0; rr < kRZ; ++rr) {
     const int gz = z0 + zb + rr;
-    if (gx < NX && gz < NZ) st_nt(a.prev + base + (size_t)gz * NX + gx, out[rr]);
+    if (gx < NX && gz < NZ) st_nt(&u32at(a.prev + base, (unsigned)(gz * NX + gx)), out[rr]);
   }
 }
 
