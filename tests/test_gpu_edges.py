@@ -9,7 +9,9 @@ Against the FP64 oracle (same tolerances as the parity tests):
 
 And the largest problem one call takes in this test: 4100 shots on a 1020x520
 padded grid, i.e. 2.17e9 cells per wavefield buffer, past 2^31 (every shot
-offset is 64-bit), checked bitwise against the same shot run alone.
+offset is 64-bit), checked bitwise against the same shot run alone; and
+nearly the largest single plane (just under 2^29 cells), acoustic and VTI,
+against a small grid around the same source.
 """
 import dataclasses
 
@@ -150,3 +152,53 @@ def test_offsets_past_2_31_elements(sw):
     assert torch.any(d != 0) and torch.any(g != 0)
     assert torch.equal(d, d1)
     assert torch.equal(g, g1)
+
+
+@pytest.mark.parametrize("physics", ["acoustic", "vti"])
+def test_largest_plane_matches_a_small_grid(sw, physics):
+    """One shot on nearly the largest plane a plan takes (23170 x 23170 padded
+    cells, just under 2^29). The source sits 40 cells from the far corner, so
+    the cells it reaches in 6 steps lie at the end of every plane: VTI's
+    float64 planes are addressed there at byte offsets past 2^31, close to
+    2^32. With a constant model, the same 6 steps on a 100 x 100 grid around
+    the same source see the same neighbourhood, so the gathers and the
+    gradient around the source must agree: bit for bit for acoustic; within
+    1e-6 for VTI, whose interior and C-PML tile kernels round differently."""
+    vti = physics == "vti"
+    off = np.array([[0, 0], [7, -3], [-9, 5], [2, 9]])
+    wav = np.array([[1.0, -0.5, 0.25, 0.75, -0.375, 0.125]], np.float32)
+    resid = _dev(np.random.default_rng(3).standard_normal((1, 6, 4)))
+
+    def run(n, xs):
+        print(physics, "grid", n, "source", xs, flush=True)
+        plan = sw.Plan(nx=n, nz=n, h=10.0, dt=1e-3, nt=6, pml=10,
+                       src_xz=np.array([[xs, xs]], np.int32),
+                       rec_xz=(np.array([[xs, xs]]) + off)[None].astype(np.int32),
+                       pml_vmax=2400.0, pml_f0=15.0, ckpt_every=3,
+                       physics=sw.VTI if vti else sw.ACOUSTIC)
+        vals = (2000.0, 2100.0, 0.1) if vti else (2000.0,)
+        m = torch.empty((len(vals), n, n), device="cuda")
+        for i, val in enumerate(vals):
+            m[i].fill_(val)
+        d = plan.forward(m, _dev(wav), save=True).clone()
+        g = plan.backward(resid)
+        win = g[:, xs - 30:xs + 31, xs - 30:xs + 31].clone()
+        del g, m
+        plan.release_workspace()
+        del plan
+        torch.cuda.empty_cache()
+        return d, win
+
+    n_big = 23150
+    assert (n_big + 20) ** 2 < 2 ** 29
+    d_big, g_big = run(n_big, n_big - 40)
+    d_small, g_small = run(100, 50)
+    torch.cuda.synchronize()
+    assert torch.any(d_small != 0) and torch.any(g_small != 0)
+    print("largest plane", physics, "gathers max", float(d_small.abs().max()), flush=True)
+    if vti:
+        assert rel_l2(_host(d_big), _host(d_small)) <= 1e-6
+        assert rel_l2(_host(g_big), _host(g_small)) <= 1e-6
+    else:
+        assert torch.equal(d_big, d_small)
+        assert torch.equal(g_big, g_small)
