@@ -173,20 +173,32 @@ def fit_keep_b(torch, plan, nt, ckpt, reserve=8 << 30):
     count steps down. Returns the count set on the plan."""
     t = dict(plan.tuning)
     nseg = -(-nt // ckpt)
-    t["keep_b"] = nseg
-    plan.set_tuning(**t)
-    ws_all = plan.workspace_bytes(True)
-    t["keep_b"] = 0
-    plan.set_tuning(**t)
-    ws_none = plan.workspace_bytes(True)
-    # a stored segment costs its B'^n planes less the checkpoint it no longer needs
-    seg = max(1, (ws_all - ws_none) // nseg)
+
+    def ws(k):  # the plan's backward workspace with k stored segments (host-side layout)
+        t["keep_b"] = k
+        plan.set_tuning(**t)
+        return plan.workspace_bytes(True)
+
     plan.release_workspace()
     gc.collect()
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
     free, _ = torch.cuda.mem_get_info()
-    keep = int(max(0, min(nseg, (free - ws_none - reserve) // seg)))
+    budget = free - reserve
+    # a stored segment costs its B'^n planes less the checkpoint it no longer
+    # needs; the first one also takes over the recomputation's B'^n buffer,
+    # so the workspace grows with the count from one stored segment on: the
+    # largest count that fits, by bisection
+    keep = 0
+    if ws(1) <= budget:
+        lo, hi = 1, nseg
+        while lo < hi:
+            mid = (lo + hi + 1) // 2
+            if ws(mid) <= budget:
+                lo = mid
+            else:
+                hi = mid - 1
+        keep = lo
     log = {"free_GiB": round(free / 2**30, 1),
            "torch_reserved_GiB": round(torch.cuda.memory_reserved() / 2**30, 1),
            "torch_allocated_GiB": round(torch.cuda.memory_allocated() / 2**30, 1),

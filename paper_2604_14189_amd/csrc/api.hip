@@ -221,13 +221,18 @@ void ac_layout(const sweep_plan* p, AcLayout& L, bool keep) {
   // a stored segment is never recomputed, so only the others need a checkpoint
   L.nkeep = keep ? std::min(std::max(p->tune.keep_b, 0), L.nseg) : 0;
   L.ck = c.take((size_t)(L.nseg - L.nkeep) * L.slot_elems * f);
-  L.Bseg = c.take((size_t)k * ns * plane * f);
+  // B'^n of a recomputed segment. The backward reverses the stored segments
+  // (the last ones) before it recomputes any other, so a plan that stores
+  // some recomputes into the first stored segment's slots (set below) and
+  // needs no buffer of its own.
+  L.Bseg = L.nkeep > 0 ? 0 : c.take((size_t)k * ns * plane * f);
   for (int i = 0; i < 4; ++i) L.lf[i] = c.take(ns * plane * f);
   L.adjaux[0] = c.take(L.aux_elems * f);
   L.adjaux[1] = c.take(L.aux_elems * f);
   L.gpart = c.take(ns * plane * f);
   L.tot = c.take(plane * sizeof(double));
   L.Bkeep = c.take((size_t)L.nkeep * k * ns * plane * f);
+  if (L.nkeep > 0) L.Bseg = L.Bkeep;
   L.bwd_end = c.off;
 }
 

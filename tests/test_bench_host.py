@@ -47,22 +47,25 @@ def test_keep_b_fills_free_memory(bench):
     w, plan = _plan()
     nseg = -(-w.nt // w.ckpt_every)
     sizes = {}
-    for k in (0, nseg):
+    for k in range(nseg + 1):
         plan.set_tuning(rz=8, pml_rz=4, tblock=2, keep_b=k)
         sizes[k] = plan.workspace_bytes(True)
-    net = (sizes[nseg] - sizes[0]) // nseg
     plan.set_tuning(rz=8, pml_rz=4, tblock=2)
     plan.reserve_workspace = lambda fb=True: plan.workspace_bytes(fb)
     free = 287 * GiB
     keep = bench.fit_keep_b(_fake_torch(free), plan, w.nt, w.ckpt_every)
     # the largest count whose workspace leaves the 8 GiB reserve free
-    assert keep == (free - sizes[0] - 8 * GiB) // net
+    assert keep == max(k for k in range(1, nseg + 1) if sizes[k] <= free - 8 * GiB)
+    assert 0 < keep < nseg
     assert plan.tuning["keep_b"] == keep
     assert plan.workspace_bytes(True) <= free - 8 * GiB
     plan.set_tuning(rz=8, pml_rz=4, tblock=2, keep_b=keep + 1)
     assert plan.workspace_bytes(True) > free - 8 * GiB
-    # a stored segment costs less than its planes: its checkpoint is dropped
+    # a stored segment costs less than its planes: its checkpoint is dropped;
+    # and the first one also takes over the recomputation's buffer
+    net = sizes[nseg] - sizes[nseg - 1]
     assert net < w.ckpt_every * w.nshots * w.NX * w.NZ * 4
+    assert sizes[1] < sizes[0]
 
 
 def test_keep_b_caps_at_the_segment_count(bench):
