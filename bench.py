@@ -165,6 +165,15 @@ def progress(what: str):
     print(f"[bench {time.perf_counter() - T_START:7.1f} s] {what}", file=sys.stderr, flush=True)
 
 
+def _free_bytes(torch):
+    """Device memory a new workspace can take: what the device reports free,
+    plus what torch's allocator holds cached but unused (a workspace is a
+    torch tensor, so it can take a cached block; the allocator may keep a
+    very large freed block rather than return it to the device)."""
+    free, _ = torch.cuda.mem_get_info()
+    return free + max(0, torch.cuda.memory_reserved() - torch.cuda.memory_allocated())
+
+
 def fit_keep_b(torch, plan, nt, ckpt, reserve=8 << 30):
     """Use the HBM: store B'^n of as many checkpoint segments as the free
     memory holds after the rest of the workspace and `reserve` bytes for the
@@ -183,7 +192,7 @@ def fit_keep_b(torch, plan, nt, ckpt, reserve=8 << 30):
     gc.collect()
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
-    free, _ = torch.cuda.mem_get_info()
+    free = _free_bytes(torch)
     budget = free - reserve
     # a stored segment costs its B'^n planes less the checkpoint it no longer
     # needs; the first one also takes over the recomputation's B'^n buffer,
@@ -238,7 +247,7 @@ def fit_batch_keep_b(torch, batch, plans, nsegs, reserve=8 << 30):
     gc.collect()
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
-    free, _ = torch.cuda.mem_get_info()
+    free = _free_bytes(torch)
     lo, hi = 0.0, 1.0
     if ws_at(1.0) <= free - reserve:
         lo = 1.0
