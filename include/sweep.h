@@ -127,7 +127,10 @@ typedef struct {
                       checkpoint, so each one costs ckpt_every * nshots * NX *
                       NZ * 4 workspace bytes less its checkpoint slot (2 *
                       nshots * NX * NZ fields plus the C-PML memory variables,
-                      4 bytes each). Elastic and variable-density acoustic: the
+                      4 bytes each); with any stored, the recomputed segments
+                      write B'^n into the first stored segment's slots (free
+                      by then), so the recomputation's own buffer of the same
+                      size is dropped. Elastic and variable-density acoustic: the
                       five trace planes of each step, ckpt_every * 5 * nshots *
                       NX * NZ * 4 bytes per segment. VTI: the three trace
                       planes of each step (Bx', Bz', D2x'D2z'G), ckpt_every * 3
